@@ -1,0 +1,532 @@
+/*
+ * btdf_oracle.c -- plain FP64 CPU oracle for one time step of the
+ * boundary-thickening direct-forcing immersed-boundary lattice Boltzmann
+ * method (BTDF-IB-LBM; Jiang & Liu, arXiv 1806.09403).
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this library. It shares no code with
+ * the HIP library: its own D2Q9 tables, its own delta functions, its own
+ * loops. Everything is double precision. Every loop is the plain form of
+ * the equation it cites; there is no blocking, no fusion and no reordering
+ * beyond Algorithm 1 (Section 2.4) with NF = 1:
+ *
+ *   stream -> moments (eqs 9-10 with the body force, eq 11) ->
+ *   interpolation (eqs 12, 14) -> direct force (eq 20) ->
+ *   spreading with the thickened shell (eqs 13, 15) ->
+ *   hydrodynamic force on each body (eq 27) ->
+ *   equilibrium (eq 6), Guo force term (eq 7), BGK collision (eq 5) ->
+ *   boundary columns.
+ *
+ * The state between steps is the post-collision population A_q(x); the
+ * streaming of Algorithm 1 (last item) is therefore done at the start of
+ * the next pass, g_q(x) = A_q(x - e_q).
+ *
+ * Readings taken where the paper is silent (listed with reasons in the
+ * design notes of the repository):
+ *  - rho in eq 20 is the marker-interpolated density D_I rho;
+ *  - the hydrodynamic force on a body is minus the force the markers apply
+ *    to the fluid, F_p = -drs*ds*sum_l F_l (eq 27 with the sign that makes
+ *    the drag positive), and the torque about the body centre is
+ *    T = -drs*ds*sum_l (X_l - c) x F_l;
+ *  - u* includes half of the uniform body force G, so the immersed
+ *    boundary corrects the total velocity (eq 11 applied to G);
+ *  - the equilibrium and the Guo term use the corrected velocity of eq 11;
+ *  - boundary columns: a velocity inlet is a ghost column i = 0 set to the
+ *    equilibrium at the inlet velocity with the density of column 1 after
+ *    collision; a zero-gradient outlet is a ghost column i = nx-1 copied
+ *    from column nx-2; walls (south/north only) are halfway bounce-back;
+ *    periodic directions wrap the node index;
+ *  - stencil nodes are all nodes whose distance to the marker lies inside
+ *    the support of the delta function (weights at the edge are zero).
+ *
+ * Layout: populations are [q][j][i] with i (x) fastest; nodes sit at
+ * integer coordinates (x, y) = (i, j); lattice units dh = dt = 1.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PERIODIC 0
+#define ORC_VELOCITY_INLET 1
+#define ORC_ZERO_GRADIENT_OUTLET 2
+#define ORC_BOUNCEBACK_WALL 3
+
+#define ORC_LINEAR2 2
+#define ORC_ROMA3 3
+#define ORC_PESKIN4 4
+#define ORC_COS4 5
+
+/* D2Q9 velocities and weights, eq 8 and the weights stated after eq 7. */
+static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const double WQ[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
+                             1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+/* Opposite direction of q: the q' with e_q' = -e_q. */
+static int opposite(int q) {
+  for (int p = 0; p < 9; ++p)
+    if (EX[p] == -EX[q] && EY[p] == -EY[q]) return p;
+  return -1;
+}
+
+/* Regularised delta functions, Section 4.3. */
+double oracle_delta(int kind, double r) {
+  double a = fabs(r);
+  switch (kind) {
+    case ORC_LINEAR2: /* eq 37 */
+      return a <= 1.0 ? 1.0 - a : 0.0;
+    case ORC_ROMA3: /* eq 38 */
+      if (a <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * a * a)) / 3.0;
+      if (a <= 1.5) return (5.0 - 3.0 * a - sqrt(1.0 - 3.0 * (1.0 - a) * (1.0 - a))) / 6.0;
+      return 0.0;
+    case ORC_PESKIN4: /* eq 39 */
+      if (a < 1.0) return (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a)) / 8.0;
+      if (a < 2.0) return (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * a * a)) / 8.0;
+      return 0.0;
+    case ORC_COS4: /* cosine 4-point kernel, (1 + cos(pi r / 2)) / 4 on |r| <= 2 */
+      return a <= 2.0 ? 0.25 * (1.0 + cos(M_PI * a / 2.0)) : 0.0;
+    default:
+      return NAN;
+  }
+}
+
+/* Half-width of the support of each delta function (drf/dh / 2). */
+double oracle_delta_halfwidth(int kind) {
+  switch (kind) {
+    case ORC_LINEAR2: return 1.0;
+    case ORC_ROMA3: return 1.5;
+    case ORC_PESKIN4: return 2.0;
+    case ORC_COS4: return 2.0;
+    default: return -1.0;
+  }
+}
+
+typedef struct {
+  int nx, ny;
+  int bc[4]; /* west, east, south, north */
+  double tau;
+  int kind;
+  double drs; /* thickening * dh, dh = 1 */
+  double G[2];
+  double uin[2];
+  /* grid */
+  double *A;  /* post-collision populations [9][ny][nx] */
+  double *g;  /* streamed populations [9][ny][nx] (fluid nodes only) */
+  double *rho, *mx, *my;  /* moments of g */
+  double *ux, *uy;        /* corrected velocity of the last collision */
+  double *fx, *fy;        /* spread IB force density of the last step */
+  /* markers */
+  int nm, nm_cap;
+  double *X, *Y, *Ub, *Vb;
+  double *rho_l, *ux_l, *uy_l; /* interpolated rho and u* */
+  double *Fx, *Fy;             /* direct force, eq 20 */
+  int *body_of;
+  /* bodies */
+  int nb, nb_cap;
+  int *off; /* markers of body b are off[b] .. off[b+1]-1 */
+  double *cx, *cy, *ds;
+  double *force; /* [nb][3]: Fx, Fy, Tz on each body, last step */
+  long steps;
+  int unstable; /* 0 = fine; 1 + body for a marker trigger; -1 for a node */
+} oracle_t;
+
+static size_t nnode(const oracle_t *o) { return (size_t)o->nx * (size_t)o->ny; }
+static size_t idx(const oracle_t *o, int q, int j, int i) {
+  return ((size_t)q * o->ny + j) * o->nx + i;
+}
+static int x_periodic(const oracle_t *o) { return o->bc[0] == ORC_PERIODIC; }
+static int y_periodic(const oracle_t *o) { return o->bc[2] == ORC_PERIODIC; }
+/* Fluid columns: every column if x is periodic, else 1 .. nx-2 (ghosts at the ends). */
+static int i_first(const oracle_t *o) { return x_periodic(o) ? 0 : 1; }
+static int i_last(const oracle_t *o) { return x_periodic(o) ? o->nx - 1 : o->nx - 2; }
+static int wrap(int i, int n) { return ((i % n) + n) % n; }
+
+/* Equilibrium distribution, eq 6 with c = 1. */
+static double feq(int q, double rho, double ux, double uy) {
+  double eu = EX[q] * ux + EY[q] * uy;
+  double uu = ux * ux + uy * uy;
+  return WQ[q] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+}
+
+oracle_t *oracle_create(int nx, int ny, const int *bc, double tau, int kind,
+                        double thickening, double Gx, double Gy, double uin_x,
+                        double uin_y, double rho0, double ux0, double uy0) {
+  oracle_t *o = (oracle_t *)calloc(1, sizeof(oracle_t));
+  if (!o) return NULL;
+  o->nx = nx;
+  o->ny = ny;
+  memcpy(o->bc, bc, 4 * sizeof(int));
+  o->tau = tau;
+  o->kind = kind;
+  o->drs = thickening;
+  o->G[0] = Gx;
+  o->G[1] = Gy;
+  o->uin[0] = uin_x;
+  o->uin[1] = uin_y;
+  size_t n = nnode(o);
+  o->A = (double *)malloc(9 * n * sizeof(double));
+  o->g = (double *)calloc(9 * n, sizeof(double));
+  o->rho = (double *)calloc(n, sizeof(double));
+  o->mx = (double *)calloc(n, sizeof(double));
+  o->my = (double *)calloc(n, sizeof(double));
+  o->ux = (double *)calloc(n, sizeof(double));
+  o->uy = (double *)calloc(n, sizeof(double));
+  o->fx = (double *)calloc(n, sizeof(double));
+  o->fy = (double *)calloc(n, sizeof(double));
+  o->off = (int *)calloc(1, sizeof(int));
+  if (!o->A || !o->g || !o->rho || !o->mx || !o->my || !o->ux || !o->uy ||
+      !o->fx || !o->fy || !o->off) {
+    free(o);
+    return NULL;
+  }
+  /* Initial state: equilibrium at (rho0, u0) everywhere, ghost columns included. */
+  for (int q = 0; q < 9; ++q)
+    for (size_t k = 0; k < n; ++k) o->A[(size_t)q * n + k] = feq(q, rho0, ux0, uy0);
+  return o;
+}
+
+void oracle_destroy(oracle_t *o) {
+  if (!o) return;
+  free(o->A); free(o->g); free(o->rho); free(o->mx); free(o->my);
+  free(o->ux); free(o->uy); free(o->fx); free(o->fy);
+  free(o->X); free(o->Y); free(o->Ub); free(o->Vb);
+  free(o->rho_l); free(o->ux_l); free(o->uy_l); free(o->Fx); free(o->Fy);
+  free(o->body_of); free(o->off); free(o->cx); free(o->cy); free(o->ds);
+  free(o->force);
+  free(o);
+}
+
+static int grow_markers(oracle_t *o, int need) {
+  if (need <= o->nm_cap) return 0;
+  int cap = need * 2;
+  double **arrs[] = {&o->X, &o->Y, &o->Ub, &o->Vb, &o->rho_l, &o->ux_l, &o->uy_l, &o->Fx, &o->Fy};
+  for (int a = 0; a < 9; ++a) {
+    double *p = (double *)realloc(*arrs[a], (size_t)cap * sizeof(double));
+    if (!p) return -1;
+    *arrs[a] = p;
+  }
+  int *b = (int *)realloc(o->body_of, (size_t)cap * sizeof(int));
+  if (!b) return -1;
+  o->body_of = b;
+  o->nm_cap = cap;
+  return 0;
+}
+
+/* Append one body of n markers. xy, uv are [n][2]; uv may be NULL (at rest).
+ * Returns the body id, or -1. No validation: the tests only feed valid bodies. */
+int oracle_add_body(oracle_t *o, int n, const double *xy, const double *uv,
+                    double cx, double cy, double ds) {
+  if (grow_markers(o, o->nm + n)) return -1;
+  int b = o->nb;
+  int *off = (int *)realloc(o->off, (size_t)(b + 2) * sizeof(int));
+  double *pcx = (double *)realloc(o->cx, (size_t)(b + 1) * sizeof(double));
+  double *pcy = (double *)realloc(o->cy, (size_t)(b + 1) * sizeof(double));
+  double *pds = (double *)realloc(o->ds, (size_t)(b + 1) * sizeof(double));
+  double *pf = (double *)realloc(o->force, (size_t)(b + 1) * 3 * sizeof(double));
+  if (!off || !pcx || !pcy || !pds || !pf) return -1;
+  o->off = off; o->cx = pcx; o->cy = pcy; o->ds = pds; o->force = pf;
+  for (int l = 0; l < n; ++l) {
+    int m = o->nm + l;
+    o->X[m] = xy[2 * l];
+    o->Y[m] = xy[2 * l + 1];
+    o->Ub[m] = uv ? uv[2 * l] : 0.0;
+    o->Vb[m] = uv ? uv[2 * l + 1] : 0.0;
+    o->rho_l[m] = o->ux_l[m] = o->uy_l[m] = o->Fx[m] = o->Fy[m] = 0.0;
+    o->body_of[m] = b;
+  }
+  o->off[b] = o->nm;
+  o->nm += n;
+  o->off[b + 1] = o->nm;
+  o->cx[b] = cx;
+  o->cy[b] = cy;
+  o->ds[b] = ds;
+  o->force[3 * b] = o->force[3 * b + 1] = o->force[3 * b + 2] = 0.0;
+  o->nb += 1;
+  return b;
+}
+
+void oracle_set_marker_velocity(oracle_t *o, int b, const double *uv) {
+  for (int m = o->off[b]; m < o->off[b + 1]; ++m) {
+    int l = m - o->off[b];
+    o->Ub[m] = uv[2 * l];
+    o->Vb[m] = uv[2 * l + 1];
+  }
+}
+
+/* Streaming (Algorithm 1, last item, applied at the start of the next pass):
+ * g_q(x) = A_q(x - e_q) at every fluid node, with the boundary readings above. */
+static void stream(oracle_t *o) {
+  int nx = o->nx, ny = o->ny;
+  int i0 = i_first(o), i1 = i_last(o);
+  for (int q = 0; q < 9; ++q) {
+    int qb = opposite(q);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j) {
+      for (int i = i0; i <= i1; ++i) {
+        int sj = j - EY[q];
+        int si = i - EX[q];
+        double val;
+        if (sj < 0 || sj >= ny) {
+          if (y_periodic(o)) {
+            sj = wrap(sj, ny);
+            if (x_periodic(o)) si = wrap(si, nx);
+            val = o->A[idx(o, q, sj, si)];
+          } else {
+            /* halfway bounce-back: the population that left towards the wall returns */
+            val = o->A[idx(o, qb, j, i)];
+          }
+        } else {
+          if (x_periodic(o)) si = wrap(si, nx);
+          val = o->A[idx(o, q, sj, si)];
+        }
+        o->g[idx(o, q, j, i)] = val;
+      }
+    }
+  }
+}
+
+/* Zeroth and first moments of g (eqs 9-10). */
+static void moments(oracle_t *o) {
+  int i0 = i_first(o), i1 = i_last(o);
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < o->ny; ++j) {
+    for (int i = i0; i <= i1; ++i) {
+      double r = 0.0, mx = 0.0, my = 0.0;
+      for (int q = 0; q < 9; ++q) {
+        double v = o->g[idx(o, q, j, i)];
+        r += v;
+        mx += EX[q] * v;
+        my += EY[q] * v;
+      }
+      size_t k = (size_t)j * o->nx + i;
+      o->rho[k] = r;
+      o->mx[k] = mx;
+      o->my[k] = my;
+    }
+  }
+}
+
+/* Node memory index of the (possibly out-of-range) integer coordinate (i, j):
+ * periodic directions wrap; the tests keep non-periodic stencils inside the grid. */
+static size_t node_of(const oracle_t *o, int i, int j) {
+  if (x_periodic(o)) i = wrap(i, o->nx);
+  if (y_periodic(o)) j = wrap(j, o->ny);
+  return (size_t)j * o->nx + i;
+}
+
+/* Interpolation (eqs 12, 14), direct force (eq 20), spreading (eqs 13, 15)
+ * and hydrodynamic force and torque (eq 27) for every marker, NF = 1. All
+ * markers see the same u* (the interpolation of every marker happens before
+ * any spreading). */
+static void immersed_boundary(oracle_t *o) {
+  size_t n = nnode(o);
+  double h = oracle_delta_halfwidth(o->kind);
+  for (size_t k = 0; k < n; ++k) o->fx[k] = o->fy[k] = 0.0;
+
+  /* interpolation + direct force */
+  for (int m = 0; m < o->nm; ++m) {
+    double X = o->X[m], Y = o->Y[m];
+    double rl = 0.0, ul = 0.0, vl = 0.0;
+    for (int j = (int)ceil(Y - h); j <= (int)floor(Y + h); ++j) {
+      for (int i = (int)ceil(X - h); i <= (int)floor(X + h); ++i) {
+        double W = oracle_delta(o->kind, i - X) * oracle_delta(o->kind, j - Y);
+        size_t k = node_of(o, i, j);
+        double r = o->rho[k];
+        double us = (o->mx[k] + 0.5 * o->G[0]) / r; /* u* with G/2 */
+        double vs = (o->my[k] + 0.5 * o->G[1]) / r;
+        rl += W * r;
+        ul += W * us;
+        vl += W * vs;
+      }
+    }
+    o->rho_l[m] = rl;
+    o->ux_l[m] = ul;
+    o->uy_l[m] = vl;
+    o->Fx[m] = 2.0 * rl * (o->Ub[m] - ul); /* eq 20, dt = 1 */
+    o->Fy[m] = 2.0 * rl * (o->Vb[m] - vl);
+    int bad = !isfinite(o->Fx[m]) || !isfinite(o->Fy[m]) || !(sqrt(ul * ul + vl * vl) <= 0.3);
+    if (bad && o->unstable == 0) o->unstable = 1 + o->body_of[m];
+  }
+
+  /* spreading with the thickened solid shell: f(x_k) += W F_l drs ds / dh^2 */
+  for (int m = 0; m < o->nm; ++m) {
+    double X = o->X[m], Y = o->Y[m];
+    double s = o->drs * o->ds[o->body_of[m]];
+    for (int j = (int)ceil(Y - h); j <= (int)floor(Y + h); ++j) {
+      for (int i = (int)ceil(X - h); i <= (int)floor(X + h); ++i) {
+        double W = oracle_delta(o->kind, i - X) * oracle_delta(o->kind, j - Y);
+        size_t k = node_of(o, i, j);
+        o->fx[k] += W * o->Fx[m] * s;
+        o->fy[k] += W * o->Fy[m] * s;
+      }
+    }
+  }
+
+  /* force and torque on each body: minus what its markers apply to the fluid */
+  for (int b = 0; b < o->nb; ++b) {
+    double sx = 0.0, sy = 0.0, tz = 0.0;
+    for (int m = o->off[b]; m < o->off[b + 1]; ++m) {
+      sx += o->Fx[m];
+      sy += o->Fy[m];
+      tz += (o->X[m] - o->cx[b]) * o->Fy[m] - (o->Y[m] - o->cy[b]) * o->Fx[m];
+    }
+    double s = o->drs * o->ds[b];
+    o->force[3 * b] = -s * sx;
+    o->force[3 * b + 1] = -s * sy;
+    o->force[3 * b + 2] = -s * tz;
+  }
+}
+
+/* Corrected velocity (eq 11), equilibrium (eq 6), Guo force (eq 7) and the
+ * BGK collision (eq 5) at every fluid node, written into A. */
+static void collide(oracle_t *o) {
+  int i0 = i_first(o), i1 = i_last(o);
+  double tau = o->tau;
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+  for (int j = 0; j < o->ny; ++j) {
+    for (int i = i0; i <= i1; ++i) {
+      size_t k = (size_t)j * o->nx + i;
+      double r = o->rho[k];
+      double ftx = o->G[0] + o->fx[k];
+      double fty = o->G[1] + o->fy[k];
+      double ux = (o->mx[k] + 0.5 * ftx) / r;
+      double uy = (o->my[k] + 0.5 * fty) / r;
+      o->ux[k] = ux;
+      o->uy[k] = uy;
+      if (!(r > 0.0) || !isfinite(r)) bad = 1;
+      for (int q = 0; q < 9; ++q) {
+        double eu = EX[q] * ux + EY[q] * uy;
+        double Fq = (1.0 - 1.0 / (2.0 * tau)) * WQ[q] *
+                    ((3.0 * (EX[q] - ux) + 9.0 * eu * EX[q]) * ftx +
+                     (3.0 * (EY[q] - uy) + 9.0 * eu * EY[q]) * fty);
+        double gq = o->g[idx(o, q, j, i)];
+        o->A[idx(o, q, j, i)] = gq - (gq - feq(q, r, ux, uy)) / tau + Fq;
+      }
+    }
+  }
+  if (bad && o->unstable == 0) o->unstable = -1;
+}
+
+/* Ghost columns of the channel: velocity inlet and zero-gradient outlet. */
+static void boundary_columns(oracle_t *o) {
+  int nx = o->nx;
+  if (o->bc[0] == ORC_VELOCITY_INLET) {
+    for (int j = 0; j < o->ny; ++j) {
+      double r = 0.0;
+      for (int q = 0; q < 9; ++q) r += o->A[idx(o, q, j, 1)];
+      for (int q = 0; q < 9; ++q) o->A[idx(o, q, j, 0)] = feq(q, r, o->uin[0], o->uin[1]);
+    }
+  }
+  if (o->bc[1] == ORC_ZERO_GRADIENT_OUTLET) {
+    for (int j = 0; j < o->ny; ++j)
+      for (int q = 0; q < 9; ++q) o->A[idx(o, q, j, nx - 1)] = o->A[idx(o, q, j, nx - 2)];
+  }
+}
+
+void oracle_step(oracle_t *o, long n) {
+  for (long s = 0; s < n; ++s) {
+    stream(o);
+    moments(o);
+    immersed_boundary(o);
+    collide(o);
+    boundary_columns(o);
+    o->steps += 1;
+  }
+}
+
+/* Replace the state by the equilibrium of the given fields ([ny][nx] each;
+ * rho may be NULL for rho = 1). Clears the instability flag. */
+void oracle_init_equilibrium(oracle_t *o, const double *rho, const double *ux, const double *uy) {
+  size_t n = nnode(o);
+  for (int q = 0; q < 9; ++q)
+    for (size_t k = 0; k < n; ++k)
+      o->A[(size_t)q * n + k] = feq(q, rho ? rho[k] : 1.0, ux[k], uy[k]);
+  o->unstable = 0;
+}
+
+void oracle_get_populations(const oracle_t *o, double *dst) {
+  memcpy(dst, o->A, 9 * nnode(o) * sizeof(double));
+}
+
+void oracle_set_populations(oracle_t *o, const double *src) {
+  memcpy(o->A, src, 9 * nnode(o) * sizeof(double));
+  o->unstable = 0;
+}
+
+/* Macroscopic state of the current populations: at fluid nodes, rho and
+ * u* = (sum e g + G/2) / rho of the streamed populations; at ghost columns,
+ * plain moments of A at the ghost node. */
+void oracle_get_macroscopic(oracle_t *o, double *rho, double *ux, double *uy) {
+  stream(o);
+  moments(o);
+  int nx = o->nx;
+  for (int j = 0; j < o->ny; ++j) {
+    for (int i = 0; i < nx; ++i) {
+      size_t k = (size_t)j * nx + i;
+      if (i < i_first(o) || i > i_last(o)) {
+        double r = 0.0, mx = 0.0, my = 0.0;
+        for (int q = 0; q < 9; ++q) {
+          double v = o->A[idx(o, q, j, i)];
+          r += v;
+          mx += EX[q] * v;
+          my += EY[q] * v;
+        }
+        rho[k] = r;
+        ux[k] = mx / r;
+        uy[k] = my / r;
+      } else {
+        rho[k] = o->rho[k];
+        ux[k] = (o->mx[k] + 0.5 * o->G[0]) / o->rho[k];
+        uy[k] = (o->my[k] + 0.5 * o->G[1]) / o->rho[k];
+      }
+    }
+  }
+}
+
+/* Per-marker quantities of the last step: interpolated rho and u*, and F_l. */
+void oracle_marker_data(const oracle_t *o, double *rho_l, double *ux_l, double *uy_l,
+                        double *Fx, double *Fy) {
+  for (int m = 0; m < o->nm; ++m) {
+    rho_l[m] = o->rho_l[m];
+    ux_l[m] = o->ux_l[m];
+    uy_l[m] = o->uy_l[m];
+    Fx[m] = o->Fx[m];
+    Fy[m] = o->Fy[m];
+  }
+}
+
+/* Velocity at the markers after forcing: D_I applied to the corrected
+ * velocity u of eq 11 from the last collision. Feeds the boundary error of
+ * eq 45. */
+void oracle_marker_corrected_velocity(const oracle_t *o, double *ux_c, double *uy_c) {
+  double h = oracle_delta_halfwidth(o->kind);
+  for (int m = 0; m < o->nm; ++m) {
+    double X = o->X[m], Y = o->Y[m], su = 0.0, sv = 0.0;
+    for (int j = (int)ceil(Y - h); j <= (int)floor(Y + h); ++j) {
+      for (int i = (int)ceil(X - h); i <= (int)floor(X + h); ++i) {
+        double W = oracle_delta(o->kind, i - X) * oracle_delta(o->kind, j - Y);
+        size_t k = node_of(o, i, j);
+        su += W * o->ux[k];
+        sv += W * o->uy[k];
+      }
+    }
+    ux_c[m] = su;
+    uy_c[m] = sv;
+  }
+}
+
+void oracle_get_force_field(const oracle_t *o, double *fx, double *fy) {
+  memcpy(fx, o->fx, nnode(o) * sizeof(double));
+  memcpy(fy, o->fy, nnode(o) * sizeof(double));
+}
+
+void oracle_body_forces(const oracle_t *o, double *out) {
+  memcpy(out, o->force, (size_t)o->nb * 3 * sizeof(double));
+}
+
+int oracle_unstable(const oracle_t *o) { return o->unstable; }
+long oracle_steps(const oracle_t *o) { return o->steps; }
+int oracle_num_markers(const oracle_t *o) { return o->nm; }
+int oracle_num_bodies(const oracle_t *o) { return o->nb; }

@@ -1,0 +1,183 @@
+"""ctypes wrapper of the FP64 CPU oracle (``btdf_oracle.c``).
+
+TEST INFRASTRUCTURE: only the tests, the smoke check and the benchmark's
+CPU-baseline leg use this module. Nothing here is shared with the HIP
+library; the two meet only through the seeded inputs of ``btdf_workloads``.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+PERIODIC, VELOCITY_INLET, ZERO_GRADIENT_OUTLET, BOUNCEBACK_WALL = 0, 1, 2, 3
+LINEAR2, ROMA3, PESKIN4, COS4 = 2, 3, 4, 5
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def lib():
+    """Load the oracle library, building it with gcc if it is not there."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        L.oracle_create.restype = ctypes.c_void_p
+        L.oracle_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                    ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double]
+        L.oracle_destroy.argtypes = [ctypes.c_void_p]
+        L.oracle_add_body.restype = ctypes.c_int
+        L.oracle_add_body.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.oracle_set_marker_velocity.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
+        L.oracle_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
+        L.oracle_init_equilibrium.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        L.oracle_get_populations.argtypes = [ctypes.c_void_p, _dp]
+        L.oracle_set_populations.argtypes = [ctypes.c_void_p, _dp]
+        L.oracle_get_macroscopic.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        L.oracle_marker_data.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_marker_corrected_velocity.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.oracle_get_force_field.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.oracle_body_forces.argtypes = [ctypes.c_void_p, _dp]
+        L.oracle_unstable.restype = ctypes.c_int
+        L.oracle_unstable.argtypes = [ctypes.c_void_p]
+        L.oracle_steps.restype = ctypes.c_long
+        L.oracle_steps.argtypes = [ctypes.c_void_p]
+        L.oracle_num_markers.restype = ctypes.c_int
+        L.oracle_num_markers.argtypes = [ctypes.c_void_p]
+        L.oracle_num_bodies.restype = ctypes.c_int
+        L.oracle_num_bodies.argtypes = [ctypes.c_void_p]
+        L.oracle_delta.restype = ctypes.c_double
+        L.oracle_delta.argtypes = [ctypes.c_int, ctypes.c_double]
+        L.oracle_delta_halfwidth.restype = ctypes.c_double
+        L.oracle_delta_halfwidth.argtypes = [ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def delta(kind, r):
+    """Regularised delta function phi(r) of Section 4.3 (vectorised over r)."""
+    L = lib()
+    r = np.asarray(r, dtype=np.float64)
+    return np.vectorize(lambda v: L.oracle_delta(int(kind), float(v)))(r).astype(np.float64)
+
+
+class OracleSim:
+    """One FP64 BTDF-IB-LBM simulation on the host (Algorithm 1, NF = 1)."""
+
+    def __init__(self, nx, ny, bc, tau, kind, thickening, G=(0.0, 0.0),
+                 inflow=(0.0, 0.0), init=(1.0, 0.0, 0.0)):
+        self.nx, self.ny = int(nx), int(ny)
+        self.kind = int(kind)
+        bc_arr = (ctypes.c_int * 4)(*[int(b) for b in bc])
+        self._h = lib().oracle_create(self.nx, self.ny, bc_arr, float(tau), self.kind,
+                                      float(thickening), float(G[0]), float(G[1]),
+                                      float(inflow[0]), float(inflow[1]),
+                                      float(init[0]), float(init[1]), float(init[2]))
+        if not self._h:
+            raise MemoryError("oracle_create failed")
+        self.body_sizes = []
+
+    def close(self):
+        if self._h:
+            lib().oracle_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_body(self, xy, uv=None, cx=0.0, cy=0.0, ds=None):
+        xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+        n = xy.shape[0]
+        if ds is None:
+            # polygon perimeter / n
+            d = np.roll(xy, -1, axis=0) - xy
+            ds = float(np.sum(np.hypot(d[:, 0], d[:, 1])) / n)
+        if uv is None:
+            uvp = ctypes.cast(None, _dp)
+        else:
+            uv = np.ascontiguousarray(uv, dtype=np.float64).reshape(n, 2)
+            uvp = _ptr(uv)
+        b = lib().oracle_add_body(self._h, n, _ptr(xy), uvp, float(cx), float(cy), float(ds))
+        if b < 0:
+            raise MemoryError("oracle_add_body failed")
+        self.body_sizes.append(n)
+        return b
+
+    def set_marker_velocity(self, b, uv):
+        uv = np.ascontiguousarray(uv, dtype=np.float64).reshape(-1, 2)
+        lib().oracle_set_marker_velocity(self._h, int(b), _ptr(uv))
+
+    def step(self, n=1):
+        lib().oracle_step(self._h, int(n))
+
+    def init_equilibrium(self, ux, uy, rho=None):
+        ux = np.ascontiguousarray(ux, dtype=np.float64).reshape(self.ny, self.nx)
+        uy = np.ascontiguousarray(uy, dtype=np.float64).reshape(self.ny, self.nx)
+        rp = ctypes.cast(None, _dp)
+        if rho is not None:
+            rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(self.ny, self.nx)
+            rp = _ptr(rho)
+        lib().oracle_init_equilibrium(self._h, rp, _ptr(ux), _ptr(uy))
+
+    def populations(self):
+        out = np.empty((9, self.ny, self.nx), dtype=np.float64)
+        lib().oracle_get_populations(self._h, _ptr(out))
+        return out
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(9, self.ny, self.nx)
+        lib().oracle_set_populations(self._h, _ptr(f))
+
+    def macroscopic(self):
+        r = np.empty((self.ny, self.nx))
+        u = np.empty((self.ny, self.nx))
+        v = np.empty((self.ny, self.nx))
+        lib().oracle_get_macroscopic(self._h, _ptr(r), _ptr(u), _ptr(v))
+        return r, u, v
+
+    def marker_data(self):
+        m = lib().oracle_num_markers(self._h)
+        arrs = [np.empty(m) for _ in range(5)]
+        lib().oracle_marker_data(self._h, *[_ptr(a) for a in arrs])
+        return dict(zip(["rho", "ux", "uy", "Fx", "Fy"], arrs))
+
+    def marker_corrected_velocity(self):
+        m = lib().oracle_num_markers(self._h)
+        u, v = np.empty(m), np.empty(m)
+        lib().oracle_marker_corrected_velocity(self._h, _ptr(u), _ptr(v))
+        return u, v
+
+    def force_field(self):
+        fx = np.empty((self.ny, self.nx))
+        fy = np.empty((self.ny, self.nx))
+        lib().oracle_get_force_field(self._h, _ptr(fx), _ptr(fy))
+        return fx, fy
+
+    def forces(self):
+        nb = lib().oracle_num_bodies(self._h)
+        out = np.empty((nb, 3))
+        if nb:
+            lib().oracle_body_forces(self._h, _ptr(out))
+        return out
+
+    @property
+    def unstable(self):
+        return lib().oracle_unstable(self._h)
+
+    @property
+    def steps(self):
+        return lib().oracle_steps(self._h)
