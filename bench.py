@@ -1,0 +1,149 @@
+"""Throughput of the BTDF-IB-LBM step on one MI355X.
+
+Default workload: the particle-laden periodic lattice, 8192 x 8192 nodes,
+2000 fixed cylinders of D = 24 (75 markers each, 150 000 markers), uniform
+body force, FP32 populations, cosine 4-point delta with drs = 2.6 dh. One
+step = the marker kernel (interpolation, direct force, per-body force and
+torque) + the lattice kernel (streaming, spread gather, collision). Inputs
+are synthetic and seeded; everything is resident in HBM before timing.
+
+Prints one JSON line: MLUPS (whole job), ms per step, the roofline of the
+lattice kernel (72 algorithmic bytes per lattice update against 8 TB/s,
+timed with HIP events on the library's stream over the timed region), and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10000)
+    p.add_argument("--warmup", type=int, default=200)
+    p.add_argument("--workload", choices=["particles", "shedding", "channel"], default="particles")
+    p.add_argument("--delta", choices=["cos4", "roma3", "peskin4"], default="cos4")
+    p.add_argument("--variant", type=int, default=-1, help="lattice launch shape (-1: library default)")
+    p.add_argument("--graph-chunk", type=int, default=0)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-budget-s", type=float, default=20.0)
+    return p.parse_args()
+
+
+def make_case(args):
+    import btdf_workloads as W
+    kind = {"cos4": W.COS4, "roma3": W.ROMA3, "peskin4": W.PESKIN4}[args.delta]
+    if args.workload == "particles":
+        return W.c3(kind=kind), 4
+    if args.workload == "shedding":
+        return W.c2(kind=kind), 4
+    return W.c1(kind=kind), 8
+
+
+def cpu_baseline(case, budget_s):
+    """The FP64 oracle on the same lattice and bodies: one step to size the
+    sample, then as many more as fit the budget."""
+    import numpy as np
+    from oracle import oracle
+    o = oracle.OracleSim(case.nx, case.ny, case.bc, case.tau, case.kind, case.thickening, case.G,
+                         case.inflow, case.init)
+    for b in case.bodies:
+        o.add_body(b.xy, b.uv, b.cx, b.cy, b.ds)
+    if case.init_uy is not None:
+        ux, uy = case.init_fields()
+        o.init_equilibrium(ux, uy, np.full((case.ny, case.nx), case.init[0]))
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter()
+    k = max(1, int((budget_s - (t1 - t0)) / max(t1 - t0, 1e-9)))
+    o.step(k)
+    t2 = time.perf_counter()
+    steps = 1 + k
+    mlups = case.nodes * steps / (t2 - t0) / 1e6
+    o.close()
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%s: %d FP64 oracle steps of the full %dx%d lattice with all %d bodies (%.1f s)"
+                      % (case.name, steps, case.nx, case.ny, len(case.bodies), t2 - t0)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1806_09403_amd import Sim, _lib
+
+    case, prec = make_case(args)
+    t_setup = time.perf_counter()
+    sim = Sim.from_case(case, precision=prec)
+    if args.variant >= 0:
+        sim.set_option(_lib.OPT_LBM_VARIANT, args.variant)
+    if args.graph_chunk:
+        sim.set_option(_lib.OPT_GRAPH_CHUNK, args.graph_chunk)
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    print("setup + warmup %.1f s" % (time.perf_counter() - t_setup), file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_ib, ms_lbm = sim.step_timed(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.forces()  # surfaces an instability as an error
+
+    n = case.nodes
+    wall = t1 - t0
+    ms_step = wall * 1e3 / args.steps
+    mlups = n * args.steps / wall / 1e6
+    bytes_per_update = 9 * 2 * prec
+    achieved = n * bytes_per_update / (ms_lbm * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        key = "%s-%s-v%d" % (args.workload, args.delta, sim.get_option(_lib.OPT_LBM_VARIANT))
+        traffic = t.get(key)
+    nb, nm, _ = sim.counts()
+    line = {
+        "metric": "MLUPS (D2Q9+BTDF-IB)",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == 4 else "f64",
+        "data": "synthetic",
+        "config": {"workload": case.name, "nx": case.nx, "ny": case.ny, "bodies": nb, "markers": nm,
+                   "delta": args.delta, "thickening": case.thickening, "tau": case.tau,
+                   "lbm_variant": sim.get_option(_lib.OPT_LBM_VARIANT),
+                   "graph_chunk": args.graph_chunk},
+        "kernel_ms": {"ib_kernel": round(ms_ib, 5), "lbm_kernel": round(ms_lbm, 5)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "lbm_kernel", "bytes_per_update": bytes_per_update},
+    }
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(case, args.cpu_budget_s)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,226 @@
+/*
+ * btdf.h -- C ABI of the MI355X (gfx950) library for the boundary-thickening
+ * direct-forcing immersed-boundary lattice Boltzmann method (BTDF-IB-LBM) of
+ * Jiang & Liu, arXiv 1806.09403.
+ *
+ * One handle holds one 2-D D2Q9 simulation on one GPU: a grid of N_E
+ * Eulerian nodes and any number of rigid bodies, each represented by N_L
+ * Lagrangian markers with prescribed velocities U_b (Section 2.2). One time
+ * step is Algorithm 1 (Section 2.4) with NF = 1:
+ *   streaming, moments (eqs 9-10), interpolation of the unforced velocity to
+ *   the markers (eqs 12, 14), the direct force F_b = 2 rho (U_b - D_I u*)
+ *   (eq 20), spreading with the thickened solid shell drs (eqs 13, 15), the
+ *   hydrodynamic force and torque on each body (eq 27), and the BGK collision
+ *   with the Guo force term (eqs 5-7, 11).
+ *
+ * Units: lattice units, dh = dt = c = 1; node (i, j) sits at (x, y) = (i, j).
+ *
+ * Conventions shared by every call:
+ *  - Every call returns an int status: BTDF_OK (0) or a negative BTDF_E*
+ *    code. Nothing throws, aborts or exits across the ABI. The message of the
+ *    last failure on the calling thread is returned by btdf_last_error().
+ *  - A handle is used by one thread at a time.
+ *  - "Host array" means memory the caller owns; the library copies what it
+ *    needs during the call and keeps no pointer to it.
+ *  - Host field arrays are double precision, row-major [ny][nx] (x fastest);
+ *    population arrays are [9][ny][nx] with the D2Q9 order of eq 8:
+ *    e = (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1).
+ *  - Device memory is either one caller-owned workspace (btdf_bind_workspace,
+ *    e.g. a PyTorch tensor) or, if none is bound, allocated by the library.
+ *  - Work is enqueued on the handle's HIP stream; calls documented as
+ *    "synchronising" wait for that stream before returning.
+ */
+#ifndef BTDF_H
+#define BTDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define BTDF_OK 0
+#define BTDF_EINVAL (-1)    /* bad argument; nothing was changed */
+#define BTDF_ENOMEM (-2)    /* host or device allocation failed, or workspace too small */
+#define BTDF_EDEVICE (-3)   /* a HIP call or kernel launch failed */
+#define BTDF_ESTATE (-4)    /* call not valid in the current state */
+#define BTDF_EUNSTABLE (-5) /* the run went unstable (see btdf_step) */
+
+/* ---- boundary kinds (btdf_grid.bc_*) ----
+ * x ends: both PERIODIC, or VELOCITY_INLET (west) + ZERO_GRADIENT_OUTLET (east).
+ *   The channel ends are ghost columns i = 0 and i = nx-1 that are neither
+ *   collided nor forced. After each collision the inlet ghost is set to the
+ *   equilibrium (eq 6) at the inflow velocity with the density of column 1,
+ *   and the outlet ghost copies column nx-2.
+ * y ends: both PERIODIC, or both BOUNCEBACK_WALL (halfway bounce-back,
+ *   walls at y = -1/2 and y = ny - 1/2). */
+#define BTDF_PERIODIC 0
+#define BTDF_VELOCITY_INLET 1
+#define BTDF_ZERO_GRADIENT_OUTLET 2
+#define BTDF_BOUNCEBACK_WALL 3
+
+/* ---- regularised delta functions (Section 4.3) ----
+ * LINEAR2: 2-point, eq 37;  ROMA3: 3-point, eq 38;  PESKIN4: 4-point, eq 39;
+ * COS4: the cosine 4-point kernel (1 + cos(pi r / 2)) / 4 on |r| <= 2.
+ * Stencils: LINEAR2 floor(X) .. floor(X)+1; ROMA3 floor(X+1/2)-1 .. +1;
+ * PESKIN4 and COS4 floor(X)-1 .. floor(X)+2 (per direction). */
+#define BTDF_LINEAR2 2
+#define BTDF_ROMA3 3
+#define BTDF_PESKIN4 4
+#define BTDF_COS4 5
+
+/* ---- option keys (btdf_set_option / btdf_get_option) ---- */
+#define BTDF_OPT_LBM_VARIANT 1   /* launch shape of the lattice kernel, 0 .. BTDF_OPT_NUM_VARIANTS-1 */
+#define BTDF_OPT_NUM_VARIANTS 2  /* read-only: number of lattice launch shapes */
+#define BTDF_OPT_GRAPH_CHUNK 3   /* steps per captured HIP graph; 0 = plain launches (default 0) */
+#define BTDF_OPT_XCD_REMAP 4     /* 1 = map consecutive tiles to one XCD (default 1) */
+#define BTDF_OPT_TILE_X 5        /* read-only: tile width of the current variant */
+#define BTDF_OPT_TILE_Y 6        /* read-only: tile height of the current variant */
+
+typedef struct btdf_grid {
+  int32_t nx, ny;               /* nodes, ghost columns included; each >= 8 */
+  int32_t bc_west, bc_east;     /* BTDF_PERIODIC pair or VELOCITY_INLET + ZERO_GRADIENT_OUTLET */
+  int32_t bc_south, bc_north;   /* BTDF_PERIODIC pair or BOUNCEBACK_WALL pair */
+  double inflow_ux, inflow_uy;  /* velocity of the inlet ghost column */
+  double body_force_x;          /* uniform body-force density G (force per node) */
+  double body_force_y;
+  double rho0, ux0, uy0;        /* initial state: equilibrium at (rho0, u0) everywhere */
+  int32_t precision;            /* 4: FP32 populations, 8: FP64 populations */
+  int32_t history_capacity;     /* steps kept in the per-body force ring; 0 -> 4096 */
+  void *hip_stream;             /* hipStream_t to enqueue on; NULL = the null stream */
+  uint64_t flags;               /* reserved, must be 0 */
+} btdf_grid;
+
+typedef struct btdf_sim btdf_t;
+
+/* Message of the last failed call on this thread ("" if none). The pointer
+ * stays valid until the next call on the same thread. */
+const char *btdf_last_error(void);
+
+/* Create a simulation. tau > 1/2 is the BGK relaxation time (nu = (tau -
+ * 1/2)/3, the relation stated after eq 7); delta_kind is one of BTDF_LINEAR2
+ * .. BTDF_COS4; thickening = drs/dh > 0 is the solid-shell thickness of eq 15
+ * (1.0 is conventional direct forcing, eq 28; the paper suggests 1.4, 1.9
+ * and 2.6 for 2-, 3- and 4-point deltas, Section 4.4). No device memory is
+ * touched until the first call that needs it; the populations then start
+ * at the equilibrium (eq 6) at (rho0, u0), ghost columns included.
+ * Errors: EINVAL (NULL pointers, nx or ny < 8, tau <= 1/2, unknown kind,
+ * thickening <= 0, bad boundary combination, precision not 4 or 8, flags != 0).
+ * ENOMEM. */
+int btdf_create(const btdf_grid *g, double tau, int delta_kind, double thickening, btdf_t **out);
+
+/* Free everything the library allocated (not a bound workspace). Waits for
+ * the handle's stream. NULL is accepted. */
+int btdf_destroy(btdf_t *h);
+
+/* Device bytes the current grid and body set need in a caller-owned
+ * workspace (256-byte aligned start required). 0 on a NULL handle. */
+size_t btdf_workspace_bytes(const btdf_t *h);
+
+/* Use dev[0 .. bytes) as all device memory of the handle from now on. The
+ * caller keeps it alive until btdf_destroy or the next bind. If a state
+ * exists it is moved into the new workspace (synchronising). Passing NULL
+ * returns to library-owned memory. Errors: EINVAL (misaligned), ENOMEM
+ * (bytes < btdf_workspace_bytes), EDEVICE. Adding a body may later raise the
+ * requirement; calls that need device memory then return ENOMEM until a
+ * large enough workspace is bound. */
+int btdf_bind_workspace(btdf_t *h, void *dev, size_t bytes);
+
+/* Enqueue all further work on hip_stream (NULL = null stream). */
+int btdf_set_stream(btdf_t *h, void *hip_stream);
+
+/* Add a rigid body of n >= 3 markers. xy: host array [n][2] of marker
+ * positions X_l (eq 12); uv: host array [n][2] of prescribed velocities
+ * U_b,l, or NULL for a body at rest; (cx, cy): the reference point of the
+ * torque; ds > 0: the marker spacing of eq 15, or <= 0 for the polygon
+ * perimeter / n. Markers may lie outside [0, nx) in a periodic direction
+ * (their stencils wrap). In a non-periodic direction every stencil node must
+ * be a fluid node (x in 1 .. nx-2 for a channel, y in 0 .. ny-1 for walls).
+ * The body id (0, 1, ...) is written to *body_id if not NULL. Adding a body
+ * resets the force history. Errors: EINVAL, ENOMEM. */
+int btdf_add_body(btdf_t *h, int n, const double *xy, const double *uv, double cx, double cy,
+                  double ds, int *body_id);
+
+/* Replace the prescribed marker velocities of one body; uv: host [n][2].
+ * Takes effect from the next enqueued step (synchronising). */
+int btdf_set_marker_velocity(btdf_t *h, int body, const double *uv);
+
+/* Enqueue n >= 0 time steps (asynchronous). If during them a marker's
+ * force became non-finite, a marker's interpolated |u*| exceeded 0.3, or a
+ * node density became non-positive or non-finite, the next synchronising
+ * call returns BTDF_EUNSTABLE (the flag stays set until the populations are
+ * replaced by btdf_init_equilibrium, btdf_set_populations or btdf_load). */
+int btdf_step(btdf_t *h, int64_t n);
+
+/* Same as btdf_step, but times each kernel launch with HIP events on the
+ * handle's stream and writes the mean duration per launch in milliseconds
+ * of the marker kernel (*ms_ib, 0 if no bodies) and of the lattice kernel
+ * (*ms_lbm). Synchronising. */
+int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm);
+
+/* Hydrodynamic force and torque on every body at the last step:
+ * out[3*b + 0..2] = (Fx, Fy, Tz), Fx,y = -drs ds sum_l F_l (eq 27, sign:
+ * force of the fluid on the body), Tz = -drs ds sum_l (X_l - c) x F_l.
+ * Zeros before the first step. Synchronising. Errors: EINVAL (cap_bodies <
+ * number of bodies), EUNSTABLE (values still written). */
+int btdf_forces(btdf_t *h, double *out, int cap_bodies);
+
+/* Per-step (Fx, Fy, Tz) of every body for the steps not yet returned, oldest
+ * first, at most max_steps of them: out[(k*nbodies + b)*3 + c]. Steps older
+ * than the ring capacity are dropped. *n_written receives the count.
+ * Synchronising. */
+int btdf_force_history(btdf_t *h, double *out, int64_t max_steps, int64_t *n_written);
+
+/* Replace the populations by the equilibrium (eq 6) of the host fields rho,
+ * ux, uy ([ny][nx]; rho may be NULL for rho0 everywhere). Synchronising. */
+int btdf_init_equilibrium(btdf_t *h, const double *rho, const double *ux, const double *uy);
+
+/* Density and velocity of the current state, host [ny][nx] each. At fluid
+ * nodes: rho = sum_q g_q and u* = (sum_q e_q g_q + G/2) / rho of the
+ * streamed populations g_q(x) = f_q(x - e_q) (what the next step
+ * interpolates); at channel ghost columns: plain moments of the ghost node.
+ * Synchronising. */
+int btdf_get_macroscopic(btdf_t *h, double *rho, double *ux, double *uy);
+
+/* Post-collision populations f_q (full values, not deviations) as host FP64
+ * [9][ny][nx]; set replaces them (rounded to the handle's precision) and
+ * clears the instability flag. Synchronising. */
+int btdf_get_populations(btdf_t *h, double *dst);
+int btdf_set_populations(btdf_t *h, const double *src);
+
+/* Per-marker values of the last step (host arrays of length = total
+ * markers, any may be NULL): interpolated rho_l and u*_l (eqs 12, 14) and
+ * the direct force F_l (eq 20). Synchronising. */
+int btdf_get_marker_data(btdf_t *h, double *rho_l, double *ux_l, double *uy_l, double *Fx,
+                         double *Fy);
+
+/* Checkpoint: the populations in the handle's own precision plus the step
+ * counter. btdf_state_bytes gives the size; save writes it into the host
+ * buffer dst, load restores it (bit-identical resume). Synchronising. */
+size_t btdf_state_bytes(const btdf_t *h);
+int btdf_save(btdf_t *h, void *dst, size_t bytes);
+int btdf_load(btdf_t *h, const void *src, size_t bytes);
+
+/* Number of bodies, total markers and steps taken so far. */
+int btdf_counts(const btdf_t *h, int *n_bodies, int *n_markers, int64_t *n_steps);
+
+/* Tuning knobs (BTDF_OPT_*). set returns EINVAL for unknown keys or values. */
+int btdf_set_option(btdf_t *h, int key, int64_t value);
+int btdf_get_option(const btdf_t *h, int key, int64_t *value);
+
+/* Boundary-thickness calibration on the host (no device), Section 2.3:
+ * A_ij = (1/dh^2) sum_k phi_ik phi_kj dh ds (eq 22) over the stencil nodes
+ * of the n markers xy ([n][2], host), drs_vec = dh A^{-1} 1 (eq 25) and
+ * drs = mean(drs_vec) (eq 26), with dh = 1. *drs_mean receives the mean,
+ * drs_per_marker (length n, may be NULL) the local values. Errors: EINVAL
+ * (n < 1, bad kind, ds <= 0), ESTATE (A singular to working precision). */
+int btdf_calibrate_thickening(int delta_kind, int n, const double *xy, double ds,
+                              double *drs_mean, double *drs_per_marker);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BTDF_H */

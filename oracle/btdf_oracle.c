@@ -530,3 +530,15 @@ int oracle_unstable(const oracle_t *o) { return o->unstable; }
 long oracle_steps(const oracle_t *o) { return o->steps; }
 int oracle_num_markers(const oracle_t *o) { return o->nm; }
 int oracle_num_bodies(const oracle_t *o) { return o->nb; }
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* Threads the parallel loops use (1 without OpenMP). */
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -61,8 +61,15 @@ def lib():
         L.oracle_delta.argtypes = [ctypes.c_int, ctypes.c_double]
         L.oracle_delta_halfwidth.restype = ctypes.c_double
         L.oracle_delta_halfwidth.argtypes = [ctypes.c_int]
+        L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_num_threads.argtypes = []
         _lib = L
     return _lib
+
+
+def num_threads():
+    """Threads the oracle's parallel loops use."""
+    return int(lib().oracle_num_threads())
 
 
 def delta(kind, r):

@@ -1,0 +1,162 @@
+"""Python names of the C ABI (include/btdf.h), one function per C call.
+
+Each function converts its arguments (numpy arrays, tuples, ints) into the
+C types, calls the library, raises ``BtdfError`` / ``BtdfUnstable`` on a
+non-zero status and converts the outputs back into numpy arrays.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import btdf_grid, check, dptr, f64, load
+
+
+def btdf_create(nx, ny, tau, delta_kind, thickening, bc=(0, 0, 0, 0), inflow=(0.0, 0.0),
+                body_force=(0.0, 0.0), init=(1.0, 0.0, 0.0), precision=8, history_capacity=0,
+                stream=None):
+    g = btdf_grid(nx=int(nx), ny=int(ny), bc_west=int(bc[0]), bc_east=int(bc[1]),
+                  bc_south=int(bc[2]), bc_north=int(bc[3]),
+                  inflow_ux=float(inflow[0]), inflow_uy=float(inflow[1]),
+                  body_force_x=float(body_force[0]), body_force_y=float(body_force[1]),
+                  rho0=float(init[0]), ux0=float(init[1]), uy0=float(init[2]),
+                  precision=int(precision), history_capacity=int(history_capacity),
+                  hip_stream=stream, flags=0)
+    h = ctypes.c_void_p()
+    check(load().btdf_create(ctypes.byref(g), float(tau), int(delta_kind), float(thickening),
+                             ctypes.byref(h)))
+    return h.value
+
+
+def btdf_destroy(h):
+    return check(load().btdf_destroy(h))
+
+
+def btdf_workspace_bytes(h):
+    return int(load().btdf_workspace_bytes(h))
+
+
+def btdf_bind_workspace(h, dev_ptr, nbytes):
+    return check(load().btdf_bind_workspace(h, dev_ptr, int(nbytes)))
+
+
+def btdf_set_stream(h, stream_ptr):
+    return check(load().btdf_set_stream(h, stream_ptr))
+
+
+def btdf_add_body(h, xy, uv=None, cx=0.0, cy=0.0, ds=0.0):
+    xy = f64(xy, (-1, 2))
+    n = xy.shape[0]
+    uvp = None
+    if uv is not None:
+        uv = f64(uv, (n, 2))
+        uvp = dptr(uv)
+    bid = ctypes.c_int(-1)
+    check(load().btdf_add_body(h, n, dptr(xy), uvp, float(cx), float(cy), float(ds), ctypes.byref(bid)))
+    return bid.value
+
+
+def btdf_set_marker_velocity(h, body, uv):
+    uv = f64(uv, (-1, 2))
+    return check(load().btdf_set_marker_velocity(h, int(body), dptr(uv)))
+
+
+def btdf_step(h, n):
+    return check(load().btdf_step(h, int(n)))
+
+
+def btdf_step_timed(h, n):
+    a, b = ctypes.c_double(), ctypes.c_double()
+    check(load().btdf_step_timed(h, int(n), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def btdf_counts(h):
+    nb, nm, ns = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+    check(load().btdf_counts(h, ctypes.byref(nb), ctypes.byref(nm), ctypes.byref(ns)))
+    return nb.value, nm.value, ns.value
+
+
+def btdf_forces(h):
+    nb = btdf_counts(h)[0]
+    out = np.zeros((max(nb, 1), 3))
+    check(load().btdf_forces(h, dptr(out), nb))
+    return out[:nb]
+
+
+def btdf_force_history(h, max_steps):
+    nb = btdf_counts(h)[0]
+    out = np.zeros((max(int(max_steps), 1), max(nb, 1), 3))
+    n = ctypes.c_int64()
+    check(load().btdf_force_history(h, dptr(out), int(max_steps), ctypes.byref(n)))
+    return out[:n.value, :nb]
+
+
+def btdf_init_equilibrium(h, ux, uy, rho=None):
+    ux, uy = f64(ux), f64(uy)
+    rho = None if rho is None else f64(rho)
+    return check(load().btdf_init_equilibrium(h, dptr(rho), dptr(ux), dptr(uy)))
+
+
+def btdf_get_macroscopic(h, nx, ny):
+    r, u, v = (np.empty((ny, nx)) for _ in range(3))
+    check(load().btdf_get_macroscopic(h, dptr(r), dptr(u), dptr(v)))
+    return r, u, v
+
+
+def btdf_get_populations(h, nx, ny):
+    f = np.empty((9, ny, nx))
+    check(load().btdf_get_populations(h, dptr(f)))
+    return f
+
+
+def btdf_set_populations(h, f):
+    f = f64(f)
+    return check(load().btdf_set_populations(h, dptr(f)))
+
+
+def btdf_get_marker_data(h):
+    nm = btdf_counts(h)[1]
+    arrs = [np.empty(max(nm, 1)) for _ in range(5)]
+    check(load().btdf_get_marker_data(h, *[dptr(a) for a in arrs]))
+    return dict(zip(["rho", "ux", "uy", "Fx", "Fy"], [a[:nm] for a in arrs]))
+
+
+def btdf_state_bytes(h):
+    return int(load().btdf_state_bytes(h))
+
+
+def btdf_save(h):
+    n = btdf_state_bytes(h)
+    buf = ctypes.create_string_buffer(n)
+    check(load().btdf_save(h, ctypes.cast(buf, ctypes.c_void_p), n))
+    return buf.raw
+
+
+def btdf_load(h, state):
+    buf = ctypes.create_string_buffer(bytes(state), len(state))
+    return check(load().btdf_load(h, ctypes.cast(buf, ctypes.c_void_p), len(state)))
+
+
+def btdf_set_option(h, key, value):
+    return check(load().btdf_set_option(h, int(key), int(value)))
+
+
+def btdf_get_option(h, key):
+    v = ctypes.c_int64()
+    check(load().btdf_get_option(h, int(key), ctypes.byref(v)))
+    return v.value
+
+
+def btdf_calibrate_thickening(delta_kind, xy, ds):
+    xy = f64(xy, (-1, 2))
+    n = xy.shape[0]
+    mean = ctypes.c_double()
+    per = np.empty(n)
+    check(load().btdf_calibrate_thickening(int(delta_kind), n, dptr(xy), float(ds),
+                                           ctypes.byref(mean), dptr(per)))
+    return mean.value, per
+
+
+def btdf_last_error():
+    return _lib.last_error()

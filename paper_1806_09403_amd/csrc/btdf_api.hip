@@ -1,0 +1,996 @@
+// btdf_api.hip -- host side of the C ABI declared in include/btdf.h.
+//
+// Device memory of a handle is one workspace (caller-owned or allocated
+// here) laid out as
+//   [ populations A | populations B | control (step counter, flag) ]   grid part
+//   [ force history ring | marker arrays | body arrays | tile lists ]  body part
+// The grid part has a fixed size for the handle, so rebinding or growing
+// the workspace moves it with one device copy and rebuilds the body part
+// from the host copies of the bodies.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "btdf.h"
+#include "btdf_launch.h"
+
+using namespace btdf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ok() { return BTDF_OK; }
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) return fail(BTDF_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// host value of the delta functions (calibration and validation only)
+double phi_host(int kind, double r) {
+  double a = std::fabs(r);
+  switch (kind) {
+    case kLinear2: return a <= 1.0 ? 1.0 - a : 0.0;
+    case kRoma3:
+      if (a <= 0.5) return (1.0 + std::sqrt(1.0 - 3.0 * a * a)) / 3.0;
+      if (a <= 1.5) return (5.0 - 3.0 * a - std::sqrt(std::fmax(0.0, 1.0 - 3.0 * (1.0 - a) * (1.0 - a)))) / 6.0;
+      return 0.0;
+    case kPeskin4:
+      if (a < 1.0) return (3.0 - 2.0 * a + std::sqrt(1.0 + 4.0 * a - 4.0 * a * a)) / 8.0;
+      if (a < 2.0) return (5.0 - 2.0 * a - std::sqrt(std::fmax(0.0, -7.0 + 12.0 * a - 4.0 * a * a))) / 8.0;
+      return 0.0;
+    default: return a <= 2.0 ? 0.25 * (1.0 + std::cos(M_PI * 0.5 * a)) : 0.0;
+  }
+}
+
+bool valid_kind(int k) { return k == kLinear2 || k == kRoma3 || k == kPeskin4 || k == kCos4; }
+
+}  // namespace
+
+struct btdf_sim {
+  // configuration
+  int nx = 0, ny = 0;
+  int bc[4] = {0, 0, 0, 0};
+  int prec = 8;
+  int hist_cap = 4096;
+  int kind = kCos4;
+  double tau = 1.0, drs = 1.0;
+  double G[2] = {0, 0}, uin[2] = {0, 0};
+  double rho0 = 1.0, u0[2] = {0, 0};
+  hipStream_t stream = nullptr;
+  // bodies (host copies)
+  std::vector<double> X, Y, U, V, sdrs;
+  std::vector<int> off{0};
+  std::vector<double> cx, cy, bsdrs;
+  // lattice kernel launch shape and tiles
+  int variant = 0, xcd_remap = 1, graph_chunk = 0;
+  int tile_x = 64, tile_y = 4, ntx = 0, nty = 0;
+  std::vector<int> tile_off, tile_list;
+  // device memory
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  // layout
+  int pitch = 0;
+  long long plane = 0;
+  size_t off_pop[2] = {0, 0}, off_ctl = 0, grid_bytes = 0;
+  size_t off_hist = 0, off_mk = 0, off_body = 0, off_boff = 0, off_toff = 0, off_tlist = 0, total = 0;
+  bool layout_ok = false;  // host layout current for bodies and tiles
+  bool device_ok = false;  // body part uploaded into the workspace
+  bool state_ok = false;   // populations hold a state
+  int cur = 0;             // which population buffer holds the state
+  int64_t steps = 0, hist_read = 0;
+  int64_t forces_from = 0;   // first step whose ring entry matches the body set
+  bool bodies_dirty = true;  // ring layout on the device predates the body set
+  int ib_threads = 64;
+  // graph of graph_chunk steps starting from buffer 0
+  hipGraphExec_t graph = nullptr;
+  hipStream_t cap_stream = nullptr;
+
+  int nb() const { return (int)cx.size(); }
+  int nm() const { return (int)X.size(); }
+  bool xper() const { return bc[0] == BTDF_PERIODIC; }
+  bool yper() const { return bc[2] == BTDF_PERIODIC; }
+  int i0() const { return xper() ? 0 : 1; }
+  int i1() const { return xper() ? nx - 1 : nx - 2; }
+  template <typename P>
+  P *at(size_t o) const { return reinterpret_cast<P *>(ws + o); }
+};
+
+namespace {
+
+void drop_graph(btdf_t *h) {
+  if (h->graph) {
+    (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+  }
+}
+
+// stencil-node range of a marker coordinate (all kernels are inside [floor-1, floor+2])
+void marker_range(int kind, double X, int *lo, int *hi) {
+  int b = stencil_base(kind, X);
+  *lo = b;
+  *hi = b + stencil_size(kind) - 1;
+}
+
+int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
+
+void compute_layout(btdf_t *h) {
+  const size_t elt = (size_t)h->prec;
+  h->pitch = h->nx;
+  h->plane = (((long long)h->nx * h->ny + 63) / 64) * 64;
+  const size_t pop_bytes = align256(9 * (size_t)h->plane * elt);
+  h->off_pop[0] = 0;
+  h->off_pop[1] = pop_bytes;
+  h->off_ctl = 2 * pop_bytes;
+  h->grid_bytes = h->off_ctl + 256;
+
+  variant_tile(h->variant, &h->tile_x, &h->tile_y);
+  h->ntx = (h->nx + h->tile_x - 1) / h->tile_x;
+  h->nty = (h->ny + h->tile_y - 1) / h->tile_y;
+  const int ntiles = h->ntx * h->nty;
+
+  // bin every marker into each tile its stencil touches (ascending marker ids per tile)
+  std::vector<int> cnt(ntiles + 1, 0);
+  std::vector<int> touched;
+  touched.reserve(16);
+  auto tiles_of = [&](int l) {
+    touched.clear();
+    int xlo, xhi, ylo, yhi;
+    marker_range(h->kind, h->X[l], &xlo, &xhi);
+    marker_range(h->kind, h->Y[l], &ylo, &yhi);
+    for (int j = ylo; j <= yhi; ++j) {
+      int jj = h->yper() ? ((j % h->ny) + h->ny) % h->ny : j;
+      if (jj < 0 || jj >= h->ny) continue;
+      for (int i = xlo; i <= xhi; ++i) {
+        int ii = h->xper() ? ((i % h->nx) + h->nx) % h->nx : i;
+        if (ii < 0 || ii >= h->nx) continue;
+        int t = floordiv(jj, h->tile_y) * h->ntx + floordiv(ii, h->tile_x);
+        if (std::find(touched.begin(), touched.end(), t) == touched.end()) touched.push_back(t);
+      }
+    }
+  };
+  for (int l = 0; l < h->nm(); ++l) {
+    tiles_of(l);
+    for (int t : touched) cnt[t + 1]++;
+  }
+  h->tile_off.assign(ntiles + 1, 0);
+  for (int t = 0; t < ntiles; ++t) h->tile_off[t + 1] = h->tile_off[t] + cnt[t + 1];
+  h->tile_list.assign(std::max(1, h->tile_off[ntiles]), 0);
+  std::vector<int> fill(h->tile_off.begin(), h->tile_off.end() - 1);
+  for (int l = 0; l < h->nm(); ++l) {
+    tiles_of(l);
+    for (int t : touched) h->tile_list[fill[t]++] = l;
+  }
+
+  const int nb = h->nb(), nm = h->nm();
+  size_t o = h->grid_bytes;
+  h->off_hist = o;
+  o = align256(o + (size_t)h->hist_cap * std::max(nb, 1) * 3 * sizeof(double));
+  h->off_mk = o;  // X Y U V sdrs Fx Fy rho ux uy
+  o = align256(o + 10 * (size_t)std::max(nm, 1) * sizeof(double));
+  h->off_body = o;  // cx cy bsdrs
+  o = align256(o + 3 * (size_t)std::max(nb, 1) * sizeof(double));
+  h->off_boff = o;
+  o = align256(o + (size_t)(nb + 1) * sizeof(int));
+  h->off_toff = o;
+  o = align256(o + (size_t)(ntiles + 1) * sizeof(int));
+  h->off_tlist = o;
+  o = align256(o + h->tile_list.size() * sizeof(int));
+  h->total = o;
+
+  int mx = 1;
+  for (int b = 0; b < nb; ++b) mx = std::max(mx, h->off[b + 1] - h->off[b]);
+  h->ib_threads = std::min(256, std::max(64, ((mx + 63) / 64) * 64));
+  h->layout_ok = true;
+  h->device_ok = false;
+  drop_graph(h);
+}
+
+LbmParams make_params(const btdf_t *h) {
+  LbmParams p{};
+  p.nx = h->nx;
+  p.ny = h->ny;
+  p.pitch = h->pitch;
+  p.plane = h->plane;
+  p.xper = h->xper();
+  p.yper = h->yper();
+  p.inlet = h->bc[0] == BTDF_VELOCITY_INLET;
+  p.outlet = h->bc[1] == BTDF_ZERO_GRADIENT_OUTLET;
+  p.i0 = h->i0();
+  p.i1 = h->i1();
+  p.omega = 1.0 / h->tau;
+  p.guo = 1.0 - 1.0 / (2.0 * h->tau);
+  p.Gx = h->G[0];
+  p.Gy = h->G[1];
+  p.uin_x = h->uin[0];
+  p.uin_y = h->uin[1];
+  p.ntx = h->ntx;
+  p.nty = h->nty;
+  p.xcd_remap = h->xcd_remap;
+  const size_t M = (size_t)std::max(h->nm(), 1);
+  double *mk = h->at<double>(h->off_mk);
+  p.tile_off = h->at<int>(h->off_toff);
+  p.tile_list = h->at<int>(h->off_tlist);
+  p.X = mk;
+  p.Y = mk + M;
+  p.sdrs = mk + 4 * M;
+  p.Fx = mk + 5 * M;
+  p.Fy = mk + 6 * M;
+  p.kind = h->kind;
+  p.step_ctr = h->at<long long>(h->off_ctl);
+  p.flag = h->at<int>(h->off_ctl + 8);
+  return p;
+}
+
+IbParams make_ib(const btdf_t *h) {
+  IbParams ib{};
+  const size_t M = (size_t)std::max(h->nm(), 1), B = (size_t)std::max(h->nb(), 1);
+  double *mk = h->at<double>(h->off_mk);
+  double *bd = h->at<double>(h->off_body);
+  ib.nb = h->nb();
+  ib.body_off = h->at<int>(h->off_boff);
+  ib.X = mk;
+  ib.Y = mk + M;
+  ib.U = mk + 2 * M;
+  ib.V = mk + 3 * M;
+  ib.Fx = mk + 5 * M;
+  ib.Fy = mk + 6 * M;
+  ib.rho_l = mk + 7 * M;
+  ib.ux_l = mk + 8 * M;
+  ib.uy_l = mk + 9 * M;
+  ib.cx = bd;
+  ib.cy = bd + B;
+  ib.body_sdrs = bd + 2 * B;
+  ib.hist = h->at<double>(h->off_hist);
+  ib.hist_cap = h->hist_cap;
+  return ib;
+}
+
+int upload(btdf_t *h, size_t off, const void *src, size_t bytes) {
+  if (bytes == 0) return ok();
+  HIPCHK(hipMemcpyAsync(h->ws + off, src, bytes, hipMemcpyHostToDevice, h->stream));
+  return ok();
+}
+
+int upload_bodies(btdf_t *h) {
+  const size_t M = (size_t)std::max(h->nm(), 1), B = (size_t)std::max(h->nb(), 1);
+  const size_t nm = (size_t)h->nm(), nb = (size_t)h->nb();
+  const size_t d = sizeof(double);
+  int rc;
+  if ((rc = upload(h, h->off_mk + 0 * M * d, h->X.data(), nm * d))) return rc;
+  if ((rc = upload(h, h->off_mk + 1 * M * d, h->Y.data(), nm * d))) return rc;
+  if ((rc = upload(h, h->off_mk + 2 * M * d, h->U.data(), nm * d))) return rc;
+  if ((rc = upload(h, h->off_mk + 3 * M * d, h->V.data(), nm * d))) return rc;
+  if ((rc = upload(h, h->off_mk + 4 * M * d, h->sdrs.data(), nm * d))) return rc;
+  HIPCHK(hipMemsetAsync(h->ws + h->off_mk + 5 * M * d, 0, 5 * M * d, h->stream));
+  if ((rc = upload(h, h->off_body + 0 * B * d, h->cx.data(), nb * d))) return rc;
+  if ((rc = upload(h, h->off_body + 1 * B * d, h->cy.data(), nb * d))) return rc;
+  if ((rc = upload(h, h->off_body + 2 * B * d, h->bsdrs.data(), nb * d))) return rc;
+  if ((rc = upload(h, h->off_boff, h->off.data(), (nb + 1) * sizeof(int)))) return rc;
+  if ((rc = upload(h, h->off_toff, h->tile_off.data(), h->tile_off.size() * sizeof(int)))) return rc;
+  if ((rc = upload(h, h->off_tlist, h->tile_list.data(), h->tile_list.size() * sizeof(int)))) return rc;
+  if (h->bodies_dirty)
+    HIPCHK(hipMemsetAsync(h->ws + h->off_hist, 0,
+                          (size_t)h->hist_cap * std::max(h->nb(), 1) * 3 * sizeof(double), h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));  // host vectors may change after return
+  h->device_ok = true;
+  h->bodies_dirty = false;
+  return ok();
+}
+
+int init_state(btdf_t *h) {
+  LbmParams p = make_params(h);
+  HIPCHK(launch_init_uniform(h->prec, h->ws + h->off_pop[0], p, h->rho0, h->u0[0], h->u0[1], h->stream));
+  HIPCHK(hipMemsetAsync(h->ws + h->off_ctl, 0, 256, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->cur = 0;
+  h->steps = 0;
+  h->hist_read = 0;
+  h->state_ok = true;
+  return ok();
+}
+
+// bytes of live state to carry into a new workspace: the grid part, plus the
+// force ring when it still matches the body set
+size_t moved_bytes(const btdf_t *h) { return h->bodies_dirty ? h->grid_bytes : h->off_mk; }
+
+// make the workspace hold a valid state and the current body part
+int ensure_device(btdf_t *h) {
+  if (!h->layout_ok) compute_layout(h);
+  if (h->ws == nullptr || h->ws_bytes < h->total) {
+    if (h->ws != nullptr && !h->ws_owned)
+      return fail(BTDF_ENOMEM, "bound workspace has %zu bytes, %zu needed (rebind a larger one)",
+                  h->ws_bytes, h->total);
+    char *nw = nullptr;
+    hipError_t e = hipMalloc((void **)&nw, h->total);
+    if (e != hipSuccess)
+      return fail(BTDF_ENOMEM, "hipMalloc(%zu): %s", h->total, hipGetErrorString(e));
+    if (h->ws && h->state_ok) {
+      HIPCHK(hipMemcpyAsync(nw, h->ws, moved_bytes(h), hipMemcpyDeviceToDevice, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    if (h->ws && h->ws_owned) HIPCHK(hipFree(h->ws));
+    h->ws = nw;
+    h->ws_bytes = h->total;
+    h->ws_owned = true;
+    h->device_ok = false;
+    drop_graph(h);
+  }
+  if (!h->state_ok) {
+    int rc = init_state(h);
+    if (rc) return rc;
+  }
+  if (!h->device_ok) {
+    int rc = upload_bodies(h);
+    if (rc) return rc;
+  }
+  return ok();
+}
+
+int read_ctl(btdf_t *h, long long *ctr, int *flag) {
+  unsigned char buf[16];
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipMemcpy(buf, h->ws + h->off_ctl, 16, hipMemcpyDeviceToHost));
+  std::memcpy(ctr, buf, 8);
+  std::memcpy(flag, buf + 8, 4);
+  return ok();
+}
+
+int check_flag(btdf_t *h) {
+  long long ctr;
+  int flag;
+  int rc = read_ctl(h, &ctr, &flag);
+  if (rc) return rc;
+  if (flag > 0) return fail(BTDF_EUNSTABLE, "unstable: marker of body %d (non-finite force or |u*| > 0.3)", flag - 1);
+  if (flag < 0) return fail(BTDF_EUNSTABLE, "unstable: non-positive or non-finite density at a node");
+  return ok();
+}
+
+int clear_flag(btdf_t *h) {
+  HIPCHK(hipMemsetAsync(h->ws + h->off_ctl + 8, 0, 4, h->stream));
+  return ok();
+}
+
+// one time step on the given buffers
+int enqueue_step(btdf_t *h, const LbmParams &p, const IbParams &ib, int src, hipStream_t s) {
+  const void *A = h->ws + h->off_pop[src];
+  void *B = h->ws + h->off_pop[1 - src];
+  HIPCHK(launch_ib(h->prec, A, p, ib, h->ib_threads, s));
+  HIPCHK(launch_lbm(h->prec, h->variant, A, B, p, s));
+  return ok();
+}
+
+int build_graph(btdf_t *h, const LbmParams &p, const IbParams &ib) {
+  drop_graph(h);
+  if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = 0;
+  for (int k = 0; k < h->graph_chunk && rc == 0; ++k) rc = enqueue_step(h, p, ib, k & 1, h->cap_stream);
+  hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(BTDF_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    h->graph = nullptr;
+    return fail(BTDF_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *btdf_last_error(void) { return g_err.c_str(); }
+
+int btdf_create(const btdf_grid *g, double tau, int delta_kind, double thickening, btdf_t **out) {
+  if (!g || !out) return fail(BTDF_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (g->nx < 8 || g->ny < 8) return fail(BTDF_EINVAL, "nx and ny must be >= 8 (got %d, %d)", g->nx, g->ny);
+  if ((long long)g->nx * g->ny > (1LL << 31) - 1) return fail(BTDF_EINVAL, "grid too large");
+  if (!(tau > 0.5) || !std::isfinite(tau)) return fail(BTDF_EINVAL, "tau must be > 1/2 (got %g)", tau);
+  if (!valid_kind(delta_kind)) return fail(BTDF_EINVAL, "unknown delta kind %d", delta_kind);
+  if (!(thickening > 0.0) || !std::isfinite(thickening))
+    return fail(BTDF_EINVAL, "thickening must be > 0 (got %g)", thickening);
+  const bool xp = g->bc_west == BTDF_PERIODIC && g->bc_east == BTDF_PERIODIC;
+  const bool xc = g->bc_west == BTDF_VELOCITY_INLET && g->bc_east == BTDF_ZERO_GRADIENT_OUTLET;
+  const bool yp = g->bc_south == BTDF_PERIODIC && g->bc_north == BTDF_PERIODIC;
+  const bool yw = g->bc_south == BTDF_BOUNCEBACK_WALL && g->bc_north == BTDF_BOUNCEBACK_WALL;
+  if (!(xp || xc)) return fail(BTDF_EINVAL, "x ends must be a periodic pair or inlet (west) + outlet (east)");
+  if (!(yp || yw)) return fail(BTDF_EINVAL, "y ends must be a periodic pair or a bounce-back wall pair");
+  if (g->precision != 4 && g->precision != 8) return fail(BTDF_EINVAL, "precision must be 4 or 8");
+  if (g->history_capacity < 0) return fail(BTDF_EINVAL, "history_capacity must be >= 0");
+  if (g->flags != 0) return fail(BTDF_EINVAL, "flags must be 0");
+  const double vals[] = {g->inflow_ux, g->inflow_uy, g->body_force_x, g->body_force_y, g->rho0, g->ux0, g->uy0};
+  for (double v : vals)
+    if (!std::isfinite(v)) return fail(BTDF_EINVAL, "non-finite grid parameter");
+  if (!(g->rho0 > 0.0)) return fail(BTDF_EINVAL, "rho0 must be > 0");
+
+  btdf_t *h = new (std::nothrow) btdf_sim();
+  if (!h) return fail(BTDF_ENOMEM, "out of host memory");
+  h->nx = g->nx;
+  h->ny = g->ny;
+  h->bc[0] = g->bc_west;
+  h->bc[1] = g->bc_east;
+  h->bc[2] = g->bc_south;
+  h->bc[3] = g->bc_north;
+  h->prec = g->precision;
+  h->hist_cap = g->history_capacity ? g->history_capacity : 4096;
+  h->kind = delta_kind;
+  h->tau = tau;
+  h->drs = thickening;
+  h->G[0] = g->body_force_x;
+  h->G[1] = g->body_force_y;
+  h->uin[0] = g->inflow_ux;
+  h->uin[1] = g->inflow_uy;
+  h->rho0 = g->rho0;
+  h->u0[0] = g->ux0;
+  h->u0[1] = g->uy0;
+  h->stream = (hipStream_t)g->hip_stream;
+  *out = h;
+  return ok();
+}
+
+int btdf_destroy(btdf_t *h) {
+  if (!h) return ok();
+  int rc = ok();
+  if (h->ws) {
+    if (hipStreamSynchronize(h->stream) != hipSuccess) rc = fail(BTDF_EDEVICE, "stream sync failed");
+  }
+  drop_graph(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->ws && h->ws_owned) (void)hipFree(h->ws);
+  delete h;
+  return rc;
+}
+
+size_t btdf_workspace_bytes(const btdf_t *h) {
+  if (!h) return 0;
+  if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
+  return h->total;
+}
+
+int btdf_bind_workspace(btdf_t *h, void *dev, size_t bytes) {
+  if (!h) return fail(BTDF_EINVAL, "NULL handle");
+  if (dev && ((uintptr_t)dev & 255)) return fail(BTDF_EINVAL, "workspace must be 256-byte aligned");
+  if (!h->layout_ok) compute_layout(h);
+  if (dev && bytes < h->total)
+    return fail(BTDF_ENOMEM, "workspace has %zu bytes, %zu needed", bytes, h->total);
+  if (dev == (void *)h->ws && dev) {
+    h->ws_bytes = bytes;
+    return ok();
+  }
+  if (!dev) {
+    // back to library-owned memory on the next device call
+    if (h->ws && !h->ws_owned) {
+      char *nw = nullptr;
+      hipError_t e = hipMalloc((void **)&nw, h->total);
+      if (e != hipSuccess) return fail(BTDF_ENOMEM, "hipMalloc(%zu): %s", h->total, hipGetErrorString(e));
+      if (h->state_ok) {
+        HIPCHK(hipMemcpyAsync(nw, h->ws, moved_bytes(h), hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+      }
+      h->ws = nw;
+      h->ws_bytes = h->total;
+      h->ws_owned = true;
+      h->device_ok = false;
+      drop_graph(h);
+    }
+    return ok();
+  }
+  if (h->ws && h->state_ok) {
+    HIPCHK(hipMemcpyAsync(dev, h->ws, moved_bytes(h), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  if (h->ws && h->ws_owned) HIPCHK(hipFree(h->ws));
+  h->ws = (char *)dev;
+  h->ws_bytes = bytes;
+  h->ws_owned = false;
+  h->device_ok = false;
+  drop_graph(h);
+  return ok();
+}
+
+int btdf_set_stream(btdf_t *h, void *hip_stream) {
+  if (!h) return fail(BTDF_EINVAL, "NULL handle");
+  if (h->ws && (hipStream_t)hip_stream != h->stream) {
+    // order the new stream after the work already on the old one
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  h->stream = (hipStream_t)hip_stream;
+  return ok();
+}
+
+int btdf_add_body(btdf_t *h, int n, const double *xy, const double *uv, double cx, double cy, double ds,
+                  int *body_id) {
+  if (!h || !xy) return fail(BTDF_EINVAL, "NULL argument");
+  if (n < 3) return fail(BTDF_EINVAL, "a body needs at least 3 markers (got %d)", n);
+  if (!std::isfinite(cx) || !std::isfinite(cy) || !std::isfinite(ds)) return fail(BTDF_EINVAL, "non-finite body parameter");
+  for (int l = 0; l < n; ++l) {
+    const double X = xy[2 * l], Y = xy[2 * l + 1];
+    if (!std::isfinite(X) || !std::isfinite(Y)) return fail(BTDF_EINVAL, "non-finite marker %d", l);
+    if (uv && (!std::isfinite(uv[2 * l]) || !std::isfinite(uv[2 * l + 1])))
+      return fail(BTDF_EINVAL, "non-finite marker velocity %d", l);
+    if (std::fabs(X) > 1e8 || std::fabs(Y) > 1e8) return fail(BTDF_EINVAL, "marker %d too far from the grid", l);
+    int lo, hi;
+    marker_range(h->kind, X, &lo, &hi);
+    if (!h->xper() && (lo < h->i0() || hi > h->i1()))
+      return fail(BTDF_EINVAL, "marker %d: stencil x range [%d, %d] leaves the fluid columns [%d, %d]", l, lo,
+                  hi, h->i0(), h->i1());
+    marker_range(h->kind, Y, &lo, &hi);
+    if (!h->yper() && (lo < 0 || hi > h->ny - 1))
+      return fail(BTDF_EINVAL, "marker %d: stencil y range [%d, %d] leaves the grid", l, lo, hi);
+  }
+  if (!(ds > 0.0)) {
+    double per = 0.0;
+    for (int l = 0; l < n; ++l) {
+      int m = (l + 1) % n;
+      per += std::hypot(xy[2 * m] - xy[2 * l], xy[2 * m + 1] - xy[2 * l + 1]);
+    }
+    ds = per / n;
+    if (!(ds > 0.0)) return fail(BTDF_EINVAL, "degenerate body (zero perimeter)");
+  }
+  if ((long long)h->nm() + n > (1LL << 30)) return fail(BTDF_EINVAL, "too many markers");
+  try {
+    const double s = h->drs * ds;
+    for (int l = 0; l < n; ++l) {
+      h->X.push_back(xy[2 * l]);
+      h->Y.push_back(xy[2 * l + 1]);
+      h->U.push_back(uv ? uv[2 * l] : 0.0);
+      h->V.push_back(uv ? uv[2 * l + 1] : 0.0);
+      h->sdrs.push_back(s);
+    }
+    h->off.push_back(h->nm());
+    h->cx.push_back(cx);
+    h->cy.push_back(cy);
+    h->bsdrs.push_back(s);
+  } catch (...) {
+    return fail(BTDF_ENOMEM, "out of host memory");
+  }
+  h->layout_ok = false;
+  h->device_ok = false;
+  h->bodies_dirty = true;
+  h->hist_read = h->steps;
+  h->forces_from = h->steps;
+  drop_graph(h);
+  if (body_id) *body_id = h->nb() - 1;
+  return ok();
+}
+
+int btdf_set_marker_velocity(btdf_t *h, int body, const double *uv) {
+  if (!h || !uv) return fail(BTDF_EINVAL, "NULL argument");
+  if (body < 0 || body >= h->nb()) return fail(BTDF_EINVAL, "no body %d", body);
+  const int l0 = h->off[body], l1 = h->off[body + 1];
+  for (int l = l0; l < l1; ++l)
+    if (!std::isfinite(uv[2 * (l - l0)]) || !std::isfinite(uv[2 * (l - l0) + 1]))
+      return fail(BTDF_EINVAL, "non-finite velocity");
+  for (int l = l0; l < l1; ++l) {
+    h->U[l] = uv[2 * (l - l0)];
+    h->V[l] = uv[2 * (l - l0) + 1];
+  }
+  if (h->ws && h->device_ok) {
+    const size_t M = (size_t)std::max(h->nm(), 1), d = sizeof(double);
+    int rc;
+    if ((rc = upload(h, h->off_mk + 2 * M * d + l0 * d, h->U.data() + l0, (l1 - l0) * d))) return rc;
+    if ((rc = upload(h, h->off_mk + 3 * M * d + l0 * d, h->V.data() + l0, (l1 - l0) * d))) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  return ok();
+}
+
+int btdf_step(btdf_t *h, int64_t n) {
+  if (!h) return fail(BTDF_EINVAL, "NULL handle");
+  if (n < 0) return fail(BTDF_EINVAL, "negative step count");
+  if (n == 0) return ok();
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  const LbmParams p = make_params(h);
+  const IbParams ib = make_ib(h);
+  int64_t left = n;
+  if (h->graph_chunk > 0 && left >= h->graph_chunk + (h->cur ? 1 : 0)) {
+    if (h->cur) {  // graphs start from buffer 0
+      if ((rc = enqueue_step(h, p, ib, h->cur, h->stream))) return rc;
+      h->cur ^= 1;
+      h->steps++;
+      left--;
+    }
+    if (!h->graph && (rc = build_graph(h, p, ib))) return rc;
+    while (left >= h->graph_chunk) {
+      HIPCHK(hipGraphLaunch(h->graph, h->stream));
+      left -= h->graph_chunk;
+      h->steps += h->graph_chunk;
+      // an even chunk returns the state to buffer 0
+      h->cur = (h->graph_chunk & 1) ? 1 : 0;
+      if (h->cur) break;
+    }
+  }
+  for (; left > 0; --left) {
+    if ((rc = enqueue_step(h, p, ib, h->cur, h->stream))) return rc;
+    h->cur ^= 1;
+    h->steps++;
+  }
+  return ok();
+}
+
+int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm) {
+  if (!h || !ms_ib || !ms_lbm) return fail(BTDF_EINVAL, "NULL argument");
+  if (n <= 0) return fail(BTDF_EINVAL, "step count must be > 0");
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  const LbmParams p = make_params(h);
+  const IbParams ib = make_ib(h);
+  const int chunk = 256;
+  std::vector<hipEvent_t> ev(3 * chunk, nullptr);
+  for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+  double tib = 0.0, tlbm = 0.0;
+  int64_t done = 0;
+  rc = ok();
+  while (done < n && rc == 0) {
+    const int m = (int)std::min<int64_t>(chunk, n - done);
+    for (int k = 0; k < m && rc == 0; ++k) {
+      const void *A = h->ws + h->off_pop[h->cur];
+      void *B = h->ws + h->off_pop[1 - h->cur];
+      hipError_t e = hipEventRecord(ev[3 * k], h->stream);
+      if (e == hipSuccess) e = launch_ib(h->prec, A, p, ib, h->ib_threads, h->stream);
+      if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 1], h->stream);
+      if (e == hipSuccess) e = launch_lbm(h->prec, h->variant, A, B, p, h->stream);
+      if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 2], h->stream);
+      if (e != hipSuccess) rc = fail(BTDF_EDEVICE, "timed step: %s", hipGetErrorString(e));
+      h->cur ^= 1;
+      h->steps++;
+    }
+    if (rc) break;
+    hipError_t e = hipEventSynchronize(ev[3 * (m - 1) + 2]);
+    if (e != hipSuccess) {
+      rc = fail(BTDF_EDEVICE, "hipEventSynchronize: %s", hipGetErrorString(e));
+      break;
+    }
+    for (int k = 0; k < m; ++k) {
+      float a = 0.f, b = 0.f;
+      (void)hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
+      (void)hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
+      tib += a;
+      tlbm += b;
+    }
+    done += m;
+  }
+  for (auto &e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (rc) return rc;
+  *ms_ib = h->nb() ? tib / (double)n : 0.0;
+  *ms_lbm = tlbm / (double)n;
+  return ok();
+}
+
+int btdf_forces(btdf_t *h, double *out, int cap_bodies) {
+  if (!h || (!out && h->nb() > 0)) return fail(BTDF_EINVAL, "NULL argument");
+  if (cap_bodies < h->nb()) return fail(BTDF_EINVAL, "cap_bodies %d < %d bodies", cap_bodies, h->nb());
+  const int nb = h->nb();
+  if (h->steps == 0 || !h->ws) {
+    for (int k = 0; k < 3 * nb; ++k) out[k] = 0.0;
+    return h->ws ? check_flag(h) : ok();
+  }
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (nb > 0) {
+    const long long slot = (h->steps - 1) % h->hist_cap;
+    if (h->steps <= h->forces_from) {
+      // no step since the body set changed or a state was loaded
+      for (int k = 0; k < 3 * nb; ++k) out[k] = 0.0;
+    } else {
+      HIPCHK(hipMemcpy(out, h->ws + h->off_hist + (size_t)slot * nb * 3 * sizeof(double),
+                       (size_t)nb * 3 * sizeof(double), hipMemcpyDeviceToHost));
+    }
+  }
+  return check_flag(h);
+}
+
+int btdf_force_history(btdf_t *h, double *out, int64_t max_steps, int64_t *n_written) {
+  if (!h || !n_written || (!out && max_steps > 0)) return fail(BTDF_EINVAL, "NULL argument");
+  *n_written = 0;
+  const int nb = h->nb();
+  if (!h->ws || nb == 0 || max_steps <= 0) {
+    h->hist_read = h->steps;
+    return h->ws ? check_flag(h) : ok();
+  }
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const int64_t pending = h->steps - std::max(h->hist_read, h->forces_from);
+  const int64_t avail = std::min<int64_t>(pending, h->hist_cap);
+  const int64_t first = h->steps - avail;
+  const int64_t cnt = std::min<int64_t>(avail, max_steps);
+  const size_t row = (size_t)nb * 3 * sizeof(double);
+  int64_t k = 0;
+  while (k < cnt) {
+    const int64_t slot = (first + k) % h->hist_cap;
+    const int64_t run = std::min<int64_t>(cnt - k, h->hist_cap - slot);
+    HIPCHK(hipMemcpy((char *)out + (size_t)k * row, h->ws + h->off_hist + (size_t)slot * row,
+                     (size_t)run * row, hipMemcpyDeviceToHost));
+    k += run;
+  }
+  h->hist_read = first + cnt;
+  *n_written = cnt;
+  return check_flag(h);
+}
+
+int btdf_init_equilibrium(btdf_t *h, const double *rho, const double *ux, const double *uy) {
+  if (!h || !ux || !uy) return fail(BTDF_EINVAL, "NULL argument");
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  const size_t n = (size_t)h->nx * h->ny, d = sizeof(double);
+  // stage the fields in the spare population buffer (at least 36 bytes per node)
+  double *st = h->at<double>(h->off_pop[1 - h->cur]);
+  HIPCHK(hipMemcpyAsync(st, ux, n * d, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(st + n, uy, n * d, hipMemcpyHostToDevice, h->stream));
+  if (rho) HIPCHK(hipMemcpyAsync(st + 2 * n, rho, n * d, hipMemcpyHostToDevice, h->stream));
+  LbmParams p = make_params(h);
+  HIPCHK(launch_init_eq(h->prec, h->ws + h->off_pop[h->cur], p, st + 2 * n, st, st + n, h->rho0, rho != nullptr,
+                        h->stream));
+  if ((rc = clear_flag(h))) return rc;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return ok();
+}
+
+int btdf_get_macroscopic(btdf_t *h, double *rho, double *ux, double *uy) {
+  if (!h || !rho || !ux || !uy) return fail(BTDF_EINVAL, "NULL argument");
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  const size_t n = (size_t)h->nx * h->ny, d = sizeof(double);
+  double *st = h->at<double>(h->off_pop[1 - h->cur]);
+  LbmParams p = make_params(h);
+  HIPCHK(launch_macro(h->prec, h->ws + h->off_pop[h->cur], p, st, st + n, st + 2 * n, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipMemcpy(rho, st, n * d, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(ux, st + n, n * d, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(uy, st + 2 * n, n * d, hipMemcpyDeviceToHost));
+  return ok();
+}
+
+int btdf_get_populations(btdf_t *h, double *dst) {
+  if (!h || !dst) return fail(BTDF_EINVAL, "NULL argument");
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  const size_t n = (size_t)h->nx * h->ny;
+  double *st = h->at<double>(h->off_pop[1 - h->cur]);
+  LbmParams p = make_params(h);
+  for (int q = 0; q < 9; ++q) {
+    HIPCHK(launch_plane_to_f64(h->prec, h->ws + h->off_pop[h->cur], p, q, st, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipMemcpy(dst + (size_t)q * n, st, n * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return ok();
+}
+
+int btdf_set_populations(btdf_t *h, const double *src) {
+  if (!h || !src) return fail(BTDF_EINVAL, "NULL argument");
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  const size_t n = (size_t)h->nx * h->ny;
+  double *st = h->at<double>(h->off_pop[1 - h->cur]);
+  LbmParams p = make_params(h);
+  for (int q = 0; q < 9; ++q) {
+    HIPCHK(hipMemcpyAsync(st, src + (size_t)q * n, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(launch_f64_to_plane(h->prec, h->ws + h->off_pop[h->cur], p, q, st, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  if ((rc = clear_flag(h))) return rc;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return ok();
+}
+
+int btdf_get_marker_data(btdf_t *h, double *rho_l, double *ux_l, double *uy_l, double *Fx, double *Fy) {
+  if (!h) return fail(BTDF_EINVAL, "NULL handle");
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const size_t M = (size_t)std::max(h->nm(), 1), nm = (size_t)h->nm(), d = sizeof(double);
+  double *outs[5] = {Fx, Fy, rho_l, ux_l, uy_l};
+  for (int k = 0; k < 5; ++k)
+    if (outs[k] && nm) HIPCHK(hipMemcpy(outs[k], h->ws + h->off_mk + (5 + k) * M * d, nm * d, hipMemcpyDeviceToHost));
+  return ok();
+}
+
+static const uint64_t kStateMagic = 0x4254444653544154ULL;  // "BTDFSTAT"
+
+size_t btdf_state_bytes(const btdf_t *h) {
+  if (!h) return 0;
+  return 64 + 9 * (size_t)h->nx * h->ny * (size_t)h->prec;
+}
+
+int btdf_save(btdf_t *h, void *dst, size_t bytes) {
+  if (!h || !dst) return fail(BTDF_EINVAL, "NULL argument");
+  if (bytes < btdf_state_bytes(h)) return fail(BTDF_EINVAL, "buffer of %zu bytes < %zu", bytes, btdf_state_bytes(h));
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  uint64_t hdr[8] = {kStateMagic, (uint64_t)h->prec, (uint64_t)h->nx, (uint64_t)h->ny, (uint64_t)h->steps, 0, 0, 0};
+  std::memcpy(dst, hdr, 64);
+  const size_t row = (size_t)h->nx * h->prec;
+  for (int q = 0; q < 9; ++q)
+    HIPCHK(hipMemcpy2D((char *)dst + 64 + (size_t)q * h->ny * row, row,
+                       h->ws + h->off_pop[h->cur] + (size_t)q * h->plane * h->prec, (size_t)h->pitch * h->prec,
+                       row, (size_t)h->ny, hipMemcpyDeviceToHost));
+  return ok();
+}
+
+int btdf_load(btdf_t *h, const void *src, size_t bytes) {
+  if (!h || !src) return fail(BTDF_EINVAL, "NULL argument");
+  if (bytes < btdf_state_bytes(h)) return fail(BTDF_EINVAL, "buffer of %zu bytes < %zu", bytes, btdf_state_bytes(h));
+  uint64_t hdr[8];
+  std::memcpy(hdr, src, 64);
+  if (hdr[0] != kStateMagic || hdr[1] != (uint64_t)h->prec || hdr[2] != (uint64_t)h->nx || hdr[3] != (uint64_t)h->ny)
+    return fail(BTDF_EINVAL, "state does not match this handle");
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  const size_t row = (size_t)h->nx * h->prec;
+  for (int q = 0; q < 9; ++q)
+    HIPCHK(hipMemcpy2DAsync(h->ws + h->off_pop[h->cur] + (size_t)q * h->plane * h->prec, (size_t)h->pitch * h->prec,
+                            (const char *)src + 64 + (size_t)q * h->ny * row, row, row, (size_t)h->ny,
+                            hipMemcpyHostToDevice, h->stream));
+  h->steps = (int64_t)hdr[4];
+  h->hist_read = h->steps;
+  h->forces_from = h->steps;
+  long long ctr = (long long)h->steps;
+  HIPCHK(hipMemcpyAsync(h->ws + h->off_ctl, &ctr, 8, hipMemcpyHostToDevice, h->stream));
+  if ((rc = clear_flag(h))) return rc;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return ok();
+}
+
+int btdf_counts(const btdf_t *h, int *n_bodies, int *n_markers, int64_t *n_steps) {
+  if (!h) return fail(BTDF_EINVAL, "NULL handle");
+  if (n_bodies) *n_bodies = h->nb();
+  if (n_markers) *n_markers = h->nm();
+  if (n_steps) *n_steps = h->steps;
+  return ok();
+}
+
+int btdf_set_option(btdf_t *h, int key, int64_t value) {
+  if (!h) return fail(BTDF_EINVAL, "NULL handle");
+  switch (key) {
+    case BTDF_OPT_LBM_VARIANT:
+      if (value < 0 || value >= num_variants()) return fail(BTDF_EINVAL, "variant %lld out of range", (long long)value);
+      if (value != h->variant) {
+        h->variant = (int)value;
+        h->layout_ok = false;  // tiles change
+        h->device_ok = false;
+        drop_graph(h);
+      }
+      return ok();
+    case BTDF_OPT_GRAPH_CHUNK:
+      if (value < 0 || value > 4096) return fail(BTDF_EINVAL, "graph chunk must be in 0 .. 4096");
+      if (value != h->graph_chunk) {
+        h->graph_chunk = (int)value;
+        drop_graph(h);
+      }
+      return ok();
+    case BTDF_OPT_XCD_REMAP:
+      if (value != 0 && value != 1) return fail(BTDF_EINVAL, "xcd remap must be 0 or 1");
+      h->xcd_remap = (int)value;
+      drop_graph(h);
+      return ok();
+    default: return fail(BTDF_EINVAL, "unknown or read-only option %d", key);
+  }
+}
+
+int btdf_get_option(const btdf_t *h, int key, int64_t *value) {
+  if (!h || !value) return fail(BTDF_EINVAL, "NULL argument");
+  int tx, ty;
+  switch (key) {
+    case BTDF_OPT_LBM_VARIANT: *value = h->variant; return ok();
+    case BTDF_OPT_NUM_VARIANTS: *value = num_variants(); return ok();
+    case BTDF_OPT_GRAPH_CHUNK: *value = h->graph_chunk; return ok();
+    case BTDF_OPT_XCD_REMAP: *value = h->xcd_remap; return ok();
+    case BTDF_OPT_TILE_X: variant_tile(h->variant, &tx, &ty); *value = tx; return ok();
+    case BTDF_OPT_TILE_Y: variant_tile(h->variant, &tx, &ty); *value = ty; return ok();
+    default: return fail(BTDF_EINVAL, "unknown option %d", key);
+  }
+}
+
+int btdf_calibrate_thickening(int delta_kind, int n, const double *xy, double ds, double *drs_mean,
+                              double *drs_per_marker) {
+  if (!xy || !drs_mean) return fail(BTDF_EINVAL, "NULL argument");
+  if (n < 1) return fail(BTDF_EINVAL, "need at least one marker");
+  if (!valid_kind(delta_kind)) return fail(BTDF_EINVAL, "unknown delta kind %d", delta_kind);
+  if (!(ds > 0.0) || !std::isfinite(ds)) return fail(BTDF_EINVAL, "ds must be > 0");
+  for (int l = 0; l < 2 * n; ++l)
+    if (!std::isfinite(xy[l]) || std::fabs(xy[l]) > 1e8) return fail(BTDF_EINVAL, "bad marker coordinate");
+  const int S = stencil_size(delta_kind);
+  // per marker: stencil base and weights; A_lm = ds sum_k W_lk W_mk (eq 22, dh = 1)
+  std::vector<int> bx(n), by(n);
+  std::vector<double> wx(4 * (size_t)n), wy(4 * (size_t)n);
+  for (int l = 0; l < n; ++l) {
+    bx[l] = stencil_base(delta_kind, xy[2 * l]);
+    by[l] = stencil_base(delta_kind, xy[2 * l + 1]);
+    for (int a = 0; a < S; ++a) {
+      wx[4 * l + a] = phi_host(delta_kind, (double)(bx[l] + a) - xy[2 * l]);
+      wy[4 * l + a] = phi_host(delta_kind, (double)(by[l] + a) - xy[2 * l + 1]);
+    }
+  }
+  std::vector<double> A;
+  try {
+    A.assign((size_t)n * n, 0.0);
+  } catch (...) {
+    return fail(BTDF_ENOMEM, "out of host memory");
+  }
+  for (int l = 0; l < n; ++l) {
+    for (int m = 0; m < n; ++m) {
+      const int ox = bx[m] - bx[l], oy = by[m] - by[l];
+      if (ox <= -S || ox >= S || oy <= -S || oy >= S) continue;
+      double s = 0.0;
+      for (int c = 0; c < S; ++c) {
+        const int cm = c - oy;
+        if (cm < 0 || cm >= S) continue;
+        for (int a = 0; a < S; ++a) {
+          const int am = a - ox;
+          if (am < 0 || am >= S) continue;
+          s += wx[4 * l + a] * wy[4 * l + c] * wx[4 * m + am] * wy[4 * m + cm];
+        }
+      }
+      A[(size_t)l * n + m] = ds * s;
+    }
+  }
+  // solve A x = 1 (eqs 24-25) by LU with partial pivoting
+  std::vector<double> x(n, 1.0);
+  double amax = 0.0;
+  for (double v : A) amax = std::max(amax, std::fabs(v));
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int r = k + 1; r < n; ++r)
+      if (std::fabs(A[(size_t)r * n + k]) > std::fabs(A[(size_t)piv * n + k])) piv = r;
+    if (!(std::fabs(A[(size_t)piv * n + k]) > 1e-13 * amax))
+      return fail(BTDF_ESTATE, "matrix A is singular to working precision (markers too dense?)");
+    if (piv != k) {
+      for (int c = 0; c < n; ++c) std::swap(A[(size_t)k * n + c], A[(size_t)piv * n + c]);
+      std::swap(x[k], x[piv]);
+    }
+    const double d = A[(size_t)k * n + k];
+    for (int r = k + 1; r < n; ++r) {
+      const double f = A[(size_t)r * n + k] / d;
+      if (f == 0.0) continue;
+      for (int c = k; c < n; ++c) A[(size_t)r * n + c] -= f * A[(size_t)k * n + c];
+      x[r] -= f * x[k];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double s = x[k];
+    for (int c = k + 1; c < n; ++c) s -= A[(size_t)k * n + c] * x[c];
+    x[k] = s / A[(size_t)k * n + k];
+  }
+  double mean = 0.0;
+  for (int l = 0; l < n; ++l) mean += x[l];
+  *drs_mean = mean / n;
+  if (drs_per_marker)
+    for (int l = 0; l < n; ++l) drs_per_marker[l] = x[l];
+  return ok();
+}
+
+}  // extern "C"

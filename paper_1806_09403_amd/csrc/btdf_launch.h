@@ -1,0 +1,25 @@
+// btdf_launch.h -- host-side entry points of the kernels (internal to the library).
+#pragma once
+
+#include "btdf_device.h"
+
+namespace btdf {
+
+int num_variants();
+void variant_tile(int v, int *tx, int *ty);
+
+hipError_t launch_lbm(int prec, int variant, const void *A, void *B, const LbmParams &p, hipStream_t s);
+hipError_t launch_ib(int prec, const void *A, const LbmParams &p, const IbParams &ib, int threads,
+                     hipStream_t s);
+hipError_t launch_init_uniform(int prec, void *A, const LbmParams &p, double r, double u, double v,
+                               hipStream_t s);
+hipError_t launch_init_eq(int prec, void *A, const LbmParams &p, const double *rho, const double *ux,
+                          const double *uy, double rho0, int per_node_rho, hipStream_t s);
+hipError_t launch_plane_to_f64(int prec, const void *A, const LbmParams &p, int q, double *out,
+                               hipStream_t s);
+hipError_t launch_f64_to_plane(int prec, void *A, const LbmParams &p, int q, const double *in,
+                               hipStream_t s);
+hipError_t launch_macro(int prec, const void *A, const LbmParams &p, double *rho, double *ux, double *uy,
+                        hipStream_t s);
+
+}  // namespace btdf

@@ -1,0 +1,132 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, validates its arguments on the host (no device call is
+made before an argument error), and its host-side thickness calibration
+(eqs 22, 25, 26) equals the oracle's."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import btdf_workloads as W
+from oracle import calib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "btdf.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1806_09403_amd import _lib, build
+    if not os.path.exists(_lib.LIB_PATH):
+        build.build()
+    return _lib.load()
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(btdf_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_1806_09403_amd import _lib
+    names = declared()
+    assert len(names) >= 20
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (btdf_[a-z_]+)\b", out))
+    assert set(names) <= exported, sorted(set(names) - exported)
+    assert set(names) == set(_lib.SIGNATURES), sorted(set(names) ^ set(_lib.SIGNATURES))
+    for n in names:
+        getattr(lib, n)
+
+
+def err(fn, *a, **k):
+    from paper_1806_09403_amd import BtdfError
+    with pytest.raises(BtdfError) as e:
+        fn(*a, **k)
+    return e.value
+
+
+def test_create_validation(lib):
+    from paper_1806_09403_amd import api
+    good = dict(bc=W.CHANNEL, inflow=(0.02, 0.0), init=(1.0, 0.02, 0.0))
+    bad = [
+        ((7, 50, 0.6, W.COS4, 2.6), good, "nx and ny"),
+        ((50, 50, 0.5, W.COS4, 2.6), good, "tau"),
+        ((50, 50, float("nan"), W.COS4, 2.6), good, "tau"),
+        ((50, 50, 0.6, 7, 2.6), good, "delta kind"),
+        ((50, 50, 0.6, W.COS4, 0.0), good, "thickening"),
+        ((50, 50, 0.6, W.COS4, 2.6), dict(good, bc=(1, 1, 0, 0)), "x ends"),
+        ((50, 50, 0.6, W.COS4, 2.6), dict(good, bc=(0, 0, 0, 3)), "y ends"),
+        ((50, 50, 0.6, W.COS4, 2.6), dict(good, precision=2), "precision"),
+        ((50, 50, 0.6, W.COS4, 2.6), dict(good, init=(0.0, 0.0, 0.0)), "rho0"),
+    ]
+    for args, kw, msg in bad:
+        e = err(api.btdf_create, *args, **kw)
+        assert e.code == -1 and msg in str(e), (args, kw, str(e))
+    h = api.btdf_create(50, 50, 0.6, W.COS4, 2.6, **good)
+    api.btdf_destroy(h)
+    assert lib.btdf_destroy(None) == 0
+
+
+def test_add_body_validation_and_workspace(lib):
+    from paper_1806_09403_amd import api
+    h = api.btdf_create(64, 40, 0.6, W.COS4, 2.6, bc=W.CHANNEL, inflow=(0.02, 0.0))
+    try:
+        w0 = api.btdf_workspace_bytes(h)
+        assert err(api.btdf_add_body, h, np.zeros((2, 2))).code == -1          # n < 3
+        # stencil leaving the fluid columns (x = 1 .. 62) at the inlet side
+        xy = W.cylinder_markers(3.0, 20.0, 4.0, 12)
+        e = err(api.btdf_add_body, h, xy)
+        assert "fluid columns" in str(e)
+        nan = W.cylinder_markers(30.0, 20.0, 8.0, 12)
+        nan[3, 0] = np.nan
+        assert "non-finite" in str(err(api.btdf_add_body, h, nan))
+        assert api.btdf_counts(h) == (0, 0, 0)
+        b = W.cylinder_body(30.0, 20.0, 8.0)
+        assert api.btdf_add_body(h, b.xy, None, b.cx, b.cy, b.ds) == 0
+        assert api.btdf_add_body(h, b.xy + [5.0, 0.0], None, b.cx + 5, b.cy, 0.0) == 1
+        nb, nm, ns = api.btdf_counts(h)
+        assert (nb, nm, ns) == (2, 2 * b.xy.shape[0], 0)
+        assert api.btdf_workspace_bytes(h) > w0
+        assert "no body" in str(err(api.btdf_set_marker_velocity, h, 5, np.zeros((3, 2))))
+        assert err(api.btdf_set_option, h, 999, 0).code == -1
+        assert err(api.btdf_set_option, h, 1, 10 ** 6).code == -1
+        assert api.btdf_get_option(h, 2) >= 2
+        assert err(api.btdf_step, h, -1).code == -1
+    finally:
+        api.btdf_destroy(h)
+
+
+def test_periodic_markers_may_leave_the_box(lib):
+    from paper_1806_09403_amd import api
+    h = api.btdf_create(64, 48, 0.6, W.ROMA3, 1.9)
+    try:
+        b = W.cylinder_body(1.0, 47.5, 10.0)           # straddles two periodic edges
+        assert api.btdf_add_body(h, b.xy, None, b.cx, b.cy, b.ds) == 0
+    finally:
+        api.btdf_destroy(h)
+
+
+@pytest.mark.parametrize("kind", [W.LINEAR2, W.ROMA3, W.PESKIN4, W.COS4])
+@pytest.mark.parametrize("D,ratio", [(16.0, 1.0), (20.0, 0.8), (40.0, 1.3), (9.0, 1.0)])
+def test_calibration_matches_oracle(lib, kind, D, ratio):
+    from paper_1806_09403_amd import api
+    n = int(round(np.pi * D / ratio))
+    xy = W.cylinder_markers(50.3, 47.9, D, n)
+    ds = np.pi * D / n
+    mean, per = api.btdf_calibrate_thickening(kind, xy, ds)
+    ref = calib.thickness_vector(kind, xy, ds)
+    assert abs(mean - ref.mean()) < 1e-11 * abs(ref.mean())
+    assert np.max(np.abs(per - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+def test_calibration_errors(lib):
+    from paper_1806_09403_amd import api
+    xy = np.array([[1.0, 1.0], [1.0, 1.0], [3.0, 1.0]])   # two coincident markers: A singular
+    assert err(api.btdf_calibrate_thickening, W.ROMA3, xy, 1.0).code == -4
+    assert err(api.btdf_calibrate_thickening, 9, xy, 1.0).code == -1
+    assert err(api.btdf_calibrate_thickening, W.ROMA3, xy, 0.0).code == -1

@@ -1,0 +1,162 @@
+"""GPU runs checked against what the method fixes at any size, the stored
+oracle history of the Re = 200 channel, the instability guard, and the
+full 8192^2 particle-laden workload one step at a time against the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import btdf_workloads as W
+from oracle.oracle import OracleSim
+
+pytestmark = pytest.mark.gpu
+
+EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def sim(*a, **k):
+    from paper_1806_09403_amd import Sim
+    return Sim(*a, **k)
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_mass_and_momentum_budget(precision):
+    c = W.random_case(20, nx=128, ny=96, n_bodies=3, precision=precision)
+    from paper_1806_09403_amd import Sim
+    g = Sim.from_case(c)
+    f0 = g.populations()
+    m0 = f0.sum()
+    for _ in range(5):
+        p0 = np.einsum("q,qij->", EX, g.populations())
+        g.step(1)
+        f1 = g.populations()
+        p1 = np.einsum("q,qij->", EX, f1)
+        drag = g.forces()[:, 0].sum()
+        tol = 1e-12 if precision == 8 else 2e-4
+        assert abs((p1 - p0) - (c.nx * c.ny * c.G[0] - drag)) < tol * (abs(p0) + abs(drag) + 1)
+    rel = abs(f1.sum() - m0) / m0
+    log("  precision %d: relative mass drift %.2e" % (precision, rel))
+    assert rel < (1e-13 if precision == 8 else 1e-6)
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_uniform_flow_with_comoving_markers(precision):
+    u0 = (0.03, -0.01)
+    g = sim(96, 64, 0.7, W.COS4, 2.6, init=(1.0,) + u0, precision=precision)
+    b = W.cylinder_body(40.3, 30.7, 20.0)
+    g.add_body(b.xy, np.tile(u0, (b.xy.shape[0], 1)), b.cx, b.cy, b.ds)
+    f0 = g.populations()
+    g.step(40)
+    md = g.marker_data()
+    tol = 1e-15 if precision == 8 else 1e-8
+    assert np.max(np.abs(md["Fx"])) < tol and np.max(np.abs(md["Fy"])) < tol
+    assert np.max(np.abs(g.populations() - f0)) < (1e-15 if precision == 8 else 1e-8)
+
+
+@pytest.mark.parametrize("precision,tol", [(8, 1e-9), (4, 2e-3)])
+def test_poiseuille_bounce_back(precision, tol):
+    H, G, tau = 16, 1e-6, 0.8
+    nu = (tau - 0.5) / 3
+    g = sim(8, H, tau, W.COS4, 2.6, bc=(0, 0, 3, 3), body_force=(G, 0.0), precision=precision)
+    g.step(int(40 * H * H / (np.pi ** 2 * nu)) + 1000)
+    _, u, _ = g.macroscopic()
+    y = np.arange(H) + 0.5
+    exact = G / (2 * nu) * y * (H - y) + G * (16 * tau * tau - 16 * tau + 1) / (24 * nu)
+    err = np.max(np.abs(u[:, 3] - exact)) / np.max(exact)
+    log("  poiseuille precision %d rel err %.2e" % (precision, err))
+    assert err < tol
+
+
+def test_instability_guard():
+    from paper_1806_09403_amd import BtdfUnstable
+    c = W.random_case(21, nx=64, ny=64, n_bodies=1)
+    from paper_1806_09403_amd import Sim
+    g = Sim.from_case(c, precision=4)
+    g.step(2)
+    g.forces()
+    f = g.populations()
+    b = c.bodies[0]
+    i, j = int(np.floor(b.xy[0, 0])) % c.nx, int(np.floor(b.xy[0, 1])) % c.ny
+    f[0, j, i] = np.nan
+    g.set_populations(f)
+    g.step(1)
+    with pytest.raises(BtdfUnstable) as e:
+        g.forces()
+    assert "body 0" in str(e.value) or "density" in str(e.value)
+    # the oracle flags the same condition
+    o = OracleSim(c.nx, c.ny, c.bc, c.tau, c.kind, c.thickening, c.G, c.inflow, c.init)
+    o.add_body(b.xy, b.uv, b.cx, b.cy, b.ds)
+    o.set_populations(f)
+    o.step(1)
+    assert o.unstable != 0
+    # clearing the state clears the flag
+    ux, uy = c.init_fields()
+    g.init_equilibrium(ux, uy)
+    g.step(1)
+    g.forces()
+
+
+def test_channel_re200_forces_match_stored_oracle():
+    ref = np.loadtxt(os.path.join(GOLD, "c2_oracle_forces_5k.txt"))
+    c = W.c2()
+    from paper_1806_09403_amd import Sim
+    log("fp32 2000x800 channel, 5000 steps")
+    g = Sim.from_case(c, precision=4)
+    rows = []
+    every = int(ref[1, 0] - ref[0, 0])
+    for _ in range(ref.shape[0]):
+        g.step(every)
+        rows.append(g.forces()[0])
+    F = np.array(rows)
+    q = 0.5 * c.U ** 2 * c.D
+    cd, cl = F[:, 0] / q, F[:, 1] / q
+    cd_r, cl_r = ref[:, 1] / q, ref[:, 2] / q
+    scale = np.max(np.abs(cd_r))
+    dcd = np.max(np.abs(cd - cd_r)) / scale
+    dcl = np.max(np.abs(cl - cl_r)) / scale
+    log("  max |dCd| / max|Cd| = %.2e, max |dCl| / max|Cd| = %.2e, final Cd %.4f vs %.4f"
+        % (dcd, dcl, cd[-1], cd_r[-1]))
+    # relative agreement wherever Cd is not near a zero crossing
+    big = np.abs(cd_r) > 0.1 * scale
+    assert np.max(np.abs(cd[big] - cd_r[big]) / np.abs(cd_r[big])) < 1e-3
+    assert dcd < 1e-3 and dcl < 1e-3
+
+
+@pytest.mark.parametrize("kind", [W.COS4, W.ROMA3])
+def test_particle_laden_8192_one_step_against_oracle(kind):
+    """Full 8192^2 periodic lattice with 2000 cylinders (150 000 markers), FP32,
+    in the launch configuration the benchmark times: after 20 steps the state
+    is handed to the oracle, both take one step, and every population, marker
+    force and body force is compared."""
+    from paper_1806_09403_amd import Sim
+    c = W.c3(kind=kind)
+    log("8192^2 kind=%d: building GPU case" % kind)
+    g = Sim.from_case(c, precision=4)
+    g.step(20)
+    f = g.populations()
+    log("  oracle setup")
+    o = OracleSim(c.nx, c.ny, c.bc, c.tau, c.kind, c.thickening, c.G, c.inflow, c.init)
+    for b in c.bodies:
+        o.add_body(b.xy, b.uv, b.cx, b.cy, b.ds)
+    o.set_populations(f)
+    del f
+    log("  one step each")
+    o.step(1)
+    g.step(1)
+    d = np.max(np.abs(g.populations() - o.populations()))
+    log("  max |df| = %.3e" % d)
+    assert d < 2e-7
+    mo, mg = o.marker_data(), g.marker_data()
+    for k in ("Fx", "Fy"):
+        rel = np.max(np.abs(mg[k] - mo[k])) / np.max(np.abs(mo[k]))
+        log("  %s rel %.2e" % (k, rel))
+        assert rel < 1e-12
+    Fo, Fg = o.forces(), g.forces()
+    assert np.max(np.abs(Fg - Fo)) < 1e-12 * np.max(np.abs(Fo))
+    o.close()

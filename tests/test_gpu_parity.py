@@ -1,0 +1,220 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle,
+element by element, on seeded inputs.
+
+FP64 populations: every population, marker force and body force after
+each step agrees with the oracle to a few ulps of the values involved
+(the two differ only in summation order and FMA contraction); after the
+2000 steps of the 200x120 Re = 40 channel the velocity field agrees to
+1e-12 relative. FP32 populations: one step from the same state agrees to
+the FP32 rounding of the stored deviations, the marker forces (computed in
+FP64 from the FP32 populations) to 1e-12 relative.
+"""
+import numpy as np
+import pytest
+
+import btdf_workloads as W
+from oracle.oracle import OracleSim
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_of(c):
+    s = OracleSim(c.nx, c.ny, c.bc, c.tau, c.kind, c.thickening, c.G, c.inflow, c.init)
+    for b in c.bodies:
+        s.add_body(b.xy, b.uv, b.cx, b.cy, b.ds)
+    if c.init_uy is not None:
+        ux, uy = c.init_fields()
+        s.init_equilibrium(ux, uy, np.full((c.ny, c.nx), c.init[0]))
+    return s
+
+
+def gpu_of(c, precision=None, **opts):
+    from paper_1806_09403_amd import Sim
+    s = Sim.from_case(c, precision=precision)
+    for k, v in opts.items():
+        s.set_option(k, v)
+    return s
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+CASES = [
+    # (seed, nx, ny, kind, bc) -- ragged against every tile shape
+    (0, 197, 83, W.COS4, W.FULLY_PERIODIC),
+    (1, 131, 70, W.ROMA3, W.CHANNEL),
+    (2, 70, 61, W.PESKIN4, (W.PERIODIC, W.PERIODIC, W.BOUNCEBACK_WALL, W.BOUNCEBACK_WALL)),
+    (3, 90, 37, W.LINEAR2, (W.VELOCITY_INLET, W.ZERO_GRADIENT_OUTLET, W.BOUNCEBACK_WALL,
+                            W.BOUNCEBACK_WALL)),
+    (4, 300, 9, W.COS4, W.FULLY_PERIODIC),
+]
+
+
+@pytest.mark.parametrize("seed,nx,ny,kind,bc", CASES)
+def test_fp64_steps_match_oracle(seed, nx, ny, kind, bc):
+    log("fp64 parity seed=%d %dx%d kind=%d bc=%s" % (seed, nx, ny, kind, bc))
+    c = W.random_case(seed, nx=nx, ny=ny, kind=kind, bc=bc, n_bodies=3 if ny > 20 else 1)
+    o, g = oracle_of(c), gpu_of(c, precision=8)
+    assert np.max(np.abs(g.populations() - o.populations())) < 1e-15
+    for step in range(6):
+        o.step(1)
+        g.step(1)
+        fo, fg = o.populations(), g.populations()
+        assert np.max(np.abs(fg - fo)) < 1e-14, step
+        mo, mg = o.marker_data(), g.marker_data()
+        scale = max(1e-300, np.max(np.abs(mo["Fx"])) + np.max(np.abs(mo["Fy"])))
+        for k in ("Fx", "Fy"):
+            assert np.max(np.abs(mg[k] - mo[k])) < 1e-12 * scale, (step, k)
+        for k in ("rho", "ux", "uy"):
+            assert np.max(np.abs(mg[k] - mo[k])) < 1e-14, (step, k)
+        Fo, Fg = o.forces(), g.forces()
+        assert np.max(np.abs(Fg - Fo)) < 1e-12 * max(1e-300, np.max(np.abs(Fo))), step
+    ro, uo, vo = o.macroscopic()
+    rg, ug, vg = g.macroscopic()
+    assert np.max(np.abs(rg - ro)) < 1e-14
+    assert np.max(np.abs(ug - uo)) < 1e-14 and np.max(np.abs(vg - vo)) < 1e-14
+
+
+def test_fp64_channel_2000_steps():
+    c = W.c1()
+    log("fp64 200x120 channel, 2000 steps")
+    o, g = oracle_of(c), gpu_of(c, precision=8)
+    Fo, Fg = [], []
+    for _ in range(20):
+        o.step(100)
+        g.step(100)
+        Fo.append(o.forces()[0])
+        Fg.append(g.forces()[0])
+    _, uo, vo = o.macroscopic()
+    _, ug, vg = g.macroscopic()
+    umax = max(np.max(np.abs(uo)), np.max(np.abs(vo)))
+    err = max(np.max(np.abs(ug - uo)), np.max(np.abs(vg - vo))) / umax
+    log("  max |du| / max |u| = %.3e" % err)
+    assert err < 1e-12
+    Fo, Fg = np.array(Fo), np.array(Fg)
+    cd_o = 2 * Fo[:, 0] / (c.U ** 2 * c.D)
+    cd_g = 2 * Fg[:, 0] / (c.U ** 2 * c.D)
+    assert np.max(np.abs(cd_g - cd_o)) < 1e-10 * np.max(np.abs(cd_o))
+    assert np.max(np.abs(Fg[:, 1] - Fo[:, 1])) < 1e-10 * np.max(np.abs(Fo[:, 0]))
+
+
+def test_force_history_matches_oracle():
+    c = W.random_case(11, nx=64, ny=48, n_bodies=2)
+    o, g = oracle_of(c), gpu_of(c, precision=8)
+    ref = []
+    for _ in range(25):
+        o.step(1)
+        ref.append(o.forces())
+    g.step(25)
+    hist = g.force_history(100)
+    assert hist.shape == (25, 2, 3)
+    assert np.max(np.abs(hist - np.array(ref))) < 1e-12 * np.max(np.abs(ref))
+    assert g.force_history(100).shape[0] == 0
+    assert np.allclose(g.forces(), ref[-1], rtol=0, atol=1e-12 * np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("seed,kind,bc", [(5, W.COS4, W.FULLY_PERIODIC), (6, W.ROMA3, W.CHANNEL)])
+def test_fp32_one_step_from_same_state(seed, kind, bc):
+    c = W.random_case(seed, nx=203, ny=77, kind=kind, bc=bc, n_bodies=3)
+    g = gpu_of(c, precision=4)
+    g.step(7)
+    f = g.populations()                # FP32 state as FP64 full populations
+    o = oracle_of(c)
+    o.set_populations(f)
+    o.step(1)
+    g.step(1)
+    d = np.max(np.abs(g.populations() - o.populations()))
+    log("  fp32 one-step max |df| = %.3e" % d)
+    assert d < 2e-7
+    mo, mg = o.marker_data(), g.marker_data()
+    for k in ("Fx", "Fy"):
+        assert np.max(np.abs(mg[k] - mo[k])) < 1e-12 * np.max(np.abs(mo[k]))
+    assert np.max(np.abs(g.forces() - o.forces())) < 1e-12 * np.max(np.abs(o.forces()))
+
+
+def test_every_launch_shape_is_bit_identical():
+    from paper_1806_09403_amd import _lib
+    c = W.random_case(8, nx=263, ny=50, kind=W.COS4, bc=W.FULLY_PERIODIC, n_bodies=3)
+    ref = None
+    g0 = gpu_of(c, precision=4)
+    nv = g0.get_option(_lib.OPT_NUM_VARIANTS)
+    for v in range(nv):
+        for remap in (0, 1):
+            g = gpu_of(c, precision=4)
+            g.set_option(_lib.OPT_LBM_VARIANT, v)
+            g.set_option(_lib.OPT_XCD_REMAP, remap)
+            g.step(9)
+            f = g.populations()
+            if ref is None:
+                ref = f
+            assert np.array_equal(f, ref), (v, remap)
+
+
+def test_graph_replay_is_bit_identical():
+    from paper_1806_09403_amd import _lib
+    c = W.random_case(9, nx=120, ny=64, n_bodies=2)
+    a = gpu_of(c, precision=8)
+    b = gpu_of(c, precision=8)
+    b.set_option(_lib.OPT_GRAPH_CHUNK, 6)
+    for n in (1, 13, 6, 5, 20):      # odd counts realign, several replays per call
+        a.step(n)
+        b.step(n)
+        assert np.array_equal(a.populations(), b.populations()), n
+        assert np.array_equal(a.forces(), b.forces()), n
+    hb = b.force_history(100)
+    ha = a.force_history(100)
+    assert np.array_equal(ha, hb)
+
+
+def test_deterministic_runs():
+    c = W.random_case(10, nx=150, ny=90, n_bodies=3)
+    runs = []
+    for _ in range(2):
+        g = gpu_of(c, precision=4)
+        g.step(30)
+        runs.append((g.populations(), g.forces()))
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+
+
+def test_save_load_resume_bit_identical():
+    c = W.random_case(12, nx=96, ny=40, n_bodies=2)
+    a = gpu_of(c, precision=4)
+    a.step(10)
+    state = a.save()
+    a.step(10)
+    b = gpu_of(c, precision=4)
+    b.load(state)
+    b.step(10)
+    assert np.array_equal(a.populations(), b.populations())
+    assert np.array_equal(a.forces(), b.forces())
+
+
+def test_no_bodies_and_minimum_grid():
+    from paper_1806_09403_amd import Sim
+    for nx, ny in ((8, 8), (9, 13)):
+        o = OracleSim(nx, ny, W.FULLY_PERIODIC, 0.7, W.COS4, 2.6, G=(1e-5, 0.0))
+        g = Sim(nx, ny, 0.7, W.COS4, 2.6, body_force=(1e-5, 0.0))
+        y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+        ux = 0.01 * np.sin(2 * np.pi * y / ny)
+        uy = 0.01 * np.cos(2 * np.pi * x / nx)
+        o.init_equilibrium(ux, uy)
+        g.init_equilibrium(ux, uy)
+        o.step(5)
+        g.step(5)
+        assert np.max(np.abs(g.populations() - o.populations())) < 1e-15
+        assert g.forces().shape == (0, 3)
+
+
+def test_large_body_and_small_bodies():
+    # one body with more markers than a workgroup (loop in the marker kernel)
+    # and three-marker bodies
+    c = W.random_case(13, nx=160, ny=160, n_bodies=0)
+    c.bodies = [W.cylinder_body(80.0, 80.0, 110.0, 700),
+                W.cylinder_body(20.0, 20.0, 2.0, 3), W.cylinder_body(140.5, 20.2, 3.0, 3)]
+    o, g = oracle_of(c), gpu_of(c, precision=8)
+    for _ in range(3):
+        o.step(1)
+        g.step(1)
+    assert np.max(np.abs(g.populations() - o.populations())) < 1e-14
+    assert np.max(np.abs(g.forces() - o.forces())) < 1e-12 * np.max(np.abs(o.forces()))
