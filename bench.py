@@ -34,6 +34,12 @@ def parse():
     p.add_argument("--delta", choices=["cos4", "roma3", "peskin4"], default="cos4")
     p.add_argument("--variant", type=int, default=-1, help="lattice launch shape (-1: library default)")
     p.add_argument("--graph-chunk", type=int, default=0)
+    p.add_argument("--row-pad", type=int, default=0)
+    p.add_argument("--interior", type=int, default=-1, help="1/0: uniform-base path for interior waves (-1: library default)")
+    p.add_argument("--overlap", type=int, default=-1, help="1/0: marker kernel beside the lattice kernel (-1: library default)")
+    p.add_argument("--plane-pad", type=int, default=0)
+    p.add_argument("--copy-probe-mb", type=int, default=0,
+                   help="before timing, copy a tensor of this size once (counter calibration)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-budget-s", type=float, default=20.0)
     return p.parse_args()
@@ -86,13 +92,38 @@ def main():
 
     case, prec = make_case(args)
     t_setup = time.perf_counter()
-    sim = Sim.from_case(case, precision=prec)
+    sim = Sim.from_case(case, precision=prec, set_init=False)
+    if args.row_pad:
+        sim.set_option(_lib.OPT_ROW_PAD, args.row_pad)
+    if args.plane_pad:
+        sim.set_option(_lib.OPT_PLANE_PAD, args.plane_pad)
+    if case.init_uy is not None:
+        import numpy as np
+        ux, uy = case.init_fields()
+        sim.init_equilibrium(ux, uy, np.full((case.ny, case.nx), case.init[0]))
     if args.variant >= 0:
         sim.set_option(_lib.OPT_LBM_VARIANT, args.variant)
     if args.graph_chunk:
         sim.set_option(_lib.OPT_GRAPH_CHUNK, args.graph_chunk)
+    if args.interior >= 0:
+        sim.set_option(_lib.OPT_INTERIOR_PATH, args.interior)
+    if args.overlap >= 0:
+        sim.set_option(_lib.OPT_OVERLAP, args.overlap)
     sim.step(args.warmup)
     torch.cuda.synchronize()
+    if args.copy_probe_mb:
+        nbytes = args.copy_probe_mb << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        print("copy probe: %d MiB read + %d MiB written in %.3f ms (%.1f GB/s)"
+              % (args.copy_probe_mb, args.copy_probe_mb, (t1 - t0) * 1e3, 2 * nbytes / (t1 - t0) / 1e9),
+              file=sys.stderr, flush=True)
+        del src, dst
     print("setup + warmup %.1f s" % (time.perf_counter() - t_setup), file=sys.stderr, flush=True)
 
     torch.cuda.synchronize()
@@ -131,6 +162,9 @@ def main():
         "config": {"workload": case.name, "nx": case.nx, "ny": case.ny, "bodies": nb, "markers": nm,
                    "delta": args.delta, "thickening": case.thickening, "tau": case.tau,
                    "lbm_variant": sim.get_option(_lib.OPT_LBM_VARIANT),
+                   "row_pad": args.row_pad, "plane_pad": args.plane_pad,
+                   "interior_path": sim.get_option(_lib.OPT_INTERIOR_PATH),
+                   "overlap": sim.get_option(_lib.OPT_OVERLAP),
                    "graph_chunk": args.graph_chunk},
         "kernel_ms": {"ib_kernel": round(ms_ib, 5), "lbm_kernel": round(ms_lbm, 5)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -182,14 +182,14 @@ def c5(steps=5000, precision=4) -> Case:
 
 
 def random_case(seed, nx=37, ny=29, kind=COS4, bc=FULLY_PERIODIC, n_bodies=2, precision=8,
-                G=(1e-5, -4e-6), moving=True, tau=0.7) -> Case:
+                G=(1e-5, -4e-6), moving=True, tau=0.7, D_range=(4.0, 9.0)) -> Case:
     """Small seeded case with several bodies, prescribed marker velocities, a
     body force and a smooth non-uniform initial flow (parity tests)."""
     rng = np.random.default_rng(seed)
     bodies = []
     margin = 5.0
     for b in range(n_bodies):
-        D = float(rng.uniform(4.0, 9.0))
+        D = float(rng.uniform(*D_range))
         lo_x = margin + D / 2 if bc[0] != PERIODIC else 0.0
         hi_x = nx - 1 - margin - D / 2 if bc[0] != PERIODIC else float(nx)
         lo_y = margin + D / 2 if bc[2] != PERIODIC else 0.0

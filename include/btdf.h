@@ -72,12 +72,17 @@ extern "C" {
 #define BTDF_COS4 5
 
 /* ---- option keys (btdf_set_option / btdf_get_option) ---- */
-#define BTDF_OPT_LBM_VARIANT 1   /* launch shape of the lattice kernel, 0 .. BTDF_OPT_NUM_VARIANTS-1 */
+#define BTDF_OPT_LBM_VARIANT 1   /* launch shape of the lattice kernel, 0 .. BTDF_OPT_NUM_VARIANTS-1 (default 6: 32x8 tiles) */
 #define BTDF_OPT_NUM_VARIANTS 2  /* read-only: number of lattice launch shapes */
 #define BTDF_OPT_GRAPH_CHUNK 3   /* steps per captured HIP graph; 0 = plain launches (default 0) */
 #define BTDF_OPT_XCD_REMAP 4     /* 1 = map consecutive tiles to one XCD (default 1) */
 #define BTDF_OPT_TILE_X 5        /* read-only: tile width of the current variant */
 #define BTDF_OPT_TILE_Y 6        /* read-only: tile height of the current variant */
+#define BTDF_OPT_ROW_PAD 7       /* elements added to each grid row (>= 0); only before the first device use */
+#define BTDF_OPT_PLANE_PAD 8     /* elements added to each population plane, multiple of 64; same restriction */
+#define BTDF_OPT_INTERIOR_PATH 9 /* 1: waves away from every edge load from wave-uniform bases; 0 (default): always the general pull */
+#define BTDF_OPT_OVERLAP 10      /* 1: marker kernel on a second stream beside the lattice tiles it does not touch; 0 (default): in order */
+#define BTDF_OPT_FORCED_TILES 11 /* read-only: lattice tiles touched by some marker's stencil */
 
 typedef struct btdf_grid {
   int32_t nx, ny;               /* nodes, ghost columns included; each >= 8 */
@@ -154,10 +159,11 @@ int btdf_set_marker_velocity(btdf_t *h, int body, const double *uv);
  * replaced by btdf_init_equilibrium, btdf_set_populations or btdf_load). */
 int btdf_step(btdf_t *h, int64_t n);
 
-/* Same as btdf_step, but times each kernel launch with HIP events on the
- * handle's stream and writes the mean duration per launch in milliseconds
- * of the marker kernel (*ms_ib, 0 if no bodies) and of the lattice kernel
- * (*ms_lbm). Synchronising. */
+/* Same as btdf_step, but times the kernels with HIP events on the streams
+ * they run on and writes, in milliseconds per step, the duration of the
+ * marker kernel (*ms_ib, 0 if no bodies) and of the lattice kernel (*ms_lbm;
+ * the sum of its launches when the marker kernel overlaps it).
+ * Synchronising. */
 int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm);
 
 /* Hydrodynamic force and torque on every body at the last step:
@@ -206,7 +212,8 @@ int btdf_load(btdf_t *h, const void *src, size_t bytes);
 /* Number of bodies, total markers and steps taken so far. */
 int btdf_counts(const btdf_t *h, int *n_bodies, int *n_markers, int64_t *n_steps);
 
-/* Tuning knobs (BTDF_OPT_*). set returns EINVAL for unknown keys or values. */
+/* Tuning knobs (BTDF_OPT_*). set returns EINVAL for unknown keys or values,
+ * ESTATE for a layout option once the populations exist on the device. */
 int btdf_set_option(btdf_t *h, int key, int64_t value);
 int btdf_get_option(const btdf_t *h, int key, int64_t *value);
 

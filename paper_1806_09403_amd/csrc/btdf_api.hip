@@ -83,9 +83,15 @@ struct btdf_sim {
   std::vector<int> off{0};
   std::vector<double> cx, cy, bsdrs;
   // lattice kernel launch shape and tiles
-  int variant = 0, xcd_remap = 1, graph_chunk = 0;
+  // launch defaults measured fastest on the 8192^2 particle-laden workload:
+  // 32x8 tiles, general pull, marker kernel before the lattice kernel
+  int variant = 6, xcd_remap = 1, graph_chunk = 0, interior = 0;
+  int row_pad = 0, plane_pad = 0;
   int tile_x = 64, tile_y = 4, ntx = 0, nty = 0;
   std::vector<int> tile_off, tile_list;
+  std::vector<int> tile_map;  // tiles no marker touches first, then the forced tiles
+  int n_free = 0, n_forced = 0;
+  int overlap = 0;            // run the marker kernel beside the lattice launch of the free tiles
   // device memory
   char *ws = nullptr;
   size_t ws_bytes = 0;
@@ -94,7 +100,8 @@ struct btdf_sim {
   int pitch = 0;
   long long plane = 0;
   size_t off_pop[2] = {0, 0}, off_ctl = 0, grid_bytes = 0;
-  size_t off_hist = 0, off_mk = 0, off_body = 0, off_boff = 0, off_toff = 0, off_tlist = 0, total = 0;
+  size_t off_hist = 0, off_mk = 0, off_mkw = 0, off_mkixy = 0, off_mkbody = 0, off_body = 0, off_boff = 0,
+         off_toff = 0, off_tlist = 0, off_tmap = 0, total = 0;
   bool layout_ok = false;  // host layout current for bodies and tiles
   bool device_ok = false;  // body part uploaded into the workspace
   bool state_ok = false;   // populations hold a state
@@ -102,10 +109,11 @@ struct btdf_sim {
   int64_t steps = 0, hist_read = 0;
   int64_t forces_from = 0;   // first step whose ring entry matches the body set
   bool bodies_dirty = true;  // ring layout on the device predates the body set
-  int ib_threads = 64;
   // graph of graph_chunk steps starting from buffer 0
   hipGraphExec_t graph = nullptr;
   hipStream_t cap_stream = nullptr;
+  hipStream_t side = nullptr;            // marker kernel when it overlaps the lattice kernel
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   int nb() const { return (int)cx.size(); }
   int nm() const { return (int)X.size(); }
@@ -137,8 +145,8 @@ int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
 
 void compute_layout(btdf_t *h) {
   const size_t elt = (size_t)h->prec;
-  h->pitch = h->nx;
-  h->plane = (((long long)h->nx * h->ny + 63) / 64) * 64;
+  h->pitch = h->nx + h->row_pad;
+  h->plane = (((long long)h->pitch * h->ny + 63) / 64) * 64 + h->plane_pad;
   const size_t pop_bytes = align256(9 * (size_t)h->plane * elt);
   h->off_pop[0] = 0;
   h->off_pop[1] = pop_bytes;
@@ -182,6 +190,14 @@ void compute_layout(btdf_t *h) {
     tiles_of(l);
     for (int t : touched) h->tile_list[fill[t]++] = l;
   }
+  h->tile_map.clear();
+  h->tile_map.reserve(ntiles);
+  for (int t = 0; t < ntiles; ++t)
+    if (h->tile_off[t + 1] == h->tile_off[t]) h->tile_map.push_back(t);
+  h->n_free = (int)h->tile_map.size();
+  for (int t = 0; t < ntiles; ++t)
+    if (h->tile_off[t + 1] != h->tile_off[t]) h->tile_map.push_back(t);
+  h->n_forced = ntiles - h->n_free;
 
   const int nb = h->nb(), nm = h->nm();
   size_t o = h->grid_bytes;
@@ -189,6 +205,12 @@ void compute_layout(btdf_t *h) {
   o = align256(o + (size_t)h->hist_cap * std::max(nb, 1) * 3 * sizeof(double));
   h->off_mk = o;  // X Y U V sdrs Fx Fy rho ux uy
   o = align256(o + 10 * (size_t)std::max(nm, 1) * sizeof(double));
+  h->off_mkw = o;  // 10 values per marker in the population type
+  o = align256(o + 10 * (size_t)std::max(nm, 1) * elt);
+  h->off_mkixy = o;
+  o = align256(o + 2 * (size_t)std::max(nm, 1) * sizeof(int));
+  h->off_mkbody = o;
+  o = align256(o + (size_t)std::max(nm, 1) * sizeof(int));
   h->off_body = o;  // cx cy bsdrs
   o = align256(o + 3 * (size_t)std::max(nb, 1) * sizeof(double));
   h->off_boff = o;
@@ -197,11 +219,11 @@ void compute_layout(btdf_t *h) {
   o = align256(o + (size_t)(ntiles + 1) * sizeof(int));
   h->off_tlist = o;
   o = align256(o + h->tile_list.size() * sizeof(int));
+  h->off_tmap = o;
+  o = align256(o + (size_t)ntiles * sizeof(int));
   h->total = o;
 
-  int mx = 1;
-  for (int b = 0; b < nb; ++b) mx = std::max(mx, h->off[b + 1] - h->off[b]);
-  h->ib_threads = std::min(256, std::max(64, ((mx + 63) / 64) * 64));
+
   h->layout_ok = true;
   h->device_ok = false;
   drop_graph(h);
@@ -228,15 +250,11 @@ LbmParams make_params(const btdf_t *h) {
   p.ntx = h->ntx;
   p.nty = h->nty;
   p.xcd_remap = h->xcd_remap;
-  const size_t M = (size_t)std::max(h->nm(), 1);
-  double *mk = h->at<double>(h->off_mk);
+  p.interior = h->interior;
   p.tile_off = h->at<int>(h->off_toff);
   p.tile_list = h->at<int>(h->off_tlist);
-  p.X = mk;
-  p.Y = mk + M;
-  p.sdrs = mk + 4 * M;
-  p.Fx = mk + 5 * M;
-  p.Fy = mk + 6 * M;
+  p.mk_w = h->ws + h->off_mkw;
+  p.mk_ixy = h->at<int>(h->off_mkixy);
   p.kind = h->kind;
   p.step_ctr = h->at<long long>(h->off_ctl);
   p.flag = h->at<int>(h->off_ctl + 8);
@@ -249,7 +267,10 @@ IbParams make_ib(const btdf_t *h) {
   double *mk = h->at<double>(h->off_mk);
   double *bd = h->at<double>(h->off_body);
   ib.nb = h->nb();
+  ib.nm = h->nm();
   ib.body_off = h->at<int>(h->off_boff);
+  ib.mk_body = h->at<int>(h->off_mkbody);
+  ib.slot = h->at<int>(h->off_ctl + 16);
   ib.X = mk;
   ib.Y = mk + M;
   ib.U = mk + 2 * M;
@@ -259,6 +280,9 @@ IbParams make_ib(const btdf_t *h) {
   ib.rho_l = mk + 7 * M;
   ib.ux_l = mk + 8 * M;
   ib.uy_l = mk + 9 * M;
+  ib.sdrs = mk + 4 * M;
+  ib.mk_w = h->ws + h->off_mkw;
+  ib.mk_ixy = h->at<int>(h->off_mkixy);
   ib.cx = bd;
   ib.cy = bd + B;
   ib.body_sdrs = bd + 2 * B;
@@ -288,8 +312,14 @@ int upload_bodies(btdf_t *h) {
   if ((rc = upload(h, h->off_body + 1 * B * d, h->cy.data(), nb * d))) return rc;
   if ((rc = upload(h, h->off_body + 2 * B * d, h->bsdrs.data(), nb * d))) return rc;
   if ((rc = upload(h, h->off_boff, h->off.data(), (nb + 1) * sizeof(int)))) return rc;
+  std::vector<int> body_of((size_t)h->nm());
+  for (int b = 0; b < h->nb(); ++b)
+    for (int l = h->off[b]; l < h->off[b + 1]; ++l) body_of[l] = b;
+  if ((rc = upload(h, h->off_mkbody, body_of.data(), body_of.size() * sizeof(int)))) return rc;
+  HIPCHK(hipStreamSynchronize(h->stream));  // body_of is a local
   if ((rc = upload(h, h->off_toff, h->tile_off.data(), h->tile_off.size() * sizeof(int)))) return rc;
   if ((rc = upload(h, h->off_tlist, h->tile_list.data(), h->tile_list.size() * sizeof(int)))) return rc;
+  if ((rc = upload(h, h->off_tmap, h->tile_map.data(), h->tile_map.size() * sizeof(int)))) return rc;
   if (h->bodies_dirty)
     HIPCHK(hipMemsetAsync(h->ws + h->off_hist, 0,
                           (size_t)h->hist_cap * std::max(h->nb(), 1) * 3 * sizeof(double), h->stream));
@@ -372,12 +402,52 @@ int clear_flag(btdf_t *h) {
   return ok();
 }
 
-// one time step on the given buffers
-int enqueue_step(btdf_t *h, const LbmParams &p, const IbParams &ib, int src, hipStream_t s) {
+// events around the kernels of one step, for btdf_step_timed
+struct StepEvents {
+  hipEvent_t ib0, ib1, a0, a1, b0, b1;
+};
+
+bool overlapping(const btdf_t *h) { return h->overlap && h->nb() > 0 && h->n_free > 0 && h->n_forced > 0; }
+
+int make_side(btdf_t *h) {
+  if (!h->side) HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+  if (!h->ev_fork) HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+  if (!h->ev_join) HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+  return ok();
+}
+
+// One time step on the given buffers. With the overlap, the marker kernel
+// runs on the side stream beside the lattice launch over the tiles no marker
+// touches; the launch over the forced tiles waits for it (their spread force
+// needs this step's F_l) and advances the step counter.
+int enqueue_step(btdf_t *h, const LbmParams &p, const IbParams &ib, int src, hipStream_t s,
+                 const StepEvents *te) {
   const void *A = h->ws + h->off_pop[src];
   void *B = h->ws + h->off_pop[1 - src];
-  HIPCHK(launch_ib(h->prec, A, p, ib, h->ib_threads, s));
-  HIPCHK(launch_lbm(h->prec, h->variant, A, B, p, s));
+  const int *map = h->at<int>(h->off_tmap);
+  if (overlapping(h)) {
+    int rc = make_side(h);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(h->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+    if (te) HIPCHK(hipEventRecord(te->ib0, h->side));
+    HIPCHK(launch_ib(h->prec, A, p, ib, h->side));
+    if (te) HIPCHK(hipEventRecord(te->ib1, h->side));
+    HIPCHK(hipEventRecord(h->ev_join, h->side));
+    if (te) HIPCHK(hipEventRecord(te->a0, s));
+    HIPCHK(launch_lbm(h->prec, h->variant, A, B, p, TileRange{map, 0, h->n_free, 0}, ib, s));
+    if (te) HIPCHK(hipEventRecord(te->a1, s));
+    HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
+    if (te) HIPCHK(hipEventRecord(te->b0, s));
+    HIPCHK(launch_lbm(h->prec, h->variant, A, B, p, TileRange{map, h->n_free, h->n_forced, 1}, ib, s));
+    if (te) HIPCHK(hipEventRecord(te->b1, s));
+    return ok();
+  }
+  if (te) HIPCHK(hipEventRecord(te->ib0, s));
+  HIPCHK(launch_ib(h->prec, A, p, ib, s));
+  if (te) HIPCHK(hipEventRecord(te->ib1, s));
+  HIPCHK(launch_lbm(h->prec, h->variant, A, B, p, TileRange{nullptr, 0, h->ntx * h->nty, 1}, ib, s));
+  if (te) HIPCHK(hipEventRecord(te->a1, s));
   return ok();
 }
 
@@ -387,7 +457,7 @@ int build_graph(btdf_t *h, const LbmParams &p, const IbParams &ib) {
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
   int rc = 0;
-  for (int k = 0; k < h->graph_chunk && rc == 0; ++k) rc = enqueue_step(h, p, ib, k & 1, h->cap_stream);
+  for (int k = 0; k < h->graph_chunk && rc == 0; ++k) rc = enqueue_step(h, p, ib, k & 1, h->cap_stream, nullptr);
   hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
   if (rc) {
     if (g) (void)hipGraphDestroy(g);
@@ -465,6 +535,9 @@ int btdf_destroy(btdf_t *h) {
   }
   drop_graph(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->side) (void)hipStreamDestroy(h->side);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->ws && h->ws_owned) (void)hipFree(h->ws);
   delete h;
   return rc;
@@ -615,7 +688,7 @@ int btdf_step(btdf_t *h, int64_t n) {
   int64_t left = n;
   if (h->graph_chunk > 0 && left >= h->graph_chunk + (h->cur ? 1 : 0)) {
     if (h->cur) {  // graphs start from buffer 0
-      if ((rc = enqueue_step(h, p, ib, h->cur, h->stream))) return rc;
+      if ((rc = enqueue_step(h, p, ib, h->cur, h->stream, nullptr))) return rc;
       h->cur ^= 1;
       h->steps++;
       left--;
@@ -631,7 +704,7 @@ int btdf_step(btdf_t *h, int64_t n) {
     }
   }
   for (; left > 0; --left) {
-    if ((rc = enqueue_step(h, p, ib, h->cur, h->stream))) return rc;
+    if ((rc = enqueue_step(h, p, ib, h->cur, h->stream, nullptr))) return rc;
     h->cur ^= 1;
     h->steps++;
   }
@@ -646,37 +719,37 @@ int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm) {
   const LbmParams p = make_params(h);
   const IbParams ib = make_ib(h);
   const int chunk = 256;
-  std::vector<hipEvent_t> ev(3 * chunk, nullptr);
+  std::vector<hipEvent_t> ev(6 * chunk, nullptr);
   for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+  const bool ov = overlapping(h);
   double tib = 0.0, tlbm = 0.0;
   int64_t done = 0;
   rc = ok();
   while (done < n && rc == 0) {
     const int m = (int)std::min<int64_t>(chunk, n - done);
     for (int k = 0; k < m && rc == 0; ++k) {
-      const void *A = h->ws + h->off_pop[h->cur];
-      void *B = h->ws + h->off_pop[1 - h->cur];
-      hipError_t e = hipEventRecord(ev[3 * k], h->stream);
-      if (e == hipSuccess) e = launch_ib(h->prec, A, p, ib, h->ib_threads, h->stream);
-      if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 1], h->stream);
-      if (e == hipSuccess) e = launch_lbm(h->prec, h->variant, A, B, p, h->stream);
-      if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 2], h->stream);
-      if (e != hipSuccess) rc = fail(BTDF_EDEVICE, "timed step: %s", hipGetErrorString(e));
+      const StepEvents te{ev[6 * k], ev[6 * k + 1], ev[6 * k + 2], ev[6 * k + 3], ev[6 * k + 4], ev[6 * k + 5]};
+      rc = enqueue_step(h, p, ib, h->cur, h->stream, &te);
       h->cur ^= 1;
       h->steps++;
     }
     if (rc) break;
-    hipError_t e = hipEventSynchronize(ev[3 * (m - 1) + 2]);
+    hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
-      rc = fail(BTDF_EDEVICE, "hipEventSynchronize: %s", hipGetErrorString(e));
+      rc = fail(BTDF_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
       break;
     }
     for (int k = 0; k < m; ++k) {
-      float a = 0.f, b = 0.f;
-      (void)hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
-      (void)hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
+      float a = 0.f, b = 0.f, c = 0.f;
+      (void)hipEventElapsedTime(&a, ev[6 * k], ev[6 * k + 1]);
+      if (ov) {
+        (void)hipEventElapsedTime(&b, ev[6 * k + 2], ev[6 * k + 3]);
+        (void)hipEventElapsedTime(&c, ev[6 * k + 4], ev[6 * k + 5]);
+      } else {
+        (void)hipEventElapsedTime(&b, ev[6 * k + 1], ev[6 * k + 3]);
+      }
       tib += a;
-      tlbm += b;
+      tlbm += b + c;
     }
     done += m;
   }
@@ -897,6 +970,27 @@ int btdf_set_option(btdf_t *h, int key, int64_t value) {
       h->xcd_remap = (int)value;
       drop_graph(h);
       return ok();
+    case BTDF_OPT_OVERLAP:
+      if (value != 0 && value != 1) return fail(BTDF_EINVAL, "overlap flag must be 0 or 1");
+      h->overlap = (int)value;
+      drop_graph(h);
+      return ok();
+    case BTDF_OPT_INTERIOR_PATH:
+      if (value != 0 && value != 1) return fail(BTDF_EINVAL, "interior path flag must be 0 or 1");
+      h->interior = (int)value;
+      drop_graph(h);
+      return ok();
+    case BTDF_OPT_ROW_PAD:
+    case BTDF_OPT_PLANE_PAD:
+      if (value < 0 || value > (1 << 20) || (key == BTDF_OPT_PLANE_PAD && value % 64))
+        return fail(BTDF_EINVAL, "padding must be in 0 .. 2^20 (planes: a multiple of 64)");
+      if (h->state_ok) return fail(BTDF_ESTATE, "layout options must be set before the first device use");
+      if (key == BTDF_OPT_ROW_PAD)
+        h->row_pad = (int)value;
+      else
+        h->plane_pad = (int)value;
+      h->layout_ok = false;
+      return ok();
     default: return fail(BTDF_EINVAL, "unknown or read-only option %d", key);
   }
 }
@@ -911,6 +1005,14 @@ int btdf_get_option(const btdf_t *h, int key, int64_t *value) {
     case BTDF_OPT_XCD_REMAP: *value = h->xcd_remap; return ok();
     case BTDF_OPT_TILE_X: variant_tile(h->variant, &tx, &ty); *value = tx; return ok();
     case BTDF_OPT_TILE_Y: variant_tile(h->variant, &tx, &ty); *value = ty; return ok();
+    case BTDF_OPT_ROW_PAD: *value = h->row_pad; return ok();
+    case BTDF_OPT_INTERIOR_PATH: *value = h->interior; return ok();
+    case BTDF_OPT_OVERLAP: *value = h->overlap; return ok();
+    case BTDF_OPT_FORCED_TILES:
+      if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
+      *value = h->n_forced;
+      return ok();
+    case BTDF_OPT_PLANE_PAD: *value = h->plane_pad; return ok();
     default: return fail(BTDF_EINVAL, "unknown option %d", key);
   }
 }

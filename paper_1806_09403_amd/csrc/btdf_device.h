@@ -71,42 +71,60 @@ struct LbmParams {
   // tiles of the lattice kernel
   int ntx, nty;
   int xcd_remap;
+  int interior;          // 1: waves away from every edge take the uniform-base path
   // marker lists per tile (spread gather)
   const int *tile_off;   // [ntx*nty + 1]
   const int *tile_list;  // marker ids, ascending within a tile
-  const double *X, *Y;   // marker positions
-  const double *Fx, *Fy; // direct force of this step
-  const double *sdrs;    // drs * ds of the marker's body
+  const void *mk_w;      // per marker, in the population type: wx[4], wy[4], drs ds F_x, drs ds F_y
+  const int *mk_ixy;     // per marker: stencil origin (wrapped in periodic directions)
   int kind;
   long long *step_ctr;   // steps completed on the device
   int *flag;             // instability flag: 0 fine, 1 + body, -1 node
 };
 
+// tiles handled by one launch of the lattice kernel
+struct TileRange {
+  const int *map;  // tile ids; null = identity over all tiles
+  int base, count; // launch covers map[base .. base+count)
+  int count_step;  // this launch advances the device step counter
+};
+
 struct IbParams {
-  int nb;
+  int nb, nm;
   const int *body_off;  // [nb + 1]
+  const int *mk_body;   // body of each marker
   const double *X, *Y, *U, *V;
   const double *cx, *cy;
   const double *body_sdrs;  // drs * ds per body
+  const double *sdrs;       // drs * ds per marker
   double *Fx, *Fy, *rho_l, *ux_l, *uy_l;
+  void *mk_w;               // spread weights and scaled forces for the lattice kernel
+  int *mk_ixy;
   double *hist;  // [cap][nb][3]
   int hist_cap;
+  int *slot;     // ring entry of the current step (written by the marker kernel)
 };
 
 // Streaming pull g_q(x, y) = f_q(x - e_q, y - e_q) with the boundary readings:
 // periodic directions wrap, halfway bounce-back walls in y return the
 // opposite population of the same node; channel ends read the ghost columns.
-template <typename T>
+template <typename T, bool NTL = false>
+__device__ __forceinline__ T load(const T *ptr) {
+  if (NTL) return __builtin_nontemporal_load(ptr);
+  return *ptr;
+}
+
+template <typename T, bool NTL = false>
 __device__ __forceinline__ T pull(const T *__restrict__ A, const LbmParams &p, int q, int x, int y) {
   int sx = x - ex(q);
   int sy = y - ey(q);
   if (p.yper) {
     sy = sy < 0 ? sy + p.ny : (sy >= p.ny ? sy - p.ny : sy);
   } else if (sy < 0 || sy >= p.ny) {
-    return A[(long long)opp(q) * p.plane + (long long)y * p.pitch + x];
+    return load<T, NTL>(&A[(long long)opp(q) * p.plane + (long long)y * p.pitch + x]);
   }
   if (p.xper) sx = sx < 0 ? sx + p.nx : (sx >= p.nx ? sx - p.nx : sx);
-  return A[(long long)q * p.plane + (long long)sy * p.pitch + sx];
+  return load<T, NTL>(&A[(long long)q * p.plane + (long long)sy * p.pitch + sx]);
 }
 
 // Consecutive tiles go to the same XCD: hardware dispatches block b to XCD

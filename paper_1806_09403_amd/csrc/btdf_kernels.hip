@@ -29,40 +29,63 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Marker kernel: 16 lanes per marker, one per node of the (up to) 4x4
+// stencil, 16 markers per workgroup, over all markers of all bodies. Each
+// lane pulls its node's populations and forms rho and u* there (eqs 9-10,
+// u* with G/2); the weighted sums of eqs 12/14 are reduced across the 16
+// lanes by shuffles and lane 0 of the group forms F_l (eq 20). Each marker's
+// delta weights, stencil origin and drs ds F_l are left for the lattice
+// kernel's spread gather. The per-body sums of eq 27 are formed by extra
+// workgroups of the lattice kernel, after this kernel has completed.
 template <typename T>
 __global__ __launch_bounds__(256) void ib_kernel(const T *__restrict__ A, LbmParams p, IbParams ib) {
-  __shared__ double red[3][4];
-  const int b = blockIdx.x;
-  const int l0 = ib.body_off[b], l1 = ib.body_off[b + 1];
-  const double cx = ib.cx[b], cy = ib.cy[b];
+  const int node = (int)threadIdx.x & 15;
+  const int l = (int)blockIdx.x * 16 + ((int)threadIdx.x >> 4);
+  const bool act = l < ib.nm;
   const int S = stencil_size(p.kind);
-  double sfx = 0.0, sfy = 0.0, stz = 0.0;
-  int bad = 0;
-  for (int l = l0 + (int)threadIdx.x; l < l1; l += blockDim.x) {
-    const double X = ib.X[l], Y = ib.Y[l];
-    const int bx = stencil_base(p.kind, X), by = stencil_base(p.kind, Y);
-    double wx[4], wy[4];
+  const int a = node & 3, c = node >> 2;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ib.slot[0] = (int)(p.step_ctr[0] % ib.hist_cap);
+
+  double wr = 0.0, wu = 0.0, wv = 0.0, X = 0.0, Y = 0.0;
+  int bx = 0, by = 0;
+  if (act) {
+    X = ib.X[l];
+    Y = ib.Y[l];
+    bx = stencil_base(p.kind, X);
+    by = stencil_base(p.kind, Y);
+  }
+  // lanes 0-3 of the group evaluate the x weights, lanes 4-7 the y weights
+  double ph = 0.0;
+  if (act && node < 8) {
+    const int k = node & 3;
+    if (k < S) ph = node < 4 ? phi(p.kind, (double)(bx + k) - X) : phi(p.kind, (double)(by + k) - Y);
+  }
+  const int gl = (int)threadIdx.x & ~15 & 63;  // first lane of the group within the wave
+  const double phx = __shfl(ph, gl + a, 64);
+  const double phy = __shfl(ph, gl + 4 + c, 64);
+  if (act) {
+    T *mw = reinterpret_cast<T *>(ib.mk_w) + 10 * (long long)l;
+    if (c == 0) mw[a] = (T)phx;
+    if (a == 0) mw[4 + c] = (T)phy;
+    if (a < S && c < S) {
+      const double W = phx * phy;
+      int i = bx + a, j = by + c;
+      if (p.xper) i = ((i % p.nx) + p.nx) % p.nx;
+      if (p.yper) j = ((j % p.ny) + p.ny) % p.ny;
+      double drho = 0.0, mx = 0.0, my = 0.0;
+      if (i >= 1 && i <= p.nx - 2 && j >= 1 && j <= p.ny - 2) {
+        // no wrap, no wall: one 32-bit offset, the shifts fold into the plane base
+        const unsigned off = ((unsigned)j * (unsigned)p.pitch + (unsigned)i) * (unsigned)sizeof(T);
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      wx[a] = a < S ? phi(p.kind, (double)(bx + a) - X) : 0.0;
-      wy[a] = a < S ? phi(p.kind, (double)(by + a) - Y) : 0.0;
-    }
-    // stencil origin inside the grid; in a periodic direction a node index
-    // past the end then needs one subtraction (S <= 4 < 8 <= nx, ny)
-    const int bxw = p.xper ? ((bx % p.nx) + p.nx) % p.nx : bx;
-    const int byw = p.yper ? ((by % p.ny) + p.ny) % p.ny : by;
-    double rl = 0.0, ul = 0.0, vl = 0.0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      if (c >= S) break;
-      int j = byw + c;
-      if (j >= p.ny) j -= p.ny;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        if (a >= S) break;
-        int i = bxw + a;
-        if (i >= p.nx) i -= p.nx;
-        double drho = 0.0, mx = 0.0, my = 0.0;
+        for (int q = 0; q < 9; ++q) {
+          const char *base = reinterpret_cast<const char *>(A + (long long)q * p.plane -
+                                                            (long long)ey(q) * p.pitch - ex(q));
+          const double g = (double)*reinterpret_cast<const T *>(base + off);
+          drho += g;
+          mx += ex(q) * g;
+          my += ey(q) * g;
+        }
+      } else {
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
           const double g = (double)pull(A, p, q, i, j);
@@ -70,47 +93,71 @@ __global__ __launch_bounds__(256) void ib_kernel(const T *__restrict__ A, LbmPar
           mx += ex(q) * g;
           my += ey(q) * g;
         }
-        const double rho = 1.0 + drho;
-        const double W = wx[a] * wy[c];
-        rl += W * rho;
-        ul += W * ((mx + 0.5 * p.Gx) / rho);
-        vl += W * ((my + 0.5 * p.Gy) / rho);
       }
+      const double rho = 1.0 + drho;
+      const double inv = 1.0 / rho;
+      wr = W * rho;
+      wu = W * ((mx + 0.5 * p.Gx) * inv);
+      wv = W * ((my + 0.5 * p.Gy) * inv);
     }
-    const double Fx = 2.0 * rl * (ib.U[l] - ul);
-    const double Fy = 2.0 * rl * (ib.V[l] - vl);
+  }
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) {
+    wr += __shfl_xor(wr, off, 16);
+    wu += __shfl_xor(wu, off, 16);
+    wv += __shfl_xor(wv, off, 16);
+  }
+  if (act && node == 0) {
+    const double Fx = 2.0 * wr * (ib.U[l] - wu);
+    const double Fy = 2.0 * wr * (ib.V[l] - wv);
     ib.Fx[l] = Fx;
     ib.Fy[l] = Fy;
-    ib.rho_l[l] = rl;
-    ib.ux_l[l] = ul;
-    ib.uy_l[l] = vl;
-    if (!isfinite(Fx) || !isfinite(Fy) || !(sqrt(ul * ul + vl * vl) <= 0.3)) bad = 1;
+    ib.rho_l[l] = wr;
+    ib.ux_l[l] = wu;
+    ib.uy_l[l] = wv;
+    const double sd = ib.sdrs[l];
+    T *mw = reinterpret_cast<T *>(ib.mk_w) + 10 * (long long)l;
+    mw[8] = (T)(Fx * sd);
+    mw[9] = (T)(Fy * sd);
+    ib.mk_ixy[2 * l] = p.xper ? ((bx % p.nx) + p.nx) % p.nx : bx;
+    ib.mk_ixy[2 * l + 1] = p.yper ? ((by % p.ny) + p.ny) % p.ny : by;
+    if (!isfinite(Fx) || !isfinite(Fy) || !(sqrt(wu * wu + wv * wv) <= 0.3)) p.flag[0] = 1 + ib.mk_body[l];
+  }
+}
+
+// Hydrodynamic force and torque on body b (eq 27 with the body's sign): a
+// workgroup of NT lanes sums its markers' F_l in a fixed order and writes
+// the history ring entry of the step.
+template <int NT>
+__device__ void body_reduce(const IbParams &ib, int b, int tid, double (*red)[NT / 64]) {
+  const int l0 = ib.body_off[b], l1 = ib.body_off[b + 1];
+  const double cx = ib.cx[b], cy = ib.cy[b];
+  double sfx = 0.0, sfy = 0.0, stz = 0.0;
+  for (int l = l0 + tid; l < l1; l += NT) {
+    const double Fx = ib.Fx[l], Fy = ib.Fy[l];
     sfx += Fx;
     sfy += Fy;
-    stz += (X - cx) * Fy - (Y - cy) * Fx;
+    stz += (ib.X[l] - cx) * Fy - (ib.Y[l] - cy) * Fx;
   }
-  if (bad) p.flag[0] = 1 + b;
   sfx = wave_sum(sfx);
   sfy = wave_sum(sfy);
   stz = wave_sum(stz);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = tid & 63, w = tid >> 6;
   if (lane == 0) {
     red[0][w] = sfx;
     red[1][w] = sfy;
     red[2][w] = stz;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
+  if (tid == 0) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int k = 0; k < nw; ++k) {
+    for (int k = 0; k < NT / 64; ++k) {
       s0 += red[0][k];
       s1 += red[1][k];
       s2 += red[2][k];
     }
     const double s = ib.body_sdrs[b];
-    const long long slot = p.step_ctr[0] % ib.hist_cap;
-    double *h = ib.hist + (slot * ib.nb + b) * 3;
+    double *h = ib.hist + ((long long)ib.slot[0] * ib.nb + b) * 3;
     h[0] = -s * s0;
     h[1] = -s * s1;
     h[2] = -s * s2;
@@ -120,63 +167,111 @@ __global__ __launch_bounds__(256) void ib_kernel(const T *__restrict__ A, LbmPar
 // ------------------------------------------------------------------ lattice kernel
 constexpr int kChunk = 64;  // markers staged in LDS per pass
 
-template <typename T, int BX, int BY, int NPT, bool NT>
+template <typename T>
+__device__ __forceinline__ T recip(T x);
+template <>
+__device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
+
+// Corrected velocity (eq 11), equilibrium (eq 6), Guo term (eq 7) and BGK
+// relaxation (eq 5) on the streamed deviations g~_q of one node:
+//   out_q = (1 - omega) g~_q + omega feq~_q + F_q.
+// Opposite directions share the even part of omega feq~ + F and differ in
+// the sign of the odd part, so each pair (q, opp q) is formed together:
+//   even = w (C + eu (4.5 omega rho eu + 9 guo ef)),  odd = 3 w (omega rho eu + guo ef),
+//   C = omega drho - 1.5 omega rho |u|^2 - 3 guo u.f,  eu = e_q.u,  ef = e_q.f.
+template <typename T>
+__device__ __forceinline__ void collide(const T g[9], T ftx, T fty, T omega, T guo, T out[9], T &rho) {
+  T drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+  rho = (T)1 + drho;
+  const T mx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
+  const T my = (g[2] - g[4]) + (g[5] - g[8]) + (g[6] - g[7]);
+  const T inv = recip<T>(rho);
+  const T ux = (mx + (T)0.5 * ftx) * inv;
+  const T uy = (my + (T)0.5 * fty) * inv;
+  const T orho = omega * rho;
+  const T C = omega * drho - (T)1.5 * orho * (ux * ux + uy * uy) - (T)3 * guo * (ux * ftx + uy * fty);
+  const T K1 = (T)4.5 * orho, K2 = (T)9 * guo;
+  const T omc = (T)1 - omega;
+  out[0] = omc * g[0] + (T)(4.0 / 9.0) * C;
+  auto pair = [&](int qp, int qm, T eu, T ef, T w) {
+    const T even = w * (C + eu * (K1 * eu + K2 * ef));
+    const T odd = (T)3 * w * (orho * eu + guo * ef);
+    out[qp] = omc * g[qp] + even + odd;
+    out[qm] = omc * g[qm] + even - odd;
+  };
+  pair(1, 3, ux, ftx, (T)(1.0 / 9.0));
+  pair(2, 4, uy, fty, (T)(1.0 / 9.0));
+  pair(5, 7, ux + uy, ftx + fty, (T)(1.0 / 36.0));
+  pair(6, 8, uy - ux, fty - ftx, (T)(1.0 / 36.0));
+}
+
+template <typename T, bool NT>
+__device__ __forceinline__ void store(T *ptr, T v) {
+  if (NT)
+    __builtin_nontemporal_store(v, ptr);
+  else
+    *ptr = v;
+}
+
+template <typename T, int BX, int BY, int NPT, bool NT, bool NTL>
 __global__ __launch_bounds__(BX *BY) void lbm_kernel(const T *__restrict__ A, T *__restrict__ B,
-                                                     LbmParams p) {
+                                                     LbmParams p, TileRange r, IbParams ib) {
   constexpr int TX = BX * NPT;
   __shared__ int s_ix[kChunk], s_iy[kChunk];
-  __shared__ double s_wx[kChunk][4], s_wy[kChunk][4], s_fx[kChunk], s_fy[kChunk];
+  __shared__ T s_w[kChunk][10];  // wx[4], wy[4], drs ds F_x, drs ds F_y
 
-  const int nblk = p.ntx * p.nty;
-  const int t = p.xcd_remap ? xcd_tile((int)blockIdx.x, nblk) : (int)blockIdx.x;
+  if ((int)blockIdx.x >= r.count) {  // workgroups past the tiles: one body each
+    __shared__ double red[3][BX * BY / 64];
+    body_reduce<BX * BY>(ib, (int)blockIdx.x - r.count, (int)threadIdx.y * BX + (int)threadIdx.x, red);
+    return;
+  }
+
+  // this launch covers tiles map[base .. base+count) (all tiles in order if map is null)
+  const int li = p.xcd_remap ? xcd_tile((int)blockIdx.x, r.count) : (int)blockIdx.x;
+  const int t = r.map ? r.map[r.base + li] : li;
   const int tyi = t / p.ntx;
   const int txi = t - tyi * p.ntx;
   const int y = tyi * BY + (int)threadIdx.y;
   const int xb = txi * TX + (int)threadIdx.x;
 
-  double fib_x[NPT], fib_y[NPT];
+  T fib_x[NPT], fib_y[NPT];
 #pragma unroll
-  for (int k = 0; k < NPT; ++k) fib_x[k] = fib_y[k] = 0.0;
+  for (int k = 0; k < NPT; ++k) fib_x[k] = fib_y[k] = (T)0;
 
-  // spread (eqs 13, 15) as a gather over the markers listed for this tile
+  // spread (eqs 13, 15) as a gather over the markers listed for this tile;
+  // the marker kernel left each marker's weights and drs ds F_l
   const int m0 = p.tile_off[t], m1 = p.tile_off[t + 1];
-  if (m1 > m0) {
+  const bool forced = m1 > m0;
+  if (forced) {
     const int S = stencil_size(p.kind);
     const int tid = (int)threadIdx.y * BX + (int)threadIdx.x;
+    const T *mw = reinterpret_cast<const T *>(p.mk_w);
     for (int c0 = m0; c0 < m1; c0 += kChunk) {
       const int cnt = min(kChunk, m1 - c0);
       __syncthreads();
       if (tid < cnt) {
         const int l = p.tile_list[c0 + tid];
-        const double X = p.X[l], Y = p.Y[l];
-        int bx = stencil_base(p.kind, X), by = stencil_base(p.kind, Y);
+        s_ix[tid] = p.mk_ixy[2 * l];
+        s_iy[tid] = p.mk_ixy[2 * l + 1];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          s_wx[tid][a] = a < S ? phi(p.kind, (double)(bx + a) - X) : 0.0;
-          s_wy[tid][a] = a < S ? phi(p.kind, (double)(by + a) - Y) : 0.0;
-        }
-        if (p.xper) bx = ((bx % p.nx) + p.nx) % p.nx;
-        if (p.yper) by = ((by % p.ny) + p.ny) % p.ny;
-        s_ix[tid] = bx;
-        s_iy[tid] = by;
-        const double s = p.sdrs[l];
-        s_fx[tid] = p.Fx[l] * s;
-        s_fy[tid] = p.Fy[l] * s;
+        for (int k = 0; k < 10; ++k) s_w[tid][k] = mw[10 * (long long)l + k];
       }
       __syncthreads();
       for (int e = 0; e < cnt; ++e) {
         int dy = y - s_iy[e];
         if (p.yper && dy < 0) dy += p.ny;
         if ((unsigned)dy < (unsigned)S) {
-          const double wyv = s_wy[e][dy];
+          const T wyv = s_w[e][4 + dy];
 #pragma unroll
           for (int k = 0; k < NPT; ++k) {
             int dx = xb + k * BX - s_ix[e];
             if (p.xper && dx < 0) dx += p.nx;
             if ((unsigned)dx < (unsigned)S) {
-              const double W = s_wx[e][dx] * wyv;
-              fib_x[k] += W * s_fx[e];
-              fib_y[k] += W * s_fy[e];
+              const T W = s_w[e][dx] * wyv;
+              fib_x[k] += W * s_w[e][8];
+              fib_y[k] += W * s_w[e][9];
             }
           }
         }
@@ -185,45 +280,55 @@ __global__ __launch_bounds__(BX *BY) void lbm_kernel(const T *__restrict__ A, T 
   }
   if (y >= p.ny) return;
 
+  // A wave whose nodes and their neighbours need no wrap and no wall takes
+  // the interior path: every pull is one load from a wave-uniform base plus
+  // the lane's byte offset. A wave spans WR rows of the tile (1 if BX >= 64).
+  constexpr int WR = BX >= 64 ? 1 : 64 / BX;
+  constexpr int WX = BX >= 64 ? 64 : BX;
+  const int yw = __builtin_amdgcn_readfirstlane(y - (BX >= 64 ? 0 : ((int)threadIdx.y % WR)));
+  const int xw = __builtin_amdgcn_readfirstlane(BX >= 64 ? txi * TX + ((int)threadIdx.x & ~63) : txi * TX);
+  const bool interior = p.interior && yw >= 1 && yw + WR <= p.ny - 1 && xw >= 1 &&
+                        xw + WX + (NPT - 1) * BX <= p.nx - 1;
+  const unsigned rowoff = (unsigned)(y - yw) * (unsigned)p.pitch;
+
   const T omega = (T)p.omega, guo = (T)p.guo;
+  const T Gx = (T)p.Gx, Gy = (T)p.Gy;
   bool bad = false;
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int x = xb + k * BX;
-    if (x < p.i0 || x > p.i1) continue;
+    if (!interior && (x < p.i0 || x > p.i1)) continue;
     T g[9];
+    // byte offset of the node from the wave's first row: one 32-bit register
+    // shared by all loads and stores of the interior path
+    const unsigned xoff = (rowoff + (unsigned)x) * (unsigned)sizeof(T);
+    if (interior) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) g[q] = pull(A, p, q, x, y);
-    T drho = g[0];
+      for (int q = 0; q < 9; ++q) {
+        const char *base = reinterpret_cast<const char *>(A + (long long)q * p.plane +
+                                                          (long long)(yw - ey(q)) * p.pitch - ex(q));
+        g[q] = load<T, NTL>(reinterpret_cast<const T *>(base + xoff));
+      }
+    } else {
 #pragma unroll
-    for (int q = 1; q < 9; ++q) drho += g[q];
-    const T rho = (T)1 + drho;
-    const T mx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
-    const T my = (g[2] - g[4]) + (g[5] - g[8]) + (g[6] - g[7]);
-    const T ftx = (T)(p.Gx + fib_x[k]);
-    const T fty = (T)(p.Gy + fib_y[k]);
-    const T inv = (T)1 / rho;
-    const T ux = (mx + (T)0.5 * ftx) * inv;
-    const T uy = (my + (T)0.5 * fty) * inv;
-    const T uu = ux * ux + uy * uy;
-    bad |= !(rho > (T)0) || !isfinite(rho);
-    const long long base = (long long)y * p.pitch + x;
-    T out[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      const T w = (T)wq(q);
-      const T eu = (T)ex(q) * ux + (T)ey(q) * uy;
-      const T P = (T)3 * eu + (T)4.5 * eu * eu - (T)1.5 * uu;
-      const T feq = w * (drho + rho * P);  // deviation of eq 6 from w_q
-      const T Fq = guo * w *
-                   (((T)3 * ((T)ex(q) - ux) + (T)9 * eu * (T)ex(q)) * ftx +
-                    ((T)3 * ((T)ey(q) - uy) + (T)9 * eu * (T)ey(q)) * fty);
-      out[q] = g[q] - omega * (g[q] - feq) + Fq;
-      if (NT)
-        __builtin_nontemporal_store(out[q], &B[(long long)q * p.plane + base]);
-      else
-        B[(long long)q * p.plane + base] = out[q];
+      for (int q = 0; q < 9; ++q) g[q] = pull<T, NTL>(A, p, q, x, y);
     }
+    const T ftx = forced ? (T)(p.Gx + (double)fib_x[k]) : Gx;
+    const T fty = forced ? (T)(p.Gy + (double)fib_y[k]) : Gy;
+    T out[9], rho;
+    collide<T>(g, ftx, fty, omega, guo, out, rho);
+    bad |= !(rho > (T)0) || !isfinite(rho);
+    if (interior) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        char *base = reinterpret_cast<char *>(B + (long long)q * p.plane + (long long)yw * p.pitch);
+        store<T, NT>(reinterpret_cast<T *>(base + xoff), out[q]);
+      }
+      continue;
+    }
+    const long long base = (long long)y * p.pitch + x;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) store<T, NT>(&B[(long long)q * p.plane + base], out[q]);
     if (p.inlet && x == 1) {
       // inlet ghost: equilibrium at the inflow velocity, density of column 1
       T dr = out[0];
@@ -246,7 +351,7 @@ __global__ __launch_bounds__(BX *BY) void lbm_kernel(const T *__restrict__ A, T 
     }
   }
   if (bad) p.flag[0] = -1;
-  if (t == 0 && threadIdx.x == 0 && threadIdx.y == 0) p.step_ctr[0] = p.step_ctr[0] + 1;
+  if (r.count_step && li == 0 && threadIdx.x == 0 && threadIdx.y == 0) p.step_ctr[0] = p.step_ctr[0] + 1;
 }
 
 // ------------------------------------------------------------------ state kernels
@@ -342,34 +447,47 @@ static int grid_for(const LbmParams &p) {
   return (int)(b < 65536 ? b : 65536);
 }
 
-template <typename T, int BX, int BY, int NPT, bool NT>
-static hipError_t launch_lbm_t(const T *A, T *B, const LbmParams &p, hipStream_t s) {
-  const int nblk = p.ntx * p.nty;
-  hipLaunchKernelGGL((lbm_kernel<T, BX, BY, NPT, NT>), dim3(nblk), dim3(BX, BY), 0, s, A, B, p);
+template <typename T, int BX, int BY, int NPT, bool NT, bool NTL>
+static hipError_t launch_lbm_t(const T *A, T *B, const LbmParams &p, const TileRange &r, const IbParams &ib,
+                               hipStream_t s) {
+  const int bodies = r.count_step ? ib.nb : 0;  // the counting launch also reduces the bodies
+  if (r.count + bodies <= 0) return hipSuccess;
+  hipLaunchKernelGGL((lbm_kernel<T, BX, BY, NPT, NT, NTL>), dim3(r.count + bodies), dim3(BX, BY), 0, s, A, B, p,
+                     r, ib);
   return hipGetLastError();
 }
 
-// launch shapes: {BX, BY, NPT, nontemporal}
-#define BTDF_VARIANTS(X) \
-  X(0, 64, 4, 1, false)  \
-  X(1, 256, 1, 1, false) \
-  X(2, 64, 4, 2, false)  \
-  X(3, 128, 2, 2, false) \
-  X(4, 256, 1, 2, false) \
-  X(5, 64, 4, 1, true)   \
-  X(6, 256, 1, 1, true)  \
-  X(7, 64, 4, 2, true)   \
-  X(8, 128, 2, 2, true)  \
-  X(9, 256, 1, 2, true)
+// launch shapes: {id, BX, BY, nodes per thread, nontemporal stores, nontemporal loads}
+#define BTDF_VARIANTS(X)         \
+  X(0, 64, 4, 1, true, false)    \
+  X(1, 64, 4, 1, false, false)   \
+  X(2, 256, 1, 1, true, false)   \
+  X(3, 64, 4, 2, true, false)    \
+  X(4, 128, 2, 2, true, false)   \
+  X(5, 256, 1, 2, true, false)   \
+  X(6, 32, 8, 1, true, false)    \
+  X(7, 64, 8, 1, true, false)    \
+  X(8, 128, 4, 1, true, false)   \
+  X(9, 64, 2, 1, true, false)    \
+  X(10, 128, 1, 1, true, false)  \
+  X(11, 64, 4, 1, true, true)    \
+  X(12, 64, 16, 1, true, false)  \
+  X(13, 32, 4, 1, true, false)   \
+  X(14, 32, 16, 1, true, false)  \
+  X(15, 32, 8, 2, true, false)   \
+  X(16, 16, 16, 1, true, false)  \
+  X(17, 32, 8, 1, true, true)    \
+  X(18, 16, 8, 1, true, false)   \
+  X(19, 32, 2, 1, true, false)
 
-int num_variants() { return 10; }
+int num_variants() { return 20; }
 
 void variant_tile(int v, int *tx, int *ty) {
-#define X(id, bx, by, npt, nt) \
-  if (v == id) {               \
-    *tx = bx * npt;            \
-    *ty = by;                  \
-    return;                    \
+#define X(id, bx, by, npt, nt, ntl) \
+  if (v == id) {                    \
+    *tx = bx * npt;                 \
+    *ty = by;                       \
+    return;                         \
   }
   BTDF_VARIANTS(X)
 #undef X
@@ -378,26 +496,28 @@ void variant_tile(int v, int *tx, int *ty) {
 }
 
 template <typename T>
-static hipError_t launch_lbm_any(int v, const T *A, T *B, const LbmParams &p, hipStream_t s) {
-#define X(id, bx, by, npt, nt) \
-  if (v == id) return launch_lbm_t<T, bx, by, npt, nt>(A, B, p, s);
+static hipError_t launch_lbm_any(int v, const T *A, T *B, const LbmParams &p, const TileRange &r,
+                                 const IbParams &ib, hipStream_t s) {
+#define X(id, bx, by, npt, nt, ntl) \
+  if (v == id) return launch_lbm_t<T, bx, by, npt, nt, ntl>(A, B, p, r, ib, s);
   BTDF_VARIANTS(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_lbm(int prec, int v, const void *A, void *B, const LbmParams &p, hipStream_t s) {
-  if (prec == 4) return launch_lbm_any<float>(v, (const float *)A, (float *)B, p, s);
-  return launch_lbm_any<double>(v, (const double *)A, (double *)B, p, s);
+hipError_t launch_lbm(int prec, int v, const void *A, void *B, const LbmParams &p, const TileRange &r,
+                      const IbParams &ib, hipStream_t s) {
+  if (prec == 4) return launch_lbm_any<float>(v, (const float *)A, (float *)B, p, r, ib, s);
+  return launch_lbm_any<double>(v, (const double *)A, (double *)B, p, r, ib, s);
 }
 
-hipError_t launch_ib(int prec, const void *A, const LbmParams &p, const IbParams &ib, int threads,
-                     hipStream_t s) {
-  if (ib.nb == 0) return hipSuccess;
+hipError_t launch_ib(int prec, const void *A, const LbmParams &p, const IbParams &ib, hipStream_t s) {
+  if (ib.nm == 0) return hipSuccess;
+  const int blocks = (ib.nm + 15) / 16;
   if (prec == 4)
-    hipLaunchKernelGGL(ib_kernel<float>, dim3(ib.nb), dim3(threads), 0, s, (const float *)A, p, ib);
+    hipLaunchKernelGGL(ib_kernel<float>, dim3(blocks), dim3(256), 0, s, (const float *)A, p, ib);
   else
-    hipLaunchKernelGGL(ib_kernel<double>, dim3(ib.nb), dim3(threads), 0, s, (const double *)A, p, ib);
+    hipLaunchKernelGGL(ib_kernel<double>, dim3(blocks), dim3(256), 0, s, (const double *)A, p, ib);
   return hipGetLastError();
 }
 

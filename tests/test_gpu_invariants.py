@@ -56,7 +56,12 @@ def test_uniform_flow_with_comoving_markers(precision):
     md = g.marker_data()
     tol = 1e-15 if precision == 8 else 1e-8
     assert np.max(np.abs(md["Fx"])) < tol and np.max(np.abs(md["Fy"])) < tol
-    assert np.max(np.abs(g.populations() - f0)) < (1e-15 if precision == 8 else 1e-8)
+    f = g.populations()
+    # FP64 keeps the uniform state exactly; in FP32 the 1-ulp hardware
+    # reciprocal leaves a few ulps of the populations (ulp(0.44) = 3e-8)
+    spread = np.max(np.abs(f - f.reshape(9, -1).mean(axis=1)[:, None, None]))
+    assert spread < (1e-15 if precision == 8 else 1.5e-7)
+    assert np.max(np.abs(f - f0)) < (1e-15 if precision == 8 else 3e-7)
 
 
 @pytest.mark.parametrize("precision,tol", [(8, 1e-9), (4, 2e-3)])

@@ -54,12 +54,15 @@ CASES = [
 @pytest.mark.parametrize("seed,nx,ny,kind,bc", CASES)
 def test_fp64_steps_match_oracle(seed, nx, ny, kind, bc):
     log("fp64 parity seed=%d %dx%d kind=%d bc=%s" % (seed, nx, ny, kind, bc))
-    c = W.random_case(seed, nx=nx, ny=ny, kind=kind, bc=bc, n_bodies=3 if ny > 20 else 1)
+    thin = ny < 20
+    c = W.random_case(seed, nx=nx, ny=ny, kind=kind, bc=bc, n_bodies=1 if thin else 3,
+                      D_range=(2.0, 3.0) if thin else (4.0, 9.0))
     o, g = oracle_of(c), gpu_of(c, precision=8)
     assert np.max(np.abs(g.populations() - o.populations())) < 1e-15
     for step in range(6):
         o.step(1)
         g.step(1)
+        assert o.unstable == 0, step
         fo, fg = o.populations(), g.populations()
         assert np.max(np.abs(fg - fo)) < 1e-14, step
         mo, mg = o.marker_data(), g.marker_data()
@@ -140,23 +143,30 @@ def test_every_launch_shape_is_bit_identical():
     g0 = gpu_of(c, precision=4)
     nv = g0.get_option(_lib.OPT_NUM_VARIANTS)
     for v in range(nv):
-        for remap in (0, 1):
+        for remap, interior, overlap in ((0, 1, 1), (1, 1, 1), (1, 0, 1), (1, 1, 0)):
             g = gpu_of(c, precision=4)
             g.set_option(_lib.OPT_LBM_VARIANT, v)
             g.set_option(_lib.OPT_XCD_REMAP, remap)
+            g.set_option(_lib.OPT_INTERIOR_PATH, interior)
+            g.set_option(_lib.OPT_OVERLAP, overlap)
+            assert 0 < g.get_option(_lib.OPT_FORCED_TILES)
             g.step(9)
             f = g.populations()
+            hist = g.force_history(20)
+            assert hist.shape[0] == 9
             if ref is None:
-                ref = f
-            assert np.array_equal(f, ref), (v, remap)
+                ref, ref_hist = f, hist
+            assert np.array_equal(f, ref), (v, remap, interior, overlap)
+            assert np.array_equal(hist, ref_hist), (v, remap, interior, overlap)
 
 
 def test_graph_replay_is_bit_identical():
     from paper_1806_09403_amd import _lib
     c = W.random_case(9, nx=120, ny=64, n_bodies=2)
     a = gpu_of(c, precision=8)
+    a.set_option(_lib.OPT_OVERLAP, 0)
     b = gpu_of(c, precision=8)
-    b.set_option(_lib.OPT_GRAPH_CHUNK, 6)
+    b.set_option(_lib.OPT_GRAPH_CHUNK, 6)     # graph of the overlapped step
     for n in (1, 13, 6, 5, 20):      # odd counts realign, several replays per call
         a.step(n)
         b.step(n)
