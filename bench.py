@@ -9,8 +9,10 @@ are synthetic and seeded; everything is resident in HBM before timing.
 
 Prints one JSON line: MLUPS (whole job), ms per step, the roofline of the
 lattice kernel (72 algorithmic bytes per lattice update against 8 TB/s,
-timed with HIP events on the library's stream over the timed region), and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+timed with HIP events on the library's stream over the timed region), the
+batched mode on 256 uneven channel cases beside the same cases run one
+after another, and the FP64 CPU oracle timed on a bounded sample of the
+same workload.
 """
 import argparse
 import json
@@ -41,6 +43,11 @@ def parse():
     p.add_argument("--copy-probe-mb", type=int, default=0,
                    help="before timing, copy a tensor of this size once (counter calibration)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-batched", action="store_true", help="skip the batched-mode figures")
+    p.add_argument("--batched-steps", type=int, default=5000)
+    p.add_argument("--batched-graph-chunk", type=int, default=50)
+    p.add_argument("--seq-steps", type=int, default=200,
+                   help="steps per case when timing the sequential single-case runs")
     p.add_argument("--cpu-budget-s", type=float, default=20.0)
     return p.parse_args()
 
@@ -79,6 +86,61 @@ def cpu_baseline(case, budget_s):
     return {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "%s: %d FP64 oracle steps of the full %dx%d lattice with all %d bodies (%.1f s)"
                       % (case.name, steps, case.nx, case.ny, len(case.bodies), t2 - t0)}
+
+
+def bench_batched(args):
+    """The 256 uneven channel cases: one batch (autotuned launch shape, graph
+    replay) against the same cases run one after another as single cases
+    (graph replay too). Cases that trip the instability guard in the batched
+    run are left out of both sums (their work before stopping is not counted)."""
+    import torch
+    import btdf_workloads as W
+    from paper_1806_09403_amd import BatchSim, Sim, _lib
+
+    cases = W.c4()
+    t_setup = time.perf_counter()
+    b = BatchSim(cases, precision=4)
+    best = b.autotune(steps_per_trial=5)
+    b.set_option(_lib.OPT_GRAPH_CHUNK, args.batched_graph_chunk)
+    b.step(100)
+    torch.cuda.synchronize()
+    print("batched setup + tune + warmup %.1f s" % (time.perf_counter() - t_setup), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    b.step(args.batched_steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    unstable, _ = b.status()
+    ms_ib, ms_lbm = b.step_timed(200)
+    b.close()
+    del b
+    stable = [k for k in range(len(cases)) if not unstable[k]]
+    nodes = sum(cases[k].nodes for k in stable)
+    mlups = nodes * args.batched_steps / wall / 1e6
+    achieved = nodes * 72 / (ms_lbm * 1e-3) / 1e9
+    print("batched: %d of %d cases stable, %.1f MLUPS" % (len(stable), len(cases), mlups), file=sys.stderr, flush=True)
+
+    t_seq = 0.0
+    for k in stable:
+        s = Sim.from_case(cases[k], precision=4)
+        s.set_option(_lib.OPT_GRAPH_CHUNK, args.batched_graph_chunk)
+        s.step(args.batched_graph_chunk)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(args.seq_steps)
+        torch.cuda.synchronize()
+        t_seq += (time.perf_counter() - t0) / args.seq_steps
+        s.close()
+    seq_mlups = nodes / t_seq / 1e6
+    print("sequential: %.1f MLUPS" % seq_mlups, file=sys.stderr, flush=True)
+    return {"workload": "256 uneven single-cylinder channels (W 128..1024, H = W/2, D 8..48, Re 0.1..200), FP32",
+            "cases": len(cases), "stable_cases": len(stable), "nodes": nodes, "steps": args.batched_steps,
+            "value": round(mlups, 2), "unit": "MLUPS", "ms_per_step": round(wall * 1e3 / args.batched_steps, 5),
+            "sequential_mlups": round(seq_mlups, 2), "speedup_vs_sequential": round(mlups / seq_mlups, 3),
+            "sequential_sample": "each stable case alone, %d graph-replayed steps" % args.seq_steps,
+            "lbm_variant": best, "graph_chunk": args.batched_graph_chunk,
+            "kernel_ms": {"ib_batch_kernel": round(ms_ib, 5), "lbm_batch_kernel": round(ms_lbm, 5)},
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": "lbm_batch_kernel"}}
 
 
 def main():
@@ -139,12 +201,16 @@ def main():
     mlups = n * args.steps / wall / 1e6
     bytes_per_update = 9 * 2 * prec
     achieved = n * bytes_per_update / (ms_lbm * 1e-3) / 1e9
+    # measured HBM bytes per launch (profiles/traffic.json, counter runs of this
+    # exact configuration) over the same live duration: GB/s like `achieved`
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
-        key = "%s-%s-v%d" % (args.workload, args.delta, sim.get_option(_lib.OPT_LBM_VARIANT))
-        traffic = t.get(key)
+        key = "%s-%s-v%d-i%d-o%d" % (args.workload, args.delta, sim.get_option(_lib.OPT_LBM_VARIANT),
+                                     sim.get_option(_lib.OPT_INTERIOR_PATH), sim.get_option(_lib.OPT_OVERLAP))
+        if key in t:
+            traffic = round(t[key]["bytes_per_launch"] / (ms_lbm * 1e-3) / 1e9, 1)
     nb, nm, _ = sim.counts()
     line = {
         "metric": "MLUPS (D2Q9+BTDF-IB)",
@@ -174,6 +240,9 @@ def main():
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    if not args.no_batched:
+        line["batched"] = bench_batched(args)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_budget_s)
     print(json.dumps(line), flush=True)

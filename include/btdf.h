@@ -83,6 +83,7 @@ extern "C" {
 #define BTDF_OPT_INTERIOR_PATH 9 /* 1: waves away from every edge load from wave-uniform bases; 0 (default): always the general pull */
 #define BTDF_OPT_OVERLAP 10      /* 1: marker kernel on a second stream beside the lattice tiles it does not touch; 0 (default): in order */
 #define BTDF_OPT_FORCED_TILES 11 /* read-only: lattice tiles touched by some marker's stencil */
+#define BTDF_OPT_MASK_UNSTABLE 12 /* batches only: 1 (default) = a case that went unstable stops, the others go on */
 
 typedef struct btdf_grid {
   int32_t nx, ny;               /* nodes, ghost columns included; each >= 8 */
@@ -216,6 +217,55 @@ int btdf_counts(const btdf_t *h, int *n_bodies, int *n_markers, int64_t *n_steps
  * ESTATE for a layout option once the populations exist on the device. */
 int btdf_set_option(btdf_t *h, int key, int64_t value);
 int btdf_get_option(const btdf_t *h, int key, int64_t *value);
+
+/* Autotuner: run steps_per_trial steps in every launch shape of the lattice
+ * kernel (BTDF_OPT_LBM_VARIANT x BTDF_OPT_INTERIOR_PATH), timed with HIP
+ * events, and keep the fastest. The trials advance the simulation by
+ * 2 x NUM_VARIANTS x steps_per_trial steps (all launch shapes give
+ * bit-identical results, so the trajectory is the one plain stepping gives). *best_variant (may be NULL) receives
+ * the chosen variant. Synchronising. */
+int btdf_autotune(btdf_t *h, int64_t steps_per_trial, int *best_variant);
+
+/* ---- batches: many independent cases stepped together ----
+ * A batch holds n_cases independent simulations (grids[c], taus[c],
+ * delta_kinds[c], thickenings[c], as for btdf_create; one precision for all;
+ * the stream of grids[0]). A batch step runs the marker kernel over the
+ * markers of every case and the lattice kernel over the tiles of every case,
+ * one launch each, so small cases fill the GPU together. Each case is an
+ * ordinary handle (btdf_batch_case) for every state call (forces, history,
+ * populations, macroscopic fields, marker data, save/load, counts); stepping,
+ * binding, options and adding bodies go through the batch. With
+ * BTDF_OPT_MASK_UNSTABLE (default on) a case whose instability flag is set
+ * stops stepping and the others continue; btdf_batch_status reports which.
+ * A stopped case's populations are those of one of its last two steps (the
+ * ping-pong buffers no longer alternate) and its state calls return
+ * BTDF_EUNSTABLE; the other cases are bit-identical to running alone. */
+typedef struct btdf_batch btdf_batch_t;
+
+int btdf_batch_create(int n_cases, const btdf_grid *grids, const double *taus, const int *delta_kinds,
+                      const double *thickenings, btdf_batch_t **out);
+int btdf_batch_destroy(btdf_batch_t *b);
+/* The handle of case i (owned by the batch; valid until btdf_batch_destroy). */
+int btdf_batch_case(btdf_batch_t *b, int i, btdf_t **h);
+int btdf_batch_add_body(btdf_batch_t *b, int case_id, int n, const double *xy, const double *uv, double cx,
+                        double cy, double ds, int *body_id);
+/* Device bytes for all cases. Adding bodies changes it; a caller-owned
+ * workspace must then be replaced by a fresh one (ESTATE otherwise). */
+size_t btdf_batch_workspace_bytes(const btdf_batch_t *b);
+int btdf_batch_bind_workspace(btdf_batch_t *b, void *dev, size_t bytes);
+int btdf_batch_set_stream(btdf_batch_t *b, void *hip_stream);
+/* n steps of every case (asynchronous); graphs per BTDF_OPT_GRAPH_CHUNK. */
+int btdf_batch_step(btdf_batch_t *b, int64_t n);
+/* As btdf_step_timed: mean ms per step of the marker and lattice launches. */
+int btdf_batch_step_timed(btdf_batch_t *b, int64_t n, double *ms_ib, double *ms_lbm);
+/* unstable[c] = 1 if case c's instability flag is set (array of n_cases, may
+ * be NULL); *n_steps = batch steps taken. Synchronising. */
+int btdf_batch_status(btdf_batch_t *b, int *unstable, int64_t *n_steps);
+/* Options: BTDF_OPT_LBM_VARIANT, _GRAPH_CHUNK, _XCD_REMAP, _INTERIOR_PATH, _MASK_UNSTABLE. */
+int btdf_batch_set_option(btdf_batch_t *b, int key, int64_t value);
+int btdf_batch_get_option(const btdf_batch_t *b, int key, int64_t *value);
+/* As btdf_autotune, for the batched launches. */
+int btdf_batch_autotune(btdf_batch_t *b, int64_t steps_per_trial, int *best_variant);
 
 /* Boundary-thickness calibration on the host (no device), Section 2.3:
  * A_ij = (1/dh^2) sum_k phi_ik phi_kj dh ds (eq 22) over the stencil nodes

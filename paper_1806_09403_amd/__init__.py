@@ -7,7 +7,7 @@ wraps one simulation with torch-owned device memory and stream.
 """
 from ._lib import (BtdfError, BtdfUnstable, COS4, LINEAR2, PESKIN4, ROMA3, PERIODIC, VELOCITY_INLET,
                    ZERO_GRADIENT_OUTLET, BOUNCEBACK_WALL, load)
-from .sim import Sim
+from .sim import BatchSim, Sim
 
-__all__ = ["Sim", "BtdfError", "BtdfUnstable", "load", "COS4", "LINEAR2", "PESKIN4", "ROMA3",
+__all__ = ["Sim", "BatchSim", "BtdfError", "BtdfUnstable", "load", "COS4", "LINEAR2", "PESKIN4", "ROMA3",
            "PERIODIC", "VELOCITY_INLET", "ZERO_GRADIENT_OUTLET", "BOUNCEBACK_WALL"]

@@ -20,6 +20,7 @@ PERIODIC, VELOCITY_INLET, ZERO_GRADIENT_OUTLET, BOUNCEBACK_WALL = 0, 1, 2, 3
 LINEAR2, ROMA3, PESKIN4, COS4 = 2, 3, 4, 5
 OPT_LBM_VARIANT, OPT_NUM_VARIANTS, OPT_GRAPH_CHUNK, OPT_XCD_REMAP, OPT_TILE_X, OPT_TILE_Y = 1, 2, 3, 4, 5, 6
 OPT_ROW_PAD, OPT_PLANE_PAD, OPT_INTERIOR_PATH, OPT_OVERLAP, OPT_FORCED_TILES = 7, 8, 9, 10, 11
+OPT_MASK_UNSTABLE = 12
 
 _NAMES = {OK: "BTDF_OK", EINVAL: "BTDF_EINVAL", ENOMEM: "BTDF_ENOMEM", EDEVICE: "BTDF_EDEVICE",
           ESTATE: "BTDF_ESTATE", EUNSTABLE: "BTDF_EUNSTABLE"}
@@ -82,6 +83,22 @@ SIGNATURES = {
     "btdf_get_option": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_i64)]),
     "btdf_calibrate_thickening": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double,
                                                  _dp, _dp]),
+    "btdf_autotune": (ctypes.c_int, [_vp, _i64, ctypes.POINTER(ctypes.c_int)]),
+    "btdf_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(btdf_grid), _dp,
+                                         ctypes.POINTER(ctypes.c_int), _dp, ctypes.POINTER(_vp)]),
+    "btdf_batch_destroy": (ctypes.c_int, [_vp]),
+    "btdf_batch_case": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_vp)]),
+    "btdf_batch_add_body": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_int)]),
+    "btdf_batch_workspace_bytes": (ctypes.c_size_t, [_vp]),
+    "btdf_batch_bind_workspace": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    "btdf_batch_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "btdf_batch_step": (ctypes.c_int, [_vp, _i64]),
+    "btdf_batch_step_timed": (ctypes.c_int, [_vp, _i64, _dp, _dp]),
+    "btdf_batch_status": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64)]),
+    "btdf_batch_set_option": (ctypes.c_int, [_vp, ctypes.c_int, _i64]),
+    "btdf_batch_get_option": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_i64)]),
+    "btdf_batch_autotune": (ctypes.c_int, [_vp, _i64, ctypes.POINTER(ctypes.c_int)]),
 }
 
 _lib = None

@@ -160,3 +160,102 @@ def btdf_calibrate_thickening(delta_kind, xy, ds):
 
 def btdf_last_error():
     return _lib.last_error()
+
+
+def btdf_autotune(h, steps_per_trial):
+    v = ctypes.c_int(-1)
+    check(load().btdf_autotune(h, int(steps_per_trial), ctypes.byref(v)))
+    return v.value
+
+
+def _grid(nx, ny, bc, inflow, body_force, init, precision, history_capacity, stream):
+    return btdf_grid(nx=int(nx), ny=int(ny), bc_west=int(bc[0]), bc_east=int(bc[1]),
+                     bc_south=int(bc[2]), bc_north=int(bc[3]),
+                     inflow_ux=float(inflow[0]), inflow_uy=float(inflow[1]),
+                     body_force_x=float(body_force[0]), body_force_y=float(body_force[1]),
+                     rho0=float(init[0]), ux0=float(init[1]), uy0=float(init[2]),
+                     precision=int(precision), history_capacity=int(history_capacity),
+                     hip_stream=stream, flags=0)
+
+
+def btdf_batch_create(cases, stream=None):
+    """cases: list of dicts with the keyword arguments of btdf_create."""
+    n = len(cases)
+    grids = (btdf_grid * n)(*[_grid(c["nx"], c["ny"], c.get("bc", (0, 0, 0, 0)), c.get("inflow", (0.0, 0.0)),
+                                    c.get("body_force", (0.0, 0.0)), c.get("init", (1.0, 0.0, 0.0)),
+                                    c.get("precision", 8), c.get("history_capacity", 0), stream)
+                              for c in cases])
+    taus = np.array([c["tau"] for c in cases], dtype=np.float64)
+    kinds = (ctypes.c_int * n)(*[int(c["delta_kind"]) for c in cases])
+    th = np.array([c["thickening"] for c in cases], dtype=np.float64)
+    b = ctypes.c_void_p()
+    check(load().btdf_batch_create(n, grids, dptr(taus), kinds, dptr(th), ctypes.byref(b)))
+    return b.value
+
+
+def btdf_batch_destroy(b):
+    return check(load().btdf_batch_destroy(b))
+
+
+def btdf_batch_case(b, i):
+    h = ctypes.c_void_p()
+    check(load().btdf_batch_case(b, int(i), ctypes.byref(h)))
+    return h.value
+
+
+def btdf_batch_add_body(b, case_id, xy, uv=None, cx=0.0, cy=0.0, ds=0.0):
+    xy = f64(xy, (-1, 2))
+    n = xy.shape[0]
+    uvp = None
+    if uv is not None:
+        uv = f64(uv, (n, 2))
+        uvp = dptr(uv)
+    bid = ctypes.c_int(-1)
+    check(load().btdf_batch_add_body(b, int(case_id), n, dptr(xy), uvp, float(cx), float(cy), float(ds),
+                                     ctypes.byref(bid)))
+    return bid.value
+
+
+def btdf_batch_workspace_bytes(b):
+    return int(load().btdf_batch_workspace_bytes(b))
+
+
+def btdf_batch_bind_workspace(b, dev_ptr, nbytes):
+    return check(load().btdf_batch_bind_workspace(b, dev_ptr, int(nbytes)))
+
+
+def btdf_batch_set_stream(b, stream_ptr):
+    return check(load().btdf_batch_set_stream(b, stream_ptr))
+
+
+def btdf_batch_step(b, n):
+    return check(load().btdf_batch_step(b, int(n)))
+
+
+def btdf_batch_step_timed(b, n):
+    a, c = ctypes.c_double(), ctypes.c_double()
+    check(load().btdf_batch_step_timed(b, int(n), ctypes.byref(a), ctypes.byref(c)))
+    return a.value, c.value
+
+
+def btdf_batch_status(b, n_cases):
+    st = (ctypes.c_int * max(1, n_cases))()
+    ns = ctypes.c_int64()
+    check(load().btdf_batch_status(b, st, ctypes.byref(ns)))
+    return np.array(st[:n_cases], dtype=bool), ns.value
+
+
+def btdf_batch_set_option(b, key, value):
+    return check(load().btdf_batch_set_option(b, int(key), int(value)))
+
+
+def btdf_batch_get_option(b, key):
+    v = ctypes.c_int64()
+    check(load().btdf_batch_get_option(b, int(key), ctypes.byref(v)))
+    return v.value
+
+
+def btdf_batch_autotune(b, steps_per_trial):
+    v = ctypes.c_int(-1)
+    check(load().btdf_batch_autotune(b, int(steps_per_trial), ctypes.byref(v)))
+    return v.value

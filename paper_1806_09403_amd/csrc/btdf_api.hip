@@ -17,12 +17,12 @@
 #include <string>
 #include <vector>
 
-#include "btdf.h"
-#include "btdf_launch.h"
+#include "btdf_internal.h"
 
 using namespace btdf;
 
-namespace {
+namespace btdf {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -36,15 +36,6 @@ int fail(int code, const char *fmt, ...) {
   return code;
 }
 
-int ok() { return BTDF_OK; }
-
-#define HIPCHK(call)                                                                   \
-  do {                                                                                 \
-    hipError_t e_ = (call);                                                            \
-    if (e_ != hipSuccess) return fail(BTDF_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
-
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // host value of the delta functions (calibration and validation only)
 double phi_host(int kind, double r) {
@@ -65,67 +56,6 @@ double phi_host(int kind, double r) {
 
 bool valid_kind(int k) { return k == kLinear2 || k == kRoma3 || k == kPeskin4 || k == kCos4; }
 
-}  // namespace
-
-struct btdf_sim {
-  // configuration
-  int nx = 0, ny = 0;
-  int bc[4] = {0, 0, 0, 0};
-  int prec = 8;
-  int hist_cap = 4096;
-  int kind = kCos4;
-  double tau = 1.0, drs = 1.0;
-  double G[2] = {0, 0}, uin[2] = {0, 0};
-  double rho0 = 1.0, u0[2] = {0, 0};
-  hipStream_t stream = nullptr;
-  // bodies (host copies)
-  std::vector<double> X, Y, U, V, sdrs;
-  std::vector<int> off{0};
-  std::vector<double> cx, cy, bsdrs;
-  // lattice kernel launch shape and tiles
-  // launch defaults measured fastest on the 8192^2 particle-laden workload:
-  // 32x8 tiles, general pull, marker kernel before the lattice kernel
-  int variant = 6, xcd_remap = 1, graph_chunk = 0, interior = 0;
-  int row_pad = 0, plane_pad = 0;
-  int tile_x = 64, tile_y = 4, ntx = 0, nty = 0;
-  std::vector<int> tile_off, tile_list;
-  std::vector<int> tile_map;  // tiles no marker touches first, then the forced tiles
-  int n_free = 0, n_forced = 0;
-  int overlap = 0;            // run the marker kernel beside the lattice launch of the free tiles
-  // device memory
-  char *ws = nullptr;
-  size_t ws_bytes = 0;
-  bool ws_owned = false;
-  // layout
-  int pitch = 0;
-  long long plane = 0;
-  size_t off_pop[2] = {0, 0}, off_ctl = 0, grid_bytes = 0;
-  size_t off_hist = 0, off_mk = 0, off_mkw = 0, off_mkixy = 0, off_mkbody = 0, off_body = 0, off_boff = 0,
-         off_toff = 0, off_tlist = 0, off_tmap = 0, total = 0;
-  bool layout_ok = false;  // host layout current for bodies and tiles
-  bool device_ok = false;  // body part uploaded into the workspace
-  bool state_ok = false;   // populations hold a state
-  int cur = 0;             // which population buffer holds the state
-  int64_t steps = 0, hist_read = 0;
-  int64_t forces_from = 0;   // first step whose ring entry matches the body set
-  bool bodies_dirty = true;  // ring layout on the device predates the body set
-  // graph of graph_chunk steps starting from buffer 0
-  hipGraphExec_t graph = nullptr;
-  hipStream_t cap_stream = nullptr;
-  hipStream_t side = nullptr;            // marker kernel when it overlaps the lattice kernel
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-
-  int nb() const { return (int)cx.size(); }
-  int nm() const { return (int)X.size(); }
-  bool xper() const { return bc[0] == BTDF_PERIODIC; }
-  bool yper() const { return bc[2] == BTDF_PERIODIC; }
-  int i0() const { return xper() ? 0 : 1; }
-  int i1() const { return xper() ? nx - 1 : nx - 2; }
-  template <typename P>
-  P *at(size_t o) const { return reinterpret_cast<P *>(ws + o); }
-};
-
-namespace {
 
 void drop_graph(btdf_t *h) {
   if (h->graph) {
@@ -215,14 +145,23 @@ void compute_layout(btdf_t *h) {
   o = align256(o + 3 * (size_t)std::max(nb, 1) * sizeof(double));
   h->off_boff = o;
   o = align256(o + (size_t)(nb + 1) * sizeof(int));
+  // the tile region is sized for the launch shape with the most tiles and for
+  // the most tiles one marker stencil can touch (2 x 5), so a change of launch
+  // shape never changes the workspace size
+  long long max_tiles = 0;
+  for (int v = 0; v < num_variants(); ++v) {
+    int tx, ty;
+    variant_tile(v, &tx, &ty);
+    max_tiles = std::max(max_tiles, (long long)((h->nx + tx - 1) / tx) * ((h->ny + ty - 1) / ty));
+  }
+  const size_t list_cap = 10 * (size_t)nm + 1;
   h->off_toff = o;
-  o = align256(o + (size_t)(ntiles + 1) * sizeof(int));
+  o = align256(o + (size_t)(max_tiles + 1) * sizeof(int));
   h->off_tlist = o;
-  o = align256(o + h->tile_list.size() * sizeof(int));
+  o = align256(o + list_cap * sizeof(int));
   h->off_tmap = o;
-  o = align256(o + (size_t)ntiles * sizeof(int));
+  o = align256(o + (size_t)max_tiles * sizeof(int));
   h->total = o;
-
 
   h->layout_ok = true;
   h->device_ok = false;
@@ -473,7 +412,121 @@ int build_graph(btdf_t *h, const LbmParams &p, const IbParams &ib) {
   return ok();
 }
 
-}  // namespace
+// move the handle's device memory to dev[0 .. bytes) (null: library-owned)
+int bind_impl(btdf_t *h, void *dev, size_t bytes) {
+  if (dev && ((uintptr_t)dev & 255)) return fail(BTDF_EINVAL, "workspace must be 256-byte aligned");
+  if (!h->layout_ok) compute_layout(h);
+  if (dev && bytes < h->total)
+    return fail(BTDF_ENOMEM, "workspace has %zu bytes, %zu needed", bytes, h->total);
+  if (dev == (void *)h->ws && dev) {
+    h->ws_bytes = bytes;
+    return ok();
+  }
+  if (!dev) {
+    // back to library-owned memory on the next device call
+    if (h->ws && !h->ws_owned) {
+      char *nw = nullptr;
+      hipError_t e = hipMalloc((void **)&nw, h->total);
+      if (e != hipSuccess) return fail(BTDF_ENOMEM, "hipMalloc(%zu): %s", h->total, hipGetErrorString(e));
+      if (h->state_ok) {
+        HIPCHK(hipMemcpyAsync(nw, h->ws, moved_bytes(h), hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+      }
+      h->ws = nw;
+      h->ws_bytes = h->total;
+      h->ws_owned = true;
+      h->device_ok = false;
+      drop_graph(h);
+    }
+    return ok();
+  }
+  if (h->ws && h->state_ok) {
+    HIPCHK(hipMemcpyAsync(dev, h->ws, moved_bytes(h), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  if (h->ws && h->ws_owned) HIPCHK(hipFree(h->ws));
+  h->ws = (char *)dev;
+  h->ws_bytes = bytes;
+  h->ws_owned = false;
+  h->device_ok = false;
+  drop_graph(h);
+  return ok();
+}
+
+int add_body_impl(btdf_t *h, int n, const double *xy, const double *uv, double cx, double cy, double ds,
+                  int *body_id) {
+  if (n < 3) return fail(BTDF_EINVAL, "a body needs at least 3 markers (got %d)", n);
+  if (!std::isfinite(cx) || !std::isfinite(cy) || !std::isfinite(ds)) return fail(BTDF_EINVAL, "non-finite body parameter");
+  for (int l = 0; l < n; ++l) {
+    const double X = xy[2 * l], Y = xy[2 * l + 1];
+    if (!std::isfinite(X) || !std::isfinite(Y)) return fail(BTDF_EINVAL, "non-finite marker %d", l);
+    if (uv && (!std::isfinite(uv[2 * l]) || !std::isfinite(uv[2 * l + 1])))
+      return fail(BTDF_EINVAL, "non-finite marker velocity %d", l);
+    if (std::fabs(X) > 1e8 || std::fabs(Y) > 1e8) return fail(BTDF_EINVAL, "marker %d too far from the grid", l);
+    int lo, hi;
+    marker_range(h->kind, X, &lo, &hi);
+    if (!h->xper() && (lo < h->i0() || hi > h->i1()))
+      return fail(BTDF_EINVAL, "marker %d: stencil x range [%d, %d] leaves the fluid columns [%d, %d]", l, lo,
+                  hi, h->i0(), h->i1());
+    marker_range(h->kind, Y, &lo, &hi);
+    if (!h->yper() && (lo < 0 || hi > h->ny - 1))
+      return fail(BTDF_EINVAL, "marker %d: stencil y range [%d, %d] leaves the grid", l, lo, hi);
+  }
+  if (!(ds > 0.0)) {
+    double per = 0.0;
+    for (int l = 0; l < n; ++l) {
+      int m = (l + 1) % n;
+      per += std::hypot(xy[2 * m] - xy[2 * l], xy[2 * m + 1] - xy[2 * l + 1]);
+    }
+    ds = per / n;
+    if (!(ds > 0.0)) return fail(BTDF_EINVAL, "degenerate body (zero perimeter)");
+  }
+  if ((long long)h->nm() + n > (1LL << 30)) return fail(BTDF_EINVAL, "too many markers");
+  try {
+    const double s = h->drs * ds;
+    for (int l = 0; l < n; ++l) {
+      h->X.push_back(xy[2 * l]);
+      h->Y.push_back(xy[2 * l + 1]);
+      h->U.push_back(uv ? uv[2 * l] : 0.0);
+      h->V.push_back(uv ? uv[2 * l + 1] : 0.0);
+      h->sdrs.push_back(s);
+    }
+    h->off.push_back(h->nm());
+    h->cx.push_back(cx);
+    h->cy.push_back(cy);
+    h->bsdrs.push_back(s);
+  } catch (...) {
+    return fail(BTDF_ENOMEM, "out of host memory");
+  }
+  h->layout_ok = false;
+  h->device_ok = false;
+  h->bodies_dirty = true;
+  h->hist_read = h->steps;
+  h->forces_from = h->steps;
+  drop_graph(h);
+  if (body_id) *body_id = h->nb() - 1;
+  return ok();
+}
+
+int destroy_impl(btdf_t *h) {
+  int rc = ok();
+  if (h->ws) {
+    if (hipStreamSynchronize(h->stream) != hipSuccess) rc = fail(BTDF_EDEVICE, "stream sync failed");
+  }
+  drop_graph(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->side) (void)hipStreamDestroy(h->side);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->ws && h->ws_owned) (void)hipFree(h->ws);
+  delete h;
+  return rc;
+}
+
+}  // namespace host
+}  // namespace btdf
+
+using namespace btdf::host;
 
 extern "C" {
 
@@ -529,18 +582,8 @@ int btdf_create(const btdf_grid *g, double tau, int delta_kind, double thickenin
 
 int btdf_destroy(btdf_t *h) {
   if (!h) return ok();
-  int rc = ok();
-  if (h->ws) {
-    if (hipStreamSynchronize(h->stream) != hipSuccess) rc = fail(BTDF_EDEVICE, "stream sync failed");
-  }
-  drop_graph(h);
-  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-  if (h->side) (void)hipStreamDestroy(h->side);
-  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
-  if (h->ws && h->ws_owned) (void)hipFree(h->ws);
-  delete h;
-  return rc;
+  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; destroy the batch");
+  return destroy_impl(h);
 }
 
 size_t btdf_workspace_bytes(const btdf_t *h) {
@@ -551,47 +594,13 @@ size_t btdf_workspace_bytes(const btdf_t *h) {
 
 int btdf_bind_workspace(btdf_t *h, void *dev, size_t bytes) {
   if (!h) return fail(BTDF_EINVAL, "NULL handle");
-  if (dev && ((uintptr_t)dev & 255)) return fail(BTDF_EINVAL, "workspace must be 256-byte aligned");
-  if (!h->layout_ok) compute_layout(h);
-  if (dev && bytes < h->total)
-    return fail(BTDF_ENOMEM, "workspace has %zu bytes, %zu needed", bytes, h->total);
-  if (dev == (void *)h->ws && dev) {
-    h->ws_bytes = bytes;
-    return ok();
-  }
-  if (!dev) {
-    // back to library-owned memory on the next device call
-    if (h->ws && !h->ws_owned) {
-      char *nw = nullptr;
-      hipError_t e = hipMalloc((void **)&nw, h->total);
-      if (e != hipSuccess) return fail(BTDF_ENOMEM, "hipMalloc(%zu): %s", h->total, hipGetErrorString(e));
-      if (h->state_ok) {
-        HIPCHK(hipMemcpyAsync(nw, h->ws, moved_bytes(h), hipMemcpyDeviceToDevice, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-      }
-      h->ws = nw;
-      h->ws_bytes = h->total;
-      h->ws_owned = true;
-      h->device_ok = false;
-      drop_graph(h);
-    }
-    return ok();
-  }
-  if (h->ws && h->state_ok) {
-    HIPCHK(hipMemcpyAsync(dev, h->ws, moved_bytes(h), hipMemcpyDeviceToDevice, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-  }
-  if (h->ws && h->ws_owned) HIPCHK(hipFree(h->ws));
-  h->ws = (char *)dev;
-  h->ws_bytes = bytes;
-  h->ws_owned = false;
-  h->device_ok = false;
-  drop_graph(h);
-  return ok();
+  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; bind the batch's workspace");
+  return bind_impl(h, dev, bytes);
 }
 
 int btdf_set_stream(btdf_t *h, void *hip_stream) {
   if (!h) return fail(BTDF_EINVAL, "NULL handle");
+  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; set the batch's stream");
   if (h->ws && (hipStream_t)hip_stream != h->stream) {
     // order the new stream after the work already on the old one
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -603,57 +612,8 @@ int btdf_set_stream(btdf_t *h, void *hip_stream) {
 int btdf_add_body(btdf_t *h, int n, const double *xy, const double *uv, double cx, double cy, double ds,
                   int *body_id) {
   if (!h || !xy) return fail(BTDF_EINVAL, "NULL argument");
-  if (n < 3) return fail(BTDF_EINVAL, "a body needs at least 3 markers (got %d)", n);
-  if (!std::isfinite(cx) || !std::isfinite(cy) || !std::isfinite(ds)) return fail(BTDF_EINVAL, "non-finite body parameter");
-  for (int l = 0; l < n; ++l) {
-    const double X = xy[2 * l], Y = xy[2 * l + 1];
-    if (!std::isfinite(X) || !std::isfinite(Y)) return fail(BTDF_EINVAL, "non-finite marker %d", l);
-    if (uv && (!std::isfinite(uv[2 * l]) || !std::isfinite(uv[2 * l + 1])))
-      return fail(BTDF_EINVAL, "non-finite marker velocity %d", l);
-    if (std::fabs(X) > 1e8 || std::fabs(Y) > 1e8) return fail(BTDF_EINVAL, "marker %d too far from the grid", l);
-    int lo, hi;
-    marker_range(h->kind, X, &lo, &hi);
-    if (!h->xper() && (lo < h->i0() || hi > h->i1()))
-      return fail(BTDF_EINVAL, "marker %d: stencil x range [%d, %d] leaves the fluid columns [%d, %d]", l, lo,
-                  hi, h->i0(), h->i1());
-    marker_range(h->kind, Y, &lo, &hi);
-    if (!h->yper() && (lo < 0 || hi > h->ny - 1))
-      return fail(BTDF_EINVAL, "marker %d: stencil y range [%d, %d] leaves the grid", l, lo, hi);
-  }
-  if (!(ds > 0.0)) {
-    double per = 0.0;
-    for (int l = 0; l < n; ++l) {
-      int m = (l + 1) % n;
-      per += std::hypot(xy[2 * m] - xy[2 * l], xy[2 * m + 1] - xy[2 * l + 1]);
-    }
-    ds = per / n;
-    if (!(ds > 0.0)) return fail(BTDF_EINVAL, "degenerate body (zero perimeter)");
-  }
-  if ((long long)h->nm() + n > (1LL << 30)) return fail(BTDF_EINVAL, "too many markers");
-  try {
-    const double s = h->drs * ds;
-    for (int l = 0; l < n; ++l) {
-      h->X.push_back(xy[2 * l]);
-      h->Y.push_back(xy[2 * l + 1]);
-      h->U.push_back(uv ? uv[2 * l] : 0.0);
-      h->V.push_back(uv ? uv[2 * l + 1] : 0.0);
-      h->sdrs.push_back(s);
-    }
-    h->off.push_back(h->nm());
-    h->cx.push_back(cx);
-    h->cy.push_back(cy);
-    h->bsdrs.push_back(s);
-  } catch (...) {
-    return fail(BTDF_ENOMEM, "out of host memory");
-  }
-  h->layout_ok = false;
-  h->device_ok = false;
-  h->bodies_dirty = true;
-  h->hist_read = h->steps;
-  h->forces_from = h->steps;
-  drop_graph(h);
-  if (body_id) *body_id = h->nb() - 1;
-  return ok();
+  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; use btdf_batch_add_body");
+  return add_body_impl(h, n, xy, uv, cx, cy, ds, body_id);
 }
 
 int btdf_set_marker_velocity(btdf_t *h, int body, const double *uv) {
@@ -679,6 +639,7 @@ int btdf_set_marker_velocity(btdf_t *h, int body, const double *uv) {
 
 int btdf_step(btdf_t *h, int64_t n) {
   if (!h) return fail(BTDF_EINVAL, "NULL handle");
+  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; step the batch");
   if (n < 0) return fail(BTDF_EINVAL, "negative step count");
   if (n == 0) return ok();
   int rc = ensure_device(h);
@@ -713,6 +674,7 @@ int btdf_step(btdf_t *h, int64_t n) {
 
 int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm) {
   if (!h || !ms_ib || !ms_lbm) return fail(BTDF_EINVAL, "NULL argument");
+  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; step the batch");
   if (n <= 0) return fail(BTDF_EINVAL, "step count must be > 0");
   int rc = ensure_device(h);
   if (rc) return rc;
@@ -758,6 +720,40 @@ int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm) {
   if (rc) return rc;
   *ms_ib = h->nb() ? tib / (double)n : 0.0;
   *ms_lbm = tlbm / (double)n;
+  return ok();
+}
+
+int btdf_autotune(btdf_t *h, int64_t steps_per_trial, int *best_variant) {
+  if (!h) return fail(BTDF_EINVAL, "NULL handle");
+  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; tune the batch");
+  if (steps_per_trial < 1) return fail(BTDF_EINVAL, "steps_per_trial must be >= 1");
+  double best = 1e300;
+  int bv = h->variant, bi = h->interior;
+  for (int v = 0; v < num_variants(); ++v) {
+    for (int in = 0; in < 2; ++in) {
+      if (h->variant != v) {
+        h->variant = v;
+        h->layout_ok = false;  // the workspace size does not depend on the launch shape
+      }
+      h->interior = in;
+      drop_graph(h);
+      double a = 0.0, l = 0.0;
+      int rc = btdf_step_timed(h, steps_per_trial, &a, &l);
+      if (rc) return rc;
+      if (a + l < best) {
+        best = a + l;
+        bv = v;
+        bi = in;
+      }
+    }
+  }
+  if (h->variant != bv) {
+    h->variant = bv;
+    h->layout_ok = false;
+  }
+  h->interior = bi;
+  drop_graph(h);
+  if (best_variant) *best_variant = bv;
   return ok();
 }
 
@@ -948,6 +944,7 @@ int btdf_counts(const btdf_t *h, int *n_bodies, int *n_markers, int64_t *n_steps
 
 int btdf_set_option(btdf_t *h, int key, int64_t value) {
   if (!h) return fail(BTDF_EINVAL, "NULL handle");
+  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; set options on the batch");
   switch (key) {
     case BTDF_OPT_LBM_VARIANT:
       if (value < 0 || value >= num_variants()) return fail(BTDF_EINVAL, "variant %lld out of range", (long long)value);

@@ -105,6 +105,23 @@ struct IbParams {
   int *slot;     // ring entry of the current step (written by the marker kernel)
 };
 
+// one case of a batch: its parameters and its two population buffers
+struct CaseDesc {
+  LbmParams p;
+  IbParams ib;
+  void *pop[2];
+};
+
+// where the workgroups of the batched launches go
+struct BatchMap {
+  const int *tile_case, *tile_local;  // per lattice workgroup: case and tile within the case
+  const int *body_case, *body_local;  // per body-reduction workgroup
+  const int *mblk_case, *mblk_first;  // per marker workgroup: case and its first marker
+  int ntiles, nbodies, nmblk;
+  int xcd_remap;
+  int mask_unstable;  // skip the work of cases whose instability flag is set
+};
+
 // Streaming pull g_q(x, y) = f_q(x - e_q, y - e_q) with the boundary readings:
 // periodic directions wrap, halfway bounce-back walls in y return the
 // opposite population of the same node; channel ends read the ghost columns.

@@ -1,0 +1,101 @@
+// btdf_internal.h -- host-side state of a simulation handle and the helpers
+// shared by the single-case API (btdf_api.hip) and the batch API
+// (btdf_batch.hip). Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "btdf.h"
+#include "btdf_launch.h"
+
+#define HIPCHK(call)                                                                            \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess) return btdf::host::fail(BTDF_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+struct btdf_sim {
+  void *owner = nullptr;  // the batch this handle is a case of (null: stand-alone)
+  // configuration
+  int nx = 0, ny = 0;
+  int bc[4] = {0, 0, 0, 0};
+  int prec = 8;
+  int hist_cap = 4096;
+  int kind = btdf::kCos4;
+  double tau = 1.0, drs = 1.0;
+  double G[2] = {0, 0}, uin[2] = {0, 0};
+  double rho0 = 1.0, u0[2] = {0, 0};
+  hipStream_t stream = nullptr;
+  // bodies (host copies)
+  std::vector<double> X, Y, U, V, sdrs;
+  std::vector<int> off{0};
+  std::vector<double> cx, cy, bsdrs;
+  // lattice kernel launch shape and tiles
+  // launch defaults measured fastest on the 8192^2 particle-laden workload:
+  // 32x8 tiles, general pull, marker kernel before the lattice kernel
+  int variant = 6, xcd_remap = 1, graph_chunk = 0, interior = 0;
+  int row_pad = 0, plane_pad = 0;
+  int tile_x = 64, tile_y = 4, ntx = 0, nty = 0;
+  std::vector<int> tile_off, tile_list;
+  std::vector<int> tile_map;  // tiles no marker touches first, then the forced tiles
+  int n_free = 0, n_forced = 0;
+  int overlap = 0;            // run the marker kernel beside the lattice launch of the free tiles
+  // device memory
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  // layout
+  int pitch = 0;
+  long long plane = 0;
+  size_t off_pop[2] = {0, 0}, off_ctl = 0, grid_bytes = 0;
+  size_t off_hist = 0, off_mk = 0, off_mkw = 0, off_mkixy = 0, off_mkbody = 0, off_body = 0, off_boff = 0,
+         off_toff = 0, off_tlist = 0, off_tmap = 0, total = 0;
+  bool layout_ok = false;  // host layout current for bodies and tiles
+  bool device_ok = false;  // body part uploaded into the workspace
+  bool state_ok = false;   // populations hold a state
+  int cur = 0;             // which population buffer holds the state
+  int64_t steps = 0, hist_read = 0;
+  int64_t forces_from = 0;   // first step whose ring entry matches the body set
+  bool bodies_dirty = true;  // ring layout on the device predates the body set
+  // graph of graph_chunk steps starting from buffer 0
+  hipGraphExec_t graph = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipStream_t side = nullptr;            // marker kernel when it overlaps the lattice kernel
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
+  int nb() const { return (int)cx.size(); }
+  int nm() const { return (int)X.size(); }
+  bool xper() const { return bc[0] == BTDF_PERIODIC; }
+  bool yper() const { return bc[2] == BTDF_PERIODIC; }
+  int i0() const { return xper() ? 0 : 1; }
+  int i1() const { return xper() ? nx - 1 : nx - 2; }
+  template <typename P>
+  P *at(size_t o) const { return reinterpret_cast<P *>(ws + o); }
+};
+
+
+namespace btdf {
+namespace host {
+
+int fail(int code, const char *fmt, ...);
+inline int ok() { return BTDF_OK; }
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+bool valid_kind(int k);
+void drop_graph(btdf_t *h);
+void compute_layout(btdf_t *h);
+LbmParams make_params(const btdf_t *h);
+IbParams make_ib(const btdf_t *h);
+int ensure_device(btdf_t *h);
+int check_flag(btdf_t *h);
+int read_ctl(btdf_t *h, long long *ctr, int *flag);
+int bind_impl(btdf_t *h, void *dev, size_t bytes);
+int add_body_impl(btdf_t *h, int n, const double *xy, const double *uv, double cx, double cy, double ds,
+                  int *body_id);
+int destroy_impl(btdf_t *h);
+
+}  // namespace host
+}  // namespace btdf

@@ -37,14 +37,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 // delta weights, stencil origin and drs ds F_l are left for the lattice
 // kernel's spread gather. The per-body sums of eq 27 are formed by extra
 // workgroups of the lattice kernel, after this kernel has completed.
+// one marker per 16-lane group; l = marker id, act = l is a marker of ib
 template <typename T>
-__global__ __launch_bounds__(256) void ib_kernel(const T *__restrict__ A, LbmParams p, IbParams ib) {
+__device__ __forceinline__ void ib_marker(const T *__restrict__ A, const LbmParams &p, const IbParams &ib, int l,
+                                          bool act) {
   const int node = (int)threadIdx.x & 15;
-  const int l = (int)blockIdx.x * 16 + ((int)threadIdx.x >> 4);
-  const bool act = l < ib.nm;
   const int S = stencil_size(p.kind);
   const int a = node & 3, c = node >> 2;
-  if (blockIdx.x == 0 && threadIdx.x == 0) ib.slot[0] = (int)(p.step_ctr[0] % ib.hist_cap);
 
   double wr = 0.0, wu = 0.0, wv = 0.0, X = 0.0, Y = 0.0;
   int bx = 0, by = 0;
@@ -123,6 +122,16 @@ __global__ __launch_bounds__(256) void ib_kernel(const T *__restrict__ A, LbmPar
     ib.mk_ixy[2 * l + 1] = p.yper ? ((by % p.ny) + p.ny) % p.ny : by;
     if (!isfinite(Fx) || !isfinite(Fy) || !(sqrt(wu * wu + wv * wv) <= 0.3)) p.flag[0] = 1 + ib.mk_body[l];
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void ib_kernel(const T *__restrict__ A, LbmParams p, IbParams ib) {
+  // markers of one body are contiguous and share stencil nodes: consecutive
+  // workgroups go to one XCD so its L2 serves the shared population lines
+  const int blk = p.xcd_remap ? xcd_tile((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  const int l = blk * 16 + ((int)threadIdx.x >> 4);
+  if (blk == 0 && threadIdx.x == 0) ib.slot[0] = (int)(p.step_ctr[0] % ib.hist_cap);
+  ib_marker<T>(A, p, ib, l, l < ib.nm);
 }
 
 // Hydrodynamic force and torque on body b (eq 27 with the body's sign): a
@@ -215,22 +224,12 @@ __device__ __forceinline__ void store(T *ptr, T v) {
     *ptr = v;
 }
 
+// one tile t of the lattice: streaming pull, spread gather, collision
 template <typename T, int BX, int BY, int NPT, bool NT, bool NTL>
-__global__ __launch_bounds__(BX *BY) void lbm_kernel(const T *__restrict__ A, T *__restrict__ B,
-                                                     LbmParams p, TileRange r, IbParams ib) {
+__device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict__ B, const LbmParams &p, int t) {
   constexpr int TX = BX * NPT;
   __shared__ int s_ix[kChunk], s_iy[kChunk];
   __shared__ T s_w[kChunk][10];  // wx[4], wy[4], drs ds F_x, drs ds F_y
-
-  if ((int)blockIdx.x >= r.count) {  // workgroups past the tiles: one body each
-    __shared__ double red[3][BX * BY / 64];
-    body_reduce<BX * BY>(ib, (int)blockIdx.x - r.count, (int)threadIdx.y * BX + (int)threadIdx.x, red);
-    return;
-  }
-
-  // this launch covers tiles map[base .. base+count) (all tiles in order if map is null)
-  const int li = p.xcd_remap ? xcd_tile((int)blockIdx.x, r.count) : (int)blockIdx.x;
-  const int t = r.map ? r.map[r.base + li] : li;
   const int tyi = t / p.ntx;
   const int txi = t - tyi * p.ntx;
   const int y = tyi * BY + (int)threadIdx.y;
@@ -351,7 +350,56 @@ __global__ __launch_bounds__(BX *BY) void lbm_kernel(const T *__restrict__ A, T 
     }
   }
   if (bad) p.flag[0] = -1;
+}
+
+template <typename T, int BX, int BY, int NPT, bool NT, bool NTL>
+__global__ __launch_bounds__(BX *BY) void lbm_kernel(const T *__restrict__ A, T *__restrict__ B,
+                                                     LbmParams p, TileRange r, IbParams ib) {
+  if ((int)blockIdx.x >= r.count) {  // workgroups past the tiles: one body each
+    __shared__ double red[3][BX * BY / 64];
+    body_reduce<BX * BY>(ib, (int)blockIdx.x - r.count, (int)threadIdx.y * BX + (int)threadIdx.x, red);
+    return;
+  }
+  // this launch covers tiles map[base .. base+count) (all tiles in order if map is null)
+  const int li = p.xcd_remap ? xcd_tile((int)blockIdx.x, r.count) : (int)blockIdx.x;
+  const int t = r.map ? r.map[r.base + li] : li;
+  lbm_tile<T, BX, BY, NPT, NT, NTL>(A, B, p, t);
   if (r.count_step && li == 0 && threadIdx.x == 0 && threadIdx.y == 0) p.step_ctr[0] = p.step_ctr[0] + 1;
+}
+
+// ---- batched cases: every tile, marker and body of all cases in one launch each
+// (the per-case parameters are the single-case ones, read from a table)
+
+template <typename T, int BX, int BY, int NPT, bool NT, bool NTL>
+__global__ __launch_bounds__(BX *BY) void lbm_batch_kernel(const CaseDesc *__restrict__ cases, BatchMap m,
+                                                           int parity) {
+  if ((int)blockIdx.x >= m.ntiles) {  // one body each
+    const int gb = (int)blockIdx.x - m.ntiles;
+    const CaseDesc &cd = cases[m.body_case[gb]];
+    __shared__ double red[3][BX * BY / 64];
+    body_reduce<BX * BY>(cd.ib, m.body_local[gb], (int)threadIdx.y * BX + (int)threadIdx.x, red);
+    return;
+  }
+  const int li = m.xcd_remap ? xcd_tile((int)blockIdx.x, m.ntiles) : (int)blockIdx.x;
+  const int c = m.tile_case[li];
+  const int t = m.tile_local[li];
+  const CaseDesc &cd = cases[c];
+  if (m.mask_unstable && cd.p.flag[0] != 0) return;  // an unstable case stops; the others go on
+  lbm_tile<T, BX, BY, NPT, NT, NTL>(reinterpret_cast<const T *>(cd.pop[parity]),
+                                    reinterpret_cast<T *>(cd.pop[parity ^ 1]), cd.p, t);
+  if (t == 0 && threadIdx.x == 0 && threadIdx.y == 0) cd.p.step_ctr[0] = cd.p.step_ctr[0] + 1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void ib_batch_kernel(const CaseDesc *__restrict__ cases, BatchMap m, int parity) {
+  const int blk = m.xcd_remap ? xcd_tile((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  const int c = m.mblk_case[blk];
+  const int first = m.mblk_first[blk];
+  const CaseDesc &cd = cases[c];
+  if (m.mask_unstable && cd.p.flag[0] != 0) return;
+  if (first == 0 && threadIdx.x == 0) cd.ib.slot[0] = (int)(cd.p.step_ctr[0] % cd.ib.hist_cap);
+  const int l = first + ((int)threadIdx.x >> 4);
+  ib_marker<T>(reinterpret_cast<const T *>(cd.pop[parity]), cd.p, cd.ib, l, l < cd.ib.nm);
 }
 
 // ------------------------------------------------------------------ state kernels
@@ -509,6 +557,34 @@ hipError_t launch_lbm(int prec, int v, const void *A, void *B, const LbmParams &
                       const IbParams &ib, hipStream_t s) {
   if (prec == 4) return launch_lbm_any<float>(v, (const float *)A, (float *)B, p, r, ib, s);
   return launch_lbm_any<double>(v, (const double *)A, (double *)B, p, r, ib, s);
+}
+
+template <typename T>
+static hipError_t launch_lbm_batch_any(int v, const CaseDesc *cases, const BatchMap &m, int parity, hipStream_t s) {
+#define X(id, bx, by, npt, nt, ntl)                                                                          \
+  if (v == id) {                                                                                           \
+    hipLaunchKernelGGL((lbm_batch_kernel<T, bx, by, npt, nt, ntl>), dim3(m.ntiles + m.nbodies), dim3(bx, by), \
+                       0, s, cases, m, parity);                                                            \
+    return hipGetLastError();                                                                              \
+  }
+  BTDF_VARIANTS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_lbm_batch(int prec, int v, const CaseDesc *cases, const BatchMap &m, int parity, hipStream_t s) {
+  if (m.ntiles + m.nbodies <= 0) return hipSuccess;
+  if (prec == 4) return launch_lbm_batch_any<float>(v, cases, m, parity, s);
+  return launch_lbm_batch_any<double>(v, cases, m, parity, s);
+}
+
+hipError_t launch_ib_batch(int prec, const CaseDesc *cases, const BatchMap &m, int parity, hipStream_t s) {
+  if (m.nmblk <= 0) return hipSuccess;
+  if (prec == 4)
+    hipLaunchKernelGGL(ib_batch_kernel<float>, dim3(m.nmblk), dim3(256), 0, s, cases, m, parity);
+  else
+    hipLaunchKernelGGL(ib_batch_kernel<double>, dim3(m.nmblk), dim3(256), 0, s, cases, m, parity);
+  return hipGetLastError();
 }
 
 hipError_t launch_ib(int prec, const void *A, const LbmParams &p, const IbParams &ib, hipStream_t s) {

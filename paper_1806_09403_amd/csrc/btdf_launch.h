@@ -11,6 +11,9 @@ void variant_tile(int v, int *tx, int *ty);
 hipError_t launch_lbm(int prec, int variant, const void *A, void *B, const LbmParams &p, const TileRange &r,
                       const IbParams &ib, hipStream_t s);
 hipError_t launch_ib(int prec, const void *A, const LbmParams &p, const IbParams &ib, hipStream_t s);
+hipError_t launch_lbm_batch(int prec, int variant, const CaseDesc *cases, const BatchMap &m, int parity,
+                            hipStream_t s);
+hipError_t launch_ib_batch(int prec, const CaseDesc *cases, const BatchMap &m, int parity, hipStream_t s);
 hipError_t launch_init_uniform(int prec, void *A, const LbmParams &p, double r, double u, double v,
                                hipStream_t s);
 hipError_t launch_init_eq(int prec, void *A, const LbmParams &p, const double *rho, const double *ux,

@@ -109,3 +109,95 @@ class Sim:
 
     def get_option(self, key):
         return api.btdf_get_option(self.h, key)
+
+    def autotune(self, steps_per_trial=20):
+        return api.btdf_autotune(self._workspace(), steps_per_trial)
+
+
+class _CaseView(Sim):
+    """A case of a BatchSim: every state call of Sim, on the batch's memory."""
+
+    def __init__(self, batch, i, nx, ny, precision):
+        self._batch = batch
+        self.h = api.btdf_batch_case(batch.b, i)
+        self.nx, self.ny, self.precision = nx, ny, precision
+        self._ws = None
+
+    def _workspace(self):
+        self._batch._workspace()
+        return self.h
+
+    def close(self):
+        self.h = None  # owned by the batch
+
+    def step(self, n=1):
+        raise RuntimeError("step the batch, not one of its cases")
+
+
+class BatchSim:
+    """Many independent cases stepped together (one launch per kernel per step)."""
+
+    def __init__(self, cases, precision=4, device=None):
+        """cases: btdf_workloads.Case objects (bodies and initial flow included)."""
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("BatchSim needs a ROCm GPU")
+        self.device = torch.device("cuda" if device is None else device)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+        spec = [dict(nx=c.nx, ny=c.ny, tau=c.tau, delta_kind=c.kind, thickening=c.thickening, bc=c.bc,
+                     inflow=c.inflow, body_force=c.G, init=c.init, precision=precision) for c in cases]
+        self.b = api.btdf_batch_create(spec, self.stream.cuda_stream)
+        self.n = len(cases)
+        self._ws = None
+        self.cases = []
+        for i, c in enumerate(cases):
+            for body in c.bodies:
+                api.btdf_batch_add_body(self.b, i, body.xy, body.uv, body.cx, body.cy, body.ds)
+            self.cases.append(_CaseView(self, i, c.nx, c.ny, precision))
+        for i, c in enumerate(cases):
+            if c.init_uy is not None:
+                ux, uy = c.init_fields()
+                self.cases[i].init_equilibrium(ux, uy, np.full((c.ny, c.nx), c.init[0]))
+
+    def _workspace(self):
+        import torch
+        need = api.btdf_batch_workspace_bytes(self.b)
+        if self._ws is None or self._ws_need != need:
+            ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            api.btdf_batch_bind_workspace(self.b, ws.data_ptr(), ws.numel())
+            self._ws, self._ws_need = ws, need
+        return self.b
+
+    def add_body(self, case_id, xy, uv=None, cx=0.0, cy=0.0, ds=0.0):
+        return api.btdf_batch_add_body(self.b, case_id, xy, uv, cx, cy, ds)
+
+    def step(self, n=1):
+        return api.btdf_batch_step(self._workspace(), n)
+
+    def step_timed(self, n):
+        return api.btdf_batch_step_timed(self._workspace(), n)
+
+    def status(self):
+        return api.btdf_batch_status(self._workspace(), self.n)
+
+    def set_option(self, key, value):
+        return api.btdf_batch_set_option(self.b, key, value)
+
+    def get_option(self, key):
+        return api.btdf_batch_get_option(self.b, key)
+
+    def autotune(self, steps_per_trial=20):
+        return api.btdf_batch_autotune(self._workspace(), steps_per_trial)
+
+    def close(self):
+        if getattr(self, "b", None):
+            api.btdf_batch_destroy(self.b)
+            self.b = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
