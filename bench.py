@@ -40,14 +40,16 @@ def parse():
     p.add_argument("--interior", type=int, default=-1, help="1/0: uniform-base path for interior waves (-1: library default)")
     p.add_argument("--overlap", type=int, default=-1, help="1/0: marker kernel beside the lattice kernel (-1: library default)")
     p.add_argument("--plane-pad", type=int, default=0)
+    p.add_argument("--row-align", type=int, default=-1, help="row alignment in bytes (-1: library default)")
     p.add_argument("--copy-probe-mb", type=int, default=0,
                    help="before timing, copy a tensor of this size once (counter calibration)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-batched", action="store_true", help="skip the batched-mode figures")
+    p.add_argument("--only-batched", action="store_true", help="print the batched-mode figures alone")
     p.add_argument("--batched-steps", type=int, default=5000)
     p.add_argument("--batched-graph-chunk", type=int, default=50)
     p.add_argument("--seq-steps", type=int, default=200,
-                   help="steps per case when timing the sequential single-case runs")
+                   help="steps per case when timing the sequential single-case runs (0: skip them)")
     p.add_argument("--cpu-budget-s", type=float, default=20.0)
     return p.parse_args()
 
@@ -88,6 +90,23 @@ def cpu_baseline(case, budget_s):
                       % (case.name, steps, case.nx, case.ny, len(case.bodies), t2 - t0)}
 
 
+def copy_probe(mb):
+    """One plain device copy of known size: the reference dispatch against
+    which the HBM byte counters of the kernels are scaled."""
+    import torch
+    nbytes = mb << 20
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    print("copy probe: %d MiB read + %d MiB written in %.3f ms (%.1f GB/s)"
+          % (mb, mb, (t1 - t0) * 1e3, 2 * nbytes / (t1 - t0) / 1e9), file=sys.stderr, flush=True)
+    del src, dst
+
+
 def bench_batched(args):
     """The 256 uneven channel cases: one batch (autotuned launch shape, graph
     replay) against the same cases run one after another as single cases
@@ -99,7 +118,8 @@ def bench_batched(args):
 
     cases = W.c4()
     t_setup = time.perf_counter()
-    b = BatchSim(cases, precision=4)
+    b = BatchSim(cases, precision=4,
+                 options={_lib.OPT_ROW_ALIGN: args.row_align} if args.row_align >= 0 else None)
     best = b.autotune(steps_per_trial=5)
     b.set_option(_lib.OPT_GRAPH_CHUNK, args.batched_graph_chunk)
     b.step(100)
@@ -111,8 +131,15 @@ def bench_batched(args):
     wall = time.perf_counter() - t0
     unstable, _ = b.status()
     ms_ib, ms_lbm = b.step_timed(200)
+    b_align = b.get_option(_lib.OPT_ROW_ALIGN)
     b.close()
     del b
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f).get("batched-v%d-a%d" % (best, b_align))
+        if t:
+            traffic = round(t["bytes_per_launch"] / (ms_lbm * 1e-3) / 1e9, 1)
     stable = [k for k in range(len(cases)) if not unstable[k]]
     nodes = sum(cases[k].nodes for k in stable)
     mlups = nodes * args.batched_steps / wall / 1e6
@@ -120,7 +147,7 @@ def bench_batched(args):
     print("batched: %d of %d cases stable, %.1f MLUPS" % (len(stable), len(cases), mlups), file=sys.stderr, flush=True)
 
     t_seq = 0.0
-    for k in stable:
+    for k in (stable if args.seq_steps > 0 else []):
         s = Sim.from_case(cases[k], precision=4)
         s.set_option(_lib.OPT_GRAPH_CHUNK, args.batched_graph_chunk)
         s.step(args.batched_graph_chunk)
@@ -130,17 +157,20 @@ def bench_batched(args):
         torch.cuda.synchronize()
         t_seq += (time.perf_counter() - t0) / args.seq_steps
         s.close()
-    seq_mlups = nodes / t_seq / 1e6
-    print("sequential: %.1f MLUPS" % seq_mlups, file=sys.stderr, flush=True)
+    seq_mlups = nodes / t_seq / 1e6 if t_seq > 0 else None
+    if seq_mlups:
+        print("sequential: %.1f MLUPS" % seq_mlups, file=sys.stderr, flush=True)
     return {"workload": "256 uneven single-cylinder channels (W 128..1024, H = W/2, D 8..48, Re 0.1..200), FP32",
             "cases": len(cases), "stable_cases": len(stable), "nodes": nodes, "steps": args.batched_steps,
             "value": round(mlups, 2), "unit": "MLUPS", "ms_per_step": round(wall * 1e3 / args.batched_steps, 5),
-            "sequential_mlups": round(seq_mlups, 2), "speedup_vs_sequential": round(mlups / seq_mlups, 3),
+            "sequential_mlups": round(seq_mlups, 2) if seq_mlups else None,
+            "speedup_vs_sequential": round(mlups / seq_mlups, 3) if seq_mlups else None,
             "sequential_sample": "each stable case alone, %d graph-replayed steps" % args.seq_steps,
-            "lbm_variant": best, "graph_chunk": args.batched_graph_chunk,
+            "lbm_variant": best, "graph_chunk": args.batched_graph_chunk, "row_align": b_align,
             "kernel_ms": {"ib_batch_kernel": round(ms_ib, 5), "lbm_batch_kernel": round(ms_lbm, 5)},
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": "lbm_batch_kernel"}}
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                         "kernel": "lbm_batch_kernel"}}
 
 
 def main():
@@ -152,11 +182,18 @@ def main():
     import torch
     from paper_1806_09403_amd import Sim, _lib
 
+    if args.only_batched:
+        if args.copy_probe_mb:
+            copy_probe(args.copy_probe_mb)
+        print(json.dumps(bench_batched(args)), flush=True)
+        return
     case, prec = make_case(args)
     t_setup = time.perf_counter()
     sim = Sim.from_case(case, precision=prec, set_init=False)
     if args.row_pad:
         sim.set_option(_lib.OPT_ROW_PAD, args.row_pad)
+    if args.row_align >= 0:
+        sim.set_option(_lib.OPT_ROW_ALIGN, args.row_align)
     if args.plane_pad:
         sim.set_option(_lib.OPT_PLANE_PAD, args.plane_pad)
     if case.init_uy is not None:
@@ -174,18 +211,7 @@ def main():
     sim.step(args.warmup)
     torch.cuda.synchronize()
     if args.copy_probe_mb:
-        nbytes = args.copy_probe_mb << 20
-        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        print("copy probe: %d MiB read + %d MiB written in %.3f ms (%.1f GB/s)"
-              % (args.copy_probe_mb, args.copy_probe_mb, (t1 - t0) * 1e3, 2 * nbytes / (t1 - t0) / 1e9),
-              file=sys.stderr, flush=True)
-        del src, dst
+        copy_probe(args.copy_probe_mb)
     print("setup + warmup %.1f s" % (time.perf_counter() - t_setup), file=sys.stderr, flush=True)
 
     torch.cuda.synchronize()

@@ -84,6 +84,8 @@ extern "C" {
 #define BTDF_OPT_OVERLAP 10      /* 1: marker kernel on a second stream beside the lattice tiles it does not touch; 0 (default): in order */
 #define BTDF_OPT_FORCED_TILES 11 /* read-only: lattice tiles touched by some marker's stencil */
 #define BTDF_OPT_MASK_UNSTABLE 12 /* batches only: 1 (default) = a case that went unstable stops, the others go on */
+#define BTDF_OPT_ROW_ALIGN 13     /* bytes (0 or a power of two 4..4096, default 128): each row starts on this
+                                    boundary, pitch = round_up(nx, align) + row pad; only before the first device use */
 
 typedef struct btdf_grid {
   int32_t nx, ny;               /* nodes, ghost columns included; each >= 8 */
@@ -261,7 +263,7 @@ int btdf_batch_step_timed(btdf_batch_t *b, int64_t n, double *ms_ib, double *ms_
 /* unstable[c] = 1 if case c's instability flag is set (array of n_cases, may
  * be NULL); *n_steps = batch steps taken. Synchronising. */
 int btdf_batch_status(btdf_batch_t *b, int *unstable, int64_t *n_steps);
-/* Options: BTDF_OPT_LBM_VARIANT, _GRAPH_CHUNK, _XCD_REMAP, _INTERIOR_PATH, _MASK_UNSTABLE. */
+/* Options: BTDF_OPT_LBM_VARIANT, _GRAPH_CHUNK, _XCD_REMAP, _INTERIOR_PATH, _MASK_UNSTABLE, _ROW_ALIGN. */
 int btdf_batch_set_option(btdf_batch_t *b, int key, int64_t value);
 int btdf_batch_get_option(const btdf_batch_t *b, int key, int64_t *value);
 /* As btdf_autotune, for the batched launches. */

@@ -21,6 +21,7 @@ LINEAR2, ROMA3, PESKIN4, COS4 = 2, 3, 4, 5
 OPT_LBM_VARIANT, OPT_NUM_VARIANTS, OPT_GRAPH_CHUNK, OPT_XCD_REMAP, OPT_TILE_X, OPT_TILE_Y = 1, 2, 3, 4, 5, 6
 OPT_ROW_PAD, OPT_PLANE_PAD, OPT_INTERIOR_PATH, OPT_OVERLAP, OPT_FORCED_TILES = 7, 8, 9, 10, 11
 OPT_MASK_UNSTABLE = 12
+OPT_ROW_ALIGN = 13
 
 _NAMES = {OK: "BTDF_OK", EINVAL: "BTDF_EINVAL", ENOMEM: "BTDF_ENOMEM", EDEVICE: "BTDF_EDEVICE",
           ESTATE: "BTDF_ESTATE", EUNSTABLE: "BTDF_EUNSTABLE"}

@@ -75,7 +75,8 @@ int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
 
 void compute_layout(btdf_t *h) {
   const size_t elt = (size_t)h->prec;
-  h->pitch = h->nx + h->row_pad;
+  const int a = h->row_align > 0 ? std::max(1, h->row_align / (int)elt) : 1;
+  h->pitch = (h->nx + a - 1) / a * a + h->row_pad;
   h->plane = (((long long)h->pitch * h->ny + 63) / 64) * 64 + h->plane_pad;
   const size_t pop_bytes = align256(9 * (size_t)h->plane * elt);
   h->off_pop[0] = 0;
@@ -237,32 +238,37 @@ int upload(btdf_t *h, size_t off, const void *src, size_t bytes) {
 }
 
 int upload_bodies(btdf_t *h) {
+  // the whole body part [off_mk, total) is staged on the host and sent in one
+  // copy; arrays the kernels fill (marker forces, weights, stencil origins)
+  // start at zero
   const size_t M = (size_t)std::max(h->nm(), 1), B = (size_t)std::max(h->nb(), 1);
   const size_t nm = (size_t)h->nm(), nb = (size_t)h->nb();
   const size_t d = sizeof(double);
-  int rc;
-  if ((rc = upload(h, h->off_mk + 0 * M * d, h->X.data(), nm * d))) return rc;
-  if ((rc = upload(h, h->off_mk + 1 * M * d, h->Y.data(), nm * d))) return rc;
-  if ((rc = upload(h, h->off_mk + 2 * M * d, h->U.data(), nm * d))) return rc;
-  if ((rc = upload(h, h->off_mk + 3 * M * d, h->V.data(), nm * d))) return rc;
-  if ((rc = upload(h, h->off_mk + 4 * M * d, h->sdrs.data(), nm * d))) return rc;
-  HIPCHK(hipMemsetAsync(h->ws + h->off_mk + 5 * M * d, 0, 5 * M * d, h->stream));
-  if ((rc = upload(h, h->off_body + 0 * B * d, h->cx.data(), nb * d))) return rc;
-  if ((rc = upload(h, h->off_body + 1 * B * d, h->cy.data(), nb * d))) return rc;
-  if ((rc = upload(h, h->off_body + 2 * B * d, h->bsdrs.data(), nb * d))) return rc;
-  if ((rc = upload(h, h->off_boff, h->off.data(), (nb + 1) * sizeof(int)))) return rc;
-  std::vector<int> body_of((size_t)h->nm());
+  std::vector<char> &st = h->stage;
+  st.assign(h->total - h->off_mk, 0);
+  auto put = [&](size_t off, const void *src, size_t bytes) {
+    if (bytes) std::memcpy(st.data() + (off - h->off_mk), src, bytes);
+  };
+  put(h->off_mk + 0 * M * d, h->X.data(), nm * d);
+  put(h->off_mk + 1 * M * d, h->Y.data(), nm * d);
+  put(h->off_mk + 2 * M * d, h->U.data(), nm * d);
+  put(h->off_mk + 3 * M * d, h->V.data(), nm * d);
+  put(h->off_mk + 4 * M * d, h->sdrs.data(), nm * d);
+  put(h->off_body + 0 * B * d, h->cx.data(), nb * d);
+  put(h->off_body + 1 * B * d, h->cy.data(), nb * d);
+  put(h->off_body + 2 * B * d, h->bsdrs.data(), nb * d);
+  put(h->off_boff, h->off.data(), (nb + 1) * sizeof(int));
+  int *body_of = reinterpret_cast<int *>(st.data() + (h->off_mkbody - h->off_mk));
   for (int b = 0; b < h->nb(); ++b)
     for (int l = h->off[b]; l < h->off[b + 1]; ++l) body_of[l] = b;
-  if ((rc = upload(h, h->off_mkbody, body_of.data(), body_of.size() * sizeof(int)))) return rc;
-  HIPCHK(hipStreamSynchronize(h->stream));  // body_of is a local
-  if ((rc = upload(h, h->off_toff, h->tile_off.data(), h->tile_off.size() * sizeof(int)))) return rc;
-  if ((rc = upload(h, h->off_tlist, h->tile_list.data(), h->tile_list.size() * sizeof(int)))) return rc;
-  if ((rc = upload(h, h->off_tmap, h->tile_map.data(), h->tile_map.size() * sizeof(int)))) return rc;
+  put(h->off_toff, h->tile_off.data(), h->tile_off.size() * sizeof(int));
+  put(h->off_tlist, h->tile_list.data(), h->tile_list.size() * sizeof(int));
+  put(h->off_tmap, h->tile_map.data(), h->tile_map.size() * sizeof(int));
+  HIPCHK(hipMemcpyAsync(h->ws + h->off_mk, st.data(), st.size(), hipMemcpyHostToDevice, h->stream));
   if (h->bodies_dirty)
     HIPCHK(hipMemsetAsync(h->ws + h->off_hist, 0,
                           (size_t)h->hist_cap * std::max(h->nb(), 1) * 3 * sizeof(double), h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));  // host vectors may change after return
+  HIPCHK(hipStreamSynchronize(h->stream));  // the staging buffer may change after return
   h->device_ok = true;
   h->bodies_dirty = false;
   return ok();
@@ -988,6 +994,13 @@ int btdf_set_option(btdf_t *h, int key, int64_t value) {
         h->plane_pad = (int)value;
       h->layout_ok = false;
       return ok();
+    case BTDF_OPT_ROW_ALIGN:
+      if (value != 0 && (value < 4 || value > 4096 || (value & (value - 1))))
+        return fail(BTDF_EINVAL, "row alignment must be 0 or a power of two in 4 .. 4096 bytes");
+      if (h->state_ok) return fail(BTDF_ESTATE, "layout options must be set before the first device use");
+      h->row_align = (int)value;
+      h->layout_ok = false;
+      return ok();
     default: return fail(BTDF_EINVAL, "unknown or read-only option %d", key);
   }
 }
@@ -1010,6 +1023,7 @@ int btdf_get_option(const btdf_t *h, int key, int64_t *value) {
       *value = h->n_forced;
       return ok();
     case BTDF_OPT_PLANE_PAD: *value = h->plane_pad; return ok();
+    case BTDF_OPT_ROW_ALIGN: *value = h->row_align; return ok();
     default: return fail(BTDF_EINVAL, "unknown option %d", key);
   }
 }

@@ -35,7 +35,7 @@ struct btdf_batch {
   BatchMap map{};
   bool layout_ok = false, device_ok = false;
   // launch options
-  int variant = 6, xcd_remap = 1, mask = 1, graph_chunk = 0, interior = 0;
+  int variant = 6, xcd_remap = 1, mask = 1, graph_chunk = 0, interior = 0, row_align = 128;
   hipGraphExec_t graph = nullptr;
   hipStream_t cap_stream = nullptr;
   // time
@@ -60,6 +60,7 @@ void batch_layout(btdf_batch_t *b) {
     h->variant = b->variant;
     h->xcd_remap = b->xcd_remap;
     h->interior = b->interior;
+    h->row_align = b->row_align;
     compute_layout(h);
     long long mt = 0;
     for (int v = 0; v < num_variants(); ++v) {
@@ -459,6 +460,14 @@ int btdf_batch_set_option(btdf_batch_t *b, int key, int64_t value) {
       b->interior = (int)value;
       b->layout_ok = false;
       return ok();
+    case BTDF_OPT_ROW_ALIGN:
+      if (value != 0 && (value < 4 || value > 4096 || (value & (value - 1))))
+        return fail(BTDF_EINVAL, "row alignment must be 0 or a power of two in 4 .. 4096 bytes");
+      for (const btdf_t *h : b->cases)
+        if (h->state_ok) return fail(BTDF_ESTATE, "layout options must be set before the first device use");
+      b->row_align = (int)value;
+      b->layout_ok = false;
+      return ok();
     case BTDF_OPT_MASK_UNSTABLE:
       if (value != 0 && value != 1) return fail(BTDF_EINVAL, "mask flag must be 0 or 1");
       b->mask = (int)value;
@@ -477,6 +486,7 @@ int btdf_batch_get_option(const btdf_batch_t *b, int key, int64_t *value) {
     case BTDF_OPT_XCD_REMAP: *value = b->xcd_remap; return ok();
     case BTDF_OPT_INTERIOR_PATH: *value = b->interior; return ok();
     case BTDF_OPT_MASK_UNSTABLE: *value = b->mask; return ok();
+    case BTDF_OPT_ROW_ALIGN: *value = b->row_align; return ok();
     default: return fail(BTDF_EINVAL, "unknown batch option %d", key);
   }
 }

@@ -383,11 +383,14 @@ __global__ __launch_bounds__(BX *BY) void lbm_batch_kernel(const CaseDesc *__res
   const int li = m.xcd_remap ? xcd_tile((int)blockIdx.x, m.ntiles) : (int)blockIdx.x;
   const int c = m.tile_case[li];
   const int t = m.tile_local[li];
-  const CaseDesc &cd = cases[c];
-  if (m.mask_unstable && cd.p.flag[0] != 0) return;  // an unstable case stops; the others go on
-  lbm_tile<T, BX, BY, NPT, NT, NTL>(reinterpret_cast<const T *>(cd.pop[parity]),
-                                    reinterpret_cast<T *>(cd.pop[parity ^ 1]), cd.p, t);
-  if (t == 0 && threadIdx.x == 0 && threadIdx.y == 0) cd.p.step_ctr[0] = cd.p.step_ctr[0] + 1;
+  // the case's parameters are copied once into registers, as a kernel
+  // argument would be, rather than re-read through the table
+  const LbmParams p = cases[c].p;
+  const T *A = reinterpret_cast<const T *>(cases[c].pop[parity]);
+  T *B = reinterpret_cast<T *>(cases[c].pop[parity ^ 1]);
+  if (m.mask_unstable && p.flag[0] != 0) return;  // an unstable case stops; the others go on
+  lbm_tile<T, BX, BY, NPT, NT, NTL>(A, B, p, t);
+  if (t == 0 && threadIdx.x == 0 && threadIdx.y == 0) p.step_ctr[0] = p.step_ctr[0] + 1;
 }
 
 template <typename T>
@@ -395,11 +398,13 @@ __global__ __launch_bounds__(256) void ib_batch_kernel(const CaseDesc *__restric
   const int blk = m.xcd_remap ? xcd_tile((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
   const int c = m.mblk_case[blk];
   const int first = m.mblk_first[blk];
-  const CaseDesc &cd = cases[c];
-  if (m.mask_unstable && cd.p.flag[0] != 0) return;
-  if (first == 0 && threadIdx.x == 0) cd.ib.slot[0] = (int)(cd.p.step_ctr[0] % cd.ib.hist_cap);
+  const LbmParams p = cases[c].p;
+  const IbParams ib = cases[c].ib;
+  const T *A = reinterpret_cast<const T *>(cases[c].pop[parity]);
+  if (m.mask_unstable && p.flag[0] != 0) return;
+  if (first == 0 && threadIdx.x == 0) ib.slot[0] = (int)(p.step_ctr[0] % ib.hist_cap);
   const int l = first + ((int)threadIdx.x >> 4);
-  ib_marker<T>(reinterpret_cast<const T *>(cd.pop[parity]), cd.p, cd.ib, l, l < cd.ib.nm);
+  ib_marker<T>(A, p, ib, l, l < ib.nm);
 }
 
 // ------------------------------------------------------------------ state kernels

@@ -28,10 +28,13 @@ class Sim:
         self._ws = None
 
     @classmethod
-    def from_case(cls, case, precision=None, set_init=True):
-        """Build from a ``btdf_workloads.Case`` (bodies and initial flow included)."""
+    def from_case(cls, case, precision=None, set_init=True, options=None):
+        """Build from a ``btdf_workloads.Case`` (bodies and initial flow included);
+        options: {BTDF_OPT_* key: value} set before any device memory is made."""
         s = cls(case.nx, case.ny, case.tau, case.kind, case.thickening, case.bc, case.inflow, case.G,
                 case.init, case.precision if precision is None else precision)
+        for k, v in (options or {}).items():
+            s.set_option(k, v)
         for b in case.bodies:
             s.add_body(b.xy, b.uv, b.cx, b.cy, b.ds)
         if set_init and case.init_uy is not None:
@@ -137,8 +140,9 @@ class _CaseView(Sim):
 class BatchSim:
     """Many independent cases stepped together (one launch per kernel per step)."""
 
-    def __init__(self, cases, precision=4, device=None):
-        """cases: btdf_workloads.Case objects (bodies and initial flow included)."""
+    def __init__(self, cases, precision=4, device=None, options=None):
+        """cases: btdf_workloads.Case objects (bodies and initial flow included);
+        options: {BTDF_OPT_* key: value} set before any device memory is made."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("BatchSim needs a ROCm GPU")
@@ -148,6 +152,8 @@ class BatchSim:
         spec = [dict(nx=c.nx, ny=c.ny, tau=c.tau, delta_kind=c.kind, thickening=c.thickening, bc=c.bc,
                      inflow=c.inflow, body_force=c.G, init=c.init, precision=precision) for c in cases]
         self.b = api.btdf_batch_create(spec, self.stream.cuda_stream)
+        for k, v in (options or {}).items():
+            api.btdf_batch_set_option(self.b, k, v)
         self.n = len(cases)
         self._ws = None
         self.cases = []

@@ -130,3 +130,15 @@ def test_calibration_errors(lib):
     assert err(api.btdf_calibrate_thickening, W.ROMA3, xy, 1.0).code == -4
     assert err(api.btdf_calibrate_thickening, 9, xy, 1.0).code == -1
     assert err(api.btdf_calibrate_thickening, W.ROMA3, xy, 0.0).code == -1
+
+
+def test_header_constants_match_binding():
+    """Every #define of include/btdf.h has the same value in the binding."""
+    from paper_1806_09403_amd import _lib
+    text = open(HEADER).read()
+    found = 0
+    for name, val in re.findall(r"^#define BTDF_(\w+)[ \t]+\(?(-?\d+)\)?", text, re.M):
+        assert hasattr(_lib, name), name
+        assert getattr(_lib, name) == int(val), (name, val)
+        found += 1
+    assert found >= 25
