@@ -542,3 +542,285 @@ int oracle_num_threads(void) {
   return 1;
 #endif
 }
+
+/* ======================================================================
+ * Reverse mode. The step above is a differentiable map
+ *   A_{t+1} = Step(A_t; U_b, X, c, u_in, G)
+ * that also emits the body forces h_t (Fx, Fy, Tz per body, eq 27). For a
+ * scalar J = sum_t sum_b hbar_t . h_t (hbar given), oracle_adjoint returns
+ * dJ/dA_0, dJ/du_in, dJ/dG, dJ/dX_l, dJ/dU_b,l and dJ/dc_b (the centre
+ * enters the torque only). It runs the n forward steps keeping every state
+ * (a full tape: the oracle is for small grids), then walks back through the
+ * steps, each time recomputing the step's intermediates from its stored
+ * state and applying the transposes of its parts in reverse order:
+ *   boundary columns -> collision (eqs 5-7, 11) -> body force (eq 27) ->
+ *   spreading (eqs 13, 15) -> direct force (eq 20) -> interpolation
+ *   (eqs 12, 14) -> u* of the moments -> moments (eqs 9-10) -> streaming.
+ * Positions enter through the weights W_lk = phi(x_k - X_l) phi(y_k - Y_l),
+ * whose derivative uses phi' (oracle_delta_deriv).
+ * ====================================================================== */
+
+/* d phi / d r of the delta functions of Section 4.3 (one-sided 0 outside
+ * the support; LINEAR2 takes -sign(r), its kink at r = 0 having no
+ * derivative). */
+double oracle_delta_deriv(int kind, double r) {
+  double a = fabs(r), s = r < 0.0 ? -1.0 : 1.0;
+  switch (kind) {
+    case ORC_LINEAR2:
+      return a < 1.0 ? -s : 0.0;
+    case ORC_ROMA3:
+      if (a <= 0.5) return s * (-a / sqrt(1.0 - 3.0 * a * a));
+      if (a < 1.5) {
+        double b = 1.0 - a;
+        return s * (-3.0 - 3.0 * b / sqrt(1.0 - 3.0 * b * b)) / 6.0;
+      }
+      return 0.0;
+    case ORC_PESKIN4:
+      if (a < 1.0) return s * (-2.0 + (2.0 - 4.0 * a) / sqrt(1.0 + 4.0 * a - 4.0 * a * a)) / 8.0;
+      if (a < 2.0) return s * (-2.0 - (6.0 - 4.0 * a) / sqrt(-7.0 + 12.0 * a - 4.0 * a * a)) / 8.0;
+      return 0.0;
+    case ORC_COS4:
+      return a <= 2.0 ? -s * (M_PI / 8.0) * sin(M_PI * a / 2.0) : 0.0;
+    default:
+      return NAN;
+  }
+}
+
+/* Where the streaming of node (i, j), direction q, reads A: the element
+ * index of the source (see stream()). */
+static size_t stream_source(const oracle_t *o, int q, int j, int i) {
+  int sj = j - EY[q], si = i - EX[q];
+  if (sj < 0 || sj >= o->ny) {
+    if (y_periodic(o)) {
+      sj = wrap(sj, o->ny);
+      if (x_periodic(o)) si = wrap(si, o->nx);
+      return idx(o, q, sj, si);
+    }
+    return idx(o, opposite(q), j, i);
+  }
+  if (x_periodic(o)) si = wrap(si, o->nx);
+  return idx(o, q, sj, si);
+}
+
+/* d feq_q / d rho at fixed u, and d feq_q / d u at fixed rho (eq 6). */
+static double feq_drho(int q, double ux, double uy) { return feq(q, 1.0, ux, uy); }
+static void feq_du(int q, double rho, double ux, double uy, double *dx, double *dy) {
+  double eu = EX[q] * ux + EY[q] * uy;
+  *dx = WQ[q] * rho * (3.0 * EX[q] + 9.0 * eu * EX[q] - 3.0 * ux);
+  *dy = WQ[q] * rho * (3.0 * EY[q] + 9.0 * eu * EY[q] - 3.0 * uy);
+}
+
+/* n steps forward from the current state (the state advances by n, as with
+ * oracle_step), then the reverse sweep. hist_bar is [n][nb][3]; every
+ * output may be NULL; outputs are overwritten, not accumulated:
+ * pop_bar [9][ny][nx], inflow_bar [2], force_bar [2], xy_bar [nm][2],
+ * uv_bar [nm][2], centre_bar [nb][2]. Returns 0, or -1 when memory fails
+ * or the forward run went unstable. */
+int oracle_adjoint(oracle_t *o, long n, const double *hist_bar, double *pop_bar,
+                   double *inflow_bar, double *force_bar, double *xy_bar, double *uv_bar,
+                   double *centre_bar) {
+  const size_t N = nnode(o), S = 9 * N;
+  const int nx = o->nx, ny = o->ny, nb = o->nb, nm = o->nm;
+  const int i0 = i_first(o), i1 = i_last(o);
+  const double tau = o->tau, h = oracle_delta_halfwidth(o->kind);
+  double *tape = (double *)malloc((size_t)(n + 1) * S * sizeof(double));
+  double *hist = (double *)malloc((size_t)(n > 0 ? n : 1) * (nb > 0 ? nb : 1) * 3 * sizeof(double));
+  double *Abar = (double *)calloc(S, sizeof(double));
+  double *Bbar = (double *)malloc(S * sizeof(double));
+  double *gbar = (double *)malloc(S * sizeof(double));
+  double *fbx = (double *)malloc(N * sizeof(double)), *fby = (double *)malloc(N * sizeof(double));
+  double *Fbx = (double *)malloc((size_t)(nm > 0 ? nm : 1) * sizeof(double));
+  double *Fby = (double *)malloc((size_t)(nm > 0 ? nm : 1) * sizeof(double));
+  double gin[2] = {0.0, 0.0}, gG[2] = {0.0, 0.0};
+  double *gxy = (double *)calloc((size_t)(nm > 0 ? nm : 1) * 2, sizeof(double));
+  double *guv = (double *)calloc((size_t)(nm > 0 ? nm : 1) * 2, sizeof(double));
+  double *gc = (double *)calloc((size_t)(nb > 0 ? nb : 1) * 2, sizeof(double));
+  int rc = 0;
+  if (!tape || !hist || !Abar || !Bbar || !gbar || !fbx || !fby || !Fbx || !Fby || !gxy || !guv || !gc) {
+    rc = -1;
+    goto done;
+  }
+
+  /* forward, keeping every state and the body forces of every step */
+  memcpy(tape, o->A, S * sizeof(double));
+  for (long t = 0; t < n; ++t) {
+    oracle_step(o, 1);
+    memcpy(tape + (size_t)(t + 1) * S, o->A, S * sizeof(double));
+    memcpy(hist + (size_t)t * nb * 3, o->force, (size_t)nb * 3 * sizeof(double));
+  }
+  if (o->unstable) {
+    rc = -1;
+    goto done;
+  }
+
+  /* Abar holds dJ/dA_{t+1}; J does not read the final state */
+  for (long t = n - 1; t >= 0; --t) {
+    const double *Anext = tape + (size_t)(t + 1) * S;
+    /* recompute the intermediates of step t from its state */
+    memcpy(o->A, tape + (size_t)t * S, S * sizeof(double));
+    stream(o);
+    moments(o);
+    immersed_boundary(o);
+
+    /* boundary columns (applied last in the forward step, so first here) */
+    memcpy(Bbar, Abar, S * sizeof(double));
+    if (o->bc[1] == ORC_ZERO_GRADIENT_OUTLET) {
+      for (int j = 0; j < ny; ++j)
+        for (int q = 0; q < 9; ++q) {
+          Bbar[idx(o, q, j, nx - 2)] += Bbar[idx(o, q, j, nx - 1)];
+          Bbar[idx(o, q, j, nx - 1)] = 0.0;
+        }
+    }
+    if (o->bc[0] == ORC_VELOCITY_INLET) {
+      for (int j = 0; j < ny; ++j) {
+        double r = 0.0; /* density of column 1 after collision */
+        for (int q = 0; q < 9; ++q) r += Anext[idx(o, q, j, 1)];
+        double rbar = 0.0;
+        for (int q = 0; q < 9; ++q) {
+          double bb = Bbar[idx(o, q, j, 0)];
+          double dx, dy;
+          feq_du(q, r, o->uin[0], o->uin[1], &dx, &dy);
+          rbar += bb * feq_drho(q, o->uin[0], o->uin[1]);
+          gin[0] += bb * dx;
+          gin[1] += bb * dy;
+          Bbar[idx(o, q, j, 0)] = 0.0;
+        }
+        for (int q = 0; q < 9; ++q) Bbar[idx(o, q, j, 1)] += rbar;
+      }
+    }
+
+    /* collision at every fluid node: B_q = g_q - (g_q - feq_q(rho, u)) / tau + F_q,
+     * u = (m + f/2) / rho, f = G + f_IB */
+    memset(gbar, 0, S * sizeof(double));
+    for (size_t k = 0; k < N; ++k) fbx[k] = fby[k] = 0.0;
+    for (int j = 0; j < ny; ++j) {
+      for (int i = i0; i <= i1; ++i) {
+        size_t k = (size_t)j * nx + i;
+        double r = o->rho[k];
+        double ftx = o->G[0] + o->fx[k], fty = o->G[1] + o->fy[k];
+        double ux = (o->mx[k] + 0.5 * ftx) / r, uy = (o->my[k] + 0.5 * fty) / r;
+        double c = 1.0 - 1.0 / (2.0 * tau);
+        double rbar = 0.0, ubx = 0.0, uby = 0.0, ftbx = 0.0, ftby = 0.0;
+        for (int q = 0; q < 9; ++q) {
+          double bb = Bbar[idx(o, q, j, i)];
+          double eu = EX[q] * ux + EY[q] * uy;
+          double ef = EX[q] * ftx + EY[q] * fty;
+          double dx, dy;
+          feq_du(q, r, ux, uy, &dx, &dy);
+          gbar[idx(o, q, j, i)] += (1.0 - 1.0 / tau) * bb;
+          rbar += bb * feq_drho(q, ux, uy) / tau;
+          /* d F_q / d u and d F_q / d f of eq 7 */
+          ubx += bb * (dx / tau + c * WQ[q] * (-3.0 * ftx + 9.0 * ef * EX[q]));
+          uby += bb * (dy / tau + c * WQ[q] * (-3.0 * fty + 9.0 * ef * EY[q]));
+          ftbx += bb * c * WQ[q] * (3.0 * (EX[q] - ux) + 9.0 * eu * EX[q]);
+          ftby += bb * c * WQ[q] * (3.0 * (EY[q] - uy) + 9.0 * eu * EY[q]);
+        }
+        /* u = (m + f/2) / rho */
+        double mbx = ubx / r, mby = uby / r;
+        ftbx += 0.5 * ubx / r;
+        ftby += 0.5 * uby / r;
+        rbar -= (ubx * ux + uby * uy) / r;
+        for (int q = 0; q < 9; ++q) gbar[idx(o, q, j, i)] += rbar + EX[q] * mbx + EY[q] * mby;
+        fbx[k] = ftbx;
+        fby[k] = ftby;
+        gG[0] += ftbx;
+        gG[1] += ftby;
+      }
+    }
+
+    /* body force and torque (eq 27), then spreading (eqs 13, 15): dJ/dF_l */
+    for (int m = 0; m < nm; ++m) {
+      int b = o->body_of[m];
+      double s = o->drs * o->ds[b];
+      const double *hb = hist_bar + ((size_t)t * nb + b) * 3;
+      double X = o->X[m], Y = o->Y[m];
+      /* F_b = -s sum F_l ; T_b = -s sum (X_l - c) x F_l */
+      double Fbarx = -s * hb[0] + s * hb[2] * (Y - o->cy[b]);
+      double Fbary = -s * hb[1] - s * hb[2] * (X - o->cx[b]);
+      gxy[2 * m] += -s * hb[2] * o->Fy[m];
+      gxy[2 * m + 1] += s * hb[2] * o->Fx[m];
+      for (int j = (int)ceil(Y - h); j <= (int)floor(Y + h); ++j) {
+        for (int i = (int)ceil(X - h); i <= (int)floor(X + h); ++i) {
+          double px = oracle_delta(o->kind, i - X), py = oracle_delta(o->kind, j - Y);
+          double dpx = -oracle_delta_deriv(o->kind, i - X) * py; /* dW/dX */
+          double dpy = -px * oracle_delta_deriv(o->kind, j - Y); /* dW/dY */
+          size_t k = node_of(o, i, j);
+          Fbarx += px * py * s * fbx[k];
+          Fbary += px * py * s * fby[k];
+          double fdot = s * (o->Fx[m] * fbx[k] + o->Fy[m] * fby[k]);
+          gxy[2 * m] += dpx * fdot;
+          gxy[2 * m + 1] += dpy * fdot;
+        }
+      }
+      Fbx[m] = Fbarx;
+      Fby[m] = Fbary;
+    }
+    for (int b = 0; b < nb; ++b) { /* the centre enters the torque only */
+      const double *hb = hist_bar + ((size_t)t * nb + b) * 3;
+      const double *Fb = hist + ((size_t)t * nb + b) * 3;
+      gc[2 * b] += -hb[2] * Fb[1];
+      gc[2 * b + 1] += hb[2] * Fb[0];
+    }
+
+    /* direct force (eq 20) and interpolation (eqs 12, 14) */
+    for (int m = 0; m < nm; ++m) {
+      double X = o->X[m], Y = o->Y[m];
+      double rl = o->rho_l[m], ul = o->ux_l[m], vl = o->uy_l[m];
+      /* F = 2 rho_l (U_b - u*_l) */
+      double rlbar = 2.0 * (Fbx[m] * (o->Ub[m] - ul) + Fby[m] * (o->Vb[m] - vl));
+      double ulbar = -2.0 * rl * Fbx[m], vlbar = -2.0 * rl * Fby[m];
+      guv[2 * m] += 2.0 * rl * Fbx[m];
+      guv[2 * m + 1] += 2.0 * rl * Fby[m];
+      for (int j = (int)ceil(Y - h); j <= (int)floor(Y + h); ++j) {
+        for (int i = (int)ceil(X - h); i <= (int)floor(X + h); ++i) {
+          double px = oracle_delta(o->kind, i - X), py = oracle_delta(o->kind, j - Y);
+          double W = px * py;
+          double dpx = -oracle_delta_deriv(o->kind, i - X) * py;
+          double dpy = -px * oracle_delta_deriv(o->kind, j - Y);
+          size_t k = node_of(o, i, j);
+          double r = o->rho[k];
+          double us = (o->mx[k] + 0.5 * o->G[0]) / r, vs = (o->my[k] + 0.5 * o->G[1]) / r;
+          double v = rlbar * r + ulbar * us + vlbar * vs;
+          gxy[2 * m] += dpx * v;
+          gxy[2 * m + 1] += dpy * v;
+          /* node adjoints of rho and u* = (m + G/2) / rho */
+          double usbar = W * ulbar, vsbar = W * vlbar;
+          double rbar = W * rlbar - (usbar * us + vsbar * vs) / r;
+          double mbx = usbar / r, mby = vsbar / r;
+          gG[0] += 0.5 * usbar / r;
+          gG[1] += 0.5 * vsbar / r;
+          int jj = (int)(k / (size_t)nx), ii = (int)(k % (size_t)nx);
+          for (int q = 0; q < 9; ++q) gbar[idx(o, q, jj, ii)] += rbar + EX[q] * mbx + EY[q] * mby;
+        }
+      }
+    }
+
+    /* streaming: g_q(x) = A(source) for every fluid node, so the adjoint of
+     * the state collects each g's adjoint at its source */
+    memset(Abar, 0, S * sizeof(double));
+    for (int q = 0; q < 9; ++q)
+      for (int j = 0; j < ny; ++j)
+        for (int i = i0; i <= i1; ++i) Abar[stream_source(o, q, j, i)] += gbar[idx(o, q, j, i)];
+  }
+
+  /* back to the final state, with the intermediates of the last step as
+   * oracle_step leaves them (the step is recomputed from its stored state) */
+  if (n > 0) {
+    memcpy(o->A, tape + (size_t)(n - 1) * S, S * sizeof(double));
+    stream(o);
+    moments(o);
+    immersed_boundary(o);
+    collide(o);
+    boundary_columns(o);
+  }
+  if (pop_bar) memcpy(pop_bar, Abar, S * sizeof(double));
+  if (inflow_bar) { inflow_bar[0] = gin[0]; inflow_bar[1] = gin[1]; }
+  if (force_bar) { force_bar[0] = gG[0]; force_bar[1] = gG[1]; }
+  if (xy_bar) memcpy(xy_bar, gxy, (size_t)nm * 2 * sizeof(double));
+  if (uv_bar) memcpy(uv_bar, guv, (size_t)nm * 2 * sizeof(double));
+  if (centre_bar) memcpy(centre_bar, gc, (size_t)nb * 2 * sizeof(double));
+done:
+  free(tape); free(hist); free(Abar); free(Bbar); free(gbar); free(fbx); free(fby);
+  free(Fbx); free(Fby); free(gxy); free(guv); free(gc);
+  return rc;
+}

@@ -61,6 +61,10 @@ def lib():
         L.oracle_delta.argtypes = [ctypes.c_int, ctypes.c_double]
         L.oracle_delta_halfwidth.restype = ctypes.c_double
         L.oracle_delta_halfwidth.argtypes = [ctypes.c_int]
+        L.oracle_delta_deriv.restype = ctypes.c_double
+        L.oracle_delta_deriv.argtypes = [ctypes.c_int, ctypes.c_double]
+        L.oracle_adjoint.restype = ctypes.c_int
+        L.oracle_adjoint.argtypes = [ctypes.c_void_p, ctypes.c_long, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         _lib = L
@@ -77,6 +81,13 @@ def delta(kind, r):
     L = lib()
     r = np.asarray(r, dtype=np.float64)
     return np.vectorize(lambda v: L.oracle_delta(int(kind), float(v)))(r).astype(np.float64)
+
+
+def delta_deriv(kind, r):
+    """phi'(r) of the delta functions (vectorised over r)."""
+    L = lib()
+    r = np.asarray(r, dtype=np.float64)
+    return np.vectorize(lambda v: L.oracle_delta_deriv(int(kind), float(v)))(r).astype(np.float64)
 
 
 class OracleSim:
@@ -188,3 +199,22 @@ class OracleSim:
     @property
     def steps(self):
         return lib().oracle_steps(self._h)
+
+    def adjoint(self, n, hist_bar):
+        """Run n steps (the state advances by n), then the reverse sweep for
+        J = sum(hist_bar * history of these n steps); hist_bar is [n][nb][3].
+        Returns dJ/d(initial populations, inflow, body force, marker
+        positions, marker velocities, body centres)."""
+        nb = lib().oracle_num_bodies(self._h)
+        nm = lib().oracle_num_markers(self._h)
+        hb = np.ascontiguousarray(hist_bar, dtype=np.float64).reshape(int(n), nb, 3)
+        if hb.size == 0:
+            hb = np.zeros(1)
+        out = dict(populations=np.empty((9, self.ny, self.nx)), inflow=np.empty(2), body_force=np.empty(2),
+                   xy=np.empty((max(nm, 1), 2)), uv=np.empty((max(nm, 1), 2)), centres=np.empty((max(nb, 1), 2)))
+        rc = lib().oracle_adjoint(self._h, int(n), _ptr(hb), _ptr(out["populations"]), _ptr(out["inflow"]),
+                                  _ptr(out["body_force"]), _ptr(out["xy"]), _ptr(out["uv"]), _ptr(out["centres"]))
+        if rc != 0:
+            raise RuntimeError("oracle_adjoint failed (memory or an unstable forward run)")
+        out["xy"], out["uv"], out["centres"] = out["xy"][:nm], out["uv"][:nm], out["centres"][:nb]
+        return out
