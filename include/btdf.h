@@ -205,9 +205,12 @@ int btdf_set_populations(btdf_t *h, const double *src);
 int btdf_get_marker_data(btdf_t *h, double *rho_l, double *ux_l, double *uy_l, double *Fx,
                          double *Fy);
 
-/* Checkpoint: the populations in the handle's own precision plus the step
- * counter. btdf_state_bytes gives the size; save writes it into the host
- * buffer dst, load restores it (bit-identical resume). Synchronising. */
+/* Checkpoint: the populations as the handle stores them (its precision, as
+ * deviations from the equilibrium at the initial velocity of btdf_grid)
+ * plus the step counter. btdf_state_bytes gives the size; save writes it
+ * into the host buffer dst, load restores it (bit-identical resume) into a
+ * handle of the same size, precision and initial velocity (else EINVAL).
+ * Synchronising. */
 size_t btdf_state_bytes(const btdf_t *h);
 int btdf_save(btdf_t *h, void *dst, size_t bytes);
 int btdf_load(btdf_t *h, const void *src, size_t bytes);
@@ -268,6 +271,49 @@ int btdf_batch_set_option(btdf_batch_t *b, int key, int64_t value);
 int btdf_batch_get_option(const btdf_batch_t *b, int key, int64_t *value);
 /* As btdf_autotune, for the batched launches. */
 int btdf_batch_autotune(btdf_batch_t *b, int64_t steps_per_trial, int *best_variant);
+
+/* ---- reverse mode: gradients of a weighted force history ----
+ * J = sum over the n steps t and bodies b of hist_bar[t][b] . (Fx, Fy, Tz)
+ * of that step (eq 27): any weighting of the force history, e.g. the time
+ * mean of the drag coefficient, hist_bar[t][b] = (2 / (rho0 U^2 D n), 0, 0).
+ * btdf_adjoint takes the n steps exactly as btdf_step(n) would (same kernels,
+ * same final state, same history ring), then sweeps back through Algorithm 1
+ * (Section 2.4) step by step with the transposes of its parts: boundary
+ * columns, collision (eqs 5-7, 11), body force (eq 27), spreading (eqs 13,
+ * 15), direct force (eq 20), interpolation (eqs 12, 14), moments (eqs 9-10)
+ * and streaming. States of the forward run are kept all (checkpoint_every
+ * >= n: a tape, no recomputation) or every K-th (checkpoint_every = K; 0
+ * picks ceil(sqrt(n))), the states between checkpoints being recomputed one
+ * segment at a time; both give bit-identical gradients. The arithmetic runs
+ * in the handle's precision; gradients are returned in FP64.
+ *   hist_bar  [n][n_bodies][3] host, FP64 (may be NULL without bodies)
+ *   grads     host arrays to fill; any member may be NULL:
+ *     populations [9][ny][nx]  dJ/d(populations before the first step)
+ *     inflow      [2]          dJ/d(inlet velocity of the ghost column); the
+ *                              initial state is an input of its own
+ *     body_force  [2]          dJ/dG (uniform body-force density)
+ *     marker_xy   [n_markers][2]  dJ/d(marker positions), through phi' of the
+ *                              delta function (LINEAR2: one-sided at its kink)
+ *     marker_uv   [n_markers][2]  dJ/d(prescribed marker velocities)
+ *     centres     [n_bodies][2]   dJ/d(body centres) through the torque only
+ *                              (moving a body also moves its markers)
+ *   work      device memory of btdf_adjoint_workspace_bytes bytes, 256-byte
+ *             aligned, or NULL (the library allocates and frees it)
+ *   ms        [3] or NULL: milliseconds of the forward run, of the
+ *             recomputation and of the reverse steps (HIP events)
+ * Synchronising. Errors: EINVAL, ENOMEM, EUNSTABLE (the run went unstable:
+ * no gradient), EDEVICE. */
+typedef struct btdf_gradients {
+  double *populations;
+  double *inflow;
+  double *body_force;
+  double *marker_xy;
+  double *marker_uv;
+  double *centres;
+} btdf_gradients;
+size_t btdf_adjoint_workspace_bytes(btdf_t *h, int64_t n_steps, int64_t checkpoint_every);
+int btdf_adjoint(btdf_t *h, int64_t n_steps, int64_t checkpoint_every, const double *hist_bar,
+                 btdf_gradients *grads, void *work, size_t work_bytes, double *ms);
 
 /* Boundary-thickness calibration on the host (no device), Section 2.3:
  * A_ij = (1/dh^2) sum_k phi_ik phi_kj dh ds (eq 22) over the stencil nodes

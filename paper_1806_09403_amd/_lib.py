@@ -55,6 +55,12 @@ _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
 
 # name -> (restype, argtypes)
+class btdf_gradients(ctypes.Structure):
+    _fields_ = [("populations", ctypes.POINTER(ctypes.c_double)), ("inflow", ctypes.POINTER(ctypes.c_double)),
+                ("body_force", ctypes.POINTER(ctypes.c_double)), ("marker_xy", ctypes.POINTER(ctypes.c_double)),
+                ("marker_uv", ctypes.POINTER(ctypes.c_double)), ("centres", ctypes.POINTER(ctypes.c_double))]
+
+
 SIGNATURES = {
     "btdf_last_error": (ctypes.c_char_p, []),
     "btdf_create": (ctypes.c_int, [ctypes.POINTER(btdf_grid), ctypes.c_double, ctypes.c_int,
@@ -100,6 +106,9 @@ SIGNATURES = {
     "btdf_batch_set_option": (ctypes.c_int, [_vp, ctypes.c_int, _i64]),
     "btdf_batch_get_option": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_i64)]),
     "btdf_batch_autotune": (ctypes.c_int, [_vp, _i64, ctypes.POINTER(ctypes.c_int)]),
+    "btdf_adjoint_workspace_bytes": (ctypes.c_size_t, [_vp, _i64, _i64]),
+    "btdf_adjoint": (ctypes.c_int, [_vp, _i64, _i64, _dp, ctypes.POINTER(btdf_gradients), _vp, ctypes.c_size_t,
+                                    _dp]),
 }
 
 _lib = None

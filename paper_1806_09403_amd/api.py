@@ -9,7 +9,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import btdf_grid, check, dptr, f64, load
+from ._lib import btdf_gradients, btdf_grid, check, dptr, f64, load
 
 
 def btdf_create(nx, ny, tau, delta_kind, thickening, bc=(0, 0, 0, 0), inflow=(0.0, 0.0),
@@ -259,3 +259,25 @@ def btdf_batch_autotune(b, steps_per_trial):
     v = ctypes.c_int(-1)
     check(load().btdf_batch_autotune(b, int(steps_per_trial), ctypes.byref(v)))
     return v.value
+
+
+def btdf_adjoint_workspace_bytes(h, n_steps, checkpoint_every=0):
+    return int(load().btdf_adjoint_workspace_bytes(h, int(n_steps), int(checkpoint_every)))
+
+
+def btdf_adjoint(h, nx, ny, n_steps, hist_bar, checkpoint_every=0, work=None, work_bytes=0):
+    """Returns (gradients dict, (ms forward, ms recompute, ms reverse))."""
+    nb, nm, _ = btdf_counts(h)
+    hb = None
+    if nb:
+        hb = f64(hist_bar, (int(n_steps), nb, 3))
+    out = dict(populations=np.empty((9, ny, nx)), inflow=np.empty(2), body_force=np.empty(2),
+               marker_xy=np.empty((max(nm, 1), 2)), marker_uv=np.empty((max(nm, 1), 2)),
+               centres=np.empty((max(nb, 1), 2)))
+    g = btdf_gradients(**{k: dptr(v) for k, v in out.items()})
+    ms = np.zeros(3)
+    check(load().btdf_adjoint(h, int(n_steps), int(checkpoint_every), dptr(hb), ctypes.byref(g), work,
+                              int(work_bytes), dptr(ms)))
+    out["marker_xy"], out["marker_uv"], out["centres"] = out["marker_xy"][:nm], out["marker_uv"][:nm], \
+        out["centres"][:nb]
+    return out, tuple(ms)

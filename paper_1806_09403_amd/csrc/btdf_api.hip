@@ -73,6 +73,44 @@ void marker_range(int kind, double X, int *lo, int *hi) {
 
 int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
 
+// bin every marker into each tile (tx x ty nodes, ntx x nty tiles) its
+// stencil touches: off[t] .. off[t+1] index ascending marker ids in list
+void bin_markers(const btdf_t *h, int tx, int ty, int ntx, int nty, std::vector<int> &off,
+                 std::vector<int> &list) {
+  const int ntiles = ntx * nty;
+  std::vector<int> cnt(ntiles + 1, 0);
+  std::vector<int> touched;
+  touched.reserve(16);
+  auto tiles_of = [&](int l) {
+    touched.clear();
+    int xlo, xhi, ylo, yhi;
+    marker_range(h->kind, h->X[l], &xlo, &xhi);
+    marker_range(h->kind, h->Y[l], &ylo, &yhi);
+    for (int j = ylo; j <= yhi; ++j) {
+      int jj = h->yper() ? ((j % h->ny) + h->ny) % h->ny : j;
+      if (jj < 0 || jj >= h->ny) continue;
+      for (int i = xlo; i <= xhi; ++i) {
+        int ii = h->xper() ? ((i % h->nx) + h->nx) % h->nx : i;
+        if (ii < 0 || ii >= h->nx) continue;
+        int t = floordiv(jj, ty) * ntx + floordiv(ii, tx);
+        if (std::find(touched.begin(), touched.end(), t) == touched.end()) touched.push_back(t);
+      }
+    }
+  };
+  for (int l = 0; l < h->nm(); ++l) {
+    tiles_of(l);
+    for (int t : touched) cnt[t + 1]++;
+  }
+  off.assign(ntiles + 1, 0);
+  for (int t = 0; t < ntiles; ++t) off[t + 1] = off[t] + cnt[t + 1];
+  list.assign(std::max(1, off[ntiles]), 0);
+  std::vector<int> fill(off.begin(), off.end() - 1);
+  for (int l = 0; l < h->nm(); ++l) {
+    tiles_of(l);
+    for (int t : touched) list[fill[t]++] = l;
+  }
+}
+
 void compute_layout(btdf_t *h) {
   const size_t elt = (size_t)h->prec;
   const int a = h->row_align > 0 ? std::max(1, h->row_align / (int)elt) : 1;
@@ -89,38 +127,7 @@ void compute_layout(btdf_t *h) {
   h->nty = (h->ny + h->tile_y - 1) / h->tile_y;
   const int ntiles = h->ntx * h->nty;
 
-  // bin every marker into each tile its stencil touches (ascending marker ids per tile)
-  std::vector<int> cnt(ntiles + 1, 0);
-  std::vector<int> touched;
-  touched.reserve(16);
-  auto tiles_of = [&](int l) {
-    touched.clear();
-    int xlo, xhi, ylo, yhi;
-    marker_range(h->kind, h->X[l], &xlo, &xhi);
-    marker_range(h->kind, h->Y[l], &ylo, &yhi);
-    for (int j = ylo; j <= yhi; ++j) {
-      int jj = h->yper() ? ((j % h->ny) + h->ny) % h->ny : j;
-      if (jj < 0 || jj >= h->ny) continue;
-      for (int i = xlo; i <= xhi; ++i) {
-        int ii = h->xper() ? ((i % h->nx) + h->nx) % h->nx : i;
-        if (ii < 0 || ii >= h->nx) continue;
-        int t = floordiv(jj, h->tile_y) * h->ntx + floordiv(ii, h->tile_x);
-        if (std::find(touched.begin(), touched.end(), t) == touched.end()) touched.push_back(t);
-      }
-    }
-  };
-  for (int l = 0; l < h->nm(); ++l) {
-    tiles_of(l);
-    for (int t : touched) cnt[t + 1]++;
-  }
-  h->tile_off.assign(ntiles + 1, 0);
-  for (int t = 0; t < ntiles; ++t) h->tile_off[t + 1] = h->tile_off[t] + cnt[t + 1];
-  h->tile_list.assign(std::max(1, h->tile_off[ntiles]), 0);
-  std::vector<int> fill(h->tile_off.begin(), h->tile_off.end() - 1);
-  for (int l = 0; l < h->nm(); ++l) {
-    tiles_of(l);
-    for (int t : touched) h->tile_list[fill[t]++] = l;
-  }
+  bin_markers(h, h->tile_x, h->tile_y, h->ntx, h->nty, h->tile_off, h->tile_list);
   h->tile_map.clear();
   h->tile_map.reserve(ntiles);
   for (int t = 0; t < ntiles; ++t)
@@ -187,6 +194,8 @@ LbmParams make_params(const btdf_t *h) {
   p.Gy = h->G[1];
   p.uin_x = h->uin[0];
   p.uin_y = h->uin[1];
+  p.urx = h->u0[0];  // the stored deviations are taken from feq(1, initial velocity)
+  p.ury = h->u0[1];
   p.ntx = h->ntx;
   p.nty = h->nty;
   p.xcd_remap = h->xcd_remap;
@@ -348,10 +357,6 @@ int clear_flag(btdf_t *h) {
 }
 
 // events around the kernels of one step, for btdf_step_timed
-struct StepEvents {
-  hipEvent_t ib0, ib1, a0, a1, b0, b1;
-};
-
 bool overlapping(const btdf_t *h) { return h->overlap && h->nb() > 0 && h->n_free > 0 && h->n_forced > 0; }
 
 int make_side(btdf_t *h) {
@@ -907,6 +912,8 @@ int btdf_save(btdf_t *h, void *dst, size_t bytes) {
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(h->stream));
   uint64_t hdr[8] = {kStateMagic, (uint64_t)h->prec, (uint64_t)h->nx, (uint64_t)h->ny, (uint64_t)h->steps, 0, 0, 0};
+  std::memcpy(&hdr[5], &h->u0[0], 8);  // the reference state of the stored deviations
+  std::memcpy(&hdr[6], &h->u0[1], 8);
   std::memcpy(dst, hdr, 64);
   const size_t row = (size_t)h->nx * h->prec;
   for (int q = 0; q < 9; ++q)
@@ -921,8 +928,12 @@ int btdf_load(btdf_t *h, const void *src, size_t bytes) {
   if (bytes < btdf_state_bytes(h)) return fail(BTDF_EINVAL, "buffer of %zu bytes < %zu", bytes, btdf_state_bytes(h));
   uint64_t hdr[8];
   std::memcpy(hdr, src, 64);
-  if (hdr[0] != kStateMagic || hdr[1] != (uint64_t)h->prec || hdr[2] != (uint64_t)h->nx || hdr[3] != (uint64_t)h->ny)
-    return fail(BTDF_EINVAL, "state does not match this handle");
+  uint64_t r0, r1;
+  std::memcpy(&r0, &h->u0[0], 8);
+  std::memcpy(&r1, &h->u0[1], 8);
+  if (hdr[0] != kStateMagic || hdr[1] != (uint64_t)h->prec || hdr[2] != (uint64_t)h->nx || hdr[3] != (uint64_t)h->ny ||
+      hdr[5] != r0 || hdr[6] != r1)
+    return fail(BTDF_EINVAL, "state does not match this handle (size, precision or initial velocity)");
   int rc = ensure_device(h);
   if (rc) return rc;
   const size_t row = (size_t)h->nx * h->prec;

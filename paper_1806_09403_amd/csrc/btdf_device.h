@@ -24,6 +24,16 @@ __host__ __device__ __forceinline__ constexpr int opp(int q) {
   return q == 0 ? 0 : (q < 5 ? ((q + 1) % 4) + 1 : ((q - 3) % 4) + 5);
 }
 
+// Populations are stored as deviations f_q - c_q from the equilibrium of a
+// reference state, c_q = feq_q(1, u_ref) (eq 6), with u_ref the velocity the
+// run starts from. sum_q c_q = 1 and sum_q e_q c_q = u_ref, so the stored
+// values sum to rho - 1 and their first moment is m - u_ref: in a flow near
+// its reference state every stored value, and every rounding error, is small.
+__host__ __device__ __forceinline__ double ref_c(int q, double urx, double ury) {
+  const double eu = ex(q) * urx + ey(q) * ury;
+  return wq(q) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * (urx * urx + ury * ury));
+}
+
 // ---- delta kinds (same codes as the public header)
 enum : int { kLinear2 = 2, kRoma3 = 3, kPeskin4 = 4, kCos4 = 5 };
 
@@ -43,6 +53,27 @@ __device__ __forceinline__ double phi(int kind, double r) {
   }
   // kCos4
   return a <= 2.0 ? 0.25 * (1.0 + cospi(0.5 * a)) : 0.0;
+}
+
+// d phi / d r of the same kernels (the adjoint's position derivatives; LINEAR2
+// takes -sign(r) away from its kink at r = 0)
+__device__ __forceinline__ double dphi(int kind, double r) {
+  const double a = fabs(r), sg = r < 0.0 ? -1.0 : 1.0;
+  if (kind == kLinear2) return a < 1.0 ? -sg : 0.0;
+  if (kind == kRoma3) {
+    if (a <= 0.5) return sg * (-a / sqrt(1.0 - 3.0 * a * a));
+    if (a < 1.5) {
+      const double b = 1.0 - a;
+      return sg * (-3.0 - 3.0 * b / sqrt(fmax(1e-300, 1.0 - 3.0 * b * b))) * (1.0 / 6.0);
+    }
+    return 0.0;
+  }
+  if (kind == kPeskin4) {
+    if (a < 1.0) return sg * (-2.0 + (2.0 - 4.0 * a) / sqrt(1.0 + 4.0 * a - 4.0 * a * a)) * 0.125;
+    if (a < 2.0) return sg * (-2.0 - (6.0 - 4.0 * a) / sqrt(fmax(1e-300, -7.0 + 12.0 * a - 4.0 * a * a))) * 0.125;
+    return 0.0;
+  }
+  return a <= 2.0 ? -sg * (0.125 * M_PI) * sinpi(0.5 * a) : 0.0;
 }
 
 // stencil nodes per direction: floor(X) .. +1 (2-point), floor(X+1/2)-1 .. +1
@@ -68,6 +99,7 @@ struct LbmParams {
   double guo;       // 1 - 1 / (2 tau)
   double Gx, Gy;    // uniform body-force density
   double uin_x, uin_y;
+  double urx, ury;  // reference velocity: populations are stored as f_q - feq_q(1, u_ref)
   // tiles of the lattice kernel
   int ntx, nty;
   int xcd_remap;
@@ -112,6 +144,26 @@ struct CaseDesc {
   void *pop[2];
 };
 
+// the adjoint (reverse) step: its own 64 x 4 tiling of the lattice with the
+// markers binned per tile, and the per-node records of the tiles a marker
+// stencil touches ("forced" tiles)
+constexpr int kAdjTX = 64, kAdjTY = 4, kAdjRec = 5;
+struct AdjParams {
+  int ntx, nty;                     // adjoint tiles
+  const int *tile_off, *tile_list;  // markers whose stencil touches each tile, ascending
+  const int *tile_slot;             // forced slot of each tile, -1 when no stencil touches it
+  const int *forced;                // tile of each forced slot
+  int nforced;
+  double *rec;   // [nforced][kAdjTX * kAdjTY][5]: dJ/df (x, y), rho, u*_x, u*_y at the node
+  double *part;  // [tiles][4]: dJ/dG (x, y), dJ/du_in (x, y), summed over steps per tile
+  // marker side (one entry per marker)
+  const double *Fx, *Fy, *rho_l, *ux_l, *uy_l;  // forward values of the step being reversed
+  double *mk_adj;                                // [nm][3]: dJ/d rho_l, dJ/d u*_l (x, y)
+  double *xy_bar, *uv_bar;                       // [nm][2] each, summed over steps
+  double *c_bar;                                 // [nm][2]: each marker's share of dJ/d(body centre)
+  const double *hist_bar;                        // [nb][3]: weights of this step's body forces
+};
+
 // where the workgroups of the batched launches go
 struct BatchMap {
   const int *tile_case, *tile_local;  // per lattice workgroup: case and tile within the case
@@ -122,9 +174,69 @@ struct BatchMap {
   int mask_unstable;  // skip the work of cases whose instability flag is set
 };
 
-// Streaming pull g_q(x, y) = f_q(x - e_q, y - e_q) with the boundary readings:
-// periodic directions wrap, halfway bounce-back walls in y return the
-// opposite population of the same node; channel ends read the ghost columns.
+// ---- arithmetic shared by the forward and adjoint kernels
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T recip(T x);
+// FP32: the hardware reciprocal refined by one Newton step. The bare
+// reciprocal is within an ulp but not unbiased; used for u = (m + f/2) / rho
+// every step, its bias acts like a small body force and shifts long runs.
+template <>
+__device__ __forceinline__ float recip<float>(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+template <>
+__device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
+
+// Corrected velocity (eq 11), equilibrium (eq 6), Guo term (eq 7) and BGK
+// relaxation (eq 5) on the stored deviations g~_q = g_q - c_q of one node:
+//   out~_q = (1 - omega) g~_q + omega (feq_q - c_q) + F_q.
+// With drho = rho - 1, du = u - u_ref (both formed from small terms only),
+// eu = e.u, ea = e.du, eb = e.(u + u_ref) and ef = e.f, opposite directions
+// share the even part and differ in the sign of the odd part:
+//   even = w (C + 4.5 omega (drho eu^2 + ea eb) + 9 guo eu ef)
+//   odd  = 3 w (omega (drho eu + ea) + guo ef)
+//   C    = omega (drho (1 - 1.5 |u|^2) - 1.5 du.(u + u_ref)) - 3 guo u.f
+// (with u_ref = 0 this is omega feq~ + F of the plain deviations f - w).
+template <typename T>
+__device__ __forceinline__ void collide(const T g[9], T ftx, T fty, T omega, T guo, T urx, T ury, T out[9],
+                                        T &rho) {
+  T drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+  rho = (T)1 + drho;
+  const T mx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);  // m - u_ref
+  const T my = (g[2] - g[4]) + (g[5] - g[8]) + (g[6] - g[7]);
+  const T inv = recip<T>(rho);
+  const T dux = (mx + (T)0.5 * ftx - drho * urx) * inv;
+  const T duy = (my + (T)0.5 * fty - drho * ury) * inv;
+  const T ux = urx + dux, uy = ury + duy;
+  const T sx = ux + urx, sy = uy + ury;
+  const T C = omega * (drho * ((T)1 - (T)1.5 * (ux * ux + uy * uy)) - (T)1.5 * (dux * sx + duy * sy)) -
+              (T)3 * guo * (ux * ftx + uy * fty);
+  const T K1 = (T)4.5 * omega, K2 = (T)9 * guo;
+  const T omc = (T)1 - omega;
+  out[0] = omc * g[0] + (T)(4.0 / 9.0) * C;
+  auto pair = [&](int qp, int qm, T eu, T ea, T eb, T ef, T w) {
+    const T even = w * (C + K1 * (drho * eu * eu + ea * eb) + K2 * eu * ef);
+    const T odd = (T)3 * w * (omega * (drho * eu + ea) + guo * ef);
+    out[qp] = omc * g[qp] + even + odd;
+    out[qm] = omc * g[qm] + even - odd;
+  };
+  pair(1, 3, ux, dux, sx, ftx, (T)(1.0 / 9.0));
+  pair(2, 4, uy, duy, sy, fty, (T)(1.0 / 9.0));
+  pair(5, 7, ux + uy, dux + duy, sx + sy, ftx + fty, (T)(1.0 / 36.0));
+  pair(6, 8, uy - ux, duy - dux, sy - sx, fty - ftx, (T)(1.0 / 36.0));
+}
+
+// Streaming pull g_q(x, y) = f_q(x - e_q, y - e_q), as a stored deviation,
+// with the boundary readings: periodic directions wrap, halfway bounce-back
+// walls in y return the opposite population of the same node; channel ends
+// read the ghost columns.
 template <typename T, bool NTL = false>
 __device__ __forceinline__ T load(const T *ptr) {
   if (NTL) return __builtin_nontemporal_load(ptr);
@@ -138,7 +250,9 @@ __device__ __forceinline__ T pull(const T *__restrict__ A, const LbmParams &p, i
   if (p.yper) {
     sy = sy < 0 ? sy + p.ny : (sy >= p.ny ? sy - p.ny : sy);
   } else if (sy < 0 || sy >= p.ny) {
-    return load<T, NTL>(&A[(long long)opp(q) * p.plane + (long long)y * p.pitch + x]);
+    // the stored opposite population, moved from its offset c_opp to c_q
+    return load<T, NTL>(&A[(long long)opp(q) * p.plane + (long long)y * p.pitch + x]) +
+           (T)(-6.0 * wq(q) * (ex(q) * p.urx + ey(q) * p.ury));
   }
   if (p.xper) sx = sx < 0 ? sx + p.nx : (sx >= p.nx ? sx - p.nx : sx);
   return load<T, NTL>(&A[(long long)q * p.plane + (long long)sy * p.pitch + sx]);

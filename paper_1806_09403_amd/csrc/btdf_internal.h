@@ -89,6 +89,7 @@ inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 bool valid_kind(int k);
 void drop_graph(btdf_t *h);
 void compute_layout(btdf_t *h);
+void bin_markers(const btdf_t *h, int tx, int ty, int ntx, int nty, std::vector<int> &off, std::vector<int> &list);
 LbmParams make_params(const btdf_t *h);
 IbParams make_ib(const btdf_t *h);
 int ensure_device(btdf_t *h);
@@ -98,6 +99,13 @@ int bind_impl(btdf_t *h, void *dev, size_t bytes);
 int add_body_impl(btdf_t *h, int n, const double *xy, const double *uv, double cx, double cy, double ds,
                   int *body_id);
 int destroy_impl(btdf_t *h);
+// HIP events around the kernels of one step (timed stepping)
+struct StepEvents {
+  hipEvent_t ib0, ib1, a0, a1, b0, b1;
+};
+// one step from population buffer src into the other, on stream s
+int enqueue_step(btdf_t *h, const LbmParams &p, const IbParams &ib, int src, hipStream_t s,
+                 const StepEvents *te);
 
 }  // namespace host
 }  // namespace btdf

@@ -1,33 +1,31 @@
 // btdf_kernels.hip -- gfx950 kernels of one BTDF-IB-LBM time step.
 //
-//   ib_kernel   one workgroup per body: interpolation of rho and the
-//               unforced velocity u* to the markers (eqs 12, 14) from the
-//               streamed populations at the stencil nodes (eqs 9-10, u*
-//               including G/2), the direct force F_l = 2 rho_l (U_b - u*_l)
-//               (eq 20), and the per-body sums of eq 27 (force and torque)
-//               by wavefront shuffles, written to the history ring.
+//   ib_kernel   16 lanes per marker, one per stencil node: interpolation of
+//               rho and the unforced velocity u* to the markers (eqs 12, 14)
+//               from the streamed populations at the stencil nodes (eqs 9-10,
+//               u* including G/2) and the direct force F_l = 2 rho_l
+//               (U_b - u*_l) (eq 20); the weights and drs ds F_l are left
+//               for the lattice kernel.
 //   lbm_kernel  one thread per node (NPT nodes per thread along x): the
 //               streaming pull, moments, the spread force of the markers
 //               whose stencils touch the tile (eqs 13, 15, gathered from the
 //               tile's marker list in LDS -- no atomics, fixed summation
 //               order), the corrected velocity (eq 11), equilibrium (eq 6),
 //               Guo term (eq 7) and BGK collision (eq 5), and the channel
-//               ghost columns.
+//               ghost columns; extra workgroups form the per-body force and
+//               torque sums of eq 27 into the history ring.
 //
-// Populations are stored as deviations f~_q = f_q - w_q (rho0 = 1) in
-// structure-of-arrays planes [q][y][pitch]; sums of deviations keep the
-// FP32 path free of the cancellation against w_q.
+// Populations are stored as deviations f~_q = f_q - feq_q(1, u_ref) from the
+// equilibrium of the reference state the run starts from, in
+// structure-of-arrays planes [q][y][pitch]; sums of deviations keep the FP32
+// path free of the cancellation against the reference populations, and the
+// rounding of a near-reference flow small.
 #include "btdf_device.h"
 #include "btdf_launch.h"
 
 namespace btdf {
 
 // ------------------------------------------------------------------ marker kernel
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
 
 // Marker kernel: 16 lanes per marker, one per node of the (up to) 4x4
 // stencil, 16 markers per workgroup, over all markers of all bodies. Each
@@ -96,8 +94,8 @@ __device__ __forceinline__ void ib_marker(const T *__restrict__ A, const LbmPara
       const double rho = 1.0 + drho;
       const double inv = 1.0 / rho;
       wr = W * rho;
-      wu = W * ((mx + 0.5 * p.Gx) * inv);
-      wv = W * ((my + 0.5 * p.Gy) * inv);
+      wu = W * ((mx + p.urx + 0.5 * p.Gx) * inv);  // the stored values' first moment is m - u_ref
+      wv = W * ((my + p.ury + 0.5 * p.Gy) * inv);
     }
   }
 #pragma unroll
@@ -176,46 +174,6 @@ __device__ void body_reduce(const IbParams &ib, int b, int tid, double (*red)[NT
 // ------------------------------------------------------------------ lattice kernel
 constexpr int kChunk = 64;  // markers staged in LDS per pass
 
-template <typename T>
-__device__ __forceinline__ T recip(T x);
-template <>
-__device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <>
-__device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
-
-// Corrected velocity (eq 11), equilibrium (eq 6), Guo term (eq 7) and BGK
-// relaxation (eq 5) on the streamed deviations g~_q of one node:
-//   out_q = (1 - omega) g~_q + omega feq~_q + F_q.
-// Opposite directions share the even part of omega feq~ + F and differ in
-// the sign of the odd part, so each pair (q, opp q) is formed together:
-//   even = w (C + eu (4.5 omega rho eu + 9 guo ef)),  odd = 3 w (omega rho eu + guo ef),
-//   C = omega drho - 1.5 omega rho |u|^2 - 3 guo u.f,  eu = e_q.u,  ef = e_q.f.
-template <typename T>
-__device__ __forceinline__ void collide(const T g[9], T ftx, T fty, T omega, T guo, T out[9], T &rho) {
-  T drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
-  rho = (T)1 + drho;
-  const T mx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
-  const T my = (g[2] - g[4]) + (g[5] - g[8]) + (g[6] - g[7]);
-  const T inv = recip<T>(rho);
-  const T ux = (mx + (T)0.5 * ftx) * inv;
-  const T uy = (my + (T)0.5 * fty) * inv;
-  const T orho = omega * rho;
-  const T C = omega * drho - (T)1.5 * orho * (ux * ux + uy * uy) - (T)3 * guo * (ux * ftx + uy * fty);
-  const T K1 = (T)4.5 * orho, K2 = (T)9 * guo;
-  const T omc = (T)1 - omega;
-  out[0] = omc * g[0] + (T)(4.0 / 9.0) * C;
-  auto pair = [&](int qp, int qm, T eu, T ef, T w) {
-    const T even = w * (C + eu * (K1 * eu + K2 * ef));
-    const T odd = (T)3 * w * (orho * eu + guo * ef);
-    out[qp] = omc * g[qp] + even + odd;
-    out[qm] = omc * g[qm] + even - odd;
-  };
-  pair(1, 3, ux, ftx, (T)(1.0 / 9.0));
-  pair(2, 4, uy, fty, (T)(1.0 / 9.0));
-  pair(5, 7, ux + uy, ftx + fty, (T)(1.0 / 36.0));
-  pair(6, 8, uy - ux, fty - ftx, (T)(1.0 / 36.0));
-}
-
 template <typename T, bool NT>
 __device__ __forceinline__ void store(T *ptr, T v) {
   if (NT)
@@ -292,6 +250,7 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
 
   const T omega = (T)p.omega, guo = (T)p.guo;
   const T Gx = (T)p.Gx, Gy = (T)p.Gy;
+  const T urx = (T)p.urx, ury = (T)p.ury;
   bool bad = false;
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
@@ -315,7 +274,7 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
     const T ftx = forced ? (T)(p.Gx + (double)fib_x[k]) : Gx;
     const T fty = forced ? (T)(p.Gy + (double)fib_y[k]) : Gy;
     T out[9], rho;
-    collide<T>(g, ftx, fty, omega, guo, out, rho);
+    collide<T>(g, ftx, fty, omega, guo, urx, ury, out, rho);
     bad |= !(rho > (T)0) || !isfinite(rho);
     if (interior) {
 #pragma unroll
@@ -333,15 +292,14 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
       T dr = out[0];
 #pragma unroll
       for (int q = 1; q < 9; ++q) dr += out[q];
-      const T r = (T)1 + dr;
-      const T ui = (T)p.uin_x, vi = (T)p.uin_y;
-      const T uui = ui * ui + vi * vi;
+      // feq_q(1 + dr, u_in) - c_q = w (dr (1 + P_in) + P_in - P_ref), P(u) = 3 e.u + 4.5 (e.u)^2 - 1.5 |u|^2
       const long long gb = (long long)y * p.pitch;
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
-        const T eu = (T)ex(q) * ui + (T)ey(q) * vi;
-        B[(long long)q * p.plane + gb] =
-            (T)wq(q) * (dr + r * ((T)3 * eu + (T)4.5 * eu * eu - (T)1.5 * uui));
+        const double ein = ex(q) * p.uin_x + ey(q) * p.uin_y;
+        const double pin = 3.0 * ein + 4.5 * ein * ein - 1.5 * (p.uin_x * p.uin_x + p.uin_y * p.uin_y);
+        const double pref = ref_c(q, p.urx, p.ury) / wq(q) - 1.0;
+        B[(long long)q * p.plane + gb] = (T)wq(q) * (dr * (T)(1.0 + pin) + (T)(pin - pref));
       }
     }
     if (p.outlet && x == p.nx - 2) {
@@ -425,7 +383,7 @@ __global__ void init_eq_kernel(T *__restrict__ A, LbmParams p, const double *__r
     for (int q = 0; q < 9; ++q) {
       const double eu = ex(q) * u + ey(q) * v;
       const double feq = wq(q) * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-      A[(long long)q * p.plane + (long long)y * p.pitch + x] = (T)(feq - wq(q));
+      A[(long long)q * p.plane + (long long)y * p.pitch + x] = (T)(feq - ref_c(q, p.urx, p.ury));
     }
   }
 }
@@ -441,7 +399,7 @@ __global__ void init_uniform_kernel(T *__restrict__ A, LbmParams p, double r, do
     for (int q = 0; q < 9; ++q) {
       const double eu = ex(q) * u + ey(q) * v;
       const double feq = wq(q) * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-      A[(long long)q * p.plane + (long long)y * p.pitch + x] = (T)(feq - wq(q));
+      A[(long long)q * p.plane + (long long)y * p.pitch + x] = (T)(feq - ref_c(q, p.urx, p.ury));
     }
   }
 }
@@ -453,7 +411,7 @@ __global__ void plane_to_f64_kernel(const T *__restrict__ A, LbmParams p, int q,
   for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
        k += (long long)gridDim.x * blockDim.x) {
     const int y = (int)(k / p.nx), x = (int)(k - (long long)y * p.nx);
-    out[k] = (double)A[(long long)q * p.plane + (long long)y * p.pitch + x] + wq(q);
+    out[k] = (double)A[(long long)q * p.plane + (long long)y * p.pitch + x] + ref_c(q, p.urx, p.ury);
   }
 }
 
@@ -463,7 +421,7 @@ __global__ void f64_to_plane_kernel(T *__restrict__ A, LbmParams p, int q, const
   for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
        k += (long long)gridDim.x * blockDim.x) {
     const int y = (int)(k / p.nx), x = (int)(k - (long long)y * p.nx);
-    A[(long long)q * p.plane + (long long)y * p.pitch + x] = (T)(in[k] - wq(q));
+    A[(long long)q * p.plane + (long long)y * p.pitch + x] = (T)(in[k] - ref_c(q, p.urx, p.ury));
   }
 }
 
@@ -486,6 +444,8 @@ __global__ void macro_kernel(const T *__restrict__ A, LbmParams p, double *__res
       my += ey(q) * g;
     }
     const double r = 1.0 + dr;
+    mx += p.urx;  // the stored values' first moment is m - u_ref
+    my += p.ury;
     rho[k] = r;
     ux[k] = fluid ? (mx + 0.5 * p.Gx) / r : mx / r;
     uy[k] = fluid ? (my + 0.5 * p.Gy) / r : my / r;

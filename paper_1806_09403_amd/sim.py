@@ -116,6 +116,21 @@ class Sim:
     def autotune(self, steps_per_trial=20):
         return api.btdf_autotune(self._workspace(), steps_per_trial)
 
+    def adjoint(self, n_steps, hist_bar, checkpoint_every=0):
+        """Take n_steps (as step(n_steps) would) and return the gradients of
+        J = sum(hist_bar * force history of these steps) and the timings
+        (ms of the forward run, the recomputation and the reverse steps).
+        The adjoint's device memory is a torch tensor, freed on return."""
+        import torch
+        h = self._workspace()
+        nbytes = api.btdf_adjoint_workspace_bytes(h, n_steps, checkpoint_every)
+        work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        try:
+            return api.btdf_adjoint(h, self.nx, self.ny, n_steps, hist_bar, checkpoint_every,
+                                    work.data_ptr(), work.numel())
+        finally:
+            del work
+
 
 class _CaseView(Sim):
     """A case of a BatchSim: every state call of Sim, on the batch's memory."""

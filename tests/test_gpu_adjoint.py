@@ -1,0 +1,197 @@
+"""GPU reverse mode (btdf_adjoint) through the C ABI.
+
+FP64: every gradient equals the FP64 oracle's adjoint on small cases of
+every boundary kind and delta (the oracle's adjoint is itself pinned to
+central differences of its forward step). Checkpointed and taped sweeps are
+bit-identical, and the forward run inside btdf_adjoint leaves exactly the
+state and history plain stepping leaves. On the 800x400 Re = 100 channel
+(126 markers, 5000 steps) the FP32 adjoint's gradient of the mean drag
+coefficient with respect to the inflow speed, the cylinder centre and
+marker velocities agrees with FP64 central differences of the GPU forward
+run (h = 1e-4).
+"""
+import numpy as np
+import pytest
+
+import btdf_workloads as W
+from oracle.oracle import OracleSim
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def oracle_of(c):
+    o = OracleSim(c.nx, c.ny, c.bc, c.tau, c.kind, c.thickening, c.G, c.inflow, c.init)
+    for b in c.bodies:
+        o.add_body(b.xy, b.uv, b.cx, b.cy, b.ds)
+    if c.init_uy is not None:
+        ux, uy = c.init_fields()
+        o.init_equilibrium(ux, uy, np.full((c.ny, c.nx), c.init[0]))
+    return o
+
+
+def gpu_of(c, precision):
+    from paper_1806_09403_amd import Sim
+    return Sim.from_case(c, precision=precision)
+
+
+CASES = [
+    # (seed, nx, ny, kind, bc, n_bodies, n_steps)
+    (1, 24, 20, W.COS4, W.FULLY_PERIODIC, 2, 6),
+    (2, 18, 16, W.ROMA3, W.CHANNEL, 1, 10),
+    (3, 26, 20, W.PESKIN4, (W.PERIODIC, W.PERIODIC, W.BOUNCEBACK_WALL, W.BOUNCEBACK_WALL), 2, 5),
+    (4, 18, 17, W.COS4, (W.VELOCITY_INLET, W.ZERO_GRADIENT_OUTLET, W.BOUNCEBACK_WALL, W.BOUNCEBACK_WALL), 1, 10),
+    (5, 25, 19, W.LINEAR2, W.FULLY_PERIODIC, 2, 4),
+    (8, 150, 70, W.COS4, W.FULLY_PERIODIC, 3, 7),  # several adjoint tiles, ragged edges, bodies across the periodic edges
+]
+KEYS = [("populations", "populations"), ("inflow", "inflow"), ("body_force", "body_force"),
+        ("marker_xy", "xy"), ("marker_uv", "uv"), ("centres", "centres")]
+
+
+def small_case(seed, nx, ny, kind, bc, nbody):
+    c = W.random_case(seed, nx=nx, ny=ny, kind=kind, bc=bc, n_bodies=nbody, D_range=(4.0, 6.0))
+    if bc[0] == W.VELOCITY_INLET:
+        c.inflow = (0.03, 0.004)
+    return c
+
+
+@pytest.mark.parametrize("seed,nx,ny,kind,bc,nbody,n", CASES)
+def test_fp64_adjoint_matches_oracle(seed, nx, ny, kind, bc, nbody, n):
+    log("fp64 adjoint vs oracle seed=%d %dx%d kind=%d" % (seed, nx, ny, kind))
+    c = small_case(seed, nx, ny, kind, bc, nbody)
+    hbar = np.random.default_rng(200 + seed).standard_normal((n, nbody, 3))
+    go = oracle_of(c).adjoint(n, hbar)
+    s = gpu_of(c, 8)
+    gg, ms = s.adjoint(n, hbar, checkpoint_every=0)
+    for gk, ok in KEYS:
+        ref, got = go[ok], gg[gk]
+        scale = max(np.max(np.abs(ref)), 1e-300) if ref.size else 1.0
+        assert got.shape == ref.shape, gk
+        assert np.max(np.abs(got - ref), initial=0.0) <= 1e-11 * scale + 1e-300, (gk, np.max(np.abs(got - ref)), scale)
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_checkpointing_is_bit_identical_and_leaves_the_forward_state(precision):
+    c = small_case(8, 150, 70, W.COS4, W.FULLY_PERIODIC, 3)
+    n = 23
+    hbar = np.random.default_rng(9).standard_normal((n, 3, 3))
+    ref = gpu_of(c, precision)
+    ref.step(n)
+    f_ref, h_ref = ref.populations(), ref.force_history(n)
+    results = []
+    for K in (0, 1, 4, 7, n, 10 * n):
+        s = gpu_of(c, precision)
+        g, _ = s.adjoint(n, hbar, checkpoint_every=K)
+        assert np.array_equal(s.populations(), f_ref), K
+        assert np.array_equal(s.force_history(n), h_ref), K
+        results.append(g)
+    for g in results[1:]:
+        for k in g:
+            assert np.array_equal(g[k], results[0][k]), k
+
+
+def test_fp32_adjoint_close_to_fp64():
+    c = small_case(8, 150, 70, W.COS4, W.FULLY_PERIODIC, 3)
+    n = 15
+    hbar = np.random.default_rng(10).standard_normal((n, 3, 3))
+    g64, _ = gpu_of(c, 8).adjoint(n, hbar)
+    g32, _ = gpu_of(c, 4).adjoint(n, hbar)
+    for k in ("marker_uv", "marker_xy", "body_force", "centres"):
+        scale = np.max(np.abs(g64[k]))
+        assert np.max(np.abs(g32[k] - g64[k])) <= 2e-4 * scale, k
+
+
+def c5_J(U, dx=0.0, dy=0.0, uv=None, precision=8, steps=5000):
+    """Mean drag coefficient of the 800x400 channel over `steps` steps, with
+    inflow and initial flow U, the cylinder moved by (dx, dy)."""
+    from paper_1806_09403_amd import Sim
+    c = W.c5(steps=steps, precision=precision)
+    b = c.bodies[0]
+    s = Sim(c.nx, c.ny, c.tau, c.kind, c.thickening, c.bc, (U, 0.0), c.G, (1.0, U, 0.0), precision,
+            history_capacity=steps)
+    s.add_body(b.xy + np.array([dx, dy]), b.uv if uv is None else uv, b.cx + dx, b.cy + dy, b.ds)
+    s.step(steps)
+    h = s.force_history(steps)
+    s.close()
+    return float(np.mean(2.0 * h[:, 0, 0] / (U * U * c.D)))
+
+
+def feq_dU(U, nx, ny):
+    """d/dU of the initial populations feq_q(1, (U, 0)) at every node."""
+    ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], float)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    d = w * (3.0 * ex + 9.0 * ex * ex * U - 3.0 * U)
+    return np.broadcast_to(d[:, None, None], (9, ny, nx))
+
+
+def c5_adjoint(precision, n, K=0):
+    from paper_1806_09403_amd import Sim
+    c = W.c5(precision=precision)
+    U, D = c.U, c.D
+    b = c.bodies[0]
+    s = Sim(c.nx, c.ny, c.tau, c.kind, c.thickening, c.bc, (U, 0.0), c.G, (1.0, U, 0.0), precision,
+            history_capacity=n)
+    s.add_body(b.xy, b.uv, b.cx, b.cy, b.ds)
+    hbar = np.zeros((n, 1, 3))
+    hbar[:, 0, 0] = 2.0 / (U * U * D) / n
+    g, ms = s.adjoint(n, hbar, checkpoint_every=K)
+    hist = s.force_history(n)
+    J = float(np.mean(2.0 * hist[:, 0, 0] / (U * U * D)))
+    # dJ/dU: through the inlet and the initial state feq(1, U) (the flow's
+    # response), plus the explicit -2 J / U of the coefficient's 1/U^2
+    dU_flow = g["inflow"][0] + float(np.sum(g["populations"] * feq_dU(U, c.nx, c.ny)))
+    dU = dU_flow - 2.0 * J / U
+    dx = float(np.sum(g["marker_xy"][:, 0]) + g["centres"][0, 0])
+    dy = float(np.sum(g["marker_xy"][:, 1]) + g["centres"][0, 1])
+    log("  precision %d: J = %.8f dJ/dU %.8e (flow part %.8e) dJ/dx %.8e dJ/dy %.3e; "
+        "ms fwd %.1f recompute %.1f reverse %.1f" % (precision, J, dU, dU_flow, dx, dy, *ms))
+    s.close()
+    return dict(J=J, dU=dU, dU_flow=dU_flow, dx=dx, dy=dy, xy=g["marker_xy"], cx=g["centres"][0, 0],
+                uv=g["marker_uv"])
+
+
+@pytest.mark.slow
+def test_c5_gradients_match_fp64_central_differences():
+    """FP64 adjoint: every gradient within 1e-4 relative of FP64 central
+    differences (h = 1e-4). FP32 adjoint: the same, with each bound scaled by
+    the size of the terms the quantity is summed from -- the FP32 forward run
+    itself carries a relative error of ~1e-4 on J here (the impulsive start
+    drives a large acoustic transient whose rounding the mean drag
+    inherits), which enters dJ/dU through the explicit -2 J / U, and dJ/dx_c
+    is a sum of per-marker terms that cancel to ~1e-3 of their size."""
+    c = W.c5()
+    U, n, h = c.U, 5000, 1e-4
+    log("c5 adjoint: 800x400, 126 markers, %d steps, sqrt(N) checkpoints" % n)
+    a64 = c5_adjoint(8, n)
+    a32 = c5_adjoint(4, n)
+    fdU = (c5_J(U + h) - c5_J(U - h)) / (2 * h)
+    fdx = (c5_J(U, dx=h) - c5_J(U, dx=-h)) / (2 * h)
+    fdy = (c5_J(U, dy=h) - c5_J(U, dy=-h)) / (2 * h)
+    log("  FD: dJ/dU %.8e dJ/dx %.8e dJ/dy %.3e" % (fdU, fdx, fdy))
+    tol = 1e-4
+    # FP64
+    assert abs(a64["dU"] - fdU) <= tol * abs(fdU)
+    assert abs(a64["dx"] - fdx) <= tol * abs(fdx)
+    assert abs(a64["dy"] - fdy) <= tol * abs(fdx)  # symmetric: both ~0
+    # FP32, against the sizes of the summed terms
+    assert abs(a32["dU"] - fdU) <= tol * (abs(a32["dU_flow"]) + 2.0 * a32["J"] / U)
+    xscale = float(np.sum(np.abs(a64["xy"][:, 0])) + abs(a64["cx"]))
+    assert abs(a32["dx"] - fdx) <= tol * xscale
+    assert abs(a32["dy"] - fdy) <= tol * xscale
+    # the response parts of FP32 and FP64 agree marker by marker
+    assert abs(a32["dU_flow"] - a64["dU_flow"]) <= tol * abs(a64["dU_flow"])
+    assert np.max(np.abs(a32["xy"] - a64["xy"])) <= tol * np.max(np.abs(a64["xy"]))
+    assert np.max(np.abs(a32["uv"] - a64["uv"])) <= tol * np.max(np.abs(a64["uv"]))
+    nm = c.bodies[0].xy.shape[0]
+    floor = 1e-3 * np.max(np.abs(a64["uv"]))
+    for l in (0, 31, 70):
+        for comp in (0, 1):
+            uv = np.zeros((nm, 2))
+            uv[l, comp] = h
+            fd = (c5_J(U, uv=uv) - c5_J(U, uv=-uv)) / (2 * h)
+            log("  dJ/dU_b[%d,%d] FP64 %.8e FP32 %.8e FD %.8e" % (l, comp, a64["uv"][l, comp], a32["uv"][l, comp], fd))
+            assert abs(a64["uv"][l, comp] - fd) <= tol * max(abs(fd), floor)
+            assert abs(a32["uv"][l, comp] - fd) <= tol * max(abs(fd), floor)
