@@ -11,8 +11,8 @@ Prints one JSON line: MLUPS (whole job), ms per step, the roofline of the
 lattice kernel (72 algorithmic bytes per lattice update against 8 TB/s,
 timed with HIP events on the library's stream over the timed region), the
 batched mode on 256 uneven channel cases beside the same cases run one
-after another, and the FP64 CPU oracle timed on a bounded sample of the
-same workload.
+after another, the cost of the adjoint sweep beside the forward run, and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -51,6 +51,9 @@ def parse():
     p.add_argument("--seq-steps", type=int, default=200,
                    help="steps per case when timing the sequential single-case runs (0: skip them)")
     p.add_argument("--cpu-budget-s", type=float, default=20.0)
+    p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint figures")
+    p.add_argument("--only-adjoint", action="store_true", help="print the adjoint figures alone")
+    p.add_argument("--adjoint-steps", type=int, default=5000)
     return p.parse_args()
 
 
@@ -173,6 +176,60 @@ def bench_batched(args):
                          "kernel": "lbm_batch_kernel"}}
 
 
+def bench_adjoint(args):
+    """Cost of the reverse sweep on the 800x400 Re = 100 channel (126
+    markers, FP32): gradient of the mean drag coefficient over the horizon,
+    with sqrt(N) checkpoints and with a full tape, against the forward run
+    alone (replayed from graphs of 50 steps, its fastest form)."""
+    import numpy as np
+    import torch
+    import btdf_workloads as W
+    from paper_1806_09403_amd import Sim, _lib
+
+    c = W.c5(precision=4)
+    n = args.adjoint_steps
+    b = c.bodies[0]
+
+    def make():
+        s = Sim(c.nx, c.ny, c.tau, c.kind, c.thickening, c.bc, c.inflow, c.G, c.init, 4, history_capacity=n)
+        s.add_body(b.xy, b.uv, b.cx, b.cy, b.ds)
+        return s
+
+    s = make()
+    s.set_option(_lib.OPT_GRAPH_CHUNK, 50)
+    s.step(100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(n)
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t0) * 1e3
+    s.close()
+    hbar = np.zeros((n, 1, 3))
+    hbar[:, 0, 0] = 2.0 / (c.U * c.U * c.D) / n
+    out = {"workload": "800x400 channel, D = 40, 126 markers, Re 100, FP32; J = mean Cd over %d steps" % n,
+           "steps": n, "forward_ms_per_step": round(fwd_ms / n, 5)}
+    for name, K in (("sqrt_checkpoints", 0), ("tape", n)):
+        s = make()
+        s.adjoint(min(n, 60), hbar[:min(n, 60)], checkpoint_every=K)  # first launches, graph paths
+        s.close()
+        s = make()
+        nbytes = _lib.load().btdf_adjoint_workspace_bytes(s._workspace(), n, K)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g, ms = s.adjoint(n, hbar, checkpoint_every=K)
+        wall = (time.perf_counter() - t0) * 1e3
+        s.close()
+        rev = ms[1] + ms[2]
+        out[name] = {"checkpoint_every": K if K else int(np.ceil(np.sqrt(n))), "workspace_gb": round(nbytes / 1e9, 3),
+                     "forward_pass_ms": round(ms[0], 2), "recompute_ms": round(ms[1], 2),
+                     "reverse_ms": round(ms[2], 2), "call_wall_ms": round(wall, 1),
+                     "adjoint_over_forward": round(rev / fwd_ms, 3)}
+        print("adjoint %s: forward pass %.1f ms, recompute %.1f ms, reverse %.1f ms; (recompute + reverse) / "
+              "forward = %.2f" % (name, ms[0], ms[1], ms[2], rev / fwd_ms), file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -182,6 +239,9 @@ def main():
     import torch
     from paper_1806_09403_amd import Sim, _lib
 
+    if args.only_adjoint:
+        print(json.dumps(bench_adjoint(args)), flush=True)
+        return
     if args.only_batched:
         if args.copy_probe_mb:
             copy_probe(args.copy_probe_mb)
@@ -268,6 +328,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batched:
         line["batched"] = bench_batched(args)
+        torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        line["adjoint"] = bench_adjoint(args)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_budget_s)

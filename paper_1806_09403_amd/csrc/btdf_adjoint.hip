@@ -11,9 +11,10 @@
 // bit-identical gradients.
 //
 // Workspace (one region, 256-byte-aligned parts):
-//   [ checkpoints or tape states | segment states | G x 2 | marker scratch |
-//     adjoint tile bins | node records | tile sums | weights of the history |
-//     control + one history slot | dJ/dA_0 in FP64 ]
+//   [ checkpoints or tape states | segment states | G x 2 | per-step marker
+//     records | marker adjoints and gradients | adjoint tile bins | tile sums |
+//     weights of the history (all, and one segment's) | control + one
+//     history slot | dJ/dA_0 in FP64 ]
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,21 +32,79 @@ namespace {
 struct AdjLayout {
   int64_t n = 0, K = 0;
   bool tape = false;
-  int64_t n_store = 0;  // tape states (tape) or checkpoints (segments)
-  int64_t n_seg = 0;    // segment states (checkpoint mode)
+  int64_t n_store = 0;  // tape states 1 .. n-1, or checkpoints at t = 0, K, 2K, ...
+  int64_t n_seg = 0;    // segment states (checkpoint mode: K)
+  int64_t n_slot = 0;   // per-step marker records (tape: n, checkpoints: K)
   size_t state = 0;     // bytes of one population state
-  size_t off_store = 0, off_seg = 0, off_g[2] = {0, 0};
-  size_t off_mk = 0, off_mkw = 0, off_mkixy = 0, off_mkadj = 0, off_xyb = 0, off_uvb = 0, off_cb = 0;
-  size_t off_toff = 0, off_tlist = 0, off_tslot = 0, off_forced = 0, off_rec = 0, off_part = 0;
-  size_t off_hbar = 0, off_ctl = 0, off_hist1 = 0, off_out = 0, total = 0;
-  // adjoint tiles and their markers
-  int ntx = 0, nty = 0, nforced = 0;
-  std::vector<int> toff, tlist, tslot, forced;
+  size_t slot = 0;      // bytes of one marker record
+  size_t off_store = 0, off_seg = 0, off_g[2] = {0, 0}, off_slots = 0;
+  size_t off_mkadj = 0, off_xyb = 0, off_uvb = 0, off_cb = 0;
+  size_t off_toff = 0, off_tlist = 0, off_noff = 0, off_nlist = 0, off_part = 0;
+  size_t off_hbar = 0, off_hseg = 0, off_ctl = 0, off_hist1 = 0, off_out = 0, total = 0;
+  // adjoint tiles and their markers; markers covering each stencil node
+  int ntx = 0, nty = 0;
+  std::vector<int> toff, tlist, noff, nlist;
 };
+
+// For every marker l and stencil lane k = 4 j + i (i, j < stencil size), the
+// markers whose stencil covers that node, ascending, packed as
+// (marker << 4) | (dx << 2) | dy with (dx, dy) the node's place in the
+// covering marker's stencil.
+void cover_lists(const btdf_t *h, std::vector<int> &off, std::vector<int> &list) {
+  const int nm = h->nm(), S = stencil_size(h->kind);
+  struct Hit {
+    long long node;
+    int marker, lane;
+  };
+  std::vector<Hit> hits;
+  hits.reserve((size_t)nm * S * S);
+  auto origin = [&](int l, int *ox, int *oy) {
+    *ox = stencil_base(h->kind, h->X[l]);
+    *oy = stencil_base(h->kind, h->Y[l]);
+  };
+  auto key = [&](int x, int y) -> long long {
+    if (h->xper()) x = ((x % h->nx) + h->nx) % h->nx;
+    if (h->yper()) y = ((y % h->ny) + h->ny) % h->ny;
+    return (long long)y * h->nx + x;
+  };
+  for (int l = 0; l < nm; ++l) {
+    int ox, oy;
+    origin(l, &ox, &oy);
+    for (int j = 0; j < S; ++j)
+      for (int i = 0; i < S; ++i) hits.push_back({key(ox + i, oy + j), l, (i << 2) | j});
+  }
+  std::sort(hits.begin(), hits.end(), [](const Hit &a, const Hit &b) {
+    return a.node != b.node ? a.node < b.node : a.marker < b.marker;
+  });
+  off.assign((size_t)nm * 16 + 1, 0);
+  list.clear();
+  for (int l = 0; l < nm; ++l) {
+    int ox, oy;
+    origin(l, &ox, &oy);
+    for (int k = 0; k < 16; ++k) {
+      off[(size_t)l * 16 + k] = (int)list.size();
+      const int i = k & 3, j = k >> 2;
+      if (i >= S || j >= S) continue;
+      const long long nk = key(ox + i, oy + j);
+      auto lo = std::lower_bound(hits.begin(), hits.end(), nk,
+                                 [](const Hit &a, long long v) { return a.node < v; });
+      for (auto it = lo; it != hits.end() && it->node == nk; ++it) list.push_back((it->marker << 4) | it->lane);
+    }
+  }
+  off[(size_t)nm * 16] = (int)list.size();
+  if (list.empty()) list.push_back(0);
+}
 
 int64_t default_K(int64_t n) {
   int64_t K = (int64_t)std::ceil(std::sqrt((double)n));
   return std::max<int64_t>(1, K);
+}
+
+// one marker record: Fx Fy rho_l ux_l uy_l (FP64), spread weights (10 per
+// marker, population type), stencil origins (2 ints)
+size_t slot_bytes(const btdf_t *h) {
+  const size_t M = (size_t)std::max(h->nm(), 1);
+  return align256(5 * M * sizeof(double)) + align256(10 * M * (size_t)h->prec) + align256(2 * M * sizeof(int));
 }
 
 void adj_layout(const btdf_t *h, int64_t n, int64_t K, AdjLayout *L) {
@@ -53,25 +112,21 @@ void adj_layout(const btdf_t *h, int64_t n, int64_t K, AdjLayout *L) {
   L->K = K > 0 ? K : default_K(n);
   L->tape = L->K >= n;
   L->state = align256(9 * (size_t)h->plane * (size_t)h->prec);
+  L->slot = slot_bytes(h);
   if (L->tape) {
-    L->n_store = std::max<int64_t>(0, n - 1);  // states 1 .. n-1 (state 0 stays in the handle)
+    L->n_store = std::max<int64_t>(0, n - 1);
     L->n_seg = 0;
+    L->n_slot = n;
   } else {
-    L->n_store = (n + L->K - 1) / L->K;  // checkpoints at t = 0, K, 2K, ...
-    L->n_seg = L->K - 1;                 // states t0+1 .. t0+K-1 of one segment
+    L->n_store = (n + L->K - 1) / L->K;
+    L->n_seg = L->K;
+    L->n_slot = L->K;
   }
   L->ntx = (h->nx + kAdjTX - 1) / kAdjTX;
   L->nty = (h->ny + kAdjTY - 1) / kAdjTY;
   const int ntiles = L->ntx * L->nty;
   bin_markers(h, kAdjTX, kAdjTY, L->ntx, L->nty, L->toff, L->tlist);
-  L->tslot.assign(ntiles, -1);
-  L->forced.clear();
-  for (int t = 0; t < ntiles; ++t)
-    if (L->toff[t + 1] > L->toff[t]) {
-      L->tslot[t] = (int)L->forced.size();
-      L->forced.push_back(t);
-    }
-  L->nforced = (int)L->forced.size();
+  cover_lists(h, L->noff, L->nlist);
 
   const size_t M = (size_t)std::max(h->nm(), 1), B = (size_t)std::max(h->nb(), 1), d = sizeof(double);
   size_t o = 0;
@@ -83,12 +138,8 @@ void adj_layout(const btdf_t *h, int64_t n, int64_t K, AdjLayout *L) {
   o += L->state;
   L->off_g[1] = o;
   o += L->state;
-  L->off_mk = o;  // Fx Fy rho_l ux_l uy_l
-  o = align256(o + 5 * M * d);
-  L->off_mkw = o;
-  o = align256(o + 10 * M * (size_t)h->prec);
-  L->off_mkixy = o;
-  o = align256(o + 2 * M * sizeof(int));
+  L->off_slots = o;
+  o += (size_t)L->n_slot * L->slot;
   L->off_mkadj = o;
   o = align256(o + 3 * M * d);
   L->off_xyb = o;
@@ -101,16 +152,16 @@ void adj_layout(const btdf_t *h, int64_t n, int64_t K, AdjLayout *L) {
   o = align256(o + (size_t)(ntiles + 1) * sizeof(int));
   L->off_tlist = o;
   o = align256(o + L->tlist.size() * sizeof(int));
-  L->off_tslot = o;
-  o = align256(o + (size_t)ntiles * sizeof(int));
-  L->off_forced = o;
-  o = align256(o + (size_t)std::max(L->nforced, 1) * sizeof(int));
-  L->off_rec = o;
-  o = align256(o + (size_t)std::max(L->nforced, 1) * kAdjTX * kAdjTY * kAdjRec * d);
+  L->off_noff = o;
+  o = align256(o + L->noff.size() * sizeof(int));
+  L->off_nlist = o;
+  o = align256(o + L->nlist.size() * sizeof(int));
   L->off_part = o;
   o = align256(o + (size_t)ntiles * 4 * d);
   L->off_hbar = o;
-  o = align256(o + (size_t)std::max<int64_t>(n, 1) * B * 3 * d);
+  o = align256(o + (size_t)n * B * 3 * d);
+  L->off_hseg = o;
+  o = align256(o + (size_t)(L->tape ? 1 : L->K) * B * 3 * d);
   L->off_ctl = o;
   o = align256(o + 256);
   L->off_hist1 = o;
@@ -125,37 +176,158 @@ int put(hipStream_t s, char *base, size_t off, const void *src, size_t bytes) {
   return ok();
 }
 
+// everything one adjoint call launches with
+struct Adj {
+  btdf_t *h = nullptr;
+  const AdjLayout *L = nullptr;
+  char *w = nullptr;
+  LbmParams p{}, pa{};  // the handle's, and the copy whose flag and counter are the scratch's
+  IbParams ib{}, iba{};
+  AdjParams a{};
+  int nt = 0;
+
+  char *store(int64_t i) const { return w + L->off_store + (size_t)i * L->state; }
+  char *seg(int64_t i) const { return w + L->off_seg + (size_t)i * L->state; }
+  char *gbuf(int i) const { return w + L->off_g[i]; }
+  // marker record k: the marker kernel's outputs of one step
+  void slot_params(int64_t k, const LbmParams &pb, const IbParams &ibb, LbmParams *po, IbParams *io) const {
+    const size_t M = (size_t)std::max(h->nm(), 1);
+    char *r = w + L->off_slots + (size_t)k * L->slot;
+    double *mk = reinterpret_cast<double *>(r);
+    *po = pb;
+    *io = ibb;
+    io->Fx = mk;
+    io->Fy = mk + M;
+    io->rho_l = mk + 2 * M;
+    io->ux_l = mk + 3 * M;
+    io->uy_l = mk + 4 * M;
+    io->mk_w = r + align256(5 * M * sizeof(double));
+    io->mk_ixy = reinterpret_cast<int *>(r + align256(5 * M * sizeof(double)) + align256(10 * M * (size_t)h->prec));
+    po->mk_w = io->mk_w;
+    po->mk_ixy = io->mk_ixy;
+  }
+  AdjParams adj_params(const IbParams &io, const double *hbar) const {
+    AdjParams x = a;
+    x.Fx = io.Fx;
+    x.Fy = io.Fy;
+    x.rho_l = io.rho_l;
+    x.ux_l = io.ux_l;
+    x.uy_l = io.uy_l;
+    x.hist_bar = hbar;
+    return x;
+  }
+};
+
+// one reversed step: state A (its marker record k already holds the step's
+// marker values), dJ/dg of the next step in G[gi] -> dJ/dg of this step in G[gi ^ 1]
+int reverse_step(const Adj &X, const void *A, int64_t k, const double *hbar, int gi, hipStream_t s) {
+  LbmParams pk;
+  IbParams ik;
+  X.slot_params(k, X.pa, X.iba, &pk, &ik);
+  const AdjParams ak = X.adj_params(ik, hbar);
+  const int prec = X.h->prec;
+  HIPCHK(launch_adj_marker(prec, A, X.gbuf(gi), pk, ik, ak, s));
+  HIPCHK(launch_adj_lattice(prec, A, X.gbuf(gi), X.gbuf(gi ^ 1), pk, ak, s));
+  return ok();
+}
+
+// checkpoint mode, one segment of len steps whose first state is in seg(0):
+// recompute the states seg(1 .. len-1) and every step's marker record
+int recompute_segment(const Adj &X, int64_t len, hipStream_t s) {
+  const int prec = X.h->prec;
+  for (int64_t k = 0; k < len; ++k) {
+    LbmParams pk;
+    IbParams ik;
+    X.slot_params(k, X.pa, X.iba, &pk, &ik);
+    HIPCHK(launch_ib(prec, X.seg(k), pk, ik, s));
+    if (k + 1 < len)
+      HIPCHK(launch_lbm(prec, X.h->variant, X.seg(k), X.seg(k + 1), pk, TileRange{nullptr, 0, X.nt, 0}, ik, s));
+  }
+  return ok();
+}
+
+// reverse the len steps of seg(0 .. len-1); the weights of their forces are in
+// the segment's slice of hist_bar, G[gi] holds dJ/dg of the step after them
+int reverse_segment(const Adj &X, int64_t len, int gi, hipStream_t s) {
+  const double *hseg = reinterpret_cast<const double *>(X.w + X.L->off_hseg);
+  const int nb = X.h->nb();
+  for (int64_t k = len - 1; k >= 0; --k) {
+    int rc = reverse_step(X, X.seg(k), k, hseg + (size_t)k * nb * 3, gi, s);
+    if (rc) return rc;
+    gi ^= 1;
+  }
+  return ok();
+}
+
+// K forward steps of the handle from its buffer c, on stream s
+int forward_steps(const Adj &X, int64_t len, int c, hipStream_t s) {
+  for (int64_t k = 0; k < len; ++k) {
+    int rc = enqueue_step(X.h, X.p, X.ib, c, s, nullptr);
+    if (rc) return rc;
+    c ^= 1;
+  }
+  return ok();
+}
+
+// capture what fn enqueues into an executable graph
+template <typename F>
+int capture(hipStream_t cap, hipGraphExec_t *out, F fn) {
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  int rc = fn(cap);
+  hipError_t e = hipStreamEndCapture(cap, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(BTDF_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    *out = nullptr;
+    return fail(BTDF_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  return ok();
+}
+
+struct Owned {
+  char *mem = nullptr;
+  hipStream_t cap = nullptr;
+  std::vector<hipEvent_t> ev;
+  hipGraphExec_t graphs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  ~Owned() {
+    for (hipGraphExec_t g : graphs)
+      if (g) (void)hipGraphExecDestroy(g);
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (mem) (void)hipFree(mem);
+  }
+};
+
 int adjoint_impl(btdf_t *h, int64_t n, int64_t K, const double *hist_bar, btdf_gradients *gr, char *w,
                  size_t wbytes, double *ms) {
   AdjLayout L;
   adj_layout(h, n, K, &L);
-  char *own = nullptr;
+  Owned own;
   if (w == nullptr) {
-    hipError_t e = hipMalloc((void **)&own, L.total);
+    hipError_t e = hipMalloc((void **)&own.mem, L.total);
     if (e != hipSuccess) return fail(BTDF_ENOMEM, "hipMalloc(%zu): %s", L.total, hipGetErrorString(e));
-    w = own;
+    w = own.mem;
   } else if (wbytes < L.total) {
     return fail(BTDF_ENOMEM, "adjoint workspace has %zu bytes, %zu needed", wbytes, L.total);
   } else if ((uintptr_t)w & 255) {
     return fail(BTDF_EINVAL, "adjoint workspace must be 256-byte aligned");
   }
-  struct Free {
-    char *p;
-    ~Free() {
-      if (p) (void)hipFree(p);
-    }
-  } guard{own};
 
   hipStream_t s = h->stream;
   const int nb = h->nb(), nm = h->nm();
   const int ntiles = L.ntx * L.nty;
   const size_t M = (size_t)std::max(nm, 1), d = sizeof(double);
   int rc;
-  // bins, history weights, zeroed sums
   if ((rc = put(s, w, L.off_toff, L.toff.data(), L.toff.size() * sizeof(int))) ||
       (rc = put(s, w, L.off_tlist, L.tlist.data(), L.tlist.size() * sizeof(int))) ||
-      (rc = put(s, w, L.off_tslot, L.tslot.data(), L.tslot.size() * sizeof(int))) ||
-      (rc = put(s, w, L.off_forced, L.forced.data(), L.forced.size() * sizeof(int))) ||
+      (rc = put(s, w, L.off_noff, L.noff.data(), L.noff.size() * sizeof(int))) ||
+      (rc = put(s, w, L.off_nlist, L.nlist.data(), L.nlist.size() * sizeof(int))) ||
       (rc = put(s, w, L.off_hbar, hist_bar, (size_t)n * nb * 3 * d)))
     return rc;
   HIPCHK(hipMemsetAsync(w + L.off_xyb, 0, 2 * M * d, s));
@@ -165,162 +337,157 @@ int adjoint_impl(btdf_t *h, int64_t n, int64_t K, const double *hist_bar, btdf_g
   HIPCHK(hipMemsetAsync(w + L.off_ctl, 0, 256, s));
   HIPCHK(hipMemsetAsync(w + L.off_g[0], 0, L.state, s));  // dJ/dA_n = 0: J reads the history only
 
-  // the handle's parameters (forward run: its ring, counter and flag), and a
-  // copy whose marker outputs, counter, flag and ring go to the scratch (the
-  // recomputation and the sweep leave the handle's view untouched)
-  const LbmParams p = make_params(h);
-  const IbParams ib = make_ib(h);
-  LbmParams pa = p;
-  IbParams iba = ib;
-  double *mk = reinterpret_cast<double *>(w + L.off_mk);
-  iba.Fx = mk;
-  iba.Fy = mk + M;
-  iba.rho_l = mk + 2 * M;
-  iba.ux_l = mk + 3 * M;
-  iba.uy_l = mk + 4 * M;
-  iba.mk_w = w + L.off_mkw;
-  iba.mk_ixy = reinterpret_cast<int *>(w + L.off_mkixy);
-  iba.hist = reinterpret_cast<double *>(w + L.off_hist1);
-  iba.hist_cap = 1;
-  iba.slot = reinterpret_cast<int *>(w + L.off_ctl + 16);
-  pa.mk_w = iba.mk_w;
-  pa.mk_ixy = iba.mk_ixy;
-  pa.step_ctr = reinterpret_cast<long long *>(w + L.off_ctl);
-  pa.flag = reinterpret_cast<int *>(w + L.off_ctl + 8);
-
-  AdjParams a{};
+  Adj X;
+  X.h = h;
+  X.L = &L;
+  X.w = w;
+  X.nt = h->ntx * h->nty;
+  X.p = make_params(h);
+  X.ib = make_ib(h);
+  // the recomputation and the sweep count, flag and record history into the
+  // scratch: the handle's view of its run stays the forward run's
+  X.pa = X.p;
+  X.iba = X.ib;
+  X.iba.hist = reinterpret_cast<double *>(w + L.off_hist1);
+  X.iba.hist_cap = 1;
+  X.iba.slot = reinterpret_cast<int *>(w + L.off_ctl + 16);
+  X.pa.step_ctr = reinterpret_cast<long long *>(w + L.off_ctl);
+  X.pa.flag = reinterpret_cast<int *>(w + L.off_ctl + 8);
+  AdjParams &a = X.a;
   a.ntx = L.ntx;
   a.nty = L.nty;
   a.tile_off = reinterpret_cast<const int *>(w + L.off_toff);
   a.tile_list = reinterpret_cast<const int *>(w + L.off_tlist);
-  a.tile_slot = reinterpret_cast<const int *>(w + L.off_tslot);
-  a.forced = reinterpret_cast<const int *>(w + L.off_forced);
-  a.nforced = L.nforced;
-  a.rec = reinterpret_cast<double *>(w + L.off_rec);
+  a.node_off = reinterpret_cast<const int *>(w + L.off_noff);
+  a.node_list = reinterpret_cast<const int *>(w + L.off_nlist);
   a.part = reinterpret_cast<double *>(w + L.off_part);
-  a.Fx = iba.Fx;
-  a.Fy = iba.Fy;
-  a.rho_l = iba.rho_l;
-  a.ux_l = iba.ux_l;
-  a.uy_l = iba.uy_l;
   a.mk_adj = reinterpret_cast<double *>(w + L.off_mkadj);
   a.xy_bar = reinterpret_cast<double *>(w + L.off_xyb);
   a.uv_bar = reinterpret_cast<double *>(w + L.off_uvb);
   a.c_bar = reinterpret_cast<double *>(w + L.off_cb);
   const double *hbar_dev = reinterpret_cast<const double *>(w + L.off_hbar);
 
-  std::vector<hipEvent_t> ev;
-  auto mark = [&](hipEvent_t *e) -> int {
-    HIPCHK(hipEventCreate(e));
-    HIPCHK(hipEventRecord(*e, s));
+  auto mark = [&]() -> int {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    own.ev.push_back(e);
+    HIPCHK(hipEventRecord(e, s));
     return ok();
   };
-  struct Events {
-    std::vector<hipEvent_t> *v;
-    ~Events() {
-      for (hipEvent_t e : *v) (void)hipEventDestroy(e);
-    }
-  } evguard{&ev};
-  ev.reserve(4 + 2 * (size_t)L.n_store);
-  hipEvent_t e;
-  if ((rc = mark(&e))) return rc;
-  ev.push_back(e);
+  if ((rc = mark())) return rc;
 
-  // ---- forward run
-  const int nt = h->ntx * h->nty;
-  const int cur0 = h->cur;
-  char *state0 = h->ws + h->off_pop[cur0];
-  auto store_state = [&](int64_t i) { return w + L.off_store + (size_t)i * L.state; };
-  auto seg_state = [&](int64_t i) { return w + L.off_seg + (size_t)i * L.state; };
-  const size_t copy_bytes = 9 * (size_t)h->plane * (size_t)h->prec;
+  const int prec = h->prec;
+  const size_t copy_bytes = 9 * (size_t)h->plane * (size_t)prec;
+  int gi = 0;  // G[gi] holds dJ/dg of the step after the one being reversed
   if (L.tape) {
-    // state t of the run: t = 0 in the handle's buffer, 1 .. n-1 in the tape,
-    // n in the handle's other buffer
+    // ---- forward: state t in the handle's buffer (t = 0), the tape (1 .. n-1)
+    // and the handle's other buffer (t = n); each step's marker values kept
+    const int cur0 = h->cur;
+    char *state0 = h->ws + h->off_pop[cur0];
+    auto A_of = [&](int64_t t) -> char * { return t == 0 ? state0 : X.store(t - 1); };
     for (int64_t t = 0; t < n; ++t) {
-      const void *A = t == 0 ? (const void *)state0 : (const void *)store_state(t - 1);
-      void *B = t == n - 1 ? (void *)(h->ws + h->off_pop[1 - cur0]) : (void *)store_state(t);
-      HIPCHK(launch_ib(h->prec, A, p, ib, s));
-      HIPCHK(launch_lbm(h->prec, h->variant, A, B, p, TileRange{nullptr, 0, nt, 1}, ib, s));
+      LbmParams pt;
+      IbParams it;
+      X.slot_params(t, X.p, X.ib, &pt, &it);
+      void *B = t == n - 1 ? (void *)(h->ws + h->off_pop[1 - cur0]) : (void *)X.store(t);
+      HIPCHK(launch_ib(prec, A_of(t), pt, it, s));
+      HIPCHK(launch_lbm(prec, h->variant, A_of(t), B, pt, TileRange{nullptr, 0, X.nt, 1}, it, s));
     }
     h->cur = 1 - cur0;
     h->steps += n;
-  } else {
-    for (int64_t t = 0; t < n; ++t) {
-      if (t % L.K == 0)
-        HIPCHK(hipMemcpyAsync(store_state(t / L.K), h->ws + h->off_pop[h->cur], copy_bytes,
-                              hipMemcpyDeviceToDevice, s));
-      if ((rc = enqueue_step(h, p, ib, h->cur, s, nullptr))) return rc;
-      h->cur ^= 1;
-      h->steps++;
+    {  // the handle's marker arrays show the last step, as after btdf_step
+      LbmParams pt;
+      IbParams it;
+      X.slot_params(n - 1, X.p, X.ib, &pt, &it);
+      HIPCHK(hipMemcpyAsync(X.ib.Fx, it.Fx, 5 * M * d, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(X.ib.mk_w, it.mk_w, 10 * M * (size_t)prec, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(X.ib.mk_ixy, it.mk_ixy, 2 * M * sizeof(int), hipMemcpyDeviceToDevice, s));
     }
-  }
-  if ((rc = mark(&e))) return rc;
-  ev.push_back(e);
-  if ((rc = check_flag(h))) return rc;  // synchronises; an unstable run has no gradient
-
-  // ---- reverse sweep, segment by segment from the last
-  double t_recompute = 0.0, t_reverse = 0.0;
-  int gi = 0;  // G[gi] holds dJ/dg of the step after the one being reversed
-  const int64_t nseg = L.tape ? 1 : L.n_store;
-  for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
-    const int64_t t0 = L.tape ? 0 : sgi * L.K;
-    const int64_t t1 = L.tape ? n : std::min<int64_t>(n, t0 + L.K);
-    auto A_of = [&](int64_t t) -> char * {
-      if (L.tape) return t == 0 ? state0 : store_state(t - 1);
-      return t == t0 ? store_state(sgi) : seg_state(t - t0 - 1);
-    };
-    hipEvent_t r0, r1, r2;
-    if ((rc = mark(&r0))) return rc;
-    ev.push_back(r0);
-    if (!L.tape)
-      for (int64_t t = t0; t + 1 < t1; ++t) {
-        HIPCHK(launch_ib(h->prec, A_of(t), pa, iba, s));
-        HIPCHK(launch_lbm(h->prec, h->variant, A_of(t), A_of(t + 1), pa, TileRange{nullptr, 0, nt, 0}, iba, s));
-      }
-    if ((rc = mark(&r1))) return rc;
-    ev.push_back(r1);
-    for (int64_t t = t1 - 1; t >= t0; --t) {
-      const char *A = A_of(t);
-      void *Gn = w + L.off_g[gi];
-      void *Go = w + L.off_g[gi ^ 1];
-      a.hist_bar = hbar_dev + (size_t)t * nb * 3;
-      HIPCHK(launch_ib(h->prec, A, pa, iba, s));  // the step's marker values
-      HIPCHK(launch_adj_lattice(h->prec, A, Gn, Go, pa, a, s));
-      HIPCHK(launch_adj_marker(pa, iba, a, s));
-      HIPCHK(launch_adj_spread(h->prec, Go, pa, a, s));
+    if ((rc = mark())) return rc;
+    if ((rc = check_flag(h))) return rc;  // synchronises; an unstable run has no gradient
+    if ((rc = mark()) || (rc = mark())) return rc;  // no recomputation: an empty interval
+    for (int64_t t = n - 1; t >= 0; --t) {
+      if ((rc = reverse_step(X, A_of(t), t, hbar_dev + (size_t)t * nb * 3, gi, s))) return rc;
       gi ^= 1;
     }
-    if ((rc = mark(&r2))) return rc;
-    ev.push_back(r2);
+    if ((rc = mark())) return rc;
+  } else {
+    // ---- forward, checkpoint at the start of every segment; whole segments
+    // replay one captured graph per starting buffer
+    const int64_t S = L.n_store;
+    const bool graphs = S >= 3;
+    if (graphs) HIPCHK(hipStreamCreateWithFlags(&own.cap, hipStreamNonBlocking));
+    for (int64_t sg = 0; sg < S; ++sg) {
+      const int64_t len = std::min<int64_t>(L.K, n - sg * L.K);
+      HIPCHK(hipMemcpyAsync(X.store(sg), h->ws + h->off_pop[h->cur], copy_bytes, hipMemcpyDeviceToDevice, s));
+      if (graphs && len == L.K) {
+        hipGraphExec_t &g = own.graphs[h->cur];
+        const int c = h->cur;
+        if (!g && (rc = capture(own.cap, &g, [&](hipStream_t cs) { return forward_steps(X, len, c, cs); }))) return rc;
+        HIPCHK(hipGraphLaunch(g, s));
+      } else if ((rc = forward_steps(X, len, h->cur, s))) {
+        return rc;
+      }
+      if (len & 1) h->cur ^= 1;
+      h->steps += len;
+    }
+    if ((rc = mark())) return rc;
+    if ((rc = check_flag(h))) return rc;
+
+    // ---- reverse, segment by segment from the last: restore the checkpoint
+    // into the segment buffer, recompute the segment, reverse its steps
+    for (int64_t sg = S - 1; sg >= 0; --sg) {
+      const int64_t t0 = sg * L.K, len = std::min<int64_t>(L.K, n - t0);
+      HIPCHK(hipMemcpyAsync(X.seg(0), X.store(sg), copy_bytes, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(w + L.off_hseg, hbar_dev + (size_t)t0 * nb * 3, (size_t)len * nb * 3 * d,
+                            hipMemcpyDeviceToDevice, s));
+      if ((rc = mark())) return rc;
+      if (graphs && len == L.K) {
+        hipGraphExec_t &g = own.graphs[2];
+        if (!g && (rc = capture(own.cap, &g, [&](hipStream_t cs) { return recompute_segment(X, len, cs); })))
+          return rc;
+        HIPCHK(hipGraphLaunch(g, s));
+      } else if ((rc = recompute_segment(X, len, s))) {
+        return rc;
+      }
+      if ((rc = mark())) return rc;
+      if (graphs && len == L.K) {
+        hipGraphExec_t &g = own.graphs[3 + gi];
+        const int g0 = gi;
+        if (!g && (rc = capture(own.cap, &g, [&](hipStream_t cs) { return reverse_segment(X, len, g0, cs); })))
+          return rc;
+        HIPCHK(hipGraphLaunch(g, s));
+      } else if ((rc = reverse_segment(X, len, gi, s))) {
+        return rc;
+      }
+      if (len & 1) gi ^= 1;
+      if ((rc = mark())) return rc;
+    }
   }
 
   // ---- results
   double *out64 = reinterpret_cast<double *>(w + L.off_out);
-  HIPCHK(launch_adj_unpull(h->prec, w + L.off_g[gi], p, out64, s));
+  HIPCHK(launch_adj_unpull(prec, X.gbuf(gi), X.p, out64, s));
   HIPCHK(hipStreamSynchronize(s));
   {
-    long long ctr;
     int flag;
-    unsigned char buf[16];
-    HIPCHK(hipMemcpy(buf, w + L.off_ctl, 16, hipMemcpyDeviceToHost));
-    std::memcpy(&ctr, buf, 8);
-    std::memcpy(&flag, buf + 8, 4);
+    HIPCHK(hipMemcpy(&flag, w + L.off_ctl + 8, 4, hipMemcpyDeviceToHost));
     if (flag != 0) return fail(BTDF_EUNSTABLE, "the recomputed steps went unstable");
   }
   if (gr->populations)
     HIPCHK(hipMemcpy(gr->populations, out64, 9 * (size_t)h->nx * h->ny * d, hipMemcpyDeviceToHost));
   std::vector<double> part((size_t)ntiles * 4);
   HIPCHK(hipMemcpy(part.data(), w + L.off_part, part.size() * d, hipMemcpyDeviceToHost));
-  double sg[4] = {0, 0, 0, 0};
+  double sg4[4] = {0, 0, 0, 0};
   for (int t = 0; t < ntiles; ++t)
-    for (int k = 0; k < 4; ++k) sg[k] += part[4 * (size_t)t + k];
+    for (int k = 0; k < 4; ++k) sg4[k] += part[4 * (size_t)t + k];
   if (gr->body_force) {
-    gr->body_force[0] = sg[0];
-    gr->body_force[1] = sg[1];
+    gr->body_force[0] = sg4[0];
+    gr->body_force[1] = sg4[1];
   }
   if (gr->inflow) {
-    gr->inflow[0] = sg[2];
-    gr->inflow[1] = sg[3];
+    gr->inflow[0] = sg4[2];
+    gr->inflow[1] = sg4[3];
   }
   if (gr->marker_xy && nm) HIPCHK(hipMemcpy(gr->marker_xy, a.xy_bar, 2 * (size_t)nm * d, hipMemcpyDeviceToHost));
   if (gr->marker_uv && nm) HIPCHK(hipMemcpy(gr->marker_uv, a.uv_bar, 2 * (size_t)nm * d, hipMemcpyDeviceToHost));
@@ -337,19 +504,20 @@ int adjoint_impl(btdf_t *h, int64_t n, int64_t K, const double *hist_bar, btdf_g
       gr->centres[2 * b + 1] = sy;
     }
   }
-  if (ms) {  // events: start, end of the forward run, then (start, recomputed, reversed) per segment
+  if (ms) {
+    // events: start, end of the forward run, then (recompute start, reverse
+    // start, end) per segment (one segment for a tape)
     float f = 0.f;
-    (void)hipEventElapsedTime(&f, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&f, own.ev[0], own.ev[1]);
     ms[0] = f;
-    for (size_t k = 2; k + 2 < ev.size(); k += 3) {
+    ms[1] = ms[2] = 0.0;
+    for (size_t k = 2; k + 2 < own.ev.size(); k += 3) {
       float a1 = 0.f, a2 = 0.f;
-      (void)hipEventElapsedTime(&a1, ev[k], ev[k + 1]);
-      (void)hipEventElapsedTime(&a2, ev[k + 1], ev[k + 2]);
-      t_recompute += a1;
-      t_reverse += a2;
+      (void)hipEventElapsedTime(&a1, own.ev[k], own.ev[k + 1]);
+      (void)hipEventElapsedTime(&a2, own.ev[k + 1], own.ev[k + 2]);
+      ms[1] += a1;
+      ms[2] += a2;
     }
-    ms[1] = t_recompute;
-    ms[2] = t_reverse;
   }
   return ok();
 }

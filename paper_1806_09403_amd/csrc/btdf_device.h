@@ -145,16 +145,14 @@ struct CaseDesc {
 };
 
 // the adjoint (reverse) step: its own 64 x 4 tiling of the lattice with the
-// markers binned per tile, and the per-node records of the tiles a marker
-// stencil touches ("forced" tiles)
-constexpr int kAdjTX = 64, kAdjTY = 4, kAdjRec = 5;
+// markers binned per tile
+constexpr int kAdjTX = 64, kAdjTY = 4;
 struct AdjParams {
   int ntx, nty;                     // adjoint tiles
   const int *tile_off, *tile_list;  // markers whose stencil touches each tile, ascending
-  const int *tile_slot;             // forced slot of each tile, -1 when no stencil touches it
-  const int *forced;                // tile of each forced slot
-  int nforced;
-  double *rec;   // [nforced][kAdjTX * kAdjTY][5]: dJ/df (x, y), rho, u*_x, u*_y at the node
+  // for each marker l and stencil lane k (16 per marker), the markers whose
+  // stencil covers that node, ascending, packed as (marker << 4) | (dx << 2) | dy
+  const int *node_off, *node_list;
   double *part;  // [tiles][4]: dJ/dG (x, y), dJ/du_in (x, y), summed over steps per tile
   // marker side (one entry per marker)
   const double *Fx, *Fy, *rho_l, *ux_l, *uy_l;  // forward values of the step being reversed

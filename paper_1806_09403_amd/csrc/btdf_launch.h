@@ -16,8 +16,8 @@ hipError_t launch_lbm_batch(int prec, int variant, const CaseDesc *cases, const 
 hipError_t launch_ib_batch(int prec, const CaseDesc *cases, const BatchMap &m, int parity, hipStream_t s);
 hipError_t launch_adj_lattice(int prec, const void *A, const void *Gnext, void *Gout, const LbmParams &p,
                               const AdjParams &a, hipStream_t s);
-hipError_t launch_adj_marker(const LbmParams &p, const IbParams &ib, const AdjParams &a, hipStream_t s);
-hipError_t launch_adj_spread(int prec, void *Gout, const LbmParams &p, const AdjParams &a, hipStream_t s);
+hipError_t launch_adj_marker(int prec, const void *A, const void *Gnext, const LbmParams &p, const IbParams &ib,
+                             const AdjParams &a, hipStream_t s);
 hipError_t launch_adj_unpull(int prec, const void *G, const LbmParams &p, double *out, hipStream_t s);
 hipError_t launch_init_uniform(int prec, void *A, const LbmParams &p, double r, double u, double v,
                                hipStream_t s);
