@@ -195,3 +195,53 @@ def test_c5_gradients_match_fp64_central_differences():
             log("  dJ/dU_b[%d,%d] FP64 %.8e FP32 %.8e FD %.8e" % (l, comp, a64["uv"][l, comp], a32["uv"][l, comp], fd))
             assert abs(a64["uv"][l, comp] - fd) <= tol * max(abs(fd), floor)
             assert abs(a32["uv"][l, comp] - fd) <= tol * max(abs(fd), floor)
+
+
+def torch_equilibrium(rho, ux, uy, nx, ny):
+    """feq_q(rho, (ux, uy)) of eq 6, uniform, as a differentiable [9, ny, nx] tensor."""
+    import torch
+    ex = torch.tensor([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=torch.float64)
+    ey = torch.tensor([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=torch.float64)
+    w = torch.tensor([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, dtype=torch.float64)
+    eu = ex * ux + ey * uy
+    f = w * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy))
+    return f[:, None, None].expand(9, ny, nx).contiguous()
+
+
+def test_autograd_rollout_matches_finite_differences():
+    """J = mean drag coefficient through torch: the initial state and the
+    inflow built from U, the markers placed around a centre; gradients by
+    loss.backward() against central differences of the same FP64 run."""
+    import torch
+    from paper_1806_09403_amd.autograd import RolloutSpec, rollout
+    nx, ny, D, n, U0 = 120, 60, 10.0, 300, 0.04
+    body = W.cylinder_body(30.0, 30.0, D)
+    nl = body.xy.shape[0]
+    offsets = torch.from_numpy(body.xy - np.array([body.cx, body.cy]))
+    spec = RolloutSpec(nx, ny, W.tau_from_nu(U0 * D / 40.0), n, (nl,), (body.ds,), W.COS4,
+                       W.PAPER_THICKENING[W.COS4], W.CHANNEL, 8, 0, (U0, 0.0))
+
+    def J_of(U, c, uv):
+        zero = torch.zeros((), dtype=torch.float64)
+        hist = rollout(spec, torch_equilibrium(1.0, U, zero, nx, ny), torch.stack([U, zero]),
+                       torch.zeros(2, dtype=torch.float64), c[None, :] + offsets, uv, c[None, :])
+        return torch.mean(2.0 * hist[:, 0, 0] / (U * U * D))
+
+    U = torch.tensor(U0, dtype=torch.float64, requires_grad=True)
+    c = torch.tensor([body.cx, body.cy], dtype=torch.float64, requires_grad=True)
+    uv = torch.zeros((nl, 2), dtype=torch.float64, requires_grad=True)
+    J = J_of(U, c, uv)
+    J.backward()
+    h = 1e-5
+    with torch.no_grad():
+        fdU = (J_of(U + h, c, uv) - J_of(U - h, c, uv)).item() / (2 * h)
+        e0 = torch.tensor([h, 0.0], dtype=torch.float64)
+        fdx = (J_of(U, c + e0, uv) - J_of(U, c - e0, uv)).item() / (2 * h)
+        duv = torch.zeros_like(uv)
+        duv[5, 1] = h
+        fduv = (J_of(U, c, uv + duv) - J_of(U, c, uv - duv)).item() / (2 * h)
+    log("autograd: dJ/dU %.8e FD %.8e; dJ/dcx %.8e FD %.8e; dJ/dV_5 %.8e FD %.8e"
+        % (U.grad.item(), fdU, c.grad[0].item(), fdx, uv.grad[5, 1].item(), fduv))
+    assert abs(U.grad.item() - fdU) <= 1e-6 * abs(fdU)
+    assert abs(c.grad[0].item() - fdx) <= 1e-5 * abs(fdx)
+    assert abs(uv.grad[5, 1].item() - fduv) <= 1e-6 * abs(fduv)
