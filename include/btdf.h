@@ -299,8 +299,10 @@ int btdf_batch_autotune(btdf_batch_t *b, int64_t steps_per_trial, int *best_vari
  *                              (moving a body also moves its markers)
  *   work      device memory of btdf_adjoint_workspace_bytes bytes, 256-byte
  *             aligned, or NULL (the library allocates and frees it)
- *   ms        [3] or NULL: milliseconds of the forward run, of the
- *             recomputation and of the reverse steps (HIP events)
+ *   ms        [3] or NULL: milliseconds (HIP events) of the forward run, of
+ *             the recomputation (summed; with checkpoints it runs on a second
+ *             stream under the reverse steps of the segment above) and of the
+ *             whole reverse sweep, recomputation included
  * Synchronising. Errors: EINVAL, ENOMEM, EUNSTABLE (the run went unstable:
  * no gradient), EDEVICE. */
 typedef struct btdf_gradients {

@@ -33,8 +33,8 @@ struct AdjLayout {
   int64_t n = 0, K = 0;
   bool tape = false;
   int64_t n_store = 0;  // tape states 1 .. n-1, or checkpoints at t = 0, K, 2K, ...
-  int64_t n_seg = 0;    // segment states (checkpoint mode: K)
-  int64_t n_slot = 0;   // per-step marker records (tape: n, checkpoints: K)
+  int64_t n_seg = 0;    // segment states (checkpoint mode: two sets of K)
+  int64_t n_slot = 0;   // per-step marker records (tape: n, checkpoints: two sets of K)
   size_t state = 0;     // bytes of one population state
   size_t slot = 0;      // bytes of one marker record
   size_t off_store = 0, off_seg = 0, off_g[2] = {0, 0}, off_slots = 0;
@@ -119,8 +119,8 @@ void adj_layout(const btdf_t *h, int64_t n, int64_t K, AdjLayout *L) {
     L->n_slot = n;
   } else {
     L->n_store = (n + L->K - 1) / L->K;
-    L->n_seg = L->K;
-    L->n_slot = L->K;
+    L->n_seg = 2 * L->K;
+    L->n_slot = 2 * L->K;
   }
   L->ntx = (h->nx + kAdjTX - 1) / kAdjTX;
   L->nty = (h->ny + kAdjTY - 1) / kAdjTY;
@@ -161,7 +161,7 @@ void adj_layout(const btdf_t *h, int64_t n, int64_t K, AdjLayout *L) {
   L->off_hbar = o;
   o = align256(o + (size_t)n * B * 3 * d);
   L->off_hseg = o;
-  o = align256(o + (size_t)(L->tape ? 1 : L->K) * B * 3 * d);
+  o = align256(o + (size_t)(L->tape ? 1 : 2 * L->K) * B * 3 * d);
   L->off_ctl = o;
   o = align256(o + 256);
   L->off_hist1 = o;
@@ -187,7 +187,12 @@ struct Adj {
   int nt = 0;
 
   char *store(int64_t i) const { return w + L->off_store + (size_t)i * L->state; }
-  char *seg(int64_t i) const { return w + L->off_seg + (size_t)i * L->state; }
+  // segment buffers: two sets of K states (and of K marker records), so one
+  // segment can be recomputed while the next one up is reversed
+  char *seg(int set, int64_t i) const { return w + L->off_seg + ((size_t)set * L->K + i) * L->state; }
+  const double *hseg(int set) const {
+    return reinterpret_cast<const double *>(w + L->off_hseg) + (size_t)set * L->K * std::max(h->nb(), 1) * 3;
+  }
   char *gbuf(int i) const { return w + L->off_g[i]; }
   // marker record k: the marker kernel's outputs of one step
   void slot_params(int64_t k, const LbmParams &pb, const IbParams &ibb, LbmParams *po, IbParams *io) const {
@@ -231,28 +236,30 @@ int reverse_step(const Adj &X, const void *A, int64_t k, const double *hbar, int
   return ok();
 }
 
-// checkpoint mode, one segment of len steps whose first state is in seg(0):
-// recompute the states seg(1 .. len-1) and every step's marker record
-int recompute_segment(const Adj &X, int64_t len, hipStream_t s) {
+// checkpoint mode, one segment of len steps whose first state is in
+// seg(set, 0): recompute the states seg(set, 1 .. len-1) and every step's
+// marker record (records set * K + k)
+int recompute_segment(const Adj &X, int set, int64_t len, hipStream_t s) {
   const int prec = X.h->prec;
   for (int64_t k = 0; k < len; ++k) {
     LbmParams pk;
     IbParams ik;
-    X.slot_params(k, X.pa, X.iba, &pk, &ik);
-    HIPCHK(launch_ib(prec, X.seg(k), pk, ik, s));
+    X.slot_params(set * X.L->K + k, X.pa, X.iba, &pk, &ik);
+    HIPCHK(launch_ib(prec, X.seg(set, k), pk, ik, s));
     if (k + 1 < len)
-      HIPCHK(launch_lbm(prec, X.h->variant, X.seg(k), X.seg(k + 1), pk, TileRange{nullptr, 0, X.nt, 0}, ik, s));
+      HIPCHK(launch_lbm(prec, X.h->variant, X.seg(set, k), X.seg(set, k + 1), pk, TileRange{nullptr, 0, X.nt, 0},
+                        ik, s));
   }
   return ok();
 }
 
-// reverse the len steps of seg(0 .. len-1); the weights of their forces are in
-// the segment's slice of hist_bar, G[gi] holds dJ/dg of the step after them
-int reverse_segment(const Adj &X, int64_t len, int gi, hipStream_t s) {
-  const double *hseg = reinterpret_cast<const double *>(X.w + X.L->off_hseg);
+// reverse the len steps of seg(set, 0 .. len-1); the weights of their forces
+// are in the set's slice of hist_bar, G[gi] holds dJ/dg of the step after them
+int reverse_segment(const Adj &X, int set, int64_t len, int gi, hipStream_t s) {
+  const double *hseg = X.hseg(set);
   const int nb = X.h->nb();
   for (int64_t k = len - 1; k >= 0; --k) {
-    int rc = reverse_step(X, X.seg(k), k, hseg + (size_t)k * nb * 3, gi, s);
+    int rc = reverse_step(X, X.seg(set, k), set * X.L->K + k, hseg + (size_t)k * nb * 3, gi, s);
     if (rc) return rc;
     gi ^= 1;
   }
@@ -292,13 +299,16 @@ int capture(hipStream_t cap, hipGraphExec_t *out, F fn) {
 
 struct Owned {
   char *mem = nullptr;
-  hipStream_t cap = nullptr;
+  hipStream_t cap = nullptr, side = nullptr;
   std::vector<hipEvent_t> ev;
-  hipGraphExec_t graphs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // forward from buffer 0 / 1; recompute into set 0 / 1; reverse of set 0 / 1
+  // starting from G[0] / G[1]
+  hipGraphExec_t fwd[2] = {nullptr, nullptr}, rec[2] = {nullptr, nullptr}, rev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   ~Owned() {
-    for (hipGraphExec_t g : graphs)
+    for (hipGraphExec_t g : {fwd[0], fwd[1], rec[0], rec[1], rev[0][0], rev[0][1], rev[1][0], rev[1][1]})
       if (g) (void)hipGraphExecDestroy(g);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    if (side) (void)hipStreamDestroy(side);
     if (cap) (void)hipStreamDestroy(cap);
     if (mem) (void)hipFree(mem);
   }
@@ -379,6 +389,7 @@ int adjoint_impl(btdf_t *h, int64_t n, int64_t K, const double *hist_bar, btdf_g
   const int prec = h->prec;
   const size_t copy_bytes = 9 * (size_t)h->plane * (size_t)prec;
   int gi = 0;  // G[gi] holds dJ/dg of the step after the one being reversed
+  double rec_ms = 0.0, sweep_ms = 0.0;
   if (L.tape) {
     // ---- forward: state t in the handle's buffer (t = 0), the tape (1 .. n-1)
     // and the handle's other buffer (t = n); each step's marker values kept
@@ -405,12 +416,16 @@ int adjoint_impl(btdf_t *h, int64_t n, int64_t K, const double *hist_bar, btdf_g
     }
     if ((rc = mark())) return rc;
     if ((rc = check_flag(h))) return rc;  // synchronises; an unstable run has no gradient
-    if ((rc = mark()) || (rc = mark())) return rc;  // no recomputation: an empty interval
+    if ((rc = mark())) return rc;
     for (int64_t t = n - 1; t >= 0; --t) {
       if ((rc = reverse_step(X, A_of(t), t, hbar_dev + (size_t)t * nb * 3, gi, s))) return rc;
       gi ^= 1;
     }
     if ((rc = mark())) return rc;
+    HIPCHK(hipStreamSynchronize(s));
+    float f = 0.f;
+    (void)hipEventElapsedTime(&f, own.ev[2], own.ev[3]);
+    sweep_ms = f;
   } else {
     // ---- forward, checkpoint at the start of every segment; whole segments
     // replay one captured graph per starting buffer
@@ -421,7 +436,7 @@ int adjoint_impl(btdf_t *h, int64_t n, int64_t K, const double *hist_bar, btdf_g
       const int64_t len = std::min<int64_t>(L.K, n - sg * L.K);
       HIPCHK(hipMemcpyAsync(X.store(sg), h->ws + h->off_pop[h->cur], copy_bytes, hipMemcpyDeviceToDevice, s));
       if (graphs && len == L.K) {
-        hipGraphExec_t &g = own.graphs[h->cur];
+        hipGraphExec_t &g = own.fwd[h->cur];
         const int c = h->cur;
         if (!g && (rc = capture(own.cap, &g, [&](hipStream_t cs) { return forward_steps(X, len, c, cs); }))) return rc;
         HIPCHK(hipGraphLaunch(g, s));
@@ -434,35 +449,86 @@ int adjoint_impl(btdf_t *h, int64_t n, int64_t K, const double *hist_bar, btdf_g
     if ((rc = mark())) return rc;
     if ((rc = check_flag(h))) return rc;
 
-    // ---- reverse, segment by segment from the last: restore the checkpoint
-    // into the segment buffer, recompute the segment, reverse its steps
-    for (int64_t sg = S - 1; sg >= 0; --sg) {
-      const int64_t t0 = sg * L.K, len = std::min<int64_t>(L.K, n - t0);
-      HIPCHK(hipMemcpyAsync(X.seg(0), X.store(sg), copy_bytes, hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemcpyAsync(w + L.off_hseg, hbar_dev + (size_t)t0 * nb * 3, (size_t)len * nb * 3 * d,
-                            hipMemcpyDeviceToDevice, s));
-      if ((rc = mark())) return rc;
-      if (graphs && len == L.K) {
-        hipGraphExec_t &g = own.graphs[2];
-        if (!g && (rc = capture(own.cap, &g, [&](hipStream_t cs) { return recompute_segment(X, len, cs); })))
-          return rc;
-        HIPCHK(hipGraphLaunch(g, s));
-      } else if ((rc = recompute_segment(X, len, s))) {
-        return rc;
-      }
-      if ((rc = mark())) return rc;
-      if (graphs && len == L.K) {
-        hipGraphExec_t &g = own.graphs[3 + gi];
-        const int g0 = gi;
-        if (!g && (rc = capture(own.cap, &g, [&](hipStream_t cs) { return reverse_segment(X, len, g0, cs); })))
-          return rc;
-        HIPCHK(hipGraphLaunch(g, s));
-      } else if ((rc = reverse_segment(X, len, gi, s))) {
-        return rc;
-      }
-      if (len & 1) gi ^= 1;
-      if ((rc = mark())) return rc;
+    // ---- reverse, segment by segment from the last. Segment sg uses buffer
+    // set sg & 1. A side stream restores the checkpoint and recomputes the
+    // segment below while this stream reverses the current one; events order
+    // each recomputation after the reversal that last used its set, and each
+    // reversal after its own recomputation.
+    HIPCHK(hipStreamCreateWithFlags(&own.side, hipStreamNonBlocking));
+    hipStream_t s2 = own.side;
+    hipEvent_t evRec[2], evRev[2], e0, eEnd;
+    for (int k = 0; k < 2; ++k) {
+      HIPCHK(hipEventCreateWithFlags(&evRec[k], hipEventDisableTiming));
+      own.ev.push_back(evRec[k]);
+      HIPCHK(hipEventCreateWithFlags(&evRev[k], hipEventDisableTiming));
+      own.ev.push_back(evRev[k]);
     }
+    HIPCHK(hipEventCreate(&e0));
+    own.ev.push_back(e0);
+    HIPCHK(hipEventCreate(&eEnd));
+    own.ev.push_back(eEnd);
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> rec_ev;  // timing of each recomputation
+    HIPCHK(hipEventRecord(e0, s));
+    HIPCHK(hipStreamWaitEvent(s2, e0, 0));  // the side stream starts after the forward run
+    auto prep = [&](int64_t sg) -> int {
+      const int set = (int)(sg & 1);
+      const int64_t t0 = sg * L.K, len = std::min<int64_t>(L.K, n - t0);
+      HIPCHK(hipMemcpyAsync(X.seg(set, 0), X.store(sg), copy_bytes, hipMemcpyDeviceToDevice, s2));
+      HIPCHK(hipMemcpyAsync(const_cast<double *>(X.hseg(set)), hbar_dev + (size_t)t0 * nb * 3,
+                            (size_t)len * nb * 3 * d, hipMemcpyDeviceToDevice, s2));
+      hipEvent_t a0, a1;
+      HIPCHK(hipEventCreate(&a0));
+      own.ev.push_back(a0);
+      HIPCHK(hipEventCreate(&a1));
+      own.ev.push_back(a1);
+      HIPCHK(hipEventRecord(a0, s2));
+      int r;
+      if (graphs && len == L.K) {
+        hipGraphExec_t &g = own.rec[set];
+        if (!g && (r = capture(own.cap, &g, [&](hipStream_t cs) { return recompute_segment(X, set, len, cs); })))
+          return r;
+        HIPCHK(hipGraphLaunch(g, s2));
+      } else if ((r = recompute_segment(X, set, len, s2))) {
+        return r;
+      }
+      HIPCHK(hipEventRecord(a1, s2));
+      rec_ev.push_back({a0, a1});
+      HIPCHK(hipEventRecord(evRec[set], s2));
+      return ok();
+    };
+    if ((rc = prep(S - 1))) return rc;
+    for (int64_t sg = S - 1; sg >= 0; --sg) {
+      const int set = (int)(sg & 1);
+      const int64_t len = std::min<int64_t>(L.K, n - sg * L.K);
+      if (sg >= 1) {
+        // the set of segment sg - 1 was last reversed as segment sg + 1
+        if (sg + 1 < S) HIPCHK(hipStreamWaitEvent(s2, evRev[(sg + 1) & 1], 0));
+        if ((rc = prep(sg - 1))) return rc;
+      }
+      HIPCHK(hipStreamWaitEvent(s, evRec[set], 0));
+      if (graphs && len == L.K) {
+        hipGraphExec_t &g = own.rev[set][gi];
+        const int g0 = gi;
+        if (!g && (rc = capture(own.cap, &g, [&](hipStream_t cs) { return reverse_segment(X, set, len, g0, cs); })))
+          return rc;
+        HIPCHK(hipGraphLaunch(g, s));
+      } else if ((rc = reverse_segment(X, set, len, gi, s))) {
+        return rc;
+      }
+      HIPCHK(hipEventRecord(evRev[set], s));
+      if (len & 1) gi ^= 1;
+    }
+    HIPCHK(hipEventRecord(eEnd, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float f = 0.f;
+    double trec = 0.0;
+    for (auto &pr : rec_ev) {
+      (void)hipEventElapsedTime(&f, pr.first, pr.second);
+      trec += f;
+    }
+    (void)hipEventElapsedTime(&f, e0, eEnd);
+    sweep_ms = f;
+    rec_ms = trec;
   }
 
   // ---- results
@@ -505,19 +571,11 @@ int adjoint_impl(btdf_t *h, int64_t n, int64_t K, const double *hist_bar, btdf_g
     }
   }
   if (ms) {
-    // events: start, end of the forward run, then (recompute start, reverse
-    // start, end) per segment (one segment for a tape)
     float f = 0.f;
     (void)hipEventElapsedTime(&f, own.ev[0], own.ev[1]);
-    ms[0] = f;
-    ms[1] = ms[2] = 0.0;
-    for (size_t k = 2; k + 2 < own.ev.size(); k += 3) {
-      float a1 = 0.f, a2 = 0.f;
-      (void)hipEventElapsedTime(&a1, own.ev[k], own.ev[k + 1]);
-      (void)hipEventElapsedTime(&a2, own.ev[k + 1], own.ev[k + 2]);
-      ms[1] += a1;
-      ms[2] += a2;
-    }
+    ms[0] = f;         // the forward run
+    ms[1] = rec_ms;    // recomputation, summed (it runs under the reverse steps)
+    ms[2] = sweep_ms;  // the whole reverse sweep, recomputation included
   }
   return ok();
 }

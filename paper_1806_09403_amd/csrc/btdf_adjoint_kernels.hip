@@ -81,8 +81,7 @@ __device__ __forceinline__ NodeFwd node_forward(const Gv gv[9], double ftx, doub
 // inlet's dJ/du_in share is added there.
 template <typename T, typename Gv>
 __device__ __forceinline__ void node_dJdB(const T *__restrict__ Gn, const LbmParams &p, int x, int y,
-                                          const Gv g[9], double ftx, double fty, T bb[9], double *sUx,
-                                          double *sUy) {
+                                          const Gv g[9], T bb[9], double *sUx, double *sUy) {
 #pragma unroll
   for (int q = 0; q < 9; ++q) bb[q] = pull_adj<T>(Gn, p, q, x, y);
   if (p.outlet && x == p.nx - 2) {  // B(nx-1, y) = B(nx-2, y)
@@ -193,6 +192,7 @@ __device__ __forceinline__ void node_spread_force(const LbmParams &p, const AdjP
   const T *mw = reinterpret_cast<const T *>(p.mk_w);
   T sx = (T)0, sy = (T)0;
   const int c0 = a.node_off[16 * l + k], c1 = a.node_off[16 * l + k + 1];
+#pragma unroll 4
   for (int c = c0; c < c1; ++c) {
     const int e = a.node_list[c];
     const T *w = mw + 10 * (long long)(e >> 4);
@@ -232,15 +232,15 @@ __global__ __launch_bounds__(256) void adj_marker_kernel(const T *__restrict__ A
     if (p.xper) xx = ((xx % p.nx) + p.nx) % p.nx;
     if (p.yper) yy = ((yy % p.ny) + p.ny) % p.ny;
     // the node's forward values and dJ/df, as the lattice kernel forms them
-    T g[9];
+    // every load that does not depend on the covering markers goes first
+    T g[9], bb[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) g[q] = pull<T>(A, p, q, xx, yy);
+    node_dJdB<T>(Gn, p, xx, yy, g, bb, nullptr, nullptr);
     T sfx, sfy;
     node_spread_force<T>(p, a, l, lane, &sfx, &sfy);
     const double ftx = (double)(T)(p.Gx + (double)sfx), fty = (double)(T)(p.Gy + (double)sfy);
     const NodeFwd nf = node_forward(g, ftx, fty, p);
-    T bb[9];
-    node_dJdB<T>(Gn, p, xx, yy, g, ftx, fty, bb, nullptr, nullptr);
     Mom mo;
 #pragma unroll
     for (int q = 0; q < 9; ++q) mo.add(q, (double)bb[q]);

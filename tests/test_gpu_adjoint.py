@@ -147,7 +147,7 @@ def c5_adjoint(precision, n, K=0):
     dx = float(np.sum(g["marker_xy"][:, 0]) + g["centres"][0, 0])
     dy = float(np.sum(g["marker_xy"][:, 1]) + g["centres"][0, 1])
     log("  precision %d: J = %.8f dJ/dU %.8e (flow part %.8e) dJ/dx %.8e dJ/dy %.3e; "
-        "ms fwd %.1f recompute %.1f reverse %.1f" % (precision, J, dU, dU_flow, dx, dy, *ms))
+        "ms fwd %.1f recompute (overlapped) %.1f sweep %.1f" % (precision, J, dU, dU_flow, dx, dy, *ms))
     s.close()
     return dict(J=J, dU=dU, dU_flow=dU_flow, dx=dx, dy=dy, xy=g["marker_xy"], cx=g["centres"][0, 0],
                 uv=g["marker_uv"])
