@@ -129,6 +129,9 @@ typedef struct {
   double *force; /* [nb][3]: Fx, Fy, Tz on each body, last step */
   long steps;
   int unstable; /* 0 = fine; 1 + body for a marker trigger; -1 for a node */
+  int nf;       /* forcing passes per step (Algorithm 1 step 3; 1 = BTDF as proposed) */
+  double *usx, *usy; /* u*^k at every node during the passes */
+  double *dFx, *dFy; /* force increment of the current pass, per marker */
 } oracle_t;
 
 static size_t nnode(const oracle_t *o) { return (size_t)o->nx * (size_t)o->ny; }
@@ -175,8 +178,11 @@ oracle_t *oracle_create(int nx, int ny, const int *bc, double tau, int kind,
   o->fx = (double *)calloc(n, sizeof(double));
   o->fy = (double *)calloc(n, sizeof(double));
   o->off = (int *)calloc(1, sizeof(int));
+  o->nf = 1;
+  o->usx = (double *)calloc(n, sizeof(double));
+  o->usy = (double *)calloc(n, sizeof(double));
   if (!o->A || !o->g || !o->rho || !o->mx || !o->my || !o->ux || !o->uy ||
-      !o->fx || !o->fy || !o->off) {
+      !o->fx || !o->fy || !o->off || !o->usx || !o->usy) {
     free(o);
     return NULL;
   }
@@ -194,14 +200,20 @@ void oracle_destroy(oracle_t *o) {
   free(o->rho_l); free(o->ux_l); free(o->uy_l); free(o->Fx); free(o->Fy);
   free(o->body_of); free(o->off); free(o->cx); free(o->cy); free(o->ds);
   free(o->force);
+  free(o->usx); free(o->usy); free(o->dFx); free(o->dFy);
   free(o);
 }
+
+/* Forcing passes per step (Algorithm 1 step 3 with NF passes: the multi
+ * direct forcing of eqs 29-31 on the thickened spreading). */
+void oracle_set_forcing_passes(oracle_t *o, int nf) { o->nf = nf < 1 ? 1 : nf; }
 
 static int grow_markers(oracle_t *o, int need) {
   if (need <= o->nm_cap) return 0;
   int cap = need * 2;
-  double **arrs[] = {&o->X, &o->Y, &o->Ub, &o->Vb, &o->rho_l, &o->ux_l, &o->uy_l, &o->Fx, &o->Fy};
-  for (int a = 0; a < 9; ++a) {
+  double **arrs[] = {&o->X, &o->Y, &o->Ub, &o->Vb, &o->rho_l, &o->ux_l, &o->uy_l, &o->Fx, &o->Fy,
+                     &o->dFx, &o->dFy};
+  for (int a = 0; a < 11; ++a) {
     double *p = (double *)realloc(*arrs[a], (size_t)cap * sizeof(double));
     if (!p) return -1;
     *arrs[a] = p;
@@ -316,49 +328,69 @@ static size_t node_of(const oracle_t *o, int i, int j) {
 }
 
 /* Interpolation (eqs 12, 14), direct force (eq 20), spreading (eqs 13, 15)
- * and hydrodynamic force and torque (eq 27) for every marker, NF = 1. All
- * markers see the same u* (the interpolation of every marker happens before
- * any spreading). */
+ * and hydrodynamic force and torque (eq 27) for every marker, in NF forcing
+ * passes (Algorithm 1 step 3; eqs 29-31 when NF > 1):
+ *   u*^0 = u* (with G/2), F_b = 0, f = 0;
+ *   for each pass: dF_l = 2 rho_l (U_b,l - D_I u*^{k-1}) (eq 20 / eq 29),
+ *   F_b += dF, df = D_E dF (eqs 13, 15), f += df,
+ *   u*^k = u*^{k-1} + df / (2 rho) at every node (eq 11 / eq 30).
+ * rho_l = D_I rho is the same in every pass. Within a pass all markers see
+ * the same u*^{k-1} (the interpolation of every marker happens before any
+ * spreading). The marker data keep the first pass's rho_l and u*_l. */
 static void immersed_boundary(oracle_t *o) {
   size_t n = nnode(o);
   double h = oracle_delta_halfwidth(o->kind);
-  for (size_t k = 0; k < n; ++k) o->fx[k] = o->fy[k] = 0.0;
-
-  /* interpolation + direct force */
-  for (int m = 0; m < o->nm; ++m) {
-    double X = o->X[m], Y = o->Y[m];
-    double rl = 0.0, ul = 0.0, vl = 0.0;
-    for (int j = (int)ceil(Y - h); j <= (int)floor(Y + h); ++j) {
-      for (int i = (int)ceil(X - h); i <= (int)floor(X + h); ++i) {
-        double W = oracle_delta(o->kind, i - X) * oracle_delta(o->kind, j - Y);
-        size_t k = node_of(o, i, j);
-        double r = o->rho[k];
-        double us = (o->mx[k] + 0.5 * o->G[0]) / r; /* u* with G/2 */
-        double vs = (o->my[k] + 0.5 * o->G[1]) / r;
-        rl += W * r;
-        ul += W * us;
-        vl += W * vs;
-      }
-    }
-    o->rho_l[m] = rl;
-    o->ux_l[m] = ul;
-    o->uy_l[m] = vl;
-    o->Fx[m] = 2.0 * rl * (o->Ub[m] - ul); /* eq 20, dt = 1 */
-    o->Fy[m] = 2.0 * rl * (o->Vb[m] - vl);
-    int bad = !isfinite(o->Fx[m]) || !isfinite(o->Fy[m]) || !(sqrt(ul * ul + vl * vl) <= 0.3);
-    if (bad && o->unstable == 0) o->unstable = 1 + o->body_of[m];
+  for (size_t k = 0; k < n; ++k) {
+    o->fx[k] = o->fy[k] = 0.0;
+    o->usx[k] = (o->mx[k] + 0.5 * o->G[0]) / o->rho[k]; /* u* with G/2 */
+    o->usy[k] = (o->my[k] + 0.5 * o->G[1]) / o->rho[k];
   }
+  for (int m = 0; m < o->nm; ++m) o->Fx[m] = o->Fy[m] = 0.0;
 
-  /* spreading with the thickened solid shell: f(x_k) += W F_l drs ds / dh^2 */
-  for (int m = 0; m < o->nm; ++m) {
-    double X = o->X[m], Y = o->Y[m];
-    double s = o->drs * o->ds[o->body_of[m]];
-    for (int j = (int)ceil(Y - h); j <= (int)floor(Y + h); ++j) {
-      for (int i = (int)ceil(X - h); i <= (int)floor(X + h); ++i) {
-        double W = oracle_delta(o->kind, i - X) * oracle_delta(o->kind, j - Y);
-        size_t k = node_of(o, i, j);
-        o->fx[k] += W * o->Fx[m] * s;
-        o->fy[k] += W * o->Fy[m] * s;
+  for (int pass = 0; pass < o->nf; ++pass) {
+    /* interpolation + direct force increment */
+    for (int m = 0; m < o->nm; ++m) {
+      double X = o->X[m], Y = o->Y[m];
+      double rl = 0.0, ul = 0.0, vl = 0.0;
+      for (int j = (int)ceil(Y - h); j <= (int)floor(Y + h); ++j) {
+        for (int i = (int)ceil(X - h); i <= (int)floor(X + h); ++i) {
+          double W = oracle_delta(o->kind, i - X) * oracle_delta(o->kind, j - Y);
+          size_t k = node_of(o, i, j);
+          rl += W * o->rho[k];
+          ul += W * o->usx[k];
+          vl += W * o->usy[k];
+        }
+      }
+      if (pass == 0) {
+        o->rho_l[m] = rl;
+        o->ux_l[m] = ul;
+        o->uy_l[m] = vl;
+        int bad = !(sqrt(ul * ul + vl * vl) <= 0.3);
+        if (bad && o->unstable == 0) o->unstable = 1 + o->body_of[m];
+      }
+      rl = o->rho_l[m];
+      o->dFx[m] = 2.0 * rl * (o->Ub[m] - ul); /* eq 20 / eq 29, dt = 1 */
+      o->dFy[m] = 2.0 * rl * (o->Vb[m] - vl);
+      o->Fx[m] += o->dFx[m];
+      o->Fy[m] += o->dFy[m];
+      int bad = !isfinite(o->Fx[m]) || !isfinite(o->Fy[m]);
+      if (bad && o->unstable == 0) o->unstable = 1 + o->body_of[m];
+    }
+    /* spreading of the increment with the thickened solid shell:
+     * df(x_k) += W dF_l drs ds / dh^2; then u*^k = u*^{k-1} + df / (2 rho) */
+    for (int m = 0; m < o->nm; ++m) {
+      double X = o->X[m], Y = o->Y[m];
+      double s = o->drs * o->ds[o->body_of[m]];
+      for (int j = (int)ceil(Y - h); j <= (int)floor(Y + h); ++j) {
+        for (int i = (int)ceil(X - h); i <= (int)floor(X + h); ++i) {
+          double W = oracle_delta(o->kind, i - X) * oracle_delta(o->kind, j - Y);
+          size_t k = node_of(o, i, j);
+          double dfx = W * o->dFx[m] * s, dfy = W * o->dFy[m] * s;
+          o->fx[k] += dfx;
+          o->fy[k] += dfy;
+          o->usx[k] += 0.5 * dfx / o->rho[k];
+          o->usy[k] += 0.5 * dfy / o->rho[k];
+        }
       }
     }
   }
@@ -636,6 +668,10 @@ int oracle_adjoint(oracle_t *o, long n, const double *hist_bar, double *pop_bar,
   double *guv = (double *)calloc((size_t)(nm > 0 ? nm : 1) * 2, sizeof(double));
   double *gc = (double *)calloc((size_t)(nb > 0 ? nb : 1) * 2, sizeof(double));
   int rc = 0;
+  if (o->nf != 1) { /* the reverse mode covers one forcing pass */
+    rc = -1;
+    goto done;
+  }
   if (!tape || !hist || !Abar || !Bbar || !gbar || !fbx || !fby || !Fbx || !Fby || !gxy || !guv || !gc) {
     rc = -1;
     goto done;

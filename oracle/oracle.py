@@ -61,6 +61,7 @@ def lib():
         L.oracle_delta.argtypes = [ctypes.c_int, ctypes.c_double]
         L.oracle_delta_halfwidth.restype = ctypes.c_double
         L.oracle_delta_halfwidth.argtypes = [ctypes.c_int]
+        L.oracle_set_forcing_passes.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.oracle_delta_deriv.restype = ctypes.c_double
         L.oracle_delta_deriv.argtypes = [ctypes.c_int, ctypes.c_double]
         L.oracle_adjoint.restype = ctypes.c_int
@@ -134,6 +135,10 @@ class OracleSim:
             raise MemoryError("oracle_add_body failed")
         self.body_sizes.append(n)
         return b
+
+    def set_forcing_passes(self, nf):
+        """Forcing passes per step (Algorithm 1 step 3; eqs 29-31 for nf > 1)."""
+        lib().oracle_set_forcing_passes(self._h, int(nf))
 
     def set_marker_velocity(self, b, uv):
         uv = np.ascontiguousarray(uv, dtype=np.float64).reshape(-1, 2)
