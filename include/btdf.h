@@ -86,6 +86,10 @@ extern "C" {
 #define BTDF_OPT_MASK_UNSTABLE 12 /* batches only: 1 (default) = a case that went unstable stops, the others go on */
 #define BTDF_OPT_ROW_ALIGN 13     /* bytes (0 or a power of two 4..4096, default 128): each row starts on this
                                     boundary, pitch = round_up(nx, align) + row pad; only before the first device use */
+#define BTDF_OPT_FORCING_PASSES 14 /* NF in 1..64 (default 1): direct-forcing passes per step (Sec. 2.3, eqs 29-31);
+                                      each pass after the first re-interpolates the velocity corrected by the force
+                                      spread so far and adds 2 rho_l (U - u) to the marker force; stand-alone
+                                      handles only, and btdf_adjoint requires NF = 1 */
 
 typedef struct btdf_grid {
   int32_t nx, ny;               /* nodes, ghost columns included; each >= 8 */

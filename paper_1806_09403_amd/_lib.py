@@ -22,6 +22,7 @@ OPT_LBM_VARIANT, OPT_NUM_VARIANTS, OPT_GRAPH_CHUNK, OPT_XCD_REMAP, OPT_TILE_X, O
 OPT_ROW_PAD, OPT_PLANE_PAD, OPT_INTERIOR_PATH, OPT_OVERLAP, OPT_FORCED_TILES = 7, 8, 9, 10, 11
 OPT_MASK_UNSTABLE = 12
 OPT_ROW_ALIGN = 13
+OPT_FORCING_PASSES = 14
 
 _NAMES = {OK: "BTDF_OK", EINVAL: "BTDF_EINVAL", ENOMEM: "BTDF_ENOMEM", EDEVICE: "BTDF_EDEVICE",
           ESTATE: "BTDF_ESTATE", EUNSTABLE: "BTDF_EUNSTABLE"}

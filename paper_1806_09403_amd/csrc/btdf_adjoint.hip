@@ -46,55 +46,6 @@ struct AdjLayout {
   std::vector<int> toff, tlist, noff, nlist;
 };
 
-// For every marker l and stencil lane k = 4 j + i (i, j < stencil size), the
-// markers whose stencil covers that node, ascending, packed as
-// (marker << 4) | (dx << 2) | dy with (dx, dy) the node's place in the
-// covering marker's stencil.
-void cover_lists(const btdf_t *h, std::vector<int> &off, std::vector<int> &list) {
-  const int nm = h->nm(), S = stencil_size(h->kind);
-  struct Hit {
-    long long node;
-    int marker, lane;
-  };
-  std::vector<Hit> hits;
-  hits.reserve((size_t)nm * S * S);
-  auto origin = [&](int l, int *ox, int *oy) {
-    *ox = stencil_base(h->kind, h->X[l]);
-    *oy = stencil_base(h->kind, h->Y[l]);
-  };
-  auto key = [&](int x, int y) -> long long {
-    if (h->xper()) x = ((x % h->nx) + h->nx) % h->nx;
-    if (h->yper()) y = ((y % h->ny) + h->ny) % h->ny;
-    return (long long)y * h->nx + x;
-  };
-  for (int l = 0; l < nm; ++l) {
-    int ox, oy;
-    origin(l, &ox, &oy);
-    for (int j = 0; j < S; ++j)
-      for (int i = 0; i < S; ++i) hits.push_back({key(ox + i, oy + j), l, (i << 2) | j});
-  }
-  std::sort(hits.begin(), hits.end(), [](const Hit &a, const Hit &b) {
-    return a.node != b.node ? a.node < b.node : a.marker < b.marker;
-  });
-  off.assign((size_t)nm * 16 + 1, 0);
-  list.clear();
-  for (int l = 0; l < nm; ++l) {
-    int ox, oy;
-    origin(l, &ox, &oy);
-    for (int k = 0; k < 16; ++k) {
-      off[(size_t)l * 16 + k] = (int)list.size();
-      const int i = k & 3, j = k >> 2;
-      if (i >= S || j >= S) continue;
-      const long long nk = key(ox + i, oy + j);
-      auto lo = std::lower_bound(hits.begin(), hits.end(), nk,
-                                 [](const Hit &a, long long v) { return a.node < v; });
-      for (auto it = lo; it != hits.end() && it->node == nk; ++it) list.push_back((it->marker << 4) | it->lane);
-    }
-  }
-  off[(size_t)nm * 16] = (int)list.size();
-  if (list.empty()) list.push_back(0);
-}
-
 int64_t default_K(int64_t n) {
   int64_t K = (int64_t)std::ceil(std::sqrt((double)n));
   return std::max<int64_t>(1, K);
@@ -596,6 +547,7 @@ int btdf_adjoint(btdf_t *h, int64_t n_steps, int64_t checkpoint_every, const dou
                  btdf_gradients *grads, void *work, size_t work_bytes, double *ms) {
   if (!h || !grads) return fail(BTDF_EINVAL, "NULL argument");
   if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch");
+  if (h->nf != 1) return fail(BTDF_ESTATE, "the reverse sweep needs one forcing pass per step (NF = 1)");
   if (n_steps < 1) return fail(BTDF_EINVAL, "n_steps must be >= 1");
   if (checkpoint_every < 0) return fail(BTDF_EINVAL, "checkpoint_every must be >= 0");
   if (h->nb() > 0 && !hist_bar) return fail(BTDF_EINVAL, "hist_bar is NULL");

@@ -111,6 +111,55 @@ void bin_markers(const btdf_t *h, int tx, int ty, int ntx, int nty, std::vector<
   }
 }
 
+// For every marker l and stencil lane k = 4 j + i (i, j < stencil size), the
+// markers whose stencil covers that node, ascending, packed as
+// (marker << 4) | (dx << 2) | dy with (dx, dy) the node's place in the
+// covering marker's stencil.
+void cover_lists(const btdf_t *h, std::vector<int> &off, std::vector<int> &list) {
+  const int nm = h->nm(), S = stencil_size(h->kind);
+  struct Hit {
+    long long node;
+    int marker, lane;
+  };
+  std::vector<Hit> hits;
+  hits.reserve((size_t)nm * S * S);
+  auto origin = [&](int l, int *ox, int *oy) {
+    *ox = stencil_base(h->kind, h->X[l]);
+    *oy = stencil_base(h->kind, h->Y[l]);
+  };
+  auto key = [&](int x, int y) -> long long {
+    if (h->xper()) x = ((x % h->nx) + h->nx) % h->nx;
+    if (h->yper()) y = ((y % h->ny) + h->ny) % h->ny;
+    return (long long)y * h->nx + x;
+  };
+  for (int l = 0; l < nm; ++l) {
+    int ox, oy;
+    origin(l, &ox, &oy);
+    for (int j = 0; j < S; ++j)
+      for (int i = 0; i < S; ++i) hits.push_back({key(ox + i, oy + j), l, (i << 2) | j});
+  }
+  std::sort(hits.begin(), hits.end(), [](const Hit &a, const Hit &b) {
+    return a.node != b.node ? a.node < b.node : a.marker < b.marker;
+  });
+  off.assign((size_t)nm * 16 + 1, 0);
+  list.clear();
+  for (int l = 0; l < nm; ++l) {
+    int ox, oy;
+    origin(l, &ox, &oy);
+    for (int k = 0; k < 16; ++k) {
+      off[(size_t)l * 16 + k] = (int)list.size();
+      const int i = k & 3, j = k >> 2;
+      if (i >= S || j >= S) continue;
+      const long long nk = key(ox + i, oy + j);
+      auto lo = std::lower_bound(hits.begin(), hits.end(), nk,
+                                 [](const Hit &a, long long v) { return a.node < v; });
+      for (auto it = lo; it != hits.end() && it->node == nk; ++it) list.push_back((it->marker << 4) | it->lane);
+    }
+  }
+  off[(size_t)nm * 16] = (int)list.size();
+  if (list.empty()) list.push_back(0);
+}
+
 void compute_layout(btdf_t *h) {
   const size_t elt = (size_t)h->prec;
   const int a = h->row_align > 0 ? std::max(1, h->row_align / (int)elt) : 1;
@@ -169,6 +218,19 @@ void compute_layout(btdf_t *h) {
   o = align256(o + list_cap * sizeof(int));
   h->off_tmap = o;
   o = align256(o + (size_t)max_tiles * sizeof(int));
+  // forcing passes beyond the first: covering-marker lists, each stencil
+  // node's rho and u*, and the accumulated marker forces (two copies)
+  h->cover_off.clear();
+  h->cover_list.clear();
+  if (h->nf > 1) cover_lists(h, h->cover_off, h->cover_list);
+  h->off_coff = o;
+  o = align256(o + h->cover_off.size() * sizeof(int));
+  h->off_clist = o;
+  o = align256(o + h->cover_list.size() * sizeof(int));
+  h->off_mdfc = o;
+  o = align256(o + (h->nf > 1 ? 56 * (size_t)std::max(nm, 1) * sizeof(double) : 0));
+  h->off_mdff = o;
+  o = align256(o + (h->nf > 1 ? 4 * (size_t)std::max(nm, 1) * sizeof(double) : 0));
   h->total = o;
 
   h->layout_ok = true;
@@ -237,6 +299,12 @@ IbParams make_ib(const btdf_t *h) {
   ib.body_sdrs = bd + 2 * B;
   ib.hist = h->at<double>(h->off_hist);
   ib.hist_cap = h->hist_cap;
+  ib.nf = h->nf;
+  ib.cover_off = h->at<int>(h->off_coff);
+  ib.cover_list = h->at<int>(h->off_clist);
+  ib.mdf_cache = h->at<double>(h->off_mdfc);
+  ib.mdf_w = ib.mdf_cache + 48 * M;
+  ib.mdf_f = h->at<double>(h->off_mdff);
   return ib;
 }
 
@@ -273,6 +341,8 @@ int upload_bodies(btdf_t *h) {
   put(h->off_toff, h->tile_off.data(), h->tile_off.size() * sizeof(int));
   put(h->off_tlist, h->tile_list.data(), h->tile_list.size() * sizeof(int));
   put(h->off_tmap, h->tile_map.data(), h->tile_map.size() * sizeof(int));
+  put(h->off_coff, h->cover_off.data(), h->cover_off.size() * sizeof(int));
+  put(h->off_clist, h->cover_list.data(), h->cover_list.size() * sizeof(int));
   HIPCHK(hipMemcpyAsync(h->ws + h->off_mk, st.data(), st.size(), hipMemcpyHostToDevice, h->stream));
   if (h->bodies_dirty)
     HIPCHK(hipMemsetAsync(h->ws + h->off_hist, 0,
@@ -1012,6 +1082,15 @@ int btdf_set_option(btdf_t *h, int key, int64_t value) {
       h->row_align = (int)value;
       h->layout_ok = false;
       return ok();
+    case BTDF_OPT_FORCING_PASSES:
+      if (value < 1 || value > 64) return fail(BTDF_EINVAL, "forcing passes must be in 1 .. 64");
+      if (value != h->nf) {
+        h->nf = (int)value;
+        h->layout_ok = false;  // the pass buffers change size
+        h->device_ok = false;
+        drop_graph(h);
+      }
+      return ok();
     default: return fail(BTDF_EINVAL, "unknown or read-only option %d", key);
   }
 }
@@ -1035,6 +1114,7 @@ int btdf_get_option(const btdf_t *h, int key, int64_t *value) {
       return ok();
     case BTDF_OPT_PLANE_PAD: *value = h->plane_pad; return ok();
     case BTDF_OPT_ROW_ALIGN: *value = h->row_align; return ok();
+    case BTDF_OPT_FORCING_PASSES: *value = h->nf; return ok();
     default: return fail(BTDF_EINVAL, "unknown option %d", key);
   }
 }

@@ -135,6 +135,12 @@ struct IbParams {
   double *hist;  // [cap][nb][3]
   int hist_cap;
   int *slot;     // ring entry of the current step (written by the marker kernel)
+  // forcing passes per step (Algorithm 1 step 3; eqs 29-31 when nf > 1)
+  int nf;
+  const int *cover_off, *cover_list;  // per marker and stencil lane: covering markers (see AdjParams)
+  double *mdf_cache;                  // [nm][16][3]: rho, u*_x, u*_y at each stencil node
+  double *mdf_w;                      // [nm][8]: x then y delta weights in FP64
+  double *mdf_f;                      // [2][nm][2]: accumulated force after the previous / this pass
 };
 
 // one case of a batch: its parameters and its two population buffers

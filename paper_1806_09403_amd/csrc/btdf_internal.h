@@ -46,6 +46,8 @@ struct btdf_sim {
   std::vector<int> tile_map;  // tiles no marker touches first, then the forced tiles
   int n_free = 0, n_forced = 0;
   int overlap = 0;            // run the marker kernel beside the lattice launch of the free tiles
+  int nf = 1;                 // forcing passes per step
+  std::vector<int> cover_off, cover_list;  // covering markers per stencil node (nf > 1)
   // device memory
   char *ws = nullptr;
   size_t ws_bytes = 0;
@@ -55,7 +57,8 @@ struct btdf_sim {
   long long plane = 0;
   size_t off_pop[2] = {0, 0}, off_ctl = 0, grid_bytes = 0;
   size_t off_hist = 0, off_mk = 0, off_mkw = 0, off_mkixy = 0, off_mkbody = 0, off_body = 0, off_boff = 0,
-         off_toff = 0, off_tlist = 0, off_tmap = 0, total = 0;
+         off_toff = 0, off_tlist = 0, off_tmap = 0, off_coff = 0, off_clist = 0, off_mdfc = 0, off_mdff = 0,
+         total = 0;
   bool layout_ok = false;  // host layout current for bodies and tiles
   bool device_ok = false;  // body part uploaded into the workspace
   bool state_ok = false;   // populations hold a state
@@ -90,6 +93,7 @@ bool valid_kind(int k);
 void drop_graph(btdf_t *h);
 void compute_layout(btdf_t *h);
 void bin_markers(const btdf_t *h, int tx, int ty, int ntx, int nty, std::vector<int> &off, std::vector<int> &list);
+void cover_lists(const btdf_t *h, std::vector<int> &off, std::vector<int> &list);
 LbmParams make_params(const btdf_t *h);
 IbParams make_ib(const btdf_t *h);
 int ensure_device(btdf_t *h);

@@ -60,6 +60,7 @@ __device__ __forceinline__ void ib_marker(const T *__restrict__ A, const LbmPara
   const int gl = (int)threadIdx.x & ~15 & 63;  // first lane of the group within the wave
   const double phx = __shfl(ph, gl + a, 64);
   const double phy = __shfl(ph, gl + 4 + c, 64);
+  if (act && node < 8 && ib.nf > 1) ib.mdf_w[8 * (long long)l + node] = ph;
   if (act) {
     T *mw = reinterpret_cast<T *>(ib.mk_w) + 10 * (long long)l;
     if (c == 0) mw[a] = (T)phx;
@@ -93,9 +94,17 @@ __device__ __forceinline__ void ib_marker(const T *__restrict__ A, const LbmPara
       }
       const double rho = 1.0 + drho;
       const double inv = 1.0 / rho;
+      const double usx = (mx + p.urx + 0.5 * p.Gx) * inv;  // the stored values' first moment is m - u_ref
+      const double usy = (my + p.ury + 0.5 * p.Gy) * inv;
       wr = W * rho;
-      wu = W * ((mx + p.urx + 0.5 * p.Gx) * inv);  // the stored values' first moment is m - u_ref
-      wv = W * ((my + p.ury + 0.5 * p.Gy) * inv);
+      wu = W * usx;
+      wv = W * usy;
+      if (ib.nf > 1) {  // later forcing passes start from the node's rho and u*
+        double *cc = ib.mdf_cache + (16 * (long long)l + node) * 3;
+        cc[0] = rho;
+        cc[1] = usx;
+        cc[2] = usy;
+      }
     }
   }
 #pragma unroll
@@ -118,7 +127,64 @@ __device__ __forceinline__ void ib_marker(const T *__restrict__ A, const LbmPara
     mw[9] = (T)(Fy * sd);
     ib.mk_ixy[2 * l] = p.xper ? ((bx % p.nx) + p.nx) % p.nx : bx;
     ib.mk_ixy[2 * l + 1] = p.yper ? ((by % p.ny) + p.ny) % p.ny : by;
+    if (ib.nf > 1) {
+      ib.mdf_f[2 * (long long)l] = Fx;
+      ib.mdf_f[2 * (long long)l + 1] = Fy;
+    }
     if (!isfinite(Fx) || !isfinite(Fy) || !(sqrt(wu * wu + wv * wv) <= 0.3)) p.flag[0] = 1 + ib.mk_body[l];
+  }
+}
+
+// Forcing pass k >= 1 (eqs 29-31): u*^k = u* + f^k / (2 rho) at the stencil
+// nodes, with f^k the spread of the force accumulated over passes 0 .. k-1
+// (formed from the markers covering each node with the FP64 weights the
+// first pass recorded); then dF = 2 rho_l (U_b - D_I u*^k) and F += dF. The last pass
+// leaves F and drs ds F for the lattice kernel. 16 lanes per marker.
+template <typename T>
+__global__ __launch_bounds__(256) void ib_pass_kernel(LbmParams p, IbParams ib, int k, int last) {
+  const int blk = p.xcd_remap ? xcd_tile((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  const int l = blk * 16 + ((int)threadIdx.x >> 4);
+  const int node = (int)threadIdx.x & 15;
+  const bool act = l < ib.nm;
+  const int S = stencil_size(p.kind);
+  const int a = node & 3, c = node >> 2;
+  const double *fin = ib.mdf_f + (long long)((k - 1) & 1) * 2 * ib.nm;
+  double *fout = ib.mdf_f + (long long)(k & 1) * 2 * ib.nm;
+  double wu = 0.0, wv = 0.0;
+  if (act && a < S && c < S) {
+    const double W = ib.mdf_w[8 * (long long)l + a] * ib.mdf_w[8 * (long long)l + 4 + c];
+    const double *cc = ib.mdf_cache + (16 * (long long)l + node) * 3;
+    double fx = 0.0, fy = 0.0;
+    for (int e = ib.cover_off[16 * l + node]; e < ib.cover_off[16 * l + node + 1]; ++e) {
+      const int v = ib.cover_list[e];
+      const long long m = v >> 4;
+      const double Wm = ib.mdf_w[8 * m + ((v >> 2) & 3)] * ib.mdf_w[8 * m + 4 + (v & 3)] * ib.sdrs[m];
+      fx += Wm * fin[2 * m];
+      fy += Wm * fin[2 * m + 1];
+    }
+    wu = W * (cc[1] + 0.5 * fx / cc[0]);
+    wv = W * (cc[2] + 0.5 * fy / cc[0]);
+  }
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) {
+    wu += __shfl_xor(wu, off, 16);
+    wv += __shfl_xor(wv, off, 16);
+  }
+  if (act && node == 0) {
+    const double rl = ib.rho_l[l];
+    const double Fx = fin[2 * (long long)l] + 2.0 * rl * (ib.U[l] - wu);
+    const double Fy = fin[2 * (long long)l + 1] + 2.0 * rl * (ib.V[l] - wv);
+    fout[2 * (long long)l] = Fx;
+    fout[2 * (long long)l + 1] = Fy;
+    if (!isfinite(Fx) || !isfinite(Fy)) p.flag[0] = 1 + ib.mk_body[l];
+    if (last) {
+      ib.Fx[l] = Fx;
+      ib.Fy[l] = Fy;
+      const double sd = ib.sdrs[l];
+      T *mw = reinterpret_cast<T *>(ib.mk_w) + 10 * (long long)l;
+      mw[8] = (T)(Fx * sd);
+      mw[9] = (T)(Fy * sd);
+    }
   }
 }
 
@@ -559,6 +625,13 @@ hipError_t launch_ib(int prec, const void *A, const LbmParams &p, const IbParams
     hipLaunchKernelGGL(ib_kernel<float>, dim3(blocks), dim3(256), 0, s, (const float *)A, p, ib);
   else
     hipLaunchKernelGGL(ib_kernel<double>, dim3(blocks), dim3(256), 0, s, (const double *)A, p, ib);
+  for (int k = 1; k < ib.nf; ++k) {  // further forcing passes
+    const int last = k == ib.nf - 1;
+    if (prec == 4)
+      hipLaunchKernelGGL(ib_pass_kernel<float>, dim3(blocks), dim3(256), 0, s, p, ib, k, last);
+    else
+      hipLaunchKernelGGL(ib_pass_kernel<double>, dim3(blocks), dim3(256), 0, s, p, ib, k, last);
+  }
   return hipGetLastError();
 }
 

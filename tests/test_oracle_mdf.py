@@ -19,6 +19,10 @@ def make(kind, thickening, nf, nx=32, ny=32, u0=(0.03, 0.01), D=8.0):
     o = OracleSim(nx, ny, W.FULLY_PERIODIC, 0.7, kind, thickening, (0.0, 0.0), (0.0, 0.0), (1.0, *u0))
     b = W.cylinder_body(15.3, 16.6, D)
     o.add_body(b.xy, None, b.cx, b.cy, b.ds)
+    # a non-uniform density, so that the 1/rho of the corrected velocity matters
+    y, x = np.mgrid[0:ny, 0:nx]
+    rho = 1.0 + 0.05 * np.sin(2 * np.pi * x / nx) * np.cos(2 * np.pi * y / ny)
+    o.init_equilibrium(np.full((ny, nx), u0[0]), np.full((ny, nx), u0[1]), rho)
     o.set_forcing_passes(nf)
     return o, b
 
