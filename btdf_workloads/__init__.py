@@ -18,6 +18,7 @@ import numpy as np
 
 # boundary kinds (west, east, south, north)
 PERIODIC, VELOCITY_INLET, ZERO_GRADIENT_OUTLET, BOUNCEBACK_WALL = 0, 1, 2, 3
+FREE_SLIP_WALL, CONVECTIVE_OUTLET = 4, 5
 # regularised delta kinds: 2-point (eq 37), 3-point (eq 38), 4-point (eq 39), cosine 4-point
 LINEAR2, ROMA3, PESKIN4, COS4 = 2, 3, 4, 5
 KIND_NAMES = {LINEAR2: "linear2", ROMA3: "roma3", PESKIN4: "peskin4", COS4: "cos4"}
@@ -27,6 +28,8 @@ PAPER_THICKENING = {LINEAR2: 1.4, ROMA3: 1.9, PESKIN4: 2.6, COS4: 2.6}
 
 CHANNEL = (VELOCITY_INLET, ZERO_GRADIENT_OUTLET, PERIODIC, PERIODIC)
 FULLY_PERIODIC = (PERIODIC, PERIODIC, PERIODIC, PERIODIC)
+# the far-field boundaries of the paper's cylinder runs (Section 5.2)
+FAR_FIELD = (VELOCITY_INLET, CONVECTIVE_OUTLET, FREE_SLIP_WALL, FREE_SLIP_WALL)
 
 
 @dataclass

@@ -36,6 +36,10 @@
  *    collision; a zero-gradient outlet is a ghost column i = nx-1 copied
  *    from column nx-2; walls (south/north only) are halfway bounce-back;
  *    periodic directions wrap the node index;
+ *  - the far-field conditions of the cylinder runs (Section 5.2): a
+ *    free-slip wall (du_x/dy = 0, u_y = 0) is a specular reflection
+ *    halfway between the edge row and the wall, and a convective outlet
+ *    advects the ghost column with the inflow speed, implicit upwind;
  *  - stencil nodes are all nodes whose distance to the marker lies inside
  *    the support of the delta function (weights at the edge are zero).
  *
@@ -50,6 +54,8 @@
 #define ORC_VELOCITY_INLET 1
 #define ORC_ZERO_GRADIENT_OUTLET 2
 #define ORC_BOUNCEBACK_WALL 3
+#define ORC_FREE_SLIP_WALL 4
+#define ORC_CONVECTIVE_OUTLET 5
 
 #define ORC_LINEAR2 2
 #define ORC_ROMA3 3
@@ -62,6 +68,13 @@ static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 static const double WQ[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
                              1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
                              1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+/* Mirror image of q in a wall parallel to x: the q' with e_q' = (e_qx, -e_qy). */
+static int mirror_y(int q) {
+  for (int p = 0; p < 9; ++p)
+    if (EX[p] == EX[q] && EY[p] == -EY[q]) return p;
+  return -1;
+}
 
 /* Opposite direction of q: the q' with e_q' = -e_q. */
 static int opposite(int q) {
@@ -284,6 +297,12 @@ static void stream(oracle_t *o) {
             sj = wrap(sj, ny);
             if (x_periodic(o)) si = wrap(si, nx);
             val = o->A[idx(o, q, sj, si)];
+          } else if (o->bc[sj < 0 ? 2 : 3] == ORC_FREE_SLIP_WALL) {
+            /* specular reflection halfway between the edge row and the wall:
+             * the population that left the neighbouring column towards the
+             * wall returns with its normal component reversed */
+            if (x_periodic(o)) si = wrap(si, nx);
+            val = o->A[idx(o, mirror_y(q), j, si)];
           } else {
             /* halfway bounce-back: the population that left towards the wall returns */
             val = o->A[idx(o, qb, j, i)];
@@ -454,6 +473,14 @@ static void boundary_columns(oracle_t *o) {
   if (o->bc[1] == ORC_ZERO_GRADIENT_OUTLET) {
     for (int j = 0; j < o->ny; ++j)
       for (int q = 0; q < 9; ++q) o->A[idx(o, q, j, nx - 1)] = o->A[idx(o, q, j, nx - 2)];
+  }
+  if (o->bc[1] == ORC_CONVECTIVE_OUTLET) {
+    /* d(phi)/dt + U d(phi)/dx = 0 at the outlet, implicit upwind in time
+     * and space with U the inflow speed: phi_N(t+1) = (phi_N(t) + U phi_{N-1}(t+1)) / (1 + U) */
+    double U = o->uin[0];
+    for (int j = 0; j < o->ny; ++j)
+      for (int q = 0; q < 9; ++q)
+        o->A[idx(o, q, j, nx - 1)] = (o->A[idx(o, q, j, nx - 1)] + U * o->A[idx(o, q, j, nx - 2)]) / (1.0 + U);
   }
 }
 
@@ -668,7 +695,8 @@ int oracle_adjoint(oracle_t *o, long n, const double *hist_bar, double *pop_bar,
   double *guv = (double *)calloc((size_t)(nm > 0 ? nm : 1) * 2, sizeof(double));
   double *gc = (double *)calloc((size_t)(nb > 0 ? nb : 1) * 2, sizeof(double));
   int rc = 0;
-  if (o->nf != 1) { /* the reverse mode covers one forcing pass */
+  if (o->nf != 1 || o->bc[1] == ORC_CONVECTIVE_OUTLET || o->bc[2] == ORC_FREE_SLIP_WALL) {
+    /* the reverse mode covers one forcing pass and the bounce-back / zero-gradient boundaries */
     rc = -1;
     goto done;
   }
