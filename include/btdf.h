@@ -49,17 +49,27 @@ extern "C" {
 #define BTDF_EUNSTABLE (-5) /* the run went unstable (see btdf_step) */
 
 /* ---- boundary kinds (btdf_grid.bc_*) ----
- * x ends: both PERIODIC, or VELOCITY_INLET (west) + ZERO_GRADIENT_OUTLET (east).
- *   The channel ends are ghost columns i = 0 and i = nx-1 that are neither
- *   collided nor forced. After each collision the inlet ghost is set to the
- *   equilibrium (eq 6) at the inflow velocity with the density of column 1,
- *   and the outlet ghost copies column nx-2.
- * y ends: both PERIODIC, or both BOUNCEBACK_WALL (halfway bounce-back,
- *   walls at y = -1/2 and y = ny - 1/2). */
+ * x ends: both PERIODIC, or VELOCITY_INLET (west) + ZERO_GRADIENT_OUTLET or
+ *   CONVECTIVE_OUTLET (east). The channel ends are ghost columns i = 0 and
+ *   i = nx-1 that are neither collided nor forced. After each collision the
+ *   inlet ghost is set to the equilibrium (eq 6) at the inflow velocity with
+ *   the density of column 1. A zero-gradient outlet ghost copies column
+ *   nx-2; a convective outlet ghost follows d/dt + U d/dx = 0 with U the
+ *   inflow speed (inflow_ux >= 0), implicit upwind:
+ *   ghost(t+1) = (ghost(t) + U column_{nx-2}(t+1)) / (1 + U)
+ *   (the far-field outflow of the paper's cylinder runs, Section 5.2).
+ * y ends: both PERIODIC, or both BOUNCEBACK_WALL (halfway bounce-back), or
+ *   both FREE_SLIP_WALL (du_x/dy = 0, u_y = 0; the far field of Section 5.2):
+ *   a specular reflection, the population that left the upstream column
+ *   towards the wall returns with its y component reversed. Walls sit at
+ *   y = -1/2 and y = ny - 1/2. btdf_adjoint supports PERIODIC,
+ *   BOUNCEBACK_WALL and ZERO_GRADIENT_OUTLET only. */
 #define BTDF_PERIODIC 0
 #define BTDF_VELOCITY_INLET 1
 #define BTDF_ZERO_GRADIENT_OUTLET 2
 #define BTDF_BOUNCEBACK_WALL 3
+#define BTDF_FREE_SLIP_WALL 4
+#define BTDF_CONVECTIVE_OUTLET 5
 
 /* ---- regularised delta functions (Section 4.3) ----
  * LINEAR2: 2-point, eq 37;  ROMA3: 3-point, eq 38;  PESKIN4: 4-point, eq 39;
@@ -93,8 +103,8 @@ extern "C" {
 
 typedef struct btdf_grid {
   int32_t nx, ny;               /* nodes, ghost columns included; each >= 8 */
-  int32_t bc_west, bc_east;     /* BTDF_PERIODIC pair or VELOCITY_INLET + ZERO_GRADIENT_OUTLET */
-  int32_t bc_south, bc_north;   /* BTDF_PERIODIC pair or BOUNCEBACK_WALL pair */
+  int32_t bc_west, bc_east;     /* BTDF_PERIODIC pair or VELOCITY_INLET + ZERO_GRADIENT / CONVECTIVE_OUTLET */
+  int32_t bc_south, bc_north;   /* BTDF_PERIODIC, BOUNCEBACK_WALL or FREE_SLIP_WALL pair */
   double inflow_ux, inflow_uy;  /* velocity of the inlet ghost column */
   double body_force_x;          /* uniform body-force density G (force per node) */
   double body_force_y;

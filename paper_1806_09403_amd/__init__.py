@@ -6,8 +6,9 @@ include/btdf.h); ``api`` exposes each C call under its own name and ``Sim``
 wraps one simulation with torch-owned device memory and stream.
 """
 from ._lib import (BtdfError, BtdfUnstable, COS4, LINEAR2, PESKIN4, ROMA3, PERIODIC, VELOCITY_INLET,
-                   ZERO_GRADIENT_OUTLET, BOUNCEBACK_WALL, load)
+                   ZERO_GRADIENT_OUTLET, BOUNCEBACK_WALL, FREE_SLIP_WALL, CONVECTIVE_OUTLET, load)
 from .sim import BatchSim, Sim
 
 __all__ = ["Sim", "BatchSim", "BtdfError", "BtdfUnstable", "load", "COS4", "LINEAR2", "PESKIN4", "ROMA3",
-           "PERIODIC", "VELOCITY_INLET", "ZERO_GRADIENT_OUTLET", "BOUNCEBACK_WALL"]
+           "PERIODIC", "VELOCITY_INLET", "ZERO_GRADIENT_OUTLET", "BOUNCEBACK_WALL", "FREE_SLIP_WALL",
+           "CONVECTIVE_OUTLET"]

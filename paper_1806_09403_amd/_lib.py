@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(PKG, "libbtdf.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSTABLE = 0, -1, -2, -3, -4, -5
 PERIODIC, VELOCITY_INLET, ZERO_GRADIENT_OUTLET, BOUNCEBACK_WALL = 0, 1, 2, 3
+FREE_SLIP_WALL, CONVECTIVE_OUTLET = 4, 5
 LINEAR2, ROMA3, PESKIN4, COS4 = 2, 3, 4, 5
 OPT_LBM_VARIANT, OPT_NUM_VARIANTS, OPT_GRAPH_CHUNK, OPT_XCD_REMAP, OPT_TILE_X, OPT_TILE_Y = 1, 2, 3, 4, 5, 6
 OPT_ROW_PAD, OPT_PLANE_PAD, OPT_INTERIOR_PATH, OPT_OVERLAP, OPT_FORCED_TILES = 7, 8, 9, 10, 11

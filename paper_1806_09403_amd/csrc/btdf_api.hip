@@ -247,7 +247,9 @@ LbmParams make_params(const btdf_t *h) {
   p.xper = h->xper();
   p.yper = h->yper();
   p.inlet = h->bc[0] == BTDF_VELOCITY_INLET;
-  p.outlet = h->bc[1] == BTDF_ZERO_GRADIENT_OUTLET;
+  p.outlet = h->bc[1] == BTDF_ZERO_GRADIENT_OUTLET ? 1 : (h->bc[1] == BTDF_CONVECTIVE_OUTLET ? 2 : 0);
+  p.slip = h->bc[2] == BTDF_FREE_SLIP_WALL;
+  p.uconv = h->uin[0];
   p.i0 = h->i0();
   p.i1 = h->i1();
   p.omega = 1.0 / h->tau;
@@ -623,11 +625,15 @@ int btdf_create(const btdf_grid *g, double tau, int delta_kind, double thickenin
   if (!(thickening > 0.0) || !std::isfinite(thickening))
     return fail(BTDF_EINVAL, "thickening must be > 0 (got %g)", thickening);
   const bool xp = g->bc_west == BTDF_PERIODIC && g->bc_east == BTDF_PERIODIC;
-  const bool xc = g->bc_west == BTDF_VELOCITY_INLET && g->bc_east == BTDF_ZERO_GRADIENT_OUTLET;
+  const bool xc = g->bc_west == BTDF_VELOCITY_INLET &&
+                  (g->bc_east == BTDF_ZERO_GRADIENT_OUTLET || g->bc_east == BTDF_CONVECTIVE_OUTLET);
   const bool yp = g->bc_south == BTDF_PERIODIC && g->bc_north == BTDF_PERIODIC;
-  const bool yw = g->bc_south == BTDF_BOUNCEBACK_WALL && g->bc_north == BTDF_BOUNCEBACK_WALL;
+  const bool yw = g->bc_south == g->bc_north &&
+                  (g->bc_south == BTDF_BOUNCEBACK_WALL || g->bc_south == BTDF_FREE_SLIP_WALL);
   if (!(xp || xc)) return fail(BTDF_EINVAL, "x ends must be a periodic pair or inlet (west) + outlet (east)");
-  if (!(yp || yw)) return fail(BTDF_EINVAL, "y ends must be a periodic pair or a bounce-back wall pair");
+  if (!(yp || yw)) return fail(BTDF_EINVAL, "y ends must be a periodic pair or a pair of walls of one kind");
+  if (g->bc_east == BTDF_CONVECTIVE_OUTLET && !(g->inflow_ux >= 0.0))
+    return fail(BTDF_EINVAL, "a convective outlet needs an inflow speed >= 0 (got %g)", g->inflow_ux);
   if (g->precision != 4 && g->precision != 8) return fail(BTDF_EINVAL, "precision must be 4 or 8");
   if (g->history_capacity < 0) return fail(BTDF_EINVAL, "history_capacity must be >= 0");
   if (g->flags != 0) return fail(BTDF_EINVAL, "flags must be 0");

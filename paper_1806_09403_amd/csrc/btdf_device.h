@@ -19,6 +19,10 @@ __host__ __device__ __forceinline__ constexpr int ey(int q) {
 __host__ __device__ __forceinline__ constexpr double wq(int q) {
   return q == 0 ? 4.0 / 9.0 : (q < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
 }
+// direction with (e_x, -e_y): the image of e_q in a wall parallel to x
+__host__ __device__ __forceinline__ constexpr int mir_y(int q) {
+  return q == 2 ? 4 : q == 4 ? 2 : q == 5 ? 8 : q == 8 ? 5 : q == 6 ? 7 : q == 7 ? 6 : q;
+}
 // direction with e_opp = -e_q
 __host__ __device__ __forceinline__ constexpr int opp(int q) {
   return q == 0 ? 0 : (q < 5 ? ((q + 1) % 4) + 1 : ((q - 3) % 4) + 5);
@@ -93,7 +97,9 @@ struct LbmParams {
   int pitch;        // elements between rows
   long long plane;  // elements between population planes
   int xper, yper;   // periodic flags
-  int inlet, outlet;
+  int inlet, outlet;  // outlet: 1 zero-gradient, 2 convective (speed uconv)
+  int slip;           // south/north walls: 0 bounce-back, 1 free-slip (specular)
+  double uconv;
   int i0, i1;       // fluid columns (inclusive)
   double omega;     // 1 / tau
   double guo;       // 1 - 1 / (2 tau)
@@ -254,6 +260,13 @@ __device__ __forceinline__ T pull(const T *__restrict__ A, const LbmParams &p, i
   if (p.yper) {
     sy = sy < 0 ? sy + p.ny : (sy >= p.ny ? sy - p.ny : sy);
   } else if (sy < 0 || sy >= p.ny) {
+    if (p.slip) {
+      // specular: the mirror population of the upstream column, moved from
+      // its offset c_mir to c_q (feq difference of (e_x, -e_y) and e_q)
+      if (p.xper) sx = sx < 0 ? sx + p.nx : (sx >= p.nx ? sx - p.nx : sx);
+      return load<T, NTL>(&A[(long long)mir_y(q) * p.plane + (long long)y * p.pitch + sx]) +
+             (T)(-6.0 * wq(q) * ey(q) * p.ury * (1.0 + 3.0 * ex(q) * p.urx));
+    }
     // the stored opposite population, moved from its offset c_opp to c_q
     return load<T, NTL>(&A[(long long)opp(q) * p.plane + (long long)y * p.pitch + x]) +
            (T)(-6.0 * wq(q) * (ex(q) * p.urx + ey(q) * p.ury));

@@ -310,8 +310,9 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
   constexpr int WX = BX >= 64 ? 64 : BX;
   const int yw = __builtin_amdgcn_readfirstlane(y - (BX >= 64 ? 0 : ((int)threadIdx.y % WR)));
   const int xw = __builtin_amdgcn_readfirstlane(BX >= 64 ? txi * TX + ((int)threadIdx.x & ~63) : txi * TX);
+  // (a wave that holds column nx-2 of a channel also writes the outlet ghost)
   const bool interior = p.interior && yw >= 1 && yw + WR <= p.ny - 1 && xw >= 1 &&
-                        xw + WX + (NPT - 1) * BX <= p.nx - 1;
+                        xw + WX + (NPT - 1) * BX <= p.nx - 1 - (p.outlet ? 1 : 0);
   const unsigned rowoff = (unsigned)(y - yw) * (unsigned)p.pitch;
 
   const T omega = (T)p.omega, guo = (T)p.guo;
@@ -368,9 +369,19 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
         B[(long long)q * p.plane + gb] = (T)wq(q) * (dr * (T)(1.0 + pin) + (T)(pin - pref));
       }
     }
-    if (p.outlet && x == p.nx - 2) {
+    if (p.outlet == 1 && x == p.nx - 2) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) B[(long long)q * p.plane + base + 1] = out[q];
+    }
+    if (p.outlet == 2 && x == p.nx - 2) {
+      // convective: d/dt + U d/dx = 0 on the ghost, implicit upwind (the
+      // reference offsets cancel: the weights sum to one)
+      const T U = (T)p.uconv, den = (T)(1.0 + p.uconv);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const long long o = (long long)q * p.plane + base + 1;
+        B[o] = (A[o] + U * out[q]) / den;
+      }
     }
   }
   if (bad) p.flag[0] = -1;

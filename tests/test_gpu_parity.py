@@ -160,6 +160,26 @@ def test_every_launch_shape_is_bit_identical():
             assert np.array_equal(hist, ref_hist), (v, remap, interior, overlap)
 
 
+def test_interior_path_keeps_the_outlet_column():
+    """nx = 513 puts column nx-2 at the end of a wave for every launch shape;
+    with the interior path on, that wave must still write the outlet ghost."""
+    from paper_1806_09403_amd import _lib
+    log("interior path at the outlet column, every launch shape")
+    c = W.random_case(12, nx=513, ny=20, kind=W.ROMA3, bc=W.CHANNEL, n_bodies=1, D_range=(3.0, 4.0))
+    o = oracle_of(c)
+    o.step(3)
+    ref = o.populations()
+    g0 = gpu_of(c, precision=8)
+    for v in range(g0.get_option(_lib.OPT_NUM_VARIANTS)):
+        g = gpu_of(c, precision=8)
+        g.set_option(_lib.OPT_LBM_VARIANT, v)
+        g.set_option(_lib.OPT_INTERIOR_PATH, 1)
+        g.step(3)
+        assert np.max(np.abs(g.populations() - ref)) < 1e-14, v
+        g.close()
+    g0.close()
+
+
 def test_graph_replay_is_bit_identical():
     from paper_1806_09403_amd import _lib
     c = W.random_case(9, nx=120, ny=64, n_bodies=2)
