@@ -219,6 +219,16 @@ int btdf_set_populations(btdf_t *h, const double *src);
 int btdf_get_marker_data(btdf_t *h, double *rho_l, double *ux_l, double *uy_l, double *Fx,
                          double *Fy);
 
+/* Velocity at every marker after the last step (host arrays of length =
+ * total markers): the corrected velocity the collision used (eq 11, with
+ * the body force and the immersed-boundary force of that step)
+ * interpolated at the marker (eq 12). At rest markers its root mean square
+ * is the boundary error of eq 45; in general U_b - u_b is the slip. Needs
+ * a step since the state or the bodies last changed (ESTATE otherwise);
+ * stand-alone handles only. Allocates a temporary device buffer for the
+ * covering-marker lists. Synchronising. */
+int btdf_marker_velocity(btdf_t *h, double *ux, double *uy);
+
 /* Checkpoint: the populations as the handle stores them (its precision, as
  * deviations from the equilibrium at the initial velocity of btdf_grid)
  * plus the step counter. btdf_state_bytes gives the size; save writes it

@@ -83,6 +83,7 @@ SIGNATURES = {
     "btdf_get_populations": (ctypes.c_int, [_vp, _dp]),
     "btdf_set_populations": (ctypes.c_int, [_vp, _dp]),
     "btdf_get_marker_data": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp, _dp]),
+    "btdf_marker_velocity": (ctypes.c_int, [_vp, _dp, _dp]),
     "btdf_state_bytes": (ctypes.c_size_t, [_vp]),
     "btdf_save": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "btdf_load": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),

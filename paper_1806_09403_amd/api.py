@@ -122,6 +122,13 @@ def btdf_get_marker_data(h):
     return dict(zip(["rho", "ux", "uy", "Fx", "Fy"], [a[:nm] for a in arrs]))
 
 
+def btdf_marker_velocity(h):
+    nm = btdf_counts(h)[1]
+    u, v = np.empty(max(nm, 1)), np.empty(max(nm, 1))
+    check(load().btdf_marker_velocity(h, dptr(u), dptr(v)))
+    return u[:nm], v[:nm]
+
+
 def btdf_state_bytes(h):
     return int(load().btdf_state_bytes(h))
 

@@ -352,6 +352,7 @@ int upload_bodies(btdf_t *h) {
   HIPCHK(hipStreamSynchronize(h->stream));  // the staging buffer may change after return
   h->device_ok = true;
   h->bodies_dirty = false;
+  h->stepped = false;  // the marker arrays start at zero again
   return ok();
 }
 
@@ -364,6 +365,7 @@ int init_state(btdf_t *h) {
   h->steps = 0;
   h->hist_read = 0;
   h->state_ok = true;
+  h->stepped = false;
   return ok();
 }
 
@@ -581,6 +583,7 @@ int add_body_impl(btdf_t *h, int n, const double *xy, const double *uv, double c
   } catch (...) {
     return fail(BTDF_ENOMEM, "out of host memory");
   }
+  h->stepped = false;
   h->layout_ok = false;
   h->device_ok = false;
   h->bodies_dirty = true;
@@ -756,6 +759,7 @@ int btdf_step(btdf_t *h, int64_t n) {
     h->cur ^= 1;
     h->steps++;
   }
+  h->stepped = true;
   return ok();
 }
 
@@ -805,6 +809,7 @@ int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm) {
   for (auto &e : ev)
     if (e) (void)hipEventDestroy(e);
   if (rc) return rc;
+  h->stepped = true;
   *ms_ib = h->nb() ? tib / (double)n : 0.0;
   *ms_lbm = tlbm / (double)n;
   return ok();
@@ -910,6 +915,7 @@ int btdf_init_equilibrium(btdf_t *h, const double *rho, const double *ux, const 
   LbmParams p = make_params(h);
   HIPCHK(launch_init_eq(h->prec, h->ws + h->off_pop[h->cur], p, st + 2 * n, st, st + n, h->rho0, rho != nullptr,
                         h->stream));
+  h->stepped = false;
   if ((rc = clear_flag(h))) return rc;
   HIPCHK(hipStreamSynchronize(h->stream));
   return ok();
@@ -957,6 +963,7 @@ int btdf_set_populations(btdf_t *h, const double *src) {
     HIPCHK(launch_f64_to_plane(h->prec, h->ws + h->off_pop[h->cur], p, q, st, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
   }
+  h->stepped = false;
   if ((rc = clear_flag(h))) return rc;
   HIPCHK(hipStreamSynchronize(h->stream));
   return ok();
@@ -971,6 +978,42 @@ int btdf_get_marker_data(btdf_t *h, double *rho_l, double *ux_l, double *uy_l, d
   double *outs[5] = {Fx, Fy, rho_l, ux_l, uy_l};
   for (int k = 0; k < 5; ++k)
     if (outs[k] && nm) HIPCHK(hipMemcpy(outs[k], h->ws + h->off_mk + (5 + k) * M * d, nm * d, hipMemcpyDeviceToHost));
+  return ok();
+}
+
+int btdf_marker_velocity(btdf_t *h, double *ux, double *uy) {
+  if (!h || !ux || !uy) return fail(BTDF_EINVAL, "NULL argument");
+  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch");
+  // the marker arrays on the device must be those of the last step, in the current layout
+  if (!h->stepped || !h->layout_ok || !h->device_ok || !h->ws)
+    return fail(BTDF_ESTATE, "no step since the state, the bodies or the layout last changed");
+  const int nm = h->nm();
+  if (nm == 0) return ok();
+  std::vector<int> off, list;
+  cover_lists(h, off, list);
+  const size_t b_off = off.size() * sizeof(int), b_list = list.size() * sizeof(int);
+  const size_t o_list = align256(b_off), o_out = o_list + align256(b_list);
+  const size_t bytes = o_out + 2 * (size_t)nm * sizeof(double);
+  char *buf = nullptr;
+  hipError_t e = hipMalloc((void **)&buf, bytes);
+  if (e != hipSuccess) return fail(BTDF_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  const LbmParams p = make_params(h);
+  const IbParams ib = make_ib(h);
+  double *out = reinterpret_cast<double *>(buf + o_out);
+  e = hipMemcpyAsync(buf, off.data(), b_off, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(buf + o_list, list.data(), b_list, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = launch_marker_velocity(h->prec, h->ws + h->off_pop[h->cur], p, ib, reinterpret_cast<const int *>(buf),
+                               reinterpret_cast<const int *>(buf + o_list), out, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  std::vector<double> host(2 * (size_t)nm);
+  if (e == hipSuccess) e = hipMemcpy(host.data(), out, host.size() * sizeof(double), hipMemcpyDeviceToHost);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return fail(BTDF_EDEVICE, "marker velocity: %s", hipGetErrorString(e));
+  for (int l = 0; l < nm; ++l) {
+    ux[l] = host[2 * (size_t)l];
+    uy[l] = host[2 * (size_t)l + 1];
+  }
   return ok();
 }
 
@@ -1012,6 +1055,7 @@ int btdf_load(btdf_t *h, const void *src, size_t bytes) {
     return fail(BTDF_EINVAL, "state does not match this handle (size, precision or initial velocity)");
   int rc = ensure_device(h);
   if (rc) return rc;
+  h->stepped = false;
   const size_t row = (size_t)h->nx * h->prec;
   for (int q = 0; q < 9; ++q)
     HIPCHK(hipMemcpy2DAsync(h->ws + h->off_pop[h->cur] + (size_t)q * h->plane * h->prec, (size_t)h->pitch * h->prec,

@@ -62,6 +62,7 @@ struct btdf_sim {
   bool layout_ok = false;  // host layout current for bodies and tiles
   bool device_ok = false;  // body part uploaded into the workspace
   bool state_ok = false;   // populations hold a state
+  bool stepped = false;    // a step ran after the state and the body part last changed
   int cur = 0;             // which population buffer holds the state
   int64_t steps = 0, hist_read = 0;
   int64_t forces_from = 0;   // first step whose ring entry matches the body set

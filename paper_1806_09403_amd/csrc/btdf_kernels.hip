@@ -629,6 +629,75 @@ hipError_t launch_ib_batch(int prec, const CaseDesc *cases, const BatchMap &m, i
   return hipGetLastError();
 }
 
+// Corrected velocity (eq 11) of the last step interpolated at every marker
+// (eq 12): the u_b of the boundary error, eq 45. From the post-collision
+// state: the collision leaves rho unchanged and the momentum at m + F (Guo
+// forcing), so u = (m' - F/2) / rho with F = G + the spread force, which is
+// rebuilt at each stencil node from the covering markers' weights and
+// drs ds F_l exactly as the lattice kernel summed it.
+template <typename T>
+__global__ __launch_bounds__(256) void marker_velocity_kernel(const T *__restrict__ A, LbmParams p, IbParams ib,
+                                                              const int *__restrict__ coff,
+                                                              const int *__restrict__ clist, double *out) {
+  const int l = (int)blockIdx.x * 16 + ((int)threadIdx.x >> 4);
+  const int node = (int)threadIdx.x & 15;
+  const int a = node & 3, c = node >> 2;
+  const int S = stencil_size(p.kind);
+  double wu = 0.0, wv = 0.0;
+  if (l < ib.nm && a < S && c < S) {
+    const double X = ib.X[l], Y = ib.Y[l];
+    const int bx = stencil_base(p.kind, X), by = stencil_base(p.kind, Y);
+    const double W = phi(p.kind, (double)(bx + a) - X) * phi(p.kind, (double)(by + c) - Y);
+    int i = bx + a, j = by + c;
+    if (p.xper) i = ((i % p.nx) + p.nx) % p.nx;
+    if (p.yper) j = ((j % p.ny) + p.ny) % p.ny;
+    const long long base = (long long)j * p.pitch + i;
+    double drho = 0.0, mx = 0.0, my = 0.0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const double g = (double)A[(long long)q * p.plane + base];
+      drho += g;
+      mx += ex(q) * g;
+      my += ey(q) * g;
+    }
+    const T *mw = reinterpret_cast<const T *>(ib.mk_w);
+    T fx = (T)0, fy = (T)0;
+    for (int e = coff[16 * l + node]; e < coff[16 * l + node + 1]; ++e) {
+      const int v = clist[e];
+      const T *w = mw + 10 * (long long)(v >> 4);
+      const T Wm = w[(v >> 2) & 3] * w[4 + (v & 3)];
+      fx += Wm * w[8];
+      fy += Wm * w[9];
+    }
+    const double ftx = (double)(T)(p.Gx + (double)fx), fty = (double)(T)(p.Gy + (double)fy);
+    const double rho = 1.0 + drho;  // stored deviations: first moment m' - u_ref
+    wu = W * ((mx + p.urx - 0.5 * ftx) / rho);
+    wv = W * ((my + p.ury - 0.5 * fty) / rho);
+  }
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) {
+    wu += __shfl_xor(wu, off, 16);
+    wv += __shfl_xor(wv, off, 16);
+  }
+  if (l < ib.nm && node == 0) {
+    out[2 * (long long)l] = wu;
+    out[2 * (long long)l + 1] = wv;
+  }
+}
+
+hipError_t launch_marker_velocity(int prec, const void *A, const LbmParams &p, const IbParams &ib,
+                                  const int *cover_off, const int *cover_list, double *out, hipStream_t s) {
+  if (ib.nm == 0) return hipSuccess;
+  const int blocks = (ib.nm + 15) / 16;
+  if (prec == 4)
+    hipLaunchKernelGGL(marker_velocity_kernel<float>, dim3(blocks), dim3(256), 0, s, (const float *)A, p, ib,
+                       cover_off, cover_list, out);
+  else
+    hipLaunchKernelGGL(marker_velocity_kernel<double>, dim3(blocks), dim3(256), 0, s, (const double *)A, p, ib,
+                       cover_off, cover_list, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_ib(int prec, const void *A, const LbmParams &p, const IbParams &ib, hipStream_t s) {
   if (ib.nm == 0) return hipSuccess;
   const int blocks = (ib.nm + 15) / 16;

@@ -98,6 +98,10 @@ class Sim:
     def marker_data(self):
         return api.btdf_get_marker_data(self._workspace())
 
+    def marker_velocity(self):
+        """(u, v) at every marker after the last step (eq 11 interpolated by eq 12)."""
+        return api.btdf_marker_velocity(self._workspace())
+
     def save(self):
         return api.btdf_save(self._workspace())
 

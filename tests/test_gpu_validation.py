@@ -1,0 +1,52 @@
+"""The paper's cylinder validation on the GPU (Section 5.2, Table 3, row
+of the present method): a 40D x 40D domain meshed with 1601 x 1601 nodes
+(D/dh = 40), cylinder at (18D, 20D), uniform inflow, free-slip top and
+bottom, convective outflow, 3-point delta with thickening 1.9, FP32
+populations, U = 0.05.
+
+The paper does not give its relaxation time, inflow speed or discrete
+boundary conditions, so these are physics checks with tolerances, not
+parity: C_D within 3 %, the wake length within 5 %, St within 3 %, the
+lift amplitude within 5 % and the drag swing within 25 % of the printed
+values.
+"""
+import pytest
+
+import btdf_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+PAPER = {"re40": {"Cd": 1.551, "Lw": 2.40},
+         "re200": {"Cd": 1.364, "Cd_dev": 0.042, "Cl_dev": 0.699, "St": 0.195}}
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def test_steady_wake_at_re40():
+    from paper_1806_09403_amd import validation as V
+    log("v40 Re 40, 1601^2, up to 80 000 steps")
+    r = V.run_steady(W.v40(40.0), max_steps=80_000, log=log)
+    log("  %s" % r)
+    assert r["converged"]
+    assert rel(r["Cd"], PAPER["re40"]["Cd"]) < 0.03
+    assert rel(r["Lw"], PAPER["re40"]["Lw"]) < 0.05
+    assert abs(r["Cl"]) < 1e-3   # symmetric steady wake
+
+
+def test_shedding_at_re200():
+    from paper_1806_09403_amd import validation as V
+    log("v40 Re 200, 1601^2, 100 000 + 30 000 steps")
+    r = V.run_unsteady(W.v40(200.0), warmup=100_000, window=30_000, log=log)
+    log("  %s" % r)
+    p = PAPER["re200"]
+    assert rel(r["Cd"], p["Cd"]) < 0.03
+    assert rel(r["St"], p["St"]) < 0.03
+    assert rel(r["Cl_dev"], p["Cl_dev"]) < 0.05
+    assert rel(r["Cd_dev"], p["Cd_dev"]) < 0.25
+    assert abs(r["Cl_mean"]) < 0.02
