@@ -122,23 +122,28 @@ def c2(kind=COS4, perturb=True, steps=100000, precision=4) -> Case:
                 precision=precision, U=U, D=D)
 
 
-def v40(re=40.0, kind=ROMA3, U=0.05, precision=4, perturb=None) -> Case:
+def v40(re=40.0, kind=ROMA3, U=0.05, precision=4, perturb=None, D=40, ds=1.0, thickening=None) -> Case:
     """The paper's cylinder validation (Section 5.2, Table 3): a 40D x 40D
-    domain meshed with 1601 x 1601 nodes (D/dh = 40), the cylinder at
-    (18D, 20D), uniform inflow, free-slip top and bottom, convective outflow;
-    the 3-point delta with its thickening 1.9 (Section 4.4) and one marker per
-    grid spacing (126 markers). nu = U D / Re. An unsteady run (Re above the
-    onset of shedding) gets a u_y bump behind the cylinder to break the
-    symmetry; perturb=False/True overrides."""
-    D, n = 40.0, 1601
+    domain meshed with 40 D + 1 nodes a side (1601 x 1601 at D/dh = 40), the
+    cylinder at (18D, 20D), uniform inflow, free-slip top and bottom,
+    convective outflow; by default the 3-point delta with its thickening 1.9
+    (Section 4.4) and markers ds = dh apart (126 at D = 40). thickening=1.0
+    is the conventional direct forcing (drs = dh). nu = U D / Re. An
+    unsteady run (Re above the onset of shedding) gets a u_y bump behind the
+    cylinder to break the symmetry; perturb=False/True overrides."""
+    D = int(D)
+    n = 40 * D + 1
     xc, yc = 18.0 * D, 20.0 * D
     if perturb is None:
         perturb = re > 46.0
     bump = 10.0 * shedding_perturbation(n, n, U, D, xc, yc) if perturb else None
+    n_mk = int(round(np.pi * D / ds))
+    drs = PAPER_THICKENING[kind] if thickening is None else float(thickening)
     return Case(name="v40-%dx%d-Re%g" % (n, n, re), nx=n, ny=n, bc=FAR_FIELD,
-                tau=tau_from_nu(U * D / re), kind=kind, thickening=PAPER_THICKENING[kind],
+                tau=tau_from_nu(U * D / re), kind=kind, thickening=drs,
                 inflow=(U, 0.0), init=(1.0, U, 0.0), init_uy=bump,
-                bodies=[cylinder_body(xc, yc, D, 126)], steps=0, precision=precision, U=U, D=D)
+                bodies=[cylinder_body(xc, yc, float(D), n_mk)], steps=0, precision=precision, U=U,
+                D=float(D))
 
 
 def random_centres(n, L, dmin, seed=0, max_draws=1_000_000):

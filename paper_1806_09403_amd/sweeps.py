@@ -1,0 +1,121 @@
+"""Parameter sweeps of the paper's studies, run with this library.
+
+* ``calibration`` (Section 4.4, Fig. 4): the mean calibrated shell
+  thickness drs/dh (eqs 22, 25, 26) of a cylinder against the marker
+  spacing ds/dh and the resolution D/dh, for each delta function. Host only.
+* ``spacing`` (Fig. 9): drag and boundary error (eq 45) at Re 40 of the
+  conventional direct forcing (drs = dh) for several ds/dh, beside the
+  thickened shell at ds = dh.
+* ``resolution`` (Fig. 11): drag at Re 40 against D/dh for both, and the
+  convergence slope of the drag error against the finest resolution.
+* ``passes`` (Fig. 16): drag and boundary error at Re 40 against the number
+  of forcing passes NF, for drs = dh (multi direct forcing) and for the
+  thickened shell.
+
+The flow runs are the 40D x 40D far-field case of ``btdf_workloads.v40``.
+
+    python -m paper_1806_09403_amd.sweeps passes [--out result.json]
+"""
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import api
+from ._lib import COS4, LINEAR2, PESKIN4, ROMA3
+from .validation import run_steady
+
+KIND_NAME = {LINEAR2: "2-point", ROMA3: "3-point", PESKIN4: "4-point", COS4: "cosine 4-point"}
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def calibration(kinds=(LINEAR2, ROMA3, PESKIN4, COS4), D_values=(20, 40, 80),
+                ds_values=(0.5, 0.75, 1.0, 1.25, 1.5), log=_log):
+    import btdf_workloads as W
+    rows = []
+    for kind in kinds:
+        for D in D_values:
+            for ds in ds_values:
+                n = int(round(math.pi * D / ds))
+                b = W.cylinder_body(0.3 + 2.0 * D, 0.6 + 2.0 * D, float(D), n)
+                mean, _ = api.btdf_calibrate_thickening(kind, b.xy, b.ds)
+                rows.append({"kind": KIND_NAME[kind], "D": D, "ds": b.ds, "drs_mean": mean})
+                log("calibration %-15s D/dh %3d ds/dh %.3f  drs/dh %.4f" % (KIND_NAME[kind], D, b.ds, mean))
+    return rows
+
+
+def _flow(label, case, log, **kw):
+    t = time.time()
+    r = run_steady(case, log=None, **kw)
+    r.update({"run": label, "seconds": round(time.time() - t, 1)})
+    log("%-28s C_D %.4f  L_w %.3f  boundary error %.3e  steps %d  (%s s)"
+        % (label, r["Cd"], r["Lw"], r["boundary_error"], r["steps"], r["seconds"]))
+    return r
+
+
+def spacing(ratios=(0.25, 0.5, 1.0, 1.5, 3.0), re=40.0, log=_log):
+    import btdf_workloads as W
+    rows = []
+    for ds in ratios:
+        rows.append(_flow("DF ds/dh=%g" % ds, W.v40(re, ds=ds, thickening=1.0), log))
+    rows.append(_flow("BTDF ds/dh=1", W.v40(re, ds=1.0), log))
+    return rows
+
+
+def resolution(D_values=(10, 20, 40, 80, 160), re=40.0, log=_log):
+    import btdf_workloads as W
+    out = {}
+    for name, drs in (("DF", 1.0), ("BTDF", None)):
+        rows = []
+        for D in D_values:
+            rows.append(_flow("%s D/dh=%d" % (name, D), W.v40(re, D=D, thickening=drs), log,
+                              min_steps=1000 * D, check_every=100 * D, max_steps=5000 * D))
+        for r_, D in zip(rows, D_values):
+            r_["D"] = D
+        ref = rows[-1]["Cd"]
+        Ds = np.array(D_values[:-1], dtype=float)
+        err = np.array([abs(r_["Cd"] - ref) / ref for r_ in rows[:-1]])
+        slope = float("nan")
+        if len(err) > 1 and np.all(err > 0):
+            slope = float(-np.polyfit(np.log(Ds), np.log(err), 1)[0])
+        log("%s: drag error slope against D/dh = %.3f (reference D/dh = %d)" % (name, slope, D_values[-1]))
+        out[name] = {"rows": rows, "slope": slope}
+    return out
+
+
+def passes(nfs=(1, 2, 3, 4, 5, 10, 20), re=40.0, log=_log):
+    import btdf_workloads as W
+    rows = []
+    for name, drs in (("MDF", 1.0), ("BTDF", None)):
+        for nf in nfs:
+            r = _flow("%s NF=%d" % (name, nf), W.v40(re, thickening=drs), log, forcing_passes=nf)
+            r["NF"] = nf
+            rows.append(r)
+    return rows
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("study", choices=["calibration", "spacing", "resolution", "passes"])
+    ap.add_argument("--out", default=None, help="write the rows as JSON here")
+    ap.add_argument("--sizes", default=None, help="resolution: comma-separated D/dh values")
+    a = ap.parse_args(argv)
+    if a.study == "resolution" and a.sizes:
+        res = resolution(tuple(int(v) for v in a.sizes.split(",")))
+    else:
+        res = {"calibration": calibration, "spacing": spacing, "resolution": resolution,
+               "passes": passes}[a.study]()
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1, default=float)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -58,6 +58,12 @@ def wake_length(ux_line, x_rear, D):
     return float((x0 - x_rear) / D)
 
 
+def boundary_error(ub, vb, U):
+    """Eq 45 for markers at rest: the root mean square of the velocity
+    interpolated at the markers, in units of the inflow speed."""
+    return float(np.sqrt(np.mean(np.asarray(ub) ** 2 + np.asarray(vb) ** 2)) / U)
+
+
 def _sim(case, precision, graph_chunk, forcing_passes):
     s = Sim.from_case(case, precision=precision)
     s.set_option(_lib.OPT_GRAPH_CHUNK, graph_chunk)
@@ -85,13 +91,15 @@ def run_steady(case, max_steps=200_000, min_steps=40_000, check_every=4000, tol=
                 log("  step %d  C_D(rho=1) %.6f" % (steps, hist[-1]))
             converged = (steps >= min_steps and len(hist) >= 3 and
                          all(abs(hist[-k] - hist[-k - 1]) < tol * abs(hist[-1]) for k in (1, 2)))
+        ub, vb = s.marker_velocity()
         rho, ux, _ = s.macroscopic()
         rho_inf = float(rho[:, 1].mean())
         F = s.forces()[0]
         q = 0.5 * rho_inf * U * U * D
         jc = int(round(body.cy))
         return {"steps": steps, "converged": bool(converged), "Cd": float(F[0] / q), "Cl": float(F[1] / q),
-                "rho_inf": rho_inf, "Lw": wake_length(ux[jc, :], body.cx + 0.5 * D, D)}
+                "rho_inf": rho_inf, "Lw": wake_length(ux[jc, :], body.cx + 0.5 * D, D),
+                "boundary_error": boundary_error(ub, vb, U)}
     finally:
         s.close()
 

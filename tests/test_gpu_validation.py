@@ -50,3 +50,19 @@ def test_shedding_at_re200():
     assert rel(r["Cl_dev"], p["Cl_dev"]) < 0.05
     assert rel(r["Cd_dev"], p["Cd_dev"]) < 0.25
     assert abs(r["Cl_mean"]) < 0.02
+
+
+def test_one_pass_of_the_thickened_shell_against_forcing_passes():
+    """Fig. 16's comparison at Re 40, D/dh = 40: one pass with the thickened
+    shell is about as accurate as three to four passes of conventional
+    direct forcing (drs = dh), and far better than its one pass."""
+    import btdf_workloads as Wl
+    from paper_1806_09403_amd import validation as V
+    runs = {}
+    for name, drs, nf in (("DF", 1.0, 1), ("MDF3", 1.0, 3), ("MDF4", 1.0, 4), ("BTDF", None, 1)):
+        runs[name] = V.run_steady(Wl.v40(40.0, thickening=drs), max_steps=40_000, forcing_passes=nf)
+        log("  %s C_D %.5f boundary error %.3e" % (name, runs[name]["Cd"], runs[name]["boundary_error"]))
+    assert runs["BTDF"]["boundary_error"] < runs["DF"]["boundary_error"] / 5
+    assert runs["BTDF"]["boundary_error"] < runs["MDF3"]["boundary_error"]
+    assert runs["BTDF"]["Cd"] < runs["DF"]["Cd"]
+    assert runs["BTDF"]["Cd"] <= runs["MDF4"]["Cd"] + 2e-4
