@@ -43,6 +43,14 @@
  *  - stencil nodes are all nodes whose distance to the marker lies inside
  *    the support of the delta function (weights at the edge are zero).
  *
+ * Besides the direct force of eq 20 (with NF passes, eqs 29-31), the
+ * comparison methods of Section 3 are available per step: the implicit
+ * direct forcing of eq 17 (equal to the implicit velocity correction of
+ * eqs 32-35, Appendix A), one dense solve per body with D_I D_E built from
+ * eq 21, markers of different bodies not coupled; and RKPM (eq 36 / B54),
+ * the direct force spread with epsilon_l = row sums of A^-1 (eq 22). The
+ * hydrodynamic force is minus the total force spread into the fluid.
+ *
  * Layout: populations are [q][j][i] with i (x) fastest; nodes sit at
  * integer coordinates (x, y) = (i, j); lattice units dh = dt = 1.
  */
@@ -145,7 +153,13 @@ typedef struct {
   int nf;       /* forcing passes per step (Algorithm 1 step 3; 1 = BTDF as proposed) */
   double *usx, *usy; /* u*^k at every node during the passes */
   double *dFx, *dFy; /* force increment of the current pass, per marker */
+  int method;        /* ORC_DIRECT, ORC_IMPLICIT (IDF = IVC) or ORC_RKPM */
+  double *sl;        /* per marker: the factor the spreading applies to F_l */
 } oracle_t;
+
+#define ORC_DIRECT 0
+#define ORC_IMPLICIT 1
+#define ORC_RKPM 2
 
 static size_t nnode(const oracle_t *o) { return (size_t)o->nx * (size_t)o->ny; }
 static size_t idx(const oracle_t *o, int q, int j, int i) {
@@ -213,7 +227,7 @@ void oracle_destroy(oracle_t *o) {
   free(o->rho_l); free(o->ux_l); free(o->uy_l); free(o->Fx); free(o->Fy);
   free(o->body_of); free(o->off); free(o->cx); free(o->cy); free(o->ds);
   free(o->force);
-  free(o->usx); free(o->usy); free(o->dFx); free(o->dFy);
+  free(o->usx); free(o->usy); free(o->dFx); free(o->dFy); free(o->sl);
   free(o);
 }
 
@@ -221,12 +235,18 @@ void oracle_destroy(oracle_t *o) {
  * direct forcing of eqs 29-31 on the thickened spreading). */
 void oracle_set_forcing_passes(oracle_t *o, int nf) { o->nf = nf < 1 ? 1 : nf; }
 
+/* How the marker force is formed and spread: ORC_DIRECT (eq 20, the
+ * default), ORC_IMPLICIT (eq 17: the implicit direct forcing, which
+ * Appendix A shows is the implicit velocity correction of eqs 32-35) or
+ * ORC_RKPM (eq 20 spread with the corrected operator of eq 36 / B54). */
+void oracle_set_forcing_method(oracle_t *o, int method) { o->method = method; }
+
 static int grow_markers(oracle_t *o, int need) {
   if (need <= o->nm_cap) return 0;
   int cap = need * 2;
   double **arrs[] = {&o->X, &o->Y, &o->Ub, &o->Vb, &o->rho_l, &o->ux_l, &o->uy_l, &o->Fx, &o->Fy,
-                     &o->dFx, &o->dFy};
-  for (int a = 0; a < 11; ++a) {
+                     &o->dFx, &o->dFy, &o->sl};
+  for (int a = 0; a < 12; ++a) {
     double *p = (double *)realloc(*arrs[a], (size_t)cap * sizeof(double));
     if (!p) return -1;
     *arrs[a] = p;
@@ -346,6 +366,140 @@ static size_t node_of(const oracle_t *o, int i, int j) {
   return (size_t)j * o->nx + i;
 }
 
+/* Sum over the grid nodes k of W_lk W_mk, the weights of markers l and m at
+ * node k (the node sum of eqs 21-22, with dh = 1). Node offsets from marker
+ * m take the nearest periodic image. */
+static double pair_weight(const oracle_t *o, int l, int m) {
+  double h = oracle_delta_halfwidth(o->kind), s = 0.0;
+  for (int j = (int)ceil(o->Y[l] - h); j <= (int)floor(o->Y[l] + h); ++j) {
+    for (int i = (int)ceil(o->X[l] - h); i <= (int)floor(o->X[l] + h); ++i) {
+      double dx = i - o->X[m], dy = j - o->Y[m];
+      if (x_periodic(o)) dx -= o->nx * floor(dx / o->nx + 0.5);
+      if (y_periodic(o)) dy -= o->ny * floor(dy / o->ny + 0.5);
+      s += oracle_delta(o->kind, i - o->X[l]) * oracle_delta(o->kind, j - o->Y[l]) *
+           oracle_delta(o->kind, dx) * oracle_delta(o->kind, dy);
+    }
+  }
+  return s;
+}
+
+/* The matrix A of eq 22 (drs = dh) of body b, n x n row-major. */
+static double *body_matrix_A(const oracle_t *o, int b, int *n_out) {
+  int l0 = o->off[b], n = o->off[b + 1] - l0;
+  double *A = (double *)malloc((size_t)n * n * sizeof(double));
+  if (A)
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < n; ++c) A[(size_t)r * n + c] = o->ds[b] * pair_weight(o, l0 + r, l0 + c);
+  *n_out = n;
+  return A;
+}
+
+/* Solve M X = B in place for k right-hand sides (B is n x k, row-major) by
+ * Gaussian elimination with partial pivoting; M is destroyed. Returns -1 on a
+ * zero pivot. */
+static int gauss_solve(double *M, double *B, int n, int k) {
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabs(M[(size_t)r * n + c]) > fabs(M[(size_t)p * n + c])) p = r;
+    if (M[(size_t)p * n + c] == 0.0) return -1;
+    if (p != c) {
+      for (int t = 0; t < n; ++t) {
+        double v = M[(size_t)c * n + t]; M[(size_t)c * n + t] = M[(size_t)p * n + t]; M[(size_t)p * n + t] = v;
+      }
+      for (int t = 0; t < k; ++t) {
+        double v = B[(size_t)c * k + t]; B[(size_t)c * k + t] = B[(size_t)p * k + t]; B[(size_t)p * k + t] = v;
+      }
+    }
+    for (int r = c + 1; r < n; ++r) {
+      double f = M[(size_t)r * n + c] / M[(size_t)c * n + c];
+      for (int t = c; t < n; ++t) M[(size_t)r * n + t] -= f * M[(size_t)c * n + t];
+      for (int t = 0; t < k; ++t) B[(size_t)r * k + t] -= f * B[(size_t)c * k + t];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    for (int t = 0; t < k; ++t) {
+      double v = B[(size_t)c * k + t];
+      for (int r = c + 1; r < n; ++r) v -= M[(size_t)c * n + r] * B[(size_t)r * k + t];
+      B[(size_t)c * k + t] = v / M[(size_t)c * n + c];
+    }
+  }
+  return 0;
+}
+
+/* Interpolation (eqs 12, 14) and eq 20 at every marker, then the implicit
+ * force of eq 17 or the RKPM factors of eq B54, spreading, per-marker
+ * spreading factors left in sl. */
+static void implicit_or_rkpm(oracle_t *o) {
+  double h = oracle_delta_halfwidth(o->kind);
+  for (int m = 0; m < o->nm; ++m) {
+    double X = o->X[m], Y = o->Y[m], rl = 0.0, ul = 0.0, vl = 0.0;
+    for (int j = (int)ceil(Y - h); j <= (int)floor(Y + h); ++j) {
+      for (int i = (int)ceil(X - h); i <= (int)floor(X + h); ++i) {
+        double W = oracle_delta(o->kind, i - X) * oracle_delta(o->kind, j - Y);
+        size_t k = node_of(o, i, j);
+        rl += W * o->rho[k];
+        ul += W * o->usx[k];
+        vl += W * o->usy[k];
+      }
+    }
+    o->rho_l[m] = rl;
+    o->ux_l[m] = ul;
+    o->uy_l[m] = vl;
+    if (!(sqrt(ul * ul + vl * vl) <= 0.3) && o->unstable == 0) o->unstable = 1 + o->body_of[m];
+    o->Fx[m] = 2.0 * rl * (o->Ub[m] - ul); /* eq 20; eq 17's right-hand side */
+    o->Fy[m] = 2.0 * rl * (o->Vb[m] - vl);
+  }
+  for (int b = 0; b < o->nb; ++b) {
+    int n, l0 = o->off[b];
+    double *A = body_matrix_A(o, b, &n);
+    if (!A) { o->unstable = 1 + b; continue; }
+    if (o->method == ORC_IMPLICIT) {
+      /* eq 17: (D_I D_E) F_b = 2 rho (U_b - D_I u*), with D_I D_E = drs A (eq 21) */
+      double *rhs = (double *)malloc((size_t)n * 2 * sizeof(double));
+      if (!rhs) { free(A); o->unstable = 1 + b; continue; }
+      for (int r = 0; r < n; ++r) {
+        rhs[2 * r] = o->Fx[l0 + r];
+        rhs[2 * r + 1] = o->Fy[l0 + r];
+      }
+      for (size_t t = 0; t < (size_t)n * n; ++t) A[t] *= o->drs;
+      if (gauss_solve(A, rhs, n, 2)) o->unstable = 1 + b;
+      for (int r = 0; r < n; ++r) {
+        o->Fx[l0 + r] = rhs[2 * r];
+        o->Fy[l0 + r] = rhs[2 * r + 1];
+        o->sl[l0 + r] = o->drs * o->ds[b];
+      }
+      free(rhs);
+    } else {
+      /* eq B54: epsilon_l = sum of row l of A^-1; the spreading D_EI epsilon */
+      double *inv = (double *)calloc((size_t)n * n, sizeof(double));
+      if (!inv) { free(A); o->unstable = 1 + b; continue; }
+      for (int r = 0; r < n; ++r) inv[(size_t)r * n + r] = 1.0;
+      if (gauss_solve(A, inv, n, n)) o->unstable = 1 + b;
+      for (int r = 0; r < n; ++r) {
+        double e = 0.0;
+        for (int c = 0; c < n; ++c) e += inv[(size_t)r * n + c];
+        o->sl[l0 + r] = o->ds[b] * e;
+      }
+      free(inv);
+    }
+    free(A);
+  }
+  for (int m = 0; m < o->nm; ++m) {
+    int bad = !isfinite(o->Fx[m]) || !isfinite(o->Fy[m]);
+    if (bad && o->unstable == 0) o->unstable = 1 + o->body_of[m];
+    double X = o->X[m], Y = o->Y[m];
+    for (int j = (int)ceil(Y - h); j <= (int)floor(Y + h); ++j) {
+      for (int i = (int)ceil(X - h); i <= (int)floor(X + h); ++i) {
+        double W = oracle_delta(o->kind, i - X) * oracle_delta(o->kind, j - Y);
+        size_t k = node_of(o, i, j);
+        o->fx[k] += W * o->sl[m] * o->Fx[m];
+        o->fy[k] += W * o->sl[m] * o->Fy[m];
+      }
+    }
+  }
+}
+
 /* Interpolation (eqs 12, 14), direct force (eq 20), spreading (eqs 13, 15)
  * and hydrodynamic force and torque (eq 27) for every marker, in NF forcing
  * passes (Algorithm 1 step 3; eqs 29-31 when NF > 1):
@@ -366,7 +520,7 @@ static void immersed_boundary(oracle_t *o) {
   }
   for (int m = 0; m < o->nm; ++m) o->Fx[m] = o->Fy[m] = 0.0;
 
-  for (int pass = 0; pass < o->nf; ++pass) {
+  for (int pass = 0; pass < (o->method == ORC_DIRECT ? o->nf : 0); ++pass) {
     /* interpolation + direct force increment */
     for (int m = 0; m < o->nm; ++m) {
       double X = o->X[m], Y = o->Y[m];
@@ -414,15 +568,19 @@ static void immersed_boundary(oracle_t *o) {
     }
   }
 
+  if (o->method != ORC_DIRECT) implicit_or_rkpm(o);
+
   /* force and torque on each body: minus what its markers apply to the fluid */
   for (int b = 0; b < o->nb; ++b) {
     double sx = 0.0, sy = 0.0, tz = 0.0;
     for (int m = o->off[b]; m < o->off[b + 1]; ++m) {
-      sx += o->Fx[m];
-      sy += o->Fy[m];
-      tz += (o->X[m] - o->cx[b]) * o->Fy[m] - (o->Y[m] - o->cy[b]) * o->Fx[m];
+      /* RKPM spreads s_l F_l with a factor of its own per marker */
+      double w = o->method == ORC_RKPM ? o->sl[m] : 1.0;
+      sx += w * o->Fx[m];
+      sy += w * o->Fy[m];
+      tz += w * ((o->X[m] - o->cx[b]) * o->Fy[m] - (o->Y[m] - o->cy[b]) * o->Fx[m]);
     }
-    double s = o->drs * o->ds[b];
+    double s = o->method == ORC_RKPM ? 1.0 : o->drs * o->ds[b];
     o->force[3 * b] = -s * sx;
     o->force[3 * b + 1] = -s * sy;
     o->force[3 * b + 2] = -s * tz;
@@ -695,7 +853,8 @@ int oracle_adjoint(oracle_t *o, long n, const double *hist_bar, double *pop_bar,
   double *guv = (double *)calloc((size_t)(nm > 0 ? nm : 1) * 2, sizeof(double));
   double *gc = (double *)calloc((size_t)(nb > 0 ? nb : 1) * 2, sizeof(double));
   int rc = 0;
-  if (o->nf != 1 || o->bc[1] == ORC_CONVECTIVE_OUTLET || o->bc[2] == ORC_FREE_SLIP_WALL) {
+  if (o->nf != 1 || o->method != ORC_DIRECT || o->bc[1] == ORC_CONVECTIVE_OUTLET ||
+      o->bc[2] == ORC_FREE_SLIP_WALL) {
     /* the reverse mode covers one forcing pass and the bounce-back / zero-gradient boundaries */
     rc = -1;
     goto done;

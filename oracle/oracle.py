@@ -62,6 +62,7 @@ def lib():
         L.oracle_delta_halfwidth.restype = ctypes.c_double
         L.oracle_delta_halfwidth.argtypes = [ctypes.c_int]
         L.oracle_set_forcing_passes.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.oracle_set_forcing_method.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.oracle_delta_deriv.restype = ctypes.c_double
         L.oracle_delta_deriv.argtypes = [ctypes.c_int, ctypes.c_double]
         L.oracle_adjoint.restype = ctypes.c_int
@@ -139,6 +140,12 @@ class OracleSim:
     def set_forcing_passes(self, nf):
         """Forcing passes per step (Algorithm 1 step 3; eqs 29-31 for nf > 1)."""
         lib().oracle_set_forcing_passes(self._h, int(nf))
+
+    DIRECT, IMPLICIT, RKPM = 0, 1, 2
+
+    def set_forcing_method(self, method):
+        """DIRECT (eq 20), IMPLICIT (eq 17; = IVC, eqs 32-35) or RKPM (eq 36 / B54)."""
+        lib().oracle_set_forcing_method(self._h, int(method))
 
     def set_marker_velocity(self, b, uv):
         uv = np.ascontiguousarray(uv, dtype=np.float64).reshape(-1, 2)
