@@ -71,6 +71,23 @@ extern "C" {
 #define BTDF_FREE_SLIP_WALL 4
 #define BTDF_CONVECTIVE_OUTLET 5
 
+/* ---- forcing methods (BTDF_OPT_FORCING_METHOD) ----
+ * DIRECT (default): F_l = 2 rho_l (U_l - D_I u*) (eq 20), spread with
+ *   drs ds F_l: the thickened-shell method (or conventional direct forcing
+ *   with thickening 1, multi direct forcing with NF > 1).
+ * IMPLICIT: the implicit direct forcing of eq 17, F_b = (D_I D_E)^-1 times
+ *   the direct force, one dense matrix per body (eq 21) formed and inverted
+ *   on the host; identical to the implicit velocity correction of eqs
+ *   32-35 (Appendix A) and independent of the thickening.
+ * RKPM: the direct force spread with ds epsilon_l F_l, epsilon = A^-1 1 (row
+ *   sums of A^-1, eq 22 with drs = dh; eq 36 / B54); the thickening is
+ *   unused.
+ * The hydrodynamic force of a body is minus the total force spread into the
+ * fluid. Markers of different bodies are not coupled by the matrices. */
+#define BTDF_FORCING_DIRECT 0
+#define BTDF_FORCING_IMPLICIT 1
+#define BTDF_FORCING_RKPM 2
+
 /* ---- regularised delta functions (Section 4.3) ----
  * LINEAR2: 2-point, eq 37;  ROMA3: 3-point, eq 38;  PESKIN4: 4-point, eq 39;
  * COS4: the cosine 4-point kernel (1 + cos(pi r / 2)) / 4 on |r| <= 2.
@@ -96,6 +113,9 @@ extern "C" {
 #define BTDF_OPT_MASK_UNSTABLE 12 /* batches only: 1 (default) = a case that went unstable stops, the others go on */
 #define BTDF_OPT_ROW_ALIGN 13     /* bytes (0 or a power of two 4..4096, default 128): each row starts on this
                                     boundary, pitch = round_up(nx, align) + row pad; only before the first device use */
+#define BTDF_OPT_FORCING_METHOD 15 /* BTDF_FORCING_*: how the marker force is formed and spread (Section 3);
+                                      stand-alone handles only, NF = 1, bodies of at most 2048 markers; the
+                                      matrices are formed on the host when the bodies or the method change */
 #define BTDF_OPT_FORCING_PASSES 14 /* NF in 1..64 (default 1): direct-forcing passes per step (Sec. 2.3, eqs 29-31);
                                       each pass after the first re-interpolates the velocity corrected by the force
                                       spread so far and adds 2 rho_l (U - u) to the marker force; stand-alone

@@ -24,6 +24,8 @@ OPT_ROW_PAD, OPT_PLANE_PAD, OPT_INTERIOR_PATH, OPT_OVERLAP, OPT_FORCED_TILES = 7
 OPT_MASK_UNSTABLE = 12
 OPT_ROW_ALIGN = 13
 OPT_FORCING_PASSES = 14
+OPT_FORCING_METHOD = 15
+FORCING_DIRECT, FORCING_IMPLICIT, FORCING_RKPM = 0, 1, 2
 
 _NAMES = {OK: "BTDF_OK", EINVAL: "BTDF_EINVAL", ENOMEM: "BTDF_ENOMEM", EDEVICE: "BTDF_EDEVICE",
           ESTATE: "BTDF_ESTATE", EUNSTABLE: "BTDF_EUNSTABLE"}

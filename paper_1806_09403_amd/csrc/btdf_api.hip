@@ -231,6 +231,12 @@ void compute_layout(btdf_t *h) {
   o = align256(o + (h->nf > 1 ? 56 * (size_t)std::max(nm, 1) * sizeof(double) : 0));
   h->off_mdff = o;
   o = align256(o + (h->nf > 1 ? 4 * (size_t)std::max(nm, 1) * sizeof(double) : 0));
+  // implicit forcing: one inverse matrix per body; RKPM: nothing beyond the marker factors
+  h->method_err = forcing_setup(h);
+  h->off_moff = o;
+  o = align256(o + h->minv_off.size() * sizeof(long long));
+  h->off_minv = o;
+  o = align256(o + h->minv.size() * sizeof(double));
   h->total = o;
 
   h->layout_ok = true;
@@ -306,6 +312,10 @@ IbParams make_ib(const btdf_t *h) {
   ib.cover_list = h->at<int>(h->off_clist);
   ib.mdf_cache = h->at<double>(h->off_mdfc);
   ib.mdf_w = ib.mdf_cache + 48 * M;
+  ib.method = h->method;
+  ib.max_body = h->max_body;
+  ib.minv = h->at<double>(h->off_minv);
+  ib.minv_off = h->at<long long>(h->off_moff);
   ib.mdf_f = h->at<double>(h->off_mdff);
   return ib;
 }
@@ -332,7 +342,9 @@ int upload_bodies(btdf_t *h) {
   put(h->off_mk + 1 * M * d, h->Y.data(), nm * d);
   put(h->off_mk + 2 * M * d, h->U.data(), nm * d);
   put(h->off_mk + 3 * M * d, h->V.data(), nm * d);
-  put(h->off_mk + 4 * M * d, h->sdrs.data(), nm * d);
+  // the spreading factor of each marker: drs ds, or ds epsilon_l under RKPM
+  const bool rk = h->method == BTDF_FORCING_RKPM && h->s_rkpm.size() == nm;
+  put(h->off_mk + 4 * M * d, rk ? h->s_rkpm.data() : h->sdrs.data(), nm * d);
   put(h->off_body + 0 * B * d, h->cx.data(), nb * d);
   put(h->off_body + 1 * B * d, h->cy.data(), nb * d);
   put(h->off_body + 2 * B * d, h->bsdrs.data(), nb * d);
@@ -343,6 +355,8 @@ int upload_bodies(btdf_t *h) {
   put(h->off_toff, h->tile_off.data(), h->tile_off.size() * sizeof(int));
   put(h->off_tlist, h->tile_list.data(), h->tile_list.size() * sizeof(int));
   put(h->off_tmap, h->tile_map.data(), h->tile_map.size() * sizeof(int));
+  put(h->off_moff, h->minv_off.data(), h->minv_off.size() * sizeof(long long));
+  put(h->off_minv, h->minv.data(), h->minv.size() * sizeof(double));
   put(h->off_coff, h->cover_off.data(), h->cover_off.size() * sizeof(int));
   put(h->off_clist, h->cover_list.data(), h->cover_list.size() * sizeof(int));
   HIPCHK(hipMemcpyAsync(h->ws + h->off_mk, st.data(), st.size(), hipMemcpyHostToDevice, h->stream));
@@ -376,6 +390,7 @@ size_t moved_bytes(const btdf_t *h) { return h->bodies_dirty ? h->grid_bytes : h
 // make the workspace hold a valid state and the current body part
 int ensure_device(btdf_t *h) {
   if (!h->layout_ok) compute_layout(h);
+  if (!h->method_err.empty()) return fail(BTDF_EINVAL, "%s", h->method_err.c_str());
   if (h->ws == nullptr || h->ws_bytes < h->total) {
     if (h->ws != nullptr && !h->ws_owned)
       return fail(BTDF_ENOMEM, "bound workspace has %zu bytes, %zu needed (rebind a larger one)",
@@ -580,6 +595,7 @@ int add_body_impl(btdf_t *h, int n, const double *xy, const double *uv, double c
     h->cx.push_back(cx);
     h->cy.push_back(cy);
     h->bsdrs.push_back(s);
+    h->bds.push_back(ds);
   } catch (...) {
     return fail(BTDF_ENOMEM, "out of host memory");
   }
@@ -1132,8 +1148,23 @@ int btdf_set_option(btdf_t *h, int key, int64_t value) {
       h->row_align = (int)value;
       h->layout_ok = false;
       return ok();
+    case BTDF_OPT_FORCING_METHOD:
+      if (value != BTDF_FORCING_DIRECT && value != BTDF_FORCING_IMPLICIT && value != BTDF_FORCING_RKPM)
+        return fail(BTDF_EINVAL, "unknown forcing method %lld", (long long)value);
+      if (value != BTDF_FORCING_DIRECT && h->nf != 1)
+        return fail(BTDF_ESTATE, "the implicit and RKPM methods take one forcing pass (NF = 1)");
+      if (value != h->method) {
+        h->method = (int)value;
+        h->layout_ok = false;  // matrices and marker factors change
+        h->device_ok = false;
+        h->stepped = false;
+        drop_graph(h);
+      }
+      return ok();
     case BTDF_OPT_FORCING_PASSES:
       if (value < 1 || value > 64) return fail(BTDF_EINVAL, "forcing passes must be in 1 .. 64");
+      if (value != 1 && h->method != BTDF_FORCING_DIRECT)
+        return fail(BTDF_ESTATE, "forcing passes need the direct forcing method");
       if (value != h->nf) {
         h->nf = (int)value;
         h->layout_ok = false;  // the pass buffers change size
@@ -1165,6 +1196,7 @@ int btdf_get_option(const btdf_t *h, int key, int64_t *value) {
     case BTDF_OPT_PLANE_PAD: *value = h->plane_pad; return ok();
     case BTDF_OPT_ROW_ALIGN: *value = h->row_align; return ok();
     case BTDF_OPT_FORCING_PASSES: *value = h->nf; return ok();
+    case BTDF_OPT_FORCING_METHOD: *value = h->method; return ok();
     default: return fail(BTDF_EINVAL, "unknown option %d", key);
   }
 }

@@ -146,6 +146,11 @@ struct IbParams {
   const int *cover_off, *cover_list;  // per marker and stencil lane: covering markers (see AdjParams)
   double *mdf_cache;                  // [nm][16][3]: rho, u*_x, u*_y at each stencil node
   double *mdf_w;                      // [nm][8]: x then y delta weights in FP64
+  // comparison forcing methods (Section 3)
+  int method;                         // 0 direct, 1 implicit (eq 17), 2 RKPM (eq B54)
+  int max_body;                       // markers of the largest body
+  const double *minv;                 // implicit: (D_I D_E)^-1 of each body, column-major
+  const long long *minv_off;          // implicit: start of body b's matrix
   double *mdf_f;                      // [2][nm][2]: accumulated force after the previous / this pass
 };
 

@@ -48,6 +48,13 @@ struct btdf_sim {
   int overlap = 0;            // run the marker kernel beside the lattice launch of the free tiles
   int nf = 1;                 // forcing passes per step
   std::vector<int> cover_off, cover_list;  // covering markers per stencil node (nf > 1)
+  int method = BTDF_FORCING_DIRECT;        // how the marker force is formed and spread
+  std::vector<double> minv;                // implicit: (D_I D_E)^-1 per body, column-major
+  std::vector<long long> minv_off;         // implicit: start of each body's matrix in minv
+  std::vector<double> s_rkpm;              // RKPM: spreading factor ds epsilon_l per marker
+  std::vector<double> bds;                 // arc length per marker of each body
+  int max_body = 0;                        // markers of the largest body
+  std::string method_err;                  // set-up failure of the implicit / RKPM matrices
   // device memory
   char *ws = nullptr;
   size_t ws_bytes = 0;
@@ -58,7 +65,7 @@ struct btdf_sim {
   size_t off_pop[2] = {0, 0}, off_ctl = 0, grid_bytes = 0;
   size_t off_hist = 0, off_mk = 0, off_mkw = 0, off_mkixy = 0, off_mkbody = 0, off_body = 0, off_boff = 0,
          off_toff = 0, off_tlist = 0, off_tmap = 0, off_coff = 0, off_clist = 0, off_mdfc = 0, off_mdff = 0,
-         total = 0;
+         off_moff = 0, off_minv = 0, total = 0;
   bool layout_ok = false;  // host layout current for bodies and tiles
   bool device_ok = false;  // body part uploaded into the workspace
   bool state_ok = false;   // populations hold a state
@@ -95,6 +102,9 @@ void drop_graph(btdf_t *h);
 void compute_layout(btdf_t *h);
 void bin_markers(const btdf_t *h, int tx, int ty, int ntx, int nty, std::vector<int> &off, std::vector<int> &list);
 void cover_lists(const btdf_t *h, std::vector<int> &off, std::vector<int> &list);
+// implicit / RKPM matrices of the current bodies ("" or the reason they cannot be formed)
+constexpr int kMaxImplicitBody = 2048;
+std::string forcing_setup(btdf_t *h);
 LbmParams make_params(const btdf_t *h);
 IbParams make_ib(const btdf_t *h);
 int ensure_device(btdf_t *h);

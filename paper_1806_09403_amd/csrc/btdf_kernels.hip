@@ -206,11 +206,19 @@ __device__ void body_reduce(const IbParams &ib, int b, int tid, double (*red)[NT
   const int l0 = ib.body_off[b], l1 = ib.body_off[b + 1];
   const double cx = ib.cx[b], cy = ib.cy[b];
   double sfx = 0.0, sfy = 0.0, stz = 0.0;
+  const bool per_marker = ib.method == 2;  // RKPM spreads with a factor per marker
   for (int l = l0 + tid; l < l1; l += NT) {
     const double Fx = ib.Fx[l], Fy = ib.Fy[l];
-    sfx += Fx;
-    sfy += Fy;
-    stz += (ib.X[l] - cx) * Fy - (ib.Y[l] - cy) * Fx;
+    if (per_marker) {
+      const double w = ib.sdrs[l];
+      sfx += w * Fx;
+      sfy += w * Fy;
+      stz += w * ((ib.X[l] - cx) * Fy - (ib.Y[l] - cy) * Fx);
+    } else {
+      sfx += Fx;
+      sfy += Fy;
+      stz += (ib.X[l] - cx) * Fy - (ib.Y[l] - cy) * Fx;
+    }
   }
   sfx = wave_sum(sfx);
   sfy = wave_sum(sfy);
@@ -229,7 +237,7 @@ __device__ void body_reduce(const IbParams &ib, int b, int tid, double (*red)[NT
       s1 += red[1][k];
       s2 += red[2][k];
     }
-    const double s = ib.body_sdrs[b];
+    const double s = per_marker ? 1.0 : ib.body_sdrs[b];
     double *h = ib.hist + ((long long)ib.slot[0] * ib.nb + b) * 3;
     h[0] = -s * s0;
     h[1] = -s * s1;
@@ -629,6 +637,39 @@ hipError_t launch_ib_batch(int prec, const CaseDesc *cases, const BatchMap &m, i
   return hipGetLastError();
 }
 
+// Implicit direct forcing (eq 17): one workgroup per body replaces the
+// direct force of its markers (eq 20, left by the marker kernel) by
+// (D_I D_E)^-1 times it, with the body's inverse kept column-major, and
+// leaves drs ds F_b for the lattice kernel's spread.
+template <typename T>
+__global__ __launch_bounds__(256) void idf_kernel(LbmParams p, IbParams ib) {
+  extern __shared__ double s_f[];  // [2][max_body]
+  const int b = (int)blockIdx.x;
+  const int l0 = ib.body_off[b], n = ib.body_off[b + 1] - l0;
+  for (int i = (int)threadIdx.x; i < n; i += 256) {
+    s_f[i] = ib.Fx[l0 + i];
+    s_f[ib.max_body + i] = ib.Fy[l0 + i];
+  }
+  __syncthreads();
+  const double *Mt = ib.minv + ib.minv_off[b];
+  for (int i = (int)threadIdx.x; i < n; i += 256) {
+    double fx = 0.0, fy = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const double m = Mt[(long long)j * n + i];
+      fx += m * s_f[j];
+      fy += m * s_f[ib.max_body + j];
+    }
+    const int l = l0 + i;
+    ib.Fx[l] = fx;
+    ib.Fy[l] = fy;
+    const double sd = ib.sdrs[l];
+    T *mw = reinterpret_cast<T *>(ib.mk_w) + 10 * (long long)l;
+    mw[8] = (T)(fx * sd);
+    mw[9] = (T)(fy * sd);
+    if (!isfinite(fx) || !isfinite(fy)) p.flag[0] = 1 + b;
+  }
+}
+
 // Corrected velocity (eq 11) of the last step interpolated at every marker
 // (eq 12): the u_b of the boundary error, eq 45. From the post-collision
 // state: the collision leaves rho unchanged and the momentum at m + F (Guo
@@ -705,6 +746,13 @@ hipError_t launch_ib(int prec, const void *A, const LbmParams &p, const IbParams
     hipLaunchKernelGGL(ib_kernel<float>, dim3(blocks), dim3(256), 0, s, (const float *)A, p, ib);
   else
     hipLaunchKernelGGL(ib_kernel<double>, dim3(blocks), dim3(256), 0, s, (const double *)A, p, ib);
+  if (ib.method == 1 && ib.nb > 0) {  // implicit direct forcing, one workgroup per body
+    const size_t lds = 2 * (size_t)ib.max_body * sizeof(double);
+    if (prec == 4)
+      hipLaunchKernelGGL(idf_kernel<float>, dim3(ib.nb), dim3(256), lds, s, p, ib);
+    else
+      hipLaunchKernelGGL(idf_kernel<double>, dim3(ib.nb), dim3(256), lds, s, p, ib);
+  }
   for (int k = 1; k < ib.nf; ++k) {  // further forcing passes
     const int last = k == ib.nf - 1;
     if (prec == 4)

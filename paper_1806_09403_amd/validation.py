@@ -64,23 +64,25 @@ def boundary_error(ub, vb, U):
     return float(np.sqrt(np.mean(np.asarray(ub) ** 2 + np.asarray(vb) ** 2)) / U)
 
 
-def _sim(case, precision, graph_chunk, forcing_passes):
+def _sim(case, precision, graph_chunk, forcing_passes, method=0):
     s = Sim.from_case(case, precision=precision)
     s.set_option(_lib.OPT_GRAPH_CHUNK, graph_chunk)
     if forcing_passes != 1:
         s.set_option(_lib.OPT_FORCING_PASSES, forcing_passes)
+    if method:
+        s.set_option(_lib.OPT_FORCING_METHOD, method)
     return s
 
 
 def run_steady(case, max_steps=200_000, min_steps=40_000, check_every=4000, tol=1e-3, precision=None,
-               graph_chunk=50, forcing_passes=1, log=None):
+               graph_chunk=50, forcing_passes=1, method=0, log=None):
     """Step until C_D has changed by less than tol (relative) over each of
     two successive check intervals (at least min_steps); then C_D, C_L and
     the wake length of the single body. Acoustic waves trapped between the
     inlet and the walls keep C_D moving by about 1e-3 relative for a long
     time, so tol is not set tighter by default."""
     U, D, body = case.U, case.D, case.bodies[0]
-    s = _sim(case, precision, graph_chunk, forcing_passes)
+    s = _sim(case, precision, graph_chunk, forcing_passes, method)
     try:
         hist, steps, converged = [], 0, False
         while steps < max_steps and not converged:
@@ -105,11 +107,11 @@ def run_steady(case, max_steps=200_000, min_steps=40_000, check_every=4000, tol=
 
 
 def run_unsteady(case, warmup=100_000, window=40_000, precision=None, graph_chunk=50, forcing_passes=1,
-                 log=None):
+                 method=0, log=None):
     """Run warmup steps, then record window steps: C_D and C_L as mean +-
     largest deviation, and the Strouhal number from C_L."""
     U, D = case.U, case.D
-    s = _sim(case, precision, graph_chunk, forcing_passes)
+    s = _sim(case, precision, graph_chunk, forcing_passes, method)
     piece = 4000   # below the force ring's default capacity of 4096
     try:
         done = 0

@@ -66,3 +66,15 @@ def test_one_pass_of_the_thickened_shell_against_forcing_passes():
     assert runs["BTDF"]["boundary_error"] < runs["MDF3"]["boundary_error"]
     assert runs["BTDF"]["Cd"] < runs["DF"]["Cd"]
     assert runs["BTDF"]["Cd"] <= runs["MDF4"]["Cd"] + 2e-4
+
+
+@pytest.mark.parametrize("method,name", [(1, "IVC"), (2, "RKPM")])
+def test_comparison_methods_at_re40(method, name):
+    """Table 3's IVC and RKPM rows at Re 40: C_D 1.551, L_w 2.40."""
+    from paper_1806_09403_amd import _lib, validation as V
+    import btdf_workloads as Wl
+    c = Wl.v40(40.0, thickening=1.0)
+    r = V.run_steady(c, max_steps=40_000, method=method)
+    log("  %s %s" % (name, r))
+    assert rel(r["Cd"], 1.551) < 0.03
+    assert rel(r["Lw"], 2.40) < 0.05
