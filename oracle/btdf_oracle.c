@@ -155,6 +155,11 @@ typedef struct {
   double *dFx, *dFy; /* force increment of the current pass, per marker */
   int method;        /* ORC_DIRECT, ORC_IMPLICIT (IDF = IVC) or ORC_RKPM */
   double *sl;        /* per marker: the factor the spreading applies to F_l */
+  /* rigid motion: per body a moving flag, angle, velocity and angular
+   * velocity; per marker the offset from the centre at angle 0 */
+  int *moving;
+  double *theta, *bvx, *bvy, *bom;
+  double *rx, *ry;
 } oracle_t;
 
 #define ORC_DIRECT 0
@@ -228,6 +233,7 @@ void oracle_destroy(oracle_t *o) {
   free(o->body_of); free(o->off); free(o->cx); free(o->cy); free(o->ds);
   free(o->force);
   free(o->usx); free(o->usy); free(o->dFx); free(o->dFy); free(o->sl);
+  free(o->rx); free(o->ry); free(o->moving); free(o->theta); free(o->bvx); free(o->bvy); free(o->bom);
   free(o);
 }
 
@@ -245,8 +251,8 @@ static int grow_markers(oracle_t *o, int need) {
   if (need <= o->nm_cap) return 0;
   int cap = need * 2;
   double **arrs[] = {&o->X, &o->Y, &o->Ub, &o->Vb, &o->rho_l, &o->ux_l, &o->uy_l, &o->Fx, &o->Fy,
-                     &o->dFx, &o->dFy, &o->sl};
-  for (int a = 0; a < 12; ++a) {
+                     &o->dFx, &o->dFy, &o->sl, &o->rx, &o->ry};
+  for (int a = 0; a < 14; ++a) {
     double *p = (double *)realloc(*arrs[a], (size_t)cap * sizeof(double));
     if (!p) return -1;
     *arrs[a] = p;
@@ -271,6 +277,17 @@ int oracle_add_body(oracle_t *o, int n, const double *xy, const double *uv,
   double *pf = (double *)realloc(o->force, (size_t)(b + 1) * 3 * sizeof(double));
   if (!off || !pcx || !pcy || !pds || !pf) return -1;
   o->off = off; o->cx = pcx; o->cy = pcy; o->ds = pds; o->force = pf;
+  int *mv = (int *)realloc(o->moving, (size_t)(b + 1) * sizeof(int));
+  if (!mv) return -1;
+  o->moving = mv;
+  double **barrs[] = {&o->theta, &o->bvx, &o->bvy, &o->bom};
+  for (int a = 0; a < 4; ++a) {
+    double *q = (double *)realloc(*barrs[a], (size_t)(b + 1) * sizeof(double));
+    if (!q) return -1;
+    *barrs[a] = q;
+  }
+  o->moving[b] = 0;
+  o->theta[b] = o->bvx[b] = o->bvy[b] = o->bom[b] = 0.0;
   for (int l = 0; l < n; ++l) {
     int m = o->nm + l;
     o->X[m] = xy[2 * l];
@@ -279,6 +296,8 @@ int oracle_add_body(oracle_t *o, int n, const double *xy, const double *uv,
     o->Vb[m] = uv ? uv[2 * l + 1] : 0.0;
     o->rho_l[m] = o->ux_l[m] = o->uy_l[m] = o->Fx[m] = o->Fy[m] = 0.0;
     o->body_of[m] = b;
+    o->rx[m] = xy[2 * l] - cx;
+    o->ry[m] = xy[2 * l + 1] - cy;
   }
   o->off[b] = o->nm;
   o->nm += n;
@@ -296,6 +315,57 @@ void oracle_set_marker_velocity(oracle_t *o, int b, const double *uv) {
     int l = m - o->off[b];
     o->Ub[m] = uv[2 * l];
     o->Vb[m] = uv[2 * l + 1];
+  }
+}
+
+/* Rigid motion of body b (eq 4 for a rigid body whose surface moves with
+ * the fluid it carries): from now on the body translates with (vx, vy) and
+ * turns with omega (counter-clockwise, per step) about its centre. The
+ * markers' prescribed velocity becomes the rigid field at once,
+ * U_l = V + omega x (X_l - c); after every step the centre and angle
+ * advance by one step and the markers are placed at c + R(theta) r_l, with
+ * r_l their offsets from the centre when the body was added. */
+static void rigid_markers(oracle_t *o, int b) {
+  double c = cos(o->theta[b]), s = sin(o->theta[b]);
+  for (int m = o->off[b]; m < o->off[b + 1]; ++m) {
+    o->X[m] = o->cx[b] + c * o->rx[m] - s * o->ry[m];
+    o->Y[m] = o->cy[b] + s * o->rx[m] + c * o->ry[m];
+    o->Ub[m] = o->bvx[b] - o->bom[b] * (o->Y[m] - o->cy[b]);
+    o->Vb[m] = o->bvy[b] + o->bom[b] * (o->X[m] - o->cx[b]);
+  }
+}
+
+void oracle_set_body_motion(oracle_t *o, int b, double vx, double vy, double omega) {
+  o->moving[b] = 1;
+  o->bvx[b] = vx;
+  o->bvy[b] = vy;
+  o->bom[b] = omega;
+  for (int m = o->off[b]; m < o->off[b + 1]; ++m) {
+    o->Ub[m] = vx - omega * (o->Y[m] - o->cy[b]);
+    o->Vb[m] = vy + omega * (o->X[m] - o->cx[b]);
+  }
+}
+
+/* (cx, cy, theta, vx, vy, omega) of body b. */
+void oracle_body_state(const oracle_t *o, int b, double *out) {
+  out[0] = o->cx[b]; out[1] = o->cy[b]; out[2] = o->theta[b];
+  out[3] = o->bvx[b]; out[4] = o->bvy[b]; out[5] = o->bom[b];
+}
+
+void oracle_get_marker_positions(const oracle_t *o, double *xy) {
+  for (int m = 0; m < o->nm; ++m) {
+    xy[2 * m] = o->X[m];
+    xy[2 * m + 1] = o->Y[m];
+  }
+}
+
+static void move_bodies(oracle_t *o) {
+  for (int b = 0; b < o->nb; ++b) {
+    if (!o->moving[b]) continue;
+    o->cx[b] += o->bvx[b];
+    o->cy[b] += o->bvy[b];
+    o->theta[b] += o->bom[b];
+    rigid_markers(o, b);
   }
 }
 
@@ -649,6 +719,7 @@ void oracle_step(oracle_t *o, long n) {
     immersed_boundary(o);
     collide(o);
     boundary_columns(o);
+    move_bodies(o);
     o->steps += 1;
   }
 }
@@ -853,8 +924,10 @@ int oracle_adjoint(oracle_t *o, long n, const double *hist_bar, double *pop_bar,
   double *guv = (double *)calloc((size_t)(nm > 0 ? nm : 1) * 2, sizeof(double));
   double *gc = (double *)calloc((size_t)(nb > 0 ? nb : 1) * 2, sizeof(double));
   int rc = 0;
+  int any_moving = 0;
+  for (int b = 0; b < o->nb; ++b) any_moving |= o->moving[b];
   if (o->nf != 1 || o->method != ORC_DIRECT || o->bc[1] == ORC_CONVECTIVE_OUTLET ||
-      o->bc[2] == ORC_FREE_SLIP_WALL) {
+      o->bc[2] == ORC_FREE_SLIP_WALL || any_moving) {
     /* the reverse mode covers one forcing pass and the bounce-back / zero-gradient boundaries */
     rc = -1;
     goto done;

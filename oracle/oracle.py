@@ -63,6 +63,10 @@ def lib():
         L.oracle_delta_halfwidth.argtypes = [ctypes.c_int]
         L.oracle_set_forcing_passes.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.oracle_set_forcing_method.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.oracle_set_body_motion.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double]
+        L.oracle_body_state.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
+        L.oracle_get_marker_positions.argtypes = [ctypes.c_void_p, _dp]
         L.oracle_delta_deriv.restype = ctypes.c_double
         L.oracle_delta_deriv.argtypes = [ctypes.c_int, ctypes.c_double]
         L.oracle_adjoint.restype = ctypes.c_int
@@ -140,6 +144,20 @@ class OracleSim:
     def set_forcing_passes(self, nf):
         """Forcing passes per step (Algorithm 1 step 3; eqs 29-31 for nf > 1)."""
         lib().oracle_set_forcing_passes(self._h, int(nf))
+
+    def set_body_motion(self, b, vx, vy, omega):
+        """Rigid motion of body b from now on (eq 4 for a rigid body)."""
+        lib().oracle_set_body_motion(self._h, int(b), float(vx), float(vy), float(omega))
+
+    def body_state(self, b):
+        out = np.empty(6)
+        lib().oracle_body_state(self._h, int(b), _ptr(out))
+        return out
+
+    def marker_positions(self):
+        out = np.empty((lib().oracle_num_markers(self._h), 2))
+        lib().oracle_get_marker_positions(self._h, _ptr(out))
+        return out
 
     DIRECT, IMPLICIT, RKPM = 0, 1, 2
 
