@@ -186,8 +186,33 @@ int btdf_add_body(btdf_t *h, int n, const double *xy, const double *uv, double c
                   double ds, int *body_id);
 
 /* Replace the prescribed marker velocities of one body; uv: host [n][2].
- * Takes effect from the next enqueued step (synchronising). */
+ * Takes effect from the next enqueued step (synchronising). EINVAL for a
+ * body that moves rigidly (its velocities follow the motion). */
 int btdf_set_marker_velocity(btdf_t *h, int body, const double *uv);
+
+/* Rigid motion of one body from the next step on (eq 4 for a rigid body
+ * whose surface carries the fluid with it): translation (vx, vy) and
+ * angular velocity omega (counter-clockwise, radians per step) about its
+ * centre. The prescribed marker velocity becomes U_l = V + omega x (X_l - c)
+ * at once; after every step the centre and angle advance by one step and
+ * the markers are placed at c + R(theta) r_l, r_l their offsets from the
+ * centre when the body was added. (0, 0, 0) holds the body where it is. A
+ * marker may travel less than 2 nodes per step (|V| + |omega| max|r_l|);
+ * the tile lists of the spreading carry a 2-node margin and are rebuilt on
+ * the host before any marker can have left it, so a run with moving bodies
+ * synchronises every few tens of steps. A step that would carry a stencil
+ * out of the fluid region (non-periodic directions) fails with EINVAL
+ * before it is enqueued. Moving bodies need the direct forcing with NF = 1
+ * and are not covered by btdf_adjoint; stand-alone handles only. The motion
+ * state is not part of a checkpoint. */
+int btdf_set_body_motion(btdf_t *h, int body, double vx, double vy, double omega);
+
+/* (cx, cy, theta, vx, vy, omega) of one body after the steps enqueued so
+ * far (a fixed body reports its centre, zeros elsewhere). */
+int btdf_get_body_state(const btdf_t *h, int body, double *state);
+
+/* Marker positions, host [n_markers][2]. Synchronising. */
+int btdf_get_marker_positions(btdf_t *h, double *xy);
 
 /* Enqueue n >= 0 time steps (asynchronous). If during them a marker's
  * force became non-finite, a marker's interpolated |u*| exceeded 0.3, or a
@@ -245,7 +270,7 @@ int btdf_get_marker_data(btdf_t *h, double *rho_l, double *ux_l, double *uy_l, d
  * interpolated at the marker (eq 12). At rest markers its root mean square
  * is the boundary error of eq 45; in general U_b - u_b is the slip. Needs
  * a step since the state or the bodies last changed (ESTATE otherwise);
- * stand-alone handles only. Allocates a temporary device buffer for the
+ * stand-alone handles without moving bodies only. Allocates a temporary device buffer for the
  * covering-marker lists. Synchronising. */
 int btdf_marker_velocity(btdf_t *h, double *ux, double *uy);
 

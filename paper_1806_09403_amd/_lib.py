@@ -86,6 +86,9 @@ SIGNATURES = {
     "btdf_set_populations": (ctypes.c_int, [_vp, _dp]),
     "btdf_get_marker_data": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp, _dp]),
     "btdf_marker_velocity": (ctypes.c_int, [_vp, _dp, _dp]),
+    "btdf_set_body_motion": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    "btdf_get_body_state": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
+    "btdf_get_marker_positions": (ctypes.c_int, [_vp, _dp]),
     "btdf_state_bytes": (ctypes.c_size_t, [_vp]),
     "btdf_save": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "btdf_load": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),

@@ -122,6 +122,23 @@ def btdf_get_marker_data(h):
     return dict(zip(["rho", "ux", "uy", "Fx", "Fy"], [a[:nm] for a in arrs]))
 
 
+def btdf_set_body_motion(h, body, vx, vy, omega):
+    return check(load().btdf_set_body_motion(h, int(body), float(vx), float(vy), float(omega)))
+
+
+def btdf_get_body_state(h, body):
+    out = np.empty(6)
+    check(load().btdf_get_body_state(h, int(body), dptr(out)))
+    return out
+
+
+def btdf_get_marker_positions(h):
+    nm = btdf_counts(h)[1]
+    out = np.empty((max(nm, 1), 2))
+    check(load().btdf_get_marker_positions(h, dptr(out)))
+    return out[:nm]
+
+
 def btdf_marker_velocity(h):
     nm = btdf_counts(h)[1]
     u, v = np.empty(max(nm, 1)), np.empty(max(nm, 1))

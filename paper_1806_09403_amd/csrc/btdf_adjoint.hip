@@ -549,6 +549,7 @@ int btdf_adjoint(btdf_t *h, int64_t n_steps, int64_t checkpoint_every, const dou
   if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch");
   if (h->nf != 1) return fail(BTDF_ESTATE, "the reverse sweep needs one forcing pass per step (NF = 1)");
   if (h->method != BTDF_FORCING_DIRECT) return fail(BTDF_ESTATE, "the reverse sweep covers the direct forcing only");
+  if (h->any_moving()) return fail(BTDF_ESTATE, "the reverse sweep covers fixed bodies only");
   h->stepped = false;
   if (h->bc[1] == BTDF_CONVECTIVE_OUTLET || h->bc[2] == BTDF_FREE_SLIP_WALL)
     return fail(BTDF_EINVAL, "the reverse sweep covers periodic, bounce-back and zero-gradient boundaries only");

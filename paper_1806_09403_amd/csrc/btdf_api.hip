@@ -86,6 +86,10 @@ void bin_markers(const btdf_t *h, int tx, int ty, int ntx, int nty, std::vector<
     int xlo, xhi, ylo, yhi;
     marker_range(h->kind, h->X[l], &xlo, &xhi);
     marker_range(h->kind, h->Y[l], &ylo, &yhi);
+    xlo -= h->margin;  // moving bodies: every tile the stencil can reach before the next rebuild
+    xhi += h->margin;
+    ylo -= h->margin;
+    yhi += h->margin;
     for (int j = ylo; j <= yhi; ++j) {
       int jj = h->yper() ? ((j % h->ny) + h->ny) % h->ny : j;
       if (jj < 0 || jj >= h->ny) continue;
@@ -160,6 +164,75 @@ void cover_lists(const btdf_t *h, std::vector<int> &off, std::vector<int> &list)
   if (list.empty()) list.push_back(0);
 }
 
+// the most tiles one marker's (margin-widened) stencil can touch, over every launch shape
+int tiles_per_marker(const btdf_t *h) {
+  const int L = stencil_size(h->kind) + 2 * h->margin;
+  int best = 0;
+  for (int v = 0; v < num_variants(); ++v) {
+    int tx, ty;
+    variant_tile(v, &tx, &ty);
+    best = std::max(best, ((L - 1) / tx + 2) * ((L - 1) / ty + 2));
+  }
+  return best;
+}
+
+// Host copies of the moving bodies' markers from the mirrored centre and
+// angle, with the arithmetic of the device's rigid_move_kernel.
+void mirror_positions(btdf_t *h) {
+  for (int b = 0; b < h->nb(); ++b) {
+    if (!h->bmoving[b]) continue;
+    const double c = std::cos(h->theta[b]), s = std::sin(h->theta[b]);
+    const double cx = h->cx[b], cy = h->cy[b], vx = h->bvx[b], vy = h->bvy[b], om = h->bom[b];
+    for (int l = h->off[b]; l < h->off[b + 1]; ++l) {
+      const double X = cx + c * h->rx[l] - s * h->ry[l];
+      const double Y = cy + s * h->rx[l] + c * h->ry[l];
+      h->X[l] = X;
+      h->Y[l] = Y;
+      h->U[l] = vx - om * (Y - cy);
+      h->V[l] = vy + om * (X - cx);
+    }
+  }
+}
+
+// advance the mirrored centres and angles by k steps, one step at a time as the device does
+void mirror_advance(btdf_t *h, int64_t k) {
+  for (int b = 0; b < h->nb(); ++b) {
+    if (!h->bmoving[b]) continue;
+    for (int64_t t = 0; t < k; ++t) {
+      h->cx[b] += h->bvx[b];
+      h->cy[b] += h->bvy[b];
+      h->theta[b] += h->bom[b];
+    }
+  }
+}
+
+// per-step displacement bound of the fastest marker of a moving body
+double max_marker_speed(const btdf_t *h) {
+  double v = 0.0;
+  for (int b = 0; b < h->nb(); ++b)
+    if (h->bmoving[b]) v = std::max(v, std::hypot(h->bvx[b], h->bvy[b]) + std::fabs(h->bom[b]) * h->brad[b]);
+  return v;
+}
+
+MoveParams make_move(const btdf_t *h) {
+  MoveParams mp{};
+  const size_t M = (size_t)std::max(h->nm(), 1), B = (size_t)std::max(h->nb(), 1);
+  double *mk = h->at<double>(h->off_mk);
+  double *bd = h->at<double>(h->off_body);
+  mp.nb = h->nb();
+  mp.body_off = h->at<int>(h->off_boff);
+  mp.state = h->at<double>(h->off_motion);
+  mp.moving = reinterpret_cast<const int *>(h->ws + h->off_motion + 4 * B * sizeof(double));
+  mp.cx = bd;
+  mp.cy = bd + B;
+  mp.X = mk;
+  mp.Y = mk + M;
+  mp.U = mk + 2 * M;
+  mp.V = mk + 3 * M;
+  mp.rxy = h->at<double>(h->off_rxy);
+  return mp;
+}
+
 void compute_layout(btdf_t *h) {
   const size_t elt = (size_t)h->prec;
   const int a = h->row_align > 0 ? std::max(1, h->row_align / (int)elt) : 1;
@@ -176,6 +249,11 @@ void compute_layout(btdf_t *h) {
   h->nty = (h->ny + h->tile_y - 1) / h->tile_y;
   const int ntiles = h->ntx * h->nty;
 
+  mirror_positions(h);
+  // one node beyond the travel allowance: a device position within rounding of
+  // the host's may floor to the neighbouring stencil origin
+  h->margin = h->any_moving() ? kMoveMargin + 1 : 0;
+  h->steps_to_rebin = 0;
   bin_markers(h, h->tile_x, h->tile_y, h->ntx, h->nty, h->tile_off, h->tile_list);
   h->tile_map.clear();
   h->tile_map.reserve(ntiles);
@@ -211,7 +289,7 @@ void compute_layout(btdf_t *h) {
     variant_tile(v, &tx, &ty);
     max_tiles = std::max(max_tiles, (long long)((h->nx + tx - 1) / tx) * ((h->ny + ty - 1) / ty));
   }
-  const size_t list_cap = 10 * (size_t)nm + 1;
+  const size_t list_cap = (size_t)tiles_per_marker(h) * nm + 1;
   h->off_toff = o;
   o = align256(o + (size_t)(max_tiles + 1) * sizeof(int));
   h->off_tlist = o;
@@ -237,6 +315,11 @@ void compute_layout(btdf_t *h) {
   o = align256(o + h->minv_off.size() * sizeof(long long));
   h->off_minv = o;
   o = align256(o + h->minv.size() * sizeof(double));
+  // rigid motion: [nb][4] theta vx vy omega, then [nb] moving flags; [nm][2] offsets
+  h->off_motion = o;
+  o = align256(o + 4 * (size_t)std::max(nb, 1) * sizeof(double) + (size_t)std::max(nb, 1) * sizeof(int));
+  h->off_rxy = o;
+  o = align256(o + 2 * (size_t)std::max(nm, 1) * sizeof(double));
   h->total = o;
 
   h->layout_ok = true;
@@ -333,8 +416,10 @@ int upload_bodies(btdf_t *h) {
   const size_t M = (size_t)std::max(h->nm(), 1), B = (size_t)std::max(h->nb(), 1);
   const size_t nm = (size_t)h->nm(), nb = (size_t)h->nb();
   const size_t d = sizeof(double);
+  mirror_positions(h);  // moving bodies: the markers where the mirrored motion has taken them
   std::vector<char> &st = h->stage;
   st.assign(h->total - h->off_mk, 0);
+  auto st_base = [&](const btdf_t *, size_t off) { return st.data() + (off - h->off_mk); };
   auto put = [&](size_t off, const void *src, size_t bytes) {
     if (bytes) std::memcpy(st.data() + (off - h->off_mk), src, bytes);
   };
@@ -355,6 +440,22 @@ int upload_bodies(btdf_t *h) {
   put(h->off_toff, h->tile_off.data(), h->tile_off.size() * sizeof(int));
   put(h->off_tlist, h->tile_list.data(), h->tile_list.size() * sizeof(int));
   put(h->off_tmap, h->tile_map.data(), h->tile_map.size() * sizeof(int));
+  {
+    double *ms = reinterpret_cast<double *>(st_base(h, h->off_motion));
+    int *mv = reinterpret_cast<int *>(st_base(h, h->off_motion) + 4 * B * d);
+    double *r = reinterpret_cast<double *>(st_base(h, h->off_rxy));
+    for (int b = 0; b < h->nb(); ++b) {
+      ms[4 * b] = h->theta[b];
+      ms[4 * b + 1] = h->bvx[b];
+      ms[4 * b + 2] = h->bvy[b];
+      ms[4 * b + 3] = h->bom[b];
+      mv[b] = h->bmoving[b];
+    }
+    for (size_t l = 0; l < nm; ++l) {
+      r[2 * l] = h->rx[l];
+      r[2 * l + 1] = h->ry[l];
+    }
+  }
   put(h->off_moff, h->minv_off.data(), h->minv_off.size() * sizeof(long long));
   put(h->off_minv, h->minv.data(), h->minv.size() * sizeof(double));
   put(h->off_coff, h->cover_off.data(), h->cover_off.size() * sizeof(int));
@@ -480,13 +581,16 @@ int enqueue_step(btdf_t *h, const LbmParams &p, const IbParams &ib, int src, hip
     if (te) HIPCHK(hipEventRecord(te->b0, s));
     HIPCHK(launch_lbm(h->prec, h->variant, A, B, p, TileRange{map, h->n_free, h->n_forced, 1}, ib, s));
     if (te) HIPCHK(hipEventRecord(te->b1, s));
-    return ok();
+  } else {
+    if (te) HIPCHK(hipEventRecord(te->ib0, s));
+    HIPCHK(launch_ib(h->prec, A, p, ib, s));
+    if (te) HIPCHK(hipEventRecord(te->ib1, s));
+    HIPCHK(launch_lbm(h->prec, h->variant, A, B, p, TileRange{nullptr, 0, h->ntx * h->nty, 1}, ib, s));
+    if (te) HIPCHK(hipEventRecord(te->a1, s));
   }
-  if (te) HIPCHK(hipEventRecord(te->ib0, s));
-  HIPCHK(launch_ib(h->prec, A, p, ib, s));
-  if (te) HIPCHK(hipEventRecord(te->ib1, s));
-  HIPCHK(launch_lbm(h->prec, h->variant, A, B, p, TileRange{nullptr, 0, h->ntx * h->nty, 1}, ib, s));
-  if (te) HIPCHK(hipEventRecord(te->a1, s));
+  // moving bodies advance after the step that used their positions (the body
+  // reduction in the lattice launch reads the centres)
+  if (h->any_moving()) HIPCHK(launch_rigid_move(make_move(h), s));
   return ok();
 }
 
@@ -584,13 +688,23 @@ int add_body_impl(btdf_t *h, int n, const double *xy, const double *uv, double c
   if ((long long)h->nm() + n > (1LL << 30)) return fail(BTDF_EINVAL, "too many markers");
   try {
     const double s = h->drs * ds;
+    double rad = 0.0;
     for (int l = 0; l < n; ++l) {
       h->X.push_back(xy[2 * l]);
       h->Y.push_back(xy[2 * l + 1]);
       h->U.push_back(uv ? uv[2 * l] : 0.0);
       h->V.push_back(uv ? uv[2 * l + 1] : 0.0);
       h->sdrs.push_back(s);
+      h->rx.push_back(xy[2 * l] - cx);
+      h->ry.push_back(xy[2 * l + 1] - cy);
+      rad = std::max(rad, std::hypot(xy[2 * l] - cx, xy[2 * l + 1] - cy));
     }
+    h->bmoving.push_back(0);
+    h->theta.push_back(0.0);
+    h->bvx.push_back(0.0);
+    h->bvy.push_back(0.0);
+    h->bom.push_back(0.0);
+    h->brad.push_back(rad);
     h->off.push_back(h->nm());
     h->cx.push_back(cx);
     h->cy.push_back(cy);
@@ -722,9 +836,62 @@ int btdf_add_body(btdf_t *h, int n, const double *xy, const double *uv, double c
   return add_body_impl(h, n, xy, uv, cx, cy, ds, body_id);
 }
 
+int btdf_set_body_motion(btdf_t *h, int body, double vx, double vy, double omega) {
+  if (!h) return fail(BTDF_EINVAL, "NULL handle");
+  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch");
+  if (body < 0 || body >= h->nb()) return fail(BTDF_EINVAL, "no body %d", body);
+  if (!std::isfinite(vx) || !std::isfinite(vy) || !std::isfinite(omega)) return fail(BTDF_EINVAL, "non-finite motion");
+  if (h->method != BTDF_FORCING_DIRECT || h->nf != 1)
+    return fail(BTDF_ESTATE, "moving bodies need the direct forcing method with one pass");
+  const double v = std::hypot(vx, vy) + std::fabs(omega) * h->brad[body];
+  if (!(v < kMoveMargin)) return fail(BTDF_EINVAL, "markers would travel %g nodes per step (at most %d)", v, kMoveMargin);
+  const bool first = !h->any_moving();
+  mirror_positions(h);  // where a body already moving is now
+  h->bmoving[body] = 1;
+  h->bvx[body] = vx;
+  h->bvy[body] = vy;
+  h->bom[body] = omega;
+  mirror_positions(h);  // and the rigid velocity field at those positions
+  if (first) h->layout_ok = false;  // tile lists gain their margin
+  h->device_ok = false;
+  h->steps_to_rebin = 0;
+  drop_graph(h);
+  return ok();
+}
+
+int btdf_get_body_state(const btdf_t *h, int body, double *state) {
+  if (!h || !state) return fail(BTDF_EINVAL, "NULL argument");
+  if (body < 0 || body >= h->nb()) return fail(BTDF_EINVAL, "no body %d", body);
+  state[0] = h->cx[body];
+  state[1] = h->cy[body];
+  state[2] = h->theta[body];
+  state[3] = h->bvx[body];
+  state[4] = h->bvy[body];
+  state[5] = h->bom[body];
+  return ok();
+}
+
+int btdf_get_marker_positions(btdf_t *h, double *xy) {
+  if (!h || !xy) return fail(BTDF_EINVAL, "NULL argument");
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const size_t nm = (size_t)h->nm(), d = sizeof(double);
+  if (nm == 0) return ok();
+  std::vector<double> x(nm), y(nm);
+  HIPCHK(hipMemcpy(x.data(), h->ws + h->off_mk, nm * d, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(y.data(), h->ws + h->off_mk + (size_t)std::max(h->nm(), 1) * d, nm * d, hipMemcpyDeviceToHost));
+  for (size_t l = 0; l < nm; ++l) {
+    xy[2 * l] = x[l];
+    xy[2 * l + 1] = y[l];
+  }
+  return ok();
+}
+
 int btdf_set_marker_velocity(btdf_t *h, int body, const double *uv) {
   if (!h || !uv) return fail(BTDF_EINVAL, "NULL argument");
   if (body < 0 || body >= h->nb()) return fail(BTDF_EINVAL, "no body %d", body);
+  if (h->bmoving[body]) return fail(BTDF_ESTATE, "body %d moves rigidly; its marker velocities follow the motion", body);
   const int l0 = h->off[body], l1 = h->off[body + 1];
   for (int l = l0; l < l1; ++l)
     if (!std::isfinite(uv[2 * (l - l0)]) || !std::isfinite(uv[2 * (l - l0) + 1]))
@@ -743,15 +910,9 @@ int btdf_set_marker_velocity(btdf_t *h, int body, const double *uv) {
   return ok();
 }
 
-int btdf_step(btdf_t *h, int64_t n) {
-  if (!h) return fail(BTDF_EINVAL, "NULL handle");
-  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; step the batch");
-  if (n < 0) return fail(BTDF_EINVAL, "negative step count");
-  if (n == 0) return ok();
-  int rc = ensure_device(h);
-  if (rc) return rc;
-  const LbmParams p = make_params(h);
-  const IbParams ib = make_ib(h);
+// n steps from the current buffer: graphs of graph_chunk steps where they fit
+static int run_steps(btdf_t *h, const LbmParams &p, const IbParams &ib, int64_t n) {
+  int rc;
   int64_t left = n;
   if (h->graph_chunk > 0 && left >= h->graph_chunk + (h->cur ? 1 : 0)) {
     if (h->cur) {  // graphs start from buffer 0
@@ -775,6 +936,76 @@ int btdf_step(btdf_t *h, int64_t n) {
     h->cur ^= 1;
     h->steps++;
   }
+  return ok();
+}
+
+// Moving bodies: place the host markers at the mirrored motion, check that
+// no stencil can leave the fluid region before the next rebuild, rebuild the
+// tile lists with the margin and send them. Synchronises the stream first,
+// so the host lists are not changed under a copy in flight.
+static int rebin(btdf_t *h) {
+  HIPCHK(hipStreamSynchronize(h->stream));
+  mirror_positions(h);
+  const int m = h->margin;
+  for (int b = 0; b < h->nb(); ++b) {
+    if (!h->bmoving[b]) continue;
+    for (int l = h->off[b]; l < h->off[b + 1]; ++l) {
+      int lo, hi;
+      marker_range(h->kind, h->X[l], &lo, &hi);
+      if (!h->xper() && (lo - m < h->i0() || hi + m > h->i1()))
+        return fail(BTDF_EINVAL, "moving body %d would leave the fluid columns (step %lld)", b, (long long)h->steps);
+      marker_range(h->kind, h->Y[l], &lo, &hi);
+      if (!h->yper() && (lo - m < 0 || hi + m > h->ny - 1))
+        return fail(BTDF_EINVAL, "moving body %d would leave the grid (step %lld)", b, (long long)h->steps);
+    }
+  }
+  bin_markers(h, h->tile_x, h->tile_y, h->ntx, h->nty, h->tile_off, h->tile_list);
+  if (h->tile_list.size() > (size_t)tiles_per_marker(h) * h->nm() + 1)
+    return fail(BTDF_EDEVICE, "tile lists overflow their region");
+  const int ntiles = h->ntx * h->nty;
+  h->tile_map.clear();
+  for (int t = 0; t < ntiles; ++t)
+    if (h->tile_off[t + 1] == h->tile_off[t]) h->tile_map.push_back(t);
+  const int n_free = (int)h->tile_map.size();
+  for (int t = 0; t < ntiles; ++t)
+    if (h->tile_off[t + 1] != h->tile_off[t]) h->tile_map.push_back(t);
+  if (n_free != h->n_free) drop_graph(h);  // the overlapped step launches the free tiles apart
+  h->n_free = n_free;
+  h->n_forced = ntiles - n_free;
+  int rc;
+  if ((rc = upload(h, h->off_toff, h->tile_off.data(), h->tile_off.size() * sizeof(int)))) return rc;
+  if ((rc = upload(h, h->off_tlist, h->tile_list.data(), h->tile_list.size() * sizeof(int)))) return rc;
+  if ((rc = upload(h, h->off_tmap, h->tile_map.data(), h->tile_map.size() * sizeof(int)))) return rc;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const double v = max_marker_speed(h);
+  h->steps_to_rebin = v > 0.0 ? (int64_t)std::floor(kMoveMargin / v) : ((int64_t)1 << 60);
+  if (h->steps_to_rebin < 1)
+    return fail(BTDF_EINVAL, "a moving body's markers travel %g nodes per step; less than %d are allowed", v,
+                kMoveMargin);
+  return ok();
+}
+
+int btdf_step(btdf_t *h, int64_t n) {
+  if (!h) return fail(BTDF_EINVAL, "NULL handle");
+  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; step the batch");
+  if (n < 0) return fail(BTDF_EINVAL, "negative step count");
+  if (n == 0) return ok();
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  const LbmParams p = make_params(h);
+  const IbParams ib = make_ib(h);
+  if (!h->any_moving()) {
+    if ((rc = run_steps(h, p, ib, n))) return rc;
+  } else {
+    for (int64_t left = n; left > 0;) {
+      if (h->steps_to_rebin <= 0 && (rc = rebin(h))) return rc;
+      const int64_t k = std::min(left, h->steps_to_rebin);
+      if ((rc = run_steps(h, p, ib, k))) return rc;
+      mirror_advance(h, k);
+      h->steps_to_rebin -= k;
+      left -= k;
+    }
+  }
   h->stepped = true;
   return ok();
 }
@@ -796,11 +1027,17 @@ int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm) {
   rc = ok();
   while (done < n && rc == 0) {
     const int m = (int)std::min<int64_t>(chunk, n - done);
+    const bool moving = h->any_moving();
     for (int k = 0; k < m && rc == 0; ++k) {
+      if (moving && h->steps_to_rebin <= 0 && (rc = rebin(h))) break;
       const StepEvents te{ev[6 * k], ev[6 * k + 1], ev[6 * k + 2], ev[6 * k + 3], ev[6 * k + 4], ev[6 * k + 5]};
       rc = enqueue_step(h, p, ib, h->cur, h->stream, &te);
       h->cur ^= 1;
       h->steps++;
+      if (moving) {
+        mirror_advance(h, 1);
+        h->steps_to_rebin--;
+      }
     }
     if (rc) break;
     hipError_t e = hipStreamSynchronize(h->stream);
@@ -1005,6 +1242,8 @@ int btdf_marker_velocity(btdf_t *h, double *ux, double *uy) {
     return fail(BTDF_ESTATE, "no step since the state, the bodies or the layout last changed");
   const int nm = h->nm();
   if (nm == 0) return ok();
+  if (h->any_moving())
+    return fail(BTDF_ESTATE, "moving bodies: the markers have moved on since the last step's forces");
   std::vector<int> off, list;
   cover_lists(h, off, list);
   const size_t b_off = off.size() * sizeof(int), b_list = list.size() * sizeof(int);
@@ -1153,6 +1392,8 @@ int btdf_set_option(btdf_t *h, int key, int64_t value) {
         return fail(BTDF_EINVAL, "unknown forcing method %lld", (long long)value);
       if (value != BTDF_FORCING_DIRECT && h->nf != 1)
         return fail(BTDF_ESTATE, "the implicit and RKPM methods take one forcing pass (NF = 1)");
+      if (value != BTDF_FORCING_DIRECT && h->any_moving())
+        return fail(BTDF_ESTATE, "moving bodies need the direct forcing method");
       if (value != h->method) {
         h->method = (int)value;
         h->layout_ok = false;  // matrices and marker factors change
@@ -1165,6 +1406,7 @@ int btdf_set_option(btdf_t *h, int key, int64_t value) {
       if (value < 1 || value > 64) return fail(BTDF_EINVAL, "forcing passes must be in 1 .. 64");
       if (value != 1 && h->method != BTDF_FORCING_DIRECT)
         return fail(BTDF_ESTATE, "forcing passes need the direct forcing method");
+      if (value != 1 && h->any_moving()) return fail(BTDF_ESTATE, "moving bodies take one forcing pass");
       if (value != h->nf) {
         h->nf = (int)value;
         h->layout_ok = false;  // the pass buffers change size

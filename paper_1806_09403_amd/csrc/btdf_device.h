@@ -127,6 +127,17 @@ struct TileRange {
   int count_step;  // this launch advances the device step counter
 };
 
+// rigid body motion, one workgroup per body after each step
+struct MoveParams {
+  int nb;
+  const int *body_off;
+  const int *moving;   // [nb]
+  double *state;       // [nb][4]: theta, vx, vy, omega
+  double *cx, *cy;     // body centres
+  double *X, *Y, *U, *V;
+  const double *rxy;   // [nm][2]: offset from the centre at angle 0
+};
+
 struct IbParams {
   int nb, nm;
   const int *body_off;  // [nb + 1]

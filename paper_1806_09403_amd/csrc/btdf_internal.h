@@ -55,6 +55,15 @@ struct btdf_sim {
   std::vector<double> bds;                 // arc length per marker of each body
   int max_body = 0;                        // markers of the largest body
   std::string method_err;                  // set-up failure of the implicit / RKPM matrices
+  // rigid motion (host mirror of the device integration): per body a moving
+  // flag, angle, velocity and angular velocity, per marker its offset from
+  // the centre at angle 0; tile lists carry a margin and are rebuilt before
+  // any marker can have moved by more than it
+  std::vector<int> bmoving;
+  std::vector<double> theta, bvx, bvy, bom, brad;
+  std::vector<double> rx, ry;
+  int margin = 0;
+  int64_t steps_to_rebin = 0;
   // device memory
   char *ws = nullptr;
   size_t ws_bytes = 0;
@@ -65,7 +74,7 @@ struct btdf_sim {
   size_t off_pop[2] = {0, 0}, off_ctl = 0, grid_bytes = 0;
   size_t off_hist = 0, off_mk = 0, off_mkw = 0, off_mkixy = 0, off_mkbody = 0, off_body = 0, off_boff = 0,
          off_toff = 0, off_tlist = 0, off_tmap = 0, off_coff = 0, off_clist = 0, off_mdfc = 0, off_mdff = 0,
-         off_moff = 0, off_minv = 0, total = 0;
+         off_moff = 0, off_minv = 0, off_motion = 0, off_rxy = 0, total = 0;
   bool layout_ok = false;  // host layout current for bodies and tiles
   bool device_ok = false;  // body part uploaded into the workspace
   bool state_ok = false;   // populations hold a state
@@ -81,6 +90,11 @@ struct btdf_sim {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   int nb() const { return (int)cx.size(); }
+  bool any_moving() const {
+    for (int m : bmoving)
+      if (m) return true;
+    return false;
+  }
   int nm() const { return (int)X.size(); }
   bool xper() const { return bc[0] == BTDF_PERIODIC; }
   bool yper() const { return bc[2] == BTDF_PERIODIC; }
@@ -104,6 +118,7 @@ void bin_markers(const btdf_t *h, int tx, int ty, int ntx, int nty, std::vector<
 void cover_lists(const btdf_t *h, std::vector<int> &off, std::vector<int> &list);
 // implicit / RKPM matrices of the current bodies ("" or the reason they cannot be formed)
 constexpr int kMaxImplicitBody = 2048;
+constexpr int kMoveMargin = 2;  // nodes a moving marker may travel between tile-list rebuilds
 std::string forcing_setup(btdf_t *h);
 LbmParams make_params(const btdf_t *h);
 IbParams make_ib(const btdf_t *h);

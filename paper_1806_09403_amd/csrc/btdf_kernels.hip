@@ -637,6 +637,41 @@ hipError_t launch_ib_batch(int prec, const CaseDesc *cases, const BatchMap &m, i
   return hipGetLastError();
 }
 
+// Rigid motion after a step (eq 4 for a rigid body): each moving body
+// advances its centre and angle by one step, and its markers are placed at
+// c + R(theta) r_l with the rigid velocity V + omega x (X_l - c), which the
+// next step prescribes. One workgroup per body.
+__global__ __launch_bounds__(256) void rigid_move_kernel(MoveParams mp) {
+#pragma clang fp contract(off)
+  const int b = (int)blockIdx.x;
+  if (!mp.moving[b]) return;
+  double *st = mp.state + 4 * (long long)b;
+  const double vx = st[1], vy = st[2], om = st[3];
+  const double cx = mp.cx[b] + vx, cy = mp.cy[b] + vy, th = st[0] + om;
+  __syncthreads();  // every lane has read the old state
+  if (threadIdx.x == 0) {
+    mp.cx[b] = cx;
+    mp.cy[b] = cy;
+    st[0] = th;
+  }
+  const double c = cos(th), s = sin(th);
+  for (int l = mp.body_off[b] + (int)threadIdx.x; l < mp.body_off[b + 1]; l += 256) {
+    const double rx = mp.rxy[2 * (long long)l], ry = mp.rxy[2 * (long long)l + 1];
+    const double X = cx + c * rx - s * ry;
+    const double Y = cy + s * rx + c * ry;
+    mp.X[l] = X;
+    mp.Y[l] = Y;
+    mp.U[l] = vx - om * (Y - cy);
+    mp.V[l] = vy + om * (X - cx);
+  }
+}
+
+hipError_t launch_rigid_move(const MoveParams &mp, hipStream_t s) {
+  if (mp.nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(rigid_move_kernel, dim3(mp.nb), dim3(256), 0, s, mp);
+  return hipGetLastError();
+}
+
 // Implicit direct forcing (eq 17): one workgroup per body replaces the
 // direct force of its markers (eq 20, left by the marker kernel) by
 // (D_I D_E)^-1 times it, with the body's inverse kept column-major, and

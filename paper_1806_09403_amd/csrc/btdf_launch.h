@@ -11,6 +11,7 @@ void variant_tile(int v, int *tx, int *ty);
 hipError_t launch_lbm(int prec, int variant, const void *A, void *B, const LbmParams &p, const TileRange &r,
                       const IbParams &ib, hipStream_t s);
 hipError_t launch_ib(int prec, const void *A, const LbmParams &p, const IbParams &ib, hipStream_t s);
+hipError_t launch_rigid_move(const MoveParams &mp, hipStream_t s);
 hipError_t launch_marker_velocity(int prec, const void *A, const LbmParams &p, const IbParams &ib,
                                   const int *cover_off, const int *cover_list, double *out, hipStream_t s);
 hipError_t launch_lbm_batch(int prec, int variant, const CaseDesc *cases, const BatchMap &m, int parity,

@@ -98,6 +98,22 @@ class Sim:
     def marker_data(self):
         return api.btdf_get_marker_data(self._workspace())
 
+    @property
+    def steps(self):
+        """Steps taken so far."""
+        return api.btdf_counts(self.h)[2]
+
+    def set_body_motion(self, body, vx, vy, omega):
+        """Rigid motion of a body from the next step on (translation and turn rate per step)."""
+        return api.btdf_set_body_motion(self.h, body, vx, vy, omega)
+
+    def body_state(self, body):
+        """(cx, cy, theta, vx, vy, omega) of a body."""
+        return api.btdf_get_body_state(self.h, body)
+
+    def marker_positions(self):
+        return api.btdf_get_marker_positions(self._workspace())
+
     def marker_velocity(self):
         """(u, v) at every marker after the last step (eq 11 interpolated by eq 12)."""
         return api.btdf_marker_velocity(self._workspace())

@@ -1,0 +1,147 @@
+"""GPU parity of rigidly moving bodies (eq 4 for a rigid body) against the
+oracle, and the host-side guards of the moving path (tile lists rebuilt
+before a marker can outrun their margin; a body about to leave the fluid
+region stops the run before the step is enqueued)."""
+import numpy as np
+import pytest
+
+import btdf_workloads as W
+from oracle.oracle import OracleSim
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def both(nx, ny, bc, kind, bodies, motions, init=(1.0, 0.02, 0.0), G=(0.0, 0.0), inflow=(0.0, 0.0),
+         precision=8, options=None):
+    from paper_1806_09403_amd import Sim
+    o = OracleSim(nx, ny, bc, 0.75, kind, 1.9, G, inflow, init)
+    g = Sim(nx, ny, 0.75, kind, 1.9, bc, inflow, G, init, precision)
+    for k, v in (options or {}).items():
+        g.set_option(k, v)
+    for b in bodies:
+        o.add_body(b.xy, None, b.cx, b.cy, b.ds)
+        g.add_body(b.xy, None, b.cx, b.cy, b.ds)
+    for i, m in enumerate(motions):
+        if m is not None:
+            o.set_body_motion(i, *m)
+            g.set_body_motion(i, *m)
+    return o, g
+
+
+@pytest.mark.parametrize("kind", [W.ROMA3, W.COS4])
+def test_fp64_moving_bodies_match_oracle(kind):
+    """Two bodies, one translating across both periodic seams while it
+    turns, one turning in place, one fixed; 130 steps cover several
+    tile-list rebuilds."""
+    log("moving parity kind=%d" % kind)
+    bodies = [W.cylinder_body(70.5, 44.2, 10.0, 31), W.cylinder_body(30.2, 25.7, 8.0, 25),
+              W.cylinder_body(40.6, 8.3, 6.0, 19)]
+    o, g = both(80, 50, W.FULLY_PERIODIC, kind, bodies, [(0.035, 0.021, 0.004), (0.0, 0.0, -0.006), None])
+    for n in (1, 40, 44, 45):
+        o.step(n)
+        g.step(n)
+        assert np.max(np.abs(g.populations() - o.populations())) < 1e-13, n
+        Fo, Fg = o.forces(), g.forces()
+        assert np.max(np.abs(Fg - Fo)) < 1e-11 * np.max(np.abs(Fo)), n
+        assert np.max(np.abs(g.marker_positions() - o.marker_positions())) < 1e-12, n
+        for b in range(3):
+            assert np.max(np.abs(g.body_state(b) - o.body_state(b))) < 1e-12, (n, b)
+    g.close()
+
+
+def test_fp64_moving_in_a_channel_with_walls():
+    bodies = [W.cylinder_body(30.3, 24.6, 10.0, 31)]
+    bc = (W.VELOCITY_INLET, W.ZERO_GRADIENT_OUTLET, W.BOUNCEBACK_WALL, W.BOUNCEBACK_WALL)
+    o, g = both(120, 50, bc, W.ROMA3, bodies, [(0.04, 0.0, 0.003)], inflow=(0.02, 0.0))
+    for n in (30, 50):
+        o.step(n)
+        g.step(n)
+        assert np.max(np.abs(g.populations() - o.populations())) < 1e-13, n
+    g.close()
+
+
+def test_comoving_body_leaves_a_uniform_flow_untouched():
+    from paper_1806_09403_amd import Sim
+    for prec, tol in ((8, 1e-13), (4, 1e-6)):
+        s = Sim(96, 64, 0.8, W.PESKIN4, 2.6, W.FULLY_PERIODIC, init=(1.0, 0.03, -0.01), precision=prec)
+        b = W.cylinder_body(40.2, 30.7, 12.0, 38)
+        s.add_body(b.xy, None, b.cx, b.cy, b.ds)
+        s.set_body_motion(0, 0.03, -0.01, 0.0)
+        f0 = s.populations()
+        s.step(300)
+        assert np.max(np.abs(s.populations() - f0)) < tol, prec
+        assert np.max(np.abs(s.forces())) < 1e-9
+        st = s.body_state(0)
+        assert abs(st[0] - (40.2 + 300 * 0.03)) < 1e-11 and abs(st[1] - (30.7 - 300 * 0.01)) < 1e-11
+        s.close()
+
+
+def test_launch_shapes_graphs_and_timed_steps_are_bit_identical():
+    from paper_1806_09403_amd import _lib
+    bodies = [W.cylinder_body(50.3, 30.2, 10.0, 31), W.cylinder_body(100.7, 40.1, 9.0, 28)]
+    motions = [(0.03, 0.01, 0.002), (-0.02, 0.0, -0.004)]
+    ref = None
+    for v, chunk, overlap, timed in ((6, 0, 0, False), (6, 16, 0, False), (0, 0, 1, False), (11, 5, 1, False),
+                                     (6, 0, 0, True)):
+        o, g = both(150, 64, W.FULLY_PERIODIC, W.COS4, bodies, motions, precision=4,
+                    options={_lib.OPT_LBM_VARIANT: v, _lib.OPT_GRAPH_CHUNK: chunk, _lib.OPT_OVERLAP: overlap})
+        for n in (7, 60, 33):
+            if timed:
+                g.step_timed(n)
+            else:
+                g.step(n)
+        out = (g.populations(), g.force_history(100), g.marker_positions())
+        if ref is None:
+            ref = out
+        for a, b in zip(out, ref):
+            assert np.array_equal(a, b), (v, chunk, overlap, timed)
+        g.close()
+
+
+def test_a_body_about_to_leave_the_fluid_stops_the_run():
+    """Host-side guard: the body heads for the south wall; the run refuses
+    the step that could carry a stencil out of the grid, and everything
+    stepped before stays as the oracle has it."""
+    from paper_1806_09403_amd import BtdfError
+    bc = (W.PERIODIC, W.PERIODIC, W.BOUNCEBACK_WALL, W.BOUNCEBACK_WALL)
+    bodies = [W.cylinder_body(40.0, 15.0, 8.0, 25)]
+    o, g = both(80, 40, bc, W.ROMA3, bodies, [(0.0, -0.05, 0.0)])
+    done = 0
+    with pytest.raises(BtdfError):
+        for _ in range(400):
+            g.step(5)
+            done += 5
+    st = g.body_state(0)
+    lowest = np.min(g.marker_positions()[:, 1])
+    log("  stopped after %d steps, centre y %.3f, lowest marker %.3f" % (g.steps, st[1], lowest))
+    assert np.floor(lowest + 0.5) - 1 >= 0   # every 3-point stencil still inside the grid
+    assert lowest < 6.0                   # and the guard did not stop it far from the wall
+    o.step(g.steps)
+    assert np.max(np.abs(g.populations() - o.populations())) < 1e-13
+    g.close()
+
+
+def test_refusals():
+    from paper_1806_09403_amd import BtdfError, _lib
+    bodies = [W.cylinder_body(30.0, 20.0, 8.0, 25)]
+    o, g = both(64, 40, W.FULLY_PERIODIC, W.ROMA3, bodies, [None])
+    with pytest.raises(BtdfError):
+        g.set_body_motion(0, 2.5, 0.0, 0.0)                  # faster than the margin allows
+    with pytest.raises(BtdfError):
+        g.set_body_motion(3, 0.0, 0.0, 0.0)                  # no such body
+    g.set_body_motion(0, 0.01, 0.0, 0.0)
+    for key, val in ((_lib.OPT_FORCING_METHOD, 1), (_lib.OPT_FORCING_PASSES, 2)):
+        with pytest.raises(BtdfError):
+            g.set_option(key, val)
+    with pytest.raises(BtdfError):
+        g.set_marker_velocity(0, np.zeros((25, 2)))
+    with pytest.raises(BtdfError):
+        g.adjoint(2, np.zeros((2, 1, 3)))
+    g.step(2)
+    with pytest.raises(BtdfError):   # the markers have moved on since the step's forces
+        g.marker_velocity()
+    g.close()
