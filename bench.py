@@ -54,6 +54,8 @@ def parse():
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint figures")
     p.add_argument("--only-adjoint", action="store_true", help="print the adjoint figures alone")
     p.add_argument("--adjoint-steps", type=int, default=5000)
+    p.add_argument("--no-validation", action="store_true",
+                   help="skip the 1601^2 cylinder check at Re 40 (Table 3)")
     return p.parse_args()
 
 
@@ -230,6 +232,20 @@ def bench_adjoint(args):
     return out
 
 
+def bench_validation(args):
+    """The paper's cylinder case at its own size (Section 5.2), Re 40:
+    drag coefficient and wake length against Table 3's row of the method."""
+    import btdf_workloads as W
+    from paper_1806_09403_amd import validation
+    t0 = time.perf_counter()
+    case = W.v40(40.0)
+    r = validation.run_steady(case, max_steps=40_000)
+    return {"workload": case.name, "delta": "roma3", "thickening": case.thickening, "Re": 40,
+            "steps": r["steps"], "Cd": round(r["Cd"], 5), "Lw": round(r["Lw"], 4),
+            "boundary_error": float("%.4g" % r["boundary_error"]),
+            "paper": {"Cd": 1.551, "Lw": 2.40}, "seconds": round(time.perf_counter() - t0, 1)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -331,6 +347,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_adjoint:
         line["adjoint"] = bench_adjoint(args)
+        torch.cuda.empty_cache()
+    if not args.no_validation:
+        line["validation"] = bench_validation(args)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_budget_s)

@@ -588,6 +588,7 @@ int enqueue_step(btdf_t *h, const LbmParams &p, const IbParams &ib, int src, hip
     HIPCHK(launch_lbm(h->prec, h->variant, A, B, p, TileRange{nullptr, 0, h->ntx * h->nty, 1}, ib, s));
     if (te) HIPCHK(hipEventRecord(te->a1, s));
   }
+  if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, A, B, p, s));
   // moving bodies advance after the step that used their positions (the body
   // reduction in the lattice launch reads the centres)
   if (h->any_moving()) HIPCHK(launch_rigid_move(make_move(h), s));

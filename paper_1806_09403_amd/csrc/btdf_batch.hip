@@ -196,6 +196,9 @@ int batch_enqueue(btdf_batch_t *b, int parity, hipStream_t s, const BatchEvents 
   if (te) HIPCHK(hipEventRecord(te->e1, s));
   HIPCHK(launch_lbm_batch(b->prec, b->variant, desc, b->map, parity, s));
   if (te) HIPCHK(hipEventRecord(te->e2, s));
+  bool conv = false;
+  for (const btdf_t *c : b->cases) conv |= c->bc[1] == BTDF_CONVECTIVE_OUTLET;
+  if (conv) HIPCHK(launch_conv_outlet_batch(b->prec, desc, (int)b->cases.size(), b->mask, parity, s));
   return ok();
 }
 

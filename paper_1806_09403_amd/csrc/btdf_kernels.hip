@@ -381,16 +381,6 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
 #pragma unroll
       for (int q = 0; q < 9; ++q) B[(long long)q * p.plane + base + 1] = out[q];
     }
-    if (p.outlet == 2 && x == p.nx - 2) {
-      // convective: d/dt + U d/dx = 0 on the ghost, implicit upwind (the
-      // reference offsets cancel: the weights sum to one)
-      const T U = (T)p.uconv, den = (T)(1.0 + p.uconv);
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        const long long o = (long long)q * p.plane + base + 1;
-        B[o] = (A[o] + U * out[q]) / den;
-      }
-    }
   }
   if (bad) p.flag[0] = -1;
 }
@@ -634,6 +624,58 @@ hipError_t launch_ib_batch(int prec, const CaseDesc *cases, const BatchMap &m, i
     hipLaunchKernelGGL(ib_batch_kernel<float>, dim3(m.nmblk), dim3(256), 0, s, cases, m, parity);
   else
     hipLaunchKernelGGL(ib_batch_kernel<double>, dim3(m.nmblk), dim3(256), 0, s, cases, m, parity);
+  return hipGetLastError();
+}
+
+// Convective outlet (d/dt + U d/dx = 0 on the ghost column, implicit
+// upwind): after the lattice kernel has written column nx-2 of B, the ghost
+// of B is (ghost of A + U column nx-2 of B) / (1 + U). The reference
+// offsets of the stored deviations cancel (the weights sum to one). Kept
+// out of the lattice kernel, where it cost registers on every node.
+template <typename T>
+__device__ __forceinline__ void conv_outlet_row(const T *__restrict__ A, T *__restrict__ B, const LbmParams &p,
+                                                int y) {
+  const T U = (T)p.uconv, den = (T)(1.0 + p.uconv);
+  const long long base = (long long)y * p.pitch + p.nx - 2;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const long long o = (long long)q * p.plane + base;
+    B[o + 1] = (A[o + 1] + U * B[o]) / den;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void conv_outlet_kernel(const T *__restrict__ A, T *__restrict__ B, LbmParams p) {
+  const int y = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (y < p.ny) conv_outlet_row<T>(A, B, p, y);
+}
+
+// batches: one workgroup per case, cases without a convective outlet (or stopped) return
+template <typename T>
+__global__ __launch_bounds__(256) void conv_outlet_batch_kernel(const CaseDesc *__restrict__ cases, int mask_unstable,
+                                                                int parity) {
+  const CaseDesc &cd = cases[blockIdx.x];
+  if (cd.p.outlet != 2 || (mask_unstable && cd.p.flag[0] != 0)) return;
+  const T *A = reinterpret_cast<const T *>(cd.pop[parity]);
+  T *B = reinterpret_cast<T *>(cd.pop[parity ^ 1]);
+  for (int y = (int)threadIdx.x; y < cd.p.ny; y += 256) conv_outlet_row<T>(A, B, cd.p, y);
+}
+
+hipError_t launch_conv_outlet(int prec, const void *A, void *B, const LbmParams &p, hipStream_t s) {
+  const int blocks = (p.ny + 255) / 256;
+  if (prec == 4)
+    hipLaunchKernelGGL(conv_outlet_kernel<float>, dim3(blocks), dim3(256), 0, s, (const float *)A, (float *)B, p);
+  else
+    hipLaunchKernelGGL(conv_outlet_kernel<double>, dim3(blocks), dim3(256), 0, s, (const double *)A, (double *)B, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_conv_outlet_batch(int prec, const CaseDesc *cases, int ncases, int mask_unstable, int parity,
+                                    hipStream_t s) {
+  if (prec == 4)
+    hipLaunchKernelGGL(conv_outlet_batch_kernel<float>, dim3(ncases), dim3(256), 0, s, cases, mask_unstable, parity);
+  else
+    hipLaunchKernelGGL(conv_outlet_batch_kernel<double>, dim3(ncases), dim3(256), 0, s, cases, mask_unstable, parity);
   return hipGetLastError();
 }
 

@@ -12,6 +12,9 @@ hipError_t launch_lbm(int prec, int variant, const void *A, void *B, const LbmPa
                       const IbParams &ib, hipStream_t s);
 hipError_t launch_ib(int prec, const void *A, const LbmParams &p, const IbParams &ib, hipStream_t s);
 hipError_t launch_rigid_move(const MoveParams &mp, hipStream_t s);
+hipError_t launch_conv_outlet(int prec, const void *A, void *B, const LbmParams &p, hipStream_t s);
+hipError_t launch_conv_outlet_batch(int prec, const CaseDesc *cases, int ncases, int mask_unstable, int parity,
+                                    hipStream_t s);
 hipError_t launch_marker_velocity(int prec, const void *A, const LbmParams &p, const IbParams &ib,
                                   const int *cover_off, const int *cover_list, double *out, hipStream_t s);
 hipError_t launch_lbm_batch(int prec, int variant, const CaseDesc *cases, const BatchMap &m, int parity,
