@@ -39,6 +39,8 @@ def parse():
     p.add_argument("--row-pad", type=int, default=0)
     p.add_argument("--interior", type=int, default=-1, help="1/0: uniform-base path for interior waves (-1: library default)")
     p.add_argument("--overlap", type=int, default=-1, help="1/0: marker kernel beside the lattice kernel (-1: library default)")
+    p.add_argument("--blocking", type=int, default=-1,
+                   help="1/0: two steps per pass away from the bodies (-1: library default)")
     p.add_argument("--plane-pad", type=int, default=0)
     p.add_argument("--row-align", type=int, default=-1, help="row alignment in bytes (-1: library default)")
     p.add_argument("--copy-probe-mb", type=int, default=0,
@@ -284,15 +286,18 @@ def main():
         sim.set_option(_lib.OPT_INTERIOR_PATH, args.interior)
     if args.overlap >= 0:
         sim.set_option(_lib.OPT_OVERLAP, args.overlap)
+    if args.blocking >= 0:
+        sim.set_option(_lib.OPT_TEMPORAL_BLOCKING, args.blocking)
     sim.step(args.warmup)
     torch.cuda.synchronize()
     if args.copy_probe_mb:
         copy_probe(args.copy_probe_mb)
     print("setup + warmup %.1f s" % (time.perf_counter() - t_setup), file=sys.stderr, flush=True)
 
+    fused_tiles = sim.get_option(_lib.OPT_FUSED_TILES)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ms_ib, ms_lbm = sim.step_timed(args.steps)
+    ms_ib, ms_single, ms_pair = sim.step_timed_split(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sim.forces()  # surfaces an instability as an error
@@ -301,18 +306,29 @@ def main():
     wall = t1 - t0
     ms_step = wall * 1e3 / args.steps
     mlups = n * args.steps / wall / 1e6
-    bytes_per_update = 9 * 2 * prec
-    achieved = n * bytes_per_update / (ms_lbm * 1e-3) / 1e9
+    node_bytes = 9 * 2 * prec  # one read and one write of the 9 populations
+    variant = sim.get_option(_lib.OPT_LBM_VARIANT)
+    if fused_tiles > 0:
+        # dominant kernel: the two-step pass, 2 updates per node per launch of node_bytes
+        tile_nodes = sim.get_option(_lib.OPT_TILE_X) * sim.get_option(_lib.OPT_TILE_Y)
+        launch_nodes = fused_tiles * tile_nodes
+        launch_ms = 2.0 * ms_pair
+        kernel, bytes_per_update = "lbm2_kernel", node_bytes / 2
+        key = "%s-%s-v%d-b1" % (args.workload, args.delta, variant)
+    else:
+        launch_nodes, launch_ms = n, ms_single
+        kernel, bytes_per_update = "lbm_kernel", node_bytes
+        key = "%s-%s-v%d-i%d-o%d" % (args.workload, args.delta, variant, sim.get_option(_lib.OPT_INTERIOR_PATH),
+                                     sim.get_option(_lib.OPT_OVERLAP))
+    achieved = launch_nodes * node_bytes / (launch_ms * 1e-3) / 1e9
     # measured HBM bytes per launch (profiles/traffic.json, counter runs of this
     # exact configuration) over the same live duration: GB/s like `achieved`
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
-        key = "%s-%s-v%d-i%d-o%d" % (args.workload, args.delta, sim.get_option(_lib.OPT_LBM_VARIANT),
-                                     sim.get_option(_lib.OPT_INTERIOR_PATH), sim.get_option(_lib.OPT_OVERLAP))
         if key in t:
-            traffic = round(t[key]["bytes_per_launch"] / (ms_lbm * 1e-3) / 1e9, 1)
+            traffic = round(t[key]["bytes_per_launch"] / (launch_ms * 1e-3) / 1e9, 1)
     nb, nm, _ = sim.counts()
     line = {
         "metric": "MLUPS (D2Q9+BTDF-IB)",
@@ -333,11 +349,17 @@ def main():
                    "row_pad": args.row_pad, "plane_pad": args.plane_pad,
                    "interior_path": sim.get_option(_lib.OPT_INTERIOR_PATH),
                    "overlap": sim.get_option(_lib.OPT_OVERLAP),
-                   "graph_chunk": args.graph_chunk},
-        "kernel_ms": {"ib_kernel": round(ms_ib, 5), "lbm_kernel": round(ms_lbm, 5)},
+                   "graph_chunk": args.graph_chunk,
+                   "temporal_blocking": sim.get_option(_lib.OPT_TEMPORAL_BLOCKING),
+                   "two_step_tiles": fused_tiles, "two_step_nodes_frac": round(launch_nodes / n, 4)
+                   if fused_tiles else 0.0},
+        "kernel_ms": {"ib_kernel": round(ms_ib, 5), "lbm_kernel": round(ms_single, 5),
+                      "lbm2_kernel": round(2.0 * ms_pair, 5)},
+        "kernel_ms_note": "ib_kernel and lbm_kernel: per step; lbm2_kernel: per launch (two steps)",
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "lbm_kernel", "bytes_per_update": bytes_per_update},
+                     "kernel": kernel, "bytes_per_update": bytes_per_update,
+                     "nodes_per_launch": launch_nodes, "launch_ms": round(launch_ms, 5)},
     }
     sim.close()
     del sim

@@ -25,6 +25,7 @@ OPT_MASK_UNSTABLE = 12
 OPT_ROW_ALIGN = 13
 OPT_FORCING_PASSES = 14
 OPT_FORCING_METHOD = 15
+OPT_TEMPORAL_BLOCKING, OPT_FUSED_TILES = 16, 17
 FORCING_DIRECT, FORCING_IMPLICIT, FORCING_RKPM = 0, 1, 2
 
 _NAMES = {OK: "BTDF_OK", EINVAL: "BTDF_EINVAL", ENOMEM: "BTDF_ENOMEM", EDEVICE: "BTDF_EDEVICE",
@@ -86,6 +87,7 @@ SIGNATURES = {
     "btdf_set_populations": (ctypes.c_int, [_vp, _dp]),
     "btdf_get_marker_data": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp, _dp]),
     "btdf_marker_velocity": (ctypes.c_int, [_vp, _dp, _dp]),
+    "btdf_step_timed_split": (ctypes.c_int, [_vp, _i64, _dp]),
     "btdf_set_body_motion": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "btdf_get_body_state": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "btdf_get_marker_positions": (ctypes.c_int, [_vp, _dp]),

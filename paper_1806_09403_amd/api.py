@@ -122,6 +122,12 @@ def btdf_get_marker_data(h):
     return dict(zip(["rho", "ux", "uy", "Fx", "Fy"], [a[:nm] for a in arrs]))
 
 
+def btdf_step_timed_split(h, n):
+    out = np.empty(3)
+    check(load().btdf_step_timed_split(h, int(n), dptr(out)))
+    return tuple(float(v) for v in out)
+
+
 def btdf_set_body_motion(h, body, vx, vy, omega):
     return check(load().btdf_set_body_motion(h, int(body), float(vx), float(vy), float(omega)))
 

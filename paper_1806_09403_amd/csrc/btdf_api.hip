@@ -164,6 +164,66 @@ void cover_lists(const btdf_t *h, std::vector<int> &off, std::vector<int> &list)
   if (list.empty()) list.push_back(0);
 }
 
+// Tiles for temporal blocking on the current launch shape: a tile is "near"
+// if a marker stencil grown by one node reaches it or if it lies within two
+// nodes of a domain edge. Near tiles step singly; so do, for their first
+// step only, the ring nodes just outside them (whose intermediate state the
+// near tiles' second step pulls).
+void fused_lists(btdf_t *h) {
+  h->fmap.clear();
+  h->n_quad = h->n_wide = h->n_fused = h->n_near = 0;
+  h->near.clear();
+  if (!h->tblock) return;
+  const int tx = h->tile_x, ty = h->tile_y, ntx = h->ntx, nty = h->nty, ntiles = ntx * nty;
+  std::vector<char> near(ntiles, 0);
+  for (int t = 0; t < ntiles; ++t) {
+    const int x0 = (t % ntx) * tx, y0 = (t / ntx) * ty;
+    if (x0 < 2 || x0 + tx + 2 > h->nx || y0 < 2 || y0 + ty + 2 > h->ny) near[t] = 1;
+  }
+  for (int l = 0; l < h->nm(); ++l) {
+    int xlo, xhi, ylo, yhi;
+    marker_range(h->kind, h->X[l], &xlo, &xhi);
+    marker_range(h->kind, h->Y[l], &ylo, &yhi);
+    xlo -= 1 + h->margin;
+    xhi += 1 + h->margin;
+    ylo -= 1 + h->margin;
+    yhi += 1 + h->margin;
+    for (int j = ylo; j <= yhi; ++j) {
+      const int jj = h->yper() ? ((j % h->ny) + h->ny) % h->ny : j;
+      if (jj < 0 || jj >= h->ny) continue;
+      for (int i = xlo; i <= xhi; ++i) {
+        const int ii = h->xper() ? ((i % h->nx) + h->nx) % h->nx : i;
+        if (ii < 0 || ii >= h->nx) continue;
+        near[(jj / ty) * ntx + ii / tx] = 1;
+      }
+    }
+  }
+  // two-step tiles: pairs of side-by-side lattice tiles where the launch
+  // shape has a wide pass (first tile of each pair listed), then the rest
+  std::vector<char> grouped(ntiles, 0);
+  for (int w : {4, 2}) {
+    const size_t start = h->fmap.size();
+    if (variant_has_wide_lbm2(h->variant, h->prec, w))
+      for (int b = 0; b < nty; ++b)
+        for (int a = 0; a + w - 1 < ntx; a += w) {
+          const int t = b * ntx + a;
+          bool ok = true;
+          for (int k = 0; k < w; ++k) ok = ok && !near[t + k] && !grouped[t + k];
+          if (!ok) continue;
+          h->fmap.push_back(t);
+          for (int k = 0; k < w; ++k) grouped[t + k] = 1;
+        }
+    (w == 4 ? h->n_quad : h->n_wide) = (int)(h->fmap.size() - start);
+  }
+  for (int t = 0; t < ntiles; ++t)
+    if (!near[t] && !grouped[t]) h->fmap.push_back(t);
+  h->n_fused = (int)h->fmap.size() - h->n_quad - h->n_wide;
+  for (int t = 0; t < ntiles; ++t)
+    if (near[t]) h->fmap.push_back(t);
+  h->n_near = (int)h->fmap.size() - h->n_quad - h->n_wide - h->n_fused;
+  h->near.assign(near.begin(), near.end());
+}
+
 // the most tiles one marker's (margin-widened) stencil can touch, over every launch shape
 int tiles_per_marker(const btdf_t *h) {
   const int L = stencil_size(h->kind) + 2 * h->margin;
@@ -315,6 +375,17 @@ void compute_layout(btdf_t *h) {
   o = align256(o + h->minv_off.size() * sizeof(long long));
   h->off_minv = o;
   o = align256(o + h->minv.size() * sizeof(double));
+  // temporal blocking: the tiles that take two steps at once, then the tiles
+  // stepped singly (those next to the bodies and the edges, grown by their
+  // neighbours), then those next to the bodies and the edges; and a third
+  // population buffer for the singly stepped tiles' intermediate state
+  fused_lists(h);
+  h->off_fmap = o;
+  o = align256(o + 2 * (size_t)max_tiles * sizeof(int));
+  h->off_near = o;  // one flag per tile
+  o = align256(o + (size_t)max_tiles);
+  h->off_pop3 = o;
+  o = align256(o + (h->tblock ? pop_bytes : 0));
   // rigid motion: [nb][4] theta vx vy omega, then [nb] moving flags; [nm][2] offsets
   h->off_motion = o;
   o = align256(o + 4 * (size_t)std::max(nb, 1) * sizeof(double) + (size_t)std::max(nb, 1) * sizeof(int));
@@ -456,6 +527,8 @@ int upload_bodies(btdf_t *h) {
       r[2 * l + 1] = h->ry[l];
     }
   }
+  put(h->off_fmap, h->fmap.data(), h->fmap.size() * sizeof(int));
+  put(h->off_near, h->near.data(), h->near.size());
   put(h->off_moff, h->minv_off.data(), h->minv_off.size() * sizeof(long long));
   put(h->off_minv, h->minv.data(), h->minv.size() * sizeof(double));
   put(h->off_coff, h->cover_off.data(), h->cover_off.size() * sizeof(int));
@@ -911,6 +984,9 @@ int btdf_set_marker_velocity(btdf_t *h, int body, const double *uv) {
   return ok();
 }
 
+static int enqueue_pair(btdf_t *h, const LbmParams &p, const IbParams &ib, hipStream_t s, hipEvent_t *ev);
+static bool blocking_active(const btdf_t *h);
+
 // n steps from the current buffer: graphs of graph_chunk steps where they fit
 static int run_steps(btdf_t *h, const LbmParams &p, const IbParams &ib, int64_t n) {
   int rc;
@@ -995,7 +1071,11 @@ int btdf_step(btdf_t *h, int64_t n) {
   if (rc) return rc;
   const LbmParams p = make_params(h);
   const IbParams ib = make_ib(h);
-  if (!h->any_moving()) {
+  if (blocking_active(h) && n >= 2) {
+    for (int64_t k = 0; k < n / 2; ++k)
+      if ((rc = enqueue_pair(h, p, ib, h->stream, nullptr))) return rc;
+    if ((n & 1) && (rc = run_steps(h, p, ib, 1))) return rc;
+  } else if (!h->any_moving()) {
     if ((rc = run_steps(h, p, ib, n))) return rc;
   } else {
     for (int64_t left = n; left > 0;) {
@@ -1011,8 +1091,77 @@ int btdf_step(btdf_t *h, int64_t n) {
   return ok();
 }
 
-int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm) {
-  if (!h || !ms_ib || !ms_lbm) return fail(BTDF_EINVAL, "NULL argument");
+// two steps from buffer cur into 1 - cur (temporal blocking): the tiles near
+// the bodies or the domain edges step twice by way of the third buffer X
+// (their first step also covers the ring of nodes just outside them), with
+// the marker kernel between; every other tile takes both steps at once
+// (lbm2_kernel), on the side stream beside that chain when the overlap
+// option is set (the two write disjoint tiles of the destination and read
+// only the source and X). ev: 7 events (before/after the first marker
+// kernel, after the near tiles' first step, after the second marker kernel,
+// after their second step, before/after the two-step kernel) or null.
+static hipError_t launch_two_step(const btdf_t *h, const void *A, void *B, const LbmParams &p, const int *fm,
+                                  hipStream_t s) {
+  hipError_t e = launch_lbm2(h->prec, h->variant, 4, A, B, p, fm, h->n_quad, s);
+  if (e == hipSuccess) e = launch_lbm2(h->prec, h->variant, 2, A, B, p, fm + h->n_quad, h->n_wide, s);
+  if (e == hipSuccess)
+    e = launch_lbm2(h->prec, h->variant, 1, A, B, p, fm + h->n_quad + h->n_wide, h->n_fused, s);
+  return e;
+}
+
+static int enqueue_pair(btdf_t *h, const LbmParams &p, const IbParams &ib, hipStream_t s, hipEvent_t *ev) {
+  const void *A = h->ws + h->off_pop[h->cur];
+  void *B = h->ws + h->off_pop[1 - h->cur];
+  void *X = h->ws + h->off_pop3;
+  const int *fm = h->at<int>(h->off_fmap);
+  const bool ov = h->overlap != 0;
+  hipStream_t s2 = s;
+  if (ov) {
+    int rc = make_side(h);
+    if (rc) return rc;
+    s2 = h->side;
+    HIPCHK(hipEventRecord(h->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(s2, h->ev_fork, 0));
+    if (ev) HIPCHK(hipEventRecord(ev[5], s2));
+    HIPCHK(launch_two_step(h, A, B, p, fm, s2));
+    if (ev) HIPCHK(hipEventRecord(ev[6], s2));
+    HIPCHK(hipEventRecord(h->ev_join, s2));
+  }
+  if (ev) HIPCHK(hipEventRecord(ev[0], s));
+  HIPCHK(launch_ib(h->prec, A, p, ib, s));
+  if (ev) HIPCHK(hipEventRecord(ev[1], s));
+  const int nb0 = h->n_quad + h->n_wide + h->n_fused;  // the near tiles start here in the map
+  HIPCHK(launch_lbm(h->prec, h->variant, A, X, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
+  HIPCHK(launch_ring(h->prec, A, X, p, fm + nb0, h->n_near, h->at<unsigned char>(h->off_near), h->tile_x,
+                     h->tile_y, s));
+  if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, A, X, p, s));
+  if (ev) HIPCHK(hipEventRecord(ev[2], s));
+  HIPCHK(launch_ib(h->prec, X, p, ib, s));
+  if (ev) HIPCHK(hipEventRecord(ev[3], s));
+  HIPCHK(launch_lbm(h->prec, h->variant, X, B, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
+  if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, X, B, p, s));
+  if (ev) HIPCHK(hipEventRecord(ev[4], s));
+  if (ov) {
+    HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
+  } else {
+    if (ev) HIPCHK(hipEventRecord(ev[5], s));
+    HIPCHK(launch_two_step(h, A, B, p, fm, s));
+    if (ev) HIPCHK(hipEventRecord(ev[6], s));
+  }
+  h->cur ^= 1;
+  h->steps += 2;
+  return ok();
+}
+
+static bool blocking_active(const btdf_t *h) {
+  return h->tblock && h->graph_chunk == 0 && h->layout_ok && h->n_quad + h->n_wide + h->n_fused > 0 &&
+         !h->any_moving() &&
+         variant_has_lbm2(h->variant, h->prec);
+}
+
+// per-step means over n timed steps: out[0] marker kernels, out[1] single-step
+// lattice kernels, out[2] the two-step kernel (per step, i.e. half a launch)
+static int timed_impl(btdf_t *h, int64_t n, double *out) {
   if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; step the batch");
   if (n <= 0) return fail(BTDF_EINVAL, "step count must be > 0");
   int rc = ensure_device(h);
@@ -1020,18 +1169,23 @@ int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm) {
   const LbmParams p = make_params(h);
   const IbParams ib = make_ib(h);
   const int chunk = 256;
-  std::vector<hipEvent_t> ev(6 * chunk, nullptr);
+  std::vector<hipEvent_t> ev(7 * chunk, nullptr);
   for (auto &e : ev) HIPCHK(hipEventCreate(&e));
   const bool ov = overlapping(h);
-  double tib = 0.0, tlbm = 0.0;
+  double tib = 0.0, tlbm = 0.0, tpair = 0.0;
   int64_t done = 0;
   rc = ok();
   while (done < n && rc == 0) {
-    const int m = (int)std::min<int64_t>(chunk, n - done);
+    const bool pairs = blocking_active(h) && n - done >= 2;
+    const int m = pairs ? (int)std::min<int64_t>(chunk, (n - done) / 2) : (int)std::min<int64_t>(chunk, n - done);
     const bool moving = h->any_moving();
     for (int k = 0; k < m && rc == 0; ++k) {
+      if (pairs) {
+        rc = enqueue_pair(h, p, ib, h->stream, &ev[7 * k]);
+        continue;
+      }
       if (moving && h->steps_to_rebin <= 0 && (rc = rebin(h))) break;
-      const StepEvents te{ev[6 * k], ev[6 * k + 1], ev[6 * k + 2], ev[6 * k + 3], ev[6 * k + 4], ev[6 * k + 5]};
+      const StepEvents te{ev[7 * k], ev[7 * k + 1], ev[7 * k + 2], ev[7 * k + 3], ev[7 * k + 4], ev[7 * k + 5]};
       rc = enqueue_step(h, p, ib, h->cur, h->stream, &te);
       h->cur ^= 1;
       h->steps++;
@@ -1047,26 +1201,54 @@ int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm) {
       break;
     }
     for (int k = 0; k < m; ++k) {
-      float a = 0.f, b = 0.f, c = 0.f;
-      (void)hipEventElapsedTime(&a, ev[6 * k], ev[6 * k + 1]);
+      float a = 0.f, b = 0.f, c = 0.f, d = 0.f, f = 0.f;
+      hipEvent_t *E = &ev[7 * k];
+      if (pairs) {
+        (void)hipEventElapsedTime(&a, E[0], E[1]);
+        (void)hipEventElapsedTime(&b, E[1], E[2]);
+        (void)hipEventElapsedTime(&c, E[2], E[3]);
+        (void)hipEventElapsedTime(&d, E[3], E[4]);
+        (void)hipEventElapsedTime(&f, E[5], E[6]);
+        tib += a + c;
+        tlbm += b + d;
+        tpair += f;
+        continue;
+      }
+      (void)hipEventElapsedTime(&a, E[0], E[1]);
       if (ov) {
-        (void)hipEventElapsedTime(&b, ev[6 * k + 2], ev[6 * k + 3]);
-        (void)hipEventElapsedTime(&c, ev[6 * k + 4], ev[6 * k + 5]);
+        (void)hipEventElapsedTime(&b, E[2], E[3]);
+        (void)hipEventElapsedTime(&c, E[4], E[5]);
       } else {
-        (void)hipEventElapsedTime(&b, ev[6 * k + 1], ev[6 * k + 3]);
+        (void)hipEventElapsedTime(&b, E[1], E[3]);
       }
       tib += a;
       tlbm += b + c;
     }
-    done += m;
+    done += pairs ? 2 * (int64_t)m : m;
   }
   for (auto &e : ev)
     if (e) (void)hipEventDestroy(e);
   if (rc) return rc;
   h->stepped = true;
-  *ms_ib = h->nb() ? tib / (double)n : 0.0;
-  *ms_lbm = tlbm / (double)n;
+  out[0] = h->nb() ? tib / (double)n : 0.0;
+  out[1] = tlbm / (double)n;
+  out[2] = tpair / (double)n;
   return ok();
+}
+
+int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm) {
+  if (!h || !ms_ib || !ms_lbm) return fail(BTDF_EINVAL, "NULL argument");
+  double out[3];
+  int rc = timed_impl(h, n, out);
+  if (rc) return rc;
+  *ms_ib = out[0];
+  *ms_lbm = out[1] + out[2];
+  return ok();
+}
+
+int btdf_step_timed_split(btdf_t *h, int64_t n, double *ms) {
+  if (!h || !ms) return fail(BTDF_EINVAL, "NULL argument");
+  return timed_impl(h, n, ms);
 }
 
 int btdf_autotune(btdf_t *h, int64_t steps_per_trial, int *best_variant) {
@@ -1388,6 +1570,15 @@ int btdf_set_option(btdf_t *h, int key, int64_t value) {
       h->row_align = (int)value;
       h->layout_ok = false;
       return ok();
+    case BTDF_OPT_TEMPORAL_BLOCKING:
+      if (value != 0 && value != 1) return fail(BTDF_EINVAL, "temporal blocking flag must be 0 or 1");
+      if (value != h->tblock) {
+        h->tblock = (int)value;
+        h->layout_ok = false;  // the tile lists and the third buffer
+        h->device_ok = false;
+        drop_graph(h);
+      }
+      return ok();
     case BTDF_OPT_FORCING_METHOD:
       if (value != BTDF_FORCING_DIRECT && value != BTDF_FORCING_IMPLICIT && value != BTDF_FORCING_RKPM)
         return fail(BTDF_EINVAL, "unknown forcing method %lld", (long long)value);
@@ -1440,6 +1631,11 @@ int btdf_get_option(const btdf_t *h, int key, int64_t *value) {
     case BTDF_OPT_ROW_ALIGN: *value = h->row_align; return ok();
     case BTDF_OPT_FORCING_PASSES: *value = h->nf; return ok();
     case BTDF_OPT_FORCING_METHOD: *value = h->method; return ok();
+    case BTDF_OPT_TEMPORAL_BLOCKING: *value = h->tblock; return ok();
+    case BTDF_OPT_FUSED_TILES:
+      if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
+      *value = blocking_active(h) ? 4 * h->n_quad + 2 * h->n_wide + h->n_fused : 0;  // in lattice tiles
+      return ok();
     default: return fail(BTDF_EINVAL, "unknown option %d", key);
   }
 }

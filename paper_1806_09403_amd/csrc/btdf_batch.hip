@@ -295,6 +295,7 @@ int btdf_batch_create(int n_cases, const btdf_grid *grids, const double *taus, c
       return fail(rc, "%s", msg.c_str());
     }
     h->owner = b;
+    h->tblock = 0;  // the batch steps its cases itself, one step at a time
     h->stream = (hipStream_t)grids[0].hip_stream;
     b->cases.push_back(h);
   }

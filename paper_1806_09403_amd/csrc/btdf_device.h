@@ -230,28 +230,39 @@ __device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
 //   odd  = 3 w (omega (drho eu + ea) + guo ef)
 //   C    = omega (drho (1 - 1.5 |u|^2) - 1.5 du.(u + u_ref)) - 3 guo u.f
 // (with u_ref = 0 this is omega feq~ + F of the plain deviations f - w).
+// fused multiply-add, spelled out: a * b + c rounded once
+__device__ __forceinline__ float fmx(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmx(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T>
 __device__ __forceinline__ void collide(const T g[9], T ftx, T fty, T omega, T guo, T urx, T ury, T out[9],
                                         T &rho) {
+  // Every multiply-add is written out and nothing else is fused, so the same
+  // inputs give the same bits whichever kernel the collision is inlined into
+  // (left to itself the compiler fuses differently once it hoists common
+  // terms, as in the two-step kernel).
+#pragma clang fp contract(off)
   T drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
   rho = (T)1 + drho;
   const T mx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);  // m - u_ref
   const T my = (g[2] - g[4]) + (g[5] - g[8]) + (g[6] - g[7]);
   const T inv = recip<T>(rho);
-  const T dux = (mx + (T)0.5 * ftx - drho * urx) * inv;
-  const T duy = (my + (T)0.5 * fty - drho * ury) * inv;
+  const T dux = fmx(-drho, urx, fmx((T)0.5, ftx, mx)) * inv;
+  const T duy = fmx(-drho, ury, fmx((T)0.5, fty, my)) * inv;
   const T ux = urx + dux, uy = ury + duy;
   const T sx = ux + urx, sy = uy + ury;
-  const T C = omega * (drho * ((T)1 - (T)1.5 * (ux * ux + uy * uy)) - (T)1.5 * (dux * sx + duy * sy)) -
-              (T)3 * guo * (ux * ftx + uy * fty);
+  const T a = fmx((T)-1.5, fmx(ux, ux, uy * uy), (T)1);
+  const T c1 = fmx(drho, a, (T)-1.5 * fmx(dux, sx, duy * sy));
+  const T C = fmx(omega, c1, -((T)3 * guo) * fmx(ux, ftx, uy * fty));
   const T K1 = (T)4.5 * omega, K2 = (T)9 * guo;
   const T omc = (T)1 - omega;
-  out[0] = omc * g[0] + (T)(4.0 / 9.0) * C;
+  out[0] = fmx(omc, g[0], (T)(4.0 / 9.0) * C);
   auto pair = [&](int qp, int qm, T eu, T ea, T eb, T ef, T w) {
-    const T even = w * (C + K1 * (drho * eu * eu + ea * eb) + K2 * eu * ef);
-    const T odd = (T)3 * w * (omega * (drho * eu + ea) + guo * ef);
-    out[qp] = omc * g[qp] + even + odd;
-    out[qm] = omc * g[qm] + even - odd;
+    const T de = drho * eu;
+    const T even = w * fmx(K2 * eu, ef, fmx(K1, fmx(de, eu, ea * eb), C));
+    const T odd = ((T)3 * w) * fmx(omega, de + ea, guo * ef);
+    out[qp] = fmx(omc, g[qp], even) + odd;
+    out[qm] = fmx(omc, g[qm], even) - odd;
   };
   pair(1, 3, ux, dux, sx, ftx, (T)(1.0 / 9.0));
   pair(2, 4, uy, duy, sy, fty, (T)(1.0 / 9.0));

@@ -599,6 +599,217 @@ hipError_t launch_lbm(int prec, int v, const void *A, void *B, const LbmParams &
   return launch_lbm_any<double>(v, (const double *)A, (double *)B, p, r, ib, s);
 }
 
+// ---- two steps in one pass (temporal blocking) for tiles away from every marker
+//
+// A tile whose nodes and their neighbours carry no immersed-boundary force
+// advances two steps at once: the workgroup streams and collides step n on
+// the tile grown by one node (pulls from A, state n), keeps that state in
+// LDS, and streams and collides step n+1 for the tile's own nodes from LDS,
+// writing state n+2 to C. Each node is read and written once for two
+// updates instead of twice. Only the uniform body force acts there (the
+// spread force is zero on and next to such tiles), so both collisions are
+// the single-step kernel's, value for value. The host hands over only tiles
+// at least two nodes from every domain edge, so no pull wraps or meets a
+// wall or a ghost column's update.
+// OX x OY output tile worked by BX x BY threads (each thread takes the
+// output nodes ii = threadIdx.x + k BX, jj = threadIdx.y + m BY); the map
+// holds the id of the tile's first lattice tile (tile_x x tile_y grid).
+template <typename T, int OX, int OY, int BX, int BY, bool NT>
+__global__ __launch_bounds__(BX *BY) void lbm2_kernel(const T *__restrict__ A, T *__restrict__ C, LbmParams p,
+                                                     const int *__restrict__ map, int count, int tile_x,
+                                                     int tile_y) {
+  constexpr int RX = OX + 2, RY = OY + 2;  // the grown tile
+  __shared__ T s_f[9][RY][RX];
+  const int li = p.xcd_remap ? xcd_tile((int)blockIdx.x, count) : (int)blockIdx.x;
+  const int t = map[li];
+  const int tyi = t / p.ntx;
+  const int txi = t - tyi * p.ntx;
+  const int x0 = txi * tile_x, y0 = tyi * tile_y;
+  const int tid = (int)threadIdx.y * BX + (int)threadIdx.x;
+  const T omega = (T)p.omega, guo = (T)p.guo;
+  const T Gx = (T)p.Gx, Gy = (T)p.Gy;
+  const T urx = (T)p.urx, ury = (T)p.ury;
+  bool bad = false;
+  // step n on the grown tile: first the OX columns of every grown row, so
+  // that consecutive lanes take consecutive, line-aligned nodes of a row,
+  // then the two edge columns; two nodes per round, both nodes' loads issued
+  // before either collision, so more loads are in flight
+  constexpr int TOT = RY * OX + 2 * RY, NTH = BX * BY;
+  auto node_of = [&](int k, int &i, int &j) {
+    if (k < RY * OX) {
+      j = k / OX;
+      i = 1 + (k - j * OX);
+    } else {
+      j = (k - RY * OX) >> 1;
+      i = (k & 1) ? OX + 1 : 0;
+    }
+  };
+  for (int k = tid; k < TOT; k += 2 * NTH) {
+    int ia, ja, ib, jb;
+    node_of(k, ia, ja);
+    const bool two = k + NTH < TOT;
+    node_of(two ? k + NTH : k, ib, jb);
+    const int xa = x0 - 1 + ia, ya = y0 - 1 + ja, xb = x0 - 1 + ib, yb = y0 - 1 + jb;
+    T ga[9], gb[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      ga[q] = A[(long long)q * p.plane + (long long)(ya - ey(q)) * p.pitch + (xa - ex(q))];
+      gb[q] = A[(long long)q * p.plane + (long long)(yb - ey(q)) * p.pitch + (xb - ex(q))];
+    }
+    T out[9], rho;
+    collide<T>(ga, Gx, Gy, omega, guo, urx, ury, out, rho);
+    bad |= !(rho > (T)0) || !isfinite(rho);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s_f[q][ja][ia] = out[q];
+    if (two) {
+      collide<T>(gb, Gx, Gy, omega, guo, urx, ury, out, rho);
+      bad |= !(rho > (T)0) || !isfinite(rho);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) s_f[q][jb][ib] = out[q];
+    }
+  }
+  __syncthreads();
+  // step n+1 on the tile's own nodes, pulling from the LDS copy of state n+1
+#pragma unroll
+  for (int jj = (int)threadIdx.y; jj < OY; jj += BY) {
+#pragma unroll
+    for (int ii = (int)threadIdx.x; ii < OX; ii += BX) {
+      const int i = ii + 1, j = jj + 1;
+      T g[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) g[q] = s_f[q][j - ey(q)][i - ex(q)];
+      T out[9], rho;
+      collide<T>(g, Gx, Gy, omega, guo, urx, ury, out, rho);
+      bad |= !(rho > (T)0) || !isfinite(rho);
+      const long long base = (long long)(y0 + jj) * p.pitch + x0 + ii;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) store<T, NT>(&C[(long long)q * p.plane + base], out[q]);
+    }
+  }
+  if (bad) p.flag[0] = -1;
+}
+
+template <typename T, int OX, int OY, int BX, int BY, bool NT>
+static hipError_t launch_lbm2_t(const T *A, T *C, const LbmParams &p, const int *map, int count, int tx, int ty,
+                                hipStream_t s) {
+  if constexpr (9 * (OX + 2) * (OY + 2) * sizeof(T) <= 65536) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL((lbm2_kernel<T, OX, OY, BX, BY, NT>), dim3(count), dim3(BX, BY), 0, s, A, C, p, map, count,
+                       tx, ty);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+static hipError_t launch_lbm2_any(int v, int width, const T *A, T *C, const LbmParams &p, const int *map, int count,
+                                  hipStream_t s) {
+  int tx, ty;
+  variant_tile(v, &tx, &ty);
+  // width lattice tiles side by side, one thread per output node
+  if (width == 4) {
+    if (tx == 32 && ty == 8) return launch_lbm2_t<T, 128, 8, 128, 8, true>(A, C, p, map, count, tx, ty, s);
+    if (tx == 32 && ty == 4) return launch_lbm2_t<T, 128, 4, 128, 4, true>(A, C, p, map, count, tx, ty, s);
+    return hipErrorInvalidValue;
+  }
+  if (width == 2) {
+    if (tx == 32 && ty == 8) return launch_lbm2_t<T, 64, 8, 64, 8, true>(A, C, p, map, count, tx, ty, s);
+    if (tx == 32 && ty == 4) return launch_lbm2_t<T, 64, 4, 64, 4, true>(A, C, p, map, count, tx, ty, s);
+    if (tx == 64 && ty == 4) return launch_lbm2_t<T, 128, 4, 128, 4, true>(A, C, p, map, count, tx, ty, s);
+    return hipErrorInvalidValue;
+  }
+#define X(id, bx, by, npt, nt, ntl)                                                                   \
+  if (v == id)                                                                                      \
+    return npt == 1 && width == 1 ? launch_lbm2_t<T, bx, by, bx, by, nt>(A, C, p, map, count, tx, ty, s)    \
+                                  : hipErrorInvalidValue;
+  BTDF_VARIANTS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_lbm2(int prec, int v, int width, const void *A, void *C, const LbmParams &p, const int *map,
+                       int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (prec == 4) return launch_lbm2_any<float>(v, width, (const float *)A, (float *)C, p, map, count, s);
+  return launch_lbm2_any<double>(v, width, (const double *)A, (double *)C, p, map, count, s);
+}
+
+// whether a launch shape's two-step pass can also take width (2 or 4) of its tiles side by side
+bool variant_has_wide_lbm2(int v, int prec, int width) {
+  int tx, ty;
+  variant_tile(v, &tx, &ty);
+  bool shape = false;
+  if (width == 2) shape = (tx == 32 && (ty == 8 || ty == 4)) || (tx == 64 && ty == 4);
+  if (width == 4) shape = tx == 32 && (ty == 8 || ty == 4);
+  return shape && 9 * (width * tx + 2) * (ty + 2) * prec <= 65536;
+}
+
+// The first step of the ring of every near tile: the nodes one step outside
+// the tile that lie in a two-step tile (plain interior nodes, no
+// immersed-boundary force; a node next to two near tiles is written twice
+// with the same value). One workgroup per near tile, so the ring is read
+// from the lines the tile's own step has just brought into L2.
+template <typename T>
+__global__ __launch_bounds__(128) void ring_kernel(const T *__restrict__ A, T *__restrict__ X, LbmParams p,
+                                                   const int *__restrict__ near_map, const unsigned char *__restrict__ near,
+                                                   int tile_x, int tile_y) {
+  const int t = near_map[blockIdx.x];
+  const int tyi = t / p.ntx, txi = t - tyi * p.ntx;
+  const int x0 = txi * tile_x, y0 = tyi * tile_y;
+  const int per = 2 * (tile_x + 2) + 2 * tile_y;  // ring positions: two rows, two columns
+  for (int k = (int)threadIdx.x; k < per; k += 128) {
+    int x, y;
+    if (k < tile_x + 2) {
+      x = x0 - 1 + k;
+      y = y0 - 1;
+    } else if (k < 2 * (tile_x + 2)) {
+      x = x0 - 1 + (k - (tile_x + 2));
+      y = y0 + tile_y;
+    } else {
+      const int r = k - 2 * (tile_x + 2);
+      x = (r & 1) ? x0 + tile_x : x0 - 1;
+      y = y0 + (r >> 1);
+    }
+    if (p.xper) x = x < 0 ? x + p.nx : (x >= p.nx ? x - p.nx : x);
+    if (p.yper) y = y < 0 ? y + p.ny : (y >= p.ny ? y - p.ny : y);
+    if (x < 0 || x >= p.nx || y < 0 || y >= p.ny) continue;
+    if (near[(y / tile_y) * p.ntx + x / tile_x]) continue;  // a near tile steps its own nodes
+    T g[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) g[q] = A[(long long)q * p.plane + (long long)(y - ey(q)) * p.pitch + (x - ex(q))];
+    T out[9], rho;
+    collide<T>(g, (T)p.Gx, (T)p.Gy, (T)p.omega, (T)p.guo, (T)p.urx, (T)p.ury, out, rho);
+    const long long base = (long long)y * p.pitch + x;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) X[(long long)q * p.plane + base] = out[q];
+    if (!(rho > (T)0) || !isfinite(rho)) p.flag[0] = -1;
+  }
+}
+
+hipError_t launch_ring(int prec, const void *A, void *X, const LbmParams &p, const int *near_map, int n_near,
+                       const unsigned char *near, int tile_x, int tile_y, hipStream_t s) {
+  if (n_near <= 0) return hipSuccess;
+  if (prec == 4)
+    hipLaunchKernelGGL(ring_kernel<float>, dim3(n_near), dim3(128), 0, s, (const float *)A, (float *)X, p, near_map,
+                       near, tile_x, tile_y);
+  else
+    hipLaunchKernelGGL(ring_kernel<double>, dim3(n_near), dim3(128), 0, s, (const double *)A, (double *)X, p,
+                       near_map, near, tile_x, tile_y);
+  return hipGetLastError();
+}
+
+// whether a launch shape has a two-step kernel (one node per thread, LDS within 64 KB)
+bool variant_has_lbm2(int v, int prec) {
+  int tx, ty;
+  variant_tile(v, &tx, &ty);
+#define X(id, bx, by, npt, nt, ntl) \
+  if (v == id) return npt == 1 && 9 * (bx + 2) * (by + 2) * prec <= 65536;
+  BTDF_VARIANTS(X)
+#undef X
+  return false;
+}
+
 template <typename T>
 static hipError_t launch_lbm_batch_any(int v, const CaseDesc *cases, const BatchMap &m, int parity, hipStream_t s) {
 #define X(id, bx, by, npt, nt, ntl)                                                                          \

@@ -98,6 +98,10 @@ class Sim:
     def marker_data(self):
         return api.btdf_get_marker_data(self._workspace())
 
+    def step_timed_split(self, n):
+        """Per-step ms of (marker kernels, single-step lattice kernels, two-step lattice kernel)."""
+        return api.btdf_step_timed_split(self._workspace(), n)
+
     @property
     def steps(self):
         """Steps taken so far."""

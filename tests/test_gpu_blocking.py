@@ -1,0 +1,102 @@
+"""Temporal blocking (two steps per pass for tiles away from the markers
+and the domain edges) gives bit-identical results to single steps, for every
+boundary set, forcing method, precision and launch shape that has the
+two-step kernel."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import btdf_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def run(c, blocking, steps, precision=4, options=None, timed=False):
+    from paper_1806_09403_amd import Sim, _lib
+    s = Sim.from_case(c, precision=precision)
+    for k, v in (options or {}).items():
+        s.set_option(k, v)
+    s.set_option(_lib.OPT_TEMPORAL_BLOCKING, blocking)
+    fused = s.get_option(_lib.OPT_FUSED_TILES)
+    for n in steps:
+        if timed:
+            s.step_timed_split(n)
+        else:
+            s.step(n)
+    out = (s.populations(), s.force_history(200), fused)
+    s.close()
+    return out
+
+
+def bodies_case(seed, nx, ny, bc, kind=W.COS4, n=6):
+    c = W.random_case(seed, nx=nx, ny=ny, kind=kind, bc=bc, n_bodies=n, D_range=(6.0, 12.0))
+    return c
+
+
+CASES = [
+    ("periodic", 41, 512, 256, W.FULLY_PERIODIC),
+    ("channel", 42, 400, 200, W.CHANNEL),
+    ("walls", 43, 300, 160, (W.PERIODIC, W.PERIODIC, W.BOUNCEBACK_WALL, W.BOUNCEBACK_WALL)),
+    ("far-field", 44, 420, 180, W.FAR_FIELD),
+]
+
+
+@pytest.mark.parametrize("precision", [4, 8])
+@pytest.mark.parametrize("name,seed,nx,ny,bc", CASES)
+def test_blocked_steps_are_bit_identical(name, seed, nx, ny, bc, precision):
+    log("blocking %s prec=%d" % (name, precision))
+    c = bodies_case(seed, nx, ny, bc)
+    steps = (1, 2, 7, 20)
+    ref = run(c, 0, steps, precision)
+    got = run(c, 1, steps, precision)
+    assert got[2] > 0 and ref[2] == 0
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+@pytest.mark.parametrize("opts", ["passes", "implicit", "rkpm", "timed"])
+def test_blocking_with_other_features(opts):
+    from paper_1806_09403_amd import _lib
+    c = bodies_case(45, 384, 192, W.CHANNEL, kind=W.ROMA3)
+    o = {"passes": {_lib.OPT_FORCING_PASSES: 3}, "implicit": {_lib.OPT_FORCING_METHOD: 1},
+         "rkpm": {_lib.OPT_FORCING_METHOD: 2}, "timed": {}}[opts]
+    timed = opts == "timed"
+    ref = run(c, 0, (3, 10), 4, o, timed=timed)
+    got = run(c, 1, (3, 10), 4, o, timed=timed)
+    assert got[2] > 0
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+def test_every_launch_shape_with_the_two_step_kernel():
+    from paper_1806_09403_amd import Sim, _lib
+    c = bodies_case(46, 520, 260, W.FULLY_PERIODIC)
+    ref = run(c, 0, (9,))
+    s = Sim.from_case(c, precision=4)
+    nv = s.get_option(_lib.OPT_NUM_VARIANTS)
+    s.close()
+    active = 0
+    for v in range(nv):
+        got = run(c, 1, (9,), options={_lib.OPT_LBM_VARIANT: v})
+        active += got[2] > 0
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), v
+    assert active >= 10
+
+
+def test_moving_bodies_step_singly_under_blocking():
+    from paper_1806_09403_amd import Sim, _lib
+    outs = []
+    for blocking in (0, 1):
+        s = Sim(256, 128, 0.8, W.ROMA3, 1.9, W.FULLY_PERIODIC, init=(1.0, 0.02, 0.0), precision=4)
+        b = W.cylinder_body(100.3, 60.2, 12.0, 38)
+        s.add_body(b.xy, None, b.cx, b.cy, b.ds)
+        s.set_option(_lib.OPT_TEMPORAL_BLOCKING, blocking)
+        s.set_body_motion(0, 0.03, 0.0, 0.001)
+        assert s.get_option(_lib.OPT_FUSED_TILES) == 0
+        s.step(50)
+        outs.append(s.populations())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
