@@ -431,6 +431,7 @@ LbmParams make_params(const btdf_t *h) {
   p.kind = h->kind;
   p.step_ctr = h->at<long long>(h->off_ctl);
   p.flag = h->at<int>(h->off_ctl + 8);
+  fill_collision(p);
   return p;
 }
 
@@ -1092,48 +1093,55 @@ int btdf_step(btdf_t *h, int64_t n) {
 }
 
 // two steps from buffer cur into 1 - cur (temporal blocking): the tiles near
-// the bodies or the domain edges step twice by way of the third buffer X
-// (their first step also covers the ring of nodes just outside them), with
-// the marker kernel between; every other tile takes both steps at once
-// (lbm2_kernel), on the side stream beside that chain when the overlap
-// option is set (the two write disjoint tiles of the destination and read
-// only the source and X). ev: 7 events (before/after the first marker
-// kernel, after the near tiles' first step, after the second marker kernel,
-// after their second step, before/after the two-step kernel) or null.
-static hipError_t launch_two_step(const btdf_t *h, const void *A, void *B, const LbmParams &p, const int *fm,
-                                  hipStream_t s) {
-  hipError_t e = launch_lbm2(h->prec, h->variant, 4, A, B, p, fm, h->n_quad, s);
-  if (e == hipSuccess) e = launch_lbm2(h->prec, h->variant, 2, A, B, p, fm + h->n_quad, h->n_wide, s);
+// the bodies or the domain edges step twice by way of the third buffer X,
+// with the marker kernel between; every other tile takes both steps at once
+// (lbm2_kernel). The nodes just outside the near tiles (the ring) must hold
+// their first step in X before the near tiles' second step: the two-step pass
+// writes them, so it runs first. With the overlap option the two-step pass
+// runs on the side stream beside the near chain instead (it writes disjoint
+// tiles of the destination and reads only the source) and the ring kernel
+// supplies the ring. ev: 7 events (before/after the first marker kernel,
+// after the near tiles' first step, after the second marker kernel, after
+// their second step, before/after the two-step pass) or null.
+static hipError_t launch_two_step(const btdf_t *h, const void *A, void *B, void *X, const unsigned char *near,
+                                  const LbmParams &p, const int *fm, hipStream_t s) {
+  hipError_t e = launch_lbm2(h->prec, h->variant, 4, A, B, p, fm, h->n_quad, X, near, s);
+  if (e == hipSuccess) e = launch_lbm2(h->prec, h->variant, 2, A, B, p, fm + h->n_quad, h->n_wide, X, near, s);
   if (e == hipSuccess)
-    e = launch_lbm2(h->prec, h->variant, 1, A, B, p, fm + h->n_quad + h->n_wide, h->n_fused, s);
+    e = launch_lbm2(h->prec, h->variant, 1, A, B, p, fm + h->n_quad + h->n_wide, h->n_fused, X, near, s);
   return e;
 }
+
+static bool pair_overlap(const btdf_t *h) { return h->overlap != 0; }
 
 static int enqueue_pair(btdf_t *h, const LbmParams &p, const IbParams &ib, hipStream_t s, hipEvent_t *ev) {
   const void *A = h->ws + h->off_pop[h->cur];
   void *B = h->ws + h->off_pop[1 - h->cur];
   void *X = h->ws + h->off_pop3;
   const int *fm = h->at<int>(h->off_fmap);
-  const bool ov = h->overlap != 0;
-  hipStream_t s2 = s;
+  const unsigned char *near = h->at<unsigned char>(h->off_near);
+  const bool ov = pair_overlap(h);
   if (ov) {
     int rc = make_side(h);
     if (rc) return rc;
-    s2 = h->side;
     HIPCHK(hipEventRecord(h->ev_fork, s));
-    HIPCHK(hipStreamWaitEvent(s2, h->ev_fork, 0));
-    if (ev) HIPCHK(hipEventRecord(ev[5], s2));
-    HIPCHK(launch_two_step(h, A, B, p, fm, s2));
-    if (ev) HIPCHK(hipEventRecord(ev[6], s2));
-    HIPCHK(hipEventRecord(h->ev_join, s2));
+    HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+    if (ev) HIPCHK(hipEventRecord(ev[5], h->side));
+    HIPCHK(launch_two_step(h, A, B, X, nullptr, p, fm, h->side));
+    if (ev) HIPCHK(hipEventRecord(ev[6], h->side));
+    HIPCHK(hipEventRecord(h->ev_join, h->side));
   }
   if (ev) HIPCHK(hipEventRecord(ev[0], s));
   HIPCHK(launch_ib(h->prec, A, p, ib, s));
   if (ev) HIPCHK(hipEventRecord(ev[1], s));
+  if (!ov) {
+    if (ev) HIPCHK(hipEventRecord(ev[5], s));
+    HIPCHK(launch_two_step(h, A, B, X, near, p, fm, s));
+    if (ev) HIPCHK(hipEventRecord(ev[6], s));
+  }
   const int nb0 = h->n_quad + h->n_wide + h->n_fused;  // the near tiles start here in the map
   HIPCHK(launch_lbm(h->prec, h->variant, A, X, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
-  HIPCHK(launch_ring(h->prec, A, X, p, fm + nb0, h->n_near, h->at<unsigned char>(h->off_near), h->tile_x,
-                     h->tile_y, s));
+  if (ov) HIPCHK(launch_ring(h->prec, A, X, p, fm + nb0, h->n_near, near, h->tile_x, h->tile_y, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, A, X, p, s));
   if (ev) HIPCHK(hipEventRecord(ev[2], s));
   HIPCHK(launch_ib(h->prec, X, p, ib, s));
@@ -1141,13 +1149,7 @@ static int enqueue_pair(btdf_t *h, const LbmParams &p, const IbParams &ib, hipSt
   HIPCHK(launch_lbm(h->prec, h->variant, X, B, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, X, B, p, s));
   if (ev) HIPCHK(hipEventRecord(ev[4], s));
-  if (ov) {
-    HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
-  } else {
-    if (ev) HIPCHK(hipEventRecord(ev[5], s));
-    HIPCHK(launch_two_step(h, A, B, p, fm, s));
-    if (ev) HIPCHK(hipEventRecord(ev[6], s));
-  }
+  if (ov) HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
   h->cur ^= 1;
   h->steps += 2;
   return ok();
@@ -1205,7 +1207,8 @@ static int timed_impl(btdf_t *h, int64_t n, double *out) {
       hipEvent_t *E = &ev[7 * k];
       if (pairs) {
         (void)hipEventElapsedTime(&a, E[0], E[1]);
-        (void)hipEventElapsedTime(&b, E[1], E[2]);
+        // the near tiles' first step follows the two-step pass unless that runs beside it
+        (void)hipEventElapsedTime(&b, pair_overlap(h) ? E[1] : E[6], E[2]);
         (void)hipEventElapsedTime(&c, E[2], E[3]);
         (void)hipEventElapsedTime(&d, E[3], E[4]);
         (void)hipEventElapsedTime(&f, E[5], E[6]);

@@ -91,6 +91,47 @@ __host__ __device__ __forceinline__ int stencil_base(int kind, double X) {
   return (int)floor(X) - 1;
 }
 
+// ---- per-launch constants of the collision (eqs 5-7, 11), in the population
+// type; formed once on the host so the kernels read them from scalar registers
+
+template <typename T>
+struct CollK {
+  T omega, omc;  // omega, 1 - omega
+  T a9, a36;     // 4.5 omega w, for w = 1/9 (axes) and w = 1/36 (diagonals)
+  T b9, b36;     // 3 omega w
+  T c9, c36;     // 9 guo w
+  T d9, d36;     // 3 guo w
+  T m3g;         // -3 guo
+  T urx, ury;    // reference velocity
+};
+
+// The factors of the Guo term that depend on the force density f only, per
+// direction pair (1,3), (2,4), (5,7), (6,8) with e.f = f_x, f_y, f_x + f_y,
+// f_y - f_x: ev = 9 guo w e.f (even part), od = 3 guo w e.f (odd part);
+// g = -3 guo f (isotropic part, taken times u). Plain products and sums, so
+// the host and the device form the same bits from the same f.
+template <typename T>
+struct ForceK {
+  T fx, fy, gx, gy;
+  T ev[4], od[4];
+};
+
+template <typename T>
+__host__ __device__ inline ForceK<T> force_terms(const CollK<T> &k, T fx, T fy) {
+#pragma clang fp contract(off)
+  ForceK<T> f;
+  const T e[4] = {fx, fy, fx + fy, fy - fx};
+  f.fx = fx;
+  f.fy = fy;
+  f.gx = k.m3g * fx;
+  f.gy = k.m3g * fy;
+  for (int i = 0; i < 4; ++i) {
+    f.ev[i] = (i < 2 ? k.c9 : k.c36) * e[i];
+    f.od[i] = (i < 2 ? k.d9 : k.d36) * e[i];
+  }
+  return f;
+}
+
 // ---- parameters of one simulation, passed by value to every kernel
 struct LbmParams {
   int nx, ny;       // nodes (ghost columns included)
@@ -118,7 +159,54 @@ struct LbmParams {
   int kind;
   long long *step_ctr;   // steps completed on the device
   int *flag;             // instability flag: 0 fine, 1 + body, -1 node
+  // collision constants and the uniform body force's Guo factors, per precision
+  CollK<float> kf;
+  CollK<double> kd;
+  ForceK<float> gf;
+  ForceK<double> gd;
 };
+
+// the collision constants of tau-derived omega and guo and of u_ref, rounded
+// once from FP64
+template <typename T>
+inline CollK<T> make_coll(double omega, double guo, double urx, double ury) {
+  CollK<T> k;
+  k.omega = (T)omega;
+  k.omc = (T)(1.0 - omega);
+  k.a9 = (T)(0.5 * omega);
+  k.a36 = (T)(0.125 * omega);
+  k.b9 = (T)(omega / 3.0);
+  k.b36 = (T)(omega / 12.0);
+  k.c9 = (T)guo;
+  k.c36 = (T)(0.25 * guo);
+  k.d9 = (T)(guo / 3.0);
+  k.d36 = (T)(guo / 12.0);
+  k.m3g = (T)(-3.0 * guo);
+  k.urx = (T)urx;
+  k.ury = (T)ury;
+  return k;
+}
+
+// fill the constants of p from its omega, guo, reference velocity and body force
+inline void fill_collision(LbmParams &p) {
+  p.kf = make_coll<float>(p.omega, p.guo, p.urx, p.ury);
+  p.kd = make_coll<double>(p.omega, p.guo, p.urx, p.ury);
+  p.gf = force_terms<float>(p.kf, (float)p.Gx, (float)p.Gy);
+  p.gd = force_terms<double>(p.kd, p.Gx, p.Gy);
+}
+
+template <typename T>
+__device__ __forceinline__ const CollK<T> &coll(const LbmParams &p);
+template <>
+__device__ __forceinline__ const CollK<float> &coll<float>(const LbmParams &p) { return p.kf; }
+template <>
+__device__ __forceinline__ const CollK<double> &coll<double>(const LbmParams &p) { return p.kd; }
+template <typename T>
+__device__ __forceinline__ const ForceK<T> &gforce(const LbmParams &p);
+template <>
+__device__ __forceinline__ const ForceK<float> &gforce<float>(const LbmParams &p) { return p.gf; }
+template <>
+__device__ __forceinline__ const ForceK<double> &gforce<double>(const LbmParams &p) { return p.gd; }
 
 // tiles handled by one launch of the lattice kernel
 struct TileRange {
@@ -220,54 +308,78 @@ __device__ __forceinline__ float recip<float>(float x) {
 template <>
 __device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
 
+// A wave-uniform pointer pinned to scalar registers, so that an access
+// through it plus a 32-bit lane offset is one load or store with a scalar
+// base (the compiler may otherwise fold the uniform part into a 64-bit
+// per-lane address and spend vector instructions on every access).
+// (The result is a global-memory pointer, so accesses stay global ones.)
+template <typename P>
+using global_ptr = __attribute__((address_space(1))) P *;
+template <typename P>
+__device__ __forceinline__ global_ptr<P> uniform_ptr(P *ptr) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(ptr);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (global_ptr<P>)(((unsigned long long)hi << 32) | lo);
+}
+// store v at byte offset off from a uniform global base (nontemporal if NT)
+template <typename T, bool NT>
+__device__ __forceinline__ void store_uniform(global_ptr<char> base, unsigned off, T v) {
+  global_ptr<T> ptr = (global_ptr<T>)(base + off);
+  if (NT)
+    __builtin_nontemporal_store(v, ptr);
+  else
+    *ptr = v;
+}
+
+// fused multiply-add, spelled out: a * b + c rounded once
+__device__ __forceinline__ float fmx(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmx(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Corrected velocity (eq 11), equilibrium (eq 6), Guo term (eq 7) and BGK
 // relaxation (eq 5) on the stored deviations g~_q = g_q - c_q of one node:
 //   out~_q = (1 - omega) g~_q + omega (feq_q - c_q) + F_q.
 // With drho = rho - 1, du = u - u_ref (both formed from small terms only),
 // eu = e.u, ea = e.du, eb = e.(u + u_ref) and ef = e.f, opposite directions
 // share the even part and differ in the sign of the odd part:
-//   even = w (C + 4.5 omega (drho eu^2 + ea eb) + 9 guo eu ef)
-//   odd  = 3 w (omega (drho eu + ea) + guo ef)
+//   even = w C + 4.5 omega w (drho eu^2 + ea eb) + eu (9 guo w ef)
+//   odd  = 3 omega w (drho eu + ea) + 3 guo w ef
 //   C    = omega (drho (1 - 1.5 |u|^2) - 1.5 du.(u + u_ref)) - 3 guo u.f
 // (with u_ref = 0 this is omega feq~ + F of the plain deviations f - w).
-// fused multiply-add, spelled out: a * b + c rounded once
-__device__ __forceinline__ float fmx(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmx(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
+// The products of constants (and of constants and f) come in through k and
+// f, so a kernel whose force is uniform takes them from scalar registers.
 template <typename T>
-__device__ __forceinline__ void collide(const T g[9], T ftx, T fty, T omega, T guo, T urx, T ury, T out[9],
-                                        T &rho) {
+__device__ __forceinline__ void collide(const T g[9], const ForceK<T> &f, const CollK<T> &k, T out[9], T &rho) {
   // Every multiply-add is written out and nothing else is fused, so the same
   // inputs give the same bits whichever kernel the collision is inlined into
   // (left to itself the compiler fuses differently once it hoists common
   // terms, as in the two-step kernel).
 #pragma clang fp contract(off)
-  T drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+  const T drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
   rho = (T)1 + drho;
   const T mx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);  // m - u_ref
   const T my = (g[2] - g[4]) + (g[5] - g[8]) + (g[6] - g[7]);
   const T inv = recip<T>(rho);
-  const T dux = fmx(-drho, urx, fmx((T)0.5, ftx, mx)) * inv;
-  const T duy = fmx(-drho, ury, fmx((T)0.5, fty, my)) * inv;
-  const T ux = urx + dux, uy = ury + duy;
-  const T sx = ux + urx, sy = uy + ury;
+  const T dux = fmx(-drho, k.urx, fmx((T)0.5, f.fx, mx)) * inv;
+  const T duy = fmx(-drho, k.ury, fmx((T)0.5, f.fy, my)) * inv;
+  const T ux = k.urx + dux, uy = k.ury + duy;
+  const T sx = ux + k.urx, sy = uy + k.ury;
   const T a = fmx((T)-1.5, fmx(ux, ux, uy * uy), (T)1);
   const T c1 = fmx(drho, a, (T)-1.5 * fmx(dux, sx, duy * sy));
-  const T C = fmx(omega, c1, -((T)3 * guo) * fmx(ux, ftx, uy * fty));
-  const T K1 = (T)4.5 * omega, K2 = (T)9 * guo;
-  const T omc = (T)1 - omega;
-  out[0] = fmx(omc, g[0], (T)(4.0 / 9.0) * C);
-  auto pair = [&](int qp, int qm, T eu, T ea, T eb, T ef, T w) {
+  const T C = fmx(k.omega, c1, fmx(ux, f.gx, uy * f.gy));
+  const T C9 = C * (T)(1.0 / 9.0), C36 = C * (T)(1.0 / 36.0);
+  out[0] = fmx(k.omc, g[0], (T)(4.0 / 9.0) * C);
+  auto pair = [&](int qp, int qm, T eu, T ea, T eb, T ev, T od, T ka, T kb, T wC) {
     const T de = drho * eu;
-    const T even = w * fmx(K2 * eu, ef, fmx(K1, fmx(de, eu, ea * eb), C));
-    const T odd = ((T)3 * w) * fmx(omega, de + ea, guo * ef);
-    out[qp] = fmx(omc, g[qp], even) + odd;
-    out[qm] = fmx(omc, g[qm], even) - odd;
+    const T even = fmx(ka, fmx(de, eu, ea * eb), fmx(eu, ev, wC));
+    const T odd = fmx(kb, de + ea, od);
+    out[qp] = fmx(k.omc, g[qp], even) + odd;
+    out[qm] = fmx(k.omc, g[qm], even) - odd;
   };
-  pair(1, 3, ux, dux, sx, ftx, (T)(1.0 / 9.0));
-  pair(2, 4, uy, duy, sy, fty, (T)(1.0 / 9.0));
-  pair(5, 7, ux + uy, dux + duy, sx + sy, ftx + fty, (T)(1.0 / 36.0));
-  pair(6, 8, uy - ux, duy - dux, sy - sx, fty - ftx, (T)(1.0 / 36.0));
+  pair(1, 3, ux, dux, sx, f.ev[0], f.od[0], k.a9, k.b9, C9);
+  pair(2, 4, uy, duy, sy, f.ev[1], f.od[1], k.a9, k.b9, C9);
+  pair(5, 7, ux + uy, dux + duy, sx + sy, f.ev[2], f.od[2], k.a36, k.b36, C36);
+  pair(6, 8, uy - ux, duy - dux, sy - sx, f.ev[3], f.od[3], k.a36, k.b36, C36);
 }
 
 // Streaming pull g_q(x, y) = f_q(x - e_q, y - e_q), as a stored deviation,

@@ -323,9 +323,7 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
                         xw + WX + (NPT - 1) * BX <= p.nx - 1 - (p.outlet ? 1 : 0);
   const unsigned rowoff = (unsigned)(y - yw) * (unsigned)p.pitch;
 
-  const T omega = (T)p.omega, guo = (T)p.guo;
-  const T Gx = (T)p.Gx, Gy = (T)p.Gy;
-  const T urx = (T)p.urx, ury = (T)p.ury;
+  const CollK<T> &K = coll<T>(p);
   bool bad = false;
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
@@ -346,10 +344,13 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
 #pragma unroll
       for (int q = 0; q < 9; ++q) g[q] = pull<T, NTL>(A, p, q, x, y);
     }
-    const T ftx = forced ? (T)(p.Gx + (double)fib_x[k]) : Gx;
-    const T fty = forced ? (T)(p.Gy + (double)fib_y[k]) : Gy;
     T out[9], rho;
-    collide<T>(g, ftx, fty, omega, guo, urx, ury, out, rho);
+    if (forced) {
+      const ForceK<T> F = force_terms<T>(K, (T)(p.Gx + (double)fib_x[k]), (T)(p.Gy + (double)fib_y[k]));
+      collide<T>(g, F, K, out, rho);
+    } else {
+      collide<T>(g, gforce<T>(p), K, out, rho);
+    }
     bad |= !(rho > (T)0) || !isfinite(rho);
     if (interior) {
 #pragma unroll
@@ -617,18 +618,27 @@ hipError_t launch_lbm(int prec, int v, const void *A, void *B, const LbmParams &
 template <typename T, int OX, int OY, int BX, int BY, bool NT>
 __global__ __launch_bounds__(BX *BY) void lbm2_kernel(const T *__restrict__ A, T *__restrict__ C, LbmParams p,
                                                      const int *__restrict__ map, int count, int tile_x,
-                                                     int tile_y) {
+                                                     int tile_y, T *__restrict__ X,
+                                                     const unsigned char *__restrict__ near) {
   constexpr int RX = OX + 2, RY = OY + 2;  // the grown tile
   __shared__ T s_f[9][RY][RX];
+  __shared__ unsigned char s_near[3][8];  // near flags of the lattice tiles around the group (0: none)
   const int li = p.xcd_remap ? xcd_tile((int)blockIdx.x, count) : (int)blockIdx.x;
   const int t = map[li];
   const int tyi = t / p.ntx;
   const int txi = t - tyi * p.ntx;
   const int x0 = txi * tile_x, y0 = tyi * tile_y;
   const int tid = (int)threadIdx.y * BX + (int)threadIdx.x;
-  const T omega = (T)p.omega, guo = (T)p.guo;
-  const T Gx = (T)p.Gx, Gy = (T)p.Gy;
-  const T urx = (T)p.urx, ury = (T)p.ury;
+  const int W = OX / tile_x;  // lattice tiles in the group (1, 2 or 4), one tile row tall
+  // A group never touches a domain edge, so its neighbouring tile positions
+  // (rows tyi-1 .. tyi+1, columns txi-1 .. txi+W) all exist; the group's own
+  // tiles are not near.
+  if (near && tid < 24) {
+    const int r = tid >> 3, c = tid & 7;
+    s_near[r][c] = (c > W + 1 || (r == 1 && c >= 1 && c <= W)) ? 0 : near[(tyi - 1 + r) * p.ntx + txi - 1 + c];
+  }
+  const CollK<T> &K = coll<T>(p);
+  const ForceK<T> &F = gforce<T>(p);
   bool bad = false;
   // step n on the grown tile: first the OX columns of every grown row, so
   // that consecutive lanes take consecutive, line-aligned nodes of a row,
@@ -649,26 +659,35 @@ __global__ __launch_bounds__(BX *BY) void lbm2_kernel(const T *__restrict__ A, T
     node_of(k, ia, ja);
     const bool two = k + NTH < TOT;
     node_of(two ? k + NTH : k, ib, jb);
-    const int xa = x0 - 1 + ia, ya = y0 - 1 + ja, xb = x0 - 1 + ib, yb = y0 - 1 + jb;
+    // byte offsets of the two nodes from the tile's grown corner (x0-1, y0-1);
+    // each pull is then a uniform per-population base plus one of them
+    const unsigned oa = (unsigned)(ja * p.pitch + ia) * (unsigned)sizeof(T);
+    const unsigned ob = (unsigned)(jb * p.pitch + ib) * (unsigned)sizeof(T);
     T ga[9], gb[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-      ga[q] = A[(long long)q * p.plane + (long long)(ya - ey(q)) * p.pitch + (xa - ex(q))];
-      gb[q] = A[(long long)q * p.plane + (long long)(yb - ey(q)) * p.pitch + (xb - ex(q))];
+      const char *base = reinterpret_cast<const char *>(A + (long long)q * p.plane +
+                                                        (long long)(y0 - 1 - ey(q)) * p.pitch + (x0 - 1 - ex(q)));
+      ga[q] = *reinterpret_cast<const T *>(base + oa);
+      gb[q] = *reinterpret_cast<const T *>(base + ob);
     }
     T out[9], rho;
-    collide<T>(ga, Gx, Gy, omega, guo, urx, ury, out, rho);
+    collide<T>(ga, F, K, out, rho);
     bad |= !(rho > (T)0) || !isfinite(rho);
 #pragma unroll
     for (int q = 0; q < 9; ++q) s_f[q][ja][ia] = out[q];
     if (two) {
-      collide<T>(gb, Gx, Gy, omega, guo, urx, ury, out, rho);
+      collide<T>(gb, F, K, out, rho);
       bad |= !(rho > (T)0) || !isfinite(rho);
 #pragma unroll
       for (int q = 0; q < 9; ++q) s_f[q][jb][ib] = out[q];
     }
   }
   __syncthreads();
+  // whether any neighbouring tile is near (uniform: every lane reads the same words)
+  const unsigned *nw = reinterpret_cast<const unsigned *>(&s_near[0][0]);
+  const bool ring = near && (nw[0] | nw[1] | nw[2] | nw[3] | nw[4] | nw[5]) != 0;
+  const int sh = __builtin_ctz((unsigned)tile_x);  // tile widths are powers of two
   // step n+1 on the tile's own nodes, pulling from the LDS copy of state n+1
 #pragma unroll
   for (int jj = (int)threadIdx.y; jj < OY; jj += BY) {
@@ -679,11 +698,32 @@ __global__ __launch_bounds__(BX *BY) void lbm2_kernel(const T *__restrict__ A, T
 #pragma unroll
       for (int q = 0; q < 9; ++q) g[q] = s_f[q][j - ey(q)][i - ex(q)];
       T out[9], rho;
-      collide<T>(g, Gx, Gy, omega, guo, urx, ury, out, rho);
+      collide<T>(g, F, K, out, rho);
       bad |= !(rho > (T)0) || !isfinite(rho);
-      const long long base = (long long)(y0 + jj) * p.pitch + x0 + ii;
+      const unsigned off = (unsigned)(jj * p.pitch + ii) * (unsigned)sizeof(T);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) store<T, NT>(&C[(long long)q * p.plane + base], out[q]);
+      for (int q = 0; q < 9; ++q) {
+        store_uniform<T, NT>(uniform_ptr(reinterpret_cast<char *>(C + (long long)q * p.plane + (long long)y0 * p.pitch + x0)),
+                             off, out[q]);
+      }
+      // the ring: a node of the group's edge gives X its state n+1 in each
+      // direction q whose neighbour (x + e_q) lies in a near tile, the one
+      // population that tile's second step pulls from it
+      if (ring && (ii == 0 || ii == OX - 1 || jj == 0 || jj == OY - 1)) {
+        // the neighbouring tile (row, column in s_near) in each direction
+        const int cl = ii == 0 ? 0 : 1 + ((ii - 1) >> sh), cm = 1 + (ii >> sh);
+        const int cr = ii == OX - 1 ? W + 1 : 1 + ((ii + 1) >> sh);
+        const int rd = jj == 0 ? 0 : 1, ru = jj == OY - 1 ? 2 : 1;
+#pragma unroll
+        for (int q = 1; q < 9; ++q) {
+          const int r = ey(q) < 0 ? rd : (ey(q) > 0 ? ru : 1);
+          const int c = ex(q) < 0 ? cl : (ex(q) > 0 ? cr : cm);
+          if (s_near[r][c])
+            store_uniform<T, false>(
+                uniform_ptr(reinterpret_cast<char *>(X + (long long)q * p.plane + (long long)y0 * p.pitch + x0)),
+                off, s_f[q][jj + 1][ii + 1]);
+        }
+      }
     }
   }
   if (bad) p.flag[0] = -1;
@@ -691,11 +731,13 @@ __global__ __launch_bounds__(BX *BY) void lbm2_kernel(const T *__restrict__ A, T
 
 template <typename T, int OX, int OY, int BX, int BY, bool NT>
 static hipError_t launch_lbm2_t(const T *A, T *C, const LbmParams &p, const int *map, int count, int tx, int ty,
-                                hipStream_t s) {
+                                T *X, const unsigned char *near, hipStream_t s) {
   if constexpr (9 * (OX + 2) * (OY + 2) * sizeof(T) <= 65536) {
     if (count <= 0) return hipSuccess;
+    // the group is OX / tx lattice tiles (at most 4, a power of two wide) of one tile row
+    if (OX % tx != 0 || OX / tx > 4 || OY != ty || (tx & (tx - 1)) != 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL((lbm2_kernel<T, OX, OY, BX, BY, NT>), dim3(count), dim3(BX, BY), 0, s, A, C, p, map, count,
-                       tx, ty);
+                       tx, ty, X, near);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -704,24 +746,24 @@ static hipError_t launch_lbm2_t(const T *A, T *C, const LbmParams &p, const int 
 
 template <typename T>
 static hipError_t launch_lbm2_any(int v, int width, const T *A, T *C, const LbmParams &p, const int *map, int count,
-                                  hipStream_t s) {
+                                  T *X, const unsigned char *near, hipStream_t s) {
   int tx, ty;
   variant_tile(v, &tx, &ty);
   // width lattice tiles side by side, one thread per output node
   if (width == 4) {
-    if (tx == 32 && ty == 8) return launch_lbm2_t<T, 128, 8, 128, 8, true>(A, C, p, map, count, tx, ty, s);
-    if (tx == 32 && ty == 4) return launch_lbm2_t<T, 128, 4, 128, 4, true>(A, C, p, map, count, tx, ty, s);
+    if (tx == 32 && ty == 8) return launch_lbm2_t<T, 128, 8, 128, 8, true>(A, C, p, map, count, tx, ty, X, near, s);
+    if (tx == 32 && ty == 4) return launch_lbm2_t<T, 128, 4, 128, 4, true>(A, C, p, map, count, tx, ty, X, near, s);
     return hipErrorInvalidValue;
   }
   if (width == 2) {
-    if (tx == 32 && ty == 8) return launch_lbm2_t<T, 64, 8, 64, 8, true>(A, C, p, map, count, tx, ty, s);
-    if (tx == 32 && ty == 4) return launch_lbm2_t<T, 64, 4, 64, 4, true>(A, C, p, map, count, tx, ty, s);
-    if (tx == 64 && ty == 4) return launch_lbm2_t<T, 128, 4, 128, 4, true>(A, C, p, map, count, tx, ty, s);
+    if (tx == 32 && ty == 8) return launch_lbm2_t<T, 64, 8, 64, 8, true>(A, C, p, map, count, tx, ty, X, near, s);
+    if (tx == 32 && ty == 4) return launch_lbm2_t<T, 64, 4, 64, 4, true>(A, C, p, map, count, tx, ty, X, near, s);
+    if (tx == 64 && ty == 4) return launch_lbm2_t<T, 128, 4, 128, 4, true>(A, C, p, map, count, tx, ty, X, near, s);
     return hipErrorInvalidValue;
   }
 #define X(id, bx, by, npt, nt, ntl)                                                                   \
   if (v == id)                                                                                      \
-    return npt == 1 && width == 1 ? launch_lbm2_t<T, bx, by, bx, by, nt>(A, C, p, map, count, tx, ty, s)    \
+    return npt == 1 && width == 1 ? launch_lbm2_t<T, bx, by, bx, by, nt>(A, C, p, map, count, tx, ty, X, near, s)    \
                                   : hipErrorInvalidValue;
   BTDF_VARIANTS(X)
 #undef X
@@ -729,10 +771,11 @@ static hipError_t launch_lbm2_any(int v, int width, const T *A, T *C, const LbmP
 }
 
 hipError_t launch_lbm2(int prec, int v, int width, const void *A, void *C, const LbmParams &p, const int *map,
-                       int count, hipStream_t s) {
+                       int count, void *X, const unsigned char *near, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  if (prec == 4) return launch_lbm2_any<float>(v, width, (const float *)A, (float *)C, p, map, count, s);
-  return launch_lbm2_any<double>(v, width, (const double *)A, (double *)C, p, map, count, s);
+  if (prec == 4)
+    return launch_lbm2_any<float>(v, width, (const float *)A, (float *)C, p, map, count, (float *)X, near, s);
+  return launch_lbm2_any<double>(v, width, (const double *)A, (double *)C, p, map, count, (double *)X, near, s);
 }
 
 // whether a launch shape's two-step pass can also take width (2 or 4) of its tiles side by side
@@ -748,8 +791,9 @@ bool variant_has_wide_lbm2(int v, int prec, int width) {
 // The first step of the ring of every near tile: the nodes one step outside
 // the tile that lie in a two-step tile (plain interior nodes, no
 // immersed-boundary force; a node next to two near tiles is written twice
-// with the same value). One workgroup per near tile, so the ring is read
-// from the lines the tile's own step has just brought into L2.
+// with the same value), stored only in the directions that point into a
+// near tile. One workgroup per near tile, so the ring is read from the lines
+// the tile's own step has just brought into L2.
 template <typename T>
 __global__ __launch_bounds__(128) void ring_kernel(const T *__restrict__ A, T *__restrict__ X, LbmParams p,
                                                    const int *__restrict__ near_map, const unsigned char *__restrict__ near,
@@ -779,10 +823,13 @@ __global__ __launch_bounds__(128) void ring_kernel(const T *__restrict__ A, T *_
 #pragma unroll
     for (int q = 0; q < 9; ++q) g[q] = A[(long long)q * p.plane + (long long)(y - ey(q)) * p.pitch + (x - ex(q))];
     T out[9], rho;
-    collide<T>(g, (T)p.Gx, (T)p.Gy, (T)p.omega, (T)p.guo, (T)p.urx, (T)p.ury, out, rho);
+    collide<T>(g, gforce<T>(p), coll<T>(p), out, rho);
     const long long base = (long long)y * p.pitch + x;
+    // only the populations that a near tile pulls: direction q when x + e_q
+    // lies in a near tile (such a node is interior, so no wrap is needed)
 #pragma unroll
-    for (int q = 0; q < 9; ++q) X[(long long)q * p.plane + base] = out[q];
+    for (int q = 1; q < 9; ++q)
+      if (near[((y + ey(q)) / tile_y) * p.ntx + (x + ex(q)) / tile_x]) X[(long long)q * p.plane + base] = out[q];
     if (!(rho > (T)0) || !isfinite(rho)) p.flag[0] = -1;
   }
 }

@@ -12,8 +12,10 @@ hipError_t launch_lbm(int prec, int variant, const void *A, void *B, const LbmPa
                       const IbParams &ib, hipStream_t s);
 hipError_t launch_ib(int prec, const void *A, const LbmParams &p, const IbParams &ib, hipStream_t s);
 hipError_t launch_rigid_move(const MoveParams &mp, hipStream_t s);
+// two steps A -> C over the listed groups of width lattice tiles; with near
+// non-null, edge nodes next to a near tile also store their first step in X
 hipError_t launch_lbm2(int prec, int variant, int width, const void *A, void *C, const LbmParams &p, const int *map,
-                       int count, hipStream_t s);
+                       int count, void *X, const unsigned char *near, hipStream_t s);
 bool variant_has_wide_lbm2(int variant, int prec, int width);
 bool variant_has_lbm2(int variant, int prec);
 hipError_t launch_ring(int prec, const void *A, void *X, const LbmParams &p, const int *near_map, int n_near,

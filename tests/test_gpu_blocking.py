@@ -58,13 +58,17 @@ def test_blocked_steps_are_bit_identical(name, seed, nx, ny, bc, precision):
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
-@pytest.mark.parametrize("opts", ["passes", "implicit", "rkpm", "timed"])
+@pytest.mark.parametrize("opts", ["passes", "implicit", "rkpm", "timed", "overlap", "overlap-timed"])
 def test_blocking_with_other_features(opts):
+    """(With the overlap option the two-step pass runs on a second stream and
+    the ring kernel, not the pass, gives the near tiles their neighbours'
+    first step.)"""
     from paper_1806_09403_amd import _lib
     c = bodies_case(45, 384, 192, W.CHANNEL, kind=W.ROMA3)
     o = {"passes": {_lib.OPT_FORCING_PASSES: 3}, "implicit": {_lib.OPT_FORCING_METHOD: 1},
-         "rkpm": {_lib.OPT_FORCING_METHOD: 2}, "timed": {}}[opts]
-    timed = opts == "timed"
+         "rkpm": {_lib.OPT_FORCING_METHOD: 2}, "timed": {}, "overlap": {_lib.OPT_OVERLAP: 1},
+         "overlap-timed": {_lib.OPT_OVERLAP: 1}}[opts]
+    timed = opts.endswith("timed")
     ref = run(c, 0, (3, 10), 4, o, timed=timed)
     got = run(c, 1, (3, 10), 4, o, timed=timed)
     assert got[2] > 0
