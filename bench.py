@@ -40,7 +40,7 @@ def parse():
     p.add_argument("--interior", type=int, default=-1, help="1/0: uniform-base path for interior waves (-1: library default)")
     p.add_argument("--overlap", type=int, default=-1, help="1/0: marker kernel beside the lattice kernel (-1: library default)")
     p.add_argument("--blocking", type=int, default=-1,
-                   help="1/0: two steps per pass away from the bodies (-1: library default)")
+                   help="steps per pass away from the bodies: 0 off, 1 deepest, 2 or 3 (-1: library default)")
     p.add_argument("--plane-pad", type=int, default=0)
     p.add_argument("--row-align", type=int, default=-1, help="row alignment in bytes (-1: library default)")
     p.add_argument("--copy-probe-mb", type=int, default=0,
@@ -295,9 +295,10 @@ def main():
     print("setup + warmup %.1f s" % (time.perf_counter() - t_setup), file=sys.stderr, flush=True)
 
     fused_tiles = sim.get_option(_lib.OPT_FUSED_TILES)
+    depth = sim.get_option(_lib.OPT_STEPS_PER_PASS)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ms_ib, ms_single, ms_pair = sim.step_timed_split(args.steps)
+    ms_ib, ms_single, ms_pass = sim.step_timed_split(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sim.forces()  # surfaces an instability as an error
@@ -309,12 +310,12 @@ def main():
     node_bytes = 9 * 2 * prec  # one read and one write of the 9 populations
     variant = sim.get_option(_lib.OPT_LBM_VARIANT)
     if fused_tiles > 0:
-        # dominant kernel: the two-step pass, 2 updates per node per launch of node_bytes
+        # dominant kernel: the blocked pass, depth updates per node per launch of node_bytes
         tile_nodes = sim.get_option(_lib.OPT_TILE_X) * sim.get_option(_lib.OPT_TILE_Y)
         launch_nodes = fused_tiles * tile_nodes
-        launch_ms = 2.0 * ms_pair
-        kernel, bytes_per_update = "lbm2_kernel", node_bytes / 2
-        key = "%s-%s-v%d-b1" % (args.workload, args.delta, variant)
+        launch_ms = depth * ms_pass
+        kernel, bytes_per_update = "lbm%d_kernel" % depth, node_bytes / depth
+        key = "%s-%s-v%d-p%d" % (args.workload, args.delta, variant, depth)
     else:
         launch_nodes, launch_ms = n, ms_single
         kernel, bytes_per_update = "lbm_kernel", node_bytes
@@ -351,11 +352,12 @@ def main():
                    "overlap": sim.get_option(_lib.OPT_OVERLAP),
                    "graph_chunk": args.graph_chunk,
                    "temporal_blocking": sim.get_option(_lib.OPT_TEMPORAL_BLOCKING),
-                   "two_step_tiles": fused_tiles, "two_step_nodes_frac": round(launch_nodes / n, 4)
-                   if fused_tiles else 0.0},
-        "kernel_ms": {"ib_kernel": round(ms_ib, 5), "lbm_kernel": round(ms_single, 5),
-                      "lbm2_kernel": round(2.0 * ms_pair, 5)},
-        "kernel_ms_note": "ib_kernel and lbm_kernel: per step; lbm2_kernel: per launch (two steps)",
+                   "steps_per_pass": depth, "blocked_tiles": fused_tiles,
+                   "blocked_nodes_frac": round(launch_nodes / n, 4) if fused_tiles else 0.0},
+        "kernel_ms": dict([("ib_kernel", round(ms_ib, 5)), ("lbm_kernel", round(ms_single, 5))] +
+                          ([(kernel, round(launch_ms, 5))] if fused_tiles > 0 else [])),
+        "kernel_ms_note": "ib_kernel and lbm_kernel: per step" +
+                          ("; %s: per launch (%d steps)" % (kernel, depth) if fused_tiles > 0 else ""),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": kernel, "bytes_per_update": bytes_per_update,

@@ -116,14 +116,20 @@ extern "C" {
 #define BTDF_OPT_FORCING_METHOD 15 /* BTDF_FORCING_*: how the marker force is formed and spread (Section 3);
                                       stand-alone handles only, NF = 1, bodies of at most 2048 markers; the
                                       matrices are formed on the host when the bodies or the method change */
-#define BTDF_OPT_TEMPORAL_BLOCKING 16 /* 1 (default): tiles at least one node clear of every marker stencil and
-                                         two nodes clear of the domain edges take two steps per pass (each node
-                                         read and written once for two updates); the others step singly with the
-                                         marker kernel between. Results are bit-identical to single steps. Takes
-                                         one more population buffer. Steps run singly instead with a graph chunk
-                                         > 0, with moving bodies, or with a launch shape of more than one node
-                                         per thread. 0: off. Batch cases step singly. */
-#define BTDF_OPT_FUSED_TILES 17       /* read-only: tiles that take the two-step pass (0 when it is not active) */
+#define BTDF_OPT_TEMPORAL_BLOCKING 16 /* d steps per pass for the tiles at least d-1 nodes clear of every marker
+                                         stencil and d nodes clear of the domain edges (each node read and
+                                         written once for d updates); the others step singly with the marker
+                                         kernel between, and the pass gives them the intermediate states of the
+                                         nodes just outside. Results are bit-identical to single steps.
+                                         1 (default): the deepest the launch shape has (3, or 2 when the overlap
+                                         option is set or the shape has no three-step pass, as for tiles one or
+                                         two rows tall); 2 or 3: that depth where the shape has it, else the
+                                         next lower; 0: off. Takes d-1 more population buffers. Steps run singly
+                                         instead with a graph chunk > 0, with moving bodies, or with a launch
+                                         shape of more than one node per thread; batch cases step singly. A step
+                                         count that is not a multiple of d ends with single steps. */
+#define BTDF_OPT_FUSED_TILES 17       /* read-only: lattice tiles that take the blocked pass (0 when it is not active) */
+#define BTDF_OPT_STEPS_PER_PASS 18    /* read-only: steps per pass of those tiles (1 when blocking is not active) */
 #define BTDF_OPT_FORCING_PASSES 14 /* NF in 1..64 (default 1): direct-forcing passes per step (Sec. 2.3, eqs 29-31);
                                       each pass after the first re-interpolates the velocity corrected by the force
                                       spread so far and adds 2 rho_l (U - u) to the marker force; stand-alone
@@ -237,8 +243,9 @@ int btdf_step(btdf_t *h, int64_t n);
 int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm);
 
 /* As btdf_step_timed with the lattice time split: ms[0] marker kernels,
- * ms[1] single-step lattice kernels, ms[2] the two-step kernel of temporal
- * blocking (per step: half its mean launch duration), all means per step. */
+ * ms[1] single-step lattice kernels, ms[2] the blocked pass of temporal
+ * blocking (per step: its mean launch duration over the steps per pass),
+ * all means per step. */
 int btdf_step_timed_split(btdf_t *h, int64_t n, double *ms);
 
 /* Hydrodynamic force and torque on every body at the last step:

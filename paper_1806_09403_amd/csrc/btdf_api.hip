@@ -164,30 +164,50 @@ void cover_lists(const btdf_t *h, std::vector<int> &off, std::vector<int> &list)
   if (list.empty()) list.push_back(0);
 }
 
-// Tiles for temporal blocking on the current launch shape: a tile is "near"
-// if a marker stencil grown by one node reaches it or if it lies within two
-// nodes of a domain edge. Near tiles step singly; so do, for their first
-// step only, the ring nodes just outside them (whose intermediate state the
-// near tiles' second step pulls).
+// steps per pass of the tiles away from the bodies for the options and the
+// launch shape: 3 where the shape has the three-step pass (unless the
+// overlap option asks for the two-step pass beside the near tiles), else 2
+// where it has the two-step pass, else 1 (no blocking)
+int pass_depth(const btdf_t *h) {
+  if (!h->tblock) return 1;
+  const int want = h->tblock == 1 ? (h->overlap ? 2 : 3) : h->tblock;
+  if (want >= 3 && variant_has_lbm3(h->variant, h->prec, 1)) return 3;
+  if (variant_has_lbm2(h->variant, h->prec)) return 2;
+  return 1;
+}
+
+// whether the pass of depth d has a launch over w lattice tiles side by side
+static bool has_group(const btdf_t *h, int d, int w) {
+  if (d == 3) return variant_has_lbm3(h->variant, h->prec, w);
+  return w == 1 ? variant_has_lbm2(h->variant, h->prec) : variant_has_wide_lbm2(h->variant, h->prec, w);
+}
+
+// Tiles for temporal blocking of depth d = h->depth on the current launch
+// shape: a tile is "near" if a marker stencil grown by d - 1 nodes reaches
+// it or if it lies within d nodes of a domain edge (a pass takes its first
+// step over its tiles grown by d - 1 nodes, which must hold no forced and no
+// boundary node). Near tiles step singly, with the marker kernel between;
+// the pass gives them the intermediate states of the nodes just outside.
 void fused_lists(btdf_t *h) {
   h->fmap.clear();
   h->n_quad = h->n_wide = h->n_fused = h->n_near = 0;
   h->near.clear();
-  if (!h->tblock) return;
+  const int d = h->depth;
+  if (d < 2) return;
   const int tx = h->tile_x, ty = h->tile_y, ntx = h->ntx, nty = h->nty, ntiles = ntx * nty;
   std::vector<char> near(ntiles, 0);
   for (int t = 0; t < ntiles; ++t) {
     const int x0 = (t % ntx) * tx, y0 = (t / ntx) * ty;
-    if (x0 < 2 || x0 + tx + 2 > h->nx || y0 < 2 || y0 + ty + 2 > h->ny) near[t] = 1;
+    if (x0 < d || x0 + tx + d > h->nx || y0 < d || y0 + ty + d > h->ny) near[t] = 1;
   }
   for (int l = 0; l < h->nm(); ++l) {
     int xlo, xhi, ylo, yhi;
     marker_range(h->kind, h->X[l], &xlo, &xhi);
     marker_range(h->kind, h->Y[l], &ylo, &yhi);
-    xlo -= 1 + h->margin;
-    xhi += 1 + h->margin;
-    ylo -= 1 + h->margin;
-    yhi += 1 + h->margin;
+    xlo -= d - 1 + h->margin;
+    xhi += d - 1 + h->margin;
+    ylo -= d - 1 + h->margin;
+    yhi += d - 1 + h->margin;
     for (int j = ylo; j <= yhi; ++j) {
       const int jj = h->yper() ? ((j % h->ny) + h->ny) % h->ny : j;
       if (jj < 0 || jj >= h->ny) continue;
@@ -203,7 +223,7 @@ void fused_lists(btdf_t *h) {
   std::vector<char> grouped(ntiles, 0);
   for (int w : {4, 2}) {
     const size_t start = h->fmap.size();
-    if (variant_has_wide_lbm2(h->variant, h->prec, w))
+    if (has_group(h, d, w))
       for (int b = 0; b < nty; ++b)
         for (int a = 0; a + w - 1 < ntx; a += w) {
           const int t = b * ntx + a;
@@ -379,13 +399,16 @@ void compute_layout(btdf_t *h) {
   // stepped singly (those next to the bodies and the edges, grown by their
   // neighbours), then those next to the bodies and the edges; and a third
   // population buffer for the singly stepped tiles' intermediate state
+  h->depth = pass_depth(h);
   fused_lists(h);
   h->off_fmap = o;
   o = align256(o + 2 * (size_t)max_tiles * sizeof(int));
   h->off_near = o;  // one flag per tile
   o = align256(o + (size_t)max_tiles);
-  h->off_pop3 = o;
-  o = align256(o + (h->tblock ? pop_bytes : 0));
+  h->off_pop3 = o;  // the near tiles' intermediate states n+1 (and n+2 for three steps)
+  o = align256(o + (h->depth >= 2 ? pop_bytes : 0));
+  h->off_pop4 = o;
+  o = align256(o + (h->depth >= 3 ? pop_bytes : 0));
   // rigid motion: [nb][4] theta vx vy omega, then [nb] moving flags; [nm][2] offsets
   h->off_motion = o;
   o = align256(o + 4 * (size_t)std::max(nb, 1) * sizeof(double) + (size_t)std::max(nb, 1) * sizeof(int));
@@ -985,7 +1008,7 @@ int btdf_set_marker_velocity(btdf_t *h, int body, const double *uv) {
   return ok();
 }
 
-static int enqueue_pair(btdf_t *h, const LbmParams &p, const IbParams &ib, hipStream_t s, hipEvent_t *ev);
+static int enqueue_pass(btdf_t *h, const LbmParams &p, const IbParams &ib, hipStream_t s, hipEvent_t *ev);
 static bool blocking_active(const btdf_t *h);
 
 // n steps from the current buffer: graphs of graph_chunk steps where they fit
@@ -1072,10 +1095,11 @@ int btdf_step(btdf_t *h, int64_t n) {
   if (rc) return rc;
   const LbmParams p = make_params(h);
   const IbParams ib = make_ib(h);
-  if (blocking_active(h) && n >= 2) {
-    for (int64_t k = 0; k < n / 2; ++k)
-      if ((rc = enqueue_pair(h, p, ib, h->stream, nullptr))) return rc;
-    if ((n & 1) && (rc = run_steps(h, p, ib, 1))) return rc;
+  if (blocking_active(h) && n >= h->depth) {
+    const int d = h->depth;
+    for (int64_t k = 0; k < n / d; ++k)
+      if ((rc = enqueue_pass(h, p, ib, h->stream, nullptr))) return rc;
+    if ((n % d) && (rc = run_steps(h, p, ib, n % d))) return rc;
   } else if (!h->any_moving()) {
     if ((rc = run_steps(h, p, ib, n))) return rc;
   } else {
@@ -1155,10 +1179,52 @@ static int enqueue_pair(btdf_t *h, const LbmParams &p, const IbParams &ib, hipSt
   return ok();
 }
 
+// three steps from buffer cur into 1 - cur (three-step blocking): as a pair,
+// with the near tiles' states n+1 and n+2 in X1 and X2 and the marker kernel
+// before each of their steps; the three-step pass runs first and writes both
+// rings. ev: 9 events, the pair's 7 and, after the third marker kernel and
+// after the near tiles' third step, ev[7] and ev[8]; or null.
+static int enqueue_triple(btdf_t *h, const LbmParams &p, const IbParams &ib, hipStream_t s, hipEvent_t *ev) {
+  const void *A = h->ws + h->off_pop[h->cur];
+  void *B = h->ws + h->off_pop[1 - h->cur];
+  void *X1 = h->ws + h->off_pop3;
+  void *X2 = h->ws + h->off_pop4;
+  const int *fm = h->at<int>(h->off_fmap);
+  const unsigned char *near = h->at<unsigned char>(h->off_near);
+  const int nb0 = h->n_quad + h->n_wide + h->n_fused;  // the near tiles start here in the map
+  if (ev) HIPCHK(hipEventRecord(ev[0], s));
+  HIPCHK(launch_ib(h->prec, A, p, ib, s));
+  if (ev) HIPCHK(hipEventRecord(ev[1], s));
+  if (ev) HIPCHK(hipEventRecord(ev[5], s));
+  HIPCHK(launch_lbm3(h->prec, h->variant, 4, A, B, p, fm, h->n_quad, X1, X2, near, s));
+  HIPCHK(launch_lbm3(h->prec, h->variant, 2, A, B, p, fm + h->n_quad, h->n_wide, X1, X2, near, s));
+  HIPCHK(launch_lbm3(h->prec, h->variant, 1, A, B, p, fm + h->n_quad + h->n_wide, h->n_fused, X1, X2, near, s));
+  if (ev) HIPCHK(hipEventRecord(ev[6], s));
+  HIPCHK(launch_lbm(h->prec, h->variant, A, X1, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
+  if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, A, X1, p, s));
+  if (ev) HIPCHK(hipEventRecord(ev[2], s));
+  HIPCHK(launch_ib(h->prec, X1, p, ib, s));
+  if (ev) HIPCHK(hipEventRecord(ev[3], s));
+  HIPCHK(launch_lbm(h->prec, h->variant, X1, X2, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
+  if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, X1, X2, p, s));
+  if (ev) HIPCHK(hipEventRecord(ev[4], s));
+  HIPCHK(launch_ib(h->prec, X2, p, ib, s));
+  if (ev) HIPCHK(hipEventRecord(ev[7], s));
+  HIPCHK(launch_lbm(h->prec, h->variant, X2, B, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
+  if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, X2, B, p, s));
+  if (ev) HIPCHK(hipEventRecord(ev[8], s));
+  h->cur ^= 1;
+  h->steps += 3;
+  return ok();
+}
+
+static int enqueue_pass(btdf_t *h, const LbmParams &p, const IbParams &ib, hipStream_t s, hipEvent_t *ev) {
+  return h->depth == 3 ? enqueue_triple(h, p, ib, s, ev) : enqueue_pair(h, p, ib, s, ev);
+}
+
 static bool blocking_active(const btdf_t *h) {
-  return h->tblock && h->graph_chunk == 0 && h->layout_ok && h->n_quad + h->n_wide + h->n_fused > 0 &&
-         !h->any_moving() &&
-         variant_has_lbm2(h->variant, h->prec);
+  return h->depth >= 2 && h->graph_chunk == 0 && h->layout_ok && h->n_quad + h->n_wide + h->n_fused > 0 &&
+         !h->any_moving();
 }
 
 // per-step means over n timed steps: out[0] marker kernels, out[1] single-step
@@ -1170,24 +1236,25 @@ static int timed_impl(btdf_t *h, int64_t n, double *out) {
   if (rc) return rc;
   const LbmParams p = make_params(h);
   const IbParams ib = make_ib(h);
-  const int chunk = 256;
-  std::vector<hipEvent_t> ev(7 * chunk, nullptr);
+  const int chunk = 256, NE = 9;  // events per entry
+  std::vector<hipEvent_t> ev(NE * chunk, nullptr);
   for (auto &e : ev) HIPCHK(hipEventCreate(&e));
   const bool ov = overlapping(h);
+  const int d = h->depth;
   double tib = 0.0, tlbm = 0.0, tpair = 0.0;
   int64_t done = 0;
   rc = ok();
   while (done < n && rc == 0) {
-    const bool pairs = blocking_active(h) && n - done >= 2;
-    const int m = pairs ? (int)std::min<int64_t>(chunk, (n - done) / 2) : (int)std::min<int64_t>(chunk, n - done);
+    const bool pairs = blocking_active(h) && n - done >= d;  // passes of d steps
+    const int m = pairs ? (int)std::min<int64_t>(chunk, (n - done) / d) : (int)std::min<int64_t>(chunk, n - done);
     const bool moving = h->any_moving();
     for (int k = 0; k < m && rc == 0; ++k) {
       if (pairs) {
-        rc = enqueue_pair(h, p, ib, h->stream, &ev[7 * k]);
+        rc = enqueue_pass(h, p, ib, h->stream, &ev[NE * k]);
         continue;
       }
       if (moving && h->steps_to_rebin <= 0 && (rc = rebin(h))) break;
-      const StepEvents te{ev[7 * k], ev[7 * k + 1], ev[7 * k + 2], ev[7 * k + 3], ev[7 * k + 4], ev[7 * k + 5]};
+      const StepEvents te{ev[NE * k], ev[NE * k + 1], ev[NE * k + 2], ev[NE * k + 3], ev[NE * k + 4], ev[NE * k + 5]};
       rc = enqueue_step(h, p, ib, h->cur, h->stream, &te);
       h->cur ^= 1;
       h->steps++;
@@ -1203,17 +1270,21 @@ static int timed_impl(btdf_t *h, int64_t n, double *out) {
       break;
     }
     for (int k = 0; k < m; ++k) {
-      float a = 0.f, b = 0.f, c = 0.f, d = 0.f, f = 0.f;
-      hipEvent_t *E = &ev[7 * k];
+      float a = 0.f, b = 0.f, c = 0.f, e4 = 0.f, f = 0.f, g = 0.f, gg = 0.f;
+      hipEvent_t *E = &ev[NE * k];
       if (pairs) {
         (void)hipEventElapsedTime(&a, E[0], E[1]);
-        // the near tiles' first step follows the two-step pass unless that runs beside it
-        (void)hipEventElapsedTime(&b, pair_overlap(h) ? E[1] : E[6], E[2]);
+        // the near tiles' first step follows the pass unless that runs beside it
+        (void)hipEventElapsedTime(&b, d == 2 && pair_overlap(h) ? E[1] : E[6], E[2]);
         (void)hipEventElapsedTime(&c, E[2], E[3]);
-        (void)hipEventElapsedTime(&d, E[3], E[4]);
+        (void)hipEventElapsedTime(&e4, E[3], E[4]);
         (void)hipEventElapsedTime(&f, E[5], E[6]);
-        tib += a + c;
-        tlbm += b + d;
+        if (d == 3) {
+          (void)hipEventElapsedTime(&g, E[4], E[7]);
+          (void)hipEventElapsedTime(&gg, E[7], E[8]);
+        }
+        tib += a + c + g;
+        tlbm += b + e4 + gg;
         tpair += f;
         continue;
       }
@@ -1227,7 +1298,7 @@ static int timed_impl(btdf_t *h, int64_t n, double *out) {
       tib += a;
       tlbm += b + c;
     }
-    done += pairs ? 2 * (int64_t)m : m;
+    done += pairs ? (int64_t)d * m : m;
   }
   for (auto &e : ev)
     if (e) (void)hipEventDestroy(e);
@@ -1547,6 +1618,10 @@ int btdf_set_option(btdf_t *h, int key, int64_t value) {
       return ok();
     case BTDF_OPT_OVERLAP:
       if (value != 0 && value != 1) return fail(BTDF_EINVAL, "overlap flag must be 0 or 1");
+      if (value != h->overlap && h->tblock == 1) {
+        h->layout_ok = false;  // the pass depth follows the overlap option
+        h->device_ok = false;
+      }
       h->overlap = (int)value;
       drop_graph(h);
       return ok();
@@ -1574,7 +1649,7 @@ int btdf_set_option(btdf_t *h, int key, int64_t value) {
       h->layout_ok = false;
       return ok();
     case BTDF_OPT_TEMPORAL_BLOCKING:
-      if (value != 0 && value != 1) return fail(BTDF_EINVAL, "temporal blocking flag must be 0 or 1");
+      if (value < 0 || value > 3) return fail(BTDF_EINVAL, "temporal blocking must be 0 (off), 1 (deepest), 2 or 3");
       if (value != h->tblock) {
         h->tblock = (int)value;
         h->layout_ok = false;  // the tile lists and the third buffer
@@ -1638,6 +1713,10 @@ int btdf_get_option(const btdf_t *h, int key, int64_t *value) {
     case BTDF_OPT_FUSED_TILES:
       if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
       *value = blocking_active(h) ? 4 * h->n_quad + 2 * h->n_wide + h->n_fused : 0;  // in lattice tiles
+      return ok();
+    case BTDF_OPT_STEPS_PER_PASS:
+      if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
+      *value = blocking_active(h) ? h->depth : 1;
       return ok();
     default: return fail(BTDF_EINVAL, "unknown option %d", key);
   }

@@ -65,7 +65,8 @@ struct btdf_sim {
   int margin = 0;
   int64_t steps_to_rebin = 0;
   // temporal blocking: tiles taking two steps at once, then the singly stepped regions
-  int tblock = 1;
+  int tblock = 1;  // option: 0 off, 1 deepest available, 2 or 3 steps per pass
+  int depth = 1;   // steps per pass of the tiles away from the bodies (set with the layout)
   std::vector<int> fmap;  // two-step groups of 4 and 2 tiles (first tile of each), single two-step tiles, near tiles
   std::vector<unsigned char> near;  // per lattice tile: 1 if it steps singly
   int n_quad = 0, n_wide = 0, n_fused = 0, n_near = 0;
@@ -79,7 +80,7 @@ struct btdf_sim {
   size_t off_pop[2] = {0, 0}, off_ctl = 0, grid_bytes = 0;
   size_t off_hist = 0, off_mk = 0, off_mkw = 0, off_mkixy = 0, off_mkbody = 0, off_body = 0, off_boff = 0,
          off_toff = 0, off_tlist = 0, off_tmap = 0, off_coff = 0, off_clist = 0, off_mdfc = 0, off_mdff = 0,
-         off_moff = 0, off_minv = 0, off_motion = 0, off_rxy = 0, off_fmap = 0, off_near = 0, off_pop3 = 0, total = 0;
+         off_moff = 0, off_minv = 0, off_motion = 0, off_rxy = 0, off_fmap = 0, off_near = 0, off_pop3 = 0, off_pop4 = 0, total = 0;
   bool layout_ok = false;  // host layout current for bodies and tiles
   bool device_ok = false;  // body part uploaded into the workspace
   bool state_ok = false;   // populations hold a state

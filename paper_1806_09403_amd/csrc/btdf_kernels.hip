@@ -788,6 +788,240 @@ bool variant_has_wide_lbm2(int v, int prec, int width) {
   return shape && 9 * (width * tx + 2) * (ty + 2) * prec <= 65536;
 }
 
+// ---- three steps per pass (deeper temporal blocking)
+// Shapes whose three-step pass fits: the group grown by two in LDS (64 KB)
+// and its grown-by-one region within two nodes per thread.
+template <typename T, int OX, int OY>
+constexpr bool lbm3_fits() {
+  return 9 * (OX + 4) * (OY + 4) * (int)sizeof(T) <= 65536 && (OX + 2) * (OY + 2) <= 2 * OX * OY;
+}
+
+// The ring directions of an edge node of a group: bit q set when the
+// neighbour x + e_q lies in a near tile (s_near as in lbm2_kernel).
+template <int OX, int OY>
+__device__ __forceinline__ unsigned ring_mask(const unsigned char (&s_near)[3][8], int ii, int jj, int W, int sh) {
+  const int cl = ii == 0 ? 0 : 1 + ((ii - 1) >> sh), cm = 1 + (ii >> sh);
+  const int cr = ii == OX - 1 ? W + 1 : 1 + ((ii + 1) >> sh);
+  const int rd = jj == 0 ? 0 : 1, ru = jj == OY - 1 ? 2 : 1;
+  unsigned m = 0;
+#pragma unroll
+  for (int q = 1; q < 9; ++q) {
+    const int r = ey(q) < 0 ? rd : (ey(q) > 0 ? ru : 1);
+    const int c = ex(q) < 0 ? cl : (ex(q) > 0 ? cr : cm);
+    m |= s_near[r][c] ? 1u << q : 0u;
+  }
+  return m;
+}
+
+// Three steps A -> C for a group of lattice tiles OX x OY (one thread per
+// node). Step n+1 is taken over the group grown by two nodes into LDS, step
+// n+2 over the group grown by one (into registers, then back into the same
+// LDS rows in place), step n+3 over the group into C. The group's edge nodes
+// next to a near tile also give X1 their state n+1 and X2 their state n+2
+// (only the populations the near tile pulls), where the near tiles' second
+// and third steps read them.
+template <typename T, int OX, int OY, int BX, int BY, bool NT>
+__global__ __launch_bounds__(BX *BY) void lbm3_kernel(const T *__restrict__ A, T *__restrict__ C, LbmParams p,
+                                                     const int *__restrict__ map, int count, int tile_x,
+                                                     int tile_y, T *__restrict__ X1, T *__restrict__ X2,
+                                                     const unsigned char *__restrict__ near) {
+  constexpr int RX = OX + 4, RY = OY + 4;  // the group grown by two
+  constexpr int NTH = BX * BY;
+  __shared__ T s_f[9][RY][RX];
+  __shared__ unsigned char s_near[3][8];
+  const int li = p.xcd_remap ? xcd_tile((int)blockIdx.x, count) : (int)blockIdx.x;
+  const int t = map[li];
+  const int tyi = t / p.ntx;
+  const int txi = t - tyi * p.ntx;
+  const int x0 = txi * tile_x, y0 = tyi * tile_y;
+  const int tid = (int)threadIdx.y * BX + (int)threadIdx.x;
+  const int W = OX / tile_x;
+  if (near && tid < 24) {
+    const int r = tid >> 3, c = tid & 7;
+    s_near[r][c] = (c > W + 1 || (r == 1 && c >= 1 && c <= W)) ? 0 : near[(tyi - 1 + r) * p.ntx + txi - 1 + c];
+  }
+  const CollK<T> &K = coll<T>(p);
+  const ForceK<T> &F = gforce<T>(p);
+  bool bad = false;
+  // step n+1 over the grown group: the OX central columns of every row
+  // first (consecutive lanes on consecutive, line-aligned nodes), then the
+  // four edge columns; two nodes per round, loads of both issued first
+  constexpr int TOT = RY * OX + 4 * RY;
+  auto node_of = [&](int k, int &i, int &j) {
+    if (k < RY * OX) {
+      j = k / OX;
+      i = 2 + (k - j * OX);
+    } else {
+      const int e = k - RY * OX;
+      j = e >> 2;
+      const int c = e & 3;
+      i = c < 2 ? c : OX + c;
+    }
+  };
+  for (int k = tid; k < TOT; k += 2 * NTH) {
+    int ia, ja, ib, jb;
+    node_of(k, ia, ja);
+    const bool two = k + NTH < TOT;
+    node_of(two ? k + NTH : k, ib, jb);
+    const unsigned oa = (unsigned)(ja * p.pitch + ia) * (unsigned)sizeof(T);
+    const unsigned ob = (unsigned)(jb * p.pitch + ib) * (unsigned)sizeof(T);
+    T ga[9], gb[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const char *base = reinterpret_cast<const char *>(A + (long long)q * p.plane +
+                                                        (long long)(y0 - 2 - ey(q)) * p.pitch + (x0 - 2 - ex(q)));
+      ga[q] = *reinterpret_cast<const T *>(base + oa);
+      gb[q] = *reinterpret_cast<const T *>(base + ob);
+    }
+    T out[9], rho;
+    collide<T>(ga, F, K, out, rho);
+    bad |= !(rho > (T)0) || !isfinite(rho);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s_f[q][ja][ia] = out[q];
+    if (two) {
+      collide<T>(gb, F, K, out, rho);
+      bad |= !(rho > (T)0) || !isfinite(rho);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) s_f[q][jb][ib] = out[q];
+    }
+  }
+  __syncthreads();
+  const unsigned *nw = reinterpret_cast<const unsigned *>(&s_near[0][0]);
+  const bool ring = near && (nw[0] | nw[1] | nw[2] | nw[3] | nw[4] | nw[5]) != 0;
+  const int sh = __builtin_ctz((unsigned)tile_x);
+  // this thread's node of the group, and its ring directions
+  const int ii = (int)threadIdx.x, jj = (int)threadIdx.y;
+  unsigned rmask = 0;
+  if (ring && (ii == 0 || ii == OX - 1 || jj == 0 || jj == OY - 1)) rmask = ring_mask<OX, OY>(s_near, ii, jj, W, sh);
+  const unsigned off = (unsigned)(jj * p.pitch + ii) * (unsigned)sizeof(T);
+  if (rmask) {
+#pragma unroll
+    for (int q = 1; q < 9; ++q)
+      if (rmask & (1u << q))
+        store_uniform<T, false>(
+            uniform_ptr(reinterpret_cast<char *>(X1 + (long long)q * p.plane + (long long)y0 * p.pitch + x0)), off,
+            s_f[q][jj + 2][ii + 2]);
+  }
+  // step n+2 over the group grown by one (at most two nodes per thread)
+  constexpr int R2X = OX + 2, TOT2 = R2X * (OY + 2);
+  static_assert(TOT2 <= 2 * NTH, "the grown-by-one region takes at most two nodes per thread");
+  T o2a[9], o2b[9];
+  int pa = -1, pb = -1;  // their R1 positions (j * RX + i), -1: none
+  {
+    auto step2 = [&](int k2, T (&o)[9]) {
+      const int j2 = k2 / R2X, i2 = k2 - j2 * R2X;
+      const int i = i2 + 1, j = j2 + 1;
+      T g[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) g[q] = s_f[q][j - ey(q)][i - ex(q)];
+      T rho;
+      collide<T>(g, F, K, o, rho);
+      bad |= !(rho > (T)0) || !isfinite(rho);
+      return j * RX + i;
+    };
+    if (tid < TOT2) pa = step2(tid, o2a);
+    if (tid + NTH < TOT2) pb = step2(tid + NTH, o2b);
+  }
+  __syncthreads();
+  T *sf = &s_f[0][0][0];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    if (pa >= 0) sf[q * RY * RX + pa] = o2a[q];
+    if (pb >= 0) sf[q * RY * RX + pb] = o2b[q];
+  }
+  __syncthreads();
+  // step n+3 on the group's own nodes, pulling state n+2 from LDS
+  {
+    const int i = ii + 2, j = jj + 2;
+    T g[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) g[q] = s_f[q][j - ey(q)][i - ex(q)];
+    T out[9], rho;
+    collide<T>(g, F, K, out, rho);
+    bad |= !(rho > (T)0) || !isfinite(rho);
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+      store_uniform<T, NT>(uniform_ptr(reinterpret_cast<char *>(C + (long long)q * p.plane + (long long)y0 * p.pitch + x0)),
+                           off, out[q]);
+    if (rmask) {
+#pragma unroll
+      for (int q = 1; q < 9; ++q)
+        if (rmask & (1u << q))
+          store_uniform<T, false>(
+              uniform_ptr(reinterpret_cast<char *>(X2 + (long long)q * p.plane + (long long)y0 * p.pitch + x0)), off,
+              s_f[q][j][i]);
+    }
+  }
+  if (bad) p.flag[0] = -1;
+}
+
+template <typename T, int OX, int OY, int BX, int BY, bool NT>
+static hipError_t launch_lbm3_t(const T *A, T *C, const LbmParams &p, const int *map, int count, int tx, int ty,
+                                T *X1, T *X2, const unsigned char *near, hipStream_t s) {
+  if constexpr (lbm3_fits<T, OX, OY>() && BX == OX && BY == OY) {
+    if (count <= 0) return hipSuccess;
+    if (OX % tx != 0 || OX / tx > 4 || OY != ty || (tx & (tx - 1)) != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((lbm3_kernel<T, OX, OY, BX, BY, NT>), dim3(count), dim3(BX, BY), 0, s, A, C, p, map, count,
+                       tx, ty, X1, X2, near);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+static hipError_t launch_lbm3_any(int v, int width, const T *A, T *C, const LbmParams &p, const int *map, int count,
+                                  T *X1, T *X2, const unsigned char *near, hipStream_t s) {
+  int tx, ty;
+  variant_tile(v, &tx, &ty);
+  if (width == 4) {
+    if (tx == 32 && ty == 8) return launch_lbm3_t<T, 128, 8, 128, 8, true>(A, C, p, map, count, tx, ty, X1, X2, near, s);
+    return hipErrorInvalidValue;
+  }
+  if (width == 2) {
+    if (tx == 32 && ty == 8) return launch_lbm3_t<T, 64, 8, 64, 8, true>(A, C, p, map, count, tx, ty, X1, X2, near, s);
+    if (tx == 64 && ty == 4) return launch_lbm3_t<T, 128, 4, 128, 4, true>(A, C, p, map, count, tx, ty, X1, X2, near, s);
+    return hipErrorInvalidValue;
+  }
+#define X(id, bx, by, npt, nt, ntl)                                                                          \
+  if (v == id)                                                                                             \
+    return npt == 1 && width == 1 ? launch_lbm3_t<T, bx, by, bx, by, nt>(A, C, p, map, count, tx, ty, X1, X2, near, s) \
+                                  : hipErrorInvalidValue;
+  BTDF_VARIANTS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_lbm3(int prec, int v, int width, const void *A, void *C, const LbmParams &p, const int *map,
+                       int count, void *X1, void *X2, const unsigned char *near, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (prec == 4)
+    return launch_lbm3_any<float>(v, width, (const float *)A, (float *)C, p, map, count, (float *)X1, (float *)X2,
+                                  near, s);
+  return launch_lbm3_any<double>(v, width, (const double *)A, (double *)C, p, map, count, (double *)X1,
+                                 (double *)X2, near, s);
+}
+
+// whether a launch shape has a three-step pass (width 1), or one over width
+// 2 or 4 of its tiles side by side
+bool variant_has_lbm3(int v, int prec, int width) {
+  int tx, ty;
+  variant_tile(v, &tx, &ty);
+  bool fits = false;
+  if (width == 4) fits = tx == 32 && ty == 8 && (prec == 4 ? lbm3_fits<float, 128, 8>() : lbm3_fits<double, 128, 8>());
+  if (width == 2) {
+    if (tx == 32 && ty == 8) fits = prec == 4 ? lbm3_fits<float, 64, 8>() : lbm3_fits<double, 64, 8>();
+    if (tx == 64 && ty == 4) fits = prec == 4 ? lbm3_fits<float, 128, 4>() : lbm3_fits<double, 128, 4>();
+  }
+  if (width == 1) {
+#define X(id, bx, by, npt, nt, ntl) \
+  if (v == id) fits = npt == 1 && (prec == 4 ? lbm3_fits<float, bx, by>() : lbm3_fits<double, bx, by>());
+    BTDF_VARIANTS(X)
+#undef X
+  }
+  return fits;
+}
+
 // The first step of the ring of every near tile: the nodes one step outside
 // the tile that lie in a two-step tile (plain interior nodes, no
 // immersed-boundary force; a node next to two near tiles is written twice

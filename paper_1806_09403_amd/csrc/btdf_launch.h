@@ -17,6 +17,12 @@ hipError_t launch_rigid_move(const MoveParams &mp, hipStream_t s);
 hipError_t launch_lbm2(int prec, int variant, int width, const void *A, void *C, const LbmParams &p, const int *map,
                        int count, void *X, const unsigned char *near, hipStream_t s);
 bool variant_has_wide_lbm2(int variant, int prec, int width);
+// three steps A -> C over the listed groups of width lattice tiles; with near
+// non-null, edge nodes next to a near tile also store their first and second
+// steps in X1 and X2
+hipError_t launch_lbm3(int prec, int variant, int width, const void *A, void *C, const LbmParams &p, const int *map,
+                       int count, void *X1, void *X2, const unsigned char *near, hipStream_t s);
+bool variant_has_lbm3(int variant, int prec, int width);
 bool variant_has_lbm2(int variant, int prec);
 hipError_t launch_ring(int prec, const void *A, void *X, const LbmParams &p, const int *near_map, int n_near,
                        const unsigned char *near, int tile_x, int tile_y, hipStream_t s);

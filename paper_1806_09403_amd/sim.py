@@ -99,7 +99,7 @@ class Sim:
         return api.btdf_get_marker_data(self._workspace())
 
     def step_timed_split(self, n):
-        """Per-step ms of (marker kernels, single-step lattice kernels, two-step lattice kernel)."""
+        """Per-step ms of (marker kernels, single-step lattice kernels, blocked pass)."""
         return api.btdf_step_timed_split(self._workspace(), n)
 
     @property

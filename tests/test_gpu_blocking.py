@@ -1,7 +1,7 @@
-"""Temporal blocking (two steps per pass for tiles away from the markers
-and the domain edges) gives bit-identical results to single steps, for every
-boundary set, forcing method, precision and launch shape that has the
-two-step kernel."""
+"""Temporal blocking (two or three steps per pass for tiles away from the
+markers and the domain edges) gives bit-identical results to single steps,
+for every boundary set, forcing method, precision and launch shape that has
+the blocked pass."""
 import dataclasses
 
 import numpy as np
@@ -23,6 +23,8 @@ def run(c, blocking, steps, precision=4, options=None, timed=False):
         s.set_option(k, v)
     s.set_option(_lib.OPT_TEMPORAL_BLOCKING, blocking)
     fused = s.get_option(_lib.OPT_FUSED_TILES)
+    if fused:
+        assert s.get_option(_lib.OPT_STEPS_PER_PASS) in ((2, 3) if blocking in (1, 3) else (blocking,))
     for n in steps:
         if timed:
             s.step_timed_split(n)
@@ -46,20 +48,22 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("depth", [2, 3])
 @pytest.mark.parametrize("precision", [4, 8])
 @pytest.mark.parametrize("name,seed,nx,ny,bc", CASES)
-def test_blocked_steps_are_bit_identical(name, seed, nx, ny, bc, precision):
-    log("blocking %s prec=%d" % (name, precision))
+def test_blocked_steps_are_bit_identical(name, seed, nx, ny, bc, precision, depth):
+    log("blocking %s prec=%d depth=%d" % (name, precision, depth))
     c = bodies_case(seed, nx, ny, bc)
-    steps = (1, 2, 7, 20)
+    steps = (1, 2, 7, 20)   # leftovers of every size after whole passes
     ref = run(c, 0, steps, precision)
-    got = run(c, 1, steps, precision)
+    got = run(c, depth, steps, precision)
     assert got[2] > 0 and ref[2] == 0
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
+@pytest.mark.parametrize("depth", [2, 3])
 @pytest.mark.parametrize("opts", ["passes", "implicit", "rkpm", "timed", "overlap", "overlap-timed"])
-def test_blocking_with_other_features(opts):
+def test_blocking_with_other_features(opts, depth):
     """(With the overlap option the two-step pass runs on a second stream and
     the ring kernel, not the pass, gives the near tiles their neighbours'
     first step.)"""
@@ -70,12 +74,13 @@ def test_blocking_with_other_features(opts):
          "overlap-timed": {_lib.OPT_OVERLAP: 1}}[opts]
     timed = opts.endswith("timed")
     ref = run(c, 0, (3, 10), 4, o, timed=timed)
-    got = run(c, 1, (3, 10), 4, o, timed=timed)
+    got = run(c, depth, (3, 10), 4, o, timed=timed)
     assert got[2] > 0
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
-def test_every_launch_shape_with_the_two_step_kernel():
+@pytest.mark.parametrize("depth,min_active", [(2, 10), (3, 6)])
+def test_every_launch_shape_with_the_blocked_pass(depth, min_active):
     from paper_1806_09403_amd import Sim, _lib
     c = bodies_case(46, 520, 260, W.FULLY_PERIODIC)
     ref = run(c, 0, (9,))
@@ -84,10 +89,24 @@ def test_every_launch_shape_with_the_two_step_kernel():
     s.close()
     active = 0
     for v in range(nv):
-        got = run(c, 1, (9,), options={_lib.OPT_LBM_VARIANT: v})
+        got = run(c, depth, (9,), options={_lib.OPT_LBM_VARIANT: v})
         active += got[2] > 0
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), v
-    assert active >= 10
+    log("  %d launch shapes with a pass of depth %d or less" % (active, depth))
+    assert active >= min_active
+
+
+def test_default_depth_is_three_on_the_benchmark_shape():
+    from paper_1806_09403_amd import _lib
+    c = bodies_case(47, 512, 256, W.FULLY_PERIODIC)
+    from paper_1806_09403_amd import Sim
+    for prec in (4, 8):
+        s = Sim.from_case(c, precision=prec)
+        assert s.get_option(_lib.OPT_TEMPORAL_BLOCKING) == 1
+        assert s.get_option(_lib.OPT_STEPS_PER_PASS) == 3
+        s.set_option(_lib.OPT_OVERLAP, 1)      # the overlapped pass is the two-step one
+        assert s.get_option(_lib.OPT_STEPS_PER_PASS) == 2
+        s.close()
 
 
 def test_moving_bodies_step_singly_under_blocking():
