@@ -1181,9 +1181,12 @@ static int enqueue_pair(btdf_t *h, const LbmParams &p, const IbParams &ib, hipSt
 
 // three steps from buffer cur into 1 - cur (three-step blocking): as a pair,
 // with the near tiles' states n+1 and n+2 in X1 and X2 and the marker kernel
-// before each of their steps; the three-step pass runs first and writes both
-// rings. ev: 9 events, the pair's 7 and, after the third marker kernel and
-// after the near tiles' third step, ev[7] and ev[8]; or null.
+// before each of their steps. The three-step pass writes both rings, so it
+// runs before the near tiles' second step; it runs after their first step,
+// whose reads of A bring in the lines the pass's single tiles and pairs
+// (which border near tiles) read for their halos, and these go first.
+// ev: 9 events or null: marker kernel E0-E1, near step E1-E2, pass E5-E6,
+// marker kernel E6-E3, near step E3-E4, marker kernel E4-E7, near step E7-E8.
 static int enqueue_triple(btdf_t *h, const LbmParams &p, const IbParams &ib, hipStream_t s, hipEvent_t *ev) {
   const void *A = h->ws + h->off_pop[h->cur];
   void *B = h->ws + h->off_pop[1 - h->cur];
@@ -1195,14 +1198,14 @@ static int enqueue_triple(btdf_t *h, const LbmParams &p, const IbParams &ib, hip
   if (ev) HIPCHK(hipEventRecord(ev[0], s));
   HIPCHK(launch_ib(h->prec, A, p, ib, s));
   if (ev) HIPCHK(hipEventRecord(ev[1], s));
-  if (ev) HIPCHK(hipEventRecord(ev[5], s));
-  HIPCHK(launch_lbm3(h->prec, h->variant, 4, A, B, p, fm, h->n_quad, X1, X2, near, s));
-  HIPCHK(launch_lbm3(h->prec, h->variant, 2, A, B, p, fm + h->n_quad, h->n_wide, X1, X2, near, s));
-  HIPCHK(launch_lbm3(h->prec, h->variant, 1, A, B, p, fm + h->n_quad + h->n_wide, h->n_fused, X1, X2, near, s));
-  if (ev) HIPCHK(hipEventRecord(ev[6], s));
   HIPCHK(launch_lbm(h->prec, h->variant, A, X1, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, A, X1, p, s));
   if (ev) HIPCHK(hipEventRecord(ev[2], s));
+  if (ev) HIPCHK(hipEventRecord(ev[5], s));
+  HIPCHK(launch_lbm3(h->prec, h->variant, 1, A, B, p, fm + h->n_quad + h->n_wide, h->n_fused, X1, X2, near, s));
+  HIPCHK(launch_lbm3(h->prec, h->variant, 2, A, B, p, fm + h->n_quad, h->n_wide, X1, X2, near, s));
+  HIPCHK(launch_lbm3(h->prec, h->variant, 4, A, B, p, fm, h->n_quad, X1, X2, near, s));
+  if (ev) HIPCHK(hipEventRecord(ev[6], s));
   HIPCHK(launch_ib(h->prec, X1, p, ib, s));
   if (ev) HIPCHK(hipEventRecord(ev[3], s));
   HIPCHK(launch_lbm(h->prec, h->variant, X1, X2, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
@@ -1274,9 +1277,11 @@ static int timed_impl(btdf_t *h, int64_t n, double *out) {
       hipEvent_t *E = &ev[NE * k];
       if (pairs) {
         (void)hipEventElapsedTime(&a, E[0], E[1]);
-        // the near tiles' first step follows the pass unless that runs beside it
-        (void)hipEventElapsedTime(&b, d == 2 && pair_overlap(h) ? E[1] : E[6], E[2]);
-        (void)hipEventElapsedTime(&c, E[2], E[3]);
+        // the near tiles' first step: after the first marker kernel in a
+        // triple or an overlapped pair, else after the pass
+        (void)hipEventElapsedTime(&b, d == 3 || pair_overlap(h) ? E[1] : E[6], E[2]);
+        // the second marker kernel: after the pass in a triple
+        (void)hipEventElapsedTime(&c, d == 3 ? E[6] : E[2], E[3]);
         (void)hipEventElapsedTime(&e4, E[3], E[4]);
         (void)hipEventElapsedTime(&f, E[5], E[6]);
         if (d == 3) {
