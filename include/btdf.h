@@ -107,7 +107,7 @@ extern "C" {
 #define BTDF_OPT_TILE_Y 6        /* read-only: tile height of the current variant */
 #define BTDF_OPT_ROW_PAD 7       /* elements added to each grid row (>= 0); only before the first device use */
 #define BTDF_OPT_PLANE_PAD 8     /* elements added to each population plane, multiple of 64; same restriction */
-#define BTDF_OPT_INTERIOR_PATH 9 /* 1: waves away from every edge load from wave-uniform bases; 0 (default): always the general pull */
+#define BTDF_OPT_INTERIOR_PATH 9 /* 1 (default): waves away from every edge load from wave-uniform bases; 0: always the general pull */
 #define BTDF_OPT_OVERLAP 10      /* 1: marker kernel on a second stream beside the lattice tiles it does not touch; 0 (default): in order */
 #define BTDF_OPT_FORCED_TILES 11 /* read-only: lattice tiles touched by some marker's stencil */
 #define BTDF_OPT_MASK_UNSTABLE 12 /* batches only: 1 (default) = a case that went unstable stops, the others go on */

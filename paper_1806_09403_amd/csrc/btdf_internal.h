@@ -38,7 +38,7 @@ struct btdf_sim {
   // lattice kernel launch shape and tiles
   // launch defaults measured fastest on the 8192^2 particle-laden workload:
   // 32x8 tiles, general pull, marker kernel before the lattice kernel
-  int variant = 6, xcd_remap = 1, graph_chunk = 0, interior = 0;
+  int variant = 6, xcd_remap = 1, graph_chunk = 0, interior = 1;
   int row_pad = 0, plane_pad = 0;
   int row_align = 128;  // bytes; rows start on this boundary (0: packed rows)
   int tile_x = 64, tile_y = 4, ntx = 0, nty = 0;
