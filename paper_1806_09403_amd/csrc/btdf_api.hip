@@ -218,20 +218,27 @@ void fused_lists(btdf_t *h) {
       }
     }
   }
-  // two-step tiles: pairs of side-by-side lattice tiles where the launch
-  // shape has a wide pass (first tile of each pair listed), then the rest
+  // blocked tiles: groups of four, then of two side-by-side lattice tiles
+  // where the launch shape has such a pass (first tile of each group
+  // listed), then the rest. Groups are packed greedily along each row from
+  // any tile column, so a run of L far tiles leaves only L mod 4 of them
+  // outside groups of four.
   std::vector<char> grouped(ntiles, 0);
   for (int w : {4, 2}) {
     const size_t start = h->fmap.size();
     if (has_group(h, d, w))
       for (int b = 0; b < nty; ++b)
-        for (int a = 0; a + w - 1 < ntx; a += w) {
+        for (int a = 0; a + w - 1 < ntx;) {
           const int t = b * ntx + a;
           bool ok = true;
           for (int k = 0; k < w; ++k) ok = ok && !near[t + k] && !grouped[t + k];
-          if (!ok) continue;
+          if (!ok) {
+            ++a;
+            continue;
+          }
           h->fmap.push_back(t);
           for (int k = 0; k < w; ++k) grouped[t + k] = 1;
+          a += w;
         }
     (w == 4 ? h->n_quad : h->n_wide) = (int)(h->fmap.size() - start);
   }
