@@ -1192,8 +1192,12 @@ static int enqueue_pair(btdf_t *h, const LbmParams &p, const IbParams &ib, hipSt
 // runs before the near tiles' second step; it runs after their first step,
 // whose reads of A bring in the lines the pass's single tiles and pairs
 // (which border near tiles) read for their halos, and these go first.
-// ev: 9 events or null: marker kernel E0-E1, near step E1-E2, pass E5-E6,
-// marker kernel E6-E3, near step E3-E4, marker kernel E4-E7, near step E7-E8.
+// With the overlap option the pass runs on the side stream instead, beside
+// the first two marker kernels and the near tiles' first step (none of
+// which needs the rings), and their second step waits for it.
+// ev: 10 events or null: marker kernel E0-E1, near step E1-E2, pass E5-E6,
+// marker kernel E6-E3 (E2-E3 overlapped), near step E3-E4 (E9-E4
+// overlapped, E9 after the wait), marker kernel E4-E7, near step E7-E8.
 static int enqueue_triple(btdf_t *h, const LbmParams &p, const IbParams &ib, hipStream_t s, hipEvent_t *ev) {
   const void *A = h->ws + h->off_pop[h->cur];
   void *B = h->ws + h->off_pop[1 - h->cur];
@@ -1202,19 +1206,41 @@ static int enqueue_triple(btdf_t *h, const LbmParams &p, const IbParams &ib, hip
   const int *fm = h->at<int>(h->off_fmap);
   const unsigned char *near = h->at<unsigned char>(h->off_near);
   const int nb0 = h->n_quad + h->n_wide + h->n_fused;  // the near tiles start here in the map
+  const bool ov = h->overlap != 0;
+  auto pass = [&](hipStream_t st) -> hipError_t {
+    hipError_t e = launch_lbm3(h->prec, h->variant, 1, A, B, p, fm + h->n_quad + h->n_wide, h->n_fused, X1, X2,
+                               near, st);
+    if (e == hipSuccess) e = launch_lbm3(h->prec, h->variant, 2, A, B, p, fm + h->n_quad, h->n_wide, X1, X2, near, st);
+    if (e == hipSuccess) e = launch_lbm3(h->prec, h->variant, 4, A, B, p, fm, h->n_quad, X1, X2, near, st);
+    return e;
+  };
+  if (ov) {
+    int rc = make_side(h);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(h->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+    if (ev) HIPCHK(hipEventRecord(ev[5], h->side));
+    HIPCHK(pass(h->side));
+    if (ev) HIPCHK(hipEventRecord(ev[6], h->side));
+    HIPCHK(hipEventRecord(h->ev_join, h->side));
+  }
   if (ev) HIPCHK(hipEventRecord(ev[0], s));
   HIPCHK(launch_ib(h->prec, A, p, ib, s));
   if (ev) HIPCHK(hipEventRecord(ev[1], s));
   HIPCHK(launch_lbm(h->prec, h->variant, A, X1, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, A, X1, p, s));
   if (ev) HIPCHK(hipEventRecord(ev[2], s));
-  if (ev) HIPCHK(hipEventRecord(ev[5], s));
-  HIPCHK(launch_lbm3(h->prec, h->variant, 1, A, B, p, fm + h->n_quad + h->n_wide, h->n_fused, X1, X2, near, s));
-  HIPCHK(launch_lbm3(h->prec, h->variant, 2, A, B, p, fm + h->n_quad, h->n_wide, X1, X2, near, s));
-  HIPCHK(launch_lbm3(h->prec, h->variant, 4, A, B, p, fm, h->n_quad, X1, X2, near, s));
-  if (ev) HIPCHK(hipEventRecord(ev[6], s));
+  if (!ov) {
+    if (ev) HIPCHK(hipEventRecord(ev[5], s));
+    HIPCHK(pass(s));
+    if (ev) HIPCHK(hipEventRecord(ev[6], s));
+  }
   HIPCHK(launch_ib(h->prec, X1, p, ib, s));
   if (ev) HIPCHK(hipEventRecord(ev[3], s));
+  if (ov) {
+    HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
+    if (ev) HIPCHK(hipEventRecord(ev[9], s));
+  }
   HIPCHK(launch_lbm(h->prec, h->variant, X1, X2, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, X1, X2, p, s));
   if (ev) HIPCHK(hipEventRecord(ev[4], s));
@@ -1246,7 +1272,7 @@ static int timed_impl(btdf_t *h, int64_t n, double *out) {
   if (rc) return rc;
   const LbmParams p = make_params(h);
   const IbParams ib = make_ib(h);
-  const int chunk = 256, NE = 9;  // events per entry
+  const int chunk = 256, NE = 10;  // events per entry
   std::vector<hipEvent_t> ev(NE * chunk, nullptr);
   for (auto &e : ev) HIPCHK(hipEventCreate(&e));
   const bool ov = overlapping(h);
@@ -1287,9 +1313,11 @@ static int timed_impl(btdf_t *h, int64_t n, double *out) {
         // the near tiles' first step: after the first marker kernel in a
         // triple or an overlapped pair, else after the pass
         (void)hipEventElapsedTime(&b, d == 3 || pair_overlap(h) ? E[1] : E[6], E[2]);
-        // the second marker kernel: after the pass in a triple
-        (void)hipEventElapsedTime(&c, d == 3 ? E[6] : E[2], E[3]);
-        (void)hipEventElapsedTime(&e4, E[3], E[4]);
+        // the second marker kernel: after the pass in a triple (unless that
+        // runs beside it); the second near step after the wait for the pass
+        const bool ov3 = d == 3 && h->overlap != 0;
+        (void)hipEventElapsedTime(&c, d == 3 && !ov3 ? E[6] : E[2], E[3]);
+        (void)hipEventElapsedTime(&e4, ov3 ? E[9] : E[3], E[4]);
         (void)hipEventElapsedTime(&f, E[5], E[6]);
         if (d == 3) {
           (void)hipEventElapsedTime(&g, E[4], E[7]);
