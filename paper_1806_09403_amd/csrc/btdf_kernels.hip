@@ -976,10 +976,12 @@ static hipError_t launch_lbm3_any(int v, int width, const T *A, T *C, const LbmP
   variant_tile(v, &tx, &ty);
   if (width == 4) {
     if (tx == 32 && ty == 8) return launch_lbm3_t<T, 128, 8, 128, 8, true>(A, C, p, map, count, tx, ty, X1, X2, near, s);
+    if (tx == 16 && ty == 8) return launch_lbm3_t<T, 64, 8, 64, 8, true>(A, C, p, map, count, tx, ty, X1, X2, near, s);
     return hipErrorInvalidValue;
   }
   if (width == 2) {
     if (tx == 32 && ty == 8) return launch_lbm3_t<T, 64, 8, 64, 8, true>(A, C, p, map, count, tx, ty, X1, X2, near, s);
+    if (tx == 16 && ty == 8) return launch_lbm3_t<T, 32, 8, 32, 8, true>(A, C, p, map, count, tx, ty, X1, X2, near, s);
     if (tx == 64 && ty == 4) return launch_lbm3_t<T, 128, 4, 128, 4, true>(A, C, p, map, count, tx, ty, X1, X2, near, s);
     return hipErrorInvalidValue;
   }
@@ -1008,8 +1010,12 @@ bool variant_has_lbm3(int v, int prec, int width) {
   int tx, ty;
   variant_tile(v, &tx, &ty);
   bool fits = false;
-  if (width == 4) fits = tx == 32 && ty == 8 && (prec == 4 ? lbm3_fits<float, 128, 8>() : lbm3_fits<double, 128, 8>());
+  if (width == 4) {
+    if (tx == 32 && ty == 8) fits = prec == 4 ? lbm3_fits<float, 128, 8>() : lbm3_fits<double, 128, 8>();
+    if (tx == 16 && ty == 8) fits = prec == 4 ? lbm3_fits<float, 64, 8>() : lbm3_fits<double, 64, 8>();
+  }
   if (width == 2) {
+    if (tx == 16 && ty == 8) fits = prec == 4 ? lbm3_fits<float, 32, 8>() : lbm3_fits<double, 32, 8>();
     if (tx == 32 && ty == 8) fits = prec == 4 ? lbm3_fits<float, 64, 8>() : lbm3_fits<double, 64, 8>();
     if (tx == 64 && ty == 4) fits = prec == 4 ? lbm3_fits<float, 128, 4>() : lbm3_fits<double, 128, 4>();
   }
