@@ -267,6 +267,43 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
   const int y = tyi * BY + (int)threadIdx.y;
   const int xb = txi * TX + (int)threadIdx.x;
 
+  // A wave whose nodes and their neighbours need no wrap and no wall takes
+  // the interior path: every pull is one load from a wave-uniform base plus
+  // the lane's byte offset. A wave spans WR rows of the tile (1 if BX >= 64).
+  constexpr int WR = BX >= 64 ? 1 : 64 / BX;
+  constexpr int WX = BX >= 64 ? 64 : BX;
+  const int yw = __builtin_amdgcn_readfirstlane(y - (BX >= 64 ? 0 : ((int)threadIdx.y % WR)));
+  const int xw = __builtin_amdgcn_readfirstlane(BX >= 64 ? txi * TX + ((int)threadIdx.x & ~63) : txi * TX);
+  // (a wave that holds column nx-2 of a channel also writes the outlet ghost)
+  const bool interior = p.interior && yw >= 1 && yw + WR <= p.ny - 1 && xw >= 1 &&
+                        xw + WX + (NPT - 1) * BX <= p.nx - 1 - (p.outlet ? 1 : 0);
+  const unsigned rowoff = (unsigned)(y - yw) * (unsigned)p.pitch;
+
+  // the pulls are issued first, so they are in flight while the tile
+  // gathers its markers' forces
+  T g[NPT][9];
+  bool live[NPT];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int x = xb + k * BX;
+    live[k] = y < p.ny && (interior || (x >= p.i0 && x <= p.i1));
+    if (!live[k]) continue;
+    // byte offset of the node from the wave's first row: one 32-bit register
+    // shared by all loads and stores of the interior path
+    const unsigned xoff = (rowoff + (unsigned)x) * (unsigned)sizeof(T);
+    if (interior) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const char *base = reinterpret_cast<const char *>(A + (long long)q * p.plane +
+                                                          (long long)(yw - ey(q)) * p.pitch - ex(q));
+        g[k][q] = load<T, NTL>(reinterpret_cast<const T *>(base + xoff));
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) g[k][q] = pull<T, NTL>(A, p, q, x, y);
+    }
+  }
+
   T fib_x[NPT], fib_y[NPT];
 #pragma unroll
   for (int k = 0; k < NPT; ++k) fib_x[k] = fib_y[k] = (T)0;
@@ -311,45 +348,19 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
   }
   if (y >= p.ny) return;
 
-  // A wave whose nodes and their neighbours need no wrap and no wall takes
-  // the interior path: every pull is one load from a wave-uniform base plus
-  // the lane's byte offset. A wave spans WR rows of the tile (1 if BX >= 64).
-  constexpr int WR = BX >= 64 ? 1 : 64 / BX;
-  constexpr int WX = BX >= 64 ? 64 : BX;
-  const int yw = __builtin_amdgcn_readfirstlane(y - (BX >= 64 ? 0 : ((int)threadIdx.y % WR)));
-  const int xw = __builtin_amdgcn_readfirstlane(BX >= 64 ? txi * TX + ((int)threadIdx.x & ~63) : txi * TX);
-  // (a wave that holds column nx-2 of a channel also writes the outlet ghost)
-  const bool interior = p.interior && yw >= 1 && yw + WR <= p.ny - 1 && xw >= 1 &&
-                        xw + WX + (NPT - 1) * BX <= p.nx - 1 - (p.outlet ? 1 : 0);
-  const unsigned rowoff = (unsigned)(y - yw) * (unsigned)p.pitch;
-
   const CollK<T> &K = coll<T>(p);
   bool bad = false;
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int x = xb + k * BX;
-    if (!interior && (x < p.i0 || x > p.i1)) continue;
-    T g[9];
-    // byte offset of the node from the wave's first row: one 32-bit register
-    // shared by all loads and stores of the interior path
+    if (!live[k]) continue;
     const unsigned xoff = (rowoff + (unsigned)x) * (unsigned)sizeof(T);
-    if (interior) {
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        const char *base = reinterpret_cast<const char *>(A + (long long)q * p.plane +
-                                                          (long long)(yw - ey(q)) * p.pitch - ex(q));
-        g[q] = load<T, NTL>(reinterpret_cast<const T *>(base + xoff));
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 9; ++q) g[q] = pull<T, NTL>(A, p, q, x, y);
-    }
     T out[9], rho;
     if (forced) {
       const ForceK<T> F = force_terms<T>(K, (T)(p.Gx + (double)fib_x[k]), (T)(p.Gy + (double)fib_y[k]));
-      collide<T>(g, F, K, out, rho);
+      collide<T>(g[k], F, K, out, rho);
     } else {
-      collide<T>(g, gforce<T>(p), K, out, rho);
+      collide<T>(g[k], gforce<T>(p), K, out, rho);
     }
     bad |= !(rho > (T)0) || !isfinite(rho);
     if (interior) {
