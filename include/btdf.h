@@ -108,7 +108,11 @@ extern "C" {
 #define BTDF_OPT_ROW_PAD 7       /* elements added to each grid row (>= 0); only before the first device use */
 #define BTDF_OPT_PLANE_PAD 8     /* elements added to each population plane, multiple of 64; same restriction */
 #define BTDF_OPT_INTERIOR_PATH 9 /* 1 (default): waves away from every edge load from wave-uniform bases; 0: always the general pull */
-#define BTDF_OPT_OVERLAP 10      /* 1: marker kernel on a second stream beside the lattice tiles it does not touch; 0 (default): in order */
+#define BTDF_OPT_OVERLAP 10      /* 1: a second stream (default priority) takes work beside the main one: in
+                                    single steps the marker kernel beside the lattice tiles it does not touch;
+                                    with temporal blocking the blocked pass beside the near tiles' chain (at
+                                    the default depth this selects two steps per pass); 0 (default): in order.
+                                    Results are the same bits either way. */
 #define BTDF_OPT_FORCED_TILES 11 /* read-only: lattice tiles touched by some marker's stencil */
 #define BTDF_OPT_MASK_UNSTABLE 12 /* batches only: 1 (default) = a case that went unstable stops, the others go on */
 #define BTDF_OPT_ROW_ALIGN 13     /* bytes (0 or a power of two 4..4096, default 128): each row starts on this
