@@ -128,10 +128,11 @@ extern "C" {
                                          1 (default): the deepest the launch shape has (3, or 2 when the overlap
                                          option is set or the shape has no three-step pass, as for tiles one or
                                          two rows tall); 2 or 3: that depth where the shape has it, else the
-                                         next lower; 0: off. Takes d-1 more population buffers. Steps run singly
-                                         instead with a graph chunk > 0, with moving bodies, or with a launch
-                                         shape of more than one node per thread; batch cases step singly. A step
-                                         count that is not a multiple of d ends with single steps. */
+                                         next lower; 0: off. Takes d-1 more population buffers. With a graph chunk
+                                         k > 0 a graph holds k / d whole passes. Steps run singly instead with
+                                         moving bodies or with a launch shape of more than one node per thread;
+                                         batch cases step singly. A step count that is not a multiple of d ends
+                                         with single steps. */
 #define BTDF_OPT_FUSED_TILES 17       /* read-only: lattice tiles that take the blocked pass (0 when it is not active) */
 #define BTDF_OPT_STEPS_PER_PASS 18    /* read-only: steps per pass of those tiles (1 when blocking is not active) */
 #define BTDF_OPT_FORCING_PASSES 14 /* NF in 1..64 (default 1): direct-forcing passes per step (Sec. 2.3, eqs 29-31);

@@ -707,6 +707,7 @@ int build_graph(btdf_t *h, const LbmParams &p, const IbParams &ib) {
   int rc = 0;
   for (int k = 0; k < h->graph_chunk && rc == 0; ++k) rc = enqueue_step(h, p, ib, k & 1, h->cap_stream, nullptr);
   hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  h->graph_depth = 1;
   if (rc) {
     if (g) (void)hipGraphDestroy(g);
     return rc;
@@ -1016,6 +1017,7 @@ int btdf_set_marker_velocity(btdf_t *h, int body, const double *uv) {
 }
 
 static int enqueue_pass(btdf_t *h, const LbmParams &p, const IbParams &ib, hipStream_t s, hipEvent_t *ev);
+static int run_blocked(btdf_t *h, const LbmParams &p, const IbParams &ib, int64_t n);
 static bool blocking_active(const btdf_t *h);
 
 // n steps from the current buffer: graphs of graph_chunk steps where they fit
@@ -1029,7 +1031,7 @@ static int run_steps(btdf_t *h, const LbmParams &p, const IbParams &ib, int64_t 
       h->steps++;
       left--;
     }
-    if (!h->graph && (rc = build_graph(h, p, ib))) return rc;
+    if ((!h->graph || h->graph_depth != 1) && (rc = build_graph(h, p, ib))) return rc;
     while (left >= h->graph_chunk) {
       HIPCHK(hipGraphLaunch(h->graph, h->stream));
       left -= h->graph_chunk;
@@ -1103,10 +1105,7 @@ int btdf_step(btdf_t *h, int64_t n) {
   const LbmParams p = make_params(h);
   const IbParams ib = make_ib(h);
   if (blocking_active(h) && n >= h->depth) {
-    const int d = h->depth;
-    for (int64_t k = 0; k < n / d; ++k)
-      if ((rc = enqueue_pass(h, p, ib, h->stream, nullptr))) return rc;
-    if ((n % d) && (rc = run_steps(h, p, ib, n % d))) return rc;
+    if ((rc = run_blocked(h, p, ib, n))) return rc;
   } else if (!h->any_moving()) {
     if ((rc = run_steps(h, p, ib, n))) return rc;
   } else {
@@ -1258,9 +1257,70 @@ static int enqueue_pass(btdf_t *h, const LbmParams &p, const IbParams &ib, hipSt
   return h->depth == 3 ? enqueue_triple(h, p, ib, s, ev) : enqueue_pair(h, p, ib, s, ev);
 }
 
+// a graph of graph_chunk / depth whole passes, starting from buffer 0
+static int build_pass_graph(btdf_t *h, const LbmParams &p, const IbParams &ib, int passes) {
+  drop_graph(h);
+  if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  const int cur = h->cur;
+  const int64_t steps = h->steps;
+  h->cur = 0;
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = 0;
+  for (int k = 0; k < passes && rc == 0; ++k) rc = enqueue_pass(h, p, ib, h->cap_stream, nullptr);
+  hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  h->cur = cur;  // capturing ran nothing
+  h->steps = steps;
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(BTDF_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    h->graph = nullptr;
+    return fail(BTDF_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  h->graph_depth = h->depth;
+  return ok();
+}
+
+// n steps with temporal blocking: whole passes (replayed from graphs of
+// graph_chunk / depth passes when a graph chunk is set), then single steps
+static int run_blocked(btdf_t *h, const LbmParams &p, const IbParams &ib, int64_t n) {
+  const int d = h->depth;
+  const int per = h->graph_chunk / d;  // passes per graph
+  int64_t left = n;
+  int rc;
+  if (per > 0 && left >= (int64_t)per * d + (h->cur ? 1 : 0)) {
+    if (h->cur) {  // graphs start from buffer 0
+      if ((rc = enqueue_step(h, p, ib, h->cur, h->stream, nullptr))) return rc;
+      h->cur ^= 1;
+      h->steps++;
+      left--;
+    }
+    if ((!h->graph || h->graph_depth != d) && (rc = build_pass_graph(h, p, ib, per))) return rc;
+    while (left >= (int64_t)per * d) {
+      HIPCHK(hipGraphLaunch(h->graph, h->stream));
+      left -= (int64_t)per * d;
+      h->steps += (int64_t)per * d;
+      h->cur = per & 1;  // each pass swaps the buffers once
+      if (h->cur) break;
+    }
+  }
+  for (; left >= d; left -= d)
+    if ((rc = enqueue_pass(h, p, ib, h->stream, nullptr))) return rc;
+  for (; left > 0; --left) {
+    if ((rc = enqueue_step(h, p, ib, h->cur, h->stream, nullptr))) return rc;
+    h->cur ^= 1;
+    h->steps++;
+  }
+  return ok();
+}
+
 static bool blocking_active(const btdf_t *h) {
-  return h->depth >= 2 && h->graph_chunk == 0 && h->layout_ok && h->n_quad + h->n_wide + h->n_fused > 0 &&
-         !h->any_moving();
+  return h->depth >= 2 && h->layout_ok && h->n_quad + h->n_wide + h->n_fused > 0 && !h->any_moving();
 }
 
 // per-step means over n timed steps: out[0] marker kernels, out[1] single-step

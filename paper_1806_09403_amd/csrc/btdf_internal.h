@@ -91,6 +91,7 @@ struct btdf_sim {
   bool bodies_dirty = true;  // ring layout on the device predates the body set
   // graph of graph_chunk steps starting from buffer 0
   hipGraphExec_t graph = nullptr;
+  int graph_depth = 0;  // steps per pass the graph was captured with (1: single steps)
   hipStream_t cap_stream = nullptr;
   hipStream_t side = nullptr;            // marker kernel when it overlaps the lattice kernel
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;

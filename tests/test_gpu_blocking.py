@@ -123,3 +123,28 @@ def test_moving_bodies_step_singly_under_blocking():
         outs.append(s.populations())
         s.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("depth,chunk", [(3, 7), (3, 9), (3, 12), (2, 6), (2, 8)])
+def test_blocked_passes_in_graphs(depth, chunk):
+    """Graphs of chunk // depth whole passes (an even or an odd number of
+    passes, so graphs are entered from either buffer, with single steps
+    before and after) give the bits of eager single steps, checked after
+    every call: each call replays the graph one or more times, with the
+    program's own synchronising reads between the calls."""
+    from paper_1806_09403_amd import Sim, _lib
+    log("blocked graphs depth=%d chunk=%d" % (depth, chunk))
+    c = bodies_case(49, 384, 192, W.CHANNEL)
+    ref = Sim.from_case(c, precision=4)
+    ref.set_option(_lib.OPT_TEMPORAL_BLOCKING, 0)
+    got = Sim.from_case(c, precision=4)
+    got.set_option(_lib.OPT_GRAPH_CHUNK, chunk)
+    got.set_option(_lib.OPT_TEMPORAL_BLOCKING, depth)
+    assert got.get_option(_lib.OPT_STEPS_PER_PASS) == depth
+    for n in (1, 25, 2, 30, 19):
+        ref.step(n)
+        got.step(n)
+        assert np.array_equal(got.populations(), ref.populations()), n
+        assert np.array_equal(got.force_history(200), ref.force_history(200)), n
+    ref.close()
+    got.close()
