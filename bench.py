@@ -137,20 +137,28 @@ def bench_batched(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     unstable, _ = b.status()
-    ms_ib, ms_lbm = b.step_timed(200)
+    ms_ib, ms_lbm = b.step_timed(201)
     b_align = b.get_option(_lib.OPT_ROW_ALIGN)
+    depth = b.get_option(_lib.OPT_STEPS_PER_PASS)
+    blocked_nodes = (b.get_option(_lib.OPT_FUSED_TILES) * b.get_option(_lib.OPT_TILE_X) *
+                     b.get_option(_lib.OPT_TILE_Y))
     b.close()
     del b
     traffic = None
+    key = "batched-v%d-a%d%s" % (best, b_align, "-p3" if depth == 3 else "")
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
-            t = json.load(f).get("batched-v%d-a%d" % (best, b_align))
+            t = json.load(f).get(key)
         if t:
-            traffic = round(t["bytes_per_launch"] / (ms_lbm * 1e-3) / 1e9, 1)
+            traffic = round(t["bytes_per_step"] / (ms_lbm * 1e-3) / 1e9, 1)
     stable = [k for k in range(len(cases)) if not unstable[k]]
     nodes = sum(cases[k].nodes for k in stable)
     mlups = nodes * args.batched_steps / wall / 1e6
-    achieved = nodes * 72 / (ms_lbm * 1e-3) / 1e9
+    # algorithmic bytes of the lattice work per step: 72 B per node stepped
+    # singly, 72 / depth per node in the blocked pass (all cases stable)
+    bytes_per_step = 72 * (nodes - blocked_nodes) + 72 / depth * blocked_nodes if len(stable) == len(cases) \
+        else 72 * nodes
+    achieved = bytes_per_step / (ms_lbm * 1e-3) / 1e9
     print("batched: %d of %d cases stable, %.1f MLUPS" % (len(stable), len(cases), mlups), file=sys.stderr, flush=True)
 
     t_seq = 0.0
@@ -174,10 +182,14 @@ def bench_batched(args):
             "speedup_vs_sequential": round(mlups / seq_mlups, 3) if seq_mlups else None,
             "sequential_sample": "each stable case alone, %d graph-replayed steps" % args.seq_steps,
             "lbm_variant": best, "graph_chunk": args.batched_graph_chunk, "row_align": b_align,
+            "steps_per_pass": depth, "blocked_nodes_frac": round(blocked_nodes / nodes, 4),
             "kernel_ms": {"ib_batch_kernel": round(ms_ib, 5), "lbm_batch_kernel": round(ms_lbm, 5)},
+            "kernel_ms_note": "per step; lbm_batch_kernel: the lattice launches of a step (with blocking: the "
+                              "near tiles' steps and the blocked pass, a third of each triple)",
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                         "kernel": "lbm_batch_kernel"}}
+                         "kernel": "lbm_batch_kernel" if depth == 1 else "lbm3_batch_kernel+lbm_batch_kernel",
+                         "bytes_per_step": int(bytes_per_step)}}
 
 
 def bench_adjoint(args):

@@ -127,8 +127,11 @@ extern "C" {
                                          nodes just outside. Results are bit-identical to single steps.
                                          1 (default): the deepest the launch shape has (3, or 2 when the overlap
                                          option is set or the shape has no three-step pass, as for tiles one or
-                                         two rows tall); 2 or 3: that depth where the shape has it, else the
-                                         next lower; 0: off. Takes d-1 more population buffers. With a graph chunk
+                                         two rows tall) on lattices of at least 2^20 nodes (smaller ones step
+                                         singly: the extra launches of a pass outweigh the bytes saved); 2 or 3:
+                                         that depth where the shape has it, else the next lower; 0: off. In a
+                                         batch (btdf_batch_set_option) any nonzero value means three steps per
+                                         pass for every case, default on. Takes d-1 more population buffers. With a graph chunk
                                          k > 0 a graph holds k / d whole passes. Steps run singly instead with
                                          moving bodies or with a launch shape of more than one node per thread;
                                          batch cases step singly. A step count that is not a multiple of d ends

@@ -170,6 +170,9 @@ void cover_lists(const btdf_t *h, std::vector<int> &off, std::vector<int> &list)
 // where it has the two-step pass, else 1 (no blocking)
 int pass_depth(const btdf_t *h) {
   if (!h->tblock) return 1;
+  // by default only lattices large enough that the saved bytes outweigh the
+  // extra launches of a blocked pass (single handles; a batch shares them)
+  if (h->tblock == 1 && !h->owner && (long long)h->nx * h->ny < kBlockMinNodes) return 1;
   const int want = h->tblock == 1 ? (h->overlap ? 2 : 3) : h->tblock;
   if (want >= 3 && variant_has_lbm3(h->variant, h->prec, 1)) return 3;
   if (variant_has_lbm2(h->variant, h->prec)) return 2;
@@ -413,9 +416,9 @@ void compute_layout(btdf_t *h) {
   h->off_near = o;  // one flag per tile
   o = align256(o + (size_t)max_tiles);
   h->off_pop3 = o;  // the near tiles' intermediate states n+1 (and n+2 for three steps)
-  o = align256(o + (h->depth >= 2 ? pop_bytes : 0));
+  o = align256(o + (h->depth >= 2 || h->reserve_pass ? pop_bytes : 0));
   h->off_pop4 = o;
-  o = align256(o + (h->depth >= 3 ? pop_bytes : 0));
+  o = align256(o + (h->depth >= 3 || h->reserve_pass ? pop_bytes : 0));
   // rigid motion: [nb][4] theta vx vy omega, then [nb] moving flags; [nm][2] offsets
   h->off_motion = o;
   o = align256(o + 4 * (size_t)std::max(nb, 1) * sizeof(double) + (size_t)std::max(nb, 1) * sizeof(int));
@@ -1435,7 +1438,7 @@ int btdf_autotune(btdf_t *h, int64_t steps_per_trial, int *best_variant) {
     for (int in = 0; in < 2; ++in) {
       if (h->variant != v) {
         h->variant = v;
-        h->layout_ok = false;  // the workspace size does not depend on the launch shape
+        h->layout_ok = false;  // (a shape that needs a larger workspace moves the state into one)
       }
       h->interior = in;
       drop_graph(h);

@@ -36,6 +36,11 @@ struct btdf_batch {
   bool layout_ok = false, device_ok = false;
   // launch options
   int variant = 6, xcd_remap = 1, mask = 1, graph_chunk = 0, interior = 0, row_align = 128;
+  int tblock = 1;        // option: three steps per pass for the cases' tiles away from their bodies
+  bool blocked = false;  // it is on (the launch shape has the three-step pass)
+  BatchMap map_near{};   // the near tiles of every case (and the body reductions)
+  const int *g_case[3] = {nullptr, nullptr, nullptr}, *g_tile[3] = {nullptr, nullptr, nullptr};
+  int g_count[3] = {0, 0, 0};  // groups of 4, 2 and 1 tiles of every case
   hipGraphExec_t graph = nullptr;
   hipStream_t cap_stream = nullptr;
   // time
@@ -56,11 +61,15 @@ void batch_drop_graph(btdf_batch_t *b) {
 void batch_layout(btdf_batch_t *b) {
   const int K = (int)b->cases.size();
   long long max_tiles = 0, bodies = 0, mblk = 0;
+  b->blocked = b->tblock && variant_has_lbm3(b->variant, b->prec, 1);
   for (btdf_t *h : b->cases) {
     h->variant = b->variant;
     h->xcd_remap = b->xcd_remap;
     h->interior = b->interior;
     h->row_align = b->row_align;
+    h->tblock = b->blocked ? 3 : 0;  // each case's near tiles, groups and extra buffers
+    h->reserve_pass = b->tblock != 0;  // slices keep their size across launch shapes
+    h->overlap = 0;
     compute_layout(h);
     long long mt = 0;
     for (int v = 0; v < num_variants(); ++v) {
@@ -76,7 +85,8 @@ void batch_layout(btdf_batch_t *b) {
   b->off_desc = o;
   o = align256(o + (size_t)K * sizeof(CaseDesc));
   b->off_maps = o;
-  o = align256(o + (size_t)(2 * max_tiles + 2 * bodies + 2 * mblk + 6) * sizeof(int));
+  // tile maps, near-tile maps and group maps (each at most two ints per tile), body and marker maps
+  o = align256(o + (size_t)(6 * max_tiles + 2 * bodies + 2 * mblk + 16) * sizeof(int));
   b->case_off.assign(K, 0);
   for (int c = 0; c < K; ++c) {
     b->case_off[c] = o;
@@ -134,16 +144,34 @@ int batch_ensure(btdf_batch_t *b) {
     // case table
     std::vector<CaseDesc> desc(K);
     std::vector<int> tile_case, tile_local, body_case, body_local, mblk_case, mblk_first;
+    std::vector<int> near_case, near_local, gc[3], gt[3];
     for (int c = 0; c < K; ++c) {
       btdf_t *h = b->cases[c];
       desc[c].p = make_params(h);
       desc[c].ib = make_ib(h);
       desc[c].pop[0] = h->ws + h->off_pop[0];
       desc[c].pop[1] = h->ws + h->off_pop[1];
+      desc[c].pop[2] = h->ws + h->off_pop3;
+      desc[c].pop[3] = h->ws + h->off_pop4;
+      desc[c].near = h->at<unsigned char>(h->off_near);
       const int nt = h->ntx * h->nty;
       for (int t = 0; t < nt; ++t) {
         tile_case.push_back(c);
         tile_local.push_back(t);
+      }
+      if (b->blocked) {
+        // the case's map: groups of four, of two, single tiles, then near tiles
+        const int n[3] = {h->n_quad, h->n_wide, h->n_fused};
+        int k = 0;
+        for (int w = 0; w < 3; ++w)
+          for (int i = 0; i < n[w]; ++i, ++k) {
+            gc[w].push_back(c);
+            gt[w].push_back(h->fmap[k]);
+          }
+        for (int i = 0; i < h->n_near; ++i, ++k) {
+          near_case.push_back(c);
+          near_local.push_back(h->fmap[k]);
+        }
       }
       for (int bb = 0; bb < h->nb(); ++bb) {
         body_case.push_back(c);
@@ -171,14 +199,30 @@ int batch_ensure(btdf_batch_t *b) {
     int rc;
     if ((rc = put(tile_case, &b->map.tile_case)) || (rc = put(tile_local, &b->map.tile_local)) ||
         (rc = put(body_case, &b->map.body_case)) || (rc = put(body_local, &b->map.body_local)) ||
-        (rc = put(mblk_case, &b->map.mblk_case)) || (rc = put(mblk_first, &b->map.mblk_first)))
+        (rc = put(mblk_case, &b->map.mblk_case)) || (rc = put(mblk_first, &b->map.mblk_first)) ||
+        (rc = put(near_case, &b->map_near.tile_case)) || (rc = put(near_local, &b->map_near.tile_local)))
       return rc;
+    for (int w = 0; w < 3; ++w) {
+      if ((rc = put(gc[w], &b->g_case[w])) || (rc = put(gt[w], &b->g_tile[w]))) return rc;
+      b->g_count[w] = (int)gc[w].size();
+    }
     HIPCHK(hipStreamSynchronize(b->stream));  // the host vectors go out of scope
     b->map.ntiles = b->ntiles;
     b->map.nbodies = b->nbodies;
     b->map.nmblk = b->nmblk;
     b->map.xcd_remap = b->xcd_remap;
     b->map.mask_unstable = b->mask;
+    // the near tiles' steps: their own tile maps, the same body and marker maps
+    const BatchMap full = b->map;
+    b->map_near.body_case = full.body_case;
+    b->map_near.body_local = full.body_local;
+    b->map_near.mblk_case = full.mblk_case;
+    b->map_near.mblk_first = full.mblk_first;
+    b->map_near.ntiles = (int)near_case.size();
+    b->map_near.nbodies = full.nbodies;
+    b->map_near.nmblk = full.nmblk;
+    b->map_near.xcd_remap = full.xcd_remap;
+    b->map_near.mask_unstable = full.mask_unstable;
     b->device_ok = true;
     batch_drop_graph(b);
   }
@@ -189,17 +233,65 @@ struct BatchEvents {
   hipEvent_t e0, e1, e2;
 };
 
-int batch_enqueue(btdf_batch_t *b, int parity, hipStream_t s, const BatchEvents *te) {
-  const CaseDesc *desc = reinterpret_cast<const CaseDesc *>(b->ws + b->off_desc);
-  if (te) HIPCHK(hipEventRecord(te->e0, s));
-  HIPCHK(launch_ib_batch(b->prec, desc, b->map, parity, s));
-  if (te) HIPCHK(hipEventRecord(te->e1, s));
-  HIPCHK(launch_lbm_batch(b->prec, b->variant, desc, b->map, parity, s));
-  if (te) HIPCHK(hipEventRecord(te->e2, s));
+bool batch_has_conv(const btdf_batch_t *b) {
   bool conv = false;
   for (const btdf_t *c : b->cases) conv |= c->bc[1] == BTDF_CONVECTIVE_OUTLET;
-  if (conv) HIPCHK(launch_conv_outlet_batch(b->prec, desc, (int)b->cases.size(), b->mask, parity, s));
+  return conv;
+}
+
+int batch_enqueue(btdf_batch_t *b, int parity, hipStream_t s, const BatchEvents *te) {
+  const CaseDesc *desc = reinterpret_cast<const CaseDesc *>(b->ws + b->off_desc);
+  const int rt = route(parity, parity ^ 1);
+  if (te) HIPCHK(hipEventRecord(te->e0, s));
+  HIPCHK(launch_ib_batch(b->prec, desc, b->map, rt, s));
+  if (te) HIPCHK(hipEventRecord(te->e1, s));
+  HIPCHK(launch_lbm_batch(b->prec, b->variant, desc, b->map, rt, s));
+  if (te) HIPCHK(hipEventRecord(te->e2, s));
+  if (batch_has_conv(b)) HIPCHK(launch_conv_outlet_batch(b->prec, desc, (int)b->cases.size(), b->mask, rt, s));
   return ok();
+}
+
+// Three steps of every case (temporal blocking), from buffer parity into the
+// other: each case's near tiles step singly through its buffers 2 and 3 with
+// the marker kernel before each step, and the three-step pass over every
+// case's other tiles runs after their first step and before their second
+// (it writes the states they pull from just outside). ev: 8 events or null,
+// around the marker kernels (e0-e1, e4-e5, e6-e7 with e3-e4 the pass) and the
+// near steps (e1-e2, e5-e6, e7-e8 in the pairs listed).
+int batch_enqueue_triple(btdf_batch_t *b, int parity, hipStream_t s, hipEvent_t *ev) {
+  const CaseDesc *desc = reinterpret_cast<const CaseDesc *>(b->ws + b->off_desc);
+  const int A = parity, B = parity ^ 1, K = (int)b->cases.size();
+  const bool conv = batch_has_conv(b);
+  auto rec = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
+  auto near_step = [&](int src, int dst) -> int {
+    HIPCHK(launch_lbm_batch(b->prec, b->variant, desc, b->map_near, route(src, dst), s));
+    if (conv) HIPCHK(launch_conv_outlet_batch(b->prec, desc, K, b->mask, route(src, dst), s));
+    return ok();
+  };
+  int rc;
+  HIPCHK(rec(0));
+  HIPCHK(launch_ib_batch(b->prec, desc, b->map, route(A, A), s));
+  HIPCHK(rec(1));
+  if ((rc = near_step(A, 2))) return rc;
+  HIPCHK(rec(2));
+  for (int w : {2, 1, 0})  // single tiles, pairs, then groups of four
+    HIPCHK(launch_lbm3_batch(b->prec, b->variant, w == 0 ? 4 : (w == 1 ? 2 : 1), desc, b->g_case[w], b->g_tile[w],
+                             b->g_count[w], route(A, B), b->mask, b->xcd_remap, s));
+  HIPCHK(rec(3));
+  HIPCHK(launch_ib_batch(b->prec, desc, b->map, route(2, 2), s));
+  HIPCHK(rec(4));
+  if ((rc = near_step(2, 3))) return rc;
+  HIPCHK(rec(5));
+  HIPCHK(launch_ib_batch(b->prec, desc, b->map, route(3, 3), s));
+  HIPCHK(rec(6));
+  if ((rc = near_step(3, B))) return rc;
+  HIPCHK(rec(7));
+  return ok();
+}
+
+// one unit of the batch's stepping: a step, or three with temporal blocking
+int batch_unit(btdf_batch_t *b, int parity, hipStream_t s) {
+  return b->blocked ? batch_enqueue_triple(b, parity, s, nullptr) : batch_enqueue(b, parity, s, nullptr);
 }
 
 // keep every case's host view (buffer parity, step count) in step with the batch
@@ -218,7 +310,8 @@ int batch_build_graph(btdf_batch_t *b) {
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
   int rc = 0;
-  for (int k = 0; k < b->graph_chunk && rc == 0; ++k) rc = batch_enqueue(b, k & 1, b->cap_stream, nullptr);
+  const int units = b->graph_chunk / (b->blocked ? 3 : 1);
+  for (int k = 0; k < units && rc == 0; ++k) rc = batch_unit(b, k & 1, b->cap_stream);
   hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
   if (rc) {
     if (g) (void)hipGraphDestroy(g);
@@ -237,15 +330,21 @@ int batch_build_graph(btdf_batch_t *b) {
 int batch_step_timed_impl(btdf_batch_t *b, int64_t n, double *ms_ib, double *ms_lbm) {
   int rc = batch_ensure(b);
   if (rc) return rc;
-  const int chunk = 256;
-  std::vector<hipEvent_t> ev(3 * chunk, nullptr);
+  const int chunk = 256, NE = 8;  // events per entry
+  std::vector<hipEvent_t> ev(NE * chunk, nullptr);
   for (auto &e : ev) HIPCHK(hipEventCreate(&e));
   double tib = 0.0, tlbm = 0.0;
   int64_t done = 0;
   while (done < n && rc == 0) {
-    const int m = (int)std::min<int64_t>(chunk, n - done);
+    const bool tri = b->blocked && n - done >= 3;  // triples while three steps are left
+    const int m = (int)std::min<int64_t>(chunk, tri ? (n - done) / 3 : n - done);
     for (int k = 0; k < m && rc == 0; ++k) {
-      const BatchEvents te{ev[3 * k], ev[3 * k + 1], ev[3 * k + 2]};
+      if (tri) {
+        rc = batch_enqueue_triple(b, b->cur, b->stream, &ev[NE * k]);
+        if (rc == 0) batch_advance(b, 3);
+        continue;
+      }
+      const BatchEvents te{ev[NE * k], ev[NE * k + 1], ev[NE * k + 2]};
       rc = batch_enqueue(b, b->cur, b->stream, &te);
       if (rc == 0) batch_advance(b, 1);
     }
@@ -256,13 +355,21 @@ int batch_step_timed_impl(btdf_batch_t *b, int64_t n, double *ms_ib, double *ms_
       break;
     }
     for (int k = 0; k < m; ++k) {
-      float x = 0.f, y = 0.f;
-      (void)hipEventElapsedTime(&x, ev[3 * k], ev[3 * k + 1]);
-      (void)hipEventElapsedTime(&y, ev[3 * k + 1], ev[3 * k + 2]);
-      tib += x;
-      tlbm += y;
+      hipEvent_t *E = &ev[NE * k];
+      auto dt = [&](int i, int j) {
+        float x = 0.f;
+        (void)hipEventElapsedTime(&x, E[i], E[j]);
+        return (double)x;
+      };
+      if (tri) {  // marker kernels; near steps and the pass
+        tib += dt(0, 1) + dt(3, 4) + dt(5, 6);
+        tlbm += dt(1, 2) + dt(2, 3) + dt(4, 5) + dt(6, 7);
+      } else {
+        tib += dt(0, 1);
+        tlbm += dt(1, 2);
+      }
     }
-    done += m;
+    done += tri ? 3 * (int64_t)m : m;
   }
   for (auto &e : ev)
     if (e) (void)hipEventDestroy(e);
@@ -393,19 +500,25 @@ int btdf_batch_step(btdf_batch_t *b, int64_t n) {
   int rc = batch_ensure(b);
   if (rc) return rc;
   int64_t left = n;
-  if (b->graph_chunk > 0 && left >= b->graph_chunk + (b->cur ? 1 : 0)) {
+  const int d = b->blocked ? 3 : 1;       // steps per unit
+  const int64_t g = (int64_t)(b->graph_chunk / d) * d;  // steps per graph: whole units
+  if (g > 0 && left >= g + (b->cur ? 1 : 0)) {
     if (b->cur) {  // graphs start from buffer 0
       if ((rc = batch_enqueue(b, b->cur, b->stream, nullptr))) return rc;
       batch_advance(b, 1);
       left--;
     }
     if (!b->graph && (rc = batch_build_graph(b))) return rc;
-    while (left >= b->graph_chunk) {
+    while (left >= g) {
       HIPCHK(hipGraphLaunch(b->graph, b->stream));
-      left -= b->graph_chunk;
-      batch_advance(b, b->graph_chunk);
+      left -= g;
+      batch_advance(b, g);  // each unit swaps the buffers once, as g steps of an odd unit do
       if (b->cur) break;
     }
+  }
+  for (; d > 1 && left >= d; left -= d) {
+    if ((rc = batch_enqueue_triple(b, b->cur, b->stream, nullptr))) return rc;
+    batch_advance(b, d);
   }
   for (; left > 0; --left) {
     if ((rc = batch_enqueue(b, b->cur, b->stream, nullptr))) return rc;
@@ -446,7 +559,7 @@ int btdf_batch_set_option(btdf_batch_t *b, int key, int64_t value) {
       if (value < 0 || value >= num_variants()) return fail(BTDF_EINVAL, "variant %lld out of range", (long long)value);
       if (value != b->variant) {
         b->variant = (int)value;
-        b->layout_ok = false;  // case slices keep their size: only the tile lists change
+        b->layout_ok = false;  // the tile lists change, and with blocking the slice sizes
       }
       return ok();
     case BTDF_OPT_GRAPH_CHUNK:
@@ -477,6 +590,13 @@ int btdf_batch_set_option(btdf_batch_t *b, int key, int64_t value) {
       b->mask = (int)value;
       b->device_ok = false;
       return ok();
+    case BTDF_OPT_TEMPORAL_BLOCKING:
+      if (value < 0 || value > 3) return fail(BTDF_EINVAL, "temporal blocking must be 0 (off), 1 (deepest), 2 or 3");
+      if ((value != 0) != (b->tblock != 0)) {
+        b->tblock = value != 0;  // batches block three steps per pass or not at all
+        b->layout_ok = false;    // every case's lists and slice size
+      }
+      return ok();
     default: return fail(BTDF_EINVAL, "unknown or read-only batch option %d", key);
   }
 }
@@ -491,6 +611,24 @@ int btdf_batch_get_option(const btdf_batch_t *b, int key, int64_t *value) {
     case BTDF_OPT_INTERIOR_PATH: *value = b->interior; return ok();
     case BTDF_OPT_MASK_UNSTABLE: *value = b->mask; return ok();
     case BTDF_OPT_ROW_ALIGN: *value = b->row_align; return ok();
+    case BTDF_OPT_TEMPORAL_BLOCKING: *value = b->tblock; return ok();
+    case BTDF_OPT_TILE_X:
+    case BTDF_OPT_TILE_Y: {
+      int tx, ty;
+      variant_tile(b->variant, &tx, &ty);
+      *value = key == BTDF_OPT_TILE_X ? tx : ty;
+      return ok();
+    }
+    case BTDF_OPT_FUSED_TILES:  // lattice tiles of all cases in the blocked pass
+      if (!b->layout_ok) batch_layout(const_cast<btdf_batch_t *>(b));
+      *value = 0;
+      if (b->blocked)
+        for (const btdf_t *h : b->cases) *value += 4 * h->n_quad + 2 * h->n_wide + h->n_fused;
+      return ok();
+    case BTDF_OPT_STEPS_PER_PASS:
+      if (!b->layout_ok) batch_layout(const_cast<btdf_batch_t *>(b));
+      *value = b->blocked ? 3 : 1;
+      return ok();
     default: return fail(BTDF_EINVAL, "unknown batch option %d", key);
   }
 }

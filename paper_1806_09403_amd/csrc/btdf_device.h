@@ -257,8 +257,14 @@ struct IbParams {
 struct CaseDesc {
   LbmParams p;
   IbParams ib;
-  void *pop[2];
+  void *pop[4];                // the two ping-pong buffers, then the near tiles' states n+1 and n+2 (blocking)
+  const unsigned char *near;   // per lattice tile: 1 if it steps singly (blocking)
 };
+
+// a batch launch's source and destination buffers (indices into CaseDesc::pop)
+__host__ __device__ inline int route(int src, int dst) { return src | (dst << 2); }
+__host__ __device__ inline int route_src(int r) { return r & 3; }
+__host__ __device__ inline int route_dst(int r) { return r >> 2; }
 
 // the adjoint (reverse) step: its own 64 x 4 tiling of the lattice with the
 // markers binned per tile

@@ -417,7 +417,7 @@ __global__ __launch_bounds__(BX *BY) void lbm_kernel(const T *__restrict__ A, T 
 
 template <typename T, int BX, int BY, int NPT, bool NT, bool NTL>
 __global__ __launch_bounds__(BX *BY) void lbm_batch_kernel(const CaseDesc *__restrict__ cases, BatchMap m,
-                                                           int parity) {
+                                                           int rt) {
   if ((int)blockIdx.x >= m.ntiles) {  // one body each
     const int gb = (int)blockIdx.x - m.ntiles;
     const CaseDesc &cd = cases[m.body_case[gb]];
@@ -431,21 +431,21 @@ __global__ __launch_bounds__(BX *BY) void lbm_batch_kernel(const CaseDesc *__res
   // the case's parameters are copied once into registers, as a kernel
   // argument would be, rather than re-read through the table
   const LbmParams p = cases[c].p;
-  const T *A = reinterpret_cast<const T *>(cases[c].pop[parity]);
-  T *B = reinterpret_cast<T *>(cases[c].pop[parity ^ 1]);
+  const T *A = reinterpret_cast<const T *>(cases[c].pop[route_src(rt)]);
+  T *B = reinterpret_cast<T *>(cases[c].pop[route_dst(rt)]);
   if (m.mask_unstable && p.flag[0] != 0) return;  // an unstable case stops; the others go on
   lbm_tile<T, BX, BY, NPT, NT, NTL>(A, B, p, t);
   if (t == 0 && threadIdx.x == 0 && threadIdx.y == 0) p.step_ctr[0] = p.step_ctr[0] + 1;
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void ib_batch_kernel(const CaseDesc *__restrict__ cases, BatchMap m, int parity) {
+__global__ __launch_bounds__(256) void ib_batch_kernel(const CaseDesc *__restrict__ cases, BatchMap m, int rt) {
   const int blk = m.xcd_remap ? xcd_tile((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
   const int c = m.mblk_case[blk];
   const int first = m.mblk_first[blk];
   const LbmParams p = cases[c].p;
   const IbParams ib = cases[c].ib;
-  const T *A = reinterpret_cast<const T *>(cases[c].pop[parity]);
+  const T *A = reinterpret_cast<const T *>(cases[c].pop[route_src(rt)]);
   if (m.mask_unstable && p.flag[0] != 0) return;
   if (first == 0 && threadIdx.x == 0) ib.slot[0] = (int)(p.step_ctr[0] % ib.hist_cap);
   const int l = first + ((int)threadIdx.x >> 4);
@@ -832,16 +832,13 @@ __device__ __forceinline__ unsigned ring_mask(const unsigned char (&s_near)[3][8
 // (only the populations the near tile pulls), where the near tiles' second
 // and third steps read them.
 template <typename T, int OX, int OY, int BX, int BY, bool NT>
-__global__ __launch_bounds__(BX *BY) void lbm3_kernel(const T *__restrict__ A, T *__restrict__ C, LbmParams p,
-                                                     const int *__restrict__ map, int count, int tile_x,
-                                                     int tile_y, T *__restrict__ X1, T *__restrict__ X2,
-                                                     const unsigned char *__restrict__ near) {
+__device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restrict__ C, const LbmParams &p, int t,
+                                           int tile_x, int tile_y, T *__restrict__ X1, T *__restrict__ X2,
+                                           const unsigned char *__restrict__ near) {
   constexpr int RX = OX + 4, RY = OY + 4;  // the group grown by two
   constexpr int NTH = BX * BY;
   __shared__ T s_f[9][RY][RX];
   __shared__ unsigned char s_near[3][8];
-  const int li = p.xcd_remap ? xcd_tile((int)blockIdx.x, count) : (int)blockIdx.x;
-  const int t = map[li];
   const int tyi = t / p.ntx;
   const int txi = t - tyi * p.ntx;
   const int x0 = txi * tile_x, y0 = tyi * tile_y;
@@ -964,6 +961,79 @@ __global__ __launch_bounds__(BX *BY) void lbm3_kernel(const T *__restrict__ A, T
     }
   }
   if (bad) p.flag[0] = -1;
+}
+
+template <typename T, int OX, int OY, int BX, int BY, bool NT>
+__global__ __launch_bounds__(BX *BY) void lbm3_kernel(const T *__restrict__ A, T *__restrict__ C, LbmParams p,
+                                                     const int *__restrict__ map, int count, int tile_x,
+                                                     int tile_y, T *__restrict__ X1, T *__restrict__ X2,
+                                                     const unsigned char *__restrict__ near) {
+  const int li = p.xcd_remap ? xcd_tile((int)blockIdx.x, count) : (int)blockIdx.x;
+  lbm3_group<T, OX, OY, BX, BY, NT>(A, C, p, map[li], tile_x, tile_y, X1, X2, near);
+}
+
+// batches: groups of every case in one launch (a case and its group's first
+// tile per workgroup), the buffers and near flags from the case table
+template <typename T, int OX, int OY, int BX, int BY, bool NT>
+__global__ __launch_bounds__(BX *BY) void lbm3_batch_kernel(const CaseDesc *__restrict__ cases,
+                                                           const int *__restrict__ gcase,
+                                                           const int *__restrict__ gtile, int count, int rt,
+                                                           int mask_unstable, int xcd_remap, int tile_x,
+                                                           int tile_y) {
+  const int li = xcd_remap ? xcd_tile((int)blockIdx.x, count) : (int)blockIdx.x;
+  const int c = gcase[li];
+  const LbmParams p = cases[c].p;
+  if (mask_unstable && p.flag[0] != 0) return;  // the whole workgroup: an unstable case stops
+  lbm3_group<T, OX, OY, BX, BY, NT>(reinterpret_cast<const T *>(cases[c].pop[route_src(rt)]),
+                                    reinterpret_cast<T *>(cases[c].pop[route_dst(rt)]), p, gtile[li], tile_x, tile_y,
+                                    reinterpret_cast<T *>(cases[c].pop[2]), reinterpret_cast<T *>(cases[c].pop[3]),
+                                    cases[c].near);
+}
+
+template <typename T, int OX, int OY, int BX, int BY, bool NT>
+static hipError_t launch_lbm3_batch_t(const CaseDesc *cases, const int *gcase, const int *gtile, int count, int rt,
+                                      int mask, int xcd, int tx, int ty, hipStream_t s) {
+  if constexpr (lbm3_fits<T, OX, OY>() && BX == OX && BY == OY) {
+    if (count <= 0) return hipSuccess;
+    if (OX % tx != 0 || OX / tx > 4 || OY != ty || (tx & (tx - 1)) != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((lbm3_batch_kernel<T, OX, OY, BX, BY, NT>), dim3(count), dim3(BX, BY), 0, s, cases, gcase,
+                       gtile, count, rt, mask, xcd, tx, ty);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+static hipError_t launch_lbm3_batch_any(int v, int width, const CaseDesc *cases, const int *gcase, const int *gtile,
+                                        int count, int rt, int mask, int xcd, hipStream_t s) {
+  int tx, ty;
+  variant_tile(v, &tx, &ty);
+#define ARGS cases, gcase, gtile, count, rt, mask, xcd, tx, ty, s
+  if (width == 4) {
+    if (tx == 32 && ty == 8) return launch_lbm3_batch_t<T, 128, 8, 128, 8, true>(ARGS);
+    if (tx == 16 && ty == 8) return launch_lbm3_batch_t<T, 64, 8, 64, 8, true>(ARGS);
+    return hipErrorInvalidValue;
+  }
+  if (width == 2) {
+    if (tx == 32 && ty == 8) return launch_lbm3_batch_t<T, 64, 8, 64, 8, true>(ARGS);
+    if (tx == 16 && ty == 8) return launch_lbm3_batch_t<T, 32, 8, 32, 8, true>(ARGS);
+    if (tx == 64 && ty == 4) return launch_lbm3_batch_t<T, 128, 4, 128, 4, true>(ARGS);
+    return hipErrorInvalidValue;
+  }
+#define X(id, bx, by, npt, nt, ntl) \
+  if (v == id) return npt == 1 && width == 1 ? launch_lbm3_batch_t<T, bx, by, bx, by, nt>(ARGS) : hipErrorInvalidValue;
+  BTDF_VARIANTS(X)
+#undef X
+#undef ARGS
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_lbm3_batch(int prec, int v, int width, const CaseDesc *cases, const int *gcase, const int *gtile,
+                             int count, int rt, int mask, int xcd, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (prec == 4) return launch_lbm3_batch_any<float>(v, width, cases, gcase, gtile, count, rt, mask, xcd, s);
+  return launch_lbm3_batch_any<double>(v, width, cases, gcase, gtile, count, rt, mask, xcd, s);
 }
 
 template <typename T, int OX, int OY, int BX, int BY, bool NT>
@@ -1109,11 +1179,11 @@ bool variant_has_lbm2(int v, int prec) {
 }
 
 template <typename T>
-static hipError_t launch_lbm_batch_any(int v, const CaseDesc *cases, const BatchMap &m, int parity, hipStream_t s) {
+static hipError_t launch_lbm_batch_any(int v, const CaseDesc *cases, const BatchMap &m, int rt, hipStream_t s) {
 #define X(id, bx, by, npt, nt, ntl)                                                                          \
   if (v == id) {                                                                                           \
     hipLaunchKernelGGL((lbm_batch_kernel<T, bx, by, npt, nt, ntl>), dim3(m.ntiles + m.nbodies), dim3(bx, by), \
-                       0, s, cases, m, parity);                                                            \
+                       0, s, cases, m, rt);                                                                \
     return hipGetLastError();                                                                              \
   }
   BTDF_VARIANTS(X)
@@ -1121,18 +1191,18 @@ static hipError_t launch_lbm_batch_any(int v, const CaseDesc *cases, const Batch
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_lbm_batch(int prec, int v, const CaseDesc *cases, const BatchMap &m, int parity, hipStream_t s) {
+hipError_t launch_lbm_batch(int prec, int v, const CaseDesc *cases, const BatchMap &m, int rt, hipStream_t s) {
   if (m.ntiles + m.nbodies <= 0) return hipSuccess;
-  if (prec == 4) return launch_lbm_batch_any<float>(v, cases, m, parity, s);
-  return launch_lbm_batch_any<double>(v, cases, m, parity, s);
+  if (prec == 4) return launch_lbm_batch_any<float>(v, cases, m, rt, s);
+  return launch_lbm_batch_any<double>(v, cases, m, rt, s);
 }
 
-hipError_t launch_ib_batch(int prec, const CaseDesc *cases, const BatchMap &m, int parity, hipStream_t s) {
+hipError_t launch_ib_batch(int prec, const CaseDesc *cases, const BatchMap &m, int rt, hipStream_t s) {
   if (m.nmblk <= 0) return hipSuccess;
   if (prec == 4)
-    hipLaunchKernelGGL(ib_batch_kernel<float>, dim3(m.nmblk), dim3(256), 0, s, cases, m, parity);
+    hipLaunchKernelGGL(ib_batch_kernel<float>, dim3(m.nmblk), dim3(256), 0, s, cases, m, rt);
   else
-    hipLaunchKernelGGL(ib_batch_kernel<double>, dim3(m.nmblk), dim3(256), 0, s, cases, m, parity);
+    hipLaunchKernelGGL(ib_batch_kernel<double>, dim3(m.nmblk), dim3(256), 0, s, cases, m, rt);
   return hipGetLastError();
 }
 
@@ -1162,11 +1232,11 @@ __global__ __launch_bounds__(256) void conv_outlet_kernel(const T *__restrict__ 
 // batches: one workgroup per case, cases without a convective outlet (or stopped) return
 template <typename T>
 __global__ __launch_bounds__(256) void conv_outlet_batch_kernel(const CaseDesc *__restrict__ cases, int mask_unstable,
-                                                                int parity) {
+                                                                int rt) {
   const CaseDesc &cd = cases[blockIdx.x];
   if (cd.p.outlet != 2 || (mask_unstable && cd.p.flag[0] != 0)) return;
-  const T *A = reinterpret_cast<const T *>(cd.pop[parity]);
-  T *B = reinterpret_cast<T *>(cd.pop[parity ^ 1]);
+  const T *A = reinterpret_cast<const T *>(cd.pop[route_src(rt)]);
+  T *B = reinterpret_cast<T *>(cd.pop[route_dst(rt)]);
   for (int y = (int)threadIdx.x; y < cd.p.ny; y += 256) conv_outlet_row<T>(A, B, cd.p, y);
 }
 
@@ -1179,12 +1249,12 @@ hipError_t launch_conv_outlet(int prec, const void *A, void *B, const LbmParams 
   return hipGetLastError();
 }
 
-hipError_t launch_conv_outlet_batch(int prec, const CaseDesc *cases, int ncases, int mask_unstable, int parity,
+hipError_t launch_conv_outlet_batch(int prec, const CaseDesc *cases, int ncases, int mask_unstable, int rt,
                                     hipStream_t s) {
   if (prec == 4)
-    hipLaunchKernelGGL(conv_outlet_batch_kernel<float>, dim3(ncases), dim3(256), 0, s, cases, mask_unstable, parity);
+    hipLaunchKernelGGL(conv_outlet_batch_kernel<float>, dim3(ncases), dim3(256), 0, s, cases, mask_unstable, rt);
   else
-    hipLaunchKernelGGL(conv_outlet_batch_kernel<double>, dim3(ncases), dim3(256), 0, s, cases, mask_unstable, parity);
+    hipLaunchKernelGGL(conv_outlet_batch_kernel<double>, dim3(ncases), dim3(256), 0, s, cases, mask_unstable, rt);
   return hipGetLastError();
 }
 

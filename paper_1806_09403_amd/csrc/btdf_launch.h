@@ -23,17 +23,20 @@ bool variant_has_wide_lbm2(int variant, int prec, int width);
 hipError_t launch_lbm3(int prec, int variant, int width, const void *A, void *C, const LbmParams &p, const int *map,
                        int count, void *X1, void *X2, const unsigned char *near, hipStream_t s);
 bool variant_has_lbm3(int variant, int prec, int width);
+// batches: the groups of every case, gcase[k] / gtile[k] = case and first tile
+hipError_t launch_lbm3_batch(int prec, int variant, int width, const CaseDesc *cases, const int *gcase,
+                             const int *gtile, int count, int rt, int mask, int xcd, hipStream_t s);
 bool variant_has_lbm2(int variant, int prec);
 hipError_t launch_ring(int prec, const void *A, void *X, const LbmParams &p, const int *near_map, int n_near,
                        const unsigned char *near, int tile_x, int tile_y, hipStream_t s);
 hipError_t launch_conv_outlet(int prec, const void *A, void *B, const LbmParams &p, hipStream_t s);
-hipError_t launch_conv_outlet_batch(int prec, const CaseDesc *cases, int ncases, int mask_unstable, int parity,
+hipError_t launch_conv_outlet_batch(int prec, const CaseDesc *cases, int ncases, int mask_unstable, int rt,
                                     hipStream_t s);
 hipError_t launch_marker_velocity(int prec, const void *A, const LbmParams &p, const IbParams &ib,
                                   const int *cover_off, const int *cover_list, double *out, hipStream_t s);
-hipError_t launch_lbm_batch(int prec, int variant, const CaseDesc *cases, const BatchMap &m, int parity,
+hipError_t launch_lbm_batch(int prec, int variant, const CaseDesc *cases, const BatchMap &m, int rt,
                             hipStream_t s);
-hipError_t launch_ib_batch(int prec, const CaseDesc *cases, const BatchMap &m, int parity, hipStream_t s);
+hipError_t launch_ib_batch(int prec, const CaseDesc *cases, const BatchMap &m, int rt, hipStream_t s);
 hipError_t launch_adj_lattice(int prec, const void *A, const void *Gnext, void *Gout, const LbmParams &p,
                               const AdjParams &a, hipStream_t s);
 hipError_t launch_adj_marker(int prec, const void *A, const void *Gnext, const LbmParams &p, const IbParams &ib,

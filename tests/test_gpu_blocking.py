@@ -96,23 +96,31 @@ def test_every_launch_shape_with_the_blocked_pass(depth, min_active):
     assert active >= min_active
 
 
-def test_default_depth_is_three_on_the_benchmark_shape():
-    from paper_1806_09403_amd import _lib
-    c = bodies_case(47, 512, 256, W.FULLY_PERIODIC)
-    from paper_1806_09403_amd import Sim
+def test_default_depth_follows_the_lattice_size():
+    """By default lattices of 2^20 nodes or more take three steps per pass
+    (two with the overlap option) and smaller ones step singly; a depth asked
+    for explicitly applies to any size."""
+    from paper_1806_09403_amd import Sim, _lib
+    big = bodies_case(47, 1024, 1024, W.FULLY_PERIODIC)
+    small = bodies_case(47, 512, 256, W.FULLY_PERIODIC)
     for prec in (4, 8):
-        s = Sim.from_case(c, precision=prec)
+        s = Sim.from_case(big, precision=prec)
         assert s.get_option(_lib.OPT_TEMPORAL_BLOCKING) == 1
         assert s.get_option(_lib.OPT_STEPS_PER_PASS) == 3
         s.set_option(_lib.OPT_OVERLAP, 1)      # the overlapped pass is the two-step one
         assert s.get_option(_lib.OPT_STEPS_PER_PASS) == 2
+        s.close()
+        s = Sim.from_case(small, precision=prec)
+        assert s.get_option(_lib.OPT_STEPS_PER_PASS) == 1
+        s.set_option(_lib.OPT_TEMPORAL_BLOCKING, 3)
+        assert s.get_option(_lib.OPT_STEPS_PER_PASS) == 3
         s.close()
 
 
 def test_moving_bodies_step_singly_under_blocking():
     from paper_1806_09403_amd import Sim, _lib
     outs = []
-    for blocking in (0, 1):
+    for blocking in (0, 3):   # (3: asked for explicitly, whatever the lattice size)
         s = Sim(256, 128, 0.8, W.ROMA3, 1.9, W.FULLY_PERIODIC, init=(1.0, 0.02, 0.0), precision=4)
         b = W.cylinder_body(100.3, 60.2, 12.0, 38)
         s.add_body(b.xy, None, b.cx, b.cy, b.ds)
