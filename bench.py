@@ -41,6 +41,8 @@ def parse():
     p.add_argument("--overlap", type=int, default=-1, help="1/0: marker kernel beside the lattice kernel (-1: library default)")
     p.add_argument("--blocking", type=int, default=-1,
                    help="steps per pass away from the bodies: 0 off, 1 deepest, 2 or 3 (-1: library default)")
+    p.add_argument("--group-shape", type=int, default=-1,
+                   help="three-step pass groups: 0 along rows, 1 two tiles tall (-1: library default)")
     p.add_argument("--plane-pad", type=int, default=0)
     p.add_argument("--row-align", type=int, default=-1, help="row alignment in bytes (-1: library default)")
     p.add_argument("--copy-probe-mb", type=int, default=0,
@@ -49,6 +51,8 @@ def parse():
     p.add_argument("--no-batched", action="store_true", help="skip the batched-mode figures")
     p.add_argument("--only-batched", action="store_true", help="print the batched-mode figures alone")
     p.add_argument("--batched-steps", type=int, default=5000)
+    p.add_argument("--batched-variant", type=int, default=-1,
+                   help="batch launch shape (-1: autotuned; a fixed one keeps counter runs to one shape)")
     p.add_argument("--batched-graph-chunk", type=int, default=50)
     p.add_argument("--seq-steps", type=int, default=200,
                    help="steps per case when timing the sequential single-case runs (0: skip them)")
@@ -125,9 +129,17 @@ def bench_batched(args):
 
     cases = W.c4()
     t_setup = time.perf_counter()
-    b = BatchSim(cases, precision=4,
-                 options={_lib.OPT_ROW_ALIGN: args.row_align} if args.row_align >= 0 else None)
-    best = b.autotune(steps_per_trial=5)
+    opts = {}
+    if args.row_align >= 0:
+        opts[_lib.OPT_ROW_ALIGN] = args.row_align
+    if args.group_shape >= 0:
+        opts[_lib.OPT_GROUP_SHAPE] = args.group_shape
+    b = BatchSim(cases, precision=4, options=opts)
+    if args.batched_variant >= 0:
+        best = args.batched_variant
+        b.set_option(_lib.OPT_LBM_VARIANT, best)
+    else:
+        best = b.autotune(steps_per_trial=5)
     b.set_option(_lib.OPT_GRAPH_CHUNK, args.batched_graph_chunk)
     b.step(100)
     torch.cuda.synchronize()
@@ -140,12 +152,13 @@ def bench_batched(args):
     ms_ib, ms_lbm = b.step_timed(201)
     b_align = b.get_option(_lib.OPT_ROW_ALIGN)
     depth = b.get_option(_lib.OPT_STEPS_PER_PASS)
+    gshape = b.get_option(_lib.OPT_GROUP_SHAPE)
     blocked_nodes = (b.get_option(_lib.OPT_FUSED_TILES) * b.get_option(_lib.OPT_TILE_X) *
                      b.get_option(_lib.OPT_TILE_Y))
     b.close()
     del b
     traffic = None
-    key = "batched-v%d-a%d%s" % (best, b_align, "-p3" if depth == 3 else "")
+    key = "batched-v%d-a%d%s%s" % (best, b_align, "-p3" if depth == 3 else "", "-g%d" % gshape if gshape else "")
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             t = json.load(f).get(key)
@@ -182,7 +195,7 @@ def bench_batched(args):
             "speedup_vs_sequential": round(mlups / seq_mlups, 3) if seq_mlups else None,
             "sequential_sample": "each stable case alone, %d graph-replayed steps" % args.seq_steps,
             "lbm_variant": best, "graph_chunk": args.batched_graph_chunk, "row_align": b_align,
-            "steps_per_pass": depth, "blocked_nodes_frac": round(blocked_nodes / nodes, 4),
+            "steps_per_pass": depth, "group_shape": gshape, "blocked_nodes_frac": round(blocked_nodes / nodes, 4),
             "kernel_ms": {"ib_batch_kernel": round(ms_ib, 5), "lbm_batch_kernel": round(ms_lbm, 5)},
             "kernel_ms_note": "per step; lbm_batch_kernel: the lattice launches of a step (with blocking: the "
                               "near tiles' steps and the blocked pass, a third of each triple)",
@@ -300,6 +313,8 @@ def main():
         sim.set_option(_lib.OPT_OVERLAP, args.overlap)
     if args.blocking >= 0:
         sim.set_option(_lib.OPT_TEMPORAL_BLOCKING, args.blocking)
+    if args.group_shape >= 0:
+        sim.set_option(_lib.OPT_GROUP_SHAPE, args.group_shape)
     sim.step(args.warmup)
     torch.cuda.synchronize()
     if args.copy_probe_mb:
@@ -327,7 +342,8 @@ def main():
         launch_nodes = fused_tiles * tile_nodes
         launch_ms = depth * ms_pass
         kernel, bytes_per_update = "lbm%d_kernel" % depth, node_bytes / depth
-        key = "%s-%s-v%d-p%d" % (args.workload, args.delta, variant, depth)
+        gshape = sim.get_option(_lib.OPT_GROUP_SHAPE)
+        key = "%s-%s-v%d-p%d%s" % (args.workload, args.delta, variant, depth, "-g%d" % gshape if gshape else "")
     else:
         launch_nodes, launch_ms = n, ms_single
         kernel, bytes_per_update = "lbm_kernel", node_bytes
@@ -364,7 +380,8 @@ def main():
                    "overlap": sim.get_option(_lib.OPT_OVERLAP),
                    "graph_chunk": args.graph_chunk,
                    "temporal_blocking": sim.get_option(_lib.OPT_TEMPORAL_BLOCKING),
-                   "steps_per_pass": depth, "blocked_tiles": fused_tiles,
+                   "steps_per_pass": depth, "group_shape": sim.get_option(_lib.OPT_GROUP_SHAPE),
+                   "blocked_tiles": fused_tiles,
                    "blocked_nodes_frac": round(launch_nodes / n, 4) if fused_tiles else 0.0},
         "kernel_ms": dict([("ib_kernel", round(ms_ib, 5)), ("lbm_kernel", round(ms_single, 5))] +
                           ([(kernel, round(launch_ms, 5))] if fused_tiles > 0 else [])),

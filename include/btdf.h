@@ -138,6 +138,11 @@ extern "C" {
                                          with single steps. */
 #define BTDF_OPT_FUSED_TILES 17       /* read-only: lattice tiles that take the blocked pass (0 when it is not active) */
 #define BTDF_OPT_STEPS_PER_PASS 18    /* read-only: steps per pass of those tiles (1 when blocking is not active) */
+#define BTDF_OPT_GROUP_SHAPE 19       /* how the three-step pass groups its lattice tiles (launch shape 32x8):
+                                         0 (default): four, then two side by side in a row (128x8, 64x8);
+                                         1: 2x2, then 1x2 tiles (64x16, 32x16: fewer halo nodes recomputed per
+                                         node), where the precision's LDS allows 2x2 (FP32), else as 0. Tiles
+                                         left out of every group take the pass singly. Handles and batches. */
 #define BTDF_OPT_FORCING_PASSES 14 /* NF in 1..64 (default 1): direct-forcing passes per step (Sec. 2.3, eqs 29-31);
                                       each pass after the first re-interpolates the velocity corrected by the force
                                       spread so far and adds 2 rho_l (U - u) to the marker force; stand-alone

@@ -26,6 +26,7 @@ OPT_ROW_ALIGN = 13
 OPT_FORCING_PASSES = 14
 OPT_FORCING_METHOD = 15
 OPT_TEMPORAL_BLOCKING, OPT_FUSED_TILES, OPT_STEPS_PER_PASS = 16, 17, 18
+OPT_GROUP_SHAPE = 19
 FORCING_DIRECT, FORCING_IMPLICIT, FORCING_RKPM = 0, 1, 2
 
 _NAMES = {OK: "BTDF_OK", EINVAL: "BTDF_EINVAL", ENOMEM: "BTDF_ENOMEM", EDEVICE: "BTDF_EDEVICE",

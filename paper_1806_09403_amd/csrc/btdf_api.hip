@@ -174,15 +174,28 @@ int pass_depth(const btdf_t *h) {
   // extra launches of a blocked pass (single handles; a batch shares them)
   if (h->tblock == 1 && !h->owner && (long long)h->nx * h->ny < kBlockMinNodes) return 1;
   const int want = h->tblock == 1 ? (h->overlap ? 2 : 3) : h->tblock;
-  if (want >= 3 && variant_has_lbm3(h->variant, h->prec, 1)) return 3;
+  if (want >= 3 && variant_has_lbm3(h->variant, h->prec, kGroup1x1)) return 3;
   if (variant_has_lbm2(h->variant, h->prec)) return 2;
   return 1;
 }
 
-// whether the pass of depth d has a launch over w lattice tiles side by side
-static bool has_group(const btdf_t *h, int d, int w) {
-  if (d == 3) return variant_has_lbm3(h->variant, h->prec, w);
+// whether the pass of depth d has a launch over groups of the given shape
+// (two-step pass: one row of 1, 2 or 4 tiles)
+static bool has_group(const btdf_t *h, int d, int code) {
+  if (d == 3) return variant_has_lbm3(h->variant, h->prec, code);
+  const int w = code & 15;
+  if (code >> 4 != 1) return false;
   return w == 1 ? variant_has_lbm2(h->variant, h->prec) : variant_has_wide_lbm2(h->variant, h->prec, w);
+}
+
+// The shapes of the three launches of a pass of depth d: groups of four
+// tiles, of two, single tiles. Two tiles tall (2 x 2, then 1 x 2) where the
+// option asks for it and the launch shape has a 2 x 2 pass, else along rows.
+void group_kinds(int gshape, int variant, int prec, int d, int kind[3]) {
+  const bool tall = gshape == 1 && d == 3 && variant_has_lbm3(variant, prec, kGroup2x2);
+  kind[0] = tall ? kGroup2x2 : kGroup4x1;
+  kind[1] = tall ? kGroup1x2 : kGroup2x1;
+  kind[2] = kGroup1x1;
 }
 
 // Tiles for temporal blocking of depth d = h->depth on the current launch
@@ -221,29 +234,33 @@ void fused_lists(btdf_t *h) {
       }
     }
   }
-  // blocked tiles: groups of four, then of two side-by-side lattice tiles
-  // where the launch shape has such a pass (first tile of each group
-  // listed), then the rest. Groups are packed greedily along each row from
-  // any tile column, so a run of L far tiles leaves only L mod 4 of them
-  // outside groups of four.
+  // blocked tiles: groups of four lattice tiles, then of two, where the
+  // launch shape has such a pass (lower-left tile of each group listed),
+  // then the rest. Groups are packed greedily, row by row of tiles, from any
+  // tile column (and, two tiles tall, any tile row), so a run of L far tiles
+  // in a row leaves only L mod 4 of them outside groups of four along rows.
+  group_kinds(h->gshape, h->variant, h->prec, d, h->gkind);
   std::vector<char> grouped(ntiles, 0);
-  for (int w : {4, 2}) {
+  for (int g = 0; g < 2; ++g) {
+    const int code = h->gkind[g], w = code & 15, gh = code >> 4;
     const size_t start = h->fmap.size();
-    if (has_group(h, d, w))
-      for (int b = 0; b < nty; ++b)
+    if (has_group(h, d, code))
+      for (int b = 0; b + gh - 1 < nty; ++b)
         for (int a = 0; a + w - 1 < ntx;) {
           const int t = b * ntx + a;
           bool ok = true;
-          for (int k = 0; k < w; ++k) ok = ok && !near[t + k] && !grouped[t + k];
+          for (int r = 0; r < gh; ++r)
+            for (int k = 0; k < w; ++k) ok = ok && !near[t + r * ntx + k] && !grouped[t + r * ntx + k];
           if (!ok) {
             ++a;
             continue;
           }
           h->fmap.push_back(t);
-          for (int k = 0; k < w; ++k) grouped[t + k] = 1;
+          for (int r = 0; r < gh; ++r)
+            for (int k = 0; k < w; ++k) grouped[t + r * ntx + k] = 1;
           a += w;
         }
-    (w == 4 ? h->n_quad : h->n_wide) = (int)(h->fmap.size() - start);
+    (g == 0 ? h->n_quad : h->n_wide) = (int)(h->fmap.size() - start);
   }
   for (int t = 0; t < ntiles; ++t)
     if (!near[t] && !grouped[t]) h->fmap.push_back(t);
@@ -1210,10 +1227,11 @@ static int enqueue_triple(btdf_t *h, const LbmParams &p, const IbParams &ib, hip
   const int nb0 = h->n_quad + h->n_wide + h->n_fused;  // the near tiles start here in the map
   const bool ov = h->overlap != 0;
   auto pass = [&](hipStream_t st) -> hipError_t {
-    hipError_t e = launch_lbm3(h->prec, h->variant, 1, A, B, p, fm + h->n_quad + h->n_wide, h->n_fused, X1, X2,
+    hipError_t e = launch_lbm3(h->prec, h->variant, h->gkind[2], A, B, p, fm + h->n_quad + h->n_wide, h->n_fused, X1, X2,
                                near, st);
-    if (e == hipSuccess) e = launch_lbm3(h->prec, h->variant, 2, A, B, p, fm + h->n_quad, h->n_wide, X1, X2, near, st);
-    if (e == hipSuccess) e = launch_lbm3(h->prec, h->variant, 4, A, B, p, fm, h->n_quad, X1, X2, near, st);
+    if (e == hipSuccess)
+      e = launch_lbm3(h->prec, h->variant, h->gkind[1], A, B, p, fm + h->n_quad, h->n_wide, X1, X2, near, st);
+    if (e == hipSuccess) e = launch_lbm3(h->prec, h->variant, h->gkind[0], A, B, p, fm, h->n_quad, X1, X2, near, st);
     return e;
   };
   if (ov) {
@@ -1760,6 +1778,15 @@ int btdf_set_option(btdf_t *h, int key, int64_t value) {
         drop_graph(h);
       }
       return ok();
+    case BTDF_OPT_GROUP_SHAPE:
+      if (value != 0 && value != 1) return fail(BTDF_EINVAL, "group shape must be 0 (rows) or 1 (two tiles tall)");
+      if (value != h->gshape) {
+        h->gshape = (int)value;
+        h->layout_ok = false;  // the tile lists
+        h->device_ok = false;
+        drop_graph(h);
+      }
+      return ok();
     case BTDF_OPT_FORCING_METHOD:
       if (value != BTDF_FORCING_DIRECT && value != BTDF_FORCING_IMPLICIT && value != BTDF_FORCING_RKPM)
         return fail(BTDF_EINVAL, "unknown forcing method %lld", (long long)value);
@@ -1813,9 +1840,12 @@ int btdf_get_option(const btdf_t *h, int key, int64_t *value) {
     case BTDF_OPT_FORCING_PASSES: *value = h->nf; return ok();
     case BTDF_OPT_FORCING_METHOD: *value = h->method; return ok();
     case BTDF_OPT_TEMPORAL_BLOCKING: *value = h->tblock; return ok();
+    case BTDF_OPT_GROUP_SHAPE: *value = h->gshape; return ok();
     case BTDF_OPT_FUSED_TILES:
       if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
-      *value = blocking_active(h) ? 4 * h->n_quad + 2 * h->n_wide + h->n_fused : 0;  // in lattice tiles
+      *value = blocking_active(h) ? group_tiles(h->gkind[0]) * h->n_quad + group_tiles(h->gkind[1]) * h->n_wide +
+                                        h->n_fused
+                                  : 0;  // in lattice tiles
       return ok();
     case BTDF_OPT_STEPS_PER_PASS:
       if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));

@@ -41,6 +41,8 @@ struct btdf_batch {
   BatchMap map_near{};   // the near tiles of every case (and the body reductions)
   const int *g_case[3] = {nullptr, nullptr, nullptr}, *g_tile[3] = {nullptr, nullptr, nullptr};
   int g_count[3] = {0, 0, 0};  // groups of 4, 2 and 1 tiles of every case
+  int gshape = 0;              // option: the groups' shape (as for single cases)
+  int gkind[3] = {kGroup4x1, kGroup2x1, kGroup1x1};  // the shapes of those three launches
   hipGraphExec_t graph = nullptr;
   hipStream_t cap_stream = nullptr;
   // time
@@ -61,9 +63,11 @@ void batch_drop_graph(btdf_batch_t *b) {
 void batch_layout(btdf_batch_t *b) {
   const int K = (int)b->cases.size();
   long long max_tiles = 0, bodies = 0, mblk = 0;
-  b->blocked = b->tblock && variant_has_lbm3(b->variant, b->prec, 1);
+  b->blocked = b->tblock && variant_has_lbm3(b->variant, b->prec, kGroup1x1);
+  group_kinds(b->gshape, b->variant, b->prec, 3, b->gkind);
   for (btdf_t *h : b->cases) {
     h->variant = b->variant;
+    h->gshape = b->gshape;
     h->xcd_remap = b->xcd_remap;
     h->interior = b->interior;
     h->row_align = b->row_align;
@@ -275,8 +279,8 @@ int batch_enqueue_triple(btdf_batch_t *b, int parity, hipStream_t s, hipEvent_t 
   if ((rc = near_step(A, 2))) return rc;
   HIPCHK(rec(2));
   for (int w : {2, 1, 0})  // single tiles, pairs, then groups of four
-    HIPCHK(launch_lbm3_batch(b->prec, b->variant, w == 0 ? 4 : (w == 1 ? 2 : 1), desc, b->g_case[w], b->g_tile[w],
-                             b->g_count[w], route(A, B), b->mask, b->xcd_remap, s));
+    HIPCHK(launch_lbm3_batch(b->prec, b->variant, b->gkind[w], desc, b->g_case[w], b->g_tile[w], b->g_count[w],
+                             route(A, B), b->mask, b->xcd_remap, s));
   HIPCHK(rec(3));
   HIPCHK(launch_ib_batch(b->prec, desc, b->map, route(2, 2), s));
   HIPCHK(rec(4));
@@ -597,6 +601,13 @@ int btdf_batch_set_option(btdf_batch_t *b, int key, int64_t value) {
         b->layout_ok = false;    // every case's lists and slice size
       }
       return ok();
+    case BTDF_OPT_GROUP_SHAPE:
+      if (value != 0 && value != 1) return fail(BTDF_EINVAL, "group shape must be 0 (rows) or 1 (two tiles tall)");
+      if (value != b->gshape) {
+        b->gshape = (int)value;
+        b->layout_ok = false;  // every case's lists
+      }
+      return ok();
     default: return fail(BTDF_EINVAL, "unknown or read-only batch option %d", key);
   }
 }
@@ -612,6 +623,7 @@ int btdf_batch_get_option(const btdf_batch_t *b, int key, int64_t *value) {
     case BTDF_OPT_MASK_UNSTABLE: *value = b->mask; return ok();
     case BTDF_OPT_ROW_ALIGN: *value = b->row_align; return ok();
     case BTDF_OPT_TEMPORAL_BLOCKING: *value = b->tblock; return ok();
+    case BTDF_OPT_GROUP_SHAPE: *value = b->gshape; return ok();
     case BTDF_OPT_TILE_X:
     case BTDF_OPT_TILE_Y: {
       int tx, ty;
@@ -623,7 +635,8 @@ int btdf_batch_get_option(const btdf_batch_t *b, int key, int64_t *value) {
       if (!b->layout_ok) batch_layout(const_cast<btdf_batch_t *>(b));
       *value = 0;
       if (b->blocked)
-        for (const btdf_t *h : b->cases) *value += 4 * h->n_quad + 2 * h->n_wide + h->n_fused;
+        for (const btdf_t *h : b->cases)
+          *value += group_tiles(b->gkind[0]) * h->n_quad + group_tiles(b->gkind[1]) * h->n_wide + h->n_fused;
       return ok();
     case BTDF_OPT_STEPS_PER_PASS:
       if (!b->layout_ok) batch_layout(const_cast<btdf_batch_t *>(b));

@@ -71,6 +71,8 @@ struct btdf_sim {
   std::vector<int> fmap;  // two-step groups of 4 and 2 tiles (first tile of each), single two-step tiles, near tiles
   std::vector<unsigned char> near;  // per lattice tile: 1 if it steps singly
   int n_quad = 0, n_wide = 0, n_fused = 0, n_near = 0;
+  int gshape = 0;  // option: groups of the three-step pass along rows (0) or two tiles tall (1)
+  int gkind[3] = {btdf::kGroup4x1, btdf::kGroup2x1, btdf::kGroup1x1};  // the shapes of n_quad, n_wide, n_fused (set with the lists)
   // device memory
   char *ws = nullptr;
   size_t ws_bytes = 0;
@@ -122,6 +124,7 @@ inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 bool valid_kind(int k);
 void drop_graph(btdf_t *h);
 void compute_layout(btdf_t *h);
+void group_kinds(int gshape, int variant, int prec, int d, int kind[3]);
 void bin_markers(const btdf_t *h, int tx, int ty, int ntx, int nty, std::vector<int> &off, std::vector<int> &list);
 void cover_lists(const btdf_t *h, std::vector<int> &off, std::vector<int> &list);
 // implicit / RKPM matrices of the current bodies ("" or the reason they cannot be formed)

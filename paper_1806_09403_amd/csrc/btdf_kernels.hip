@@ -807,25 +807,41 @@ constexpr bool lbm3_fits() {
   return 9 * (OX + 4) * (OY + 4) * (int)sizeof(T) <= 65536 && (OX + 2) * (OY + 2) <= 2 * OX * OY;
 }
 
-// The ring directions of an edge node of a group: bit q set when the
-// neighbour x + e_q lies in a near tile (s_near as in lbm2_kernel).
+// Groups of several lattice tiles with a three-step pass: (group code,
+// lattice tile, group in nodes). The code is W | H << 4 for W x H tiles.
+#define BTDF_LBM3_GROUPS(G)                                                                              \
+  G(kGroup4x1, 32, 8, 128, 8) G(kGroup4x1, 16, 8, 64, 8) G(kGroup2x1, 32, 8, 64, 8)                      \
+  G(kGroup2x1, 16, 8, 32, 8) G(kGroup2x1, 64, 4, 128, 4) G(kGroup2x2, 32, 8, 64, 16)                      \
+  G(kGroup1x2, 32, 8, 32, 16)
+
+__host__ __device__ constexpr bool lbm3_group_ok(int ox, int oy, int tx, int ty) {
+  return tx > 0 && ty > 0 && (tx & (tx - 1)) == 0 && (ty & (ty - 1)) == 0 && ox % tx == 0 && oy % ty == 0 &&
+         ox / tx <= 4 && oy / ty <= 2;
+}
+
+// The ring directions of an edge node of a group of W x H lattice tiles:
+// bit q set when the neighbour x + e_q lies in a near tile. s_near holds the
+// near flags of the tiles around the group (row 0 below it, column 0 left of
+// it; the group's own tiles read 0).
 template <int OX, int OY>
-__device__ __forceinline__ unsigned ring_mask(const unsigned char (&s_near)[3][8], int ii, int jj, int W, int sh) {
-  const int cl = ii == 0 ? 0 : 1 + ((ii - 1) >> sh), cm = 1 + (ii >> sh);
-  const int cr = ii == OX - 1 ? W + 1 : 1 + ((ii + 1) >> sh);
-  const int rd = jj == 0 ? 0 : 1, ru = jj == OY - 1 ? 2 : 1;
+__device__ __forceinline__ unsigned ring_mask(const unsigned char (&s_near)[4][8], int ii, int jj, int W, int H,
+                                              int shx, int shy) {
+  const int cl = ii == 0 ? 0 : 1 + ((ii - 1) >> shx), cm = 1 + (ii >> shx);
+  const int cr = ii == OX - 1 ? W + 1 : 1 + ((ii + 1) >> shx);
+  const int rd = jj == 0 ? 0 : 1 + ((jj - 1) >> shy), rm = 1 + (jj >> shy);
+  const int ru = jj == OY - 1 ? H + 1 : 1 + ((jj + 1) >> shy);
   unsigned m = 0;
 #pragma unroll
   for (int q = 1; q < 9; ++q) {
-    const int r = ey(q) < 0 ? rd : (ey(q) > 0 ? ru : 1);
+    const int r = ey(q) < 0 ? rd : (ey(q) > 0 ? ru : rm);
     const int c = ex(q) < 0 ? cl : (ex(q) > 0 ? cr : cm);
     m |= s_near[r][c] ? 1u << q : 0u;
   }
   return m;
 }
 
-// Three steps A -> C for a group of lattice tiles OX x OY (one thread per
-// node). Step n+1 is taken over the group grown by two nodes into LDS, step
+// Three steps A -> C for a group of lattice tiles OX x OY (W x H tiles,
+// W <= 4, H <= 2; one thread per node). Step n+1 is taken over the group grown by two nodes into LDS, step
 // n+2 over the group grown by one (into registers, then back into the same
 // LDS rows in place), step n+3 over the group into C. The group's edge nodes
 // next to a near tile also give X1 their state n+1 and X2 their state n+2
@@ -838,15 +854,16 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
   constexpr int RX = OX + 4, RY = OY + 4;  // the group grown by two
   constexpr int NTH = BX * BY;
   __shared__ T s_f[9][RY][RX];
-  __shared__ unsigned char s_near[3][8];
+  __shared__ unsigned char s_near[4][8];
   const int tyi = t / p.ntx;
   const int txi = t - tyi * p.ntx;
   const int x0 = txi * tile_x, y0 = tyi * tile_y;
   const int tid = (int)threadIdx.y * BX + (int)threadIdx.x;
-  const int W = OX / tile_x;
-  if (near && tid < 24) {
+  const int W = OX / tile_x, H = OY / tile_y;
+  if (near && tid < 32) {
     const int r = tid >> 3, c = tid & 7;
-    s_near[r][c] = (c > W + 1 || (r == 1 && c >= 1 && c <= W)) ? 0 : near[(tyi - 1 + r) * p.ntx + txi - 1 + c];
+    const bool own = r >= 1 && r <= H && c >= 1 && c <= W;
+    s_near[r][c] = (c > W + 1 || r > H + 1 || own) ? 0 : near[(tyi - 1 + r) * p.ntx + txi - 1 + c];
   }
   const CollK<T> &K = coll<T>(p);
   const ForceK<T> &F = gforce<T>(p);
@@ -895,12 +912,12 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
   }
   __syncthreads();
   const unsigned *nw = reinterpret_cast<const unsigned *>(&s_near[0][0]);
-  const bool ring = near && (nw[0] | nw[1] | nw[2] | nw[3] | nw[4] | nw[5]) != 0;
-  const int sh = __builtin_ctz((unsigned)tile_x);
+  const bool ring = near && (nw[0] | nw[1] | nw[2] | nw[3] | nw[4] | nw[5] | nw[6] | nw[7]) != 0;
+  const int shx = __builtin_ctz((unsigned)tile_x), shy = __builtin_ctz((unsigned)tile_y);
   // this thread's node of the group, and its ring directions
   const int ii = (int)threadIdx.x, jj = (int)threadIdx.y;
   unsigned rmask = 0;
-  if (ring && (ii == 0 || ii == OX - 1 || jj == 0 || jj == OY - 1)) rmask = ring_mask<OX, OY>(s_near, ii, jj, W, sh);
+  if (ring && (ii == 0 || ii == OX - 1 || jj == 0 || jj == OY - 1)) rmask = ring_mask<OX, OY>(s_near, ii, jj, W, H, shx, shy);
   const unsigned off = (unsigned)(jj * p.pitch + ii) * (unsigned)sizeof(T);
   if (rmask) {
 #pragma unroll
@@ -995,7 +1012,7 @@ static hipError_t launch_lbm3_batch_t(const CaseDesc *cases, const int *gcase, c
                                       int mask, int xcd, int tx, int ty, hipStream_t s) {
   if constexpr (lbm3_fits<T, OX, OY>() && BX == OX && BY == OY) {
     if (count <= 0) return hipSuccess;
-    if (OX % tx != 0 || OX / tx > 4 || OY != ty || (tx & (tx - 1)) != 0) return hipErrorInvalidValue;
+    if (!lbm3_group_ok(OX, OY, tx, ty)) return hipErrorInvalidValue;
     hipLaunchKernelGGL((lbm3_batch_kernel<T, OX, OY, BX, BY, NT>), dim3(count), dim3(BX, BY), 0, s, cases, gcase,
                        gtile, count, rt, mask, xcd, tx, ty);
     return hipGetLastError();
@@ -1005,35 +1022,31 @@ static hipError_t launch_lbm3_batch_t(const CaseDesc *cases, const int *gcase, c
 }
 
 template <typename T>
-static hipError_t launch_lbm3_batch_any(int v, int width, const CaseDesc *cases, const int *gcase, const int *gtile,
+static hipError_t launch_lbm3_batch_any(int v, int code, const CaseDesc *cases, const int *gcase, const int *gtile,
                                         int count, int rt, int mask, int xcd, hipStream_t s) {
   int tx, ty;
   variant_tile(v, &tx, &ty);
 #define ARGS cases, gcase, gtile, count, rt, mask, xcd, tx, ty, s
-  if (width == 4) {
-    if (tx == 32 && ty == 8) return launch_lbm3_batch_t<T, 128, 8, 128, 8, true>(ARGS);
-    if (tx == 16 && ty == 8) return launch_lbm3_batch_t<T, 64, 8, 64, 8, true>(ARGS);
-    return hipErrorInvalidValue;
-  }
-  if (width == 2) {
-    if (tx == 32 && ty == 8) return launch_lbm3_batch_t<T, 64, 8, 64, 8, true>(ARGS);
-    if (tx == 16 && ty == 8) return launch_lbm3_batch_t<T, 32, 8, 32, 8, true>(ARGS);
-    if (tx == 64 && ty == 4) return launch_lbm3_batch_t<T, 128, 4, 128, 4, true>(ARGS);
+  if (code != kGroup1x1) {
+#define G(c, TX, TY, OX, OY) \
+  if (code == c && tx == TX && ty == TY) return launch_lbm3_batch_t<T, OX, OY, OX, OY, true>(ARGS);
+    BTDF_LBM3_GROUPS(G)
+#undef G
     return hipErrorInvalidValue;
   }
 #define X(id, bx, by, npt, nt, ntl) \
-  if (v == id) return npt == 1 && width == 1 ? launch_lbm3_batch_t<T, bx, by, bx, by, nt>(ARGS) : hipErrorInvalidValue;
+  if (v == id) return npt == 1 ? launch_lbm3_batch_t<T, bx, by, bx, by, nt>(ARGS) : hipErrorInvalidValue;
   BTDF_VARIANTS(X)
 #undef X
 #undef ARGS
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_lbm3_batch(int prec, int v, int width, const CaseDesc *cases, const int *gcase, const int *gtile,
+hipError_t launch_lbm3_batch(int prec, int v, int code, const CaseDesc *cases, const int *gcase, const int *gtile,
                              int count, int rt, int mask, int xcd, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  if (prec == 4) return launch_lbm3_batch_any<float>(v, width, cases, gcase, gtile, count, rt, mask, xcd, s);
-  return launch_lbm3_batch_any<double>(v, width, cases, gcase, gtile, count, rt, mask, xcd, s);
+  if (prec == 4) return launch_lbm3_batch_any<float>(v, code, cases, gcase, gtile, count, rt, mask, xcd, s);
+  return launch_lbm3_batch_any<double>(v, code, cases, gcase, gtile, count, rt, mask, xcd, s);
 }
 
 template <typename T, int OX, int OY, int BX, int BY, bool NT>
@@ -1041,7 +1054,7 @@ static hipError_t launch_lbm3_t(const T *A, T *C, const LbmParams &p, const int 
                                 T *X1, T *X2, const unsigned char *near, hipStream_t s) {
   if constexpr (lbm3_fits<T, OX, OY>() && BX == OX && BY == OY) {
     if (count <= 0) return hipSuccess;
-    if (OX % tx != 0 || OX / tx > 4 || OY != ty || (tx & (tx - 1)) != 0) return hipErrorInvalidValue;
+    if (!lbm3_group_ok(OX, OY, tx, ty)) return hipErrorInvalidValue;
     hipLaunchKernelGGL((lbm3_kernel<T, OX, OY, BX, BY, NT>), dim3(count), dim3(BX, BY), 0, s, A, C, p, map, count,
                        tx, ty, X1, X2, near);
     return hipGetLastError();
@@ -1051,61 +1064,53 @@ static hipError_t launch_lbm3_t(const T *A, T *C, const LbmParams &p, const int 
 }
 
 template <typename T>
-static hipError_t launch_lbm3_any(int v, int width, const T *A, T *C, const LbmParams &p, const int *map, int count,
+static hipError_t launch_lbm3_any(int v, int code, const T *A, T *C, const LbmParams &p, const int *map, int count,
                                   T *X1, T *X2, const unsigned char *near, hipStream_t s) {
   int tx, ty;
   variant_tile(v, &tx, &ty);
-  if (width == 4) {
-    if (tx == 32 && ty == 8) return launch_lbm3_t<T, 128, 8, 128, 8, true>(A, C, p, map, count, tx, ty, X1, X2, near, s);
-    if (tx == 16 && ty == 8) return launch_lbm3_t<T, 64, 8, 64, 8, true>(A, C, p, map, count, tx, ty, X1, X2, near, s);
+#define ARGS A, C, p, map, count, tx, ty, X1, X2, near, s
+  if (code != kGroup1x1) {
+#define G(c, TX, TY, OX, OY) \
+  if (code == c && tx == TX && ty == TY) return launch_lbm3_t<T, OX, OY, OX, OY, true>(ARGS);
+    BTDF_LBM3_GROUPS(G)
+#undef G
     return hipErrorInvalidValue;
   }
-  if (width == 2) {
-    if (tx == 32 && ty == 8) return launch_lbm3_t<T, 64, 8, 64, 8, true>(A, C, p, map, count, tx, ty, X1, X2, near, s);
-    if (tx == 16 && ty == 8) return launch_lbm3_t<T, 32, 8, 32, 8, true>(A, C, p, map, count, tx, ty, X1, X2, near, s);
-    if (tx == 64 && ty == 4) return launch_lbm3_t<T, 128, 4, 128, 4, true>(A, C, p, map, count, tx, ty, X1, X2, near, s);
-    return hipErrorInvalidValue;
-  }
-#define X(id, bx, by, npt, nt, ntl)                                                                          \
-  if (v == id)                                                                                             \
-    return npt == 1 && width == 1 ? launch_lbm3_t<T, bx, by, bx, by, nt>(A, C, p, map, count, tx, ty, X1, X2, near, s) \
-                                  : hipErrorInvalidValue;
+#define X(id, bx, by, npt, nt, ntl) \
+  if (v == id) return npt == 1 ? launch_lbm3_t<T, bx, by, bx, by, nt>(ARGS) : hipErrorInvalidValue;
   BTDF_VARIANTS(X)
 #undef X
+#undef ARGS
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_lbm3(int prec, int v, int width, const void *A, void *C, const LbmParams &p, const int *map,
+hipError_t launch_lbm3(int prec, int v, int code, const void *A, void *C, const LbmParams &p, const int *map,
                        int count, void *X1, void *X2, const unsigned char *near, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (prec == 4)
-    return launch_lbm3_any<float>(v, width, (const float *)A, (float *)C, p, map, count, (float *)X1, (float *)X2,
+    return launch_lbm3_any<float>(v, code, (const float *)A, (float *)C, p, map, count, (float *)X1, (float *)X2,
                                   near, s);
-  return launch_lbm3_any<double>(v, width, (const double *)A, (double *)C, p, map, count, (double *)X1,
+  return launch_lbm3_any<double>(v, code, (const double *)A, (double *)C, p, map, count, (double *)X1,
                                  (double *)X2, near, s);
 }
 
-// whether a launch shape has a three-step pass (width 1), or one over width
-// 2 or 4 of its tiles side by side
-bool variant_has_lbm3(int v, int prec, int width) {
+// whether a launch shape has a three-step pass over groups of the given
+// shape (kGroup*: W x H of its tiles)
+bool variant_has_lbm3(int v, int prec, int code) {
   int tx, ty;
   variant_tile(v, &tx, &ty);
   bool fits = false;
-  if (width == 4) {
-    if (tx == 32 && ty == 8) fits = prec == 4 ? lbm3_fits<float, 128, 8>() : lbm3_fits<double, 128, 8>();
-    if (tx == 16 && ty == 8) fits = prec == 4 ? lbm3_fits<float, 64, 8>() : lbm3_fits<double, 64, 8>();
+  if (code != kGroup1x1) {
+#define G(c, TX, TY, OX, OY) \
+  if (code == c && tx == TX && ty == TY) fits = prec == 4 ? lbm3_fits<float, OX, OY>() : lbm3_fits<double, OX, OY>();
+    BTDF_LBM3_GROUPS(G)
+#undef G
+    return fits;
   }
-  if (width == 2) {
-    if (tx == 16 && ty == 8) fits = prec == 4 ? lbm3_fits<float, 32, 8>() : lbm3_fits<double, 32, 8>();
-    if (tx == 32 && ty == 8) fits = prec == 4 ? lbm3_fits<float, 64, 8>() : lbm3_fits<double, 64, 8>();
-    if (tx == 64 && ty == 4) fits = prec == 4 ? lbm3_fits<float, 128, 4>() : lbm3_fits<double, 128, 4>();
-  }
-  if (width == 1) {
 #define X(id, bx, by, npt, nt, ntl) \
   if (v == id) fits = npt == 1 && (prec == 4 ? lbm3_fits<float, bx, by>() : lbm3_fits<double, bx, by>());
-    BTDF_VARIANTS(X)
+  BTDF_VARIANTS(X)
 #undef X
-  }
   return fits;
 }
 

@@ -17,14 +17,18 @@ hipError_t launch_rigid_move(const MoveParams &mp, hipStream_t s);
 hipError_t launch_lbm2(int prec, int variant, int width, const void *A, void *C, const LbmParams &p, const int *map,
                        int count, void *X, const unsigned char *near, hipStream_t s);
 bool variant_has_wide_lbm2(int variant, int prec, int width);
-// three steps A -> C over the listed groups of width lattice tiles; with near
+// group shapes of the three-step pass, W | H << 4 for W x H lattice tiles
+// (map entries name a group's lower-left tile)
+constexpr int kGroup1x1 = 0x11, kGroup2x1 = 0x12, kGroup4x1 = 0x14, kGroup1x2 = 0x21, kGroup2x2 = 0x22;
+constexpr int group_tiles(int code) { return (code & 15) * (code >> 4); }
+// three steps A -> C over the listed groups of the given shape; with near
 // non-null, edge nodes next to a near tile also store their first and second
 // steps in X1 and X2
-hipError_t launch_lbm3(int prec, int variant, int width, const void *A, void *C, const LbmParams &p, const int *map,
+hipError_t launch_lbm3(int prec, int variant, int code, const void *A, void *C, const LbmParams &p, const int *map,
                        int count, void *X1, void *X2, const unsigned char *near, hipStream_t s);
-bool variant_has_lbm3(int variant, int prec, int width);
+bool variant_has_lbm3(int variant, int prec, int code);
 // batches: the groups of every case, gcase[k] / gtile[k] = case and first tile
-hipError_t launch_lbm3_batch(int prec, int variant, int width, const CaseDesc *cases, const int *gcase,
+hipError_t launch_lbm3_batch(int prec, int variant, int code, const CaseDesc *cases, const int *gcase,
                              const int *gtile, int count, int rt, int mask, int xcd, hipStream_t s);
 bool variant_has_lbm2(int variant, int prec);
 hipError_t launch_ring(int prec, const void *A, void *X, const LbmParams &p, const int *near_map, int n_near,
