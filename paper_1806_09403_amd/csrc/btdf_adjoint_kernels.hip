@@ -229,8 +229,8 @@ __global__ __launch_bounds__(256) void adj_marker_kernel(const T *__restrict__ A
     dWx = -dphi(p.kind, rx) * py;  // d W / d X
     dWy = -px * dphi(p.kind, ry);  // d W / d Y
     int xx = bx + i, yy = by + j;
-    if (p.xper) xx = ((xx % p.nx) + p.nx) % p.nx;
-    if (p.yper) yy = ((yy % p.ny) + p.ny) % p.ny;
+    if (p.xper) xx = wrap_index(xx, p.nx);
+    if (p.yper) yy = wrap_index(yy, p.ny);
     // the node's forward values and dJ/df, as the lattice kernel forms them
     // every load that does not depend on the covering markers goes first
     T g[9], bb[9];

@@ -420,6 +420,15 @@ __device__ __forceinline__ T pull(const T *__restrict__ A, const LbmParams &p, i
   return load<T, NTL>(&A[(long long)q * p.plane + (long long)sy * p.pitch + sx]);
 }
 
+// The periodic image of a node index in [0, n): ((i mod n) + n) mod n,
+// with one unsigned compare for an index already in range (the usual case:
+// stencils reach at most a few nodes past an edge).
+__host__ __device__ __forceinline__ int wrap_index(int i, int n) {
+  if ((unsigned)i < (unsigned)n) return i;
+  const int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
 // Consecutive tiles go to the same XCD: hardware dispatches block b to XCD
 // b % 8, so block b takes logical tile number (b % 8) * share + b / 8.
 __device__ __forceinline__ int xcd_tile(int b, int n) {

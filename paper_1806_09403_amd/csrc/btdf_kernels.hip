@@ -68,8 +68,8 @@ __device__ __forceinline__ void ib_marker(const T *__restrict__ A, const LbmPara
     if (a < S && c < S) {
       const double W = phx * phy;
       int i = bx + a, j = by + c;
-      if (p.xper) i = ((i % p.nx) + p.nx) % p.nx;
-      if (p.yper) j = ((j % p.ny) + p.ny) % p.ny;
+      if (p.xper) i = wrap_index(i, p.nx);
+      if (p.yper) j = wrap_index(j, p.ny);
       double drho = 0.0, mx = 0.0, my = 0.0;
       if (i >= 1 && i <= p.nx - 2 && j >= 1 && j <= p.ny - 2) {
         // no wrap, no wall: one 32-bit offset, the shifts fold into the plane base
@@ -125,8 +125,8 @@ __device__ __forceinline__ void ib_marker(const T *__restrict__ A, const LbmPara
     T *mw = reinterpret_cast<T *>(ib.mk_w) + 10 * (long long)l;
     mw[8] = (T)(Fx * sd);
     mw[9] = (T)(Fy * sd);
-    ib.mk_ixy[2 * l] = p.xper ? ((bx % p.nx) + p.nx) % p.nx : bx;
-    ib.mk_ixy[2 * l + 1] = p.yper ? ((by % p.ny) + p.ny) % p.ny : by;
+    ib.mk_ixy[2 * l] = p.xper ? wrap_index(bx, p.nx) : bx;
+    ib.mk_ixy[2 * l + 1] = p.yper ? wrap_index(by, p.ny) : by;
     if (ib.nf > 1) {
       ib.mdf_f[2 * (long long)l] = Fx;
       ib.mdf_f[2 * (long long)l + 1] = Fy;
@@ -1351,8 +1351,8 @@ __global__ __launch_bounds__(256) void marker_velocity_kernel(const T *__restric
     const int bx = stencil_base(p.kind, X), by = stencil_base(p.kind, Y);
     const double W = phi(p.kind, (double)(bx + a) - X) * phi(p.kind, (double)(by + c) - Y);
     int i = bx + a, j = by + c;
-    if (p.xper) i = ((i % p.nx) + p.nx) % p.nx;
-    if (p.yper) j = ((j % p.ny) + p.ny) % p.ny;
+    if (p.xper) i = wrap_index(i, p.nx);
+    if (p.yper) j = wrap_index(j, p.ny);
     const long long base = (long long)j * p.pitch + i;
     double drho = 0.0, mx = 0.0, my = 0.0;
 #pragma unroll
