@@ -344,9 +344,10 @@ int btdf_autotune(btdf_t *h, int64_t steps_per_trial, int *best_variant);
  * binding, options and adding bodies go through the batch. With
  * BTDF_OPT_MASK_UNSTABLE (default on) a case whose instability flag is set
  * stops stepping and the others continue; btdf_batch_status reports which.
- * A stopped case's populations are those of one of its last two steps (the
- * ping-pong buffers no longer alternate) and its state calls return
- * BTDF_EUNSTABLE; the other cases are bit-identical to running alone. */
+ * A stopped case's kernels store nothing from the moment they read its flag
+ * set, so its populations are left as its last launches wrote them (tiles
+ * may hold different steps); its state calls return BTDF_EUNSTABLE. The
+ * other cases are bit-identical to running alone. */
 typedef struct btdf_batch btdf_batch_t;
 
 int btdf_batch_create(int n_cases, const btdf_grid *grids, const double *taus, const int *delta_kinds,

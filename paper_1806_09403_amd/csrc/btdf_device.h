@@ -328,6 +328,19 @@ __device__ __forceinline__ global_ptr<P> uniform_ptr(P *ptr) {
   const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
   return (global_ptr<P>)(((unsigned long long)hi << 32) | lo);
 }
+// A load through a pointer into device memory, as a global access: pointers
+// read from memory (a batch's case table) are otherwise taken as flat, whose
+// accesses need a 64-bit address per lane and wait on the LDS counter too.
+template <typename T>
+__device__ __forceinline__ T load_global(const char *base, unsigned off) {
+  return *(global_ptr<const T>)((global_ptr<const char>)base + off);
+}
+// element i of an array in device memory, as a global access
+template <typename T>
+__device__ __forceinline__ T ldg(const T *ptr, long long i) {
+  return *((global_ptr<const T>)ptr + i);
+}
+
 // store v at byte offset off from a uniform global base (nontemporal if NT)
 template <typename T, bool NT>
 __device__ __forceinline__ void store_uniform(global_ptr<char> base, unsigned off, T v) {
@@ -394,8 +407,9 @@ __device__ __forceinline__ void collide(const T g[9], const ForceK<T> &f, const 
 // read the ghost columns.
 template <typename T, bool NTL = false>
 __device__ __forceinline__ T load(const T *ptr) {
-  if (NTL) return __builtin_nontemporal_load(ptr);
-  return *ptr;
+  const global_ptr<const T> g = (global_ptr<const T>)ptr;  // device memory: a global access
+  if (NTL) return __builtin_nontemporal_load(g);
+  return *g;
 }
 
 template <typename T, bool NTL = false>

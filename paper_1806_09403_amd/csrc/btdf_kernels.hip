@@ -250,16 +250,32 @@ constexpr int kChunk = 64;  // markers staged in LDS per pass
 
 template <typename T, bool NT>
 __device__ __forceinline__ void store(T *ptr, T v) {
+  const global_ptr<T> g = (global_ptr<T>)ptr;  // device memory: a global access
   if (NT)
-    __builtin_nontemporal_store(v, ptr);
+    __builtin_nontemporal_store(v, g);
   else
-    *ptr = v;
+    *g = v;
 }
 
-// one tile t of the lattice: streaming pull, spread gather, collision
-template <typename T, int BX, int BY, int NPT, bool NT, bool NTL>
-__device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict__ B, const LbmParams &p, int t) {
+// A batch case's stop flag (nonzero once the case went unstable), read
+// with an atomic load at the start of a workgroup: the read is in flight with
+// the population loads and is not moved down to its use. Batch kernels pass
+// the case's flag, or kNoStop when unstable cases are not masked, so the load
+// needs no branch around it (whose join would wait for it at once).
+__device__ const int kNoStop = 0;
+template <bool STOP>
+__device__ __forceinline__ int stop_flag(const int *stop) {
+  if constexpr (STOP) return __hip_atomic_load((global_ptr<const int>)stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return 0;
+}
+
+// one tile t of the lattice: streaming pull, spread gather, collision; with
+// STOP and *stop set, nothing is stored (a stopped batch case)
+template <typename T, int BX, int BY, int NPT, bool NT, bool NTL, bool STOP = false>
+__device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict__ B, const LbmParams &p, int t,
+                                         const int *stop = nullptr) {
   constexpr int TX = BX * NPT;
+  const int halt = stop_flag<STOP>(stop);
   __shared__ int s_ix[kChunk], s_iy[kChunk];
   __shared__ T s_w[kChunk][10];  // wx[4], wy[4], drs ds F_x, drs ds F_y
   const int tyi = t / p.ntx;
@@ -310,7 +326,7 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
 
   // spread (eqs 13, 15) as a gather over the markers listed for this tile;
   // the marker kernel left each marker's weights and drs ds F_l
-  const int m0 = p.tile_off[t], m1 = p.tile_off[t + 1];
+  const int m0 = ldg(p.tile_off, t), m1 = ldg(p.tile_off, t + 1);
   const bool forced = m1 > m0;
   if (forced) {
     const int S = stencil_size(p.kind);
@@ -320,11 +336,11 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
       const int cnt = min(kChunk, m1 - c0);
       __syncthreads();
       if (tid < cnt) {
-        const int l = p.tile_list[c0 + tid];
-        s_ix[tid] = p.mk_ixy[2 * l];
-        s_iy[tid] = p.mk_ixy[2 * l + 1];
+        const int l = ldg(p.tile_list, c0 + tid);
+        s_ix[tid] = ldg(p.mk_ixy, 2 * l);
+        s_iy[tid] = ldg(p.mk_ixy, 2 * l + 1);
 #pragma unroll
-        for (int k = 0; k < 10; ++k) s_w[tid][k] = mw[10 * (long long)l + k];
+        for (int k = 0; k < 10; ++k) s_w[tid][k] = ldg(mw, 10 * (long long)l + k);
       }
       __syncthreads();
       for (int e = 0; e < cnt; ++e) {
@@ -346,7 +362,7 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
       }
     }
   }
-  if (y >= p.ny) return;
+  if (y >= p.ny || halt) return;  // (after the gather's last barrier)
 
   const CollK<T> &K = coll<T>(p);
   bool bad = false;
@@ -433,9 +449,10 @@ __global__ __launch_bounds__(BX *BY) void lbm_batch_kernel(const CaseDesc *__res
   const LbmParams p = cases[c].p;
   const T *A = reinterpret_cast<const T *>(cases[c].pop[route_src(rt)]);
   T *B = reinterpret_cast<T *>(cases[c].pop[route_dst(rt)]);
-  if (m.mask_unstable && p.flag[0] != 0) return;  // an unstable case stops; the others go on
-  lbm_tile<T, BX, BY, NPT, NT, NTL>(A, B, p, t);
-  if (t == 0 && threadIdx.x == 0 && threadIdx.y == 0) p.step_ctr[0] = p.step_ctr[0] + 1;
+  // an unstable case stops (stores nothing, counts no step); the others go on
+  const int *stop = m.mask_unstable ? p.flag : &kNoStop;
+  lbm_tile<T, BX, BY, NPT, NT, NTL, true>(A, B, p, t, stop);
+  if (t == 0 && threadIdx.x == 0 && threadIdx.y == 0 && !stop_flag<true>(stop)) p.step_ctr[0] = p.step_ctr[0] + 1;
 }
 
 template <typename T>
@@ -679,8 +696,8 @@ __global__ __launch_bounds__(BX *BY) void lbm2_kernel(const T *__restrict__ A, T
     for (int q = 0; q < 9; ++q) {
       const char *base = reinterpret_cast<const char *>(A + (long long)q * p.plane +
                                                         (long long)(y0 - 1 - ey(q)) * p.pitch + (x0 - 1 - ex(q)));
-      ga[q] = *reinterpret_cast<const T *>(base + oa);
-      gb[q] = *reinterpret_cast<const T *>(base + ob);
+      ga[q] = load_global<T>(base, oa);
+      gb[q] = load_global<T>(base, ob);
     }
     T out[9], rho;
     collide<T>(ga, F, K, out, rho);
@@ -847,11 +864,13 @@ __device__ __forceinline__ unsigned ring_mask(const unsigned char (&s_near)[4][8
 // next to a near tile also give X1 their state n+1 and X2 their state n+2
 // (only the populations the near tile pulls), where the near tiles' second
 // and third steps read them.
-template <typename T, int OX, int OY, int BX, int BY, bool NT>
+template <typename T, int OX, int OY, int BX, int BY, bool NT, bool STOP = false>
 __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restrict__ C, const LbmParams &p, int t,
                                            int tile_x, int tile_y, T *__restrict__ X1, T *__restrict__ X2,
-                                           const unsigned char *__restrict__ near) {
+                                           const unsigned char *__restrict__ near, const int *stop) {
   constexpr int RX = OX + 4, RY = OY + 4;  // the group grown by two
+  // a stopped batch case stores nothing; every thread still meets every barrier
+  const bool keep = !stop_flag<STOP>(stop);
   constexpr int NTH = BX * BY;
   __shared__ T s_f[9][RY][RX];
   __shared__ unsigned char s_near[4][8];
@@ -863,7 +882,10 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
   if (near && tid < 32) {
     const int r = tid >> 3, c = tid & 7;
     const bool own = r >= 1 && r <= H && c >= 1 && c <= W;
-    s_near[r][c] = (c > W + 1 || r > H + 1 || own) ? 0 : near[(tyi - 1 + r) * p.ntx + txi - 1 + c];
+    s_near[r][c] = (c > W + 1 || r > H + 1 || own)
+                       ? 0
+                       : load_global<unsigned char>(reinterpret_cast<const char *>(near),
+                                                    (unsigned)((tyi - 1 + r) * p.ntx + txi - 1 + c));
   }
   const CollK<T> &K = coll<T>(p);
   const ForceK<T> &F = gforce<T>(p);
@@ -895,8 +917,8 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
     for (int q = 0; q < 9; ++q) {
       const char *base = reinterpret_cast<const char *>(A + (long long)q * p.plane +
                                                         (long long)(y0 - 2 - ey(q)) * p.pitch + (x0 - 2 - ex(q)));
-      ga[q] = *reinterpret_cast<const T *>(base + oa);
-      gb[q] = *reinterpret_cast<const T *>(base + ob);
+      ga[q] = load_global<T>(base, oa);
+      gb[q] = load_global<T>(base, ob);
     }
     T out[9], rho;
     collide<T>(ga, F, K, out, rho);
@@ -919,7 +941,7 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
   unsigned rmask = 0;
   if (ring && (ii == 0 || ii == OX - 1 || jj == 0 || jj == OY - 1)) rmask = ring_mask<OX, OY>(s_near, ii, jj, W, H, shx, shy);
   const unsigned off = (unsigned)(jj * p.pitch + ii) * (unsigned)sizeof(T);
-  if (rmask) {
+  if (rmask && keep) {
 #pragma unroll
     for (int q = 1; q < 9; ++q)
       if (rmask & (1u << q))
@@ -964,6 +986,7 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
     T out[9], rho;
     collide<T>(g, F, K, out, rho);
     bad |= !(rho > (T)0) || !isfinite(rho);
+    if (!keep) return;  // (after the last barrier)
 #pragma unroll
     for (int q = 0; q < 9; ++q)
       store_uniform<T, NT>(uniform_ptr(reinterpret_cast<char *>(C + (long long)q * p.plane + (long long)y0 * p.pitch + x0)),
@@ -986,7 +1009,7 @@ __global__ __launch_bounds__(BX *BY) void lbm3_kernel(const T *__restrict__ A, T
                                                      int tile_y, T *__restrict__ X1, T *__restrict__ X2,
                                                      const unsigned char *__restrict__ near) {
   const int li = p.xcd_remap ? xcd_tile((int)blockIdx.x, count) : (int)blockIdx.x;
-  lbm3_group<T, OX, OY, BX, BY, NT>(A, C, p, map[li], tile_x, tile_y, X1, X2, near);
+  lbm3_group<T, OX, OY, BX, BY, NT>(A, C, p, map[li], tile_x, tile_y, X1, X2, near, nullptr);
 }
 
 // batches: groups of every case in one launch (a case and its group's first
@@ -1000,11 +1023,13 @@ __global__ __launch_bounds__(BX *BY) void lbm3_batch_kernel(const CaseDesc *__re
   const int li = xcd_remap ? xcd_tile((int)blockIdx.x, count) : (int)blockIdx.x;
   const int c = gcase[li];
   const LbmParams p = cases[c].p;
-  if (mask_unstable && p.flag[0] != 0) return;  // the whole workgroup: an unstable case stops
-  lbm3_group<T, OX, OY, BX, BY, NT>(reinterpret_cast<const T *>(cases[c].pop[route_src(rt)]),
-                                    reinterpret_cast<T *>(cases[c].pop[route_dst(rt)]), p, gtile[li], tile_x, tile_y,
-                                    reinterpret_cast<T *>(cases[c].pop[2]), reinterpret_cast<T *>(cases[c].pop[3]),
-                                    cases[c].near);
+  // an unstable case stops: its workgroups store nothing (the flag is read
+  // beside the first loads rather than ahead of them)
+  lbm3_group<T, OX, OY, BX, BY, NT, true>(reinterpret_cast<const T *>(cases[c].pop[route_src(rt)]),
+                                          reinterpret_cast<T *>(cases[c].pop[route_dst(rt)]), p, gtile[li], tile_x,
+                                          tile_y, reinterpret_cast<T *>(cases[c].pop[2]),
+                                          reinterpret_cast<T *>(cases[c].pop[3]), cases[c].near,
+                                          mask_unstable ? p.flag : &kNoStop);
 }
 
 template <typename T, int OX, int OY, int BX, int BY, bool NT>
