@@ -261,11 +261,18 @@ __device__ __forceinline__ void store(T *ptr, T v) {
 // with an atomic load at the start of a workgroup: the read is in flight with
 // the population loads and is not moved down to its use. Batch kernels pass
 // the case's flag, or kNoStop when unstable cases are not masked, so the load
-// needs no branch around it (whose join would wait for it at once).
+// needs no branch around it (whose join would wait for it at once). The
+// address carries a per-lane zero the compiler cannot see through, so the
+// value stays per lane instead of being moved to a scalar register (and
+// waited for) right after the load.
 __device__ const int kNoStop = 0;
 template <bool STOP>
 __device__ __forceinline__ int stop_flag(const int *stop) {
-  if constexpr (STOP) return __hip_atomic_load((global_ptr<const int>)stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if constexpr (STOP) {
+    int zero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+    return __hip_atomic_load((global_ptr<const int>)stop + zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   return 0;
 }
 
@@ -879,13 +886,16 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
   const int x0 = txi * tile_x, y0 = tyi * tile_y;
   const int tid = (int)threadIdx.y * BX + (int)threadIdx.x;
   const int W = OX / tile_x, H = OY / tile_y;
-  if (near && tid < 32) {
-    const int r = tid >> 3, c = tid & 7;
-    const bool own = r >= 1 && r <= H && c >= 1 && c <= W;
-    s_near[r][c] = (c > W + 1 || r > H + 1 || own)
-                       ? 0
-                       : load_global<unsigned char>(reinterpret_cast<const char *>(near),
-                                                    (unsigned)((tyi - 1 + r) * p.ntx + txi - 1 + c));
+  // the near flags of the tiles around the group: wave 0 issues their loads
+  // ahead of its first-step loads and stores them to LDS after those, just
+  // before the first barrier (the first point they are read), so no wave
+  // waits on them before its own loads go out
+  const int nr = tid >> 3, nc = tid & 7;
+  const bool nwin = tid < 32 && nc <= W + 1 && nr <= H + 1 && !(nr >= 1 && nr <= H && nc >= 1 && nc <= W);
+  unsigned char nflag = 0;
+  if (near && tid < 64) {  // wave 0 (uniform)
+    const unsigned idx = nwin ? (unsigned)((tyi - 1 + nr) * p.ntx + txi - 1 + nc) : 0u;
+    nflag = __hip_atomic_load((global_ptr<const unsigned char>)near + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   const CollK<T> &K = coll<T>(p);
   const ForceK<T> &F = gforce<T>(p);
@@ -932,6 +942,7 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
       for (int q = 0; q < 9; ++q) s_f[q][jb][ib] = out[q];
     }
   }
+  if (near && tid < 32) s_near[nr][nc] = nwin ? nflag : 0;
   __syncthreads();
   const unsigned *nw = reinterpret_cast<const unsigned *>(&s_near[0][0]);
   const bool ring = near && (nw[0] | nw[1] | nw[2] | nw[3] | nw[4] | nw[5] | nw[6] | nw[7]) != 0;
