@@ -41,6 +41,8 @@ def parse():
     p.add_argument("--overlap", type=int, default=-1, help="1/0: marker kernel beside the lattice kernel (-1: library default)")
     p.add_argument("--blocking", type=int, default=-1,
                    help="steps per pass away from the bodies: 0 off, 1 deepest, 2 or 3 (-1: library default)")
+    p.add_argument("--split-steps", type=int, default=3000,
+                   help="steps of the separate per-kernel timing run (HIP events around each launch)")
     p.add_argument("--group-shape", type=int, default=-1,
                    help="three-step pass groups: 0 along rows, 1 two tiles tall (-1: library default)")
     p.add_argument("--plane-pad", type=int, default=0)
@@ -325,10 +327,22 @@ def main():
     depth = sim.get_option(_lib.OPT_STEPS_PER_PASS)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ms_ib, ms_single, ms_pass = sim.step_timed_split(args.steps)
+    if fused_tiles > 0:
+        # the timed region: HIP events around the blocked pass's launches only
+        # (events around every launch would add about 2% to a step)
+        ms_pass = sim.step_timed_pass(args.steps)
+    else:
+        ms_ib, ms_single, ms_pass = sim.step_timed_split(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sim.forces()  # surfaces an instability as an error
+    split_steps = args.steps
+    if fused_tiles > 0:
+        # the other kernels' times: events around every launch, in a separate
+        # run after the timed region
+        split_steps = max(depth, min(args.steps, args.split_steps) // depth * depth)
+        ms_ib, ms_single, _ = sim.step_timed_split(split_steps)
+        sim.forces()
 
     n = case.nodes
     wall = t1 - t0
@@ -385,8 +399,10 @@ def main():
                    "blocked_nodes_frac": round(launch_nodes / n, 4) if fused_tiles else 0.0},
         "kernel_ms": dict([("ib_kernel", round(ms_ib, 5)), ("lbm_kernel", round(ms_single, 5))] +
                           ([(kernel, round(launch_ms, 5))] if fused_tiles > 0 else [])),
-        "kernel_ms_note": "ib_kernel and lbm_kernel: per step" +
-                          ("; %s: per launch (%d steps)" % (kernel, depth) if fused_tiles > 0 else ""),
+        "kernel_ms_note": ("%s: per launch (%d steps), HIP events around its launches over the timed steps; "
+                           "ib_kernel and lbm_kernel: per step, events around every launch over %d further steps"
+                           % (kernel, depth, split_steps)) if fused_tiles > 0 else
+                          "ib_kernel and lbm_kernel: per step, HIP events around every launch over the timed steps",
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": kernel, "bytes_per_update": bytes_per_update,

@@ -261,6 +261,14 @@ int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm);
  * all means per step. */
 int btdf_step_timed_split(btdf_t *h, int64_t n, double *ms);
 
+/* Same as btdf_step, timing only the blocked pass of temporal blocking: HIP
+ * events around the pass's launches alone (two per pass, on the stream the
+ * pass runs on), so the recording costs the steps little. *ms_pass: the
+ * pass's mean launch duration divided by the steps per pass, in milliseconds
+ * per step (0 when no pass ran: blocking off, or n below the steps per pass).
+ * Synchronising. Errors as btdf_step. */
+int btdf_step_timed_pass(btdf_t *h, int64_t n, double *ms_pass);
+
 /* Hydrodynamic force and torque on every body at the last step:
  * out[3*b + 0..2] = (Fx, Fy, Tz), Fx,y = -drs ds sum_l F_l (eq 27, sign:
  * force of the fluid on the body), Tz = -drs ds sum_l (X_l - c) x F_l.

@@ -89,6 +89,7 @@ SIGNATURES = {
     "btdf_get_marker_data": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp, _dp]),
     "btdf_marker_velocity": (ctypes.c_int, [_vp, _dp, _dp]),
     "btdf_step_timed_split": (ctypes.c_int, [_vp, _i64, _dp]),
+    "btdf_step_timed_pass": (ctypes.c_int, [_vp, _i64, _dp]),
     "btdf_set_body_motion": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "btdf_get_body_state": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "btdf_get_marker_positions": (ctypes.c_int, [_vp, _dp]),

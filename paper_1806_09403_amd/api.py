@@ -128,6 +128,12 @@ def btdf_step_timed_split(h, n):
     return tuple(float(v) for v in out)
 
 
+def btdf_step_timed_pass(h, n):
+    out = np.empty(1)
+    check(load().btdf_step_timed_pass(h, int(n), dptr(out)))
+    return float(out[0])
+
+
 def btdf_set_body_motion(h, body, vx, vy, omega):
     return check(load().btdf_set_body_motion(h, int(body), float(vx), float(vy), float(omega)))
 

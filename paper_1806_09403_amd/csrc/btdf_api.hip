@@ -1176,29 +1176,29 @@ static int enqueue_pair(btdf_t *h, const LbmParams &p, const IbParams &ib, hipSt
     if (rc) return rc;
     HIPCHK(hipEventRecord(h->ev_fork, s));
     HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-    if (ev) HIPCHK(hipEventRecord(ev[5], h->side));
+    if (ev && ev[5]) HIPCHK(hipEventRecord(ev[5], h->side));
     HIPCHK(launch_two_step(h, A, B, X, nullptr, p, fm, h->side));
-    if (ev) HIPCHK(hipEventRecord(ev[6], h->side));
+    if (ev && ev[6]) HIPCHK(hipEventRecord(ev[6], h->side));
     HIPCHK(hipEventRecord(h->ev_join, h->side));
   }
-  if (ev) HIPCHK(hipEventRecord(ev[0], s));
+  if (ev && ev[0]) HIPCHK(hipEventRecord(ev[0], s));
   HIPCHK(launch_ib(h->prec, A, p, ib, s));
-  if (ev) HIPCHK(hipEventRecord(ev[1], s));
+  if (ev && ev[1]) HIPCHK(hipEventRecord(ev[1], s));
   if (!ov) {
-    if (ev) HIPCHK(hipEventRecord(ev[5], s));
+    if (ev && ev[5]) HIPCHK(hipEventRecord(ev[5], s));
     HIPCHK(launch_two_step(h, A, B, X, near, p, fm, s));
-    if (ev) HIPCHK(hipEventRecord(ev[6], s));
+    if (ev && ev[6]) HIPCHK(hipEventRecord(ev[6], s));
   }
   const int nb0 = h->n_quad + h->n_wide + h->n_fused;  // the near tiles start here in the map
   HIPCHK(launch_lbm(h->prec, h->variant, A, X, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
   if (ov) HIPCHK(launch_ring(h->prec, A, X, p, fm + nb0, h->n_near, near, h->tile_x, h->tile_y, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, A, X, p, s));
-  if (ev) HIPCHK(hipEventRecord(ev[2], s));
+  if (ev && ev[2]) HIPCHK(hipEventRecord(ev[2], s));
   HIPCHK(launch_ib(h->prec, X, p, ib, s));
-  if (ev) HIPCHK(hipEventRecord(ev[3], s));
+  if (ev && ev[3]) HIPCHK(hipEventRecord(ev[3], s));
   HIPCHK(launch_lbm(h->prec, h->variant, X, B, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, X, B, p, s));
-  if (ev) HIPCHK(hipEventRecord(ev[4], s));
+  if (ev && ev[4]) HIPCHK(hipEventRecord(ev[4], s));
   if (ov) HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
   h->cur ^= 1;
   h->steps += 2;
@@ -1239,36 +1239,36 @@ static int enqueue_triple(btdf_t *h, const LbmParams &p, const IbParams &ib, hip
     if (rc) return rc;
     HIPCHK(hipEventRecord(h->ev_fork, s));
     HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-    if (ev) HIPCHK(hipEventRecord(ev[5], h->side));
+    if (ev && ev[5]) HIPCHK(hipEventRecord(ev[5], h->side));
     HIPCHK(pass(h->side));
-    if (ev) HIPCHK(hipEventRecord(ev[6], h->side));
+    if (ev && ev[6]) HIPCHK(hipEventRecord(ev[6], h->side));
     HIPCHK(hipEventRecord(h->ev_join, h->side));
   }
-  if (ev) HIPCHK(hipEventRecord(ev[0], s));
+  if (ev && ev[0]) HIPCHK(hipEventRecord(ev[0], s));
   HIPCHK(launch_ib(h->prec, A, p, ib, s));
-  if (ev) HIPCHK(hipEventRecord(ev[1], s));
+  if (ev && ev[1]) HIPCHK(hipEventRecord(ev[1], s));
   HIPCHK(launch_lbm(h->prec, h->variant, A, X1, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, A, X1, p, s));
-  if (ev) HIPCHK(hipEventRecord(ev[2], s));
+  if (ev && ev[2]) HIPCHK(hipEventRecord(ev[2], s));
   if (!ov) {
-    if (ev) HIPCHK(hipEventRecord(ev[5], s));
+    if (ev && ev[5]) HIPCHK(hipEventRecord(ev[5], s));
     HIPCHK(pass(s));
-    if (ev) HIPCHK(hipEventRecord(ev[6], s));
+    if (ev && ev[6]) HIPCHK(hipEventRecord(ev[6], s));
   }
   HIPCHK(launch_ib(h->prec, X1, p, ib, s));
-  if (ev) HIPCHK(hipEventRecord(ev[3], s));
+  if (ev && ev[3]) HIPCHK(hipEventRecord(ev[3], s));
   if (ov) {
     HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
-    if (ev) HIPCHK(hipEventRecord(ev[9], s));
+    if (ev && ev[9]) HIPCHK(hipEventRecord(ev[9], s));
   }
   HIPCHK(launch_lbm(h->prec, h->variant, X1, X2, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, X1, X2, p, s));
-  if (ev) HIPCHK(hipEventRecord(ev[4], s));
+  if (ev && ev[4]) HIPCHK(hipEventRecord(ev[4], s));
   HIPCHK(launch_ib(h->prec, X2, p, ib, s));
-  if (ev) HIPCHK(hipEventRecord(ev[7], s));
+  if (ev && ev[7]) HIPCHK(hipEventRecord(ev[7], s));
   HIPCHK(launch_lbm(h->prec, h->variant, X2, B, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, X2, B, p, s));
-  if (ev) HIPCHK(hipEventRecord(ev[8], s));
+  if (ev && ev[8]) HIPCHK(hipEventRecord(ev[8], s));
   h->cur ^= 1;
   h->steps += 3;
   return ok();
@@ -1346,7 +1346,12 @@ static bool blocking_active(const btdf_t *h) {
 
 // per-step means over n timed steps: out[0] marker kernels, out[1] single-step
 // lattice kernels, out[2] the two-step kernel (per step, i.e. half a launch)
-static int timed_impl(btdf_t *h, int64_t n, double *out) {
+// n steps with HIP events around the launches: every launch of a step or a
+// pass (out: ms per step of the marker kernels, single-step lattice
+// launches, blocked pass), or with pass_only just the pass's launches (out[2]
+// only; single steps carry no events), which keeps the events' own cost out
+// of the steps being timed.
+static int timed_impl(btdf_t *h, int64_t n, double *out, bool pass_only = false) {
   if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; step the batch");
   if (n <= 0) return fail(BTDF_EINVAL, "step count must be > 0");
   int rc = ensure_device(h);
@@ -1355,7 +1360,8 @@ static int timed_impl(btdf_t *h, int64_t n, double *out) {
   const IbParams ib = make_ib(h);
   const int chunk = 256, NE = 10;  // events per entry
   std::vector<hipEvent_t> ev(NE * chunk, nullptr);
-  for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+  for (size_t i = 0; i < ev.size(); ++i)
+    if (!pass_only || i % NE == 5 || i % NE == 6) HIPCHK(hipEventCreate(&ev[i]));
   const bool ov = overlapping(h);
   const int d = h->depth;
   double tib = 0.0, tlbm = 0.0, tpair = 0.0;
@@ -1372,7 +1378,7 @@ static int timed_impl(btdf_t *h, int64_t n, double *out) {
       }
       if (moving && h->steps_to_rebin <= 0 && (rc = rebin(h))) break;
       const StepEvents te{ev[NE * k], ev[NE * k + 1], ev[NE * k + 2], ev[NE * k + 3], ev[NE * k + 4], ev[NE * k + 5]};
-      rc = enqueue_step(h, p, ib, h->cur, h->stream, &te);
+      rc = enqueue_step(h, p, ib, h->cur, h->stream, pass_only ? nullptr : &te);
       h->cur ^= 1;
       h->steps++;
       if (moving) {
@@ -1389,6 +1395,11 @@ static int timed_impl(btdf_t *h, int64_t n, double *out) {
     for (int k = 0; k < m; ++k) {
       float a = 0.f, b = 0.f, c = 0.f, e4 = 0.f, f = 0.f, g = 0.f, gg = 0.f;
       hipEvent_t *E = &ev[NE * k];
+      if (pass_only) {
+        if (pairs) (void)hipEventElapsedTime(&f, E[5], E[6]);
+        tpair += f;
+        continue;
+      }
       if (pairs) {
         (void)hipEventElapsedTime(&a, E[0], E[1]);
         // the near tiles' first step: after the first marker kernel in a
@@ -1444,6 +1455,15 @@ int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm) {
 int btdf_step_timed_split(btdf_t *h, int64_t n, double *ms) {
   if (!h || !ms) return fail(BTDF_EINVAL, "NULL argument");
   return timed_impl(h, n, ms);
+}
+
+int btdf_step_timed_pass(btdf_t *h, int64_t n, double *ms_pass) {
+  if (!h || !ms_pass) return fail(BTDF_EINVAL, "NULL argument");
+  double out[3];
+  int rc = timed_impl(h, n, out, true);
+  if (rc) return rc;
+  *ms_pass = out[2];
+  return ok();
 }
 
 int btdf_autotune(btdf_t *h, int64_t steps_per_trial, int *best_variant) {

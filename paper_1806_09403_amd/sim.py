@@ -102,6 +102,10 @@ class Sim:
         """Per-step ms of (marker kernels, single-step lattice kernels, blocked pass)."""
         return api.btdf_step_timed_split(self._workspace(), n)
 
+    def step_timed_pass(self, n):
+        """n steps timing only the blocked pass (ms per step; events around its launches alone)."""
+        return api.btdf_step_timed_pass(self._workspace(), n)
+
     @property
     def steps(self):
         """Steps taken so far."""

@@ -26,7 +26,9 @@ def run(c, blocking, steps, precision=4, options=None, timed=False):
     if fused:
         assert s.get_option(_lib.OPT_STEPS_PER_PASS) in ((2, 3) if blocking in (1, 3) else (blocking,))
     for n in steps:
-        if timed:
+        if timed == "pass":
+            s.step_timed_pass(n)
+        elif timed:
             s.step_timed_split(n)
         else:
             s.step(n)
@@ -81,7 +83,7 @@ def test_tall_groups_are_bit_identical(name, seed, nx, ny, bc, precision):
 
 
 @pytest.mark.parametrize("depth", [2, 3])
-@pytest.mark.parametrize("opts", ["passes", "implicit", "rkpm", "timed", "overlap", "overlap-timed"])
+@pytest.mark.parametrize("opts", ["passes", "implicit", "rkpm", "timed", "timed-pass", "overlap", "overlap-timed"])
 def test_blocking_with_other_features(opts, depth):
     """(With the overlap option the two-step pass runs on a second stream and
     the ring kernel, not the pass, gives the near tiles their neighbours'
@@ -89,9 +91,9 @@ def test_blocking_with_other_features(opts, depth):
     from paper_1806_09403_amd import _lib
     c = bodies_case(45, 384, 192, W.CHANNEL, kind=W.ROMA3)
     o = {"passes": {_lib.OPT_FORCING_PASSES: 3}, "implicit": {_lib.OPT_FORCING_METHOD: 1},
-         "rkpm": {_lib.OPT_FORCING_METHOD: 2}, "timed": {}, "overlap": {_lib.OPT_OVERLAP: 1},
+         "rkpm": {_lib.OPT_FORCING_METHOD: 2}, "timed": {}, "timed-pass": {}, "overlap": {_lib.OPT_OVERLAP: 1},
          "overlap-timed": {_lib.OPT_OVERLAP: 1}}[opts]
-    timed = opts.endswith("timed")
+    timed = "pass" if opts == "timed-pass" else opts.endswith("timed")
     ref = run(c, 0, (3, 10), 4, o, timed=timed)
     got = run(c, depth, (3, 10), 4, o, timed=timed)
     assert got[2] > 0
@@ -177,3 +179,19 @@ def test_blocked_passes_in_graphs(depth, chunk, shape):
         assert np.array_equal(got.force_history(200), ref.force_history(200)), n
     ref.close()
     got.close()
+
+
+@pytest.mark.parametrize("depth", [0, 2, 3])
+def test_pass_timing_reports_the_pass(depth):
+    """btdf_step_timed_pass: a positive time per step when passes ran, 0
+    without blocking; the steps are the same as plain ones."""
+    from paper_1806_09403_amd import Sim, _lib
+    c = bodies_case(48, 512, 256, W.FULLY_PERIODIC)
+    ref = run(c, 0, (10,))
+    s = Sim.from_case(c, precision=4)
+    s.set_option(_lib.OPT_TEMPORAL_BLOCKING, depth)
+    ms = s.step_timed_pass(10)
+    log("  depth %d: pass %.4f ms per step" % (depth, ms))
+    assert (ms > 0) == (depth > 0)
+    assert np.array_equal(s.populations(), ref[0])
+    s.close()
