@@ -891,10 +891,12 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
   // before the first barrier (the first point they are read), so no wave
   // waits on them before its own loads go out
   const int nr = tid >> 3, nc = tid & 7;
-  const bool nwin = tid < 32 && nc <= W + 1 && nr <= H + 1 && !(nr >= 1 && nr <= H && nc >= 1 && nc <= W);
   unsigned char nflag = 0;
   if (near && tid < 64) {  // wave 0 (uniform)
-    const unsigned idx = nwin ? (unsigned)((tyi - 1 + nr) * p.ntx + txi - 1 + nc) : 0u;
+    // lanes outside the window (and the group's own tiles) read the group's
+    // first tile, which is never near: 0 without a select on the loaded value
+    const bool nwin = tid < 32 && nc <= W + 1 && nr <= H + 1 && !(nr >= 1 && nr <= H && nc >= 1 && nc <= W);
+    const unsigned idx = nwin ? (unsigned)((tyi - 1 + nr) * p.ntx + txi - 1 + nc) : (unsigned)t;
     nflag = __hip_atomic_load((global_ptr<const unsigned char>)near + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   const CollK<T> &K = coll<T>(p);
@@ -942,7 +944,7 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
       for (int q = 0; q < 9; ++q) s_f[q][jb][ib] = out[q];
     }
   }
-  if (near && tid < 32) s_near[nr][nc] = nwin ? nflag : 0;
+  if (near && tid < 32) s_near[nr][nc] = nflag;
   __syncthreads();
   const unsigned *nw = reinterpret_cast<const unsigned *>(&s_near[0][0]);
   const bool ring = near && (nw[0] | nw[1] | nw[2] | nw[3] | nw[4] | nw[5] | nw[6] | nw[7]) != 0;
