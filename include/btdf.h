@@ -428,14 +428,25 @@ size_t btdf_adjoint_workspace_bytes(btdf_t *h, int64_t n_steps, int64_t checkpoi
 int btdf_adjoint(btdf_t *h, int64_t n_steps, int64_t checkpoint_every, const double *hist_bar,
                  btdf_gradients *grads, void *work, size_t work_bytes, double *ms);
 
-/* Boundary-thickness calibration on the host (no device), Section 2.3:
- * A_ij = (1/dh^2) sum_k phi_ik phi_kj dh ds (eq 22) over the stencil nodes
- * of the n markers xy ([n][2], host), drs_vec = dh A^{-1} 1 (eq 25) and
- * drs = mean(drs_vec) (eq 26), with dh = 1. *drs_mean receives the mean,
- * drs_per_marker (length n, may be NULL) the local values. Errors: EINVAL
- * (n < 1, bad kind, ds <= 0), ESTATE (A singular to working precision). */
-int btdf_calibrate_thickening(int delta_kind, int n, const double *xy, double ds,
-                              double *drs_mean, double *drs_per_marker);
+/* Boundary-thickness calibration on the host (no device), Section 2.3, for
+ * a circular body of diameter D with n_markers equally spaced markers
+ * X_l = (D/2)(cos t_l, sin t_l), t_l = 2 pi l / n_markers, about a node, and
+ * ds = pi D / n_markers: the calibration below on that ring. *drs_mean
+ * receives drs/dh of eq 26, drs_per_marker (length n_markers, may be NULL)
+ * the local values of eq 25. Errors: EINVAL (D <= 0, n_markers < 3, bad
+ * kind, NULL drs_mean), ESTATE (A singular to working precision: markers
+ * much denser than the grid). */
+int btdf_calibrate_thickening(int delta_kind, double D, int n_markers, double *drs_mean,
+                              double *drs_per_marker);
+
+/* The same calibration for any marker set: A_ij = (1/dh^2) sum_k phi_ik
+ * phi_kj dh ds (eq 22) over the stencil nodes of the n markers xy ([n][2],
+ * host), drs_vec = dh A^{-1} 1 (eq 25) and drs = mean(drs_vec) (eq 26),
+ * with dh = 1. *drs_mean receives the mean, drs_per_marker (length n, may be
+ * NULL) the local values. Errors: EINVAL (n < 1, bad kind, ds <= 0), ESTATE
+ * (A singular to working precision). */
+int btdf_calibrate_thickening_markers(int delta_kind, int n, const double *xy, double ds,
+                                      double *drs_mean, double *drs_per_marker);
 
 #ifdef __cplusplus
 }

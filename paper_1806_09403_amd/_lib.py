@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libbtdf.so")
+# BTDF_LIBRARY may name another build of the same library (the host
+# sanitizer build of the tests); by default the in-tree libbtdf.so
+LIB_PATH = os.environ.get("BTDF_LIBRARY") or os.path.join(PKG, "libbtdf.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSTABLE = 0, -1, -2, -3, -4, -5
 PERIODIC, VELOCITY_INLET, ZERO_GRADIENT_OUTLET, BOUNCEBACK_WALL = 0, 1, 2, 3
@@ -100,8 +102,9 @@ SIGNATURES = {
                                    ctypes.POINTER(_i64)]),
     "btdf_set_option": (ctypes.c_int, [_vp, ctypes.c_int, _i64]),
     "btdf_get_option": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_i64)]),
-    "btdf_calibrate_thickening": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double,
-                                                 _dp, _dp]),
+    "btdf_calibrate_thickening": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp, _dp]),
+    "btdf_calibrate_thickening_markers": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double,
+                                                         _dp, _dp]),
     "btdf_autotune": (ctypes.c_int, [_vp, _i64, ctypes.POINTER(ctypes.c_int)]),
     "btdf_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(btdf_grid), _dp,
                                          ctypes.POINTER(ctypes.c_int), _dp, ctypes.POINTER(_vp)]),

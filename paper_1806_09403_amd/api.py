@@ -184,13 +184,21 @@ def btdf_get_option(h, key):
     return v.value
 
 
-def btdf_calibrate_thickening(delta_kind, xy, ds):
+def btdf_calibrate_thickening(delta_kind, D, n_markers):
+    mean = ctypes.c_double()
+    per = np.empty(int(n_markers))
+    check(load().btdf_calibrate_thickening(int(delta_kind), float(D), int(n_markers), ctypes.byref(mean),
+                                           dptr(per)))
+    return mean.value, per
+
+
+def btdf_calibrate_thickening_markers(delta_kind, xy, ds):
     xy = f64(xy, (-1, 2))
     n = xy.shape[0]
     mean = ctypes.c_double()
     per = np.empty(n)
-    check(load().btdf_calibrate_thickening(int(delta_kind), n, dptr(xy), float(ds),
-                                           ctypes.byref(mean), dptr(per)))
+    check(load().btdf_calibrate_thickening_markers(int(delta_kind), n, dptr(xy), float(ds),
+                                                   ctypes.byref(mean), dptr(per)))
     return mean.value, per
 
 

@@ -536,30 +536,34 @@ int adjoint_impl(btdf_t *h, int64_t n, int64_t K, const double *hist_bar, btdf_g
 extern "C" {
 
 size_t btdf_adjoint_workspace_bytes(btdf_t *h, int64_t n_steps, int64_t checkpoint_every) {
-  if (!h || n_steps < 1 || checkpoint_every < 0) return 0;
-  if (!h->layout_ok) compute_layout(h);
-  AdjLayout L;
-  adj_layout(h, n_steps, checkpoint_every, &L);
-  return L.total;
+  return guard_size([&]() -> size_t {
+    if (!h || n_steps < 1 || checkpoint_every < 0) return 0;
+    if (!h->layout_ok) compute_layout(h);
+    AdjLayout L;
+    adj_layout(h, n_steps, checkpoint_every, &L);
+    return L.total;
+  });
 }
 
 int btdf_adjoint(btdf_t *h, int64_t n_steps, int64_t checkpoint_every, const double *hist_bar,
                  btdf_gradients *grads, void *work, size_t work_bytes, double *ms) {
-  if (!h || !grads) return fail(BTDF_EINVAL, "NULL argument");
-  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch");
-  if (h->nf != 1) return fail(BTDF_ESTATE, "the reverse sweep needs one forcing pass per step (NF = 1)");
-  if (h->method != BTDF_FORCING_DIRECT) return fail(BTDF_ESTATE, "the reverse sweep covers the direct forcing only");
-  if (h->any_moving()) return fail(BTDF_ESTATE, "the reverse sweep covers fixed bodies only");
-  h->stepped = false;
-  if (h->bc[1] == BTDF_CONVECTIVE_OUTLET || h->bc[2] == BTDF_FREE_SLIP_WALL)
-    return fail(BTDF_EINVAL, "the reverse sweep covers periodic, bounce-back and zero-gradient boundaries only");
-  if (n_steps < 1) return fail(BTDF_EINVAL, "n_steps must be >= 1");
-  if (checkpoint_every < 0) return fail(BTDF_EINVAL, "checkpoint_every must be >= 0");
-  if (h->nb() > 0 && !hist_bar) return fail(BTDF_EINVAL, "hist_bar is NULL");
-  int rc = ensure_device(h);
-  if (rc) return rc;
-  if ((rc = check_flag(h))) return rc;
-  return adjoint_impl(h, n_steps, checkpoint_every, hist_bar, grads, (char *)work, work_bytes, ms);
+  return guard([&]() -> int {
+    if (!h || !grads) return fail(BTDF_EINVAL, "NULL argument");
+    if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch");
+    if (h->nf != 1) return fail(BTDF_ESTATE, "the reverse sweep needs one forcing pass per step (NF = 1)");
+    if (h->method != BTDF_FORCING_DIRECT) return fail(BTDF_ESTATE, "the reverse sweep covers the direct forcing only");
+    if (h->any_moving()) return fail(BTDF_ESTATE, "the reverse sweep covers fixed bodies only");
+    h->stepped = false;
+    if (h->bc[1] == BTDF_CONVECTIVE_OUTLET || h->bc[2] == BTDF_FREE_SLIP_WALL)
+      return fail(BTDF_EINVAL, "the reverse sweep covers periodic, bounce-back and zero-gradient boundaries only");
+    if (n_steps < 1) return fail(BTDF_EINVAL, "n_steps must be >= 1");
+    if (checkpoint_every < 0) return fail(BTDF_EINVAL, "checkpoint_every must be >= 0");
+    if (h->nb() > 0 && !hist_bar) return fail(BTDF_EINVAL, "hist_bar is NULL");
+    int rc = ensure_device(h);
+    if (rc) return rc;
+    if ((rc = check_flag(h))) return rc;
+    return adjoint_impl(h, n_steps, checkpoint_every, hist_bar, grads, (char *)work, work_bytes, ms);
+  });
 }
 
 }  // extern "C"

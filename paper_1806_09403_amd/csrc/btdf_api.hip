@@ -24,15 +24,15 @@ using namespace btdf;
 namespace btdf {
 namespace host {
 
-thread_local std::string g_err;
+// the last failure's message on this thread: a fixed buffer, so reporting
+// an error (an allocation failure included) allocates nothing
+thread_local char g_err[512] = "";
 
-int fail(int code, const char *fmt, ...) {
-  char buf[512];
+int fail(int code, const char *fmt, ...) noexcept {
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
   va_end(ap);
-  g_err = buf;
   return code;
 }
 
@@ -872,168 +872,188 @@ using namespace btdf::host;
 
 extern "C" {
 
-const char *btdf_last_error(void) { return g_err.c_str(); }
+const char *btdf_last_error(void) { return g_err; }
 
 int btdf_create(const btdf_grid *g, double tau, int delta_kind, double thickening, btdf_t **out) {
-  if (!g || !out) return fail(BTDF_EINVAL, "NULL argument");
-  *out = nullptr;
-  if (g->nx < 8 || g->ny < 8) return fail(BTDF_EINVAL, "nx and ny must be >= 8 (got %d, %d)", g->nx, g->ny);
-  if ((long long)g->nx * g->ny > (1LL << 31) - 1) return fail(BTDF_EINVAL, "grid too large");
-  if (!(tau > 0.5) || !std::isfinite(tau)) return fail(BTDF_EINVAL, "tau must be > 1/2 (got %g)", tau);
-  if (!valid_kind(delta_kind)) return fail(BTDF_EINVAL, "unknown delta kind %d", delta_kind);
-  if (!(thickening > 0.0) || !std::isfinite(thickening))
-    return fail(BTDF_EINVAL, "thickening must be > 0 (got %g)", thickening);
-  const bool xp = g->bc_west == BTDF_PERIODIC && g->bc_east == BTDF_PERIODIC;
-  const bool xc = g->bc_west == BTDF_VELOCITY_INLET &&
-                  (g->bc_east == BTDF_ZERO_GRADIENT_OUTLET || g->bc_east == BTDF_CONVECTIVE_OUTLET);
-  const bool yp = g->bc_south == BTDF_PERIODIC && g->bc_north == BTDF_PERIODIC;
-  const bool yw = g->bc_south == g->bc_north &&
-                  (g->bc_south == BTDF_BOUNCEBACK_WALL || g->bc_south == BTDF_FREE_SLIP_WALL);
-  if (!(xp || xc)) return fail(BTDF_EINVAL, "x ends must be a periodic pair or inlet (west) + outlet (east)");
-  if (!(yp || yw)) return fail(BTDF_EINVAL, "y ends must be a periodic pair or a pair of walls of one kind");
-  if (g->bc_east == BTDF_CONVECTIVE_OUTLET && !(g->inflow_ux >= 0.0))
-    return fail(BTDF_EINVAL, "a convective outlet needs an inflow speed >= 0 (got %g)", g->inflow_ux);
-  if (g->precision != 4 && g->precision != 8) return fail(BTDF_EINVAL, "precision must be 4 or 8");
-  if (g->history_capacity < 0) return fail(BTDF_EINVAL, "history_capacity must be >= 0");
-  if (g->flags != 0) return fail(BTDF_EINVAL, "flags must be 0");
-  const double vals[] = {g->inflow_ux, g->inflow_uy, g->body_force_x, g->body_force_y, g->rho0, g->ux0, g->uy0};
-  for (double v : vals)
-    if (!std::isfinite(v)) return fail(BTDF_EINVAL, "non-finite grid parameter");
-  if (!(g->rho0 > 0.0)) return fail(BTDF_EINVAL, "rho0 must be > 0");
+  return guard([&]() -> int {
+    if (!g || !out) return fail(BTDF_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (g->nx < 8 || g->ny < 8) return fail(BTDF_EINVAL, "nx and ny must be >= 8 (got %d, %d)", g->nx, g->ny);
+    if ((long long)g->nx * g->ny > (1LL << 31) - 1) return fail(BTDF_EINVAL, "grid too large");
+    if (!(tau > 0.5) || !std::isfinite(tau)) return fail(BTDF_EINVAL, "tau must be > 1/2 (got %g)", tau);
+    if (!valid_kind(delta_kind)) return fail(BTDF_EINVAL, "unknown delta kind %d", delta_kind);
+    if (!(thickening > 0.0) || !std::isfinite(thickening))
+      return fail(BTDF_EINVAL, "thickening must be > 0 (got %g)", thickening);
+    const bool xp = g->bc_west == BTDF_PERIODIC && g->bc_east == BTDF_PERIODIC;
+    const bool xc = g->bc_west == BTDF_VELOCITY_INLET &&
+                    (g->bc_east == BTDF_ZERO_GRADIENT_OUTLET || g->bc_east == BTDF_CONVECTIVE_OUTLET);
+    const bool yp = g->bc_south == BTDF_PERIODIC && g->bc_north == BTDF_PERIODIC;
+    const bool yw = g->bc_south == g->bc_north &&
+                    (g->bc_south == BTDF_BOUNCEBACK_WALL || g->bc_south == BTDF_FREE_SLIP_WALL);
+    if (!(xp || xc)) return fail(BTDF_EINVAL, "x ends must be a periodic pair or inlet (west) + outlet (east)");
+    if (!(yp || yw)) return fail(BTDF_EINVAL, "y ends must be a periodic pair or a pair of walls of one kind");
+    if (g->bc_east == BTDF_CONVECTIVE_OUTLET && !(g->inflow_ux >= 0.0))
+      return fail(BTDF_EINVAL, "a convective outlet needs an inflow speed >= 0 (got %g)", g->inflow_ux);
+    if (g->precision != 4 && g->precision != 8) return fail(BTDF_EINVAL, "precision must be 4 or 8");
+    if (g->history_capacity < 0) return fail(BTDF_EINVAL, "history_capacity must be >= 0");
+    if (g->flags != 0) return fail(BTDF_EINVAL, "flags must be 0");
+    const double vals[] = {g->inflow_ux, g->inflow_uy, g->body_force_x, g->body_force_y, g->rho0, g->ux0, g->uy0};
+    for (double v : vals)
+      if (!std::isfinite(v)) return fail(BTDF_EINVAL, "non-finite grid parameter");
+    if (!(g->rho0 > 0.0)) return fail(BTDF_EINVAL, "rho0 must be > 0");
 
-  btdf_t *h = new (std::nothrow) btdf_sim();
-  if (!h) return fail(BTDF_ENOMEM, "out of host memory");
-  h->nx = g->nx;
-  h->ny = g->ny;
-  h->bc[0] = g->bc_west;
-  h->bc[1] = g->bc_east;
-  h->bc[2] = g->bc_south;
-  h->bc[3] = g->bc_north;
-  h->prec = g->precision;
-  h->hist_cap = g->history_capacity ? g->history_capacity : 4096;
-  h->kind = delta_kind;
-  h->tau = tau;
-  h->drs = thickening;
-  h->G[0] = g->body_force_x;
-  h->G[1] = g->body_force_y;
-  h->uin[0] = g->inflow_ux;
-  h->uin[1] = g->inflow_uy;
-  h->rho0 = g->rho0;
-  h->u0[0] = g->ux0;
-  h->u0[1] = g->uy0;
-  h->stream = (hipStream_t)g->hip_stream;
-  *out = h;
-  return ok();
+    btdf_t *h = new (std::nothrow) btdf_sim();
+    if (!h) return fail(BTDF_ENOMEM, "out of host memory");
+    h->nx = g->nx;
+    h->ny = g->ny;
+    h->bc[0] = g->bc_west;
+    h->bc[1] = g->bc_east;
+    h->bc[2] = g->bc_south;
+    h->bc[3] = g->bc_north;
+    h->prec = g->precision;
+    h->hist_cap = g->history_capacity ? g->history_capacity : 4096;
+    h->kind = delta_kind;
+    h->tau = tau;
+    h->drs = thickening;
+    h->G[0] = g->body_force_x;
+    h->G[1] = g->body_force_y;
+    h->uin[0] = g->inflow_ux;
+    h->uin[1] = g->inflow_uy;
+    h->rho0 = g->rho0;
+    h->u0[0] = g->ux0;
+    h->u0[1] = g->uy0;
+    h->stream = (hipStream_t)g->hip_stream;
+    *out = h;
+    return ok();
+  });
 }
 
 int btdf_destroy(btdf_t *h) {
-  if (!h) return ok();
-  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; destroy the batch");
-  return destroy_impl(h);
+  return guard([&]() -> int {
+    if (!h) return ok();
+    if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; destroy the batch");
+    return destroy_impl(h);
+  });
 }
 
 size_t btdf_workspace_bytes(const btdf_t *h) {
-  if (!h) return 0;
-  if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
-  return h->total;
+  return guard_size([&]() -> size_t {
+    if (!h) return 0;
+    if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
+    return h->total;
+  });
 }
 
 int btdf_bind_workspace(btdf_t *h, void *dev, size_t bytes) {
-  if (!h) return fail(BTDF_EINVAL, "NULL handle");
-  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; bind the batch's workspace");
-  return bind_impl(h, dev, bytes);
+  return guard([&]() -> int {
+    if (!h) return fail(BTDF_EINVAL, "NULL handle");
+    if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; bind the batch's workspace");
+    return bind_impl(h, dev, bytes);
+  });
 }
 
 int btdf_set_stream(btdf_t *h, void *hip_stream) {
-  if (!h) return fail(BTDF_EINVAL, "NULL handle");
-  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; set the batch's stream");
-  if (h->ws && (hipStream_t)hip_stream != h->stream) {
-    // order the new stream after the work already on the old one
-    HIPCHK(hipStreamSynchronize(h->stream));
-  }
-  h->stream = (hipStream_t)hip_stream;
-  return ok();
+  return guard([&]() -> int {
+    if (!h) return fail(BTDF_EINVAL, "NULL handle");
+    if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; set the batch's stream");
+    if (h->ws && (hipStream_t)hip_stream != h->stream) {
+      // order the new stream after the work already on the old one
+      HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    h->stream = (hipStream_t)hip_stream;
+    return ok();
+  });
 }
 
 int btdf_add_body(btdf_t *h, int n, const double *xy, const double *uv, double cx, double cy, double ds,
                   int *body_id) {
-  if (!h || !xy) return fail(BTDF_EINVAL, "NULL argument");
-  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; use btdf_batch_add_body");
-  return add_body_impl(h, n, xy, uv, cx, cy, ds, body_id);
+  return guard([&]() -> int {
+    if (!h || !xy) return fail(BTDF_EINVAL, "NULL argument");
+    if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; use btdf_batch_add_body");
+    return add_body_impl(h, n, xy, uv, cx, cy, ds, body_id);
+  });
 }
 
 int btdf_set_body_motion(btdf_t *h, int body, double vx, double vy, double omega) {
-  if (!h) return fail(BTDF_EINVAL, "NULL handle");
-  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch");
-  if (body < 0 || body >= h->nb()) return fail(BTDF_EINVAL, "no body %d", body);
-  if (!std::isfinite(vx) || !std::isfinite(vy) || !std::isfinite(omega)) return fail(BTDF_EINVAL, "non-finite motion");
-  if (h->method != BTDF_FORCING_DIRECT || h->nf != 1)
-    return fail(BTDF_ESTATE, "moving bodies need the direct forcing method with one pass");
-  const double v = std::hypot(vx, vy) + std::fabs(omega) * h->brad[body];
-  if (!(v < kMoveMargin)) return fail(BTDF_EINVAL, "markers would travel %g nodes per step (at most %d)", v, kMoveMargin);
-  const bool first = !h->any_moving();
-  mirror_positions(h);  // where a body already moving is now
-  h->bmoving[body] = 1;
-  h->bvx[body] = vx;
-  h->bvy[body] = vy;
-  h->bom[body] = omega;
-  mirror_positions(h);  // and the rigid velocity field at those positions
-  if (first) h->layout_ok = false;  // tile lists gain their margin
-  h->device_ok = false;
-  h->steps_to_rebin = 0;
-  drop_graph(h);
-  return ok();
+  return guard([&]() -> int {
+    if (!h) return fail(BTDF_EINVAL, "NULL handle");
+    if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch");
+    if (body < 0 || body >= h->nb()) return fail(BTDF_EINVAL, "no body %d", body);
+    if (!std::isfinite(vx) || !std::isfinite(vy) || !std::isfinite(omega)) return fail(BTDF_EINVAL, "non-finite motion");
+    if (h->method != BTDF_FORCING_DIRECT || h->nf != 1)
+      return fail(BTDF_ESTATE, "moving bodies need the direct forcing method with one pass");
+    const double v = std::hypot(vx, vy) + std::fabs(omega) * h->brad[body];
+    if (!(v < kMoveMargin)) return fail(BTDF_EINVAL, "markers would travel %g nodes per step (at most %d)", v, kMoveMargin);
+    const bool first = !h->any_moving();
+    mirror_positions(h);  // where a body already moving is now
+    h->bmoving[body] = 1;
+    h->bvx[body] = vx;
+    h->bvy[body] = vy;
+    h->bom[body] = omega;
+    mirror_positions(h);  // and the rigid velocity field at those positions
+    if (first) h->layout_ok = false;  // tile lists gain their margin
+    h->device_ok = false;
+    h->steps_to_rebin = 0;
+    drop_graph(h);
+    return ok();
+  });
 }
 
 int btdf_get_body_state(const btdf_t *h, int body, double *state) {
-  if (!h || !state) return fail(BTDF_EINVAL, "NULL argument");
-  if (body < 0 || body >= h->nb()) return fail(BTDF_EINVAL, "no body %d", body);
-  state[0] = h->cx[body];
-  state[1] = h->cy[body];
-  state[2] = h->theta[body];
-  state[3] = h->bvx[body];
-  state[4] = h->bvy[body];
-  state[5] = h->bom[body];
-  return ok();
+  return guard([&]() -> int {
+    if (!h || !state) return fail(BTDF_EINVAL, "NULL argument");
+    if (body < 0 || body >= h->nb()) return fail(BTDF_EINVAL, "no body %d", body);
+    state[0] = h->cx[body];
+    state[1] = h->cy[body];
+    state[2] = h->theta[body];
+    state[3] = h->bvx[body];
+    state[4] = h->bvy[body];
+    state[5] = h->bom[body];
+    return ok();
+  });
 }
 
 int btdf_get_marker_positions(btdf_t *h, double *xy) {
-  if (!h || !xy) return fail(BTDF_EINVAL, "NULL argument");
-  int rc = ensure_device(h);
-  if (rc) return rc;
-  HIPCHK(hipStreamSynchronize(h->stream));
-  const size_t nm = (size_t)h->nm(), d = sizeof(double);
-  if (nm == 0) return ok();
-  std::vector<double> x(nm), y(nm);
-  HIPCHK(hipMemcpy(x.data(), h->ws + h->off_mk, nm * d, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(y.data(), h->ws + h->off_mk + (size_t)std::max(h->nm(), 1) * d, nm * d, hipMemcpyDeviceToHost));
-  for (size_t l = 0; l < nm; ++l) {
-    xy[2 * l] = x[l];
-    xy[2 * l + 1] = y[l];
-  }
-  return ok();
+  return guard([&]() -> int {
+    if (!h || !xy) return fail(BTDF_EINVAL, "NULL argument");
+    int rc = ensure_device(h);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const size_t nm = (size_t)h->nm(), d = sizeof(double);
+    if (nm == 0) return ok();
+    std::vector<double> x(nm), y(nm);
+    HIPCHK(hipMemcpy(x.data(), h->ws + h->off_mk, nm * d, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(y.data(), h->ws + h->off_mk + (size_t)std::max(h->nm(), 1) * d, nm * d, hipMemcpyDeviceToHost));
+    for (size_t l = 0; l < nm; ++l) {
+      xy[2 * l] = x[l];
+      xy[2 * l + 1] = y[l];
+    }
+    return ok();
+  });
 }
 
 int btdf_set_marker_velocity(btdf_t *h, int body, const double *uv) {
-  if (!h || !uv) return fail(BTDF_EINVAL, "NULL argument");
-  if (body < 0 || body >= h->nb()) return fail(BTDF_EINVAL, "no body %d", body);
-  if (h->bmoving[body]) return fail(BTDF_ESTATE, "body %d moves rigidly; its marker velocities follow the motion", body);
-  const int l0 = h->off[body], l1 = h->off[body + 1];
-  for (int l = l0; l < l1; ++l)
-    if (!std::isfinite(uv[2 * (l - l0)]) || !std::isfinite(uv[2 * (l - l0) + 1]))
-      return fail(BTDF_EINVAL, "non-finite velocity");
-  for (int l = l0; l < l1; ++l) {
-    h->U[l] = uv[2 * (l - l0)];
-    h->V[l] = uv[2 * (l - l0) + 1];
-  }
-  if (h->ws && h->device_ok) {
-    const size_t M = (size_t)std::max(h->nm(), 1), d = sizeof(double);
-    int rc;
-    if ((rc = upload(h, h->off_mk + 2 * M * d + l0 * d, h->U.data() + l0, (l1 - l0) * d))) return rc;
-    if ((rc = upload(h, h->off_mk + 3 * M * d + l0 * d, h->V.data() + l0, (l1 - l0) * d))) return rc;
-    HIPCHK(hipStreamSynchronize(h->stream));
-  }
-  return ok();
+  return guard([&]() -> int {
+    if (!h || !uv) return fail(BTDF_EINVAL, "NULL argument");
+    if (body < 0 || body >= h->nb()) return fail(BTDF_EINVAL, "no body %d", body);
+    if (h->bmoving[body]) return fail(BTDF_ESTATE, "body %d moves rigidly; its marker velocities follow the motion", body);
+    const int l0 = h->off[body], l1 = h->off[body + 1];
+    for (int l = l0; l < l1; ++l)
+      if (!std::isfinite(uv[2 * (l - l0)]) || !std::isfinite(uv[2 * (l - l0) + 1]))
+        return fail(BTDF_EINVAL, "non-finite velocity");
+    for (int l = l0; l < l1; ++l) {
+      h->U[l] = uv[2 * (l - l0)];
+      h->V[l] = uv[2 * (l - l0) + 1];
+    }
+    if (h->ws && h->device_ok) {
+      const size_t M = (size_t)std::max(h->nm(), 1), d = sizeof(double);
+      int rc;
+      if ((rc = upload(h, h->off_mk + 2 * M * d + l0 * d, h->U.data() + l0, (l1 - l0) * d))) return rc;
+      if ((rc = upload(h, h->off_mk + 3 * M * d + l0 * d, h->V.data() + l0, (l1 - l0) * d))) return rc;
+      HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    return ok();
+  });
 }
 
 static int enqueue_pass(btdf_t *h, const LbmParams &p, const IbParams &ib, hipStream_t s, hipEvent_t *ev);
@@ -1116,30 +1136,32 @@ static int rebin(btdf_t *h) {
 }
 
 int btdf_step(btdf_t *h, int64_t n) {
-  if (!h) return fail(BTDF_EINVAL, "NULL handle");
-  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; step the batch");
-  if (n < 0) return fail(BTDF_EINVAL, "negative step count");
-  if (n == 0) return ok();
-  int rc = ensure_device(h);
-  if (rc) return rc;
-  const LbmParams p = make_params(h);
-  const IbParams ib = make_ib(h);
-  if (blocking_active(h) && n >= h->depth) {
-    if ((rc = run_blocked(h, p, ib, n))) return rc;
-  } else if (!h->any_moving()) {
-    if ((rc = run_steps(h, p, ib, n))) return rc;
-  } else {
-    for (int64_t left = n; left > 0;) {
-      if (h->steps_to_rebin <= 0 && (rc = rebin(h))) return rc;
-      const int64_t k = std::min(left, h->steps_to_rebin);
-      if ((rc = run_steps(h, p, ib, k))) return rc;
-      mirror_advance(h, k);
-      h->steps_to_rebin -= k;
-      left -= k;
+  return guard([&]() -> int {
+    if (!h) return fail(BTDF_EINVAL, "NULL handle");
+    if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; step the batch");
+    if (n < 0) return fail(BTDF_EINVAL, "negative step count");
+    if (n == 0) return ok();
+    int rc = ensure_device(h);
+    if (rc) return rc;
+    const LbmParams p = make_params(h);
+    const IbParams ib = make_ib(h);
+    if (blocking_active(h) && n >= h->depth) {
+      if ((rc = run_blocked(h, p, ib, n))) return rc;
+    } else if (!h->any_moving()) {
+      if ((rc = run_steps(h, p, ib, n))) return rc;
+    } else {
+      for (int64_t left = n; left > 0;) {
+        if (h->steps_to_rebin <= 0 && (rc = rebin(h))) return rc;
+        const int64_t k = std::min(left, h->steps_to_rebin);
+        if ((rc = run_steps(h, p, ib, k))) return rc;
+        mirror_advance(h, k);
+        h->steps_to_rebin -= k;
+        left -= k;
+      }
     }
-  }
-  h->stepped = true;
-  return ok();
+    h->stepped = true;
+    return ok();
+  });
 }
 
 // two steps from buffer cur into 1 - cur (temporal blocking): the tiles near
@@ -1443,514 +1465,570 @@ static int timed_impl(btdf_t *h, int64_t n, double *out, bool pass_only = false)
 }
 
 int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm) {
-  if (!h || !ms_ib || !ms_lbm) return fail(BTDF_EINVAL, "NULL argument");
-  double out[3];
-  int rc = timed_impl(h, n, out);
-  if (rc) return rc;
-  *ms_ib = out[0];
-  *ms_lbm = out[1] + out[2];
-  return ok();
+  return guard([&]() -> int {
+    if (!h || !ms_ib || !ms_lbm) return fail(BTDF_EINVAL, "NULL argument");
+    double out[3];
+    int rc = timed_impl(h, n, out);
+    if (rc) return rc;
+    *ms_ib = out[0];
+    *ms_lbm = out[1] + out[2];
+    return ok();
+  });
 }
 
 int btdf_step_timed_split(btdf_t *h, int64_t n, double *ms) {
-  if (!h || !ms) return fail(BTDF_EINVAL, "NULL argument");
-  return timed_impl(h, n, ms);
+  return guard([&]() -> int {
+    if (!h || !ms) return fail(BTDF_EINVAL, "NULL argument");
+    return timed_impl(h, n, ms);
+  });
 }
 
 int btdf_step_timed_pass(btdf_t *h, int64_t n, double *ms_pass) {
-  if (!h || !ms_pass) return fail(BTDF_EINVAL, "NULL argument");
-  double out[3];
-  int rc = timed_impl(h, n, out, true);
-  if (rc) return rc;
-  *ms_pass = out[2];
-  return ok();
+  return guard([&]() -> int {
+    if (!h || !ms_pass) return fail(BTDF_EINVAL, "NULL argument");
+    double out[3];
+    int rc = timed_impl(h, n, out, true);
+    if (rc) return rc;
+    *ms_pass = out[2];
+    return ok();
+  });
 }
 
 int btdf_autotune(btdf_t *h, int64_t steps_per_trial, int *best_variant) {
-  if (!h) return fail(BTDF_EINVAL, "NULL handle");
-  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; tune the batch");
-  if (steps_per_trial < 1) return fail(BTDF_EINVAL, "steps_per_trial must be >= 1");
-  double best = 1e300;
-  int bv = h->variant, bi = h->interior;
-  for (int v = 0; v < num_variants(); ++v) {
-    for (int in = 0; in < 2; ++in) {
-      if (h->variant != v) {
-        h->variant = v;
-        h->layout_ok = false;  // (a shape that needs a larger workspace moves the state into one)
-      }
-      h->interior = in;
-      drop_graph(h);
-      double a = 0.0, l = 0.0;
-      int rc = btdf_step_timed(h, steps_per_trial, &a, &l);
-      if (rc) return rc;
-      if (a + l < best) {
-        best = a + l;
-        bv = v;
-        bi = in;
+  return guard([&]() -> int {
+    if (!h) return fail(BTDF_EINVAL, "NULL handle");
+    if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; tune the batch");
+    if (steps_per_trial < 1) return fail(BTDF_EINVAL, "steps_per_trial must be >= 1");
+    double best = 1e300;
+    int bv = h->variant, bi = h->interior;
+    for (int v = 0; v < num_variants(); ++v) {
+      for (int in = 0; in < 2; ++in) {
+        if (h->variant != v) {
+          h->variant = v;
+          h->layout_ok = false;  // (a shape that needs a larger workspace moves the state into one)
+        }
+        h->interior = in;
+        drop_graph(h);
+        double a = 0.0, l = 0.0;
+        int rc = btdf_step_timed(h, steps_per_trial, &a, &l);
+        if (rc) return rc;
+        if (a + l < best) {
+          best = a + l;
+          bv = v;
+          bi = in;
+        }
       }
     }
-  }
-  if (h->variant != bv) {
-    h->variant = bv;
-    h->layout_ok = false;
-  }
-  h->interior = bi;
-  drop_graph(h);
-  if (best_variant) *best_variant = bv;
-  return ok();
+    if (h->variant != bv) {
+      h->variant = bv;
+      h->layout_ok = false;
+    }
+    h->interior = bi;
+    drop_graph(h);
+    if (best_variant) *best_variant = bv;
+    return ok();
+  });
 }
 
 int btdf_forces(btdf_t *h, double *out, int cap_bodies) {
-  if (!h || (!out && h->nb() > 0)) return fail(BTDF_EINVAL, "NULL argument");
-  if (cap_bodies < h->nb()) return fail(BTDF_EINVAL, "cap_bodies %d < %d bodies", cap_bodies, h->nb());
-  const int nb = h->nb();
-  if (h->steps == 0 || !h->ws) {
-    for (int k = 0; k < 3 * nb; ++k) out[k] = 0.0;
-    return h->ws ? check_flag(h) : ok();
-  }
-  int rc = ensure_device(h);
-  if (rc) return rc;
-  HIPCHK(hipStreamSynchronize(h->stream));
-  if (nb > 0) {
-    const long long slot = (h->steps - 1) % h->hist_cap;
-    if (h->steps <= h->forces_from) {
-      // no step since the body set changed or a state was loaded
+  return guard([&]() -> int {
+    if (!h || (!out && h->nb() > 0)) return fail(BTDF_EINVAL, "NULL argument");
+    if (cap_bodies < h->nb()) return fail(BTDF_EINVAL, "cap_bodies %d < %d bodies", cap_bodies, h->nb());
+    const int nb = h->nb();
+    if (h->steps == 0 || !h->ws) {
       for (int k = 0; k < 3 * nb; ++k) out[k] = 0.0;
-    } else {
-      HIPCHK(hipMemcpy(out, h->ws + h->off_hist + (size_t)slot * nb * 3 * sizeof(double),
-                       (size_t)nb * 3 * sizeof(double), hipMemcpyDeviceToHost));
+      return h->ws ? check_flag(h) : ok();
     }
-  }
-  return check_flag(h);
+    int rc = ensure_device(h);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (nb > 0) {
+      const long long slot = (h->steps - 1) % h->hist_cap;
+      if (h->steps <= h->forces_from) {
+        // no step since the body set changed or a state was loaded
+        for (int k = 0; k < 3 * nb; ++k) out[k] = 0.0;
+      } else {
+        HIPCHK(hipMemcpy(out, h->ws + h->off_hist + (size_t)slot * nb * 3 * sizeof(double),
+                         (size_t)nb * 3 * sizeof(double), hipMemcpyDeviceToHost));
+      }
+    }
+    return check_flag(h);
+  });
 }
 
 int btdf_force_history(btdf_t *h, double *out, int64_t max_steps, int64_t *n_written) {
-  if (!h || !n_written || (!out && max_steps > 0)) return fail(BTDF_EINVAL, "NULL argument");
-  *n_written = 0;
-  const int nb = h->nb();
-  if (!h->ws || nb == 0 || max_steps <= 0) {
-    h->hist_read = h->steps;
-    return h->ws ? check_flag(h) : ok();
-  }
-  int rc = ensure_device(h);
-  if (rc) return rc;
-  HIPCHK(hipStreamSynchronize(h->stream));
-  const int64_t pending = h->steps - std::max(h->hist_read, h->forces_from);
-  const int64_t avail = std::min<int64_t>(pending, h->hist_cap);
-  const int64_t first = h->steps - avail;
-  const int64_t cnt = std::min<int64_t>(avail, max_steps);
-  const size_t row = (size_t)nb * 3 * sizeof(double);
-  int64_t k = 0;
-  while (k < cnt) {
-    const int64_t slot = (first + k) % h->hist_cap;
-    const int64_t run = std::min<int64_t>(cnt - k, h->hist_cap - slot);
-    HIPCHK(hipMemcpy((char *)out + (size_t)k * row, h->ws + h->off_hist + (size_t)slot * row,
-                     (size_t)run * row, hipMemcpyDeviceToHost));
-    k += run;
-  }
-  h->hist_read = first + cnt;
-  *n_written = cnt;
-  return check_flag(h);
+  return guard([&]() -> int {
+    if (!h || !n_written || (!out && max_steps > 0)) return fail(BTDF_EINVAL, "NULL argument");
+    *n_written = 0;
+    const int nb = h->nb();
+    if (!h->ws || nb == 0 || max_steps <= 0) {
+      h->hist_read = h->steps;
+      return h->ws ? check_flag(h) : ok();
+    }
+    int rc = ensure_device(h);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const int64_t pending = h->steps - std::max(h->hist_read, h->forces_from);
+    const int64_t avail = std::min<int64_t>(pending, h->hist_cap);
+    const int64_t first = h->steps - avail;
+    const int64_t cnt = std::min<int64_t>(avail, max_steps);
+    const size_t row = (size_t)nb * 3 * sizeof(double);
+    int64_t k = 0;
+    while (k < cnt) {
+      const int64_t slot = (first + k) % h->hist_cap;
+      const int64_t run = std::min<int64_t>(cnt - k, h->hist_cap - slot);
+      HIPCHK(hipMemcpy((char *)out + (size_t)k * row, h->ws + h->off_hist + (size_t)slot * row,
+                       (size_t)run * row, hipMemcpyDeviceToHost));
+      k += run;
+    }
+    h->hist_read = first + cnt;
+    *n_written = cnt;
+    return check_flag(h);
+  });
 }
 
 int btdf_init_equilibrium(btdf_t *h, const double *rho, const double *ux, const double *uy) {
-  if (!h || !ux || !uy) return fail(BTDF_EINVAL, "NULL argument");
-  int rc = ensure_device(h);
-  if (rc) return rc;
-  const size_t n = (size_t)h->nx * h->ny, d = sizeof(double);
-  // stage the fields in the spare population buffer (at least 36 bytes per node)
-  double *st = h->at<double>(h->off_pop[1 - h->cur]);
-  HIPCHK(hipMemcpyAsync(st, ux, n * d, hipMemcpyHostToDevice, h->stream));
-  HIPCHK(hipMemcpyAsync(st + n, uy, n * d, hipMemcpyHostToDevice, h->stream));
-  if (rho) HIPCHK(hipMemcpyAsync(st + 2 * n, rho, n * d, hipMemcpyHostToDevice, h->stream));
-  LbmParams p = make_params(h);
-  HIPCHK(launch_init_eq(h->prec, h->ws + h->off_pop[h->cur], p, st + 2 * n, st, st + n, h->rho0, rho != nullptr,
-                        h->stream));
-  h->stepped = false;
-  if ((rc = clear_flag(h))) return rc;
-  HIPCHK(hipStreamSynchronize(h->stream));
-  return ok();
+  return guard([&]() -> int {
+    if (!h || !ux || !uy) return fail(BTDF_EINVAL, "NULL argument");
+    int rc = ensure_device(h);
+    if (rc) return rc;
+    const size_t n = (size_t)h->nx * h->ny, d = sizeof(double);
+    // stage the fields in the spare population buffer (at least 36 bytes per node)
+    double *st = h->at<double>(h->off_pop[1 - h->cur]);
+    HIPCHK(hipMemcpyAsync(st, ux, n * d, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(st + n, uy, n * d, hipMemcpyHostToDevice, h->stream));
+    if (rho) HIPCHK(hipMemcpyAsync(st + 2 * n, rho, n * d, hipMemcpyHostToDevice, h->stream));
+    LbmParams p = make_params(h);
+    HIPCHK(launch_init_eq(h->prec, h->ws + h->off_pop[h->cur], p, st + 2 * n, st, st + n, h->rho0, rho != nullptr,
+                          h->stream));
+    h->stepped = false;
+    if ((rc = clear_flag(h))) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return ok();
+  });
 }
 
 int btdf_get_macroscopic(btdf_t *h, double *rho, double *ux, double *uy) {
-  if (!h || !rho || !ux || !uy) return fail(BTDF_EINVAL, "NULL argument");
-  int rc = ensure_device(h);
-  if (rc) return rc;
-  const size_t n = (size_t)h->nx * h->ny, d = sizeof(double);
-  double *st = h->at<double>(h->off_pop[1 - h->cur]);
-  LbmParams p = make_params(h);
-  HIPCHK(launch_macro(h->prec, h->ws + h->off_pop[h->cur], p, st, st + n, st + 2 * n, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  HIPCHK(hipMemcpy(rho, st, n * d, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(ux, st + n, n * d, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(uy, st + 2 * n, n * d, hipMemcpyDeviceToHost));
-  return ok();
+  return guard([&]() -> int {
+    if (!h || !rho || !ux || !uy) return fail(BTDF_EINVAL, "NULL argument");
+    int rc = ensure_device(h);
+    if (rc) return rc;
+    const size_t n = (size_t)h->nx * h->ny, d = sizeof(double);
+    double *st = h->at<double>(h->off_pop[1 - h->cur]);
+    LbmParams p = make_params(h);
+    HIPCHK(launch_macro(h->prec, h->ws + h->off_pop[h->cur], p, st, st + n, st + 2 * n, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipMemcpy(rho, st, n * d, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ux, st + n, n * d, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(uy, st + 2 * n, n * d, hipMemcpyDeviceToHost));
+    return ok();
+  });
 }
 
 int btdf_get_populations(btdf_t *h, double *dst) {
-  if (!h || !dst) return fail(BTDF_EINVAL, "NULL argument");
-  int rc = ensure_device(h);
-  if (rc) return rc;
-  const size_t n = (size_t)h->nx * h->ny;
-  double *st = h->at<double>(h->off_pop[1 - h->cur]);
-  LbmParams p = make_params(h);
-  for (int q = 0; q < 9; ++q) {
-    HIPCHK(launch_plane_to_f64(h->prec, h->ws + h->off_pop[h->cur], p, q, st, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    HIPCHK(hipMemcpy(dst + (size_t)q * n, st, n * sizeof(double), hipMemcpyDeviceToHost));
-  }
-  return ok();
+  return guard([&]() -> int {
+    if (!h || !dst) return fail(BTDF_EINVAL, "NULL argument");
+    int rc = ensure_device(h);
+    if (rc) return rc;
+    const size_t n = (size_t)h->nx * h->ny;
+    double *st = h->at<double>(h->off_pop[1 - h->cur]);
+    LbmParams p = make_params(h);
+    for (int q = 0; q < 9; ++q) {
+      HIPCHK(launch_plane_to_f64(h->prec, h->ws + h->off_pop[h->cur], p, q, st, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+      HIPCHK(hipMemcpy(dst + (size_t)q * n, st, n * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    return ok();
+  });
 }
 
 int btdf_set_populations(btdf_t *h, const double *src) {
-  if (!h || !src) return fail(BTDF_EINVAL, "NULL argument");
-  int rc = ensure_device(h);
-  if (rc) return rc;
-  const size_t n = (size_t)h->nx * h->ny;
-  double *st = h->at<double>(h->off_pop[1 - h->cur]);
-  LbmParams p = make_params(h);
-  for (int q = 0; q < 9; ++q) {
-    HIPCHK(hipMemcpyAsync(st, src + (size_t)q * n, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(launch_f64_to_plane(h->prec, h->ws + h->off_pop[h->cur], p, q, st, h->stream));
+  return guard([&]() -> int {
+    if (!h || !src) return fail(BTDF_EINVAL, "NULL argument");
+    int rc = ensure_device(h);
+    if (rc) return rc;
+    const size_t n = (size_t)h->nx * h->ny;
+    double *st = h->at<double>(h->off_pop[1 - h->cur]);
+    LbmParams p = make_params(h);
+    for (int q = 0; q < 9; ++q) {
+      HIPCHK(hipMemcpyAsync(st, src + (size_t)q * n, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+      HIPCHK(launch_f64_to_plane(h->prec, h->ws + h->off_pop[h->cur], p, q, st, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    h->stepped = false;
+    if ((rc = clear_flag(h))) return rc;
     HIPCHK(hipStreamSynchronize(h->stream));
-  }
-  h->stepped = false;
-  if ((rc = clear_flag(h))) return rc;
-  HIPCHK(hipStreamSynchronize(h->stream));
-  return ok();
+    return ok();
+  });
 }
 
 int btdf_get_marker_data(btdf_t *h, double *rho_l, double *ux_l, double *uy_l, double *Fx, double *Fy) {
-  if (!h) return fail(BTDF_EINVAL, "NULL handle");
-  int rc = ensure_device(h);
-  if (rc) return rc;
-  HIPCHK(hipStreamSynchronize(h->stream));
-  const size_t M = (size_t)std::max(h->nm(), 1), nm = (size_t)h->nm(), d = sizeof(double);
-  double *outs[5] = {Fx, Fy, rho_l, ux_l, uy_l};
-  for (int k = 0; k < 5; ++k)
-    if (outs[k] && nm) HIPCHK(hipMemcpy(outs[k], h->ws + h->off_mk + (5 + k) * M * d, nm * d, hipMemcpyDeviceToHost));
-  return ok();
+  return guard([&]() -> int {
+    if (!h) return fail(BTDF_EINVAL, "NULL handle");
+    int rc = ensure_device(h);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const size_t M = (size_t)std::max(h->nm(), 1), nm = (size_t)h->nm(), d = sizeof(double);
+    double *outs[5] = {Fx, Fy, rho_l, ux_l, uy_l};
+    for (int k = 0; k < 5; ++k)
+      if (outs[k] && nm) HIPCHK(hipMemcpy(outs[k], h->ws + h->off_mk + (5 + k) * M * d, nm * d, hipMemcpyDeviceToHost));
+    return ok();
+  });
 }
 
 int btdf_marker_velocity(btdf_t *h, double *ux, double *uy) {
-  if (!h || !ux || !uy) return fail(BTDF_EINVAL, "NULL argument");
-  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch");
-  // the marker arrays on the device must be those of the last step, in the current layout
-  if (!h->stepped || !h->layout_ok || !h->device_ok || !h->ws)
-    return fail(BTDF_ESTATE, "no step since the state, the bodies or the layout last changed");
-  const int nm = h->nm();
-  if (nm == 0) return ok();
-  if (h->any_moving())
-    return fail(BTDF_ESTATE, "moving bodies: the markers have moved on since the last step's forces");
-  std::vector<int> off, list;
-  cover_lists(h, off, list);
-  const size_t b_off = off.size() * sizeof(int), b_list = list.size() * sizeof(int);
-  const size_t o_list = align256(b_off), o_out = o_list + align256(b_list);
-  const size_t bytes = o_out + 2 * (size_t)nm * sizeof(double);
-  char *buf = nullptr;
-  hipError_t e = hipMalloc((void **)&buf, bytes);
-  if (e != hipSuccess) return fail(BTDF_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
-  const LbmParams p = make_params(h);
-  const IbParams ib = make_ib(h);
-  double *out = reinterpret_cast<double *>(buf + o_out);
-  e = hipMemcpyAsync(buf, off.data(), b_off, hipMemcpyHostToDevice, h->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(buf + o_list, list.data(), b_list, hipMemcpyHostToDevice, h->stream);
-  if (e == hipSuccess)
-    e = launch_marker_velocity(h->prec, h->ws + h->off_pop[h->cur], p, ib, reinterpret_cast<const int *>(buf),
-                               reinterpret_cast<const int *>(buf + o_list), out, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  std::vector<double> host(2 * (size_t)nm);
-  if (e == hipSuccess) e = hipMemcpy(host.data(), out, host.size() * sizeof(double), hipMemcpyDeviceToHost);
-  (void)hipFree(buf);
-  if (e != hipSuccess) return fail(BTDF_EDEVICE, "marker velocity: %s", hipGetErrorString(e));
-  for (int l = 0; l < nm; ++l) {
-    ux[l] = host[2 * (size_t)l];
-    uy[l] = host[2 * (size_t)l + 1];
-  }
-  return ok();
+  return guard([&]() -> int {
+    if (!h || !ux || !uy) return fail(BTDF_EINVAL, "NULL argument");
+    if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch");
+    // the marker arrays on the device must be those of the last step, in the current layout
+    if (!h->stepped || !h->layout_ok || !h->device_ok || !h->ws)
+      return fail(BTDF_ESTATE, "no step since the state, the bodies or the layout last changed");
+    const int nm = h->nm();
+    if (nm == 0) return ok();
+    if (h->any_moving())
+      return fail(BTDF_ESTATE, "moving bodies: the markers have moved on since the last step's forces");
+    std::vector<int> off, list;
+    cover_lists(h, off, list);
+    const size_t b_off = off.size() * sizeof(int), b_list = list.size() * sizeof(int);
+    const size_t o_list = align256(b_off), o_out = o_list + align256(b_list);
+    const size_t bytes = o_out + 2 * (size_t)nm * sizeof(double);
+    char *buf = nullptr;
+    hipError_t e = hipMalloc((void **)&buf, bytes);
+    if (e != hipSuccess) return fail(BTDF_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    const LbmParams p = make_params(h);
+    const IbParams ib = make_ib(h);
+    double *out = reinterpret_cast<double *>(buf + o_out);
+    e = hipMemcpyAsync(buf, off.data(), b_off, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(buf + o_list, list.data(), b_list, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = launch_marker_velocity(h->prec, h->ws + h->off_pop[h->cur], p, ib, reinterpret_cast<const int *>(buf),
+                                 reinterpret_cast<const int *>(buf + o_list), out, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    std::vector<double> host(2 * (size_t)nm);
+    if (e == hipSuccess) e = hipMemcpy(host.data(), out, host.size() * sizeof(double), hipMemcpyDeviceToHost);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return fail(BTDF_EDEVICE, "marker velocity: %s", hipGetErrorString(e));
+    for (int l = 0; l < nm; ++l) {
+      ux[l] = host[2 * (size_t)l];
+      uy[l] = host[2 * (size_t)l + 1];
+    }
+    return ok();
+  });
 }
 
 static const uint64_t kStateMagic = 0x4254444653544154ULL;  // "BTDFSTAT"
 
 size_t btdf_state_bytes(const btdf_t *h) {
-  if (!h) return 0;
-  return 64 + 9 * (size_t)h->nx * h->ny * (size_t)h->prec;
+  return guard_size([&]() -> size_t {
+    if (!h) return 0;
+    return 64 + 9 * (size_t)h->nx * h->ny * (size_t)h->prec;
+  });
 }
 
 int btdf_save(btdf_t *h, void *dst, size_t bytes) {
-  if (!h || !dst) return fail(BTDF_EINVAL, "NULL argument");
-  if (bytes < btdf_state_bytes(h)) return fail(BTDF_EINVAL, "buffer of %zu bytes < %zu", bytes, btdf_state_bytes(h));
-  int rc = ensure_device(h);
-  if (rc) return rc;
-  HIPCHK(hipStreamSynchronize(h->stream));
-  uint64_t hdr[8] = {kStateMagic, (uint64_t)h->prec, (uint64_t)h->nx, (uint64_t)h->ny, (uint64_t)h->steps, 0, 0, 0};
-  std::memcpy(&hdr[5], &h->u0[0], 8);  // the reference state of the stored deviations
-  std::memcpy(&hdr[6], &h->u0[1], 8);
-  std::memcpy(dst, hdr, 64);
-  const size_t row = (size_t)h->nx * h->prec;
-  for (int q = 0; q < 9; ++q)
-    HIPCHK(hipMemcpy2D((char *)dst + 64 + (size_t)q * h->ny * row, row,
-                       h->ws + h->off_pop[h->cur] + (size_t)q * h->plane * h->prec, (size_t)h->pitch * h->prec,
-                       row, (size_t)h->ny, hipMemcpyDeviceToHost));
-  return ok();
+  return guard([&]() -> int {
+    if (!h || !dst) return fail(BTDF_EINVAL, "NULL argument");
+    if (bytes < btdf_state_bytes(h)) return fail(BTDF_EINVAL, "buffer of %zu bytes < %zu", bytes, btdf_state_bytes(h));
+    int rc = ensure_device(h);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    uint64_t hdr[8] = {kStateMagic, (uint64_t)h->prec, (uint64_t)h->nx, (uint64_t)h->ny, (uint64_t)h->steps, 0, 0, 0};
+    std::memcpy(&hdr[5], &h->u0[0], 8);  // the reference state of the stored deviations
+    std::memcpy(&hdr[6], &h->u0[1], 8);
+    std::memcpy(dst, hdr, 64);
+    const size_t row = (size_t)h->nx * h->prec;
+    for (int q = 0; q < 9; ++q)
+      HIPCHK(hipMemcpy2D((char *)dst + 64 + (size_t)q * h->ny * row, row,
+                         h->ws + h->off_pop[h->cur] + (size_t)q * h->plane * h->prec, (size_t)h->pitch * h->prec,
+                         row, (size_t)h->ny, hipMemcpyDeviceToHost));
+    return ok();
+  });
 }
 
 int btdf_load(btdf_t *h, const void *src, size_t bytes) {
-  if (!h || !src) return fail(BTDF_EINVAL, "NULL argument");
-  if (bytes < btdf_state_bytes(h)) return fail(BTDF_EINVAL, "buffer of %zu bytes < %zu", bytes, btdf_state_bytes(h));
-  uint64_t hdr[8];
-  std::memcpy(hdr, src, 64);
-  uint64_t r0, r1;
-  std::memcpy(&r0, &h->u0[0], 8);
-  std::memcpy(&r1, &h->u0[1], 8);
-  if (hdr[0] != kStateMagic || hdr[1] != (uint64_t)h->prec || hdr[2] != (uint64_t)h->nx || hdr[3] != (uint64_t)h->ny ||
-      hdr[5] != r0 || hdr[6] != r1)
-    return fail(BTDF_EINVAL, "state does not match this handle (size, precision or initial velocity)");
-  int rc = ensure_device(h);
-  if (rc) return rc;
-  h->stepped = false;
-  const size_t row = (size_t)h->nx * h->prec;
-  for (int q = 0; q < 9; ++q)
-    HIPCHK(hipMemcpy2DAsync(h->ws + h->off_pop[h->cur] + (size_t)q * h->plane * h->prec, (size_t)h->pitch * h->prec,
-                            (const char *)src + 64 + (size_t)q * h->ny * row, row, row, (size_t)h->ny,
-                            hipMemcpyHostToDevice, h->stream));
-  h->steps = (int64_t)hdr[4];
-  h->hist_read = h->steps;
-  h->forces_from = h->steps;
-  long long ctr = (long long)h->steps;
-  HIPCHK(hipMemcpyAsync(h->ws + h->off_ctl, &ctr, 8, hipMemcpyHostToDevice, h->stream));
-  if ((rc = clear_flag(h))) return rc;
-  HIPCHK(hipStreamSynchronize(h->stream));
-  return ok();
+  return guard([&]() -> int {
+    if (!h || !src) return fail(BTDF_EINVAL, "NULL argument");
+    if (bytes < btdf_state_bytes(h)) return fail(BTDF_EINVAL, "buffer of %zu bytes < %zu", bytes, btdf_state_bytes(h));
+    uint64_t hdr[8];
+    std::memcpy(hdr, src, 64);
+    uint64_t r0, r1;
+    std::memcpy(&r0, &h->u0[0], 8);
+    std::memcpy(&r1, &h->u0[1], 8);
+    if (hdr[0] != kStateMagic || hdr[1] != (uint64_t)h->prec || hdr[2] != (uint64_t)h->nx || hdr[3] != (uint64_t)h->ny ||
+        hdr[5] != r0 || hdr[6] != r1)
+      return fail(BTDF_EINVAL, "state does not match this handle (size, precision or initial velocity)");
+    int rc = ensure_device(h);
+    if (rc) return rc;
+    h->stepped = false;
+    const size_t row = (size_t)h->nx * h->prec;
+    for (int q = 0; q < 9; ++q)
+      HIPCHK(hipMemcpy2DAsync(h->ws + h->off_pop[h->cur] + (size_t)q * h->plane * h->prec, (size_t)h->pitch * h->prec,
+                              (const char *)src + 64 + (size_t)q * h->ny * row, row, row, (size_t)h->ny,
+                              hipMemcpyHostToDevice, h->stream));
+    h->steps = (int64_t)hdr[4];
+    h->hist_read = h->steps;
+    h->forces_from = h->steps;
+    long long ctr = (long long)h->steps;
+    HIPCHK(hipMemcpyAsync(h->ws + h->off_ctl, &ctr, 8, hipMemcpyHostToDevice, h->stream));
+    if ((rc = clear_flag(h))) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return ok();
+  });
 }
 
 int btdf_counts(const btdf_t *h, int *n_bodies, int *n_markers, int64_t *n_steps) {
-  if (!h) return fail(BTDF_EINVAL, "NULL handle");
-  if (n_bodies) *n_bodies = h->nb();
-  if (n_markers) *n_markers = h->nm();
-  if (n_steps) *n_steps = h->steps;
-  return ok();
+  return guard([&]() -> int {
+    if (!h) return fail(BTDF_EINVAL, "NULL handle");
+    if (n_bodies) *n_bodies = h->nb();
+    if (n_markers) *n_markers = h->nm();
+    if (n_steps) *n_steps = h->steps;
+    return ok();
+  });
 }
 
 int btdf_set_option(btdf_t *h, int key, int64_t value) {
-  if (!h) return fail(BTDF_EINVAL, "NULL handle");
-  if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; set options on the batch");
-  switch (key) {
-    case BTDF_OPT_LBM_VARIANT:
-      if (value < 0 || value >= num_variants()) return fail(BTDF_EINVAL, "variant %lld out of range", (long long)value);
-      if (value != h->variant) {
-        h->variant = (int)value;
-        h->layout_ok = false;  // tiles change
-        h->device_ok = false;
+  return guard([&]() -> int {
+    if (!h) return fail(BTDF_EINVAL, "NULL handle");
+    if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; set options on the batch");
+    switch (key) {
+      case BTDF_OPT_LBM_VARIANT:
+        if (value < 0 || value >= num_variants()) return fail(BTDF_EINVAL, "variant %lld out of range", (long long)value);
+        if (value != h->variant) {
+          h->variant = (int)value;
+          h->layout_ok = false;  // tiles change
+          h->device_ok = false;
+          drop_graph(h);
+        }
+        return ok();
+      case BTDF_OPT_GRAPH_CHUNK:
+        if (value < 0 || value > 4096) return fail(BTDF_EINVAL, "graph chunk must be in 0 .. 4096");
+        if (value != h->graph_chunk) {
+          h->graph_chunk = (int)value;
+          drop_graph(h);
+        }
+        return ok();
+      case BTDF_OPT_XCD_REMAP:
+        if (value != 0 && value != 1) return fail(BTDF_EINVAL, "xcd remap must be 0 or 1");
+        h->xcd_remap = (int)value;
         drop_graph(h);
-      }
-      return ok();
-    case BTDF_OPT_GRAPH_CHUNK:
-      if (value < 0 || value > 4096) return fail(BTDF_EINVAL, "graph chunk must be in 0 .. 4096");
-      if (value != h->graph_chunk) {
-        h->graph_chunk = (int)value;
+        return ok();
+      case BTDF_OPT_OVERLAP:
+        if (value != 0 && value != 1) return fail(BTDF_EINVAL, "overlap flag must be 0 or 1");
+        if (value != h->overlap && h->tblock == 1) {
+          h->layout_ok = false;  // the pass depth follows the overlap option
+          h->device_ok = false;
+        }
+        h->overlap = (int)value;
         drop_graph(h);
-      }
-      return ok();
-    case BTDF_OPT_XCD_REMAP:
-      if (value != 0 && value != 1) return fail(BTDF_EINVAL, "xcd remap must be 0 or 1");
-      h->xcd_remap = (int)value;
-      drop_graph(h);
-      return ok();
-    case BTDF_OPT_OVERLAP:
-      if (value != 0 && value != 1) return fail(BTDF_EINVAL, "overlap flag must be 0 or 1");
-      if (value != h->overlap && h->tblock == 1) {
-        h->layout_ok = false;  // the pass depth follows the overlap option
-        h->device_ok = false;
-      }
-      h->overlap = (int)value;
-      drop_graph(h);
-      return ok();
-    case BTDF_OPT_INTERIOR_PATH:
-      if (value != 0 && value != 1) return fail(BTDF_EINVAL, "interior path flag must be 0 or 1");
-      h->interior = (int)value;
-      drop_graph(h);
-      return ok();
-    case BTDF_OPT_ROW_PAD:
-    case BTDF_OPT_PLANE_PAD:
-      if (value < 0 || value > (1 << 20) || (key == BTDF_OPT_PLANE_PAD && value % 64))
-        return fail(BTDF_EINVAL, "padding must be in 0 .. 2^20 (planes: a multiple of 64)");
-      if (h->state_ok) return fail(BTDF_ESTATE, "layout options must be set before the first device use");
-      if (key == BTDF_OPT_ROW_PAD)
-        h->row_pad = (int)value;
-      else
-        h->plane_pad = (int)value;
-      h->layout_ok = false;
-      return ok();
-    case BTDF_OPT_ROW_ALIGN:
-      if (value != 0 && (value < 4 || value > 4096 || (value & (value - 1))))
-        return fail(BTDF_EINVAL, "row alignment must be 0 or a power of two in 4 .. 4096 bytes");
-      if (h->state_ok) return fail(BTDF_ESTATE, "layout options must be set before the first device use");
-      h->row_align = (int)value;
-      h->layout_ok = false;
-      return ok();
-    case BTDF_OPT_TEMPORAL_BLOCKING:
-      if (value < 0 || value > 3) return fail(BTDF_EINVAL, "temporal blocking must be 0 (off), 1 (deepest), 2 or 3");
-      if (value != h->tblock) {
-        h->tblock = (int)value;
-        h->layout_ok = false;  // the tile lists and the third buffer
-        h->device_ok = false;
+        return ok();
+      case BTDF_OPT_INTERIOR_PATH:
+        if (value != 0 && value != 1) return fail(BTDF_EINVAL, "interior path flag must be 0 or 1");
+        h->interior = (int)value;
         drop_graph(h);
-      }
-      return ok();
-    case BTDF_OPT_GROUP_SHAPE:
-      if (value != 0 && value != 1) return fail(BTDF_EINVAL, "group shape must be 0 (rows) or 1 (two tiles tall)");
-      if (value != h->gshape) {
-        h->gshape = (int)value;
-        h->layout_ok = false;  // the tile lists
-        h->device_ok = false;
-        drop_graph(h);
-      }
-      return ok();
-    case BTDF_OPT_FORCING_METHOD:
-      if (value != BTDF_FORCING_DIRECT && value != BTDF_FORCING_IMPLICIT && value != BTDF_FORCING_RKPM)
-        return fail(BTDF_EINVAL, "unknown forcing method %lld", (long long)value);
-      if (value != BTDF_FORCING_DIRECT && h->nf != 1)
-        return fail(BTDF_ESTATE, "the implicit and RKPM methods take one forcing pass (NF = 1)");
-      if (value != BTDF_FORCING_DIRECT && h->any_moving())
-        return fail(BTDF_ESTATE, "moving bodies need the direct forcing method");
-      if (value != h->method) {
-        h->method = (int)value;
-        h->layout_ok = false;  // matrices and marker factors change
-        h->device_ok = false;
-        h->stepped = false;
-        drop_graph(h);
-      }
-      return ok();
-    case BTDF_OPT_FORCING_PASSES:
-      if (value < 1 || value > 64) return fail(BTDF_EINVAL, "forcing passes must be in 1 .. 64");
-      if (value != 1 && h->method != BTDF_FORCING_DIRECT)
-        return fail(BTDF_ESTATE, "forcing passes need the direct forcing method");
-      if (value != 1 && h->any_moving()) return fail(BTDF_ESTATE, "moving bodies take one forcing pass");
-      if (value != h->nf) {
-        h->nf = (int)value;
-        h->layout_ok = false;  // the pass buffers change size
-        h->device_ok = false;
-        drop_graph(h);
-      }
-      return ok();
-    default: return fail(BTDF_EINVAL, "unknown or read-only option %d", key);
-  }
+        return ok();
+      case BTDF_OPT_ROW_PAD:
+      case BTDF_OPT_PLANE_PAD:
+        if (value < 0 || value > (1 << 20) || (key == BTDF_OPT_PLANE_PAD && value % 64))
+          return fail(BTDF_EINVAL, "padding must be in 0 .. 2^20 (planes: a multiple of 64)");
+        if (h->state_ok) return fail(BTDF_ESTATE, "layout options must be set before the first device use");
+        if (key == BTDF_OPT_ROW_PAD)
+          h->row_pad = (int)value;
+        else
+          h->plane_pad = (int)value;
+        h->layout_ok = false;
+        return ok();
+      case BTDF_OPT_ROW_ALIGN:
+        if (value != 0 && (value < 4 || value > 4096 || (value & (value - 1))))
+          return fail(BTDF_EINVAL, "row alignment must be 0 or a power of two in 4 .. 4096 bytes");
+        if (h->state_ok) return fail(BTDF_ESTATE, "layout options must be set before the first device use");
+        h->row_align = (int)value;
+        h->layout_ok = false;
+        return ok();
+      case BTDF_OPT_TEMPORAL_BLOCKING:
+        if (value < 0 || value > 3) return fail(BTDF_EINVAL, "temporal blocking must be 0 (off), 1 (deepest), 2 or 3");
+        if (value != h->tblock) {
+          h->tblock = (int)value;
+          h->layout_ok = false;  // the tile lists and the third buffer
+          h->device_ok = false;
+          drop_graph(h);
+        }
+        return ok();
+      case BTDF_OPT_GROUP_SHAPE:
+        if (value != 0 && value != 1) return fail(BTDF_EINVAL, "group shape must be 0 (rows) or 1 (two tiles tall)");
+        if (value != h->gshape) {
+          h->gshape = (int)value;
+          h->layout_ok = false;  // the tile lists
+          h->device_ok = false;
+          drop_graph(h);
+        }
+        return ok();
+      case BTDF_OPT_FORCING_METHOD:
+        if (value != BTDF_FORCING_DIRECT && value != BTDF_FORCING_IMPLICIT && value != BTDF_FORCING_RKPM)
+          return fail(BTDF_EINVAL, "unknown forcing method %lld", (long long)value);
+        if (value != BTDF_FORCING_DIRECT && h->nf != 1)
+          return fail(BTDF_ESTATE, "the implicit and RKPM methods take one forcing pass (NF = 1)");
+        if (value != BTDF_FORCING_DIRECT && h->any_moving())
+          return fail(BTDF_ESTATE, "moving bodies need the direct forcing method");
+        if (value != h->method) {
+          h->method = (int)value;
+          h->layout_ok = false;  // matrices and marker factors change
+          h->device_ok = false;
+          h->stepped = false;
+          drop_graph(h);
+        }
+        return ok();
+      case BTDF_OPT_FORCING_PASSES:
+        if (value < 1 || value > 64) return fail(BTDF_EINVAL, "forcing passes must be in 1 .. 64");
+        if (value != 1 && h->method != BTDF_FORCING_DIRECT)
+          return fail(BTDF_ESTATE, "forcing passes need the direct forcing method");
+        if (value != 1 && h->any_moving()) return fail(BTDF_ESTATE, "moving bodies take one forcing pass");
+        if (value != h->nf) {
+          h->nf = (int)value;
+          h->layout_ok = false;  // the pass buffers change size
+          h->device_ok = false;
+          drop_graph(h);
+        }
+        return ok();
+      default: return fail(BTDF_EINVAL, "unknown or read-only option %d", key);
+    }
+  });
 }
 
 int btdf_get_option(const btdf_t *h, int key, int64_t *value) {
-  if (!h || !value) return fail(BTDF_EINVAL, "NULL argument");
-  int tx, ty;
-  switch (key) {
-    case BTDF_OPT_LBM_VARIANT: *value = h->variant; return ok();
-    case BTDF_OPT_NUM_VARIANTS: *value = num_variants(); return ok();
-    case BTDF_OPT_GRAPH_CHUNK: *value = h->graph_chunk; return ok();
-    case BTDF_OPT_XCD_REMAP: *value = h->xcd_remap; return ok();
-    case BTDF_OPT_TILE_X: variant_tile(h->variant, &tx, &ty); *value = tx; return ok();
-    case BTDF_OPT_TILE_Y: variant_tile(h->variant, &tx, &ty); *value = ty; return ok();
-    case BTDF_OPT_ROW_PAD: *value = h->row_pad; return ok();
-    case BTDF_OPT_INTERIOR_PATH: *value = h->interior; return ok();
-    case BTDF_OPT_OVERLAP: *value = h->overlap; return ok();
-    case BTDF_OPT_FORCED_TILES:
-      if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
-      *value = h->n_forced;
-      return ok();
-    case BTDF_OPT_PLANE_PAD: *value = h->plane_pad; return ok();
-    case BTDF_OPT_ROW_ALIGN: *value = h->row_align; return ok();
-    case BTDF_OPT_FORCING_PASSES: *value = h->nf; return ok();
-    case BTDF_OPT_FORCING_METHOD: *value = h->method; return ok();
-    case BTDF_OPT_TEMPORAL_BLOCKING: *value = h->tblock; return ok();
-    case BTDF_OPT_GROUP_SHAPE: *value = h->gshape; return ok();
-    case BTDF_OPT_FUSED_TILES:
-      if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
-      *value = blocking_active(h) ? group_tiles(h->gkind[0]) * h->n_quad + group_tiles(h->gkind[1]) * h->n_wide +
-                                        h->n_fused
-                                  : 0;  // in lattice tiles
-      return ok();
-    case BTDF_OPT_STEPS_PER_PASS:
-      if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
-      *value = blocking_active(h) ? h->depth : 1;
-      return ok();
-    default: return fail(BTDF_EINVAL, "unknown option %d", key);
-  }
+  return guard([&]() -> int {
+    if (!h || !value) return fail(BTDF_EINVAL, "NULL argument");
+    int tx, ty;
+    switch (key) {
+      case BTDF_OPT_LBM_VARIANT: *value = h->variant; return ok();
+      case BTDF_OPT_NUM_VARIANTS: *value = num_variants(); return ok();
+      case BTDF_OPT_GRAPH_CHUNK: *value = h->graph_chunk; return ok();
+      case BTDF_OPT_XCD_REMAP: *value = h->xcd_remap; return ok();
+      case BTDF_OPT_TILE_X: variant_tile(h->variant, &tx, &ty); *value = tx; return ok();
+      case BTDF_OPT_TILE_Y: variant_tile(h->variant, &tx, &ty); *value = ty; return ok();
+      case BTDF_OPT_ROW_PAD: *value = h->row_pad; return ok();
+      case BTDF_OPT_INTERIOR_PATH: *value = h->interior; return ok();
+      case BTDF_OPT_OVERLAP: *value = h->overlap; return ok();
+      case BTDF_OPT_FORCED_TILES:
+        if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
+        *value = h->n_forced;
+        return ok();
+      case BTDF_OPT_PLANE_PAD: *value = h->plane_pad; return ok();
+      case BTDF_OPT_ROW_ALIGN: *value = h->row_align; return ok();
+      case BTDF_OPT_FORCING_PASSES: *value = h->nf; return ok();
+      case BTDF_OPT_FORCING_METHOD: *value = h->method; return ok();
+      case BTDF_OPT_TEMPORAL_BLOCKING: *value = h->tblock; return ok();
+      case BTDF_OPT_GROUP_SHAPE: *value = h->gshape; return ok();
+      case BTDF_OPT_FUSED_TILES:
+        if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
+        *value = blocking_active(h) ? group_tiles(h->gkind[0]) * h->n_quad + group_tiles(h->gkind[1]) * h->n_wide +
+                                          h->n_fused
+                                    : 0;  // in lattice tiles
+        return ok();
+      case BTDF_OPT_STEPS_PER_PASS:
+        if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
+        *value = blocking_active(h) ? h->depth : 1;
+        return ok();
+      default: return fail(BTDF_EINVAL, "unknown option %d", key);
+    }
+  });
 }
 
-int btdf_calibrate_thickening(int delta_kind, int n, const double *xy, double ds, double *drs_mean,
-                              double *drs_per_marker) {
-  if (!xy || !drs_mean) return fail(BTDF_EINVAL, "NULL argument");
-  if (n < 1) return fail(BTDF_EINVAL, "need at least one marker");
-  if (!valid_kind(delta_kind)) return fail(BTDF_EINVAL, "unknown delta kind %d", delta_kind);
-  if (!(ds > 0.0) || !std::isfinite(ds)) return fail(BTDF_EINVAL, "ds must be > 0");
-  for (int l = 0; l < 2 * n; ++l)
-    if (!std::isfinite(xy[l]) || std::fabs(xy[l]) > 1e8) return fail(BTDF_EINVAL, "bad marker coordinate");
-  const int S = stencil_size(delta_kind);
-  // per marker: stencil base and weights; A_lm = ds sum_k W_lk W_mk (eq 22, dh = 1)
-  std::vector<int> bx(n), by(n);
-  std::vector<double> wx(4 * (size_t)n), wy(4 * (size_t)n);
-  for (int l = 0; l < n; ++l) {
-    bx[l] = stencil_base(delta_kind, xy[2 * l]);
-    by[l] = stencil_base(delta_kind, xy[2 * l + 1]);
-    for (int a = 0; a < S; ++a) {
-      wx[4 * l + a] = phi_host(delta_kind, (double)(bx[l] + a) - xy[2 * l]);
-      wy[4 * l + a] = phi_host(delta_kind, (double)(by[l] + a) - xy[2 * l + 1]);
-    }
-  }
-  std::vector<double> A;
-  try {
-    A.assign((size_t)n * n, 0.0);
-  } catch (...) {
-    return fail(BTDF_ENOMEM, "out of host memory");
-  }
-  for (int l = 0; l < n; ++l) {
-    for (int m = 0; m < n; ++m) {
-      const int ox = bx[m] - bx[l], oy = by[m] - by[l];
-      if (ox <= -S || ox >= S || oy <= -S || oy >= S) continue;
-      double s = 0.0;
-      for (int c = 0; c < S; ++c) {
-        const int cm = c - oy;
-        if (cm < 0 || cm >= S) continue;
-        for (int a = 0; a < S; ++a) {
-          const int am = a - ox;
-          if (am < 0 || am >= S) continue;
-          s += wx[4 * l + a] * wy[4 * l + c] * wx[4 * m + am] * wy[4 * m + cm];
-        }
+int btdf_calibrate_thickening_markers(int delta_kind, int n, const double *xy, double ds, double *drs_mean,
+                                      double *drs_per_marker) {
+  return guard([&]() -> int {
+    if (!xy || !drs_mean) return fail(BTDF_EINVAL, "NULL argument");
+    if (n < 1) return fail(BTDF_EINVAL, "need at least one marker");
+    if (!valid_kind(delta_kind)) return fail(BTDF_EINVAL, "unknown delta kind %d", delta_kind);
+    if (!(ds > 0.0) || !std::isfinite(ds)) return fail(BTDF_EINVAL, "ds must be > 0");
+    for (int l = 0; l < 2 * n; ++l)
+      if (!std::isfinite(xy[l]) || std::fabs(xy[l]) > 1e8) return fail(BTDF_EINVAL, "bad marker coordinate");
+    const int S = stencil_size(delta_kind);
+    // per marker: stencil base and weights; A_lm = ds sum_k W_lk W_mk (eq 22, dh = 1)
+    std::vector<int> bx(n), by(n);
+    std::vector<double> wx(4 * (size_t)n), wy(4 * (size_t)n);
+    for (int l = 0; l < n; ++l) {
+      bx[l] = stencil_base(delta_kind, xy[2 * l]);
+      by[l] = stencil_base(delta_kind, xy[2 * l + 1]);
+      for (int a = 0; a < S; ++a) {
+        wx[4 * l + a] = phi_host(delta_kind, (double)(bx[l] + a) - xy[2 * l]);
+        wy[4 * l + a] = phi_host(delta_kind, (double)(by[l] + a) - xy[2 * l + 1]);
       }
-      A[(size_t)l * n + m] = ds * s;
     }
-  }
-  // solve A x = 1 (eqs 24-25) by LU with partial pivoting
-  std::vector<double> x(n, 1.0);
-  double amax = 0.0;
-  for (double v : A) amax = std::max(amax, std::fabs(v));
-  for (int k = 0; k < n; ++k) {
-    int piv = k;
-    for (int r = k + 1; r < n; ++r)
-      if (std::fabs(A[(size_t)r * n + k]) > std::fabs(A[(size_t)piv * n + k])) piv = r;
-    if (!(std::fabs(A[(size_t)piv * n + k]) > 1e-13 * amax))
-      return fail(BTDF_ESTATE, "matrix A is singular to working precision (markers too dense?)");
-    if (piv != k) {
-      for (int c = 0; c < n; ++c) std::swap(A[(size_t)k * n + c], A[(size_t)piv * n + c]);
-      std::swap(x[k], x[piv]);
+    std::vector<double> A;
+    try {
+      A.assign((size_t)n * n, 0.0);
+    } catch (...) {
+      return fail(BTDF_ENOMEM, "out of host memory");
     }
-    const double d = A[(size_t)k * n + k];
-    for (int r = k + 1; r < n; ++r) {
-      const double f = A[(size_t)r * n + k] / d;
-      if (f == 0.0) continue;
-      for (int c = k; c < n; ++c) A[(size_t)r * n + c] -= f * A[(size_t)k * n + c];
-      x[r] -= f * x[k];
+    for (int l = 0; l < n; ++l) {
+      for (int m = 0; m < n; ++m) {
+        const int ox = bx[m] - bx[l], oy = by[m] - by[l];
+        if (ox <= -S || ox >= S || oy <= -S || oy >= S) continue;
+        double s = 0.0;
+        for (int c = 0; c < S; ++c) {
+          const int cm = c - oy;
+          if (cm < 0 || cm >= S) continue;
+          for (int a = 0; a < S; ++a) {
+            const int am = a - ox;
+            if (am < 0 || am >= S) continue;
+            s += wx[4 * l + a] * wy[4 * l + c] * wx[4 * m + am] * wy[4 * m + cm];
+          }
+        }
+        A[(size_t)l * n + m] = ds * s;
+      }
     }
-  }
-  for (int k = n - 1; k >= 0; --k) {
-    double s = x[k];
-    for (int c = k + 1; c < n; ++c) s -= A[(size_t)k * n + c] * x[c];
-    x[k] = s / A[(size_t)k * n + k];
-  }
-  double mean = 0.0;
-  for (int l = 0; l < n; ++l) mean += x[l];
-  *drs_mean = mean / n;
-  if (drs_per_marker)
-    for (int l = 0; l < n; ++l) drs_per_marker[l] = x[l];
-  return ok();
+    // solve A x = 1 (eqs 24-25) by LU with partial pivoting
+    std::vector<double> x(n, 1.0);
+    double amax = 0.0;
+    for (double v : A) amax = std::max(amax, std::fabs(v));
+    for (int k = 0; k < n; ++k) {
+      int piv = k;
+      for (int r = k + 1; r < n; ++r)
+        if (std::fabs(A[(size_t)r * n + k]) > std::fabs(A[(size_t)piv * n + k])) piv = r;
+      if (!(std::fabs(A[(size_t)piv * n + k]) > 1e-13 * amax))
+        return fail(BTDF_ESTATE, "matrix A is singular to working precision (markers too dense?)");
+      if (piv != k) {
+        for (int c = 0; c < n; ++c) std::swap(A[(size_t)k * n + c], A[(size_t)piv * n + c]);
+        std::swap(x[k], x[piv]);
+      }
+      const double d = A[(size_t)k * n + k];
+      for (int r = k + 1; r < n; ++r) {
+        const double f = A[(size_t)r * n + k] / d;
+        if (f == 0.0) continue;
+        for (int c = k; c < n; ++c) A[(size_t)r * n + c] -= f * A[(size_t)k * n + c];
+        x[r] -= f * x[k];
+      }
+    }
+    for (int k = n - 1; k >= 0; --k) {
+      double s = x[k];
+      for (int c = k + 1; c < n; ++c) s -= A[(size_t)k * n + c] * x[c];
+      x[k] = s / A[(size_t)k * n + k];
+    }
+    double mean = 0.0;
+    for (int l = 0; l < n; ++l) mean += x[l];
+    *drs_mean = mean / n;
+    if (drs_per_marker)
+      for (int l = 0; l < n; ++l) drs_per_marker[l] = x[l];
+    return ok();
+  });
+}
+
+int btdf_calibrate_thickening(int delta_kind, double D, int n_markers, double *drs_mean, double *drs_per_marker) {
+  return guard([&]() -> int {
+    if (!drs_mean) return fail(BTDF_EINVAL, "NULL argument");
+    if (!(D > 0.0) || !std::isfinite(D) || D > 1e7) return fail(BTDF_EINVAL, "D must be > 0 (got %g)", D);
+    if (n_markers < 3) return fail(BTDF_EINVAL, "need at least three markers");
+    // the ring of btdf_add_body's usual input: X_l = (D/2)(cos t_l, sin t_l),
+    // t_l = 2 pi l / n, about the node (0, 0); ds = pi D / n (arc spacing)
+    std::vector<double> xy(2 * (size_t)n_markers);
+    for (int l = 0; l < n_markers; ++l) {
+      const double t = 2.0 * M_PI * l / n_markers;
+      xy[2 * l] = 0.5 * D * std::cos(t);
+      xy[2 * l + 1] = 0.5 * D * std::sin(t);
+    }
+    return btdf_calibrate_thickening_markers(delta_kind, n_markers, xy.data(), M_PI * D / n_markers, drs_mean,
+                                             drs_per_marker);
+  });
 }
 
 }  // extern "C"

@@ -389,288 +389,314 @@ extern "C" {
 
 int btdf_batch_create(int n_cases, const btdf_grid *grids, const double *taus, const int *delta_kinds,
                       const double *thickenings, btdf_batch_t **out) {
-  if (!grids || !taus || !delta_kinds || !thickenings || !out) return fail(BTDF_EINVAL, "NULL argument");
-  *out = nullptr;
-  if (n_cases < 1) return fail(BTDF_EINVAL, "a batch needs at least one case");
-  for (int c = 1; c < n_cases; ++c)
-    if (grids[c].precision != grids[0].precision) return fail(BTDF_EINVAL, "all cases of a batch share one precision");
-  btdf_batch_t *b = new (std::nothrow) btdf_batch();
-  if (!b) return fail(BTDF_ENOMEM, "out of host memory");
-  for (int c = 0; c < n_cases; ++c) {
-    btdf_t *h = nullptr;
-    int rc = btdf_create(&grids[c], taus[c], delta_kinds[c], thickenings[c], &h);
-    if (rc) {
-      const std::string msg = std::string("case ") + std::to_string(c) + ": " + btdf_last_error();
-      for (btdf_t *x : b->cases) (void)destroy_impl(x);
-      delete b;
-      return fail(rc, "%s", msg.c_str());
+  return guard([&]() -> int {
+    if (!grids || !taus || !delta_kinds || !thickenings || !out) return fail(BTDF_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (n_cases < 1) return fail(BTDF_EINVAL, "a batch needs at least one case");
+    for (int c = 1; c < n_cases; ++c)
+      if (grids[c].precision != grids[0].precision) return fail(BTDF_EINVAL, "all cases of a batch share one precision");
+    btdf_batch_t *b = new (std::nothrow) btdf_batch();
+    if (!b) return fail(BTDF_ENOMEM, "out of host memory");
+    for (int c = 0; c < n_cases; ++c) {
+      btdf_t *h = nullptr;
+      int rc = btdf_create(&grids[c], taus[c], delta_kinds[c], thickenings[c], &h);
+      if (rc) {
+        const std::string msg = std::string("case ") + std::to_string(c) + ": " + btdf_last_error();
+        for (btdf_t *x : b->cases) (void)destroy_impl(x);
+        delete b;
+        return fail(rc, "%s", msg.c_str());
+      }
+      h->owner = b;
+      h->tblock = 0;  // the batch steps its cases itself, one step at a time
+      h->stream = (hipStream_t)grids[0].hip_stream;
+      b->cases.push_back(h);
     }
-    h->owner = b;
-    h->tblock = 0;  // the batch steps its cases itself, one step at a time
-    h->stream = (hipStream_t)grids[0].hip_stream;
-    b->cases.push_back(h);
-  }
-  b->prec = grids[0].precision;
-  b->stream = (hipStream_t)grids[0].hip_stream;
-  *out = b;
-  return ok();
+    b->prec = grids[0].precision;
+    b->stream = (hipStream_t)grids[0].hip_stream;
+    *out = b;
+    return ok();
+  });
 }
 
 int btdf_batch_destroy(btdf_batch_t *b) {
-  if (!b) return ok();
-  int rc = ok();
-  if (b->ws && hipStreamSynchronize(b->stream) != hipSuccess) rc = fail(BTDF_EDEVICE, "stream sync failed");
-  batch_drop_graph(b);
-  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-  for (btdf_t *h : b->cases) {
-    h->owner = nullptr;
-    h->ws = nullptr;  // slices of the batch workspace are not the case's to free
-    h->ws_owned = false;
-    (void)destroy_impl(h);
-  }
-  if (b->ws && b->ws_owned) (void)hipFree(b->ws);
-  delete b;
-  return rc;
+  return guard([&]() -> int {
+    if (!b) return ok();
+    int rc = ok();
+    if (b->ws && hipStreamSynchronize(b->stream) != hipSuccess) rc = fail(BTDF_EDEVICE, "stream sync failed");
+    batch_drop_graph(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (btdf_t *h : b->cases) {
+      h->owner = nullptr;
+      h->ws = nullptr;  // slices of the batch workspace are not the case's to free
+      h->ws_owned = false;
+      (void)destroy_impl(h);
+    }
+    if (b->ws && b->ws_owned) (void)hipFree(b->ws);
+    delete b;
+    return rc;
+  });
 }
 
 int btdf_batch_case(btdf_batch_t *b, int i, btdf_t **h) {
-  if (!b || !h) return fail(BTDF_EINVAL, "NULL argument");
-  if (i < 0 || i >= (int)b->cases.size()) return fail(BTDF_EINVAL, "no case %d", i);
-  *h = b->cases[i];
-  return ok();
+  return guard([&]() -> int {
+    if (!b || !h) return fail(BTDF_EINVAL, "NULL argument");
+    if (i < 0 || i >= (int)b->cases.size()) return fail(BTDF_EINVAL, "no case %d", i);
+    *h = b->cases[i];
+    return ok();
+  });
 }
 
 int btdf_batch_add_body(btdf_batch_t *b, int case_id, int n, const double *xy, const double *uv, double cx,
                         double cy, double ds, int *body_id) {
-  if (!b) return fail(BTDF_EINVAL, "NULL batch");
-  if (case_id < 0 || case_id >= (int)b->cases.size()) return fail(BTDF_EINVAL, "no case %d", case_id);
-  int rc = add_body_impl(b->cases[case_id], n, xy, uv, cx, cy, ds, body_id);
-  if (rc) return rc;
-  b->layout_ok = false;
-  return ok();
+  return guard([&]() -> int {
+    if (!b) return fail(BTDF_EINVAL, "NULL batch");
+    if (case_id < 0 || case_id >= (int)b->cases.size()) return fail(BTDF_EINVAL, "no case %d", case_id);
+    int rc = add_body_impl(b->cases[case_id], n, xy, uv, cx, cy, ds, body_id);
+    if (rc) return rc;
+    b->layout_ok = false;
+    return ok();
+  });
 }
 
 size_t btdf_batch_workspace_bytes(const btdf_batch_t *b) {
-  if (!b) return 0;
-  if (!b->layout_ok) batch_layout(const_cast<btdf_batch_t *>(b));
-  return b->total;
+  return guard_size([&]() -> size_t {
+    if (!b) return 0;
+    if (!b->layout_ok) batch_layout(const_cast<btdf_batch_t *>(b));
+    return b->total;
+  });
 }
 
 int btdf_batch_bind_workspace(btdf_batch_t *b, void *dev, size_t bytes) {
-  if (!b) return fail(BTDF_EINVAL, "NULL batch");
-  if (dev && ((uintptr_t)dev & 255)) return fail(BTDF_EINVAL, "workspace must be 256-byte aligned");
-  if (!b->layout_ok) batch_layout(b);
-  if (dev && bytes < b->total) return fail(BTDF_ENOMEM, "workspace has %zu bytes, %zu needed", bytes, b->total);
-  if (dev == (void *)b->ws && dev) {
-    b->ws_bytes = bytes;
-    return ok();
-  }
-  // cases move their state into their new slices inside batch_ensure
-  char *old = b->ws;
-  const bool old_owned = b->ws_owned;
-  if (dev) {
-    b->ws = (char *)dev;
-    b->ws_bytes = bytes;
-    b->ws_owned = false;
-  } else {
-    b->ws = nullptr;
-    b->ws_bytes = 0;
-    b->ws_owned = false;
-  }
-  b->device_ok = false;
-  batch_drop_graph(b);
-  int rc = ok();
-  if (b->ws) rc = batch_ensure(b);
-  else if (old) {
-    // back to library-owned memory: allocate now so the states can move out of the old slices
-    rc = batch_ensure(b);
-  }
-  if (old && old_owned) HIPCHK(hipFree(old));
-  return rc;
+  return guard([&]() -> int {
+    if (!b) return fail(BTDF_EINVAL, "NULL batch");
+    if (dev && ((uintptr_t)dev & 255)) return fail(BTDF_EINVAL, "workspace must be 256-byte aligned");
+    if (!b->layout_ok) batch_layout(b);
+    if (dev && bytes < b->total) return fail(BTDF_ENOMEM, "workspace has %zu bytes, %zu needed", bytes, b->total);
+    if (dev == (void *)b->ws && dev) {
+      b->ws_bytes = bytes;
+      return ok();
+    }
+    // cases move their state into their new slices inside batch_ensure
+    char *old = b->ws;
+    const bool old_owned = b->ws_owned;
+    if (dev) {
+      b->ws = (char *)dev;
+      b->ws_bytes = bytes;
+      b->ws_owned = false;
+    } else {
+      b->ws = nullptr;
+      b->ws_bytes = 0;
+      b->ws_owned = false;
+    }
+    b->device_ok = false;
+    batch_drop_graph(b);
+    int rc = ok();
+    if (b->ws) rc = batch_ensure(b);
+    else if (old) {
+      // back to library-owned memory: allocate now so the states can move out of the old slices
+      rc = batch_ensure(b);
+    }
+    if (old && old_owned) HIPCHK(hipFree(old));
+    return rc;
+  });
 }
 
 int btdf_batch_set_stream(btdf_batch_t *b, void *hip_stream) {
-  if (!b) return fail(BTDF_EINVAL, "NULL batch");
-  if (b->ws && (hipStream_t)hip_stream != b->stream) HIPCHK(hipStreamSynchronize(b->stream));
-  b->stream = (hipStream_t)hip_stream;
-  for (btdf_t *h : b->cases) h->stream = b->stream;
-  return ok();
+  return guard([&]() -> int {
+    if (!b) return fail(BTDF_EINVAL, "NULL batch");
+    if (b->ws && (hipStream_t)hip_stream != b->stream) HIPCHK(hipStreamSynchronize(b->stream));
+    b->stream = (hipStream_t)hip_stream;
+    for (btdf_t *h : b->cases) h->stream = b->stream;
+    return ok();
+  });
 }
 
 int btdf_batch_step(btdf_batch_t *b, int64_t n) {
-  if (!b) return fail(BTDF_EINVAL, "NULL batch");
-  if (n < 0) return fail(BTDF_EINVAL, "negative step count");
-  if (n == 0) return ok();
-  int rc = batch_ensure(b);
-  if (rc) return rc;
-  int64_t left = n;
-  const int d = b->blocked ? 3 : 1;       // steps per unit
-  const int64_t g = (int64_t)(b->graph_chunk / d) * d;  // steps per graph: whole units
-  if (g > 0 && left >= g + (b->cur ? 1 : 0)) {
-    if (b->cur) {  // graphs start from buffer 0
+  return guard([&]() -> int {
+    if (!b) return fail(BTDF_EINVAL, "NULL batch");
+    if (n < 0) return fail(BTDF_EINVAL, "negative step count");
+    if (n == 0) return ok();
+    int rc = batch_ensure(b);
+    if (rc) return rc;
+    int64_t left = n;
+    const int d = b->blocked ? 3 : 1;       // steps per unit
+    const int64_t g = (int64_t)(b->graph_chunk / d) * d;  // steps per graph: whole units
+    if (g > 0 && left >= g + (b->cur ? 1 : 0)) {
+      if (b->cur) {  // graphs start from buffer 0
+        if ((rc = batch_enqueue(b, b->cur, b->stream, nullptr))) return rc;
+        batch_advance(b, 1);
+        left--;
+      }
+      if (!b->graph && (rc = batch_build_graph(b))) return rc;
+      while (left >= g) {
+        HIPCHK(hipGraphLaunch(b->graph, b->stream));
+        left -= g;
+        batch_advance(b, g);  // each unit swaps the buffers once, as g steps of an odd unit do
+        if (b->cur) break;
+      }
+    }
+    for (; d > 1 && left >= d; left -= d) {
+      if ((rc = batch_enqueue_triple(b, b->cur, b->stream, nullptr))) return rc;
+      batch_advance(b, d);
+    }
+    for (; left > 0; --left) {
       if ((rc = batch_enqueue(b, b->cur, b->stream, nullptr))) return rc;
       batch_advance(b, 1);
-      left--;
     }
-    if (!b->graph && (rc = batch_build_graph(b))) return rc;
-    while (left >= g) {
-      HIPCHK(hipGraphLaunch(b->graph, b->stream));
-      left -= g;
-      batch_advance(b, g);  // each unit swaps the buffers once, as g steps of an odd unit do
-      if (b->cur) break;
-    }
-  }
-  for (; d > 1 && left >= d; left -= d) {
-    if ((rc = batch_enqueue_triple(b, b->cur, b->stream, nullptr))) return rc;
-    batch_advance(b, d);
-  }
-  for (; left > 0; --left) {
-    if ((rc = batch_enqueue(b, b->cur, b->stream, nullptr))) return rc;
-    batch_advance(b, 1);
-  }
-  return ok();
+    return ok();
+  });
 }
 
 int btdf_batch_step_timed(btdf_batch_t *b, int64_t n, double *ms_ib, double *ms_lbm) {
-  if (!b || !ms_ib || !ms_lbm) return fail(BTDF_EINVAL, "NULL argument");
-  if (n <= 0) return fail(BTDF_EINVAL, "step count must be > 0");
-  return batch_step_timed_impl(b, n, ms_ib, ms_lbm);
+  return guard([&]() -> int {
+    if (!b || !ms_ib || !ms_lbm) return fail(BTDF_EINVAL, "NULL argument");
+    if (n <= 0) return fail(BTDF_EINVAL, "step count must be > 0");
+    return batch_step_timed_impl(b, n, ms_ib, ms_lbm);
+  });
 }
 
 int btdf_batch_status(btdf_batch_t *b, int *unstable, int64_t *n_steps) {
-  if (!b) return fail(BTDF_EINVAL, "NULL batch");
-  if (n_steps) *n_steps = b->steps;
-  if (!unstable) return ok();
-  if (!b->ws) {
-    for (size_t c = 0; c < b->cases.size(); ++c) unstable[c] = 0;
+  return guard([&]() -> int {
+    if (!b) return fail(BTDF_EINVAL, "NULL batch");
+    if (n_steps) *n_steps = b->steps;
+    if (!unstable) return ok();
+    if (!b->ws) {
+      for (size_t c = 0; c < b->cases.size(); ++c) unstable[c] = 0;
+      return ok();
+    }
+    HIPCHK(hipStreamSynchronize(b->stream));
+    for (size_t c = 0; c < b->cases.size(); ++c) {
+      long long ctr;
+      int flag;
+      int rc = read_ctl(b->cases[c], &ctr, &flag);
+      if (rc) return rc;
+      unstable[c] = flag != 0;
+    }
     return ok();
-  }
-  HIPCHK(hipStreamSynchronize(b->stream));
-  for (size_t c = 0; c < b->cases.size(); ++c) {
-    long long ctr;
-    int flag;
-    int rc = read_ctl(b->cases[c], &ctr, &flag);
-    if (rc) return rc;
-    unstable[c] = flag != 0;
-  }
-  return ok();
+  });
 }
 
 int btdf_batch_set_option(btdf_batch_t *b, int key, int64_t value) {
-  if (!b) return fail(BTDF_EINVAL, "NULL batch");
-  switch (key) {
-    case BTDF_OPT_LBM_VARIANT:
-      if (value < 0 || value >= num_variants()) return fail(BTDF_EINVAL, "variant %lld out of range", (long long)value);
-      if (value != b->variant) {
-        b->variant = (int)value;
-        b->layout_ok = false;  // the tile lists change, and with blocking the slice sizes
-      }
-      return ok();
-    case BTDF_OPT_GRAPH_CHUNK:
-      if (value < 0 || value > 4096) return fail(BTDF_EINVAL, "graph chunk must be in 0 .. 4096");
-      b->graph_chunk = (int)value;
-      batch_drop_graph(b);
-      return ok();
-    case BTDF_OPT_XCD_REMAP:
-      if (value != 0 && value != 1) return fail(BTDF_EINVAL, "xcd remap must be 0 or 1");
-      b->xcd_remap = (int)value;
-      b->layout_ok = false;
-      return ok();
-    case BTDF_OPT_INTERIOR_PATH:
-      if (value != 0 && value != 1) return fail(BTDF_EINVAL, "interior path flag must be 0 or 1");
-      b->interior = (int)value;
-      b->layout_ok = false;
-      return ok();
-    case BTDF_OPT_ROW_ALIGN:
-      if (value != 0 && (value < 4 || value > 4096 || (value & (value - 1))))
-        return fail(BTDF_EINVAL, "row alignment must be 0 or a power of two in 4 .. 4096 bytes");
-      for (const btdf_t *h : b->cases)
-        if (h->state_ok) return fail(BTDF_ESTATE, "layout options must be set before the first device use");
-      b->row_align = (int)value;
-      b->layout_ok = false;
-      return ok();
-    case BTDF_OPT_MASK_UNSTABLE:
-      if (value != 0 && value != 1) return fail(BTDF_EINVAL, "mask flag must be 0 or 1");
-      b->mask = (int)value;
-      b->device_ok = false;
-      return ok();
-    case BTDF_OPT_TEMPORAL_BLOCKING:
-      if (value < 0 || value > 3) return fail(BTDF_EINVAL, "temporal blocking must be 0 (off), 1 (deepest), 2 or 3");
-      if ((value != 0) != (b->tblock != 0)) {
-        b->tblock = value != 0;  // batches block three steps per pass or not at all
-        b->layout_ok = false;    // every case's lists and slice size
-      }
-      return ok();
-    case BTDF_OPT_GROUP_SHAPE:
-      if (value != 0 && value != 1) return fail(BTDF_EINVAL, "group shape must be 0 (rows) or 1 (two tiles tall)");
-      if (value != b->gshape) {
-        b->gshape = (int)value;
-        b->layout_ok = false;  // every case's lists
-      }
-      return ok();
-    default: return fail(BTDF_EINVAL, "unknown or read-only batch option %d", key);
-  }
+  return guard([&]() -> int {
+    if (!b) return fail(BTDF_EINVAL, "NULL batch");
+    switch (key) {
+      case BTDF_OPT_LBM_VARIANT:
+        if (value < 0 || value >= num_variants()) return fail(BTDF_EINVAL, "variant %lld out of range", (long long)value);
+        if (value != b->variant) {
+          b->variant = (int)value;
+          b->layout_ok = false;  // the tile lists change, and with blocking the slice sizes
+        }
+        return ok();
+      case BTDF_OPT_GRAPH_CHUNK:
+        if (value < 0 || value > 4096) return fail(BTDF_EINVAL, "graph chunk must be in 0 .. 4096");
+        b->graph_chunk = (int)value;
+        batch_drop_graph(b);
+        return ok();
+      case BTDF_OPT_XCD_REMAP:
+        if (value != 0 && value != 1) return fail(BTDF_EINVAL, "xcd remap must be 0 or 1");
+        b->xcd_remap = (int)value;
+        b->layout_ok = false;
+        return ok();
+      case BTDF_OPT_INTERIOR_PATH:
+        if (value != 0 && value != 1) return fail(BTDF_EINVAL, "interior path flag must be 0 or 1");
+        b->interior = (int)value;
+        b->layout_ok = false;
+        return ok();
+      case BTDF_OPT_ROW_ALIGN:
+        if (value != 0 && (value < 4 || value > 4096 || (value & (value - 1))))
+          return fail(BTDF_EINVAL, "row alignment must be 0 or a power of two in 4 .. 4096 bytes");
+        for (const btdf_t *h : b->cases)
+          if (h->state_ok) return fail(BTDF_ESTATE, "layout options must be set before the first device use");
+        b->row_align = (int)value;
+        b->layout_ok = false;
+        return ok();
+      case BTDF_OPT_MASK_UNSTABLE:
+        if (value != 0 && value != 1) return fail(BTDF_EINVAL, "mask flag must be 0 or 1");
+        b->mask = (int)value;
+        b->device_ok = false;
+        return ok();
+      case BTDF_OPT_TEMPORAL_BLOCKING:
+        if (value < 0 || value > 3) return fail(BTDF_EINVAL, "temporal blocking must be 0 (off), 1 (deepest), 2 or 3");
+        if ((value != 0) != (b->tblock != 0)) {
+          b->tblock = value != 0;  // batches block three steps per pass or not at all
+          b->layout_ok = false;    // every case's lists and slice size
+        }
+        return ok();
+      case BTDF_OPT_GROUP_SHAPE:
+        if (value != 0 && value != 1) return fail(BTDF_EINVAL, "group shape must be 0 (rows) or 1 (two tiles tall)");
+        if (value != b->gshape) {
+          b->gshape = (int)value;
+          b->layout_ok = false;  // every case's lists
+        }
+        return ok();
+      default: return fail(BTDF_EINVAL, "unknown or read-only batch option %d", key);
+    }
+  });
 }
 
 int btdf_batch_get_option(const btdf_batch_t *b, int key, int64_t *value) {
-  if (!b || !value) return fail(BTDF_EINVAL, "NULL argument");
-  switch (key) {
-    case BTDF_OPT_LBM_VARIANT: *value = b->variant; return ok();
-    case BTDF_OPT_NUM_VARIANTS: *value = num_variants(); return ok();
-    case BTDF_OPT_GRAPH_CHUNK: *value = b->graph_chunk; return ok();
-    case BTDF_OPT_XCD_REMAP: *value = b->xcd_remap; return ok();
-    case BTDF_OPT_INTERIOR_PATH: *value = b->interior; return ok();
-    case BTDF_OPT_MASK_UNSTABLE: *value = b->mask; return ok();
-    case BTDF_OPT_ROW_ALIGN: *value = b->row_align; return ok();
-    case BTDF_OPT_TEMPORAL_BLOCKING: *value = b->tblock; return ok();
-    case BTDF_OPT_GROUP_SHAPE: *value = b->gshape; return ok();
-    case BTDF_OPT_TILE_X:
-    case BTDF_OPT_TILE_Y: {
-      int tx, ty;
-      variant_tile(b->variant, &tx, &ty);
-      *value = key == BTDF_OPT_TILE_X ? tx : ty;
-      return ok();
+  return guard([&]() -> int {
+    if (!b || !value) return fail(BTDF_EINVAL, "NULL argument");
+    switch (key) {
+      case BTDF_OPT_LBM_VARIANT: *value = b->variant; return ok();
+      case BTDF_OPT_NUM_VARIANTS: *value = num_variants(); return ok();
+      case BTDF_OPT_GRAPH_CHUNK: *value = b->graph_chunk; return ok();
+      case BTDF_OPT_XCD_REMAP: *value = b->xcd_remap; return ok();
+      case BTDF_OPT_INTERIOR_PATH: *value = b->interior; return ok();
+      case BTDF_OPT_MASK_UNSTABLE: *value = b->mask; return ok();
+      case BTDF_OPT_ROW_ALIGN: *value = b->row_align; return ok();
+      case BTDF_OPT_TEMPORAL_BLOCKING: *value = b->tblock; return ok();
+      case BTDF_OPT_GROUP_SHAPE: *value = b->gshape; return ok();
+      case BTDF_OPT_TILE_X:
+      case BTDF_OPT_TILE_Y: {
+        int tx, ty;
+        variant_tile(b->variant, &tx, &ty);
+        *value = key == BTDF_OPT_TILE_X ? tx : ty;
+        return ok();
+      }
+      case BTDF_OPT_FUSED_TILES:  // lattice tiles of all cases in the blocked pass
+        if (!b->layout_ok) batch_layout(const_cast<btdf_batch_t *>(b));
+        *value = 0;
+        if (b->blocked)
+          for (const btdf_t *h : b->cases)
+            *value += group_tiles(b->gkind[0]) * h->n_quad + group_tiles(b->gkind[1]) * h->n_wide + h->n_fused;
+        return ok();
+      case BTDF_OPT_STEPS_PER_PASS:
+        if (!b->layout_ok) batch_layout(const_cast<btdf_batch_t *>(b));
+        *value = b->blocked ? 3 : 1;
+        return ok();
+      default: return fail(BTDF_EINVAL, "unknown batch option %d", key);
     }
-    case BTDF_OPT_FUSED_TILES:  // lattice tiles of all cases in the blocked pass
-      if (!b->layout_ok) batch_layout(const_cast<btdf_batch_t *>(b));
-      *value = 0;
-      if (b->blocked)
-        for (const btdf_t *h : b->cases)
-          *value += group_tiles(b->gkind[0]) * h->n_quad + group_tiles(b->gkind[1]) * h->n_wide + h->n_fused;
-      return ok();
-    case BTDF_OPT_STEPS_PER_PASS:
-      if (!b->layout_ok) batch_layout(const_cast<btdf_batch_t *>(b));
-      *value = b->blocked ? 3 : 1;
-      return ok();
-    default: return fail(BTDF_EINVAL, "unknown batch option %d", key);
-  }
+  });
 }
 
 int btdf_batch_autotune(btdf_batch_t *b, int64_t steps_per_trial, int *best_variant) {
-  if (!b) return fail(BTDF_EINVAL, "NULL batch");
-  if (steps_per_trial < 1) return fail(BTDF_EINVAL, "steps_per_trial must be >= 1");
-  double best = 1e300;
-  int bv = b->variant, bi = b->interior;
-  for (int v = 0; v < num_variants(); ++v) {
-    for (int in = 0; in < 2; ++in) {
-      b->variant = v;
-      b->interior = in;
-      b->layout_ok = false;
-      double a = 0.0, l = 0.0;
-      int rc = batch_step_timed_impl(b, steps_per_trial, &a, &l);
-      if (rc) return rc;
-      if (a + l < best) {
-        best = a + l;
-        bv = v;
-        bi = in;
+  return guard([&]() -> int {
+    if (!b) return fail(BTDF_EINVAL, "NULL batch");
+    if (steps_per_trial < 1) return fail(BTDF_EINVAL, "steps_per_trial must be >= 1");
+    double best = 1e300;
+    int bv = b->variant, bi = b->interior;
+    for (int v = 0; v < num_variants(); ++v) {
+      for (int in = 0; in < 2; ++in) {
+        b->variant = v;
+        b->interior = in;
+        b->layout_ok = false;
+        double a = 0.0, l = 0.0;
+        int rc = batch_step_timed_impl(b, steps_per_trial, &a, &l);
+        if (rc) return rc;
+        if (a + l < best) {
+          best = a + l;
+          bv = v;
+          bi = in;
+        }
       }
     }
-  }
-  b->variant = bv;
-  b->interior = bi;
-  b->layout_ok = false;
-  if (best_variant) *best_variant = bv;
-  return ok();
+    b->variant = bv;
+    b->interior = bi;
+    b->layout_ok = false;
+    if (best_variant) *best_variant = bv;
+    return ok();
+  });
 }
 
 }  // extern "C"

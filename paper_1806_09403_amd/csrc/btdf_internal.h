@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -118,8 +120,35 @@ struct btdf_sim {
 namespace btdf {
 namespace host {
 
-int fail(int code, const char *fmt, ...);
+int fail(int code, const char *fmt, ...) noexcept;
 inline int ok() { return BTDF_OK; }
+
+// Every extern "C" entry runs its body through guard (guard_size for the
+// size queries, which report 0): an exception thrown inside, such as a
+// failed host allocation in a std::vector, becomes a status code and a
+// message instead of crossing the C ABI.
+template <typename F>
+inline int guard(F &&body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc &) {
+    return fail(BTDF_ENOMEM, "out of host memory");
+  } catch (const std::exception &e) {
+    return fail(BTDF_EDEVICE, "internal error: %s", e.what());
+  } catch (...) {
+    return fail(BTDF_EDEVICE, "internal error");
+  }
+}
+template <typename F>
+inline size_t guard_size(F &&body) noexcept {
+  size_t v = 0;
+  if (guard([&]() -> int {
+        v = body();
+        return BTDF_OK;
+      }) != BTDF_OK)
+    return 0;
+  return v;
+}
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 bool valid_kind(int k);
 void drop_graph(btdf_t *h);

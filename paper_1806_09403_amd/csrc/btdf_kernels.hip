@@ -657,7 +657,7 @@ __global__ __launch_bounds__(BX *BY) void lbm2_kernel(const T *__restrict__ A, T
                                                      const unsigned char *__restrict__ near) {
   constexpr int RX = OX + 2, RY = OY + 2;  // the grown tile
   __shared__ T s_f[9][RY][RX];
-  __shared__ unsigned char s_near[3][8];  // near flags of the lattice tiles around the group (0: none)
+  __shared__ __align__(16) unsigned char s_near[3][8];  // near flags of the lattice tiles around the group (0: none)
   const int li = p.xcd_remap ? xcd_tile((int)blockIdx.x, count) : (int)blockIdx.x;
   const int t = map[li];
   const int tyi = t / p.ntx;
@@ -720,7 +720,8 @@ __global__ __launch_bounds__(BX *BY) void lbm2_kernel(const T *__restrict__ A, T
   }
   __syncthreads();
   // whether any neighbouring tile is near (uniform: every lane reads the same words)
-  const unsigned *nw = reinterpret_cast<const unsigned *>(&s_near[0][0]);
+  unsigned nw[sizeof s_near / 4];  // the flags as words (s_near is 16-byte aligned)
+  __builtin_memcpy(nw, &s_near[0][0], sizeof nw);
   const bool ring = near && (nw[0] | nw[1] | nw[2] | nw[3] | nw[4] | nw[5]) != 0;
   const int sh = __builtin_ctz((unsigned)tile_x);  // tile widths are powers of two
   // step n+1 on the tile's own nodes, pulling from the LDS copy of state n+1
@@ -880,7 +881,7 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
   const bool keep = !stop_flag<STOP>(stop);
   constexpr int NTH = BX * BY;
   __shared__ T s_f[9][RY][RX];
-  __shared__ unsigned char s_near[4][8];
+  __shared__ __align__(16) unsigned char s_near[4][8];
   const int tyi = t / p.ntx;
   const int txi = t - tyi * p.ntx;
   const int x0 = txi * tile_x, y0 = tyi * tile_y;
@@ -946,7 +947,8 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
   }
   if (near && tid < 32) s_near[nr][nc] = nflag;
   __syncthreads();
-  const unsigned *nw = reinterpret_cast<const unsigned *>(&s_near[0][0]);
+  unsigned nw[sizeof s_near / 4];  // the flags as words (s_near is 16-byte aligned)
+  __builtin_memcpy(nw, &s_near[0][0], sizeof nw);
   const bool ring = near && (nw[0] | nw[1] | nw[2] | nw[3] | nw[4] | nw[5] | nw[6] | nw[7]) != 0;
   const int shx = __builtin_ctz((unsigned)tile_x), shy = __builtin_ctz((unsigned)tile_y);
   // this thread's node of the group, and its ring directions

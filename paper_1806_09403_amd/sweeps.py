@@ -44,7 +44,7 @@ def calibration(kinds=(LINEAR2, ROMA3, PESKIN4, COS4), D_values=(20, 40, 80),
             for ds in ds_values:
                 n = int(round(math.pi * D / ds))
                 b = W.cylinder_body(0.3 + 2.0 * D, 0.6 + 2.0 * D, float(D), n)
-                mean, _ = api.btdf_calibrate_thickening(kind, b.xy, b.ds)
+                mean, _ = api.btdf_calibrate_thickening_markers(kind, b.xy, b.ds)
                 rows.append({"kind": KIND_NAME[kind], "D": D, "ds": b.ds, "drs_mean": mean})
                 log("calibration %-15s D/dh %3d ds/dh %.3f  drs/dh %.4f" % (KIND_NAME[kind], D, b.ds, mean))
     return rows

@@ -118,18 +118,37 @@ def test_calibration_matches_oracle(lib, kind, D, ratio):
     n = int(round(np.pi * D / ratio))
     xy = W.cylinder_markers(50.3, 47.9, D, n)
     ds = np.pi * D / n
-    mean, per = api.btdf_calibrate_thickening(kind, xy, ds)
+    mean, per = api.btdf_calibrate_thickening_markers(kind, xy, ds)
     ref = calib.thickness_vector(kind, xy, ds)
     assert abs(mean - ref.mean()) < 1e-11 * abs(ref.mean())
     assert np.max(np.abs(per - ref)) < 1e-10 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("kind", [W.LINEAR2, W.ROMA3, W.PESKIN4, W.COS4])
+@pytest.mark.parametrize("D,n", [(16.0, 50), (24.0, 75), (40.0, 126)])
+def test_cylinder_calibration_matches_oracle(lib, kind, D, n):
+    """The (kind, D, n_markers) form: a ring about a node with arc spacing."""
+    from paper_1806_09403_amd import api
+    mean, per = api.btdf_calibrate_thickening(kind, D, n)
+    t = 2.0 * np.pi * np.arange(n) / n
+    xy = 0.5 * D * np.stack([np.cos(t), np.sin(t)], axis=1)
+    ref = calib.thickness_vector(kind, xy, np.pi * D / n)
+    assert abs(mean - ref.mean()) < 1e-11 * abs(ref.mean())
+    assert np.max(np.abs(per - ref)) < 1e-10 * np.max(np.abs(ref))
+    # the paper's suggested thickness for the kernel's width (Section 4.4)
+    assert abs(mean - W.PAPER_THICKENING[kind]) < 0.25
+
+
 def test_calibration_errors(lib):
     from paper_1806_09403_amd import api
     xy = np.array([[1.0, 1.0], [1.0, 1.0], [3.0, 1.0]])   # two coincident markers: A singular
-    assert err(api.btdf_calibrate_thickening, W.ROMA3, xy, 1.0).code == -4
-    assert err(api.btdf_calibrate_thickening, 9, xy, 1.0).code == -1
-    assert err(api.btdf_calibrate_thickening, W.ROMA3, xy, 0.0).code == -1
+    assert err(api.btdf_calibrate_thickening_markers, W.ROMA3, xy, 1.0).code == -4
+    assert err(api.btdf_calibrate_thickening_markers, 9, xy, 1.0).code == -1
+    assert err(api.btdf_calibrate_thickening_markers, W.ROMA3, xy, 0.0).code == -1
+    assert err(api.btdf_calibrate_thickening, W.ROMA3, 0.0, 50).code == -1
+    assert err(api.btdf_calibrate_thickening, W.ROMA3, 16.0, 2).code == -1
+    assert err(api.btdf_calibrate_thickening, 9, 16.0, 50).code == -1
+    assert err(api.btdf_calibrate_thickening, W.ROMA3, 16.0, 500).code == -4   # ds = 0.1: A singular
 
 
 def test_header_constants_match_binding():
