@@ -59,6 +59,10 @@ def parse():
     p.add_argument("--seq-steps", type=int, default=200,
                    help="steps per case when timing the sequential single-case runs (0: skip them)")
     p.add_argument("--cpu-budget-s", type=float, default=20.0)
+    p.add_argument("--cpu-one-core-budget-s", type=float, default=10.0,
+                   help="host seconds for the one-thread oracle sample (0: skip it)")
+    p.add_argument("--repeats", type=int, default=5,
+                   help="timed blocks of --steps steps each; value and ms_per_step are their median")
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint figures")
     p.add_argument("--only-adjoint", action="store_true", help="print the adjoint figures alone")
     p.add_argument("--adjoint-steps", type=int, default=5000)
@@ -77,9 +81,10 @@ def make_case(args):
     return W.c1(kind=kind), 8
 
 
-def cpu_baseline(case, budget_s):
+def cpu_sample(case, budget_s):
     """The FP64 oracle on the same lattice and bodies: one step to size the
-    sample, then as many more as fit the budget."""
+    sample, then as many more as fit the budget (none if the first step
+    already took it). Returns (MLUPS, steps, seconds)."""
     import numpy as np
     from oracle import oracle
     o = oracle.OracleSim(case.nx, case.ny, case.bc, case.tau, case.kind, case.thickening, case.G,
@@ -92,15 +97,32 @@ def cpu_baseline(case, budget_s):
     t0 = time.perf_counter()
     o.step(1)
     t1 = time.perf_counter()
-    k = max(1, int((budget_s - (t1 - t0)) / max(t1 - t0, 1e-9)))
-    o.step(k)
+    k = int((budget_s - (t1 - t0)) / max(t1 - t0, 1e-9))
+    if k > 0:
+        o.step(k)
     t2 = time.perf_counter()
-    steps = 1 + k
-    mlups = case.nodes * steps / (t2 - t0) / 1e6
+    steps = 1 + max(k, 0)
     o.close()
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "%s: %d FP64 oracle steps of the full %dx%d lattice with all %d bodies (%.1f s)"
-                      % (case.name, steps, case.nx, case.ny, len(case.bodies), t2 - t0)}
+    return case.nodes * steps / (t2 - t0) / 1e6, steps, t2 - t0
+
+
+def cpu_baseline(case, budget_s, one_core_budget_s):
+    """The unmodified FP64 oracle on the host: all its OpenMP threads, then
+    one thread."""
+    from oracle import oracle
+    cores = oracle.num_threads()
+    mlups, steps, secs = cpu_sample(case, budget_s)
+    what = "%s: %%d FP64 oracle steps of the full %dx%d lattice with all %d bodies (%%.1f s)" % (
+        case.name, case.nx, case.ny, len(case.bodies))
+    out = {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": what % (steps, secs)}
+    if one_core_budget_s > 0:
+        oracle.set_num_threads(1)
+        m1, s1, t1 = cpu_sample(case, one_core_budget_s)
+        oracle.set_num_threads(cores)
+        out["one_core"] = {"value": round(m1, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+                           "sample": what % (s1, t1)}
+    return out
 
 
 def copy_probe(mb):
@@ -317,25 +339,43 @@ def main():
         sim.set_option(_lib.OPT_TEMPORAL_BLOCKING, args.blocking)
     if args.group_shape >= 0:
         sim.set_option(_lib.OPT_GROUP_SHAPE, args.group_shape)
-    sim.step(args.warmup)
+    fused_tiles = sim.get_option(_lib.OPT_FUSED_TILES)
+    depth = sim.get_option(_lib.OPT_STEPS_PER_PASS)
+    # warmup: plain steps, then one timed call (untimed here) that creates the
+    # handle's HIP events, so the timed region creates none
+    pre = min(args.warmup, depth)
+    sim.step(args.warmup - pre)
+    if pre > 0:
+        if fused_tiles > 0:
+            sim.step_timed_pass(pre)
+        else:
+            sim.step_timed_split(pre)
     torch.cuda.synchronize()
     if args.copy_probe_mb:
         copy_probe(args.copy_probe_mb)
     print("setup + warmup %.1f s" % (time.perf_counter() - t_setup), file=sys.stderr, flush=True)
 
-    fused_tiles = sim.get_option(_lib.OPT_FUSED_TILES)
-    depth = sim.get_option(_lib.OPT_STEPS_PER_PASS)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    if fused_tiles > 0:
-        # the timed region: HIP events around the blocked pass's launches only
-        # (events around every launch would add about 2% to a step)
-        ms_pass = sim.step_timed_pass(args.steps)
-    else:
-        ms_ib, ms_single, ms_pass = sim.step_timed_split(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sim.forces()  # surfaces an instability as an error
+    # the timed region, repeated: each block is exactly --steps steps,
+    # bracketed by stream synchronisations; value and ms_per_step are the
+    # median block
+    walls, passes = [], []
+    for _ in range(max(1, args.repeats)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if fused_tiles > 0:
+            # HIP events around the blocked pass's launches only (events
+            # around every launch would add about 2% to a step)
+            ms_pass = sim.step_timed_pass(args.steps)
+        else:
+            ms_ib, ms_single, ms_pass = sim.step_timed_split(args.steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        walls.append(t1 - t0)
+        passes.append(ms_pass)
+        sim.forces()  # surfaces an instability as an error
+    order = sorted(range(len(walls)), key=lambda i: walls[i])
+    med = order[len(order) // 2]
+    wall, ms_pass = walls[med], passes[med]
     split_steps = args.steps
     if fused_tiles > 0:
         # the other kernels' times: events around every launch, in a separate
@@ -345,7 +385,6 @@ def main():
         sim.forces()
 
     n = case.nodes
-    wall = t1 - t0
     ms_step = wall * 1e3 / args.steps
     mlups = n * args.steps / wall / 1e6
     node_bytes = 9 * 2 * prec  # one read and one write of the 9 populations
@@ -405,8 +444,22 @@ def main():
                           "ib_kernel and lbm_kernel: per step, HIP events around every launch over the timed steps",
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_ratio": round(traffic / achieved, 4) if traffic else None,
                      "kernel": kernel, "bytes_per_update": bytes_per_update,
-                     "nodes_per_launch": launch_nodes, "launch_ms": round(launch_ms, 5)},
+                     "nodes_per_launch": launch_nodes, "launch_ms": round(launch_ms, 5),
+                     # the same launches priced at one read and one write of
+                     # the 9 populations per lattice update (72 B in FP32),
+                     # as if every update went through HBM, and the whole
+                     # step (immersed boundary included) at that price
+                     "single_step_accounting": {
+                         "bytes_per_update": node_bytes,
+                         "kernel_achieved": round(launch_nodes * depth * node_bytes / (launch_ms * 1e-3) / 1e9, 1),
+                         "kernel_frac": round(launch_nodes * depth * node_bytes / (launch_ms * 1e-3) / 1e9
+                                              / HBM_PEAK_GBS, 4),
+                         "step_achieved": round(n * node_bytes / (ms_step * 1e-3) / 1e9, 1),
+                         "step_frac": round(n * node_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}},
+        "repeats": len(walls),
+        "ms_per_step_repeats": [round(w * 1e3 / args.steps, 5) for w in walls],
     }
     sim.close()
     del sim
@@ -421,7 +474,7 @@ def main():
         line["validation"] = bench_validation(args)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(case, args.cpu_budget_s)
+        line["cpu_baseline"] = cpu_baseline(case, args.cpu_budget_s, args.cpu_one_core_budget_s)
     print(json.dumps(line), flush=True)
 
 

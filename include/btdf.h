@@ -134,8 +134,9 @@ extern "C" {
                                          pass for every case, default on. Takes d-1 more population buffers. With a graph chunk
                                          k > 0 a graph holds k / d whole passes. Steps run singly instead with
                                          moving bodies or with a launch shape of more than one node per thread;
-                                         batch cases step singly. A step count that is not a multiple of d ends
-                                         with single steps. */
+                                         batch cases step singly. Steps left over after whole passes: two
+                                         after three-step passes take one two-step pass over the same tiles
+                                         (groups along rows), otherwise they step singly. */
 #define BTDF_OPT_FUSED_TILES 17       /* read-only: lattice tiles that take the blocked pass (0 when it is not active) */
 #define BTDF_OPT_STEPS_PER_PASS 18    /* read-only: steps per pass of those tiles (1 when blocking is not active) */
 #define BTDF_OPT_GROUP_SHAPE 19       /* how the three-step pass groups its lattice tiles (launch shape 32x8):
@@ -251,21 +252,23 @@ int btdf_step(btdf_t *h, int64_t n);
 /* Same as btdf_step, but times the kernels with HIP events on the streams
  * they run on and writes, in milliseconds per step, the duration of the
  * marker kernel (*ms_ib, 0 if no bodies) and of the lattice kernel (*ms_lbm;
- * the sum of its launches when the marker kernel overlaps it).
+ * the sum of its launches when the marker kernel overlaps it). The events
+ * are created on the first timed call and kept until btdf_destroy.
  * Synchronising. */
 int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm);
 
-/* As btdf_step_timed with the lattice time split: ms[0] marker kernels,
- * ms[1] single-step lattice kernels, ms[2] the blocked pass of temporal
- * blocking (per step: its mean launch duration over the steps per pass),
- * all means per step. */
+/* As btdf_step_timed with the lattice time split: ms[0] marker kernels and
+ * ms[1] single-step lattice kernels, means per step; ms[2] the blocked pass
+ * of temporal blocking: its mean launch duration divided by the steps per
+ * pass (over the passes taken, a two-step remainder pass included). */
 int btdf_step_timed_split(btdf_t *h, int64_t n, double *ms);
 
 /* Same as btdf_step, timing only the blocked pass of temporal blocking: HIP
  * events around the pass's launches alone (two per pass, on the stream the
  * pass runs on), so the recording costs the steps little. *ms_pass: the
- * pass's mean launch duration divided by the steps per pass, in milliseconds
- * per step (0 when no pass ran: blocking off, or n below the steps per pass).
+ * mean launch duration of the full-depth passes divided by the steps per
+ * pass, in milliseconds per step (0 when no such pass ran: blocking off, or
+ * n below the steps per pass; a two-step remainder pass is not timed).
  * Synchronising. Errors as btdf_step. */
 int btdf_step_timed_pass(btdf_t *h, int64_t n, double *ms_pass);
 

@@ -831,6 +831,16 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Set the threads of the parallel loops (n >= 1). Results do not depend on
+ * it: the marker loops are serial and every node is written by one thread. */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ======================================================================
  * Reverse mode. The step above is a differentiable map
  *   A_{t+1} = Step(A_t; U_b, X, c, u_in, G)

@@ -76,6 +76,7 @@ def lib():
         L.oracle_adjoint.argtypes = [ctypes.c_void_p, ctypes.c_long, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -83,6 +84,11 @@ def lib():
 def num_threads():
     """Threads the oracle's parallel loops use."""
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n):
+    """Threads of the oracle's parallel loops from now on (results do not depend on it)."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def delta(kind, r):

@@ -860,6 +860,7 @@ int destroy_impl(btdf_t *h) {
   if (h->side) (void)hipStreamDestroy(h->side);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  h->tev.release();
   if (h->ws && h->ws_owned) (void)hipFree(h->ws);
   delete h;
   return rc;
@@ -1059,6 +1060,7 @@ int btdf_set_marker_velocity(btdf_t *h, int body, const double *uv) {
 static int enqueue_pass(btdf_t *h, const LbmParams &p, const IbParams &ib, hipStream_t s, hipEvent_t *ev);
 static int run_blocked(btdf_t *h, const LbmParams &p, const IbParams &ib, int64_t n);
 static bool blocking_active(const btdf_t *h);
+static bool remainder_pair(const btdf_t *h);
 
 // n steps from the current buffer: graphs of graph_chunk steps where they fit
 static int run_steps(btdf_t *h, const LbmParams &p, const IbParams &ib, int64_t n) {
@@ -1354,6 +1356,10 @@ static int run_blocked(btdf_t *h, const LbmParams &p, const IbParams &ib, int64_
   }
   for (; left >= d; left -= d)
     if ((rc = enqueue_pass(h, p, ib, h->stream, nullptr))) return rc;
+  if (left == 2 && remainder_pair(h)) {
+    if ((rc = enqueue_pair(h, p, ib, h->stream, nullptr))) return rc;
+    left = 0;
+  }
   for (; left > 0; --left) {
     if ((rc = enqueue_step(h, p, ib, h->cur, h->stream, nullptr))) return rc;
     h->cur ^= 1;
@@ -1366,13 +1372,26 @@ static bool blocking_active(const btdf_t *h) {
   return h->depth >= 2 && h->layout_ok && h->n_quad + h->n_wide + h->n_fused > 0 && !h->any_moving();
 }
 
-// per-step means over n timed steps: out[0] marker kernels, out[1] single-step
-// lattice kernels, out[2] the two-step kernel (per step, i.e. half a launch)
+// Whether two steps left over after three-step passes can take one two-step
+// pass over the same tiles: a tile clear of the margins of three steps is
+// clear of those of two, so the near set and the row groups of the
+// three-step pass serve the two-step pass as they are (its groups along
+// rows; not the groups two tiles tall).
+static bool remainder_pair(const btdf_t *h) {
+  if (h->depth != 3 || h->gkind[0] != kGroup4x1 || h->gkind[1] != kGroup2x1) return false;
+  if (!variant_has_lbm2(h->variant, h->prec)) return false;
+  if (h->n_quad && !variant_has_wide_lbm2(h->variant, h->prec, 4)) return false;
+  if (h->n_wide && !variant_has_wide_lbm2(h->variant, h->prec, 2)) return false;
+  return true;
+}
+
 // n steps with HIP events around the launches: every launch of a step or a
-// pass (out: ms per step of the marker kernels, single-step lattice
-// launches, blocked pass), or with pass_only just the pass's launches (out[2]
-// only; single steps carry no events), which keeps the events' own cost out
-// of the steps being timed.
+// pass, or with pass_only just the blocked pass's launches (out[2] only;
+// single steps and a two-step remainder carry no events), which keeps the
+// events' own cost out of the steps being timed. out[0], out[1]: ms per step
+// of the marker kernels and of the single-step lattice launches (means over
+// the n steps); out[2]: the blocked pass's mean launch duration per step it
+// covers; out[3]: the blocked pass's time per step of all n.
 static int timed_impl(btdf_t *h, int64_t n, double *out, bool pass_only = false) {
   if (h->owner) return fail(BTDF_ESTATE, "this handle is a case of a batch; step the batch");
   if (n <= 0) return fail(BTDF_EINVAL, "step count must be > 0");
@@ -1381,19 +1400,31 @@ static int timed_impl(btdf_t *h, int64_t n, double *out, bool pass_only = false)
   const LbmParams p = make_params(h);
   const IbParams ib = make_ib(h);
   const int chunk = 256, NE = 10;  // events per entry
-  std::vector<hipEvent_t> ev(NE * chunk, nullptr);
-  for (size_t i = 0; i < ev.size(); ++i)
-    if (!pass_only || i % NE == 5 || i % NE == 6) HIPCHK(hipEventCreate(&ev[i]));
+  HIPCHK(h->tev.reserve((size_t)NE * chunk));
+  std::vector<hipEvent_t> ev(h->tev.ev.begin(), h->tev.ev.begin() + (size_t)NE * chunk);
+  if (pass_only)  // only the pass's two events of each entry are recorded
+    for (size_t i = 0; i < ev.size(); ++i)
+      if (i % NE != 5 && i % NE != 6) ev[i] = nullptr;
   const bool ov = overlapping(h);
   const int d = h->depth;
   double tib = 0.0, tlbm = 0.0, tpair = 0.0;
-  int64_t done = 0;
+  int64_t done = 0, pass_steps = 0;
   rc = ok();
   while (done < n && rc == 0) {
-    const bool pairs = blocking_active(h) && n - done >= d;  // passes of d steps
-    const int m = pairs ? (int)std::min<int64_t>(chunk, (n - done) / d) : (int)std::min<int64_t>(chunk, n - done);
+    // entries of this round: passes of d steps while d are left; two left
+    // after three-step passes take one two-step pass (untimed with
+    // pass_only, so the pass's mean is that of the d-step launches)
+    const bool blk = blocking_active(h);
+    const bool pairs = blk && n - done >= d;
+    const bool rem2 = blk && !pairs && d == 3 && n - done == 2 && remainder_pair(h);
+    const int dk = pairs ? d : (rem2 ? 2 : 1);  // steps per entry
+    const int m = dk > 1 ? (int)std::min<int64_t>(chunk, (n - done) / dk) : (int)std::min<int64_t>(chunk, n - done);
     const bool moving = h->any_moving();
     for (int k = 0; k < m && rc == 0; ++k) {
+      if (rem2) {
+        rc = enqueue_pair(h, p, ib, h->stream, pass_only ? nullptr : &ev[NE * k]);
+        continue;
+      }
       if (pairs) {
         rc = enqueue_pass(h, p, ib, h->stream, &ev[NE * k]);
         continue;
@@ -1418,28 +1449,32 @@ static int timed_impl(btdf_t *h, int64_t n, double *out, bool pass_only = false)
       float a = 0.f, b = 0.f, c = 0.f, e4 = 0.f, f = 0.f, g = 0.f, gg = 0.f;
       hipEvent_t *E = &ev[NE * k];
       if (pass_only) {
-        if (pairs) (void)hipEventElapsedTime(&f, E[5], E[6]);
-        tpair += f;
+        if (pairs) {
+          (void)hipEventElapsedTime(&f, E[5], E[6]);
+          tpair += f;
+          pass_steps += dk;
+        }
         continue;
       }
-      if (pairs) {
+      if (dk > 1) {
         (void)hipEventElapsedTime(&a, E[0], E[1]);
         // the near tiles' first step: after the first marker kernel in a
         // triple or an overlapped pair, else after the pass
-        (void)hipEventElapsedTime(&b, d == 3 || pair_overlap(h) ? E[1] : E[6], E[2]);
+        (void)hipEventElapsedTime(&b, dk == 3 || pair_overlap(h) ? E[1] : E[6], E[2]);
         // the second marker kernel: after the pass in a triple (unless that
         // runs beside it); the second near step after the wait for the pass
-        const bool ov3 = d == 3 && h->overlap != 0;
-        (void)hipEventElapsedTime(&c, d == 3 && !ov3 ? E[6] : E[2], E[3]);
+        const bool ov3 = dk == 3 && h->overlap != 0;
+        (void)hipEventElapsedTime(&c, dk == 3 && !ov3 ? E[6] : E[2], E[3]);
         (void)hipEventElapsedTime(&e4, ov3 ? E[9] : E[3], E[4]);
         (void)hipEventElapsedTime(&f, E[5], E[6]);
-        if (d == 3) {
+        if (dk == 3) {
           (void)hipEventElapsedTime(&g, E[4], E[7]);
           (void)hipEventElapsedTime(&gg, E[7], E[8]);
         }
         tib += a + c + g;
         tlbm += b + e4 + gg;
         tpair += f;
+        pass_steps += dk;
         continue;
       }
       (void)hipEventElapsedTime(&a, E[0], E[1]);
@@ -1452,26 +1487,25 @@ static int timed_impl(btdf_t *h, int64_t n, double *out, bool pass_only = false)
       tib += a;
       tlbm += b + c;
     }
-    done += pairs ? (int64_t)d * m : m;
+    done += (int64_t)dk * m;
   }
-  for (auto &e : ev)
-    if (e) (void)hipEventDestroy(e);
   if (rc) return rc;
   h->stepped = true;
   out[0] = h->nb() ? tib / (double)n : 0.0;
   out[1] = tlbm / (double)n;
-  out[2] = tpair / (double)n;
+  out[2] = pass_steps ? tpair / (double)pass_steps : 0.0;
+  out[3] = tpair / (double)n;
   return ok();
 }
 
 int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm) {
   return guard([&]() -> int {
     if (!h || !ms_ib || !ms_lbm) return fail(BTDF_EINVAL, "NULL argument");
-    double out[3];
+    double out[4];
     int rc = timed_impl(h, n, out);
     if (rc) return rc;
     *ms_ib = out[0];
-    *ms_lbm = out[1] + out[2];
+    *ms_lbm = out[1] + out[3];
     return ok();
   });
 }
@@ -1479,14 +1513,20 @@ int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm) {
 int btdf_step_timed_split(btdf_t *h, int64_t n, double *ms) {
   return guard([&]() -> int {
     if (!h || !ms) return fail(BTDF_EINVAL, "NULL argument");
-    return timed_impl(h, n, ms);
+    double out[4];
+    int rc = timed_impl(h, n, out);
+    if (rc) return rc;
+    ms[0] = out[0];
+    ms[1] = out[1];
+    ms[2] = out[2];
+    return ok();
   });
 }
 
 int btdf_step_timed_pass(btdf_t *h, int64_t n, double *ms_pass) {
   return guard([&]() -> int {
     if (!h || !ms_pass) return fail(BTDF_EINVAL, "NULL argument");
-    double out[3];
+    double out[4];
     int rc = timed_impl(h, n, out, true);
     if (rc) return rc;
     *ms_pass = out[2];

@@ -33,6 +33,7 @@ struct btdf_batch {
   size_t off_desc = 0, off_maps = 0, total = 0;
   int ntiles = 0, nbodies = 0, nmblk = 0;
   BatchMap map{};
+  btdf_event_pool tev;  // events of the timed stepping calls
   bool layout_ok = false, device_ok = false;
   // launch options
   int variant = 6, xcd_remap = 1, mask = 1, graph_chunk = 0, interior = 0, row_align = 128;
@@ -335,8 +336,8 @@ int batch_step_timed_impl(btdf_batch_t *b, int64_t n, double *ms_ib, double *ms_
   int rc = batch_ensure(b);
   if (rc) return rc;
   const int chunk = 256, NE = 8;  // events per entry
-  std::vector<hipEvent_t> ev(NE * chunk, nullptr);
-  for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+  HIPCHK(b->tev.reserve((size_t)NE * chunk));
+  hipEvent_t *ev = b->tev.ev.data();
   double tib = 0.0, tlbm = 0.0;
   int64_t done = 0;
   while (done < n && rc == 0) {
@@ -375,8 +376,6 @@ int batch_step_timed_impl(btdf_batch_t *b, int64_t n, double *ms_ib, double *ms_
     }
     done += tri ? 3 * (int64_t)m : m;
   }
-  for (auto &e : ev)
-    if (e) (void)hipEventDestroy(e);
   if (rc) return rc;
   if (ms_ib) *ms_ib = tib / (double)n;
   if (ms_lbm) *ms_lbm = tlbm / (double)n;
@@ -431,6 +430,7 @@ int btdf_batch_destroy(btdf_batch_t *b) {
       h->ws_owned = false;
       (void)destroy_impl(h);
     }
+    b->tev.release();
     if (b->ws && b->ws_owned) (void)hipFree(b->ws);
     delete b;
     return rc;

@@ -20,6 +20,26 @@
     if (e_ != hipSuccess) return btdf::host::fail(BTDF_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
+// HIP events of the timed stepping calls: created on first use and kept
+// until the handle is destroyed, so timing a run neither creates nor
+// destroys events while its steps are in flight
+struct btdf_event_pool {
+  std::vector<hipEvent_t> ev;
+  hipError_t reserve(size_t n) {
+    while (ev.size() < n) {
+      hipEvent_t e = nullptr;
+      const hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      ev.push_back(e);
+    }
+    return hipSuccess;
+  }
+  void release() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+  }
+};
+
 struct btdf_sim {
   void *owner = nullptr;  // the batch this handle is a case of (null: stand-alone)
   // configuration
@@ -100,6 +120,7 @@ struct btdf_sim {
   hipStream_t cap_stream = nullptr;
   hipStream_t side = nullptr;            // marker kernel when it overlaps the lattice kernel
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  btdf_event_pool tev;  // events of the timed stepping calls
 
   int nb() const { return (int)cx.size(); }
   bool any_moving() const {
