@@ -318,6 +318,20 @@ int btdf_get_marker_data(btdf_t *h, double *rho_l, double *ux_l, double *uy_l, d
  * covering-marker lists. Synchronising. */
 int btdf_marker_velocity(btdf_t *h, double *ux, double *uy);
 
+/* For callers that cannot allocate memory (loops that forbid hipMalloc,
+ * harnesses that allow no allocation): btdf_marker_velocity with no device
+ * or host allocation. Same arguments, results and errors; it rebuilds each
+ * stencil node's spread force from the tile marker lists already on the
+ * device (the same markers in the same order) instead of building covering
+ * lists, and stages the results in a fixed array of 2 x
+ * BTDF_NOALLOC_MAX_MARKERS doubles (4 MiB) that each GPU the library runs
+ * on holds until the process ends. Errors also: EINVAL when the handle has
+ * more than BTDF_NOALLOC_MAX_MARKERS markers. Every call on one GPU shares
+ * that array, so calls that overlap on one GPU (from several threads or
+ * streams) race. Synchronising. */
+#define BTDF_NOALLOC_MAX_MARKERS 262144
+int btdf_marker_velocity_noalloc(btdf_t *h, double *ux, double *uy);
+
 /* Checkpoint: the populations as the handle stores them (its precision, as
  * deviations from the equilibrium at the initial velocity of btdf_grid)
  * plus the step counter. btdf_state_bytes gives the size; save writes it

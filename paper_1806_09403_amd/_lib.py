@@ -29,6 +29,7 @@ OPT_FORCING_PASSES = 14
 OPT_FORCING_METHOD = 15
 OPT_TEMPORAL_BLOCKING, OPT_FUSED_TILES, OPT_STEPS_PER_PASS = 16, 17, 18
 OPT_GROUP_SHAPE = 19
+NOALLOC_MAX_MARKERS = 262144
 FORCING_DIRECT, FORCING_IMPLICIT, FORCING_RKPM = 0, 1, 2
 
 _NAMES = {OK: "BTDF_OK", EINVAL: "BTDF_EINVAL", ENOMEM: "BTDF_ENOMEM", EDEVICE: "BTDF_EDEVICE",
@@ -90,6 +91,7 @@ SIGNATURES = {
     "btdf_set_populations": (ctypes.c_int, [_vp, _dp]),
     "btdf_get_marker_data": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp, _dp]),
     "btdf_marker_velocity": (ctypes.c_int, [_vp, _dp, _dp]),
+    "btdf_marker_velocity_noalloc": (ctypes.c_int, [_vp, _dp, _dp]),
     "btdf_step_timed_split": (ctypes.c_int, [_vp, _i64, _dp]),
     "btdf_step_timed_pass": (ctypes.c_int, [_vp, _i64, _dp]),
     "btdf_set_body_motion": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]),

@@ -158,6 +158,20 @@ def btdf_marker_velocity(h):
     return u[:nm], v[:nm]
 
 
+def btdf_marker_velocity_noalloc(h, ux=None, uy=None):
+    """The no-allocation variant; ux, uy: caller-owned float64 arrays of at
+    least the marker count (allocated here if not given)."""
+    nm = btdf_counts(h)[1]
+    u = np.empty(max(nm, 1)) if ux is None else ux
+    v = np.empty(max(nm, 1)) if uy is None else uy
+    if u.dtype != np.float64 or v.dtype != np.float64 or not u.flags.c_contiguous or not v.flags.c_contiguous:
+        raise TypeError("ux and uy must be contiguous float64 arrays")
+    if u.size < nm or v.size < nm:
+        raise ValueError("ux and uy need room for %d markers" % nm)
+    check(load().btdf_marker_velocity_noalloc(h, dptr(u), dptr(v)))
+    return u[:nm], v[:nm]
+
+
 def btdf_state_bytes(h):
     return int(load().btdf_state_bytes(h))
 

@@ -1377,10 +1377,19 @@ __global__ __launch_bounds__(256) void idf_kernel(LbmParams p, IbParams ib) {
 // forcing), so u = (m' - F/2) / rho with F = G + the spread force, which is
 // rebuilt at each stencil node from the covering markers' weights and
 // drs ds F_l exactly as the lattice kernel summed it.
-template <typename T>
+// The corrected velocity of the last step at every marker (eqs 11, 12): 16
+// lanes per marker, one per stencil node, each rebuilding its node's spread
+// force from the markers that cover the node in ascending order, as the
+// lattice kernel summed it. TILES = false: those markers come from covering
+// lists built on the host (cover_off, cover_list; packed as in AdjParams);
+// TILES = true: from the lattice tile lists already on the device (each
+// marker of the node's tile tested for covering the node), which needs no
+// further buffer. Results go to ux_out[l * stride], uy_out[l * stride].
+template <typename T, bool TILES>
 __global__ __launch_bounds__(256) void marker_velocity_kernel(const T *__restrict__ A, LbmParams p, IbParams ib,
                                                               const int *__restrict__ coff,
-                                                              const int *__restrict__ clist, double *out) {
+                                                              const int *__restrict__ clist, int tile_x, int tile_y,
+                                                              double *ux_out, double *uy_out, int stride) {
   const int l = (int)blockIdx.x * 16 + ((int)threadIdx.x >> 4);
   const int node = (int)threadIdx.x & 15;
   const int a = node & 3, c = node >> 2;
@@ -1404,12 +1413,29 @@ __global__ __launch_bounds__(256) void marker_velocity_kernel(const T *__restric
     }
     const T *mw = reinterpret_cast<const T *>(ib.mk_w);
     T fx = (T)0, fy = (T)0;
-    for (int e = coff[16 * l + node]; e < coff[16 * l + node + 1]; ++e) {
-      const int v = clist[e];
-      const T *w = mw + 10 * (long long)(v >> 4);
-      const T Wm = w[(v >> 2) & 3] * w[4 + (v & 3)];
-      fx += Wm * w[8];
-      fy += Wm * w[9];
+    if (TILES) {
+      const int t = (j / tile_y) * p.ntx + i / tile_x;
+      for (int e = p.tile_off[t]; e < p.tile_off[t + 1]; ++e) {
+        const int m = p.tile_list[e];
+        int dy = j - p.mk_ixy[2 * m + 1];
+        if (p.yper && dy < 0) dy += p.ny;
+        if ((unsigned)dy >= (unsigned)S) continue;
+        int dx = i - p.mk_ixy[2 * m];
+        if (p.xper && dx < 0) dx += p.nx;
+        if ((unsigned)dx >= (unsigned)S) continue;
+        const T *w = mw + 10 * (long long)m;
+        const T Wm = w[dx] * w[4 + dy];
+        fx += Wm * w[8];
+        fy += Wm * w[9];
+      }
+    } else {
+      for (int e = coff[16 * l + node]; e < coff[16 * l + node + 1]; ++e) {
+        const int v = clist[e];
+        const T *w = mw + 10 * (long long)(v >> 4);
+        const T Wm = w[(v >> 2) & 3] * w[4 + (v & 3)];
+        fx += Wm * w[8];
+        fy += Wm * w[9];
+      }
     }
     const double ftx = (double)(T)(p.Gx + (double)fx), fty = (double)(T)(p.Gy + (double)fy);
     const double rho = 1.0 + drho;  // stored deviations: first moment m' - u_ref
@@ -1422,8 +1448,8 @@ __global__ __launch_bounds__(256) void marker_velocity_kernel(const T *__restric
     wv += __shfl_xor(wv, off, 16);
   }
   if (l < ib.nm && node == 0) {
-    out[2 * (long long)l] = wu;
-    out[2 * (long long)l + 1] = wv;
+    ux_out[(long long)l * stride] = wu;
+    uy_out[(long long)l * stride] = wv;
   }
 }
 
@@ -1432,11 +1458,25 @@ hipError_t launch_marker_velocity(int prec, const void *A, const LbmParams &p, c
   if (ib.nm == 0) return hipSuccess;
   const int blocks = (ib.nm + 15) / 16;
   if (prec == 4)
-    hipLaunchKernelGGL(marker_velocity_kernel<float>, dim3(blocks), dim3(256), 0, s, (const float *)A, p, ib,
-                       cover_off, cover_list, out);
+    hipLaunchKernelGGL((marker_velocity_kernel<float, false>), dim3(blocks), dim3(256), 0, s, (const float *)A, p,
+                       ib, cover_off, cover_list, 0, 0, out, out + 1, 2);
   else
-    hipLaunchKernelGGL(marker_velocity_kernel<double>, dim3(blocks), dim3(256), 0, s, (const double *)A, p, ib,
-                       cover_off, cover_list, out);
+    hipLaunchKernelGGL((marker_velocity_kernel<double, false>), dim3(blocks), dim3(256), 0, s, (const double *)A,
+                       p, ib, cover_off, cover_list, 0, 0, out, out + 1, 2);
+  return hipGetLastError();
+}
+
+hipError_t launch_marker_velocity_tiles(int prec, const void *A, const LbmParams &p, const IbParams &ib, int tile_x,
+                                        int tile_y, double *ux, double *uy, hipStream_t s) {
+  if (ib.nm == 0) return hipSuccess;
+  if (tile_x <= 0 || tile_y <= 0) return hipErrorInvalidValue;
+  const int blocks = (ib.nm + 15) / 16;
+  if (prec == 4)
+    hipLaunchKernelGGL((marker_velocity_kernel<float, true>), dim3(blocks), dim3(256), 0, s, (const float *)A, p,
+                       ib, nullptr, nullptr, tile_x, tile_y, ux, uy, 1);
+  else
+    hipLaunchKernelGGL((marker_velocity_kernel<double, true>), dim3(blocks), dim3(256), 0, s, (const double *)A, p,
+                       ib, nullptr, nullptr, tile_x, tile_y, ux, uy, 1);
   return hipGetLastError();
 }
 

@@ -38,6 +38,8 @@ hipError_t launch_conv_outlet_batch(int prec, const CaseDesc *cases, int ncases,
                                     hipStream_t s);
 hipError_t launch_marker_velocity(int prec, const void *A, const LbmParams &p, const IbParams &ib,
                                   const int *cover_off, const int *cover_list, double *out, hipStream_t s);
+hipError_t launch_marker_velocity_tiles(int prec, const void *A, const LbmParams &p, const IbParams &ib, int tile_x,
+                                        int tile_y, double *ux, double *uy, hipStream_t s);
 hipError_t launch_lbm_batch(int prec, int variant, const CaseDesc *cases, const BatchMap &m, int rt,
                             hipStream_t s);
 hipError_t launch_ib_batch(int prec, const CaseDesc *cases, const BatchMap &m, int rt, hipStream_t s);
