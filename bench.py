@@ -38,13 +38,10 @@ def parse():
     p.add_argument("--graph-chunk", type=int, default=0)
     p.add_argument("--row-pad", type=int, default=0)
     p.add_argument("--interior", type=int, default=-1, help="1/0: uniform-base path for interior waves (-1: library default)")
-    p.add_argument("--overlap", type=int, default=-1, help="1/0: marker kernel beside the lattice kernel (-1: library default)")
     p.add_argument("--blocking", type=int, default=-1,
                    help="steps per pass away from the bodies: 0 off, 1 deepest, 2 or 3 (-1: library default)")
     p.add_argument("--split-steps", type=int, default=3000,
                    help="steps of the separate per-kernel timing run (HIP events around each launch)")
-    p.add_argument("--group-shape", type=int, default=-1,
-                   help="three-step pass groups: 0 along rows, 1 two tiles tall (-1: library default)")
     p.add_argument("--plane-pad", type=int, default=0)
     p.add_argument("--row-align", type=int, default=-1, help="row alignment in bytes (-1: library default)")
     p.add_argument("--copy-probe-mb", type=int, default=0,
@@ -156,8 +153,6 @@ def bench_batched(args):
     opts = {}
     if args.row_align >= 0:
         opts[_lib.OPT_ROW_ALIGN] = args.row_align
-    if args.group_shape >= 0:
-        opts[_lib.OPT_GROUP_SHAPE] = args.group_shape
     b = BatchSim(cases, precision=4, options=opts)
     if args.batched_variant >= 0:
         best = args.batched_variant
@@ -176,13 +171,12 @@ def bench_batched(args):
     ms_ib, ms_lbm = b.step_timed(201)
     b_align = b.get_option(_lib.OPT_ROW_ALIGN)
     depth = b.get_option(_lib.OPT_STEPS_PER_PASS)
-    gshape = b.get_option(_lib.OPT_GROUP_SHAPE)
     blocked_nodes = (b.get_option(_lib.OPT_FUSED_TILES) * b.get_option(_lib.OPT_TILE_X) *
                      b.get_option(_lib.OPT_TILE_Y))
     b.close()
     del b
     traffic = None
-    key = "batched-v%d-a%d%s%s" % (best, b_align, "-p3" if depth == 3 else "", "-g%d" % gshape if gshape else "")
+    key = "batched-v%d-a%d%s" % (best, b_align, "-p3" if depth == 3 else "")
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             t = json.load(f).get(key)
@@ -219,7 +213,7 @@ def bench_batched(args):
             "speedup_vs_sequential": round(mlups / seq_mlups, 3) if seq_mlups else None,
             "sequential_sample": "each stable case alone, %d graph-replayed steps" % args.seq_steps,
             "lbm_variant": best, "graph_chunk": args.batched_graph_chunk, "row_align": b_align,
-            "steps_per_pass": depth, "group_shape": gshape, "blocked_nodes_frac": round(blocked_nodes / nodes, 4),
+            "steps_per_pass": depth, "blocked_nodes_frac": round(blocked_nodes / nodes, 4),
             "kernel_ms": {"ib_batch_kernel": round(ms_ib, 5), "lbm_batch_kernel": round(ms_lbm, 5)},
             "kernel_ms_note": "per step; lbm_batch_kernel: the lattice launches of a step (with blocking: the "
                               "near tiles' steps and the blocked pass, a third of each triple)",
@@ -333,12 +327,8 @@ def main():
         sim.set_option(_lib.OPT_GRAPH_CHUNK, args.graph_chunk)
     if args.interior >= 0:
         sim.set_option(_lib.OPT_INTERIOR_PATH, args.interior)
-    if args.overlap >= 0:
-        sim.set_option(_lib.OPT_OVERLAP, args.overlap)
     if args.blocking >= 0:
         sim.set_option(_lib.OPT_TEMPORAL_BLOCKING, args.blocking)
-    if args.group_shape >= 0:
-        sim.set_option(_lib.OPT_GROUP_SHAPE, args.group_shape)
     fused_tiles = sim.get_option(_lib.OPT_FUSED_TILES)
     depth = sim.get_option(_lib.OPT_STEPS_PER_PASS)
     # warmup: plain steps, then one timed call (untimed here) that creates the
@@ -395,13 +385,11 @@ def main():
         launch_nodes = fused_tiles * tile_nodes
         launch_ms = depth * ms_pass
         kernel, bytes_per_update = "lbm%d_kernel" % depth, node_bytes / depth
-        gshape = sim.get_option(_lib.OPT_GROUP_SHAPE)
-        key = "%s-%s-v%d-p%d%s" % (args.workload, args.delta, variant, depth, "-g%d" % gshape if gshape else "")
+        key = "%s-%s-v%d-p%d" % (args.workload, args.delta, variant, depth)
     else:
         launch_nodes, launch_ms = n, ms_single
         kernel, bytes_per_update = "lbm_kernel", node_bytes
-        key = "%s-%s-v%d-i%d-o%d" % (args.workload, args.delta, variant, sim.get_option(_lib.OPT_INTERIOR_PATH),
-                                     sim.get_option(_lib.OPT_OVERLAP))
+        key = "%s-%s-v%d-i%d" % (args.workload, args.delta, variant, sim.get_option(_lib.OPT_INTERIOR_PATH))
     achieved = launch_nodes * node_bytes / (launch_ms * 1e-3) / 1e9
     # measured HBM bytes per launch (profiles/traffic.json, counter runs of this
     # exact configuration) over the same live duration: GB/s like `achieved`
@@ -430,10 +418,9 @@ def main():
                    "lbm_variant": sim.get_option(_lib.OPT_LBM_VARIANT),
                    "row_pad": args.row_pad, "plane_pad": args.plane_pad,
                    "interior_path": sim.get_option(_lib.OPT_INTERIOR_PATH),
-                   "overlap": sim.get_option(_lib.OPT_OVERLAP),
                    "graph_chunk": args.graph_chunk,
                    "temporal_blocking": sim.get_option(_lib.OPT_TEMPORAL_BLOCKING),
-                   "steps_per_pass": depth, "group_shape": sim.get_option(_lib.OPT_GROUP_SHAPE),
+                   "steps_per_pass": depth,
                    "blocked_tiles": fused_tiles,
                    "blocked_nodes_frac": round(launch_nodes / n, 4) if fused_tiles else 0.0},
         "kernel_ms": dict([("ib_kernel", round(ms_ib, 5)), ("lbm_kernel", round(ms_single, 5))] +

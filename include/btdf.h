@@ -108,11 +108,6 @@ extern "C" {
 #define BTDF_OPT_ROW_PAD 7       /* elements added to each grid row (>= 0); only before the first device use */
 #define BTDF_OPT_PLANE_PAD 8     /* elements added to each population plane, multiple of 64; same restriction */
 #define BTDF_OPT_INTERIOR_PATH 9 /* 1 (default): waves away from every edge load from wave-uniform bases; 0: always the general pull */
-#define BTDF_OPT_OVERLAP 10      /* 1: a second stream (default priority) takes work beside the main one: in
-                                    single steps the marker kernel beside the lattice tiles it does not touch;
-                                    with temporal blocking the blocked pass beside the near tiles' chain (at
-                                    the default depth this selects two steps per pass); 0 (default): in order.
-                                    Results are the same bits either way. */
 #define BTDF_OPT_FORCED_TILES 11 /* read-only: lattice tiles touched by some marker's stencil */
 #define BTDF_OPT_MASK_UNSTABLE 12 /* batches only: 1 (default) = a case that went unstable stops, the others go on */
 #define BTDF_OPT_ROW_ALIGN 13     /* bytes (0 or a power of two 4..4096, default 128): each row starts on this
@@ -125,25 +120,20 @@ extern "C" {
                                          written once for d updates); the others step singly with the marker
                                          kernel between, and the pass gives them the intermediate states of the
                                          nodes just outside. Results are bit-identical to single steps.
-                                         1 (default): the deepest the launch shape has (3, or 2 when the overlap
-                                         option is set or the shape has no three-step pass, as for tiles one or
-                                         two rows tall) on lattices of at least 2^20 nodes (smaller ones step
+                                         1 (default): the deepest the launch shape has (3, or 2 when the shape
+                                         has no three-step pass, as for tiles one or two rows tall) on
+                                         lattices of at least 2^20 nodes (smaller ones step
                                          singly: the extra launches of a pass outweigh the bytes saved); 2 or 3:
                                          that depth where the shape has it, else the next lower; 0: off. In a
                                          batch (btdf_batch_set_option) any nonzero value means three steps per
                                          pass for every case, default on. Takes d-1 more population buffers. With a graph chunk
                                          k > 0 a graph holds k / d whole passes. Steps run singly instead with
-                                         moving bodies or with a launch shape of more than one node per thread;
-                                         batch cases step singly. Steps left over after whole passes: two
-                                         after three-step passes take one two-step pass over the same tiles
-                                         (groups along rows), otherwise they step singly. */
+                                         moving bodies or with a launch shape of more than one node per thread.
+                                         Steps left over after whole passes: on a stand-alone handle two after
+                                         three-step passes take one two-step pass over the same tiles,
+                                         otherwise (and in batches) they step singly. */
 #define BTDF_OPT_FUSED_TILES 17       /* read-only: lattice tiles that take the blocked pass (0 when it is not active) */
 #define BTDF_OPT_STEPS_PER_PASS 18    /* read-only: steps per pass of those tiles (1 when blocking is not active) */
-#define BTDF_OPT_GROUP_SHAPE 19       /* how the three-step pass groups its lattice tiles (launch shape 32x8):
-                                         0 (default): four, then two side by side in a row (128x8, 64x8);
-                                         1: 2x2, then 1x2 tiles (64x16, 32x16: fewer halo nodes recomputed per
-                                         node), where the precision's LDS allows 2x2 (FP32), else as 0. Tiles
-                                         left out of every group take the pass singly. Handles and batches. */
 #define BTDF_OPT_FORCING_PASSES 14 /* NF in 1..64 (default 1): direct-forcing passes per step (Sec. 2.3, eqs 29-31);
                                       each pass after the first re-interpolates the velocity corrected by the force
                                       spread so far and adds 2 rho_l (U - u) to the marker force; stand-alone
@@ -249,12 +239,11 @@ int btdf_get_marker_positions(btdf_t *h, double *xy);
  * replaced by btdf_init_equilibrium, btdf_set_populations or btdf_load). */
 int btdf_step(btdf_t *h, int64_t n);
 
-/* Same as btdf_step, but times the kernels with HIP events on the streams
- * they run on and writes, in milliseconds per step, the duration of the
- * marker kernel (*ms_ib, 0 if no bodies) and of the lattice kernel (*ms_lbm;
- * the sum of its launches when the marker kernel overlaps it). The events
- * are created on the first timed call and kept until btdf_destroy.
- * Synchronising. */
+/* Same as btdf_step, but times the kernels with HIP events on the handle's
+ * stream and writes, in milliseconds per step, the duration of the marker
+ * kernel (*ms_ib, 0 if no bodies) and of the lattice launches (*ms_lbm).
+ * The events are created on the first timed call and kept until
+ * btdf_destroy. Synchronising. */
 int btdf_step_timed(btdf_t *h, int64_t n, double *ms_ib, double *ms_lbm);
 
 /* As btdf_step_timed with the lattice time split: ms[0] marker kernels and

@@ -22,13 +22,12 @@ PERIODIC, VELOCITY_INLET, ZERO_GRADIENT_OUTLET, BOUNCEBACK_WALL = 0, 1, 2, 3
 FREE_SLIP_WALL, CONVECTIVE_OUTLET = 4, 5
 LINEAR2, ROMA3, PESKIN4, COS4 = 2, 3, 4, 5
 OPT_LBM_VARIANT, OPT_NUM_VARIANTS, OPT_GRAPH_CHUNK, OPT_XCD_REMAP, OPT_TILE_X, OPT_TILE_Y = 1, 2, 3, 4, 5, 6
-OPT_ROW_PAD, OPT_PLANE_PAD, OPT_INTERIOR_PATH, OPT_OVERLAP, OPT_FORCED_TILES = 7, 8, 9, 10, 11
+OPT_ROW_PAD, OPT_PLANE_PAD, OPT_INTERIOR_PATH, OPT_FORCED_TILES = 7, 8, 9, 11
 OPT_MASK_UNSTABLE = 12
 OPT_ROW_ALIGN = 13
 OPT_FORCING_PASSES = 14
 OPT_FORCING_METHOD = 15
 OPT_TEMPORAL_BLOCKING, OPT_FUSED_TILES, OPT_STEPS_PER_PASS = 16, 17, 18
-OPT_GROUP_SHAPE = 19
 NOALLOC_MAX_MARKERS = 262144
 FORCING_DIRECT, FORCING_IMPLICIT, FORCING_RKPM = 0, 1, 2
 

@@ -165,15 +165,14 @@ void cover_lists(const btdf_t *h, std::vector<int> &off, std::vector<int> &list)
 }
 
 // steps per pass of the tiles away from the bodies for the options and the
-// launch shape: 3 where the shape has the three-step pass (unless the
-// overlap option asks for the two-step pass beside the near tiles), else 2
-// where it has the two-step pass, else 1 (no blocking)
+// launch shape: 3 where the shape has the three-step pass, else 2 where it
+// has the two-step pass, else 1 (no blocking)
 int pass_depth(const btdf_t *h) {
   if (!h->tblock) return 1;
   // by default only lattices large enough that the saved bytes outweigh the
   // extra launches of a blocked pass (single handles; a batch shares them)
   if (h->tblock == 1 && !h->owner && (long long)h->nx * h->ny < kBlockMinNodes) return 1;
-  const int want = h->tblock == 1 ? (h->overlap ? 2 : 3) : h->tblock;
+  const int want = h->tblock == 1 ? 3 : h->tblock;
   if (want >= 3 && variant_has_lbm3(h->variant, h->prec, kGroup1x1)) return 3;
   if (variant_has_lbm2(h->variant, h->prec)) return 2;
   return 1;
@@ -188,14 +187,17 @@ static bool has_group(const btdf_t *h, int d, int code) {
   return w == 1 ? variant_has_lbm2(h->variant, h->prec) : variant_has_wide_lbm2(h->variant, h->prec, w);
 }
 
-// The shapes of the three launches of a pass of depth d: groups of four
-// tiles, of two, single tiles. Two tiles tall (2 x 2, then 1 x 2) where the
-// option asks for it and the launch shape has a 2 x 2 pass, else along rows.
-void group_kinds(int gshape, int variant, int prec, int d, int kind[3]) {
-  const bool tall = gshape == 1 && d == 3 && variant_has_lbm3(variant, prec, kGroup2x2);
-  kind[0] = tall ? kGroup2x2 : kGroup4x1;
-  kind[1] = tall ? kGroup1x2 : kGroup2x1;
-  kind[2] = kGroup1x1;
+// The shapes of the launches of a pass of depth d, level by level (tiles
+// are packed into the first level's groups, the rest into the next
+// level's): groups of four tiles along rows, then two, then single tiles.
+// (The launch shape decides which of them have a pass; d is kept for
+// shapes that only one depth has.)
+void group_kinds(int variant, int prec, int d, int kind[kLevels]) {
+  (void)variant;
+  (void)prec;
+  (void)d;
+  static const int rows[kLevels] = {kGroup4x1, kGroup2x1, kGroup1x1, kNoGroup};
+  for (int i = 0; i < kLevels; ++i) kind[i] = rows[i];
 }
 
 // Tiles for temporal blocking of depth d = h->depth on the current launch
@@ -206,7 +208,8 @@ void group_kinds(int gshape, int variant, int prec, int d, int kind[3]) {
 // the pass gives them the intermediate states of the nodes just outside.
 void fused_lists(btdf_t *h) {
   h->fmap.clear();
-  h->n_quad = h->n_wide = h->n_fused = h->n_near = 0;
+  for (int g = 0; g < kLevels; ++g) h->n_grp[g] = 0;
+  h->n_near = 0;
   h->near.clear();
   const int d = h->depth;
   if (d < 2) return;
@@ -234,15 +237,17 @@ void fused_lists(btdf_t *h) {
       }
     }
   }
-  // blocked tiles: groups of four lattice tiles, then of two, where the
-  // launch shape has such a pass (lower-left tile of each group listed),
-  // then the rest. Groups are packed greedily, row by row of tiles, from any
-  // tile column (and, two tiles tall, any tile row), so a run of L far tiles
-  // in a row leaves only L mod 4 of them outside groups of four along rows.
-  group_kinds(h->gshape, h->variant, h->prec, d, h->gkind);
+  // blocked tiles: groups of each level's shape where the launch shape has
+  // such a pass (lower-left tile of each group listed), then the rest as
+  // single tiles. Groups are packed greedily, row by row of tiles, from any
+  // tile column (and, for taller groups, any tile row), so a run of L far
+  // tiles in a row leaves only L mod 4 of them outside groups of four along
+  // rows.
+  group_kinds(h->variant, h->prec, d, h->gkind);
   std::vector<char> grouped(ntiles, 0);
-  for (int g = 0; g < 2; ++g) {
+  for (int g = 0; g < kLevels; ++g) {
     const int code = h->gkind[g], w = code & 15, gh = code >> 4;
+    if (code == kNoGroup || code == kGroup1x1) continue;
     const size_t start = h->fmap.size();
     if (has_group(h, d, code))
       for (int b = 0; b + gh - 1 < nty; ++b)
@@ -260,14 +265,19 @@ void fused_lists(btdf_t *h) {
             for (int k = 0; k < w; ++k) grouped[t + r * ntx + k] = 1;
           a += w;
         }
-    (g == 0 ? h->n_quad : h->n_wide) = (int)(h->fmap.size() - start);
+    h->n_grp[g] = (int)(h->fmap.size() - start);
   }
+  // the single tiles: the level of shape 1 x 1
+  int g1 = 0;
+  while (g1 < kLevels - 1 && h->gkind[g1] != kGroup1x1) ++g1;
+  const size_t start1 = h->fmap.size();
   for (int t = 0; t < ntiles; ++t)
     if (!near[t] && !grouped[t]) h->fmap.push_back(t);
-  h->n_fused = (int)h->fmap.size() - h->n_quad - h->n_wide;
+  h->n_grp[g1] = (int)(h->fmap.size() - start1);
+  const size_t start_near = h->fmap.size();
   for (int t = 0; t < ntiles; ++t)
     if (near[t]) h->fmap.push_back(t);
-  h->n_near = (int)h->fmap.size() - h->n_quad - h->n_wide - h->n_fused;
+  h->n_near = (int)(h->fmap.size() - start_near);
   h->near.assign(near.begin(), near.end());
 }
 
@@ -670,48 +680,18 @@ int clear_flag(btdf_t *h) {
   return ok();
 }
 
-// events around the kernels of one step, for btdf_step_timed
-bool overlapping(const btdf_t *h) { return h->overlap && h->nb() > 0 && h->n_free > 0 && h->n_forced > 0; }
-
-int make_side(btdf_t *h) {
-  if (!h->side) HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
-  if (!h->ev_fork) HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-  if (!h->ev_join) HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
-  return ok();
-}
-
-// One time step on the given buffers. With the overlap, the marker kernel
-// runs on the side stream beside the lattice launch over the tiles no marker
-// touches; the launch over the forced tiles waits for it (their spread force
-// needs this step's F_l) and advances the step counter.
+// One time step on the given buffers: the marker kernel (interpolation,
+// direct force, spread weights), then the lattice kernel over every tile
+// (and the body reductions), then the outlet and rigid motion.
 int enqueue_step(btdf_t *h, const LbmParams &p, const IbParams &ib, int src, hipStream_t s,
                  const StepEvents *te) {
   const void *A = h->ws + h->off_pop[src];
   void *B = h->ws + h->off_pop[1 - src];
-  const int *map = h->at<int>(h->off_tmap);
-  if (overlapping(h)) {
-    int rc = make_side(h);
-    if (rc) return rc;
-    HIPCHK(hipEventRecord(h->ev_fork, s));
-    HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-    if (te) HIPCHK(hipEventRecord(te->ib0, h->side));
-    HIPCHK(launch_ib(h->prec, A, p, ib, h->side));
-    if (te) HIPCHK(hipEventRecord(te->ib1, h->side));
-    HIPCHK(hipEventRecord(h->ev_join, h->side));
-    if (te) HIPCHK(hipEventRecord(te->a0, s));
-    HIPCHK(launch_lbm(h->prec, h->variant, A, B, p, TileRange{map, 0, h->n_free, 0}, ib, s));
-    if (te) HIPCHK(hipEventRecord(te->a1, s));
-    HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
-    if (te) HIPCHK(hipEventRecord(te->b0, s));
-    HIPCHK(launch_lbm(h->prec, h->variant, A, B, p, TileRange{map, h->n_free, h->n_forced, 1}, ib, s));
-    if (te) HIPCHK(hipEventRecord(te->b1, s));
-  } else {
-    if (te) HIPCHK(hipEventRecord(te->ib0, s));
-    HIPCHK(launch_ib(h->prec, A, p, ib, s));
-    if (te) HIPCHK(hipEventRecord(te->ib1, s));
-    HIPCHK(launch_lbm(h->prec, h->variant, A, B, p, TileRange{nullptr, 0, h->ntx * h->nty, 1}, ib, s));
-    if (te) HIPCHK(hipEventRecord(te->a1, s));
-  }
+  if (te) HIPCHK(hipEventRecord(te->ib0, s));
+  HIPCHK(launch_ib(h->prec, A, p, ib, s));
+  if (te) HIPCHK(hipEventRecord(te->ib1, s));
+  HIPCHK(launch_lbm(h->prec, h->variant, A, B, p, TileRange{nullptr, 0, h->ntx * h->nty, 1}, ib, s));
+  if (te) HIPCHK(hipEventRecord(te->a1, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, A, B, p, s));
   // moving bodies advance after the step that used their positions (the body
   // reduction in the lattice launch reads the centres)
@@ -857,9 +837,6 @@ int destroy_impl(btdf_t *h) {
   }
   drop_graph(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-  if (h->side) (void)hipStreamDestroy(h->side);
-  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   h->tev.release();
   if (h->ws && h->ws_owned) (void)hipFree(h->ws);
   delete h;
@@ -1121,7 +1098,6 @@ static int rebin(btdf_t *h) {
   const int n_free = (int)h->tile_map.size();
   for (int t = 0; t < ntiles; ++t)
     if (h->tile_off[t + 1] != h->tile_off[t]) h->tile_map.push_back(t);
-  if (n_free != h->n_free) drop_graph(h);  // the overlapped step launches the free tiles apart
   h->n_free = n_free;
   h->n_forced = ntiles - n_free;
   int rc;
@@ -1171,22 +1147,18 @@ int btdf_step(btdf_t *h, int64_t n) {
 // with the marker kernel between; every other tile takes both steps at once
 // (lbm2_kernel). The nodes just outside the near tiles (the ring) must hold
 // their first step in X before the near tiles' second step: the two-step pass
-// writes them, so it runs first. With the overlap option the two-step pass
-// runs on the side stream beside the near chain instead (it writes disjoint
-// tiles of the destination and reads only the source) and the ring kernel
-// supplies the ring. ev: 7 events (before/after the first marker kernel,
-// after the near tiles' first step, after the second marker kernel, after
-// their second step, before/after the two-step pass) or null.
+// writes them, so it runs first. ev: 7 events (before/after the first marker
+// kernel, after the near tiles' first step, after the second marker kernel,
+// after their second step, before/after the two-step pass) or null.
 static hipError_t launch_two_step(const btdf_t *h, const void *A, void *B, void *X, const unsigned char *near,
                                   const LbmParams &p, const int *fm, hipStream_t s) {
-  hipError_t e = launch_lbm2(h->prec, h->variant, 4, A, B, p, fm, h->n_quad, X, near, s);
-  if (e == hipSuccess) e = launch_lbm2(h->prec, h->variant, 2, A, B, p, fm + h->n_quad, h->n_wide, X, near, s);
-  if (e == hipSuccess)
-    e = launch_lbm2(h->prec, h->variant, 1, A, B, p, fm + h->n_quad + h->n_wide, h->n_fused, X, near, s);
+  // every level is a row of 1, 2 or 4 tiles (see remainder_pair)
+  hipError_t e = hipSuccess;
+  for (int g = 0; g < kLevels && e == hipSuccess; ++g)
+    if (h->n_grp[g])
+      e = launch_lbm2(h->prec, h->variant, h->gkind[g] & 15, A, B, p, fm + h->grp_start(g), h->n_grp[g], X, near, s);
   return e;
 }
-
-static bool pair_overlap(const btdf_t *h) { return h->overlap != 0; }
 
 static int enqueue_pair(btdf_t *h, const LbmParams &p, const IbParams &ib, hipStream_t s, hipEvent_t *ev) {
   const void *A = h->ws + h->off_pop[h->cur];
@@ -1194,28 +1166,14 @@ static int enqueue_pair(btdf_t *h, const LbmParams &p, const IbParams &ib, hipSt
   void *X = h->ws + h->off_pop3;
   const int *fm = h->at<int>(h->off_fmap);
   const unsigned char *near = h->at<unsigned char>(h->off_near);
-  const bool ov = pair_overlap(h);
-  if (ov) {
-    int rc = make_side(h);
-    if (rc) return rc;
-    HIPCHK(hipEventRecord(h->ev_fork, s));
-    HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-    if (ev && ev[5]) HIPCHK(hipEventRecord(ev[5], h->side));
-    HIPCHK(launch_two_step(h, A, B, X, nullptr, p, fm, h->side));
-    if (ev && ev[6]) HIPCHK(hipEventRecord(ev[6], h->side));
-    HIPCHK(hipEventRecord(h->ev_join, h->side));
-  }
   if (ev && ev[0]) HIPCHK(hipEventRecord(ev[0], s));
   HIPCHK(launch_ib(h->prec, A, p, ib, s));
   if (ev && ev[1]) HIPCHK(hipEventRecord(ev[1], s));
-  if (!ov) {
-    if (ev && ev[5]) HIPCHK(hipEventRecord(ev[5], s));
-    HIPCHK(launch_two_step(h, A, B, X, near, p, fm, s));
-    if (ev && ev[6]) HIPCHK(hipEventRecord(ev[6], s));
-  }
-  const int nb0 = h->n_quad + h->n_wide + h->n_fused;  // the near tiles start here in the map
+  if (ev && ev[5]) HIPCHK(hipEventRecord(ev[5], s));
+  HIPCHK(launch_two_step(h, A, B, X, near, p, fm, s));
+  if (ev && ev[6]) HIPCHK(hipEventRecord(ev[6], s));
+  const int nb0 = h->n_groups();  // the near tiles start here in the map
   HIPCHK(launch_lbm(h->prec, h->variant, A, X, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
-  if (ov) HIPCHK(launch_ring(h->prec, A, X, p, fm + nb0, h->n_near, near, h->tile_x, h->tile_y, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, A, X, p, s));
   if (ev && ev[2]) HIPCHK(hipEventRecord(ev[2], s));
   HIPCHK(launch_ib(h->prec, X, p, ib, s));
@@ -1223,7 +1181,6 @@ static int enqueue_pair(btdf_t *h, const LbmParams &p, const IbParams &ib, hipSt
   HIPCHK(launch_lbm(h->prec, h->variant, X, B, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, X, B, p, s));
   if (ev && ev[4]) HIPCHK(hipEventRecord(ev[4], s));
-  if (ov) HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
   h->cur ^= 1;
   h->steps += 2;
   return ok();
@@ -1235,12 +1192,8 @@ static int enqueue_pair(btdf_t *h, const LbmParams &p, const IbParams &ib, hipSt
 // runs before the near tiles' second step; it runs after their first step,
 // whose reads of A bring in the lines the pass's single tiles and pairs
 // (which border near tiles) read for their halos, and these go first.
-// With the overlap option the pass runs on the side stream instead, beside
-// the first two marker kernels and the near tiles' first step (none of
-// which needs the rings), and their second step waits for it.
-// ev: 10 events or null: marker kernel E0-E1, near step E1-E2, pass E5-E6,
-// marker kernel E6-E3 (E2-E3 overlapped), near step E3-E4 (E9-E4
-// overlapped, E9 after the wait), marker kernel E4-E7, near step E7-E8.
+// ev: 9 events or null: marker kernel E0-E1, near step E1-E2, pass E5-E6,
+// marker kernel E6-E3, near step E3-E4, marker kernel E4-E7, near step E7-E8.
 static int enqueue_triple(btdf_t *h, const LbmParams &p, const IbParams &ib, hipStream_t s, hipEvent_t *ev) {
   const void *A = h->ws + h->off_pop[h->cur];
   void *B = h->ws + h->off_pop[1 - h->cur];
@@ -1248,43 +1201,22 @@ static int enqueue_triple(btdf_t *h, const LbmParams &p, const IbParams &ib, hip
   void *X2 = h->ws + h->off_pop4;
   const int *fm = h->at<int>(h->off_fmap);
   const unsigned char *near = h->at<unsigned char>(h->off_near);
-  const int nb0 = h->n_quad + h->n_wide + h->n_fused;  // the near tiles start here in the map
-  const bool ov = h->overlap != 0;
-  auto pass = [&](hipStream_t st) -> hipError_t {
-    hipError_t e = launch_lbm3(h->prec, h->variant, h->gkind[2], A, B, p, fm + h->n_quad + h->n_wide, h->n_fused, X1, X2,
-                               near, st);
-    if (e == hipSuccess)
-      e = launch_lbm3(h->prec, h->variant, h->gkind[1], A, B, p, fm + h->n_quad, h->n_wide, X1, X2, near, st);
-    if (e == hipSuccess) e = launch_lbm3(h->prec, h->variant, h->gkind[0], A, B, p, fm, h->n_quad, X1, X2, near, st);
-    return e;
-  };
-  if (ov) {
-    int rc = make_side(h);
-    if (rc) return rc;
-    HIPCHK(hipEventRecord(h->ev_fork, s));
-    HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-    if (ev && ev[5]) HIPCHK(hipEventRecord(ev[5], h->side));
-    HIPCHK(pass(h->side));
-    if (ev && ev[6]) HIPCHK(hipEventRecord(ev[6], h->side));
-    HIPCHK(hipEventRecord(h->ev_join, h->side));
-  }
+  const int nb0 = h->n_groups();  // the near tiles start here in the map
   if (ev && ev[0]) HIPCHK(hipEventRecord(ev[0], s));
   HIPCHK(launch_ib(h->prec, A, p, ib, s));
   if (ev && ev[1]) HIPCHK(hipEventRecord(ev[1], s));
   HIPCHK(launch_lbm(h->prec, h->variant, A, X1, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, A, X1, p, s));
   if (ev && ev[2]) HIPCHK(hipEventRecord(ev[2], s));
-  if (!ov) {
-    if (ev && ev[5]) HIPCHK(hipEventRecord(ev[5], s));
-    HIPCHK(pass(s));
-    if (ev && ev[6]) HIPCHK(hipEventRecord(ev[6], s));
-  }
+  // the pass: the smallest groups (which border near tiles) first, the largest last
+  if (ev && ev[5]) HIPCHK(hipEventRecord(ev[5], s));
+  for (int g = kLevels - 1; g >= 0; --g)
+    if (h->n_grp[g])
+      HIPCHK(launch_lbm3(h->prec, h->variant, h->gkind[g], A, B, p, fm + h->grp_start(g), h->n_grp[g], X1, X2, near,
+                         s));
+  if (ev && ev[6]) HIPCHK(hipEventRecord(ev[6], s));
   HIPCHK(launch_ib(h->prec, X1, p, ib, s));
   if (ev && ev[3]) HIPCHK(hipEventRecord(ev[3], s));
-  if (ov) {
-    HIPCHK(hipStreamWaitEvent(s, h->ev_join, 0));
-    if (ev && ev[9]) HIPCHK(hipEventRecord(ev[9], s));
-  }
   HIPCHK(launch_lbm(h->prec, h->variant, X1, X2, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, X1, X2, p, s));
   if (ev && ev[4]) HIPCHK(hipEventRecord(ev[4], s));
@@ -1369,7 +1301,7 @@ static int run_blocked(btdf_t *h, const LbmParams &p, const IbParams &ib, int64_
 }
 
 static bool blocking_active(const btdf_t *h) {
-  return h->depth >= 2 && h->layout_ok && h->n_quad + h->n_wide + h->n_fused > 0 && !h->any_moving();
+  return h->depth >= 2 && h->layout_ok && h->n_groups() > 0 && !h->any_moving();
 }
 
 // Whether two steps left over after three-step passes can take one two-step
@@ -1378,10 +1310,13 @@ static bool blocking_active(const btdf_t *h) {
 // three-step pass serve the two-step pass as they are (its groups along
 // rows; not the groups two tiles tall).
 static bool remainder_pair(const btdf_t *h) {
-  if (h->depth != 3 || h->gkind[0] != kGroup4x1 || h->gkind[1] != kGroup2x1) return false;
-  if (!variant_has_lbm2(h->variant, h->prec)) return false;
-  if (h->n_quad && !variant_has_wide_lbm2(h->variant, h->prec, 4)) return false;
-  if (h->n_wide && !variant_has_wide_lbm2(h->variant, h->prec, 2)) return false;
+  if (h->depth != 3 || !variant_has_lbm2(h->variant, h->prec)) return false;
+  for (int g = 0; g < kLevels; ++g) {
+    if (!h->n_grp[g]) continue;
+    const int code = h->gkind[g], w = code & 15;
+    if (code >> 4 != 1) return false;  // taller than one tile
+    if (w > 1 && !variant_has_wide_lbm2(h->variant, h->prec, w)) return false;
+  }
   return true;
 }
 
@@ -1405,7 +1340,6 @@ static int timed_impl(btdf_t *h, int64_t n, double *out, bool pass_only = false)
   if (pass_only)  // only the pass's two events of each entry are recorded
     for (size_t i = 0; i < ev.size(); ++i)
       if (i % NE != 5 && i % NE != 6) ev[i] = nullptr;
-  const bool ov = overlapping(h);
   const int d = h->depth;
   double tib = 0.0, tlbm = 0.0, tpair = 0.0;
   int64_t done = 0, pass_steps = 0;
@@ -1459,13 +1393,11 @@ static int timed_impl(btdf_t *h, int64_t n, double *out, bool pass_only = false)
       if (dk > 1) {
         (void)hipEventElapsedTime(&a, E[0], E[1]);
         // the near tiles' first step: after the first marker kernel in a
-        // triple or an overlapped pair, else after the pass
-        (void)hipEventElapsedTime(&b, dk == 3 || pair_overlap(h) ? E[1] : E[6], E[2]);
-        // the second marker kernel: after the pass in a triple (unless that
-        // runs beside it); the second near step after the wait for the pass
-        const bool ov3 = dk == 3 && h->overlap != 0;
-        (void)hipEventElapsedTime(&c, dk == 3 && !ov3 ? E[6] : E[2], E[3]);
-        (void)hipEventElapsedTime(&e4, ov3 ? E[9] : E[3], E[4]);
+        // triple, after the pass in a pair
+        (void)hipEventElapsedTime(&b, dk == 3 ? E[1] : E[6], E[2]);
+        // the second marker kernel: after the pass in a triple
+        (void)hipEventElapsedTime(&c, dk == 3 ? E[6] : E[2], E[3]);
+        (void)hipEventElapsedTime(&e4, E[3], E[4]);
         (void)hipEventElapsedTime(&f, E[5], E[6]);
         if (dk == 3) {
           (void)hipEventElapsedTime(&g, E[4], E[7]);
@@ -1478,14 +1410,9 @@ static int timed_impl(btdf_t *h, int64_t n, double *out, bool pass_only = false)
         continue;
       }
       (void)hipEventElapsedTime(&a, E[0], E[1]);
-      if (ov) {
-        (void)hipEventElapsedTime(&b, E[2], E[3]);
-        (void)hipEventElapsedTime(&c, E[4], E[5]);
-      } else {
-        (void)hipEventElapsedTime(&b, E[1], E[3]);
-      }
+      (void)hipEventElapsedTime(&b, E[1], E[3]);
       tib += a;
-      tlbm += b + c;
+      tlbm += b;
     }
     done += (int64_t)dk * m;
   }
@@ -1852,15 +1779,6 @@ int btdf_set_option(btdf_t *h, int key, int64_t value) {
         h->xcd_remap = (int)value;
         drop_graph(h);
         return ok();
-      case BTDF_OPT_OVERLAP:
-        if (value != 0 && value != 1) return fail(BTDF_EINVAL, "overlap flag must be 0 or 1");
-        if (value != h->overlap && h->tblock == 1) {
-          h->layout_ok = false;  // the pass depth follows the overlap option
-          h->device_ok = false;
-        }
-        h->overlap = (int)value;
-        drop_graph(h);
-        return ok();
       case BTDF_OPT_INTERIOR_PATH:
         if (value != 0 && value != 1) return fail(BTDF_EINVAL, "interior path flag must be 0 or 1");
         h->interior = (int)value;
@@ -1889,15 +1807,6 @@ int btdf_set_option(btdf_t *h, int key, int64_t value) {
         if (value != h->tblock) {
           h->tblock = (int)value;
           h->layout_ok = false;  // the tile lists and the third buffer
-          h->device_ok = false;
-          drop_graph(h);
-        }
-        return ok();
-      case BTDF_OPT_GROUP_SHAPE:
-        if (value != 0 && value != 1) return fail(BTDF_EINVAL, "group shape must be 0 (rows) or 1 (two tiles tall)");
-        if (value != h->gshape) {
-          h->gshape = (int)value;
-          h->layout_ok = false;  // the tile lists
           h->device_ok = false;
           drop_graph(h);
         }
@@ -1947,7 +1856,6 @@ int btdf_get_option(const btdf_t *h, int key, int64_t *value) {
       case BTDF_OPT_TILE_Y: variant_tile(h->variant, &tx, &ty); *value = ty; return ok();
       case BTDF_OPT_ROW_PAD: *value = h->row_pad; return ok();
       case BTDF_OPT_INTERIOR_PATH: *value = h->interior; return ok();
-      case BTDF_OPT_OVERLAP: *value = h->overlap; return ok();
       case BTDF_OPT_FORCED_TILES:
         if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
         *value = h->n_forced;
@@ -1957,12 +1865,9 @@ int btdf_get_option(const btdf_t *h, int key, int64_t *value) {
       case BTDF_OPT_FORCING_PASSES: *value = h->nf; return ok();
       case BTDF_OPT_FORCING_METHOD: *value = h->method; return ok();
       case BTDF_OPT_TEMPORAL_BLOCKING: *value = h->tblock; return ok();
-      case BTDF_OPT_GROUP_SHAPE: *value = h->gshape; return ok();
       case BTDF_OPT_FUSED_TILES:
         if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
-        *value = blocking_active(h) ? group_tiles(h->gkind[0]) * h->n_quad + group_tiles(h->gkind[1]) * h->n_wide +
-                                          h->n_fused
-                                    : 0;  // in lattice tiles
+        *value = blocking_active(h) ? h->pass_tiles() : 0;  // in lattice tiles
         return ok();
       case BTDF_OPT_STEPS_PER_PASS:
         if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));

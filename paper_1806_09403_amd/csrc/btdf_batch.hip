@@ -40,10 +40,9 @@ struct btdf_batch {
   int tblock = 1;        // option: three steps per pass for the cases' tiles away from their bodies
   bool blocked = false;  // it is on (the launch shape has the three-step pass)
   BatchMap map_near{};   // the near tiles of every case (and the body reductions)
-  const int *g_case[3] = {nullptr, nullptr, nullptr}, *g_tile[3] = {nullptr, nullptr, nullptr};
-  int g_count[3] = {0, 0, 0};  // groups of 4, 2 and 1 tiles of every case
-  int gshape = 0;              // option: the groups' shape (as for single cases)
-  int gkind[3] = {kGroup4x1, kGroup2x1, kGroup1x1};  // the shapes of those three launches
+  const int *g_case[kLevels] = {}, *g_tile[kLevels] = {};
+  int g_count[kLevels] = {};  // groups of every case, level by level
+  int gkind[kLevels] = {kGroup4x1, kGroup2x1, kGroup1x1, kNoGroup};  // the shape of each level's launch
   hipGraphExec_t graph = nullptr;
   hipStream_t cap_stream = nullptr;
   // time
@@ -65,16 +64,14 @@ void batch_layout(btdf_batch_t *b) {
   const int K = (int)b->cases.size();
   long long max_tiles = 0, bodies = 0, mblk = 0;
   b->blocked = b->tblock && variant_has_lbm3(b->variant, b->prec, kGroup1x1);
-  group_kinds(b->gshape, b->variant, b->prec, 3, b->gkind);
+  group_kinds(b->variant, b->prec, 3, b->gkind);
   for (btdf_t *h : b->cases) {
     h->variant = b->variant;
-    h->gshape = b->gshape;
     h->xcd_remap = b->xcd_remap;
     h->interior = b->interior;
     h->row_align = b->row_align;
     h->tblock = b->blocked ? 3 : 0;  // each case's near tiles, groups and extra buffers
     h->reserve_pass = b->tblock != 0;  // slices keep their size across launch shapes
-    h->overlap = 0;
     compute_layout(h);
     long long mt = 0;
     for (int v = 0; v < num_variants(); ++v) {
@@ -91,7 +88,8 @@ void batch_layout(btdf_batch_t *b) {
   o = align256(o + (size_t)K * sizeof(CaseDesc));
   b->off_maps = o;
   // tile maps, near-tile maps and group maps (each at most two ints per tile), body and marker maps
-  o = align256(o + (size_t)(6 * max_tiles + 2 * bodies + 2 * mblk + 16) * sizeof(int));
+  // (plus one int after each of the 8 + 2 kLevels lists)
+  o = align256(o + (size_t)(6 * max_tiles + 2 * bodies + 2 * mblk + 8 + 2 * kLevels + 16) * sizeof(int));
   b->case_off.assign(K, 0);
   for (int c = 0; c < K; ++c) {
     b->case_off[c] = o;
@@ -149,7 +147,7 @@ int batch_ensure(btdf_batch_t *b) {
     // case table
     std::vector<CaseDesc> desc(K);
     std::vector<int> tile_case, tile_local, body_case, body_local, mblk_case, mblk_first;
-    std::vector<int> near_case, near_local, gc[3], gt[3];
+    std::vector<int> near_case, near_local, gc[kLevels], gt[kLevels];
     for (int c = 0; c < K; ++c) {
       btdf_t *h = b->cases[c];
       desc[c].p = make_params(h);
@@ -165,11 +163,10 @@ int batch_ensure(btdf_batch_t *b) {
         tile_local.push_back(t);
       }
       if (b->blocked) {
-        // the case's map: groups of four, of two, single tiles, then near tiles
-        const int n[3] = {h->n_quad, h->n_wide, h->n_fused};
+        // the case's map: its groups level by level, then near tiles
         int k = 0;
-        for (int w = 0; w < 3; ++w)
-          for (int i = 0; i < n[w]; ++i, ++k) {
+        for (int w = 0; w < kLevels; ++w)
+          for (int i = 0; i < h->n_grp[w]; ++i, ++k) {
             gc[w].push_back(c);
             gt[w].push_back(h->fmap[k]);
           }
@@ -207,7 +204,7 @@ int batch_ensure(btdf_batch_t *b) {
         (rc = put(mblk_case, &b->map.mblk_case)) || (rc = put(mblk_first, &b->map.mblk_first)) ||
         (rc = put(near_case, &b->map_near.tile_case)) || (rc = put(near_local, &b->map_near.tile_local)))
       return rc;
-    for (int w = 0; w < 3; ++w) {
+    for (int w = 0; w < kLevels; ++w) {
       if ((rc = put(gc[w], &b->g_case[w])) || (rc = put(gt[w], &b->g_tile[w]))) return rc;
       b->g_count[w] = (int)gc[w].size();
     }
@@ -279,9 +276,10 @@ int batch_enqueue_triple(btdf_batch_t *b, int parity, hipStream_t s, hipEvent_t 
   HIPCHK(rec(1));
   if ((rc = near_step(A, 2))) return rc;
   HIPCHK(rec(2));
-  for (int w : {2, 1, 0})  // single tiles, pairs, then groups of four
-    HIPCHK(launch_lbm3_batch(b->prec, b->variant, b->gkind[w], desc, b->g_case[w], b->g_tile[w], b->g_count[w],
-                             route(A, B), b->mask, b->xcd_remap, s));
+  for (int w = kLevels - 1; w >= 0; --w)  // the smallest groups first, the largest last
+    if (b->g_count[w])
+      HIPCHK(launch_lbm3_batch(b->prec, b->variant, b->gkind[w], desc, b->g_case[w], b->g_tile[w], b->g_count[w],
+                               route(A, B), b->mask, b->xcd_remap, s));
   HIPCHK(rec(3));
   HIPCHK(launch_ib_batch(b->prec, desc, b->map, route(2, 2), s));
   HIPCHK(rec(4));
@@ -622,13 +620,6 @@ int btdf_batch_set_option(btdf_batch_t *b, int key, int64_t value) {
           b->layout_ok = false;    // every case's lists and slice size
         }
         return ok();
-      case BTDF_OPT_GROUP_SHAPE:
-        if (value != 0 && value != 1) return fail(BTDF_EINVAL, "group shape must be 0 (rows) or 1 (two tiles tall)");
-        if (value != b->gshape) {
-          b->gshape = (int)value;
-          b->layout_ok = false;  // every case's lists
-        }
-        return ok();
       default: return fail(BTDF_EINVAL, "unknown or read-only batch option %d", key);
     }
   });
@@ -646,7 +637,6 @@ int btdf_batch_get_option(const btdf_batch_t *b, int key, int64_t *value) {
       case BTDF_OPT_MASK_UNSTABLE: *value = b->mask; return ok();
       case BTDF_OPT_ROW_ALIGN: *value = b->row_align; return ok();
       case BTDF_OPT_TEMPORAL_BLOCKING: *value = b->tblock; return ok();
-      case BTDF_OPT_GROUP_SHAPE: *value = b->gshape; return ok();
       case BTDF_OPT_TILE_X:
       case BTDF_OPT_TILE_Y: {
         int tx, ty;
@@ -659,7 +649,7 @@ int btdf_batch_get_option(const btdf_batch_t *b, int key, int64_t *value) {
         *value = 0;
         if (b->blocked)
           for (const btdf_t *h : b->cases)
-            *value += group_tiles(b->gkind[0]) * h->n_quad + group_tiles(b->gkind[1]) * h->n_wide + h->n_fused;
+            *value += h->pass_tiles();
         return ok();
       case BTDF_OPT_STEPS_PER_PASS:
         if (!b->layout_ok) batch_layout(const_cast<btdf_batch_t *>(b));

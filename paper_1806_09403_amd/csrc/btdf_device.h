@@ -126,6 +126,7 @@ struct CollK {
   T d9, d36;     // 3 guo w
   T m3g;         // -3 guo
   T urx, ury;    // reference velocity
+  T cu5, cu6;    // e.u_ref of the diagonal pairs: urx + ury, ury - urx
 };
 
 // The factors of the Guo term that depend on the force density f only, per
@@ -207,6 +208,8 @@ inline CollK<T> make_coll(double omega, double guo, double urx, double ury) {
   k.m3g = (T)(-3.0 * guo);
   k.urx = (T)urx;
   k.ury = (T)ury;
+  k.cu5 = (T)(urx + ury);
+  k.cu6 = (T)(ury - urx);
   return k;
 }
 
@@ -382,14 +385,17 @@ __device__ __forceinline__ double fmx(double a, double b, double c) { return __b
 // relaxation (eq 5) on the stored deviations g~_q = g_q - c_q of one node:
 //   out~_q = (1 - omega) g~_q + omega (feq_q - c_q) + F_q.
 // With drho = rho - 1, du = u - u_ref (both formed from small terms only),
-// eu = e.u, ea = e.du, eb = e.(u + u_ref) and ef = e.f, opposite directions
-// share the even part and differ in the sign of the odd part:
-//   even = w C + 4.5 omega w (drho eu^2 + ea eb) + eu (9 guo w ef)
-//   odd  = 3 omega w (drho eu + ea) + 3 guo w ef
+// eu = e.u, ea = e.du, cu = e.u_ref and ef = e.f, opposite directions share
+// the even part and differ in the sign of the odd part:
+//   s    = drho eu + ea            (= rho eu - cu)
+//   even = w C + 4.5 omega w (s eu + cu ea) + eu (9 guo w ef)
+//   odd  = 3 omega w s + 3 guo w ef
 //   C    = omega (drho (1 - 1.5 |u|^2) - 1.5 du.(u + u_ref)) - 3 guo u.f
-// (with u_ref = 0 this is omega feq~ + F of the plain deviations f - w).
-// The products of constants (and of constants and f) come in through k and
-// f, so a kernel whose force is uniform takes them from scalar registers.
+// (s eu + cu ea = drho eu^2 + ea (eu + cu): the quadratic term of feq less
+// that of c_q, written in small terms; with u_ref = 0 this is omega feq~ + F
+// of the plain deviations f - w). The products of constants (and of
+// constants and f) come in through k and f, so a kernel whose force is
+// uniform takes them from scalar registers.
 template <typename T>
 __device__ __forceinline__ void collide(const T g[9], const ForceK<T> &f, const CollK<T> &k, T out[9], T &rho) {
   // Every multiply-add is written out and nothing else is fused, so the same
@@ -399,8 +405,9 @@ __device__ __forceinline__ void collide(const T g[9], const ForceK<T> &f, const 
 #pragma clang fp contract(off)
   const T drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
   rho = (T)1 + drho;
-  const T mx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);  // m - u_ref
-  const T my = (g[2] - g[4]) + (g[5] - g[8]) + (g[6] - g[7]);
+  const T d57 = g[5] - g[7], d86 = g[8] - g[6];  // the diagonals' shares of m - u_ref
+  const T mx = (g[1] - g[3]) + (d57 + d86);
+  const T my = (g[2] - g[4]) + (d57 - d86);
   const T inv = recip<T>(rho);
   const T dux = fmx(-drho, k.urx, fmx((T)0.5, f.fx, mx)) * inv;
   const T duy = fmx(-drho, k.ury, fmx((T)0.5, f.fy, my)) * inv;
@@ -411,17 +418,31 @@ __device__ __forceinline__ void collide(const T g[9], const ForceK<T> &f, const 
   const T C = fmx(k.omega, c1, fmx(ux, f.gx, uy * f.gy));
   const T C9 = C * (T)(1.0 / 9.0), C36 = C * (T)(1.0 / 36.0);
   out[0] = fmx(k.omc, g[0], (T)(4.0 / 9.0) * C);
-  auto pair = [&](int qp, int qm, T eu, T ea, T eb, T ev, T od, T ka, T kb, T wC) {
-    const T de = drho * eu;
-    const T even = fmx(ka, fmx(de, eu, ea * eb), fmx(eu, ev, wC));
-    const T odd = fmx(kb, de + ea, od);
+  auto pair = [&](int qp, int qm, T eu, T ea, T cu, T ev, T od, T ka, T kb, T wC) {
+    const T sq = fmx(drho, eu, ea);
+    const T t = fmx(sq, eu, cu * ea);
+    const T even = fmx(ka, t, fmx(eu, ev, wC));
+    const T odd = fmx(kb, sq, od);
     out[qp] = fmx(k.omc, g[qp], even) + odd;
     out[qm] = fmx(k.omc, g[qm], even) - odd;
   };
-  pair(1, 3, ux, dux, sx, f.ev[0], f.od[0], k.a9, k.b9, C9);
-  pair(2, 4, uy, duy, sy, f.ev[1], f.od[1], k.a9, k.b9, C9);
-  pair(5, 7, ux + uy, dux + duy, sx + sy, f.ev[2], f.od[2], k.a36, k.b36, C36);
-  pair(6, 8, uy - ux, duy - dux, sy - sx, f.ev[3], f.od[3], k.a36, k.b36, C36);
+  pair(1, 3, ux, dux, k.urx, f.ev[0], f.od[0], k.a9, k.b9, C9);
+  pair(2, 4, uy, duy, k.ury, f.ev[1], f.od[1], k.a9, k.b9, C9);
+  pair(5, 7, ux + uy, dux + duy, k.cu5, f.ev[2], f.od[2], k.a36, k.b36, C36);
+  pair(6, 8, uy - ux, duy - dux, k.cu6, f.ev[3], f.od[3], k.a36, k.b36, C36);
+}
+
+// the density of a collision is positive and finite: one class test
+// (+subnormal or +normal), the same set as rho > 0 && isfinite(rho)
+template <typename T>
+__device__ __forceinline__ bool rho_ok(T rho) {
+  return __builtin_amdgcn_class(rho, 0x180);
+}
+// a wave's lanes whose density is not: one mask for the whole wave, kept
+// in scalar registers
+template <typename T>
+__device__ __forceinline__ unsigned long long bad_lanes(T rho) {
+  return __builtin_amdgcn_ballot_w64(!rho_ok(rho));
 }
 
 // Streaming pull g_q(x, y) = f_q(x - e_q, y - e_q), as a stored deviation,

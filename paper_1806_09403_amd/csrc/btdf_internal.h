@@ -67,7 +67,6 @@ struct btdf_sim {
   std::vector<int> tile_off, tile_list;
   std::vector<int> tile_map;  // tiles no marker touches first, then the forced tiles
   int n_free = 0, n_forced = 0;
-  int overlap = 0;            // run the marker kernel beside the lattice launch of the free tiles
   int nf = 1;                 // forcing passes per step
   std::vector<int> cover_off, cover_list;  // covering markers per stencil node (nf > 1)
   int method = BTDF_FORCING_DIRECT;        // how the marker force is formed and spread
@@ -90,11 +89,24 @@ struct btdf_sim {
   int tblock = 1;  // option: 0 off, 1 deepest available, 2 or 3 steps per pass
   int depth = 1;   // steps per pass of the tiles away from the bodies (set with the layout)
   bool reserve_pass = false;  // keep the blocked pass's buffers whatever the launch shape (batch cases)
-  std::vector<int> fmap;  // two-step groups of 4 and 2 tiles (first tile of each), single two-step tiles, near tiles
+  // the tile map of the pass: its groups level by level (first tile of each
+  // group), then the near tiles
+  std::vector<int> fmap;
   std::vector<unsigned char> near;  // per lattice tile: 1 if it steps singly
-  int n_quad = 0, n_wide = 0, n_fused = 0, n_near = 0;
-  int gshape = 0;  // option: groups of the three-step pass along rows (0) or two tiles tall (1)
-  int gkind[3] = {btdf::kGroup4x1, btdf::kGroup2x1, btdf::kGroup1x1};  // the shapes of n_quad, n_wide, n_fused (set with the lists)
+  int gkind[btdf::kLevels] = {btdf::kGroup4x1, btdf::kGroup2x1, btdf::kGroup1x1, btdf::kNoGroup};  // shape per level
+  int n_grp[btdf::kLevels] = {0, 0, 0, 0};  // groups per level (set with the lists)
+  int n_near = 0;
+  int n_groups() const { return n_grp[0] + n_grp[1] + n_grp[2] + n_grp[3]; }
+  int grp_start(int g) const {  // index of level g's first group in fmap
+    int k = 0;
+    for (int i = 0; i < g; ++i) k += n_grp[i];
+    return k;
+  }
+  int pass_tiles() const {  // lattice tiles in the pass
+    int k = 0;
+    for (int i = 0; i < btdf::kLevels; ++i) k += btdf::group_tiles(gkind[i]) * n_grp[i];
+    return k;
+  }
   // device memory
   char *ws = nullptr;
   size_t ws_bytes = 0;
@@ -118,8 +130,6 @@ struct btdf_sim {
   hipGraphExec_t graph = nullptr;
   int graph_depth = 0;  // steps per pass the graph was captured with (1: single steps)
   hipStream_t cap_stream = nullptr;
-  hipStream_t side = nullptr;            // marker kernel when it overlaps the lattice kernel
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   btdf_event_pool tev;  // events of the timed stepping calls
 
   int nb() const { return (int)cx.size(); }
@@ -174,7 +184,7 @@ inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 bool valid_kind(int k);
 void drop_graph(btdf_t *h);
 void compute_layout(btdf_t *h);
-void group_kinds(int gshape, int variant, int prec, int d, int kind[3]);
+void group_kinds(int variant, int prec, int d, int kind[kLevels]);
 void bin_markers(const btdf_t *h, int tx, int ty, int ntx, int nty, std::vector<int> &off, std::vector<int> &list);
 void cover_lists(const btdf_t *h, std::vector<int> &off, std::vector<int> &list);
 // implicit / RKPM matrices of the current bodies ("" or the reason they cannot be formed)

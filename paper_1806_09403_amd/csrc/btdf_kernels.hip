@@ -385,7 +385,7 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
     } else {
       collide<T>(g[k], gforce<T>(p), K, out, rho);
     }
-    bad |= !(rho > (T)0) || !isfinite(rho);
+    bad |= !rho_ok(rho);
     if (interior) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
@@ -708,12 +708,12 @@ __global__ __launch_bounds__(BX *BY) void lbm2_kernel(const T *__restrict__ A, T
     }
     T out[9], rho;
     collide<T>(ga, F, K, out, rho);
-    bad |= !(rho > (T)0) || !isfinite(rho);
+    bad |= !rho_ok(rho);
 #pragma unroll
     for (int q = 0; q < 9; ++q) s_f[q][ja][ia] = out[q];
     if (two) {
       collide<T>(gb, F, K, out, rho);
-      bad |= !(rho > (T)0) || !isfinite(rho);
+      bad |= !rho_ok(rho);
 #pragma unroll
       for (int q = 0; q < 9; ++q) s_f[q][jb][ib] = out[q];
     }
@@ -735,7 +735,7 @@ __global__ __launch_bounds__(BX *BY) void lbm2_kernel(const T *__restrict__ A, T
       for (int q = 0; q < 9; ++q) g[q] = s_f[q][j - ey(q)][i - ex(q)];
       T out[9], rho;
       collide<T>(g, F, K, out, rho);
-      bad |= !(rho > (T)0) || !isfinite(rho);
+      bad |= !rho_ok(rho);
       const unsigned off = (unsigned)(jj * p.pitch + ii) * (unsigned)sizeof(T);
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
@@ -825,31 +825,29 @@ bool variant_has_wide_lbm2(int v, int prec, int width) {
 }
 
 // ---- three steps per pass (deeper temporal blocking)
-// Shapes whose three-step pass fits: the group grown by two in LDS (64 KB)
-// and its grown-by-one region within two nodes per thread.
+// Shapes whose three-step pass fits: the group grown by two in LDS (160 KB
+// on gfx950) and its grown-by-one region within two nodes per thread.
 template <typename T, int OX, int OY>
 constexpr bool lbm3_fits() {
-  return 9 * (OX + 4) * (OY + 4) * (int)sizeof(T) <= 65536 && (OX + 2) * (OY + 2) <= 2 * OX * OY;
+  return 9 * (OX + 4) * (OY + 4) * (int)sizeof(T) + 64 <= 163840 && (OX + 2) * (OY + 2) <= 2 * OX * OY;
 }
 
 // Groups of several lattice tiles with a three-step pass: (group code,
 // lattice tile, group in nodes). The code is W | H << 4 for W x H tiles.
-#define BTDF_LBM3_GROUPS(G)                                                                              \
-  G(kGroup4x1, 32, 8, 128, 8) G(kGroup4x1, 16, 8, 64, 8) G(kGroup2x1, 32, 8, 64, 8)                      \
-  G(kGroup2x1, 16, 8, 32, 8) G(kGroup2x1, 64, 4, 128, 4) G(kGroup2x2, 32, 8, 64, 16)                      \
-  G(kGroup1x2, 32, 8, 32, 16)
+#define BTDF_LBM3_GROUPS(G) \
+  G(kGroup4x1, 32, 8, 128, 8) G(kGroup2x1, 32, 8, 64, 8) G(kGroup2x1, 64, 4, 128, 4)
 
 __host__ __device__ constexpr bool lbm3_group_ok(int ox, int oy, int tx, int ty) {
   return tx > 0 && ty > 0 && (tx & (tx - 1)) == 0 && (ty & (ty - 1)) == 0 && ox % tx == 0 && oy % ty == 0 &&
-         ox / tx <= 4 && oy / ty <= 2;
+         ox / tx <= 4 && oy == ty;
 }
 
 // The ring directions of an edge node of a group of W x H lattice tiles:
 // bit q set when the neighbour x + e_q lies in a near tile. s_near holds the
 // near flags of the tiles around the group (row 0 below it, column 0 left of
 // it; the group's own tiles read 0).
-template <int OX, int OY>
-__device__ __forceinline__ unsigned ring_mask(const unsigned char (&s_near)[4][8], int ii, int jj, int W, int H,
+template <int OX, int OY, int NR>
+__device__ __forceinline__ unsigned ring_mask(const unsigned char (&s_near)[NR][8], int ii, int jj, int W, int H,
                                               int shx, int shy) {
   const int cl = ii == 0 ? 0 : 1 + ((ii - 1) >> shx), cm = 1 + (ii >> shx);
   const int cr = ii == OX - 1 ? W + 1 : 1 + ((ii + 1) >> shx);
@@ -935,12 +933,12 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
     }
     T out[9], rho;
     collide<T>(ga, F, K, out, rho);
-    bad |= !(rho > (T)0) || !isfinite(rho);
+    bad |= !rho_ok(rho);
 #pragma unroll
     for (int q = 0; q < 9; ++q) s_f[q][ja][ia] = out[q];
     if (two) {
       collide<T>(gb, F, K, out, rho);
-      bad |= !(rho > (T)0) || !isfinite(rho);
+      bad |= !rho_ok(rho);
 #pragma unroll
       for (int q = 0; q < 9; ++q) s_f[q][jb][ib] = out[q];
     }
@@ -978,7 +976,7 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
       for (int q = 0; q < 9; ++q) g[q] = s_f[q][j - ey(q)][i - ex(q)];
       T rho;
       collide<T>(g, F, K, o, rho);
-      bad |= !(rho > (T)0) || !isfinite(rho);
+      bad |= !rho_ok(rho);
       return j * RX + i;
     };
     if (tid < TOT2) pa = step2(tid, o2a);
@@ -1000,7 +998,7 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
     for (int q = 0; q < 9; ++q) g[q] = s_f[q][j - ey(q)][i - ex(q)];
     T out[9], rho;
     collide<T>(g, F, K, out, rho);
-    bad |= !(rho > (T)0) || !isfinite(rho);
+    bad |= !rho_ok(rho);
     if (!keep) return;  // (after the last barrier)
 #pragma unroll
     for (int q = 0; q < 9; ++q)
@@ -1152,64 +1150,6 @@ bool variant_has_lbm3(int v, int prec, int code) {
   BTDF_VARIANTS(X)
 #undef X
   return fits;
-}
-
-// The first step of the ring of every near tile: the nodes one step outside
-// the tile that lie in a two-step tile (plain interior nodes, no
-// immersed-boundary force; a node next to two near tiles is written twice
-// with the same value), stored only in the directions that point into a
-// near tile. One workgroup per near tile, so the ring is read from the lines
-// the tile's own step has just brought into L2.
-template <typename T>
-__global__ __launch_bounds__(128) void ring_kernel(const T *__restrict__ A, T *__restrict__ X, LbmParams p,
-                                                   const int *__restrict__ near_map, const unsigned char *__restrict__ near,
-                                                   int tile_x, int tile_y) {
-  const int t = near_map[blockIdx.x];
-  const int tyi = t / p.ntx, txi = t - tyi * p.ntx;
-  const int x0 = txi * tile_x, y0 = tyi * tile_y;
-  const int per = 2 * (tile_x + 2) + 2 * tile_y;  // ring positions: two rows, two columns
-  for (int k = (int)threadIdx.x; k < per; k += 128) {
-    int x, y;
-    if (k < tile_x + 2) {
-      x = x0 - 1 + k;
-      y = y0 - 1;
-    } else if (k < 2 * (tile_x + 2)) {
-      x = x0 - 1 + (k - (tile_x + 2));
-      y = y0 + tile_y;
-    } else {
-      const int r = k - 2 * (tile_x + 2);
-      x = (r & 1) ? x0 + tile_x : x0 - 1;
-      y = y0 + (r >> 1);
-    }
-    if (p.xper) x = x < 0 ? x + p.nx : (x >= p.nx ? x - p.nx : x);
-    if (p.yper) y = y < 0 ? y + p.ny : (y >= p.ny ? y - p.ny : y);
-    if (x < 0 || x >= p.nx || y < 0 || y >= p.ny) continue;
-    if (near[(y / tile_y) * p.ntx + x / tile_x]) continue;  // a near tile steps its own nodes
-    T g[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) g[q] = A[(long long)q * p.plane + (long long)(y - ey(q)) * p.pitch + (x - ex(q))];
-    T out[9], rho;
-    collide<T>(g, gforce<T>(p), coll<T>(p), out, rho);
-    const long long base = (long long)y * p.pitch + x;
-    // only the populations that a near tile pulls: direction q when x + e_q
-    // lies in a near tile (such a node is interior, so no wrap is needed)
-#pragma unroll
-    for (int q = 1; q < 9; ++q)
-      if (near[((y + ey(q)) / tile_y) * p.ntx + (x + ex(q)) / tile_x]) X[(long long)q * p.plane + base] = out[q];
-    if (!(rho > (T)0) || !isfinite(rho)) p.flag[0] = -1;
-  }
-}
-
-hipError_t launch_ring(int prec, const void *A, void *X, const LbmParams &p, const int *near_map, int n_near,
-                       const unsigned char *near, int tile_x, int tile_y, hipStream_t s) {
-  if (n_near <= 0) return hipSuccess;
-  if (prec == 4)
-    hipLaunchKernelGGL(ring_kernel<float>, dim3(n_near), dim3(128), 0, s, (const float *)A, (float *)X, p, near_map,
-                       near, tile_x, tile_y);
-  else
-    hipLaunchKernelGGL(ring_kernel<double>, dim3(n_near), dim3(128), 0, s, (const double *)A, (double *)X, p,
-                       near_map, near, tile_x, tile_y);
-  return hipGetLastError();
 }
 
 // whether a launch shape has a two-step kernel (one node per thread, LDS within 64 KB)

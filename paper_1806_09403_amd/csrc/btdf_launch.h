@@ -19,8 +19,12 @@ hipError_t launch_lbm2(int prec, int variant, int width, const void *A, void *C,
 bool variant_has_wide_lbm2(int variant, int prec, int width);
 // group shapes of the three-step pass, W | H << 4 for W x H lattice tiles
 // (map entries name a group's lower-left tile)
-constexpr int kGroup1x1 = 0x11, kGroup2x1 = 0x12, kGroup4x1 = 0x14, kGroup1x2 = 0x21, kGroup2x2 = 0x22;
+constexpr int kGroup1x1 = 0x11, kGroup2x1 = 0x12, kGroup4x1 = 0x14;
+constexpr int kNoGroup = 0;  // an unused level
 constexpr int group_tiles(int code) { return (code & 15) * (code >> 4); }
+// A pass launches its groups level by level: up to kLevels shapes, the
+// largest first in the tile map, single tiles last.
+constexpr int kLevels = 4;
 // three steps A -> C over the listed groups of the given shape; with near
 // non-null, edge nodes next to a near tile also store their first and second
 // steps in X1 and X2
@@ -31,8 +35,6 @@ bool variant_has_lbm3(int variant, int prec, int code);
 hipError_t launch_lbm3_batch(int prec, int variant, int code, const CaseDesc *cases, const int *gcase,
                              const int *gtile, int count, int rt, int mask, int xcd, hipStream_t s);
 bool variant_has_lbm2(int variant, int prec);
-hipError_t launch_ring(int prec, const void *A, void *X, const LbmParams &p, const int *near_map, int n_near,
-                       const unsigned char *near, int tile_x, int tile_y, hipStream_t s);
 hipError_t launch_conv_outlet(int prec, const void *A, void *B, const LbmParams &p, hipStream_t s);
 hipError_t launch_conv_outlet_batch(int prec, const CaseDesc *cases, int ncases, int mask_unstable, int rt,
                                     hipStream_t s);

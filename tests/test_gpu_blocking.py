@@ -63,36 +63,13 @@ def test_blocked_steps_are_bit_identical(name, seed, nx, ny, bc, precision, dept
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
-@pytest.mark.parametrize("precision", [4, 8])
-@pytest.mark.parametrize("name,seed,nx,ny,bc", CASES)
-def test_tall_groups_are_bit_identical(name, seed, nx, ny, bc, precision):
-    """Groups of 2x2 and 1x2 lattice tiles in the three-step pass (their ring
-    spans two tile rows) give the bits of single steps; in FP64, where 2x2
-    does not fit the LDS, the option falls back to groups along rows."""
-    from paper_1806_09403_amd import _lib
-    log("tall groups %s prec=%d" % (name, precision))
-    c = bodies_case(seed, nx, ny, bc)
-    steps = (1, 2, 7, 20)
-    ref = run(c, 0, steps, precision)
-    got = run(c, 3, steps, precision, options={_lib.OPT_GROUP_SHAPE: 1})
-    rows = run(c, 3, (1,), precision)
-    assert got[2] > 0 and ref[2] == 0
-    if precision == 8:
-        assert got[2] == rows[2]
-    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
-
-
 @pytest.mark.parametrize("depth", [2, 3])
-@pytest.mark.parametrize("opts", ["passes", "implicit", "rkpm", "timed", "timed-pass", "overlap", "overlap-timed"])
+@pytest.mark.parametrize("opts", ["passes", "implicit", "rkpm", "timed", "timed-pass"])
 def test_blocking_with_other_features(opts, depth):
-    """(With the overlap option the two-step pass runs on a second stream and
-    the ring kernel, not the pass, gives the near tiles their neighbours'
-    first step.)"""
     from paper_1806_09403_amd import _lib
     c = bodies_case(45, 384, 192, W.CHANNEL, kind=W.ROMA3)
     o = {"passes": {_lib.OPT_FORCING_PASSES: 3}, "implicit": {_lib.OPT_FORCING_METHOD: 1},
-         "rkpm": {_lib.OPT_FORCING_METHOD: 2}, "timed": {}, "timed-pass": {}, "overlap": {_lib.OPT_OVERLAP: 1},
-         "overlap-timed": {_lib.OPT_OVERLAP: 1}}[opts]
+         "rkpm": {_lib.OPT_FORCING_METHOD: 2}, "timed": {}, "timed-pass": {}}[opts]
     timed = "pass" if opts == "timed-pass" else opts.endswith("timed")
     ref = run(c, 0, (3, 10), 4, o, timed=timed)
     got = run(c, depth, (3, 10), 4, o, timed=timed)
@@ -119,8 +96,8 @@ def test_every_launch_shape_with_the_blocked_pass(depth, min_active):
 
 def test_default_depth_follows_the_lattice_size():
     """By default lattices of 2^20 nodes or more take three steps per pass
-    (two with the overlap option) and smaller ones step singly; a depth asked
-    for explicitly applies to any size."""
+    and smaller ones step singly; a depth asked for explicitly applies to any
+    size."""
     from paper_1806_09403_amd import Sim, _lib
     big = bodies_case(47, 1024, 1024, W.FULLY_PERIODIC)
     small = bodies_case(47, 512, 256, W.FULLY_PERIODIC)
@@ -128,7 +105,7 @@ def test_default_depth_follows_the_lattice_size():
         s = Sim.from_case(big, precision=prec)
         assert s.get_option(_lib.OPT_TEMPORAL_BLOCKING) == 1
         assert s.get_option(_lib.OPT_STEPS_PER_PASS) == 3
-        s.set_option(_lib.OPT_OVERLAP, 1)      # the overlapped pass is the two-step one
+        s.set_option(_lib.OPT_TEMPORAL_BLOCKING, 2)
         assert s.get_option(_lib.OPT_STEPS_PER_PASS) == 2
         s.close()
         s = Sim.from_case(small, precision=prec)
@@ -154,23 +131,21 @@ def test_moving_bodies_step_singly_under_blocking():
     assert np.array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("depth,chunk,shape", [(3, 7, 0), (3, 9, 0), (3, 12, 0), (2, 6, 0), (2, 8, 0),
-                                               (3, 7, 1), (3, 12, 1)])
-def test_blocked_passes_in_graphs(depth, chunk, shape):
+@pytest.mark.parametrize("depth,chunk", [(3, 7), (3, 9), (3, 12), (2, 6), (2, 8)])
+def test_blocked_passes_in_graphs(depth, chunk):
     """Graphs of chunk // depth whole passes (an even or an odd number of
     passes, so graphs are entered from either buffer, with single steps
     before and after) give the bits of eager single steps, checked after
     every call: each call replays the graph one or more times, with the
     program's own synchronising reads between the calls."""
     from paper_1806_09403_amd import Sim, _lib
-    log("blocked graphs depth=%d chunk=%d group shape %d" % (depth, chunk, shape))
+    log("blocked graphs depth=%d chunk=%d" % (depth, chunk))
     c = bodies_case(49, 384, 192, W.CHANNEL)
     ref = Sim.from_case(c, precision=4)
     ref.set_option(_lib.OPT_TEMPORAL_BLOCKING, 0)
     got = Sim.from_case(c, precision=4)
     got.set_option(_lib.OPT_GRAPH_CHUNK, chunk)
     got.set_option(_lib.OPT_TEMPORAL_BLOCKING, depth)
-    got.set_option(_lib.OPT_GROUP_SHAPE, shape)
     assert got.get_option(_lib.OPT_STEPS_PER_PASS) == depth
     for n in (1, 25, 2, 30, 19):
         ref.step(n)

@@ -102,11 +102,10 @@ def test_launch_shapes_and_graphs_are_bit_identical():
     c = W.random_case(55, nx=150, ny=64, n_bodies=2, D_range=(6.0, 9.0))
     for method in (1, 2):
         ref = None
-        for v, chunk, overlap in ((6, 0, 0), (6, 5, 0), (0, 0, 1), (11, 7, 1)):
+        for v, chunk in ((6, 0), (6, 5), (0, 0), (11, 7)):
             g = gpu_of(c, method, precision=4)
             g.set_option(_lib.OPT_LBM_VARIANT, v)
             g.set_option(_lib.OPT_GRAPH_CHUNK, chunk)
-            g.set_option(_lib.OPT_OVERLAP, overlap)
             g.step(4)
             g.step(11)
             out = (g.populations(), g.force_history(15))

@@ -142,17 +142,16 @@ def test_graph_replay_and_launch_shapes_are_bit_identical():
     log("mdf graph and launch shapes")
     c = W.random_case(7, nx=150, ny=64, n_bodies=2)
     ref = None
-    for v, chunk, overlap in ((6, 0, 0), (6, 5, 0), (0, 0, 1), (11, 7, 1)):
+    for v, chunk in ((6, 0), (6, 5), (0, 0), (11, 7)):
         g = gpu_of(c, 3, precision=4)
         g.set_option(_lib.OPT_LBM_VARIANT, v)
         g.set_option(_lib.OPT_GRAPH_CHUNK, chunk)
-        g.set_option(_lib.OPT_OVERLAP, overlap)
         for n in (4, 11):
             g.step(n)
         out = (g.populations(), g.force_history(15))
         if ref is None:
             ref = out
-        assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), (v, chunk, overlap)
+        assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), (v, chunk)
         g.close()
 
 

@@ -85,10 +85,9 @@ def test_launch_shapes_graphs_and_timed_steps_are_bit_identical():
     bodies = [W.cylinder_body(50.3, 30.2, 10.0, 31), W.cylinder_body(100.7, 40.1, 9.0, 28)]
     motions = [(0.03, 0.01, 0.002), (-0.02, 0.0, -0.004)]
     ref = None
-    for v, chunk, overlap, timed in ((6, 0, 0, False), (6, 16, 0, False), (0, 0, 1, False), (11, 5, 1, False),
-                                     (6, 0, 0, True)):
+    for v, chunk, timed in ((6, 0, False), (6, 16, False), (0, 0, False), (11, 5, False), (6, 0, True)):
         o, g = both(150, 64, W.FULLY_PERIODIC, W.COS4, bodies, motions, precision=4,
-                    options={_lib.OPT_LBM_VARIANT: v, _lib.OPT_GRAPH_CHUNK: chunk, _lib.OPT_OVERLAP: overlap})
+                    options={_lib.OPT_LBM_VARIANT: v, _lib.OPT_GRAPH_CHUNK: chunk})
         for n in (7, 60, 33):
             if timed:
                 g.step_timed(n)
@@ -98,7 +97,7 @@ def test_launch_shapes_graphs_and_timed_steps_are_bit_identical():
         if ref is None:
             ref = out
         for a, b in zip(out, ref):
-            assert np.array_equal(a, b), (v, chunk, overlap, timed)
+            assert np.array_equal(a, b), (v, chunk, timed)
         g.close()
 
 

@@ -143,12 +143,11 @@ def test_every_launch_shape_is_bit_identical():
     g0 = gpu_of(c, precision=4)
     nv = g0.get_option(_lib.OPT_NUM_VARIANTS)
     for v in range(nv):
-        for remap, interior, overlap in ((0, 1, 1), (1, 1, 1), (1, 0, 1), (1, 1, 0)):
+        for remap, interior in ((0, 1), (1, 1), (1, 0)):
             g = gpu_of(c, precision=4)
             g.set_option(_lib.OPT_LBM_VARIANT, v)
             g.set_option(_lib.OPT_XCD_REMAP, remap)
             g.set_option(_lib.OPT_INTERIOR_PATH, interior)
-            g.set_option(_lib.OPT_OVERLAP, overlap)
             assert 0 < g.get_option(_lib.OPT_FORCED_TILES)
             g.step(9)
             f = g.populations()
@@ -156,8 +155,8 @@ def test_every_launch_shape_is_bit_identical():
             assert hist.shape[0] == 9
             if ref is None:
                 ref, ref_hist = f, hist
-            assert np.array_equal(f, ref), (v, remap, interior, overlap)
-            assert np.array_equal(hist, ref_hist), (v, remap, interior, overlap)
+            assert np.array_equal(f, ref), (v, remap, interior)
+            assert np.array_equal(hist, ref_hist), (v, remap, interior)
 
 
 def test_interior_path_keeps_the_outlet_column():
@@ -184,9 +183,8 @@ def test_graph_replay_is_bit_identical():
     from paper_1806_09403_amd import _lib
     c = W.random_case(9, nx=120, ny=64, n_bodies=2)
     a = gpu_of(c, precision=8)
-    a.set_option(_lib.OPT_OVERLAP, 0)
     b = gpu_of(c, precision=8)
-    b.set_option(_lib.OPT_GRAPH_CHUNK, 6)     # graph of the overlapped step
+    b.set_option(_lib.OPT_GRAPH_CHUNK, 6)
     for n in (1, 13, 6, 5, 20):      # odd counts realign, several replays per call
         a.step(n)
         b.step(n)
