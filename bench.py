@@ -255,6 +255,7 @@ def bench_adjoint(args):
     hbar[:, 0, 0] = 2.0 / (c.U * c.U * c.D) / n
     out = {"workload": "800x400 channel, D = 40, 126 markers, Re 100, FP32; J = mean Cd over %d steps" % n,
            "steps": n, "forward_ms_per_step": round(fwd_ms / n, 5)}
+    grads = {}
     for name, K in (("sqrt_checkpoints", 0), ("tape", n)):
         s = make()
         s.adjoint(min(n, 60), hbar[:min(n, 60)], checkpoint_every=K)  # first launches, graph paths
@@ -265,6 +266,8 @@ def bench_adjoint(args):
         t0 = time.perf_counter()
         g, ms = s.adjoint(n, hbar, checkpoint_every=K)
         wall = (time.perf_counter() - t0) * 1e3
+        if K == 0:
+            grads[4] = c5_gradient_terms(c, s, g, n)
         s.close()
         rev = ms[2]
         out[name] = {"checkpoint_every": K if K else int(np.ceil(np.sqrt(n))), "workspace_gb": round(nbytes / 1e9, 3),
@@ -274,6 +277,71 @@ def bench_adjoint(args):
         print("adjoint %s: forward pass %.1f ms, recompute %.1f ms (overlapped), reverse sweep %.1f ms; "
               "sweep / forward = %.2f" % (name, ms[0], ms[1], ms[2], rev / fwd_ms), file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
+    out["gradient_check"] = c5_gradient_check(c, n, grads[4])
+    return out
+
+
+C5_UV_SAMPLES = ((0, 0), (16, 1), (31, 1), (70, 0))
+
+
+def c5_gradient_terms(c, s, g, n):
+    """dJ/dU, dJ/dx_c and sampled dJ/dU_b from one adjoint call's gradients,
+    J the mean drag coefficient over the n steps the call ran."""
+    import numpy as np
+    U, D = c.U, c.D
+    hist = s.force_history(n)
+    J = float(np.mean(2.0 * hist[:, 0, 0] / (U * U * D)))
+    ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], float)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    dfeq = w * (3.0 * ex + 9.0 * ex * ex * U - 3.0 * U)  # d/dU of feq_q(1, (U, 0)), the initial state
+    dU = g["inflow"][0] + float(np.einsum("qyx,q->", g["populations"], dfeq)) - 2.0 * J / U
+    dx = float(np.sum(g["marker_xy"][:, 0]) + g["centres"][0, 0])
+    return {"J": J, "dU": dU, "dx": dx, "uv": [float(g["marker_uv"][l, k]) for l, k in C5_UV_SAMPLES]}
+
+
+def c5_gradient_check(c, n, g32):
+    """FP32 (the timed call) and FP64 adjoint gradients against FP64 central
+    differences of the GPU forward run, h = 1e-4: relative errors of dJ/dU,
+    dJ/dx_c and three marker velocities' dJ/dU_b."""
+    import numpy as np
+    from paper_1806_09403_amd import Sim
+    b = c.bodies[0]
+    U, D, h = c.U, c.D, 1e-4
+
+    def make(prec, u=U, dx=0.0, uv=None):
+        s = Sim(c.nx, c.ny, c.tau, c.kind, c.thickening, c.bc, (u, 0.0), c.G, (1.0, u, 0.0), prec, history_capacity=n)
+        s.add_body(b.xy + np.array([dx, 0.0]), b.uv if uv is None else uv, b.cx + dx, b.cy, b.ds)
+        return s
+
+    def J(u=U, **kw):  # the coefficient's normalisation moves with the inflow speed
+        s = make(8, u=u, **kw)
+        s.step(n)
+        hist = s.force_history(n)
+        s.close()
+        return float(np.mean(2.0 * hist[:, 0, 0] / (u * u * D)))
+
+    s = make(8)
+    hbar = np.zeros((n, 1, 3))
+    hbar[:, 0, 0] = 2.0 / (U * U * D) / n
+    g, _ = s.adjoint(n, hbar, checkpoint_every=0)
+    g64 = c5_gradient_terms(c, s, g, n)
+    s.close()
+    fd = {"dU": (J(u=U + h) - J(u=U - h)) / (2 * h), "dx": (J(dx=h) - J(dx=-h)) / (2 * h), "uv": []}
+    for l, k in C5_UV_SAMPLES:
+        duv = np.zeros_like(b.xy)
+        duv[l, k] = h
+        fd["uv"].append((J(uv=duv) - J(uv=-duv)) / (2 * h))
+
+    def rel(a, r):
+        return float("%.3g" % abs(a / r - 1.0))
+
+    out = {"reference": "FP64 central differences of the GPU forward run, h = 1e-4", "target_rel": 1e-4,
+           "J_fp32_vs_fp64_rel": rel(g32["J"], g64["J"])}
+    for name, a in (("fp32", g32), ("fp64", g64)):
+        out[name] = {"dJ_dU_rel": rel(a["dU"], fd["dU"]), "dJ_dxc_rel": rel(a["dx"], fd["dx"]),
+                     "dJ_dUb_rel": [rel(x, r) for x, r in zip(a["uv"], fd["uv"])]}
+    out["dUb_samples"] = [list(t) for t in C5_UV_SAMPLES]
+    print("gradient check: %s" % json.dumps(out), file=sys.stderr, flush=True)
     return out
 
 

@@ -5,10 +5,11 @@ every boundary kind and delta (the oracle's adjoint is itself pinned to
 central differences of its forward step). Checkpointed and taped sweeps are
 bit-identical, and the forward run inside btdf_adjoint leaves exactly the
 state and history plain stepping leaves. On the 800x400 Re = 100 channel
-(126 markers, 5000 steps) the FP32 adjoint's gradient of the mean drag
-coefficient with respect to the inflow speed, the cylinder centre and
-marker velocities agrees with FP64 central differences of the GPU forward
-run (h = 1e-4).
+(126 markers, 5000 steps) the FP64 adjoint's gradients of the mean drag
+coefficient (inflow speed, cylinder centre, marker velocities) agree with
+FP64 central differences of the GPU forward run to 1e-4; the FP32 adjoint
+meets that bound for marker velocities norm-wise but not for the inflow
+speed and the centre (an expected failure that states the measured errors).
 """
 import numpy as np
 import pytest
@@ -153,48 +154,80 @@ def c5_adjoint(precision, n, K=0):
                 uv=g["marker_uv"])
 
 
-@pytest.mark.slow
-def test_c5_gradients_match_fp64_central_differences():
-    """FP64 adjoint: every gradient within 1e-4 relative of FP64 central
-    differences (h = 1e-4). FP32 adjoint: the same, with each bound scaled by
-    the size of the terms the quantity is summed from -- the FP32 forward run
-    itself carries a relative error of ~1e-4 on J here (the impulsive start
-    drives a large acoustic transient whose rounding the mean drag
-    inherits), which enters dJ/dU through the explicit -2 J / U, and dJ/dx_c
-    is a sum of per-marker terms that cancel to ~1e-3 of their size."""
+UV_SAMPLES = ((0, 0), (16, 1), (31, 0), (31, 1), (70, 0), (70, 1))  # not (0, 1): zero by symmetry
+
+
+@pytest.fixture(scope="module")
+def c5_gradients():
+    """FP64 and FP32 adjoints of the mean drag over 5000 steps and FP64
+    central differences of the GPU forward run (h = 1e-4) for dJ/dU, dJ/dx_c,
+    dJ/dy_c and six marker velocities."""
     c = W.c5()
     U, n, h = c.U, 5000, 1e-4
     log("c5 adjoint: 800x400, 126 markers, %d steps, sqrt(N) checkpoints" % n)
     a64 = c5_adjoint(8, n)
     a32 = c5_adjoint(4, n)
-    fdU = (c5_J(U + h) - c5_J(U - h)) / (2 * h)
-    fdx = (c5_J(U, dx=h) - c5_J(U, dx=-h)) / (2 * h)
-    fdy = (c5_J(U, dy=h) - c5_J(U, dy=-h)) / (2 * h)
-    log("  FD: dJ/dU %.8e dJ/dx %.8e dJ/dy %.3e" % (fdU, fdx, fdy))
+    fd = dict(dU=(c5_J(U + h) - c5_J(U - h)) / (2 * h),
+              dx=(c5_J(U, dx=h) - c5_J(U, dx=-h)) / (2 * h),
+              dy=(c5_J(U, dy=h) - c5_J(U, dy=-h)) / (2 * h))
+    nm = c.bodies[0].xy.shape[0]
+    fd["uv"] = {}
+    for l, comp in UV_SAMPLES:
+        uv = np.zeros((nm, 2))
+        uv[l, comp] = h
+        fd["uv"][l, comp] = (c5_J(U, uv=uv) - c5_J(U, uv=-uv)) / (2 * h)
+    log("  FD: dJ/dU %.8e dJ/dx %.8e dJ/dy %.3e" % (fd["dU"], fd["dx"], fd["dy"]))
+    for p, a in (("FP64", a64), ("FP32", a32)):
+        log("  %s relative errors: dJ/dU %.2e dJ/dx_c %.2e; dJ/dU_b %s" % (
+            p, abs(a["dU"] / fd["dU"] - 1), abs(a["dx"] / fd["dx"] - 1),
+            " ".join("%.1e" % abs(a["uv"][k] / fd["uv"][k] - 1) for k in UV_SAMPLES)))
+    return a64, a32, fd
+
+
+@pytest.mark.slow
+def test_c5_fp64_gradients_match_central_differences(c5_gradients):
+    """FP64 adjoint: dJ/dU, dJ/dx_c and six dJ/dU_b within 1e-4 relative of
+    FP64 central differences; dJ/dy_c (zero by the channel's symmetry up to
+    the half-node offset of the centre) within 1e-4 of |dJ/dx_c|."""
+    a64, _, fd = c5_gradients
     tol = 1e-4
-    # FP64
-    assert abs(a64["dU"] - fdU) <= tol * abs(fdU)
-    assert abs(a64["dx"] - fdx) <= tol * abs(fdx)
-    assert abs(a64["dy"] - fdy) <= tol * abs(fdx)  # symmetric: both ~0
-    # FP32, against the sizes of the summed terms
-    assert abs(a32["dU"] - fdU) <= tol * (abs(a32["dU_flow"]) + 2.0 * a32["J"] / U)
-    xscale = float(np.sum(np.abs(a64["xy"][:, 0])) + abs(a64["cx"]))
-    assert abs(a32["dx"] - fdx) <= tol * xscale
-    assert abs(a32["dy"] - fdy) <= tol * xscale
-    # the response parts of FP32 and FP64 agree marker by marker
+    assert abs(a64["dU"] - fd["dU"]) <= tol * abs(fd["dU"])
+    assert abs(a64["dx"] - fd["dx"]) <= tol * abs(fd["dx"])
+    assert abs(a64["dy"] - fd["dy"]) <= tol * abs(fd["dx"])
+    for k in UV_SAMPLES:
+        assert abs(a64["uv"][k] - fd["uv"][k]) <= tol * abs(fd["uv"][k]), k
+
+
+@pytest.mark.slow
+def test_c5_fp32_flow_response_matches_fp64(c5_gradients):
+    """FP32 adjoint against FP64: the flow-response part of dJ/dU (inlet and
+    initial state), every marker's dJ/dX_l and dJ/dU_b, within 1e-4 of the
+    FP64 values' scale; the sampled dJ/dU_b within 1e-4 of central
+    differences relative to the largest sampled entry (norm-wise)."""
+    a64, a32, fd = c5_gradients
+    tol = 1e-4
     assert abs(a32["dU_flow"] - a64["dU_flow"]) <= tol * abs(a64["dU_flow"])
     assert np.max(np.abs(a32["xy"] - a64["xy"])) <= tol * np.max(np.abs(a64["xy"]))
     assert np.max(np.abs(a32["uv"] - a64["uv"])) <= tol * np.max(np.abs(a64["uv"]))
-    nm = c.bodies[0].xy.shape[0]
-    floor = 1e-3 * np.max(np.abs(a64["uv"]))
-    for l in (0, 31, 70):
-        for comp in (0, 1):
-            uv = np.zeros((nm, 2))
-            uv[l, comp] = h
-            fd = (c5_J(U, uv=uv) - c5_J(U, uv=-uv)) / (2 * h)
-            log("  dJ/dU_b[%d,%d] FP64 %.8e FP32 %.8e FD %.8e" % (l, comp, a64["uv"][l, comp], a32["uv"][l, comp], fd))
-            assert abs(a64["uv"][l, comp] - fd) <= tol * max(abs(fd), floor)
-            assert abs(a32["uv"][l, comp] - fd) <= tol * max(abs(fd), floor)
+    scale = max(abs(v) for v in fd["uv"].values())
+    for k in UV_SAMPLES:
+        assert abs(a32["uv"][k] - fd["uv"][k]) <= tol * scale, k
+
+
+@pytest.mark.slow
+@pytest.mark.xfail(strict=False, reason="FP32 misses 1e-4: measured dJ/dU 3.3e-4 and dJ/dx_c 1.3e-3 relative, "
+                   "dJ/dU_b 1.4e-4 entry-wise on one of six sampled markers. "
+                   "The FP32 forward's mean drag is 9.4e-5 off FP64 (a per-step bias present from the "
+                   "first hundred steps), which enters dJ/dU through -2J/U; dJ/dx_c is a sum of "
+                   "per-marker terms that cancel to 1e-3 of their size")
+def test_c5_fp32_gradients_within_1e4_of_central_differences(c5_gradients):
+    """The FP32 target: dJ/dU, dJ/dx_c and each sampled dJ/dU_b within 1e-4
+    relative of FP64 central differences."""
+    _, a32, fd = c5_gradients
+    assert abs(a32["dU"] - fd["dU"]) <= 1e-4 * abs(fd["dU"])
+    assert abs(a32["dx"] - fd["dx"]) <= 1e-4 * abs(fd["dx"])
+    for k in UV_SAMPLES:
+        assert abs(a32["uv"][k] - fd["uv"][k]) <= 1e-4 * abs(fd["uv"][k]), k
 
 
 def torch_equilibrium(rho, ux, uy, nx, ny):
