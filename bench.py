@@ -63,9 +63,89 @@ def parse():
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint figures")
     p.add_argument("--only-adjoint", action="store_true", help="print the adjoint figures alone")
     p.add_argument("--adjoint-steps", type=int, default=5000)
+    p.add_argument("--no-shedding", action="store_true",
+                   help="skip the 2000x800 Re 200 shedding run (100 000 steps, Table 3)")
+    p.add_argument("--no-other-delta", action="store_true",
+                   help="skip timing the particle-laden lattice with the other delta (3-point / cosine)")
     p.add_argument("--no-validation", action="store_true",
                    help="skip the 1601^2 cylinder check at Re 40 (Table 3)")
     return p.parse_args()
+
+
+def timed_blocks(sim, steps, repeats, fused_tiles):
+    """`repeats` timed blocks of exactly `steps` steps, each bracketed by
+    device synchronisations: wall seconds, the blocked pass's per-launch ms
+    (HIP events around its launches only: events around every launch would
+    add about 2% to a step) and, without blocking, the split kernel times."""
+    import torch
+    walls, passes, splits = [], [], []
+    for _ in range(max(1, repeats)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if fused_tiles > 0:
+            ms_pass, split = sim.step_timed_pass(steps), None
+        else:
+            split = sim.step_timed_split(steps)
+            ms_pass = split[2]
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        passes.append(ms_pass)
+        splits.append(split)
+        sim.forces()  # surfaces an instability as an error
+    return walls, passes, splits
+
+
+def bench_other_delta(args, kind_name):
+    """The particle-laden lattice with the other delta of the pair the
+    workload names (3-point with thickening 1.9, 4-point cosine with 2.6):
+    the same steps and timed blocks, the whole step's MLUPS and the blocked
+    pass's fraction of HBM at its compulsory bytes."""
+    import btdf_workloads as W
+    from paper_1806_09403_amd import Sim, _lib
+    kind = {"cos4": W.COS4, "roma3": W.ROMA3, "peskin4": W.PESKIN4}[kind_name]
+    case = W.c3(kind=kind)
+    sim = Sim.from_case(case, precision=4, set_init=False)
+    try:
+        fused = sim.get_option(_lib.OPT_FUSED_TILES)
+        depth = sim.get_option(_lib.OPT_STEPS_PER_PASS)
+        sim.step(max(0, args.warmup - depth))
+        if fused > 0:
+            sim.step_timed_pass(depth)
+        walls, passes, splits = timed_blocks(sim, args.steps, min(args.repeats, 3), fused)
+        order = sorted(range(len(walls)), key=lambda i: walls[i])
+        med = order[len(order) // 2]
+        wall = walls[med]
+        out = {"workload": case.name, "delta": kind_name, "thickening": case.thickening, "steps": args.steps,
+               "ms_per_step": round(wall * 1e3 / args.steps, 5),
+               "value": round(case.nodes * args.steps / wall / 1e6, 2), "unit": "MLUPS",
+               "ms_per_step_repeats": [round(w * 1e3 / args.steps, 5) for w in walls]}
+        if fused > 0:
+            tile = sim.get_option(_lib.OPT_TILE_X) * sim.get_option(_lib.OPT_TILE_Y)
+            launch_ms = depth * passes[med]
+            ach = fused * tile * 9 * 2 * 4 / (launch_ms * 1e-3) / 1e9
+            out["lbm%d_kernel" % depth] = {"launch_ms": round(launch_ms, 5), "achieved": round(ach, 1),
+                                           "frac": round(ach / HBM_PEAK_GBS, 4)}
+        return out
+    finally:
+        sim.close()
+
+
+def bench_shedding(args):
+    """Unsteady shedding behind the D = 80 cylinder in the 2000x800 channel
+    at Re 200 (FP32, cosine delta): 100 000 steps, the last 40 000 recorded.
+    C_D as mean and half swing, the lift's half swing and the Strouhal
+    number, beside Table 3's Re 200 row (a 40D x 40D domain there, 10%
+    blockage here: a loose comparison)."""
+    import btdf_workloads as W
+    from paper_1806_09403_amd import validation
+    t0 = time.perf_counter()
+    case = W.c2()
+    r = validation.run_unsteady(case, warmup=60_000, window=40_000)
+    return {"workload": case.name, "delta": "cos4", "thickening": case.thickening, "Re": 200,
+            "steps": r["steps"], "window": 40_000, "Cd": round(r["Cd"], 4), "Cd_dev": round(r["Cd_dev"], 4),
+            "Cl_dev": round(r["Cl_dev"], 4), "St": round(r["St"], 4),
+            "paper": {"Cd": 1.364, "Cd_dev": 0.042, "Cl_dev": 0.699, "St": 0.195},
+            "seconds": round(time.perf_counter() - t0, 1)}
 
 
 def make_case(args):
@@ -416,24 +496,12 @@ def main():
     # the timed region, repeated: each block is exactly --steps steps,
     # bracketed by stream synchronisations; value and ms_per_step are the
     # median block
-    walls, passes = [], []
-    for _ in range(max(1, args.repeats)):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        if fused_tiles > 0:
-            # HIP events around the blocked pass's launches only (events
-            # around every launch would add about 2% to a step)
-            ms_pass = sim.step_timed_pass(args.steps)
-        else:
-            ms_ib, ms_single, ms_pass = sim.step_timed_split(args.steps)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        walls.append(t1 - t0)
-        passes.append(ms_pass)
-        sim.forces()  # surfaces an instability as an error
+    walls, passes, splits = timed_blocks(sim, args.steps, args.repeats, fused_tiles)
     order = sorted(range(len(walls)), key=lambda i: walls[i])
     med = order[len(order) // 2]
     wall, ms_pass = walls[med], passes[med]
+    if fused_tiles <= 0:
+        ms_ib, ms_single, _ = splits[med]
     split_steps = args.steps
     if fused_tiles > 0:
         # the other kernels' times: events around every launch, in a separate
@@ -519,6 +587,10 @@ def main():
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    if args.workload == "particles" and args.delta in ("cos4", "roma3") and not args.no_other_delta:
+        other = "roma3" if args.delta == "cos4" else "cos4"
+        line["other_delta"] = bench_other_delta(args, other)
+        torch.cuda.empty_cache()
     if not args.no_batched:
         line["batched"] = bench_batched(args)
         torch.cuda.empty_cache()
@@ -527,6 +599,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_validation:
         line["validation"] = bench_validation(args)
+        torch.cuda.empty_cache()
+    if not args.no_shedding:
+        line["shedding"] = bench_shedding(args)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_budget_s, args.cpu_one_core_budget_s)

@@ -52,6 +52,22 @@ def test_shedding_at_re200():
     assert abs(r["Cl_mean"]) < 0.02
 
 
+def test_blocked_channel_shedding_at_re200_loosely():
+    """The 2000x800 channel with a D = 80 cylinder at Re 200 (cosine delta,
+    FP32), 100 000 steps, the last 40 000 recorded. Its 10% blockage and
+    channel walls differ from the paper's 40D x 40D domain, so C_D and St are
+    held to Table 3's Re 200 row only within 10%, the lift's half swing
+    within 25%."""
+    from paper_1806_09403_amd import validation as V
+    log("c2 Re 200, 2000x800, 60 000 + 40 000 steps")
+    r = V.run_unsteady(W.c2(), warmup=60_000, window=40_000, log=log)
+    log("  %s" % r)
+    p = PAPER["re200"]
+    assert rel(r["Cd"], p["Cd"]) < 0.10
+    assert rel(r["St"], p["St"]) < 0.10
+    assert rel(r["Cl_dev"], p["Cl_dev"]) < 0.25
+
+
 def test_one_pass_of_the_thickened_shell_against_forcing_passes():
     """Fig. 16's comparison at Re 40, D/dh = 40: one pass with the thickened
     shell is about as accurate as three to four passes of conventional
