@@ -116,8 +116,9 @@ extern "C" {
                                       stand-alone handles only, NF = 1, bodies of at most 2048 markers; the
                                       matrices are formed on the host when the bodies or the method change */
 #define BTDF_OPT_TEMPORAL_BLOCKING 16 /* d steps per pass for the tiles at least d-1 nodes clear of every marker
-                                         stencil and d nodes clear of the domain edges (each node read and
-                                         written once for d updates); the others step singly with the marker
+                                         stencil and (see BTDF_OPT_EDGE_TILES) d nodes clear of the domain edges
+                                         (each node read and written once for d updates); the others step singly
+                                         with the marker
                                          kernel between, and the pass gives them the intermediate states of the
                                          nodes just outside. Results are bit-identical to single steps.
                                          1 (default): the deepest the launch shape has (3, or 2 when the shape
@@ -132,6 +133,14 @@ extern "C" {
                                          Steps left over after whole passes: on a stand-alone handle two after
                                          three-step passes take one two-step pass over the same tiles,
                                          otherwise (and in batches) they step singly. */
+#define BTDF_OPT_EDGE_TILES 20        /* 1: tiles within reach of a domain edge (periodic seams, walls, the inlet and a
+                                         zero-gradient outlet; not a convective outlet) also take the blocked pass,
+                                         with the boundary readings in every step, in launches of their own; 0: they
+                                         step singly with the near tiles. Default 0 for a stand-alone handle (its few
+                                         edge tiles do not repay the launches' fixed cost), 1 in a batch (whose
+                                         launches gather the edge tiles of every case). Results are bit-identical
+                                         either way. */
+#define BTDF_OPT_EDGE_FUSED_TILES 21  /* read-only: of BTDF_OPT_FUSED_TILES, the tiles within reach of a domain edge */
 #define BTDF_OPT_FUSED_TILES 17       /* read-only: lattice tiles that take the blocked pass (0 when it is not active) */
 #define BTDF_OPT_STEPS_PER_PASS 18    /* read-only: steps per pass of those tiles (1 when blocking is not active) */
 #define BTDF_OPT_FORCING_PASSES 14 /* NF in 1..64 (default 1): direct-forcing passes per step (Sec. 2.3, eqs 29-31);
@@ -383,7 +392,8 @@ int btdf_batch_step_timed(btdf_batch_t *b, int64_t n, double *ms_ib, double *ms_
 /* unstable[c] = 1 if case c's instability flag is set (array of n_cases, may
  * be NULL); *n_steps = batch steps taken. Synchronising. */
 int btdf_batch_status(btdf_batch_t *b, int *unstable, int64_t *n_steps);
-/* Options: BTDF_OPT_LBM_VARIANT, _GRAPH_CHUNK, _XCD_REMAP, _INTERIOR_PATH, _MASK_UNSTABLE, _ROW_ALIGN. */
+/* Options: BTDF_OPT_LBM_VARIANT, _GRAPH_CHUNK, _XCD_REMAP, _INTERIOR_PATH, _MASK_UNSTABLE, _ROW_ALIGN,
+   _TEMPORAL_BLOCKING, _EDGE_TILES. */
 int btdf_batch_set_option(btdf_batch_t *b, int key, int64_t value);
 int btdf_batch_get_option(const btdf_batch_t *b, int key, int64_t *value);
 /* As btdf_autotune, for the batched launches. */

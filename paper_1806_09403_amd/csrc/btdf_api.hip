@@ -181,9 +181,10 @@ int pass_depth(const btdf_t *h) {
 // whether the pass of depth d has a launch over groups of the given shape
 // (two-step pass: one row of 1, 2 or 4 tiles)
 static bool has_group(const btdf_t *h, int d, int code) {
+  if (is_edge(code)) return variant_has_edge(h->variant, h->prec, d, code);
   if (d == 3) return variant_has_lbm3(h->variant, h->prec, code);
   const int w = code & 15;
-  if (code >> 4 != 1) return false;
+  if (((code >> 4) & 15) != 1) return false;
   return w == 1 ? variant_has_lbm2(h->variant, h->prec) : variant_has_wide_lbm2(h->variant, h->prec, w);
 }
 
@@ -196,28 +197,44 @@ void group_kinds(int variant, int prec, int d, int kind[kLevels]) {
   (void)variant;
   (void)prec;
   (void)d;
-  static const int rows[kLevels] = {kGroup4x1, kGroup2x1, kGroup1x1, kNoGroup};
+  static const int rows[kLevels] = {kGroup4x1, kGroup1x4, kGroup2x1, kGroup1x1};
   for (int i = 0; i < kLevels; ++i) kind[i] = rows[i];
 }
 
 // Tiles for temporal blocking of depth d = h->depth on the current launch
 // shape: a tile is "near" if a marker stencil grown by d - 1 nodes reaches
-// it or if it lies within d nodes of a domain edge (a pass takes its first
-// step over its tiles grown by d - 1 nodes, which must hold no forced and no
-// boundary node). Near tiles step singly, with the marker kernel between;
-// the pass gives them the intermediate states of the nodes just outside.
+// it (a pass takes its first step over its tiles grown by d - 1 nodes, which
+// must hold no forced node). Near tiles step singly, with the marker kernel
+// between; the pass gives them the intermediate states of the nodes just
+// outside. Of the other tiles, those within d nodes of a domain edge (or
+// reaching past the grid) take the pass one by one with the boundary
+// readings in every step (the edge level), unless an edge in reach is a
+// convective outlet, or the zero-gradient outlet's ghost column and column
+// nx-2 fall in different tiles: those tiles are near too.
 void fused_lists(btdf_t *h) {
   h->fmap.clear();
-  for (int g = 0; g < kLevels; ++g) h->n_grp[g] = 0;
+  for (int g = 0; g < kLevels; ++g) h->n_grp[g] = h->n_edge[g] = 0;
   h->n_near = 0;
   h->near.clear();
   const int d = h->depth;
   if (d < 2) return;
   const int tx = h->tile_x, ty = h->tile_y, ntx = h->ntx, nty = h->nty, ntiles = ntx * nty;
-  std::vector<char> near(ntiles, 0);
+  // (edge groups wrap a node index by one period at most: a periodic extent
+  // must hold the widest or tallest group, four tiles, and the margins)
+  const bool edge_pass = h->edge_tiles && has_group(h, d, kEdge1x1) && (!h->xper() || h->nx >= 4 * tx + 8) &&
+                         (!h->yper() || h->ny >= 4 * ty + 8);
+  const bool conv = h->bc[1] == BTDF_CONVECTIVE_OUTLET;
+  // the zero-gradient outlet's ghost (nx-1) alone in the last tile column
+  const bool split_ghost = h->bc[1] == BTDF_ZERO_GRADIENT_OUTLET && (h->nx - 1) % tx == 0;
+  std::vector<char> near(ntiles, 0), edge(ntiles, 0);
   for (int t = 0; t < ntiles; ++t) {
     const int x0 = (t % ntx) * tx, y0 = (t / ntx) * ty;
-    if (x0 < d || x0 + tx + d > h->nx || y0 < d || y0 + ty + d > h->ny) near[t] = 1;
+    const bool xr = x0 + tx + d > h->nx;  // within reach of the east edge
+    if (!(x0 < d || xr || y0 < d || y0 + ty + d > h->ny)) continue;
+    bool ok = edge_pass;
+    if (!h->xper() && xr && conv) ok = false;
+    if (!h->xper() && split_ghost && (x0 == h->nx - 1 || x0 + tx == h->nx - 1)) ok = false;
+    (ok ? edge : near)[t] = 1;
   }
   for (int l = 0; l < h->nm(); ++l) {
     int xlo, xhi, ylo, yhi;
@@ -237,43 +254,47 @@ void fused_lists(btdf_t *h) {
       }
     }
   }
-  // blocked tiles: groups of each level's shape where the launch shape has
-  // such a pass (lower-left tile of each group listed), then the rest as
-  // single tiles. Groups are packed greedily, row by row of tiles, from any
-  // tile column (and, for taller groups, any tile row), so a run of L far
-  // tiles in a row leaves only L mod 4 of them outside groups of four along
-  // rows.
+  for (int t = 0; t < ntiles; ++t)
+    if (near[t]) edge[t] = 0;
+  // Blocked tiles, level by level (the map lists the levels in order, each
+  // group by its lower-left tile): rows of four tiles where the launch shape
+  // has such a pass, then rows of two, then single tiles. A level lists its
+  // edge groups first (flagged with kEdgeFlag), then its interior groups.
+  // Groups are packed greedily, row by row of tiles, from any tile column, so
+  // a run of L tiles of one kind in a row leaves only L mod 4 of them outside
+  // groups of four.
   group_kinds(h->variant, h->prec, d, h->gkind);
-  std::vector<char> grouped(ntiles, 0);
+  // taken[k][t]: tile t is not free for groups of kind k (0 interior, 1 edge)
+  std::vector<char> taken[2] = {std::vector<char>(ntiles), std::vector<char>(ntiles)};
+  for (int t = 0; t < ntiles; ++t) {
+    taken[0][t] = near[t] || edge[t];
+    taken[1][t] = near[t] || !edge[t];
+  }
   for (int g = 0; g < kLevels; ++g) {
-    const int code = h->gkind[g], w = code & 15, gh = code >> 4;
-    if (code == kNoGroup || code == kGroup1x1) continue;
+    const int code = h->gkind[g], w = code & 15, gh = (code >> 4) & 15;
     const size_t start = h->fmap.size();
-    if (has_group(h, d, code))
+    for (int kind = 1; kind >= 0; --kind) {
+      if (code == kNoGroup || !has_group(h, d, kind ? (kEdge | code) : code)) continue;
+      std::vector<char> &tk = taken[kind];
       for (int b = 0; b + gh - 1 < nty; ++b)
         for (int a = 0; a + w - 1 < ntx;) {
           const int t = b * ntx + a;
           bool ok = true;
           for (int r = 0; r < gh; ++r)
-            for (int k = 0; k < w; ++k) ok = ok && !near[t + r * ntx + k] && !grouped[t + r * ntx + k];
+            for (int k = 0; k < w; ++k) ok = ok && !tk[t + r * ntx + k];
           if (!ok) {
             ++a;
             continue;
           }
-          h->fmap.push_back(t);
+          h->fmap.push_back(kind ? (t | kEdgeFlag) : t);
           for (int r = 0; r < gh; ++r)
-            for (int k = 0; k < w; ++k) grouped[t + r * ntx + k] = 1;
+            for (int k = 0; k < w; ++k) tk[t + r * ntx + k] = 1;
           a += w;
         }
+      if (kind) h->n_edge[g] = (int)(h->fmap.size() - start);
+    }
     h->n_grp[g] = (int)(h->fmap.size() - start);
   }
-  // the single tiles: the level of shape 1 x 1
-  int g1 = 0;
-  while (g1 < kLevels - 1 && h->gkind[g1] != kGroup1x1) ++g1;
-  const size_t start1 = h->fmap.size();
-  for (int t = 0; t < ntiles; ++t)
-    if (!near[t] && !grouped[t]) h->fmap.push_back(t);
-  h->n_grp[g1] = (int)(h->fmap.size() - start1);
   const size_t start_near = h->fmap.size();
   for (int t = 0; t < ntiles; ++t)
     if (near[t]) h->fmap.push_back(t);
@@ -358,8 +379,8 @@ void compute_layout(btdf_t *h) {
   const size_t pop_bytes = align256(9 * (size_t)h->plane * elt);
   h->off_pop[0] = 0;
   h->off_pop[1] = pop_bytes;
-  h->off_ctl = 2 * pop_bytes;
-  h->grid_bytes = h->off_ctl + 256;
+  h->off_ctl = 2 * pop_bytes;  // 256 B of counters and flags, then 512 B of constants (kKonstBytes)
+  h->grid_bytes = h->off_ctl + 768;
 
   variant_tile(h->variant, &h->tile_x, &h->tile_y);
   h->ntx = (h->nx + h->tile_x - 1) / h->tile_x;
@@ -491,6 +512,7 @@ LbmParams make_params(const btdf_t *h) {
   p.kind = h->kind;
   p.step_ctr = h->at<long long>(h->off_ctl);
   p.flag = h->at<int>(h->off_ctl + 8);
+  p.konst = h->ws + h->off_ctl + 256;
   fill_collision(p);
   return p;
 }
@@ -609,7 +631,10 @@ int init_state(btdf_t *h) {
   LbmParams p = make_params(h);
   HIPCHK(launch_init_uniform(h->prec, h->ws + h->off_pop[0], p, h->rho0, h->u0[0], h->u0[1], h->stream));
   HIPCHK(hipMemsetAsync(h->ws + h->off_ctl, 0, 256, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
+  unsigned char konst[kKonstBytes];
+  fill_konst(p, konst);
+  HIPCHK(hipMemcpyAsync(h->ws + h->off_ctl + 256, konst, kKonstBytes, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));  // (konst is on this stack)
   h->cur = 0;
   h->steps = 0;
   h->hist_read = 0;
@@ -1154,9 +1179,11 @@ static hipError_t launch_two_step(const btdf_t *h, const void *A, void *B, void 
                                   const LbmParams &p, const int *fm, hipStream_t s) {
   // every level is a row of 1, 2 or 4 tiles (see remainder_pair)
   hipError_t e = hipSuccess;
-  for (int g = 0; g < kLevels && e == hipSuccess; ++g)
-    if (h->n_grp[g])
-      e = launch_lbm2(h->prec, h->variant, h->gkind[g] & 15, A, B, p, fm + h->grp_start(g), h->n_grp[g], X, near, s);
+  for (int g = 0; g < kLevels && e == hipSuccess; ++g) {
+    const int ne = h->n_edge[g], ni = h->n_grp[g] - ne, *lv = fm + h->grp_start(g);
+    if (ne) e = launch_lbm_edge2(h->prec, h->variant, kEdge | h->gkind[g], A, B, p, lv, ne, X, near, s);
+    if (ni && e == hipSuccess) e = launch_lbm2(h->prec, h->variant, h->gkind[g] & 15, A, B, p, lv + ne, ni, X, near, s);
+  }
   return e;
 }
 
@@ -1210,10 +1237,11 @@ static int enqueue_triple(btdf_t *h, const LbmParams &p, const IbParams &ib, hip
   if (ev && ev[2]) HIPCHK(hipEventRecord(ev[2], s));
   // the pass: the smallest groups (which border near tiles) first, the largest last
   if (ev && ev[5]) HIPCHK(hipEventRecord(ev[5], s));
-  for (int g = kLevels - 1; g >= 0; --g)
-    if (h->n_grp[g])
-      HIPCHK(launch_lbm3(h->prec, h->variant, h->gkind[g], A, B, p, fm + h->grp_start(g), h->n_grp[g], X1, X2, near,
-                         s));
+  for (int g = kLevels - 1; g >= 0; --g) {
+    const int ne = h->n_edge[g], ni = h->n_grp[g] - ne, *lv = fm + h->grp_start(g);
+    if (ne) HIPCHK(launch_lbm_edge3(h->prec, h->variant, kEdge | h->gkind[g], A, B, p, lv, ne, X1, X2, near, s));
+    if (ni) HIPCHK(launch_lbm3(h->prec, h->variant, h->gkind[g], A, B, p, lv + ne, ni, X1, X2, near, s));
+  }
   if (ev && ev[6]) HIPCHK(hipEventRecord(ev[6], s));
   HIPCHK(launch_ib(h->prec, X1, p, ib, s));
   if (ev && ev[3]) HIPCHK(hipEventRecord(ev[3], s));
@@ -1314,7 +1342,9 @@ static bool remainder_pair(const btdf_t *h) {
   for (int g = 0; g < kLevels; ++g) {
     if (!h->n_grp[g]) continue;
     const int code = h->gkind[g], w = code & 15;
-    if (code >> 4 != 1) return false;  // taller than one tile
+    if (h->n_edge[g] && !variant_has_edge(h->variant, h->prec, 2, kEdge | code)) return false;
+    if (h->n_grp[g] == h->n_edge[g]) continue;
+    if (((code >> 4) & 15) != 1) return false;  // taller than one tile
     if (w > 1 && !variant_has_wide_lbm2(h->variant, h->prec, w)) return false;
   }
   return true;
@@ -1802,6 +1832,15 @@ int btdf_set_option(btdf_t *h, int key, int64_t value) {
         h->row_align = (int)value;
         h->layout_ok = false;
         return ok();
+      case BTDF_OPT_EDGE_TILES:
+        if (value != 0 && value != 1) return fail(BTDF_EINVAL, "edge tiles must be 0 (step singly) or 1 (blocked)");
+        if (value != h->edge_tiles) {
+          h->edge_tiles = (int)value;
+          h->layout_ok = false;  // the tile lists
+          h->device_ok = false;
+          drop_graph(h);
+        }
+        return ok();
       case BTDF_OPT_TEMPORAL_BLOCKING:
         if (value < 0 || value > 3) return fail(BTDF_EINVAL, "temporal blocking must be 0 (off), 1 (deepest), 2 or 3");
         if (value != h->tblock) {
@@ -1865,6 +1904,14 @@ int btdf_get_option(const btdf_t *h, int key, int64_t *value) {
       case BTDF_OPT_FORCING_PASSES: *value = h->nf; return ok();
       case BTDF_OPT_FORCING_METHOD: *value = h->method; return ok();
       case BTDF_OPT_TEMPORAL_BLOCKING: *value = h->tblock; return ok();
+      case BTDF_OPT_EDGE_TILES: *value = h->edge_tiles; return ok();
+      case BTDF_OPT_EDGE_FUSED_TILES: {
+        if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
+        int k = 0;
+        for (int g = 0; g < kLevels; ++g) k += group_tiles(h->gkind[g]) * h->n_edge[g];
+        *value = blocking_active(h) ? k : 0;
+        return ok();
+      }
       case BTDF_OPT_FUSED_TILES:
         if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
         *value = blocking_active(h) ? h->pass_tiles() : 0;  // in lattice tiles

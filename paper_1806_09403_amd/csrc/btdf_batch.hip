@@ -41,8 +41,11 @@ struct btdf_batch {
   bool blocked = false;  // it is on (the launch shape has the three-step pass)
   BatchMap map_near{};   // the near tiles of every case (and the body reductions)
   const int *g_case[kLevels] = {}, *g_tile[kLevels] = {};
-  int g_count[kLevels] = {};  // groups of every case, level by level
-  int gkind[kLevels] = {kGroup4x1, kGroup2x1, kGroup1x1, kNoGroup};  // the shape of each level's launch
+  int g_count[kLevels] = {};  // interior groups of every case, level by level
+  const int *ge_case[kLevels] = {}, *ge_tile[kLevels] = {};
+  int ge_count[kLevels] = {};  // edge groups of every case, level by level
+  int edge_tiles = 1;          // option: tiles within reach of a case's edges take the pass
+  int gkind[kLevels] = {};  // the shape of each level's launch
   hipGraphExec_t graph = nullptr;
   hipStream_t cap_stream = nullptr;
   // time
@@ -71,6 +74,7 @@ void batch_layout(btdf_batch_t *b) {
     h->interior = b->interior;
     h->row_align = b->row_align;
     h->tblock = b->blocked ? 3 : 0;  // each case's near tiles, groups and extra buffers
+    h->edge_tiles = b->edge_tiles;
     h->reserve_pass = b->tblock != 0;  // slices keep their size across launch shapes
     compute_layout(h);
     long long mt = 0;
@@ -88,8 +92,8 @@ void batch_layout(btdf_batch_t *b) {
   o = align256(o + (size_t)K * sizeof(CaseDesc));
   b->off_maps = o;
   // tile maps, near-tile maps and group maps (each at most two ints per tile), body and marker maps
-  // (plus one int after each of the 8 + 2 kLevels lists)
-  o = align256(o + (size_t)(6 * max_tiles + 2 * bodies + 2 * mblk + 8 + 2 * kLevels + 16) * sizeof(int));
+  // (plus one int after each of the 8 + 4 kLevels lists)
+  o = align256(o + (size_t)(6 * max_tiles + 2 * bodies + 2 * mblk + 8 + 4 * kLevels + 16) * sizeof(int));
   b->case_off.assign(K, 0);
   for (int c = 0; c < K; ++c) {
     b->case_off[c] = o;
@@ -147,7 +151,7 @@ int batch_ensure(btdf_batch_t *b) {
     // case table
     std::vector<CaseDesc> desc(K);
     std::vector<int> tile_case, tile_local, body_case, body_local, mblk_case, mblk_first;
-    std::vector<int> near_case, near_local, gc[kLevels], gt[kLevels];
+    std::vector<int> near_case, near_local, gc[kLevels], gt[kLevels], gce[kLevels], gte[kLevels];
     for (int c = 0; c < K; ++c) {
       btdf_t *h = b->cases[c];
       desc[c].p = make_params(h);
@@ -163,12 +167,14 @@ int batch_ensure(btdf_batch_t *b) {
         tile_local.push_back(t);
       }
       if (b->blocked) {
-        // the case's map: its groups level by level, then near tiles
+        // the case's map: its groups level by level (edge groups first in a
+        // level), then near tiles
         int k = 0;
         for (int w = 0; w < kLevels; ++w)
           for (int i = 0; i < h->n_grp[w]; ++i, ++k) {
-            gc[w].push_back(c);
-            gt[w].push_back(h->fmap[k]);
+            const bool e = i < h->n_edge[w];
+            (e ? gce : gc)[w].push_back(c);
+            (e ? gte : gt)[w].push_back(h->fmap[k]);
           }
         for (int i = 0; i < h->n_near; ++i, ++k) {
           near_case.push_back(c);
@@ -205,13 +211,17 @@ int batch_ensure(btdf_batch_t *b) {
         (rc = put(near_case, &b->map_near.tile_case)) || (rc = put(near_local, &b->map_near.tile_local)))
       return rc;
     for (int w = 0; w < kLevels; ++w) {
-      if ((rc = put(gc[w], &b->g_case[w])) || (rc = put(gt[w], &b->g_tile[w]))) return rc;
+      if ((rc = put(gc[w], &b->g_case[w])) || (rc = put(gt[w], &b->g_tile[w])) || (rc = put(gce[w], &b->ge_case[w])) ||
+          (rc = put(gte[w], &b->ge_tile[w])))
+        return rc;
       b->g_count[w] = (int)gc[w].size();
+      b->ge_count[w] = (int)gce[w].size();
     }
     HIPCHK(hipStreamSynchronize(b->stream));  // the host vectors go out of scope
     b->map.ntiles = b->ntiles;
     b->map.nbodies = b->nbodies;
     b->map.nmblk = b->nmblk;
+    b->map.ncases = K;
     b->map.xcd_remap = b->xcd_remap;
     b->map.mask_unstable = b->mask;
     // the near tiles' steps: their own tile maps, the same body and marker maps
@@ -223,6 +233,7 @@ int batch_ensure(btdf_batch_t *b) {
     b->map_near.ntiles = (int)near_case.size();
     b->map_near.nbodies = full.nbodies;
     b->map_near.nmblk = full.nmblk;
+    b->map_near.ncases = full.ncases;
     b->map_near.xcd_remap = full.xcd_remap;
     b->map_near.mask_unstable = full.mask_unstable;
     b->device_ok = true;
@@ -276,10 +287,14 @@ int batch_enqueue_triple(btdf_batch_t *b, int parity, hipStream_t s, hipEvent_t 
   HIPCHK(rec(1));
   if ((rc = near_step(A, 2))) return rc;
   HIPCHK(rec(2));
-  for (int w = kLevels - 1; w >= 0; --w)  // the smallest groups first, the largest last
+  for (int w = kLevels - 1; w >= 0; --w) {  // the smallest groups first, the largest last
+    if (b->ge_count[w])
+      HIPCHK(launch_lbm_edge3_batch(b->prec, b->variant, kEdge | b->gkind[w], desc, b->ge_case[w], b->ge_tile[w],
+                                    b->ge_count[w], route(A, B), b->mask, b->xcd_remap, s));
     if (b->g_count[w])
       HIPCHK(launch_lbm3_batch(b->prec, b->variant, b->gkind[w], desc, b->g_case[w], b->g_tile[w], b->g_count[w],
                                route(A, B), b->mask, b->xcd_remap, s));
+  }
   HIPCHK(rec(3));
   HIPCHK(launch_ib_batch(b->prec, desc, b->map, route(2, 2), s));
   HIPCHK(rec(4));
@@ -620,6 +635,13 @@ int btdf_batch_set_option(btdf_batch_t *b, int key, int64_t value) {
           b->layout_ok = false;    // every case's lists and slice size
         }
         return ok();
+      case BTDF_OPT_EDGE_TILES:
+        if (value != 0 && value != 1) return fail(BTDF_EINVAL, "edge tiles must be 0 (step singly) or 1 (blocked)");
+        if (value != b->edge_tiles) {
+          b->edge_tiles = (int)value;
+          b->layout_ok = false;  // every case's lists
+        }
+        return ok();
       default: return fail(BTDF_EINVAL, "unknown or read-only batch option %d", key);
     }
   });
@@ -637,6 +659,7 @@ int btdf_batch_get_option(const btdf_batch_t *b, int key, int64_t *value) {
       case BTDF_OPT_MASK_UNSTABLE: *value = b->mask; return ok();
       case BTDF_OPT_ROW_ALIGN: *value = b->row_align; return ok();
       case BTDF_OPT_TEMPORAL_BLOCKING: *value = b->tblock; return ok();
+      case BTDF_OPT_EDGE_TILES: *value = b->edge_tiles; return ok();
       case BTDF_OPT_TILE_X:
       case BTDF_OPT_TILE_Y: {
         int tx, ty;

@@ -34,6 +34,7 @@ __host__ __device__ __forceinline__ constexpr int opp(int q) {
 // values sum to rho - 1 and their first moment is m - u_ref: in a flow near
 // its reference state every stored value, and every rounding error, is small.
 __host__ __device__ __forceinline__ double ref_c(int q, double urx, double ury) {
+#pragma clang fp contract(off)  // (the same bits on the host and the device)
   const double eu = ex(q) * urx + ey(q) * ury;
   return wq(q) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * (urx * urx + ury * ury));
 }
@@ -183,6 +184,7 @@ struct LbmParams {
   int kind;
   long long *step_ctr;   // steps completed on the device
   int *flag;             // instability flag: 0 fine, 1 + body, -1 node
+  const void *konst;     // device copy of the per-direction constants (fill_konst)
   // collision constants and the uniform body force's Guo factors, per precision
   CollK<float> kf;
   CollK<double> kd;
@@ -316,6 +318,7 @@ struct BatchMap {
   const int *body_case, *body_local;  // per body-reduction workgroup
   const int *mblk_case, *mblk_first;  // per marker workgroup: case and its first marker
   int ntiles, nbodies, nmblk;
+  int ncases;  // lattice launches: one step-counter workgroup per case past the bodies
   int xcd_remap;
   int mask_unstable;  // skip the work of cases whose instability flag is set
 };
@@ -445,6 +448,87 @@ __device__ __forceinline__ unsigned long long bad_lanes(T rho) {
   return __builtin_amdgcn_ballot_w64(!rho_ok(rho));
 }
 
+// The inlet ghost column after a step: eq 6 at the inflow velocity and
+// column 1's density. As stored deviations, feq_q(1 + dr, u_in) - c_q =
+// w (dr a_q + b_q) with a_q = 1 + P(u_in), b_q = P(u_in) - P(u_ref), P(u) =
+// 3 e.u + 4.5 (e.u)^2 - 1.5 |u|^2, and dr the sum of column 1's
+// post-collision deviations (inlet_dr). The single-step kernels form a and b
+// in FP64 as they go (inlet_ghost_calc); the edge kernels of the blocked
+// pass read them, and the wall shifts of pull(), from a table the host
+// fills once (fill_konst, kernel parameter konst). Both take the same FP64
+// operations in the same order without contraction, so they agree bit for
+// bit.
+template <typename T>
+__device__ __forceinline__ T inlet_dr(const T (&out)[9]) {
+  T dr = out[0];
+#pragma unroll
+  for (int q = 1; q < 9; ++q) dr += out[q];
+  return dr;
+}
+
+__host__ __device__ __forceinline__ double inlet_a(const LbmParams &p, int q) {
+#pragma clang fp contract(off)
+  const double ein = ex(q) * p.uin_x + ey(q) * p.uin_y;
+  return 1.0 + (3.0 * ein + 4.5 * ein * ein - 1.5 * (p.uin_x * p.uin_x + p.uin_y * p.uin_y));
+}
+
+__host__ __device__ __forceinline__ double inlet_b(const LbmParams &p, int q) {
+#pragma clang fp contract(off)
+  const double ein = ex(q) * p.uin_x + ey(q) * p.uin_y;
+  const double pin = 3.0 * ein + 4.5 * ein * ein - 1.5 * (p.uin_x * p.uin_x + p.uin_y * p.uin_y);
+  return pin - (ref_c(q, p.urx, p.ury) / wq(q) - 1.0);
+}
+
+template <typename T>
+__device__ __forceinline__ T inlet_ghost_calc(T dr, const LbmParams &p, int q) {
+#pragma clang fp contract(off)
+  return (T)wq(q) * (dr * (T)inlet_a(p, q) + (T)inlet_b(p, q));
+}
+
+// the shift of a population pulled from beyond a halfway bounce-back wall
+// (the stored opposite population moved from its offset c_opp to c_q) and
+// from beyond a free-slip wall (the mirror population moved from c_mir)
+__host__ __device__ __forceinline__ double wall_bb(const LbmParams &p, int q) {
+#pragma clang fp contract(off)
+  return -6.0 * wq(q) * (ex(q) * p.urx + ey(q) * p.ury);
+}
+
+__host__ __device__ __forceinline__ double wall_slip(const LbmParams &p, int q) {
+#pragma clang fp contract(off)
+  return -6.0 * wq(q) * ey(q) * p.ury * (1.0 + 3.0 * ex(q) * p.urx);
+}
+
+// the table: per precision (FP32, then FP64) a[9], b[9], bounce-back[9], slip[9]
+constexpr int kKonstBytes = 36 * 4 + 36 * 8;
+
+inline void fill_konst(const LbmParams &p, unsigned char (&out)[kKonstBytes]) {
+  float f[36];
+  double d[36];
+  for (int q = 0; q < 9; ++q) {
+    d[q] = inlet_a(p, q);
+    d[9 + q] = inlet_b(p, q);
+    d[18 + q] = wall_bb(p, q);
+    d[27 + q] = wall_slip(p, q);
+  }
+  for (int k = 0; k < 36; ++k) f[k] = (float)d[k];
+  __builtin_memcpy(out, f, sizeof f);
+  __builtin_memcpy(out + sizeof f, d, sizeof d);
+}
+
+// the table's entries of precision T: k[q] = a, k[9 + q] = b, k[18 + q] =
+// bounce-back shift, k[27 + q] = slip shift
+template <typename T>
+__device__ __forceinline__ const T *konst(const LbmParams &p) {
+  return reinterpret_cast<const T *>(static_cast<const char *>(p.konst) + (sizeof(T) == 4 ? 0 : 36 * 4));
+}
+
+template <typename T>
+__device__ __forceinline__ T inlet_ghost(T dr, const LbmParams &p, int q) {
+#pragma clang fp contract(off)
+  const T *k = konst<T>(p);
+  return (T)wq(q) * (dr * ldg(k, q) + ldg(k, 9 + q));
+}
+
 // Streaming pull g_q(x, y) = f_q(x - e_q, y - e_q), as a stored deviation,
 // with the boundary readings: periodic directions wrap, halfway bounce-back
 // walls in y return the opposite population of the same node; channel ends
@@ -458,6 +542,9 @@ __device__ __forceinline__ T load(const T *ptr) {
 
 template <typename T, bool NTL = false>
 __device__ __forceinline__ T pull(const T *__restrict__ A, const LbmParams &p, int q, int x, int y) {
+  // the wall shifts are added as written (no fused multiply-add with the
+  // load), so every kernel that pulls a wall population rounds it alike
+#pragma clang fp contract(off)
   int sx = x - ex(q);
   int sy = y - ey(q);
   if (p.yper) {
@@ -467,12 +554,10 @@ __device__ __forceinline__ T pull(const T *__restrict__ A, const LbmParams &p, i
       // specular: the mirror population of the upstream column, moved from
       // its offset c_mir to c_q (feq difference of (e_x, -e_y) and e_q)
       if (p.xper) sx = sx < 0 ? sx + p.nx : (sx >= p.nx ? sx - p.nx : sx);
-      return load<T, NTL>(&A[(long long)mir_y(q) * p.plane + (long long)y * p.pitch + sx]) +
-             (T)(-6.0 * wq(q) * ey(q) * p.ury * (1.0 + 3.0 * ex(q) * p.urx));
+      return load<T, NTL>(&A[(long long)mir_y(q) * p.plane + (long long)y * p.pitch + sx]) + (T)wall_slip(p, q);
     }
     // the stored opposite population, moved from its offset c_opp to c_q
-    return load<T, NTL>(&A[(long long)opp(q) * p.plane + (long long)y * p.pitch + x]) +
-           (T)(-6.0 * wq(q) * (ex(q) * p.urx + ey(q) * p.ury));
+    return load<T, NTL>(&A[(long long)opp(q) * p.plane + (long long)y * p.pitch + x]) + (T)wall_bb(p, q);
   }
   if (p.xper) sx = sx < 0 ? sx + p.nx : (sx >= p.nx ? sx - p.nx : sx);
   return load<T, NTL>(&A[(long long)q * p.plane + (long long)sy * p.pitch + sx]);

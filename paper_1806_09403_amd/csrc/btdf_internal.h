@@ -87,16 +87,22 @@ struct btdf_sim {
   int64_t steps_to_rebin = 0;
   // temporal blocking: tiles taking two steps at once, then the singly stepped regions
   int tblock = 1;  // option: 0 off, 1 deepest available, 2 or 3 steps per pass
+  int edge_tiles = 0;  // option: tiles within reach of a domain edge take the blocked pass
   int depth = 1;   // steps per pass of the tiles away from the bodies (set with the layout)
   bool reserve_pass = false;  // keep the blocked pass's buffers whatever the launch shape (batch cases)
   // the tile map of the pass: its groups level by level (first tile of each
   // group), then the near tiles
   std::vector<int> fmap;
   std::vector<unsigned char> near;  // per lattice tile: 1 if it steps singly
-  int gkind[btdf::kLevels] = {btdf::kGroup4x1, btdf::kGroup2x1, btdf::kGroup1x1, btdf::kNoGroup};  // shape per level
-  int n_grp[btdf::kLevels] = {0, 0, 0, 0};  // groups per level (set with the lists)
+  int gkind[btdf::kLevels] = {};  // shape per level (set with the lists)
+  int n_grp[btdf::kLevels] = {};  // groups per level
+  int n_edge[btdf::kLevels] = {};  // of those, edge groups (first in the level's list)
   int n_near = 0;
-  int n_groups() const { return n_grp[0] + n_grp[1] + n_grp[2] + n_grp[3]; }
+  int n_groups() const {
+    int k = 0;
+    for (int i = 0; i < btdf::kLevels; ++i) k += n_grp[i];
+    return k;
+  }
   int grp_start(int g) const {  // index of level g's first group in fmap
     int k = 0;
     for (int i = 0; i < g; ++i) k += n_grp[i];

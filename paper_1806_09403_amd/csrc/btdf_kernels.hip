@@ -399,18 +399,10 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
     for (int q = 0; q < 9; ++q) store<T, NT>(&B[(long long)q * p.plane + base], out[q]);
     if (p.inlet && x == 1) {
       // inlet ghost: equilibrium at the inflow velocity, density of column 1
-      T dr = out[0];
-#pragma unroll
-      for (int q = 1; q < 9; ++q) dr += out[q];
-      // feq_q(1 + dr, u_in) - c_q = w (dr (1 + P_in) + P_in - P_ref), P(u) = 3 e.u + 4.5 (e.u)^2 - 1.5 |u|^2
+      const T dr = inlet_dr<T>(out);
       const long long gb = (long long)y * p.pitch;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        const double ein = ex(q) * p.uin_x + ey(q) * p.uin_y;
-        const double pin = 3.0 * ein + 4.5 * ein * ein - 1.5 * (p.uin_x * p.uin_x + p.uin_y * p.uin_y);
-        const double pref = ref_c(q, p.urx, p.ury) / wq(q) - 1.0;
-        B[(long long)q * p.plane + gb] = (T)wq(q) * (dr * (T)(1.0 + pin) + (T)(pin - pref));
-      }
+      for (int q = 0; q < 9; ++q) B[(long long)q * p.plane + gb] = inlet_ghost_calc<T>(dr, p, q);
     }
     if (p.outlet == 1 && x == p.nx - 2) {
 #pragma unroll
@@ -423,16 +415,20 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
 template <typename T, int BX, int BY, int NPT, bool NT, bool NTL>
 __global__ __launch_bounds__(BX *BY) void lbm_kernel(const T *__restrict__ A, T *__restrict__ B,
                                                      LbmParams p, TileRange r, IbParams ib) {
-  if ((int)blockIdx.x >= r.count) {  // workgroups past the tiles: one body each
+  if ((int)blockIdx.x >= r.count) {  // workgroups past the tiles: one body each, then the step counter
+    const int gb = (int)blockIdx.x - r.count;
+    if (gb >= ib.nb) {
+      if (threadIdx.x == 0 && threadIdx.y == 0) p.step_ctr[0] = p.step_ctr[0] + 1;
+      return;
+    }
     __shared__ double red[3][BX * BY / 64];
-    body_reduce<BX * BY>(ib, (int)blockIdx.x - r.count, (int)threadIdx.y * BX + (int)threadIdx.x, red);
+    body_reduce<BX * BY>(ib, gb, (int)threadIdx.y * BX + (int)threadIdx.x, red);
     return;
   }
   // this launch covers tiles map[base .. base+count) (all tiles in order if map is null)
   const int li = p.xcd_remap ? xcd_tile((int)blockIdx.x, r.count) : (int)blockIdx.x;
   const int t = r.map ? r.map[r.base + li] : li;
   lbm_tile<T, BX, BY, NPT, NT, NTL>(A, B, p, t);
-  if (r.count_step && li == 0 && threadIdx.x == 0 && threadIdx.y == 0) p.step_ctr[0] = p.step_ctr[0] + 1;
 }
 
 // ---- batched cases: every tile, marker and body of all cases in one launch each
@@ -441,8 +437,16 @@ __global__ __launch_bounds__(BX *BY) void lbm_kernel(const T *__restrict__ A, T 
 template <typename T, int BX, int BY, int NPT, bool NT, bool NTL>
 __global__ __launch_bounds__(BX *BY) void lbm_batch_kernel(const CaseDesc *__restrict__ cases, BatchMap m,
                                                            int rt) {
-  if ((int)blockIdx.x >= m.ntiles) {  // one body each
+  if ((int)blockIdx.x >= m.ntiles) {  // one body each, then one step counter per case
     const int gb = (int)blockIdx.x - m.ntiles;
+    if (gb >= m.nbodies) {
+      if (threadIdx.x == 0 && threadIdx.y == 0) {
+        const LbmParams &p = cases[gb - m.nbodies].p;
+        // an unstable case counts no step
+        if (!stop_flag<true>(m.mask_unstable ? p.flag : &kNoStop)) p.step_ctr[0] = p.step_ctr[0] + 1;
+      }
+      return;
+    }
     const CaseDesc &cd = cases[m.body_case[gb]];
     __shared__ double red[3][BX * BY / 64];
     body_reduce<BX * BY>(cd.ib, m.body_local[gb], (int)threadIdx.y * BX + (int)threadIdx.x, red);
@@ -459,7 +463,6 @@ __global__ __launch_bounds__(BX *BY) void lbm_batch_kernel(const CaseDesc *__res
   // an unstable case stops (stores nothing, counts no step); the others go on
   const int *stop = m.mask_unstable ? p.flag : &kNoStop;
   lbm_tile<T, BX, BY, NPT, NT, NTL, true>(A, B, p, t, stop);
-  if (t == 0 && threadIdx.x == 0 && threadIdx.y == 0 && !stop_flag<true>(stop)) p.step_ctr[0] = p.step_ctr[0] + 1;
 }
 
 template <typename T>
@@ -574,9 +577,11 @@ static int grid_for(const LbmParams &p) {
 template <typename T, int BX, int BY, int NPT, bool NT, bool NTL>
 static hipError_t launch_lbm_t(const T *A, T *B, const LbmParams &p, const TileRange &r, const IbParams &ib,
                                hipStream_t s) {
-  const int bodies = r.count_step ? ib.nb : 0;  // the counting launch also reduces the bodies
-  if (r.count + bodies <= 0) return hipSuccess;
-  hipLaunchKernelGGL((lbm_kernel<T, BX, BY, NPT, NT, NTL>), dim3(r.count + bodies), dim3(BX, BY), 0, s, A, B, p,
+  // the counting launch also reduces the bodies and advances the step
+  // counter (one workgroup each past the tiles), whether or not it has tiles
+  const int extra = r.count_step ? ib.nb + 1 : 0;
+  if (r.count + extra <= 0) return hipSuccess;
+  hipLaunchKernelGGL((lbm_kernel<T, BX, BY, NPT, NT, NTL>), dim3(r.count + extra), dim3(BX, BY), 0, s, A, B, p,
                      r, ib);
   return hipGetLastError();
 }
@@ -1167,8 +1172,8 @@ template <typename T>
 static hipError_t launch_lbm_batch_any(int v, const CaseDesc *cases, const BatchMap &m, int rt, hipStream_t s) {
 #define X(id, bx, by, npt, nt, ntl)                                                                          \
   if (v == id) {                                                                                           \
-    hipLaunchKernelGGL((lbm_batch_kernel<T, bx, by, npt, nt, ntl>), dim3(m.ntiles + m.nbodies), dim3(bx, by), \
-                       0, s, cases, m, rt);                                                                \
+    hipLaunchKernelGGL((lbm_batch_kernel<T, bx, by, npt, nt, ntl>), dim3(m.ntiles + m.nbodies + m.ncases),  \
+                       dim3(bx, by), 0, s, cases, m, rt);                                                  \
     return hipGetLastError();                                                                              \
   }
   BTDF_VARIANTS(X)
@@ -1177,7 +1182,7 @@ static hipError_t launch_lbm_batch_any(int v, const CaseDesc *cases, const Batch
 }
 
 hipError_t launch_lbm_batch(int prec, int v, const CaseDesc *cases, const BatchMap &m, int rt, hipStream_t s) {
-  if (m.ntiles + m.nbodies <= 0) return hipSuccess;
+  if (m.ntiles + m.nbodies + m.ncases <= 0) return hipSuccess;
   if (prec == 4) return launch_lbm_batch_any<float>(v, cases, m, rt, s);
   return launch_lbm_batch_any<double>(v, cases, m, rt, s);
 }

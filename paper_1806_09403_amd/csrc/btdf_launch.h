@@ -20,10 +20,19 @@ bool variant_has_wide_lbm2(int variant, int prec, int width);
 // group shapes of the three-step pass, W | H << 4 for W x H lattice tiles
 // (map entries name a group's lower-left tile)
 constexpr int kGroup1x1 = 0x11, kGroup2x1 = 0x12, kGroup4x1 = 0x14;
+constexpr int kGroup1x4 = 0x41;  // (edge groups only: the ends of a channel)
 constexpr int kNoGroup = 0;  // an unused level
-constexpr int group_tiles(int code) { return (code & 15) * (code >> 4); }
+// groups of tiles within reach of a domain edge, with the boundary readings
+// in every step of the pass (btdf_edge.hip): the flag kEdge on a shape
+constexpr int kEdge = 0x100;
+constexpr int kEdge4x1 = kEdge | kGroup4x1, kEdge2x1 = kEdge | kGroup2x1, kEdge1x1 = kEdge | kGroup1x1;
+constexpr int group_tiles(int code) { return (code & 15) * ((code >> 4) & 15); }
+constexpr bool is_edge(int code) { return (code & kEdge) != 0; }
+// a pass map entry names an edge group when this bit is set (tile ids are below it)
+constexpr int kEdgeFlag = 1 << 30;
 // A pass launches its groups level by level: up to kLevels shapes, the
-// largest first in the tile map, single tiles last.
+// largest first in the tile map. A level's edge groups (map entries with
+// kEdgeFlag, btdf_edge.h) come first in its list.
 constexpr int kLevels = 4;
 // three steps A -> C over the listed groups of the given shape; with near
 // non-null, edge nodes next to a near tile also store their first and second
@@ -35,6 +44,21 @@ bool variant_has_lbm3(int variant, int prec, int code);
 hipError_t launch_lbm3_batch(int prec, int variant, int code, const CaseDesc *cases, const int *gcase,
                              const int *gtile, int count, int rt, int mask, int xcd, hipStream_t s);
 bool variant_has_lbm2(int variant, int prec);
+// Whether a pass of depth 2 or 3 takes edge groups of the given shape
+// (kEdge and a row of 1, 2 or 4 tiles, or a column of 4)
+bool variant_has_edge(int variant, int prec, int depth, int code);
+// three steps A -> C over the listed edge groups (entries may carry kEdgeFlag);
+// with near non-null, edge nodes next to a near tile also store their first
+// and second steps in X1 and X2. Batches: gcase/gtile as for launch_lbm3_batch.
+hipError_t launch_lbm_edge3(int prec, int variant, int code, const void *A, void *C, const LbmParams &p,
+                            const int *map, int count, void *X1, void *X2, const unsigned char *near, hipStream_t s);
+hipError_t launch_lbm_edge3_batch(int prec, int variant, int code, const CaseDesc *cases, const int *gcase,
+                                  const int *gtile, int count, int rt, int mask, int xcd, hipStream_t s);
+// two steps A -> C over the listed edge groups (entries may carry kEdgeFlag);
+// with near non-null, edge nodes next to a near tile also store their first
+// step in X
+hipError_t launch_lbm_edge2(int prec, int variant, int code, const void *A, void *C, const LbmParams &p,
+                            const int *map, int count, void *X, const unsigned char *near, hipStream_t s);
 hipError_t launch_conv_outlet(int prec, const void *A, void *B, const LbmParams &p, hipStream_t s);
 hipError_t launch_conv_outlet_batch(int prec, const CaseDesc *cases, int ncases, int mask_unstable, int rt,
                                     hipStream_t s);

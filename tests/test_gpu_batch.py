@@ -230,19 +230,23 @@ def test_c4_cases_batched_equal_single():
         r.close()
 
 
+@pytest.mark.parametrize("edge", [1, 0])
 @pytest.mark.parametrize("precision", [4, 8])
-def test_batch_blocking_equals_single_steps(precision):
+def test_batch_blocking_equals_single_steps(precision, edge):
     """Three steps per pass in a batch (every case's near tiles stepped singly
-    in one launch per step, every case's other tiles in the batched pass)
-    give the bits of the unblocked batch, after every call: step counts that
-    leave 0, 1 or 2 steps over, and cases with and without far tiles."""
+    in one launch per step, every case's other tiles in the batched pass;
+    edge = 1, the default, also the tiles within reach of each case's
+    edges) give the bits of the unblocked batch, after every call: step
+    counts that leave 0, 1 or 2 steps over, and cases with and without far
+    tiles."""
     from paper_1806_09403_amd import BatchSim
-    from paper_1806_09403_amd._lib import OPT_STEPS_PER_PASS, OPT_TEMPORAL_BLOCKING
+    from paper_1806_09403_amd._lib import OPT_EDGE_TILES, OPT_STEPS_PER_PASS, OPT_TEMPORAL_BLOCKING
     cases = mixed_cases() + [W.random_case(25, nx=300, ny=160, kind=W.COS4, bc=W.CHANNEL, n_bodies=2),
                              W.random_case(26, nx=260, ny=150, kind=W.ROMA3, bc=W.FAR_FIELD, n_bodies=1)]
-    log("batch blocking prec=%d" % precision)
+    log("batch blocking prec=%d edge=%d" % (precision, edge))
     a = BatchSim(cases, precision=precision, options={OPT_TEMPORAL_BLOCKING: 0})
-    b = BatchSim(cases, precision=precision)
+    b = BatchSim(cases, precision=precision, options={OPT_EDGE_TILES: edge})
+    assert b.get_option(OPT_EDGE_TILES) == edge
     assert a.get_option(OPT_STEPS_PER_PASS) == 1 and b.get_option(OPT_STEPS_PER_PASS) == 3
     for n in (1, 2, 7, 20, 3):
         a.step(n)

@@ -1,7 +1,8 @@
 """Temporal blocking (two or three steps per pass for tiles away from the
-markers and the domain edges) gives bit-identical results to single steps,
-for every boundary set, forcing method, precision and launch shape that has
-the blocked pass."""
+markers; tiles at the domain edges with the boundary readings in every
+step) gives bit-identical results to single steps, for every boundary set,
+ragged edge, forcing method, precision and launch shape that has the
+blocked pass."""
 import dataclasses
 
 import numpy as np
@@ -47,19 +48,31 @@ CASES = [
     ("channel", 42, 400, 200, W.CHANNEL),
     ("walls", 43, 300, 160, (W.PERIODIC, W.PERIODIC, W.BOUNCEBACK_WALL, W.BOUNCEBACK_WALL)),
     ("far-field", 44, 420, 180, W.FAR_FIELD),
+    # the outlet's ghost column alone in the last tile column, ragged rows
+    ("channel-ragged", 45, 417, 203, W.CHANNEL),
+    ("walls-ragged", 46, 300, 165, (W.PERIODIC, W.PERIODIC, W.BOUNCEBACK_WALL, W.BOUNCEBACK_WALL)),
 ]
 
 
+@pytest.mark.parametrize("edge", [0, 1])
 @pytest.mark.parametrize("depth", [2, 3])
 @pytest.mark.parametrize("precision", [4, 8])
 @pytest.mark.parametrize("name,seed,nx,ny,bc", CASES)
-def test_blocked_steps_are_bit_identical(name, seed, nx, ny, bc, precision, depth):
-    log("blocking %s prec=%d depth=%d" % (name, precision, depth))
+def test_blocked_steps_are_bit_identical(name, seed, nx, ny, bc, precision, depth, edge):
+    """edge = 1: the tiles within reach of the domain edges take the pass too
+    (every case here has some: periodic seams, walls, inlet and outlet)."""
+    from paper_1806_09403_amd import Sim, _lib
+    log("blocking %s prec=%d depth=%d edge=%d" % (name, precision, depth, edge))
     c = bodies_case(seed, nx, ny, bc)
     steps = (1, 2, 7, 20)   # leftovers of every size after whole passes
     ref = run(c, 0, steps, precision)
-    got = run(c, depth, steps, precision)
+    got = run(c, depth, steps, precision, options={_lib.OPT_EDGE_TILES: edge})
     assert got[2] > 0 and ref[2] == 0
+    s = Sim.from_case(c, precision=precision)
+    s.set_option(_lib.OPT_TEMPORAL_BLOCKING, depth)
+    s.set_option(_lib.OPT_EDGE_TILES, edge)
+    assert (s.get_option(_lib.OPT_EDGE_FUSED_TILES) > 0) == bool(edge)
+    s.close()
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
@@ -79,6 +92,8 @@ def test_blocking_with_other_features(opts, depth):
 
 @pytest.mark.parametrize("depth,min_active", [(2, 10), (3, 6)])
 def test_every_launch_shape_with_the_blocked_pass(depth, min_active):
+    """Every launch shape, the edge tiles in the pass wherever the shape
+    has it for them."""
     from paper_1806_09403_amd import Sim, _lib
     c = bodies_case(46, 520, 260, W.FULLY_PERIODIC)
     ref = run(c, 0, (9,))
@@ -87,7 +102,7 @@ def test_every_launch_shape_with_the_blocked_pass(depth, min_active):
     s.close()
     active = 0
     for v in range(nv):
-        got = run(c, depth, (9,), options={_lib.OPT_LBM_VARIANT: v})
+        got = run(c, depth, (9,), options={_lib.OPT_LBM_VARIANT: v, _lib.OPT_EDGE_TILES: 1})
         active += got[2] > 0
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), v
     log("  %d launch shapes with a pass of depth %d or less" % (active, depth))
@@ -131,21 +146,22 @@ def test_moving_bodies_step_singly_under_blocking():
     assert np.array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("depth,chunk", [(3, 7), (3, 9), (3, 12), (2, 6), (2, 8)])
-def test_blocked_passes_in_graphs(depth, chunk):
+@pytest.mark.parametrize("depth,chunk,edge", [(3, 7, 0), (3, 9, 1), (3, 12, 0), (2, 6, 1), (2, 8, 0)])
+def test_blocked_passes_in_graphs(depth, chunk, edge):
     """Graphs of chunk // depth whole passes (an even or an odd number of
     passes, so graphs are entered from either buffer, with single steps
     before and after) give the bits of eager single steps, checked after
     every call: each call replays the graph one or more times, with the
     program's own synchronising reads between the calls."""
     from paper_1806_09403_amd import Sim, _lib
-    log("blocked graphs depth=%d chunk=%d" % (depth, chunk))
+    log("blocked graphs depth=%d chunk=%d edge=%d" % (depth, chunk, edge))
     c = bodies_case(49, 384, 192, W.CHANNEL)
     ref = Sim.from_case(c, precision=4)
     ref.set_option(_lib.OPT_TEMPORAL_BLOCKING, 0)
     got = Sim.from_case(c, precision=4)
     got.set_option(_lib.OPT_GRAPH_CHUNK, chunk)
     got.set_option(_lib.OPT_TEMPORAL_BLOCKING, depth)
+    got.set_option(_lib.OPT_EDGE_TILES, edge)
     assert got.get_option(_lib.OPT_STEPS_PER_PASS) == depth
     for n in (1, 25, 2, 30, 19):
         ref.step(n)
