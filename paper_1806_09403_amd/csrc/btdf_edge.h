@@ -177,6 +177,27 @@ __device__ __forceinline__ void lbm3_edge_group(const T *__restrict__ A, T *__re
   const CollK<T> &K = coll<T>(p);
   const ForceK<T> &F = gforce<T>(p);
   bool bad = false;
+  // The near flags of the tiles around the group (wrapped where periodic),
+  // loaded by wave 0 ahead of its first-step loads: most edge groups have no
+  // near neighbour, and then skip the ring test of their boundary nodes.
+  __shared__ int s_any;
+  int nflag = 0;
+  if (near && tid < 64) {  // wave 0 (uniform)
+    const int gw = OX / tile_x, gh = OY / tile_y, nc = gw + 2;
+    if (tid < nc * (gh + 2)) {
+      int c = txi - 1 + tid % nc, r = tyi - 1 + tid / nc;
+      bool ok = !(r >= tyi && r < tyi + gh && c >= txi && c < txi + gw);  // (the group's own tiles)
+      if (p.xper)
+        c = wrap1(c, p.ntx);
+      else
+        ok = ok && c >= 0 && c < p.ntx;
+      if (p.yper)
+        r = wrap1(r, p.nty);
+      else
+        ok = ok && r >= 0 && r < p.nty;
+      if (ok) nflag = near[r * p.ntx + c];
+    }
+  }
   // one node's step n+1 from its pulled populations, into its slot; column 1
   // (nx-2) also writes the inlet (outlet) ghost slot beside it
   auto first = [&](const EdgeNode &n, T (&g)[9], int k) {
@@ -208,6 +229,10 @@ __device__ __forceinline__ void lbm3_edge_group(const T *__restrict__ A, T *__re
     if (na.kind == 2) first(na, ga, k);
     if (nb.kind == 2) first(nb, gb, kb);
   }
+  if (tid < 64) {
+    const unsigned long long any = __builtin_amdgcn_ballot_w64(nflag != 0);
+    if (tid == 0) s_any = any != 0;
+  }
   __syncthreads();
   // this thread's node of the group; the ring directions of the group's
   // edge nodes, and their states n+1
@@ -217,7 +242,7 @@ __device__ __forceinline__ void lbm3_edge_group(const T *__restrict__ A, T *__re
   const int kown = (jj + 2) * RX + ii + 2;
   const long long node = (long long)y * p.pitch + x;
   unsigned rmask = 0;
-  if (near && keep && mine && (ii == 0 || ii == OX - 1 || jj == 0 || jj == OY - 1 || x == p.nx - 1 || y == p.ny - 1))
+  if (s_any && keep && mine && (ii == 0 || ii == OX - 1 || jj == 0 || jj == OY - 1 || x == p.nx - 1 || y == p.ny - 1))
     rmask = edge_ring(p, near, __builtin_ctz((unsigned)tile_x), __builtin_ctz((unsigned)tile_y), x, y);
   if (rmask) {
 #pragma unroll
