@@ -120,9 +120,8 @@ def bench_other_delta(args, kind_name):
                "value": round(case.nodes * args.steps / wall / 1e6, 2), "unit": "MLUPS",
                "ms_per_step_repeats": [round(w * 1e3 / args.steps, 5) for w in walls]}
         if fused > 0:
-            tile = sim.get_option(_lib.OPT_TILE_X) * sim.get_option(_lib.OPT_TILE_Y)
             launch_ms = depth * passes[med]
-            ach = fused * tile * 9 * 2 * 4 / (launch_ms * 1e-3) / 1e9
+            ach = sim.get_option(_lib.OPT_FUSED_NODES) * 9 * 2 * 4 / (launch_ms * 1e-3) / 1e9
             out["lbm%d_kernel" % depth] = {"launch_ms": round(launch_ms, 5), "achieved": round(ach, 1),
                                            "frac": round(ach / HBM_PEAK_GBS, 4)}
         return out
@@ -251,8 +250,7 @@ def bench_batched(args):
     ms_ib, ms_lbm = b.step_timed(201)
     b_align = b.get_option(_lib.OPT_ROW_ALIGN)
     depth = b.get_option(_lib.OPT_STEPS_PER_PASS)
-    blocked_nodes = (b.get_option(_lib.OPT_FUSED_TILES) * b.get_option(_lib.OPT_TILE_X) *
-                     b.get_option(_lib.OPT_TILE_Y))
+    blocked_nodes = b.get_option(_lib.OPT_FUSED_NODES)
     b.close()
     del b
     traffic = None
@@ -517,8 +515,7 @@ def main():
     variant = sim.get_option(_lib.OPT_LBM_VARIANT)
     if fused_tiles > 0:
         # dominant kernel: the blocked pass, depth updates per node per launch of node_bytes
-        tile_nodes = sim.get_option(_lib.OPT_TILE_X) * sim.get_option(_lib.OPT_TILE_Y)
-        launch_nodes = fused_tiles * tile_nodes
+        launch_nodes = sim.get_option(_lib.OPT_FUSED_NODES)
         launch_ms = depth * ms_pass
         kernel, bytes_per_update = "lbm%d_kernel" % depth, node_bytes / depth
         key = "%s-%s-v%d-p%d" % (args.workload, args.delta, variant, depth)

@@ -141,6 +141,8 @@ extern "C" {
                                          launches gather the edge tiles of every case). Results are bit-identical
                                          either way. */
 #define BTDF_OPT_EDGE_FUSED_TILES 21  /* read-only: of BTDF_OPT_FUSED_TILES, the tiles within reach of a domain edge */
+#define BTDF_OPT_FUSED_NODES 22       /* read-only: grid nodes in the blocked pass (tiles reaching past the grid
+                                         counted by their nodes inside it); batches: over every case */
 #define BTDF_OPT_FUSED_TILES 17       /* read-only: lattice tiles that take the blocked pass (0 when it is not active) */
 #define BTDF_OPT_STEPS_PER_PASS 18    /* read-only: steps per pass of those tiles (1 when blocking is not active) */
 #define BTDF_OPT_FORCING_PASSES 14 /* NF in 1..64 (default 1): direct-forcing passes per step (Sec. 2.3, eqs 29-31);

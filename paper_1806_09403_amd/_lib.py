@@ -28,7 +28,7 @@ OPT_ROW_ALIGN = 13
 OPT_FORCING_PASSES = 14
 OPT_FORCING_METHOD = 15
 OPT_TEMPORAL_BLOCKING, OPT_FUSED_TILES, OPT_STEPS_PER_PASS = 16, 17, 18
-OPT_EDGE_TILES, OPT_EDGE_FUSED_TILES = 20, 21
+OPT_EDGE_TILES, OPT_EDGE_FUSED_TILES, OPT_FUSED_NODES = 20, 21, 22
 NOALLOC_MAX_MARKERS = 262144
 FORCING_DIRECT, FORCING_IMPLICIT, FORCING_RKPM = 0, 1, 2
 

@@ -214,6 +214,7 @@ void group_kinds(int variant, int prec, int d, int kind[kLevels]) {
 void fused_lists(btdf_t *h) {
   h->fmap.clear();
   for (int g = 0; g < kLevels; ++g) h->n_grp[g] = h->n_edge[g] = 0;
+  h->pass_nodes = 0;
   h->n_near = 0;
   h->near.clear();
   const int d = h->depth;
@@ -295,6 +296,11 @@ void fused_lists(btdf_t *h) {
     }
     h->n_grp[g] = (int)(h->fmap.size() - start);
   }
+  for (int t = 0; t < ntiles; ++t)
+    if (!near[t]) {
+      const int x0 = (t % ntx) * tx, y0 = (t / ntx) * ty;
+      h->pass_nodes += (long long)std::min(tx, h->nx - x0) * std::min(ty, h->ny - y0);
+    }
   const size_t start_near = h->fmap.size();
   for (int t = 0; t < ntiles; ++t)
     if (near[t]) h->fmap.push_back(t);
@@ -1905,6 +1911,10 @@ int btdf_get_option(const btdf_t *h, int key, int64_t *value) {
       case BTDF_OPT_FORCING_METHOD: *value = h->method; return ok();
       case BTDF_OPT_TEMPORAL_BLOCKING: *value = h->tblock; return ok();
       case BTDF_OPT_EDGE_TILES: *value = h->edge_tiles; return ok();
+      case BTDF_OPT_FUSED_NODES:
+        if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
+        *value = blocking_active(h) ? h->pass_nodes : 0;
+        return ok();
       case BTDF_OPT_EDGE_FUSED_TILES: {
         if (!h->layout_ok) compute_layout(const_cast<btdf_t *>(h));
         int k = 0;

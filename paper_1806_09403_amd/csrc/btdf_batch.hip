@@ -660,6 +660,12 @@ int btdf_batch_get_option(const btdf_batch_t *b, int key, int64_t *value) {
       case BTDF_OPT_ROW_ALIGN: *value = b->row_align; return ok();
       case BTDF_OPT_TEMPORAL_BLOCKING: *value = b->tblock; return ok();
       case BTDF_OPT_EDGE_TILES: *value = b->edge_tiles; return ok();
+      case BTDF_OPT_FUSED_NODES:  // grid nodes of all cases in the blocked pass
+        if (!b->layout_ok) batch_layout(const_cast<btdf_batch_t *>(b));
+        *value = 0;
+        if (b->blocked)
+          for (const btdf_t *h : b->cases) *value += h->pass_nodes;
+        return ok();
       case BTDF_OPT_TILE_X:
       case BTDF_OPT_TILE_Y: {
         int tx, ty;

@@ -97,6 +97,7 @@ struct btdf_sim {
   int gkind[btdf::kLevels] = {};  // shape per level (set with the lists)
   int n_grp[btdf::kLevels] = {};  // groups per level
   int n_edge[btdf::kLevels] = {};  // of those, edge groups (first in the level's list)
+  long long pass_nodes = 0;        // grid nodes in the blocked pass (partial tiles counted by their nodes)
   int n_near = 0;
   int n_groups() const {
     int k = 0;
