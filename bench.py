@@ -95,6 +95,11 @@ def timed_blocks(sim, steps, repeats, fused_tiles):
     return walls, passes, splits
 
 
+def pass_kernel(depth):
+    """Name of the blocked pass's kernel for a pass of depth steps."""
+    return "lbm%d_kernel" % depth if depth <= 3 else "lbmd_kernel"
+
+
 def bench_other_delta(args, kind_name):
     """The particle-laden lattice with the other delta of the pair the
     workload names (3-point with thickening 1.9, 4-point cosine with 2.6):
@@ -122,7 +127,7 @@ def bench_other_delta(args, kind_name):
         if fused > 0:
             launch_ms = depth * passes[med]
             ach = sim.get_option(_lib.OPT_FUSED_NODES) * 9 * 2 * 4 / (launch_ms * 1e-3) / 1e9
-            out["lbm%d_kernel" % depth] = {"launch_ms": round(launch_ms, 5), "achieved": round(ach, 1),
+            out[pass_kernel(depth)] = {"launch_ms": round(launch_ms, 5), "achieved": round(ach, 1),
                                            "frac": round(ach / HBM_PEAK_GBS, 4)}
         return out
     finally:
@@ -517,7 +522,7 @@ def main():
         # dominant kernel: the blocked pass, depth updates per node per launch of node_bytes
         launch_nodes = sim.get_option(_lib.OPT_FUSED_NODES)
         launch_ms = depth * ms_pass
-        kernel, bytes_per_update = "lbm%d_kernel" % depth, node_bytes / depth
+        kernel, bytes_per_update = pass_kernel(depth), node_bytes / depth
         key = "%s-%s-v%d-p%d" % (args.workload, args.delta, variant, depth)
     else:
         launch_nodes, launch_ms = n, ms_single

@@ -116,23 +116,25 @@ extern "C" {
                                       stand-alone handles only, NF = 1, bodies of at most 2048 markers; the
                                       matrices are formed on the host when the bodies or the method change */
 #define BTDF_OPT_TEMPORAL_BLOCKING 16 /* d steps per pass for the tiles at least d-1 nodes clear of every marker
-                                         stencil and (see BTDF_OPT_EDGE_TILES) d nodes clear of the domain edges
-                                         (each node read and written once for d updates); the others step singly
-                                         with the marker
-                                         kernel between, and the pass gives them the intermediate states of the
+                                         stencil and d nodes clear of the domain edges (at d = 2 or 3 with
+                                         BTDF_OPT_EDGE_TILES, the edge tiles too): each node read and written
+                                         once for d updates. The others step singly with the marker kernel
+                                         between, and the pass gives them the intermediate states of the
                                          nodes just outside. Results are bit-identical to single steps.
-                                         1 (default): the deepest the launch shape has (3, or 2 when the shape
-                                         has no three-step pass, as for tiles one or two rows tall) on
-                                         lattices of at least 2^20 nodes (smaller ones step
-                                         singly: the extra launches of a pass outweigh the bytes saved); 2 or 3:
-                                         that depth where the shape has it, else the next lower; 0: off. In a
-                                         batch (btdf_batch_set_option) any nonzero value means three steps per
-                                         pass for every case, default on. Takes d-1 more population buffers. With a graph chunk
-                                         k > 0 a graph holds k / d whole passes. Steps run singly instead with
-                                         moving bodies or with a launch shape of more than one node per thread.
-                                         Steps left over after whole passes: on a stand-alone handle two after
-                                         three-step passes take one two-step pass over the same tiles,
-                                         otherwise (and in batches) they step singly. */
+                                         1 (default): four steps per pass on lattices of at least 2^20 nodes
+                                         where the launch shape has them (32x8 lattice tiles), else the
+                                         deepest below (3, or 2 for tiles one or two rows tall); smaller
+                                         lattices step singly (the extra launches of a pass outweigh the
+                                         bytes saved). 2 to 5: that depth where the shape has it, else the
+                                         next lower; 0: off. In a batch (btdf_batch_set_option) any nonzero
+                                         value means three steps per pass for every case, default on. Takes
+                                         d-1 more population buffers. With a graph chunk k > 0 a graph holds
+                                         k / d whole passes. Steps run singly instead with moving bodies or
+                                         with a launch shape of more than one node per thread. Steps left
+                                         over after whole passes, on a stand-alone handle: three after
+                                         deeper passes take one three-step pass, two after passes of three
+                                         or more one two-step pass, over the same tiles; otherwise (and in
+                                         batches) they step singly. */
 #define BTDF_OPT_EDGE_TILES 20        /* 1: tiles within reach of a domain edge (periodic seams, walls, the inlet and a
                                          zero-gradient outlet; not a convective outlet) also take the blocked pass,
                                          with the boundary readings in every step, in launches of their own; 0: they

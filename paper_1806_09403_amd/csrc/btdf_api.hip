@@ -165,14 +165,18 @@ void cover_lists(const btdf_t *h, std::vector<int> &off, std::vector<int> &list)
 }
 
 // steps per pass of the tiles away from the bodies for the options and the
-// launch shape: 3 where the shape has the three-step pass, else 2 where it
-// has the two-step pass, else 1 (no blocking)
+// launch shape: the depth asked for (by default kDefaultDepth on a single
+// lattice, 3 in a batch), or the deepest below it that the shape has
+// (4 and 5 on single lattices only), else 1 (no blocking)
 int pass_depth(const btdf_t *h) {
   if (!h->tblock) return 1;
   // by default only lattices large enough that the saved bytes outweigh the
   // extra launches of a blocked pass (single handles; a batch shares them)
   if (h->tblock == 1 && !h->owner && (long long)h->nx * h->ny < kBlockMinNodes) return 1;
-  const int want = h->tblock == 1 ? 3 : h->tblock;
+  int want = h->tblock == 1 ? (h->owner ? 3 : kDefaultDepth) : h->tblock;
+  if (h->owner) want = std::min(want, 3);
+  for (int d = want; d >= 4; --d)
+    if (variant_has_deep(h->variant, h->prec, d, kGroup1x1)) return d;
   if (want >= 3 && variant_has_lbm3(h->variant, h->prec, kGroup1x1)) return 3;
   if (variant_has_lbm2(h->variant, h->prec)) return 2;
   return 1;
@@ -182,6 +186,7 @@ int pass_depth(const btdf_t *h) {
 // (two-step pass: one row of 1, 2 or 4 tiles)
 static bool has_group(const btdf_t *h, int d, int code) {
   if (is_edge(code)) return variant_has_edge(h->variant, h->prec, d, code);
+  if (d >= 4) return variant_has_deep(h->variant, h->prec, d, code);
   if (d == 3) return variant_has_lbm3(h->variant, h->prec, code);
   const int w = code & 15;
   if (((code >> 4) & 15) != 1) return false;
@@ -213,10 +218,11 @@ void group_kinds(int variant, int prec, int d, int kind[kLevels]) {
 // nx-2 fall in different tiles: those tiles are near too.
 void fused_lists(btdf_t *h) {
   h->fmap.clear();
-  for (int g = 0; g < kLevels; ++g) h->n_grp[g] = h->n_edge[g] = 0;
+  for (int g = 0; g < kLevels; ++g) h->n_grp[g] = h->n_edge[g] = h->n_ring[g] = 0;
   h->pass_nodes = 0;
   h->n_near = 0;
   h->near.clear();
+  h->rwin.clear();
   const int d = h->depth;
   if (d < 2) return;
   const int tx = h->tile_x, ty = h->tile_y, ntx = h->ntx, nty = h->nty, ntiles = ntx * nty;
@@ -295,7 +301,31 @@ void fused_lists(btdf_t *h) {
       if (kind) h->n_edge[g] = (int)(h->fmap.size() - start);
     }
     h->n_grp[g] = (int)(h->fmap.size() - start);
+    if (d >= 4) {
+      // the groups with a near tile among the tiles around them first (they
+      // write the ring), the others after them, each in packing order
+      auto ring = [&](int t) {
+        const int a = t % ntx, b = t / ntx;
+        for (int r = b - 1; r <= b + gh; ++r)
+          for (int c = a - 1; c <= a + w; ++c)
+            if (r >= 0 && r < nty && c >= 0 && c < ntx && near[r * ntx + c]) return true;
+        return false;
+      };
+      const auto mid = std::stable_partition(h->fmap.begin() + start, h->fmap.end(), ring);
+      h->n_ring[g] = (int)(mid - (h->fmap.begin() + start));
+      // each ring group's window of near flags (bit 8 r + c, r from the row
+      // below, c from the column left of the group)
+      h->rwin.resize(h->fmap.size(), 0u);
+      for (size_t k = start; k < start + (size_t)h->n_ring[g]; ++k) {
+        const int t = h->fmap[k], a = t % ntx, b = t / ntx;
+        unsigned m = 0;
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < w + 2; ++c) m |= near[(b - 1 + r) * ntx + a - 1 + c] ? 1u << (8 * r + c) : 0u;
+        h->rwin[k] = m;
+      }
+    }
   }
+  h->rwin.resize(h->fmap.size(), 0u);
   for (int t = 0; t < ntiles; ++t)
     if (!near[t]) {
       const int x0 = (t % ntx) * tx, y0 = (t / ntx) * ty;
@@ -467,12 +497,20 @@ void compute_layout(btdf_t *h) {
   fused_lists(h);
   h->off_fmap = o;
   o = align256(o + 2 * (size_t)max_tiles * sizeof(int));
+  h->off_rwin = o;  // per map entry
+  o = align256(o + 2 * (size_t)max_tiles * sizeof(unsigned));
   h->off_near = o;  // one flag per tile
   o = align256(o + (size_t)max_tiles);
-  h->off_pop3 = o;  // the near tiles' intermediate states n+1 (and n+2 for three steps)
+  h->off_pop3 = o;  // the near tiles' intermediate states n+1 .. n+depth-1
   o = align256(o + (h->depth >= 2 || h->reserve_pass ? pop_bytes : 0));
   h->off_pop4 = o;
   o = align256(o + (h->depth >= 3 || h->reserve_pass ? pop_bytes : 0));
+  h->off_pop5 = o;
+  o = align256(o + (h->depth >= 4 ? pop_bytes : 0));
+  h->off_pop6 = o;
+  o = align256(o + (h->depth >= 5 ? pop_bytes : 0));
+  // (pop_bytes is a multiple of 256, so X1 .. X4 are consecutive buffers,
+  // which the passes of four and five steps address from X1)
   // rigid motion: [nb][4] theta vx vy omega, then [nb] moving flags; [nm][2] offsets
   h->off_motion = o;
   o = align256(o + 4 * (size_t)std::max(nb, 1) * sizeof(double) + (size_t)std::max(nb, 1) * sizeof(int));
@@ -617,6 +655,7 @@ int upload_bodies(btdf_t *h) {
     }
   }
   put(h->off_fmap, h->fmap.data(), h->fmap.size() * sizeof(int));
+  put(h->off_rwin, h->rwin.data(), h->rwin.size() * sizeof(unsigned));
   put(h->off_near, h->near.data(), h->near.size());
   put(h->off_moff, h->minv_off.data(), h->minv_off.size() * sizeof(long long));
   put(h->off_minv, h->minv.data(), h->minv.size() * sizeof(double));
@@ -1069,6 +1108,7 @@ static int enqueue_pass(btdf_t *h, const LbmParams &p, const IbParams &ib, hipSt
 static int run_blocked(btdf_t *h, const LbmParams &p, const IbParams &ib, int64_t n);
 static bool blocking_active(const btdf_t *h);
 static bool remainder_pair(const btdf_t *h);
+static bool remainder_triple(const btdf_t *h);
 
 // n steps from the current buffer: graphs of graph_chunk steps where they fit
 static int run_steps(btdf_t *h, const LbmParams &p, const IbParams &ib, int64_t n) {
@@ -1264,7 +1304,48 @@ static int enqueue_triple(btdf_t *h, const LbmParams &p, const IbParams &ib, hip
   return ok();
 }
 
+// d = 4 or 5 steps from buffer cur into 1 - cur: as a triple, with the near
+// tiles' states n+1 .. n+d-1 in X1 .. X(d-1) and the marker kernel before
+// each of their steps. ev: 2d + 2 events or null: marker kernel E0-E1, near
+// step E1-E2, pass E2-E3, then for each later step s = 1 .. d-1 the marker
+// kernel E(2s+1)-E(2s+2) and the near step E(2s+2)-E(2s+3).
+static int enqueue_deep(btdf_t *h, const LbmParams &p, const IbParams &ib, hipStream_t s, hipEvent_t *ev) {
+  const int d = h->depth;
+  const void *A = h->ws + h->off_pop[h->cur];
+  void *B = h->ws + h->off_pop[1 - h->cur];
+  // (X1 .. X4 are consecutive population buffers, which the pass addresses from X1)
+  void *X[5] = {nullptr, h->ws + h->off_pop3, h->ws + h->off_pop4, h->ws + h->off_pop5, h->ws + h->off_pop6};
+  const int *fm = h->at<int>(h->off_fmap);
+  const unsigned *rwin = h->at<unsigned>(h->off_rwin);
+  const int nb0 = h->n_groups();  // the near tiles start here in the map
+  auto mark = [&](int k) -> hipError_t { return ev && ev[k] ? hipEventRecord(ev[k], s) : hipSuccess; };
+  HIPCHK(mark(0));
+  HIPCHK(launch_ib(h->prec, A, p, ib, s));
+  HIPCHK(mark(1));
+  HIPCHK(launch_lbm(h->prec, h->variant, A, X[1], p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
+  if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, A, X[1], p, s));
+  HIPCHK(mark(2));
+  // the pass: the smallest groups (which border near tiles) first, the largest last
+  for (int g = kLevels - 1; g >= 0; --g)
+    if (h->n_grp[g])
+      HIPCHK(launch_lbm_deep(h->prec, h->variant, d, h->gkind[g], A, B, p, fm + h->grp_start(g), h->n_grp[g],
+                             h->n_ring[g], X[1], rwin + h->grp_start(g), s));
+  HIPCHK(mark(3));
+  for (int k = 1; k < d; ++k) {
+    void *dst = k + 1 < d ? X[k + 1] : B;
+    HIPCHK(launch_ib(h->prec, X[k], p, ib, s));
+    HIPCHK(mark(2 * k + 2));
+    HIPCHK(launch_lbm(h->prec, h->variant, X[k], dst, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
+    if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, X[k], dst, p, s));
+    HIPCHK(mark(2 * k + 3));
+  }
+  h->cur ^= 1;
+  h->steps += d;
+  return ok();
+}
+
 static int enqueue_pass(btdf_t *h, const LbmParams &p, const IbParams &ib, hipStream_t s, hipEvent_t *ev) {
+  if (h->depth >= 4) return enqueue_deep(h, p, ib, s, ev);
   return h->depth == 3 ? enqueue_triple(h, p, ib, s, ev) : enqueue_pair(h, p, ib, s, ev);
 }
 
@@ -1322,6 +1403,10 @@ static int run_blocked(btdf_t *h, const LbmParams &p, const IbParams &ib, int64_
   }
   for (; left >= d; left -= d)
     if ((rc = enqueue_pass(h, p, ib, h->stream, nullptr))) return rc;
+  if (left >= 3 && remainder_triple(h)) {
+    if ((rc = enqueue_triple(h, p, ib, h->stream, nullptr))) return rc;
+    left -= 3;
+  }
   if (left == 2 && remainder_pair(h)) {
     if ((rc = enqueue_pair(h, p, ib, h->stream, nullptr))) return rc;
     left = 0;
@@ -1344,7 +1429,7 @@ static bool blocking_active(const btdf_t *h) {
 // three-step pass serve the two-step pass as they are (its groups along
 // rows; not the groups two tiles tall).
 static bool remainder_pair(const btdf_t *h) {
-  if (h->depth != 3 || !variant_has_lbm2(h->variant, h->prec)) return false;
+  if (h->depth < 3 || !variant_has_lbm2(h->variant, h->prec)) return false;
   for (int g = 0; g < kLevels; ++g) {
     if (!h->n_grp[g]) continue;
     const int code = h->gkind[g], w = code & 15;
@@ -1353,6 +1438,16 @@ static bool remainder_pair(const btdf_t *h) {
     if (((code >> 4) & 15) != 1) return false;  // taller than one tile
     if (w > 1 && !variant_has_wide_lbm2(h->variant, h->prec, w)) return false;
   }
+  return true;
+}
+
+// Whether three steps left over after deeper passes can take one three-step
+// pass over the same tiles (the near set of a deeper pass covers that of
+// three steps, and its groups are rows of tiles the three-step pass has).
+static bool remainder_triple(const btdf_t *h) {
+  if (h->depth < 4) return false;
+  for (int g = 0; g < kLevels; ++g)
+    if (h->n_grp[g] && (h->n_edge[g] || !variant_has_lbm3(h->variant, h->prec, h->gkind[g]))) return false;
   return true;
 }
 
@@ -1370,27 +1465,36 @@ static int timed_impl(btdf_t *h, int64_t n, double *out, bool pass_only = false)
   if (rc) return rc;
   const LbmParams p = make_params(h);
   const IbParams ib = make_ib(h);
-  const int chunk = 256, NE = 10;  // events per entry
+  const int chunk = 256, NE = 12;  // events per entry
   HIPCHK(h->tev.reserve((size_t)NE * chunk));
   std::vector<hipEvent_t> ev(h->tev.ev.begin(), h->tev.ev.begin() + (size_t)NE * chunk);
+  const int d = h->depth;
+  // the pass's two events in an entry of d steps (deeper passes number
+  // their events in launch order)
+  const int pa = d >= 4 ? 2 : 5, pb = d >= 4 ? 3 : 6;
   if (pass_only)  // only the pass's two events of each entry are recorded
     for (size_t i = 0; i < ev.size(); ++i)
-      if (i % NE != 5 && i % NE != 6) ev[i] = nullptr;
-  const int d = h->depth;
+      if ((int)(i % NE) != pa && (int)(i % NE) != pb) ev[i] = nullptr;
   double tib = 0.0, tlbm = 0.0, tpair = 0.0;
   int64_t done = 0, pass_steps = 0;
   rc = ok();
   while (done < n && rc == 0) {
-    // entries of this round: passes of d steps while d are left; two left
-    // after three-step passes take one two-step pass (untimed with
-    // pass_only, so the pass's mean is that of the d-step launches)
+    // entries of this round: passes of d steps while d are left; three
+    // left after deeper passes take one three-step pass, two left one
+    // two-step pass (untimed with pass_only, so the pass's mean is that of
+    // the d-step launches)
     const bool blk = blocking_active(h);
     const bool pairs = blk && n - done >= d;
-    const bool rem2 = blk && !pairs && d == 3 && n - done == 2 && remainder_pair(h);
-    const int dk = pairs ? d : (rem2 ? 2 : 1);  // steps per entry
+    const bool rem3 = blk && !pairs && n - done >= 3 && remainder_triple(h);
+    const bool rem2 = blk && !pairs && !rem3 && d >= 3 && n - done == 2 && remainder_pair(h);
+    const int dk = pairs ? d : (rem3 ? 3 : (rem2 ? 2 : 1));  // steps per entry
     const int m = dk > 1 ? (int)std::min<int64_t>(chunk, (n - done) / dk) : (int)std::min<int64_t>(chunk, n - done);
     const bool moving = h->any_moving();
     for (int k = 0; k < m && rc == 0; ++k) {
+      if (rem3) {
+        rc = enqueue_triple(h, p, ib, h->stream, pass_only ? nullptr : &ev[NE * k]);
+        continue;
+      }
       if (rem2) {
         rc = enqueue_pair(h, p, ib, h->stream, pass_only ? nullptr : &ev[NE * k]);
         continue;
@@ -1420,10 +1524,26 @@ static int timed_impl(btdf_t *h, int64_t n, double *out, bool pass_only = false)
       hipEvent_t *E = &ev[NE * k];
       if (pass_only) {
         if (pairs) {
-          (void)hipEventElapsedTime(&f, E[5], E[6]);
+          (void)hipEventElapsedTime(&f, E[pa], E[pb]);
           tpair += f;
           pass_steps += dk;
         }
+        continue;
+      }
+      if (dk >= 4) {  // a deeper pass: marker kernel and near step of each step, and the pass
+        (void)hipEventElapsedTime(&a, E[0], E[1]);
+        (void)hipEventElapsedTime(&b, E[1], E[2]);
+        (void)hipEventElapsedTime(&f, E[2], E[3]);
+        tib += a;
+        tlbm += b;
+        tpair += f;
+        for (int s2 = 1; s2 < dk; ++s2) {
+          (void)hipEventElapsedTime(&a, E[2 * s2 + 1], E[2 * s2 + 2]);
+          (void)hipEventElapsedTime(&b, E[2 * s2 + 2], E[2 * s2 + 3]);
+          tib += a;
+          tlbm += b;
+        }
+        pass_steps += dk;
         continue;
       }
       if (dk > 1) {
@@ -1848,7 +1968,8 @@ int btdf_set_option(btdf_t *h, int key, int64_t value) {
         }
         return ok();
       case BTDF_OPT_TEMPORAL_BLOCKING:
-        if (value < 0 || value > 3) return fail(BTDF_EINVAL, "temporal blocking must be 0 (off), 1 (deepest), 2 or 3");
+        if (value < 0 || value > 5)
+          return fail(BTDF_EINVAL, "temporal blocking must be 0 (off), 1 (the default depth) or 2 to 5 steps per pass");
         if (value != h->tblock) {
           h->tblock = (int)value;
           h->layout_ok = false;  // the tile lists and the third buffer

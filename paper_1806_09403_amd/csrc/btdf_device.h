@@ -343,6 +343,14 @@ __device__ __forceinline__ float recip<float>(float x) {
 template <>
 __device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
 
+// On gfx950 a wave holding more than 80 scalar registers (96 once rounded
+// up) leaves room for fewer waves per SIMD than the vector registers allow:
+// a 1024-thread workgroup of such waves fits once per CU instead of twice,
+// and 256-thread workgroups fit six or seven per SIMD instead of eight.
+// Kernels that would exceed it take this cap (the few values beyond it go
+// to vector register lanes).
+#define kSgprCap __attribute__((amdgpu_num_sgpr(80)))
+
 // A wave-uniform pointer pinned to scalar registers, so that an access
 // through it plus a 32-bit lane offset is one load or store with a scalar
 // base (the compiler may otherwise fold the uniform part into a 64-bit
@@ -578,6 +586,27 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   int q = n >> 3, r = n & 7;
   int xcd = b & 7, j = b >> 3;
   return xcd < r ? xcd * (q + 1) + j : r * (q + 1) + (xcd - r) * q + j;
+}
+
+// The ring directions of an edge node of a group of W x H lattice tiles:
+// bit q set when the neighbour x + e_q lies in a near tile. s_near holds the
+// near flags of the tiles around the group (row 0 below it, column 0 left of
+// it; the group's own tiles read 0).
+template <int OX, int OY, int NR>
+__device__ __forceinline__ unsigned ring_mask(const unsigned char (&s_near)[NR][8], int ii, int jj, int W, int H,
+                                              int shx, int shy) {
+  const int cl = ii == 0 ? 0 : 1 + ((ii - 1) >> shx), cm = 1 + (ii >> shx);
+  const int cr = ii == OX - 1 ? W + 1 : 1 + ((ii + 1) >> shx);
+  const int rd = jj == 0 ? 0 : 1 + ((jj - 1) >> shy), rm = 1 + (jj >> shy);
+  const int ru = jj == OY - 1 ? H + 1 : 1 + ((jj + 1) >> shy);
+  unsigned m = 0;
+#pragma unroll
+  for (int q = 1; q < 9; ++q) {
+    const int r = ey(q) < 0 ? rd : (ey(q) > 0 ? ru : rm);
+    const int c = ex(q) < 0 ? cl : (ex(q) > 0 ? cr : cm);
+    m |= s_near[r][c] ? 1u << q : 0u;
+  }
+  return m;
 }
 
 }  // namespace btdf

@@ -86,7 +86,7 @@ struct btdf_sim {
   int margin = 0;
   int64_t steps_to_rebin = 0;
   // temporal blocking: tiles taking two steps at once, then the singly stepped regions
-  int tblock = 1;  // option: 0 off, 1 deepest available, 2 or 3 steps per pass
+  int tblock = 1;  // option: 0 off, 1 the default depth, 2 to 5 steps per pass
   int edge_tiles = 0;  // option: tiles within reach of a domain edge take the blocked pass
   int depth = 1;   // steps per pass of the tiles away from the bodies (set with the layout)
   bool reserve_pass = false;  // keep the blocked pass's buffers whatever the launch shape (batch cases)
@@ -94,9 +94,11 @@ struct btdf_sim {
   // group), then the near tiles
   std::vector<int> fmap;
   std::vector<unsigned char> near;  // per lattice tile: 1 if it steps singly
+  std::vector<unsigned> rwin;       // per fmap entry of a ring group (deeper passes): the near flags around it
   int gkind[btdf::kLevels] = {};  // shape per level (set with the lists)
   int n_grp[btdf::kLevels] = {};  // groups per level
   int n_edge[btdf::kLevels] = {};  // of those, edge groups (first in the level's list)
+  int n_ring[btdf::kLevels] = {};  // passes of four or five steps: groups bordering a near tile (listed first)
   long long pass_nodes = 0;        // grid nodes in the blocked pass (partial tiles counted by their nodes)
   int n_near = 0;
   int n_groups() const {
@@ -124,7 +126,7 @@ struct btdf_sim {
   size_t off_pop[2] = {0, 0}, off_ctl = 0, grid_bytes = 0;
   size_t off_hist = 0, off_mk = 0, off_mkw = 0, off_mkixy = 0, off_mkbody = 0, off_body = 0, off_boff = 0,
          off_toff = 0, off_tlist = 0, off_tmap = 0, off_coff = 0, off_clist = 0, off_mdfc = 0, off_mdff = 0,
-         off_moff = 0, off_minv = 0, off_motion = 0, off_rxy = 0, off_fmap = 0, off_near = 0, off_pop3 = 0, off_pop4 = 0, total = 0;
+         off_moff = 0, off_minv = 0, off_motion = 0, off_rxy = 0, off_fmap = 0, off_rwin = 0, off_near = 0, off_pop3 = 0, off_pop4 = 0, off_pop5 = 0, off_pop6 = 0, total = 0;
   bool layout_ok = false;  // host layout current for bodies and tiles
   bool device_ok = false;  // body part uploaded into the workspace
   bool state_ok = false;   // populations hold a state
@@ -200,6 +202,8 @@ constexpr int kMoveMargin = 2;  // nodes a moving marker may travel between tile
 // smallest lattice that blocks by default: the 256-channel set (8 k to 520 k
 // nodes per case) ran at 11.4 GLUPS case by case unblocked, 8.2 blocked
 constexpr long long kBlockMinNodes = 1ll << 20;
+// steps per pass by default on a single lattice, where the launch shape has them
+constexpr int kDefaultDepth = 4;
 std::string forcing_setup(btdf_t *h);
 LbmParams make_params(const btdf_t *h);
 IbParams make_ib(const btdf_t *h);

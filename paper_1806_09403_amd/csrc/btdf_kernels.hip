@@ -189,7 +189,7 @@ __global__ __launch_bounds__(256) void ib_pass_kernel(LbmParams p, IbParams ib, 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void ib_kernel(const T *__restrict__ A, LbmParams p, IbParams ib) {
+__global__ __launch_bounds__(256) kSgprCap void ib_kernel(const T *__restrict__ A, LbmParams p, IbParams ib) {
   // markers of one body are contiguous and share stencil nodes: consecutive
   // workgroups go to one XCD so its L2 serves the shared population lines
   const int blk = p.xcd_remap ? xcd_tile((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
@@ -413,7 +413,7 @@ __device__ __forceinline__ void lbm_tile(const T *__restrict__ A, T *__restrict_
 }
 
 template <typename T, int BX, int BY, int NPT, bool NT, bool NTL>
-__global__ __launch_bounds__(BX *BY) void lbm_kernel(const T *__restrict__ A, T *__restrict__ B,
+__global__ __launch_bounds__(BX *BY) kSgprCap void lbm_kernel(const T *__restrict__ A, T *__restrict__ B,
                                                      LbmParams p, TileRange r, IbParams ib) {
   if ((int)blockIdx.x >= r.count) {  // workgroups past the tiles: one body each, then the step counter
     const int gb = (int)blockIdx.x - r.count;
@@ -435,7 +435,7 @@ __global__ __launch_bounds__(BX *BY) void lbm_kernel(const T *__restrict__ A, T 
 // (the per-case parameters are the single-case ones, read from a table)
 
 template <typename T, int BX, int BY, int NPT, bool NT, bool NTL>
-__global__ __launch_bounds__(BX *BY) void lbm_batch_kernel(const CaseDesc *__restrict__ cases, BatchMap m,
+__global__ __launch_bounds__(BX *BY) kSgprCap void lbm_batch_kernel(const CaseDesc *__restrict__ cases, BatchMap m,
                                                            int rt) {
   if ((int)blockIdx.x >= m.ntiles) {  // one body each, then one step counter per case
     const int gb = (int)blockIdx.x - m.ntiles;
@@ -466,7 +466,7 @@ __global__ __launch_bounds__(BX *BY) void lbm_batch_kernel(const CaseDesc *__res
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void ib_batch_kernel(const CaseDesc *__restrict__ cases, BatchMap m, int rt) {
+__global__ __launch_bounds__(256) kSgprCap void ib_batch_kernel(const CaseDesc *__restrict__ cases, BatchMap m, int rt) {
   const int blk = m.xcd_remap ? xcd_tile((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
   const int c = m.mblk_case[blk];
   const int first = m.mblk_first[blk];
@@ -845,27 +845,6 @@ constexpr bool lbm3_fits() {
 __host__ __device__ constexpr bool lbm3_group_ok(int ox, int oy, int tx, int ty) {
   return tx > 0 && ty > 0 && (tx & (tx - 1)) == 0 && (ty & (ty - 1)) == 0 && ox % tx == 0 && oy % ty == 0 &&
          ox / tx <= 4 && oy == ty;
-}
-
-// The ring directions of an edge node of a group of W x H lattice tiles:
-// bit q set when the neighbour x + e_q lies in a near tile. s_near holds the
-// near flags of the tiles around the group (row 0 below it, column 0 left of
-// it; the group's own tiles read 0).
-template <int OX, int OY, int NR>
-__device__ __forceinline__ unsigned ring_mask(const unsigned char (&s_near)[NR][8], int ii, int jj, int W, int H,
-                                              int shx, int shy) {
-  const int cl = ii == 0 ? 0 : 1 + ((ii - 1) >> shx), cm = 1 + (ii >> shx);
-  const int cr = ii == OX - 1 ? W + 1 : 1 + ((ii + 1) >> shx);
-  const int rd = jj == 0 ? 0 : 1 + ((jj - 1) >> shy), rm = 1 + (jj >> shy);
-  const int ru = jj == OY - 1 ? H + 1 : 1 + ((jj + 1) >> shy);
-  unsigned m = 0;
-#pragma unroll
-  for (int q = 1; q < 9; ++q) {
-    const int r = ey(q) < 0 ? rd : (ey(q) > 0 ? ru : rm);
-    const int c = ex(q) < 0 ? cl : (ex(q) > 0 ? cr : cm);
-    m |= s_near[r][c] ? 1u << q : 0u;
-  }
-  return m;
 }
 
 // Three steps A -> C for a group of lattice tiles OX x OY (W x H tiles,

@@ -59,6 +59,17 @@ hipError_t launch_lbm_edge3_batch(int prec, int variant, int code, const CaseDes
 // step in X
 hipError_t launch_lbm_edge2(int prec, int variant, int code, const void *A, void *C, const LbmParams &p,
                             const int *map, int count, void *X, const unsigned char *near, hipStream_t s);
+// four or five steps A -> C over the listed groups (rows of 1, 2 or 4
+// lattice tiles, at least depth nodes from every domain edge); the first
+// ring_groups of them border a near tile (rwin[k]: the near flags of the
+// tiles around group k, bit 8 r + c for row r of three from the row below
+// and column c from the column left of it), and their edge nodes also store
+// their states n+1 .. n+depth-1 in the ring buffers, consecutive population
+// buffers from ring (btdf_deep.hip)
+bool variant_has_deep(int variant, int prec, int depth, int code);
+hipError_t launch_lbm_deep(int prec, int variant, int depth, int code, const void *A, void *C, const LbmParams &p,
+                           const int *map, int count, int ring_groups, void *ring, const unsigned *rwin,
+                           hipStream_t s);
 hipError_t launch_conv_outlet(int prec, const void *A, void *B, const LbmParams &p, hipStream_t s);
 hipError_t launch_conv_outlet_batch(int prec, const CaseDesc *cases, int ncases, int mask_unstable, int rt,
                                     hipStream_t s);

@@ -169,19 +169,21 @@ def test_particle_laden_8192_one_step_against_oracle(kind):
 
 
 def test_particle_laden_8192_blocked_pass_against_oracle():
-    """The same workload through one three-step pass, the benchmark's timed
-    unit: after 21 steps (seven passes) the state is handed to the oracle,
-    the GPU takes one pass (three steps) and the oracle three single steps;
-    populations, the body forces of each of the three steps and the last
-    step's marker forces are compared. The GPU state stays FP32 across the
-    pass, so the bounds are those of three FP32 steps against FP64 ones."""
+    """The same workload through one blocked pass of the default depth d
+    (four steps), the benchmark's timed unit: after seven passes the state is
+    handed to the oracle, the GPU takes one pass (d steps) and the oracle d
+    single steps; populations, the body forces of each of the d steps and
+    the last step's marker forces are compared. The GPU state stays FP32
+    across the pass, so the bounds are those of d FP32 steps against FP64
+    ones."""
     from paper_1806_09403_amd import Sim, _lib
     c = W.c3()
     log("8192^2 blocked pass: building GPU case")
     g = Sim.from_case(c, precision=4)
-    assert g.get_option(_lib.OPT_STEPS_PER_PASS) == 3 and g.get_option(_lib.OPT_FUSED_TILES) > 0
-    g.step(21)
-    g.force_history(1000)  # drain: only the next three steps are returned below
+    d = g.get_option(_lib.OPT_STEPS_PER_PASS)
+    assert d == 4 and g.get_option(_lib.OPT_FUSED_TILES) > 0
+    g.step(7 * d)
+    g.force_history(1000)  # drain: only the next pass's steps are returned below
     f = g.populations()
     log("  oracle setup")
     o = OracleSim(c.nx, c.ny, c.bc, c.tau, c.kind, c.thickening, c.G, c.inflow, c.init)
@@ -189,18 +191,18 @@ def test_particle_laden_8192_blocked_pass_against_oracle():
         o.add_body(b.xy, b.uv, b.cx, b.cy, b.ds)
     o.set_populations(f)
     del f
-    log("  one pass on the GPU, three oracle steps")
-    g.step(3)
-    hist_g = g.force_history(3)
+    log("  one pass on the GPU, %d oracle steps" % d)
+    g.step(d)
+    hist_g = g.force_history(d)
     hist_o = []
-    for _ in range(3):
+    for _ in range(d):
         o.step(1)
         hist_o.append(o.forces())
     hist_o = np.array(hist_o)
-    assert hist_g.shape == hist_o.shape == (3, len(c.bodies), 3)
-    d = np.max(np.abs(g.populations() - o.populations()))
-    log("  max |df| after three steps = %.3e" % d)
-    assert d < 2e-7  # as for one step: FP32 rounding of the stored deviations, well below 1e-6
+    assert hist_g.shape == hist_o.shape == (d, len(c.bodies), 3)
+    df = np.max(np.abs(g.populations() - o.populations()))
+    log("  max |df| after %d steps = %.3e" % (d, df))
+    assert df < 2e-7  # as for one step: FP32 rounding of the stored deviations, well below 1e-6
     scale = np.max(np.abs(hist_o), axis=(1, 2))
     rel = np.max(np.abs(hist_g - hist_o), axis=(1, 2)) / scale
     log("  body forces rel per step %s" % rel)
