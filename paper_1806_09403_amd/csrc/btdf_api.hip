@@ -165,15 +165,15 @@ void cover_lists(const btdf_t *h, std::vector<int> &off, std::vector<int> &list)
 }
 
 // steps per pass of the tiles away from the bodies for the options and the
-// launch shape: the depth asked for (by default kDefaultDepth on a single
-// lattice, 3 in a batch), or the deepest below it that the shape has
-// (4 and 5 on single lattices only), else 1 (no blocking)
+// launch shape: the depth asked for (by default kDefaultDepth on an FP32
+// single lattice, 3 in FP64 and in a batch), or the deepest below it that
+// the shape has (4 and 5 on single lattices only), else 1 (no blocking)
 int pass_depth(const btdf_t *h) {
   if (!h->tblock) return 1;
   // by default only lattices large enough that the saved bytes outweigh the
   // extra launches of a blocked pass (single handles; a batch shares them)
   if (h->tblock == 1 && !h->owner && (long long)h->nx * h->ny < kBlockMinNodes) return 1;
-  int want = h->tblock == 1 ? (h->owner ? 3 : kDefaultDepth) : h->tblock;
+  int want = h->tblock == 1 ? (h->owner || h->prec != 4 ? 3 : kDefaultDepth) : h->tblock;
   if (h->owner) want = std::min(want, 3);
   for (int d = want; d >= 4; --d)
     if (variant_has_deep(h->variant, h->prec, d, kGroup1x1)) return d;
