@@ -121,7 +121,7 @@ extern "C" {
                                          once for d updates. The others step singly with the marker kernel
                                          between, and the pass gives them the intermediate states of the
                                          nodes just outside. Results are bit-identical to single steps.
-                                         1 (default): four steps per pass in FP32 (three in FP64) on lattices
+                                         1 (default): five steps per pass in FP32 (three in FP64) on lattices
                                          of at least 2^20 nodes where the launch shape has them (32x8 lattice
                                          tiles), else the deepest below (3, or 2 for tiles one or two rows tall); smaller
                                          lattices step singly (the extra launches of a pass outweigh the

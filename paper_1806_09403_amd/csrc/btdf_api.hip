@@ -201,9 +201,11 @@ static bool has_group(const btdf_t *h, int d, int code) {
 void group_kinds(int variant, int prec, int d, int kind[kLevels]) {
   (void)variant;
   (void)prec;
-  (void)d;
+  // five steps: squares of two by two tiles first (the fewest recomputed
+  // halo nodes per node), then columns of two, rows of two, single tiles
   static const int rows[kLevels] = {kGroup4x1, kGroup1x4, kGroup2x1, kGroup1x1};
-  for (int i = 0; i < kLevels; ++i) kind[i] = rows[i];
+  static const int squares[kLevels] = {kGroup2x2, kGroup1x2, kGroup2x1, kGroup1x1};
+  for (int i = 0; i < kLevels; ++i) kind[i] = d >= 5 ? squares[i] : rows[i];
 }
 
 // Tiles for temporal blocking of depth d = h->depth on the current launch
@@ -319,7 +321,7 @@ void fused_lists(btdf_t *h) {
       for (size_t k = start; k < start + (size_t)h->n_ring[g]; ++k) {
         const int t = h->fmap[k], a = t % ntx, b = t / ntx;
         unsigned m = 0;
-        for (int r = 0; r < 3; ++r)
+        for (int r = 0; r < gh + 2; ++r)
           for (int c = 0; c < w + 2; ++c) m |= near[(b - 1 + r) * ntx + a - 1 + c] ? 1u << (8 * r + c) : 0u;
         h->rwin[k] = m;
       }

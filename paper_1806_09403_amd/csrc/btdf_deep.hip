@@ -19,8 +19,8 @@
 // nodes run in a launch of their own, with that code; the others without.
 //
 // The host hands over groups of tiles at least D nodes from every domain
-// edge (no wrap, wall or ghost column in reach), one row of 1, 2 or 4
-// lattice tiles each.
+// edge (no wrap, wall or ghost column in reach): rows of 1, 2 or 4 lattice
+// tiles, or two tiles tall.
 #include "btdf_device.h"
 #include "btdf_launch.h"
 
@@ -123,13 +123,15 @@ __global__ __launch_bounds__(OX *OY) void lbmd_kernel(const T *__restrict__ A, T
   // x + e_q lies in a near tile (the group's own tiles never are)
   unsigned rmask = 0;
   if (RING && (ii == 0 || ii == OX - 1 || jj == 0 || jj == OY - 1)) {
-    constexpr int W = OX / TX, shx = __builtin_ctz((unsigned)TX);
+    constexpr int W = OX / TX, H = OY / TY;
+    constexpr int shx = __builtin_ctz((unsigned)TX), shy = __builtin_ctz((unsigned)TY);
     const int cl = ii == 0 ? 0 : 1 + ((ii - 1) >> shx), cm = 1 + (ii >> shx);
     const int cr = ii == OX - 1 ? W + 1 : 1 + ((ii + 1) >> shx);
-    const int rd = jj == 0 ? 0 : 1, ru = jj == OY - 1 ? 2 : 1;
+    const int rd = jj == 0 ? 0 : 1 + ((jj - 1) >> shy), rm = 1 + (jj >> shy);
+    const int ru = jj == OY - 1 ? H + 1 : 1 + ((jj + 1) >> shy);
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
-      const int r = ey(q) < 0 ? rd : (ey(q) > 0 ? ru : 1);
+      const int r = ey(q) < 0 ? rd : (ey(q) > 0 ? ru : rm);
       const int c = ex(q) < 0 ? cl : (ex(q) > 0 ? cr : cm);
       rmask |= ((win >> (8 * r + c)) & 1u) << q;
     }
@@ -146,9 +148,13 @@ __global__ __launch_bounds__(OX *OY) void lbmd_kernel(const T *__restrict__ A, T
     const long long plane = p.plane + vz;
     global_ptr<T> X = (global_ptr<T>)ring + (long long)(s - 1) * ring_stride<T>(p) + vz +
                       (long long)(y0 + jj) * p.pitch + (x0 + ii);
+    // the eight LDS reads first, so they are in flight together, then the stores
+    T v[9];
+#pragma unroll
+    for (int q = 1; q < 9; ++q) v[q] = s_f[q][jj + G][ii + G];
 #pragma unroll
     for (int q = 1; q < 9; ++q)
-      if (rmask & (1u << q)) X[q * plane] = s_f[q][jj + G][ii + G];
+      if (rmask & (1u << q)) X[q * plane] = v[q];
   };
   ring_store(1);
   T *sf = &s_f[0][0][0];
@@ -176,11 +182,13 @@ __global__ __launch_bounds__(OX *OY) void lbmd_kernel(const T *__restrict__ A, T
       }
     }
     __syncthreads();
+    // (one branch per node: the nine stores of a node under one mask)
 #pragma unroll
-    for (int q = 0; q < 9; ++q)
+    for (int r = 0; r < NR; ++r)
+      if (pos[r] >= 0) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
-        if (pos[r] >= 0) sf[q * RY * RX + pos[r]] = o[r][q];
+        for (int q = 0; q < 9; ++q) sf[q * RY * RX + pos[r]] = o[r][q];
+      }
     __syncthreads();
     ring_store(s);
   }
@@ -202,16 +210,19 @@ __global__ __launch_bounds__(OX *OY) void lbmd_kernel(const T *__restrict__ A, T
 }
 
 // The shapes of the deep passes: (depth, group code, lattice tile, group in
-// nodes). Four steps take pairs and single tiles (four 512-thread groups per
-// CU hide more latency than two of 1024 threads); five take groups of four too.
+// nodes). Four steps take rows of two tiles (four 512-thread groups per CU
+// hide more latency than two of 1024 threads) and single tiles; five take
+// squares of two by two tiles (64x16: 1.34 collisions per update against
+// 1.55 for 128x8), columns of two, rows of four and two, and single tiles.
 #define BTDF_DEEP_SHAPES(S)                                                                         \
-  S(4, kGroup2x1, 32, 8, 64, 8) S(4, kGroup1x1, 32, 8, 32, 8) S(5, kGroup4x1, 32, 8, 128, 8)      \
-  S(5, kGroup2x1, 32, 8, 64, 8) S(5, kGroup1x1, 32, 8, 32, 8)
+  S(4, kGroup2x1, 32, 8, 64, 8) S(4, kGroup1x1, 32, 8, 32, 8) S(5, kGroup2x2, 32, 8, 64, 16)     \
+  S(5, kGroup1x2, 32, 8, 32, 16) S(5, kGroup4x1, 32, 8, 128, 8) S(5, kGroup2x1, 32, 8, 64, 8)     \
+  S(5, kGroup1x1, 32, 8, 32, 8)
 
 template <typename T, int D, int OX, int OY, int TX, int TY>
 static hipError_t launch_deep_t(const T *A, T *C, const LbmParams &p, const int *map, int count, int ring_groups,
                                 void *ring, const unsigned *rwin, hipStream_t s) {
-  static_assert(OY == TY && OX / TX <= 6, "one row of tiles, its window within a 32-bit word");
+  static_assert(OX / TX <= 6 && OY / TY <= 2, "the window of tiles around a group within a 32-bit word");
   if constexpr (deep_fits<T, D, OX, OY>()) {
     // the groups that border a near tile (the first ring_groups of the map), then the others
     if (ring_groups > 0)

@@ -447,7 +447,10 @@ __device__ __forceinline__ void collide(const T g[9], const ForceK<T> &f, const 
 // (+subnormal or +normal), the same set as rho > 0 && isfinite(rho)
 template <typename T>
 __device__ __forceinline__ bool rho_ok(T rho) {
-  return __builtin_amdgcn_class(rho, 0x180);
+  if constexpr (sizeof(T) == 4)
+    return __builtin_amdgcn_classf(rho, 0x180);  // (the FP32 test: no conversion to FP64)
+  else
+    return __builtin_amdgcn_class(rho, 0x180);
 }
 // a wave's lanes whose density is not: one mask for the whole wave, kept
 // in scalar registers

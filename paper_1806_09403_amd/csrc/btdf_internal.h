@@ -203,7 +203,7 @@ constexpr int kMoveMargin = 2;  // nodes a moving marker may travel between tile
 // nodes per case) ran at 11.4 GLUPS case by case unblocked, 8.2 blocked
 constexpr long long kBlockMinNodes = 1ll << 20;
 // steps per pass by default on a single lattice, where the launch shape has them
-constexpr int kDefaultDepth = 4;
+constexpr int kDefaultDepth = 5;
 std::string forcing_setup(btdf_t *h);
 LbmParams make_params(const btdf_t *h);
 IbParams make_ib(const btdf_t *h);

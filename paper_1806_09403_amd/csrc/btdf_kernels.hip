@@ -841,10 +841,13 @@ constexpr bool lbm3_fits() {
 // lattice tile, group in nodes). The code is W | H << 4 for W x H tiles.
 #define BTDF_LBM3_GROUPS(G) \
   G(kGroup4x1, 32, 8, 128, 8) G(kGroup2x1, 32, 8, 64, 8) G(kGroup2x1, 64, 4, 128, 4)
+// groups two tiles tall, on single lattices only: those of passes of five
+// steps, for the three steps left over after them
+#define BTDF_LBM3_SQUARES(G) G(kGroup2x2, 32, 8, 64, 16) G(kGroup1x2, 32, 8, 32, 16)
 
 __host__ __device__ constexpr bool lbm3_group_ok(int ox, int oy, int tx, int ty) {
   return tx > 0 && ty > 0 && (tx & (tx - 1)) == 0 && (ty & (ty - 1)) == 0 && ox % tx == 0 && oy % ty == 0 &&
-         ox / tx <= 4 && oy == ty;
+         ox / tx <= 4 && (oy == ty || oy == 2 * ty);
 }
 
 // Three steps A -> C for a group of lattice tiles OX x OY (W x H tiles,
@@ -939,12 +942,16 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
   if (ring && (ii == 0 || ii == OX - 1 || jj == 0 || jj == OY - 1)) rmask = ring_mask<OX, OY>(s_near, ii, jj, W, H, shx, shy);
   const unsigned off = (unsigned)(jj * p.pitch + ii) * (unsigned)sizeof(T);
   if (rmask && keep) {
+    // the eight LDS reads first, so they are in flight together, then the stores
+    T v[9];
+#pragma unroll
+    for (int q = 1; q < 9; ++q) v[q] = s_f[q][jj + 2][ii + 2];
 #pragma unroll
     for (int q = 1; q < 9; ++q)
       if (rmask & (1u << q))
         store_uniform<T, false>(
             uniform_ptr(reinterpret_cast<char *>(X1 + (long long)q * p.plane + (long long)y0 * p.pitch + x0)), off,
-            s_f[q][jj + 2][ii + 2]);
+            v[q]);
   }
   // step n+2 over the group grown by one (at most two nodes per thread)
   constexpr int R2X = OX + 2, TOT2 = R2X * (OY + 2);
@@ -968,10 +975,14 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
   }
   __syncthreads();
   T *sf = &s_f[0][0][0];
+  // (one branch per node: the nine stores of a node under one mask)
+  if (pa >= 0) {
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    if (pa >= 0) sf[q * RY * RX + pa] = o2a[q];
-    if (pb >= 0) sf[q * RY * RX + pb] = o2b[q];
+    for (int q = 0; q < 9; ++q) sf[q * RY * RX + pa] = o2a[q];
+  }
+  if (pb >= 0) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sf[q * RY * RX + pb] = o2b[q];
   }
   __syncthreads();
   // step n+3 on the group's own nodes, pulling state n+2 from LDS
@@ -989,12 +1000,15 @@ __device__ __forceinline__ void lbm3_group(const T *__restrict__ A, T *__restric
       store_uniform<T, NT>(uniform_ptr(reinterpret_cast<char *>(C + (long long)q * p.plane + (long long)y0 * p.pitch + x0)),
                            off, out[q]);
     if (rmask) {
+      T v[9];
+#pragma unroll
+      for (int q = 1; q < 9; ++q) v[q] = s_f[q][j][i];
 #pragma unroll
       for (int q = 1; q < 9; ++q)
         if (rmask & (1u << q))
           store_uniform<T, false>(
               uniform_ptr(reinterpret_cast<char *>(X2 + (long long)q * p.plane + (long long)y0 * p.pitch + x0)), off,
-              s_f[q][j][i]);
+              v[q]);
     }
   }
   if (bad) p.flag[0] = -1;
@@ -1095,6 +1109,7 @@ static hipError_t launch_lbm3_any(int v, int code, const T *A, T *C, const LbmPa
 #define G(c, TX, TY, OX, OY) \
   if (code == c && tx == TX && ty == TY) return launch_lbm3_t<T, OX, OY, OX, OY, true>(ARGS);
     BTDF_LBM3_GROUPS(G)
+    BTDF_LBM3_SQUARES(G)
 #undef G
     return hipErrorInvalidValue;
   }
@@ -1126,6 +1141,7 @@ bool variant_has_lbm3(int v, int prec, int code) {
 #define G(c, TX, TY, OX, OY) \
   if (code == c && tx == TX && ty == TY) fits = prec == 4 ? lbm3_fits<float, OX, OY>() : lbm3_fits<double, OX, OY>();
     BTDF_LBM3_GROUPS(G)
+    BTDF_LBM3_SQUARES(G)
 #undef G
     return fits;
   }

@@ -21,6 +21,7 @@ bool variant_has_wide_lbm2(int variant, int prec, int width);
 // (map entries name a group's lower-left tile)
 constexpr int kGroup1x1 = 0x11, kGroup2x1 = 0x12, kGroup4x1 = 0x14;
 constexpr int kGroup1x4 = 0x41;  // (edge groups only: the ends of a channel)
+constexpr int kGroup2x2 = 0x22, kGroup1x2 = 0x21;  // (two tiles tall: passes of five steps)
 constexpr int kNoGroup = 0;  // an unused level
 // groups of tiles within reach of a domain edge, with the boundary readings
 // in every step of the pass (btdf_edge.hip): the flag kEdge on a shape
@@ -60,10 +61,10 @@ hipError_t launch_lbm_edge3_batch(int prec, int variant, int code, const CaseDes
 hipError_t launch_lbm_edge2(int prec, int variant, int code, const void *A, void *C, const LbmParams &p,
                             const int *map, int count, void *X, const unsigned char *near, hipStream_t s);
 // four or five steps A -> C over the listed groups (rows of 1, 2 or 4
-// lattice tiles, at least depth nodes from every domain edge); the first
-// ring_groups of them border a near tile (rwin[k]: the near flags of the
-// tiles around group k, bit 8 r + c for row r of three from the row below
-// and column c from the column left of it), and their edge nodes also store
+// lattice tiles, or two tiles tall, at least depth nodes from every domain
+// edge); the first ring_groups of them border a near tile (rwin[k]: the
+// near flags of the tiles around group k, bit 8 r + c for row r from the
+// row below and column c from the column left of it), and their edge nodes also store
 // their states n+1 .. n+depth-1 in the ring buffers, consecutive population
 // buffers from ring (btdf_deep.hip)
 bool variant_has_deep(int variant, int prec, int depth, int code);

@@ -111,7 +111,7 @@ def test_every_launch_shape_with_the_blocked_pass(depth, min_active):
 
 
 def test_default_depth_follows_the_lattice_size():
-    """By default lattices of 2^20 nodes or more take four steps per pass in
+    """By default lattices of 2^20 nodes or more take five steps per pass in
     FP32 and three in FP64, and smaller ones step singly; a depth asked for
     explicitly applies to any size."""
     from paper_1806_09403_amd import Sim, _lib
@@ -120,9 +120,9 @@ def test_default_depth_follows_the_lattice_size():
     for prec in (4, 8):
         s = Sim.from_case(big, precision=prec)
         assert s.get_option(_lib.OPT_TEMPORAL_BLOCKING) == 1
-        assert s.get_option(_lib.OPT_STEPS_PER_PASS) == (4 if prec == 4 else 3)
-        s.set_option(_lib.OPT_TEMPORAL_BLOCKING, 5)
-        assert s.get_option(_lib.OPT_STEPS_PER_PASS) == 5
+        assert s.get_option(_lib.OPT_STEPS_PER_PASS) == (5 if prec == 4 else 3)
+        s.set_option(_lib.OPT_TEMPORAL_BLOCKING, 4)
+        assert s.get_option(_lib.OPT_STEPS_PER_PASS) == 4
         s.set_option(_lib.OPT_TEMPORAL_BLOCKING, 3)
         assert s.get_option(_lib.OPT_STEPS_PER_PASS) == 3
         s.set_option(_lib.OPT_TEMPORAL_BLOCKING, 2)

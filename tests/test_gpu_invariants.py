@@ -170,7 +170,7 @@ def test_particle_laden_8192_one_step_against_oracle(kind):
 
 def test_particle_laden_8192_blocked_pass_against_oracle():
     """The same workload through one blocked pass of the default depth d
-    (four steps), the benchmark's timed unit: after seven passes the state is
+    (five steps), the benchmark's timed unit: after seven passes the state is
     handed to the oracle, the GPU takes one pass (d steps) and the oracle d
     single steps; populations, the body forces of each of the d steps and
     the last step's marker forces are compared. The GPU state stays FP32
@@ -181,7 +181,7 @@ def test_particle_laden_8192_blocked_pass_against_oracle():
     log("8192^2 blocked pass: building GPU case")
     g = Sim.from_case(c, precision=4)
     d = g.get_option(_lib.OPT_STEPS_PER_PASS)
-    assert d == 4 and g.get_option(_lib.OPT_FUSED_TILES) > 0
+    assert d == 5 and g.get_option(_lib.OPT_FUSED_TILES) > 0
     g.step(7 * d)
     g.force_history(1000)  # drain: only the next pass's steps are returned below
     f = g.populations()
