@@ -909,6 +909,12 @@ int destroy_impl(btdf_t *h) {
   }
   drop_graph(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->side) {
+    (void)hipStreamSynchronize(h->side);
+    (void)hipStreamDestroy(h->side);
+  }
+  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+  if (h->join_ev) (void)hipEventDestroy(h->join_ev);
   h->tev.release();
   if (h->ws && h->ws_owned) (void)hipFree(h->ws);
   delete h;
@@ -1327,11 +1333,31 @@ static int enqueue_deep(btdf_t *h, const LbmParams &p, const IbParams &ib, hipSt
   HIPCHK(launch_lbm(h->prec, h->variant, A, X[1], p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, A, X[1], p, s));
   HIPCHK(mark(2));
-  // the pass: the smallest groups (which border near tiles) first, the largest last
-  for (int g = kLevels - 1; g >= 0; --g)
-    if (h->n_grp[g])
-      HIPCHK(launch_lbm_deep(h->prec, h->variant, d, h->gkind[g], A, B, p, fm + h->grp_start(g), h->n_grp[g],
-                             h->n_ring[g], X[1], rwin + h->grp_start(g), s));
+  // the pass: the smaller groups' launches on a second stream, beside the
+  // largest groups' launch (they are one to three waves of workgroups long,
+  // and alone their tails would leave the GPU partly idle)
+  bool small = false;
+  for (int g = 1; g < kLevels; ++g) small = small || h->n_grp[g] > 0;
+  if (small && h->n_grp[0]) {
+    if (!h->side) HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    if (!h->fork_ev) HIPCHK(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
+    if (!h->join_ev) HIPCHK(hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(h->fork_ev, s));
+    HIPCHK(hipStreamWaitEvent(h->side, h->fork_ev, 0));
+    for (int g = kLevels - 1; g >= 1; --g)
+      if (h->n_grp[g])
+        HIPCHK(launch_lbm_deep(h->prec, h->variant, d, h->gkind[g], A, B, p, fm + h->grp_start(g), h->n_grp[g],
+                               h->n_ring[g], X[1], rwin + h->grp_start(g), h->side));
+    HIPCHK(hipEventRecord(h->join_ev, h->side));
+    HIPCHK(launch_lbm_deep(h->prec, h->variant, d, h->gkind[0], A, B, p, fm, h->n_grp[0], h->n_ring[0], X[1], rwin,
+                           s));
+    HIPCHK(hipStreamWaitEvent(s, h->join_ev, 0));
+  } else {
+    for (int g = kLevels - 1; g >= 0; --g)
+      if (h->n_grp[g])
+        HIPCHK(launch_lbm_deep(h->prec, h->variant, d, h->gkind[g], A, B, p, fm + h->grp_start(g), h->n_grp[g],
+                               h->n_ring[g], X[1], rwin + h->grp_start(g), s));
+  }
   HIPCHK(mark(3));
   for (int k = 1; k < d; ++k) {
     void *dst = k + 1 < d ? X[k + 1] : B;

@@ -48,6 +48,10 @@ struct btdf_batch {
   int gkind[kLevels] = {};  // the shape of each level's launch
   hipGraphExec_t graph = nullptr;
   hipStream_t cap_stream = nullptr;
+  // the blocked pass's smaller launches run on a second stream beside the
+  // largest (fork and join events)
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   // time
   int cur = 0;
   int64_t steps = 0;
@@ -287,14 +291,33 @@ int batch_enqueue_triple(btdf_batch_t *b, int parity, hipStream_t s, hipEvent_t 
   HIPCHK(rec(1));
   if ((rc = near_step(A, 2))) return rc;
   HIPCHK(rec(2));
-  for (int w = kLevels - 1; w >= 0; --w) {  // the smallest groups first, the largest last
+  // the pass: every launch but the largest groups' on a second stream beside
+  // it (the smaller ones are a few waves of workgroups long, and alone their
+  // tails would leave the GPU partly idle); the smallest groups first
+  bool small = false;
+  for (int w = 0; w < kLevels; ++w) small = small || b->ge_count[w] > 0 || (w > 0 && b->g_count[w] > 0);
+  const bool fork = small && b->g_count[0] > 0;
+  if (fork) {
+    if (!b->side) HIPCHK(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+    if (!b->fork_ev) HIPCHK(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+    if (!b->join_ev) HIPCHK(hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(b->fork_ev, s));
+    HIPCHK(hipStreamWaitEvent(b->side, b->fork_ev, 0));
+  }
+  const hipStream_t ss = fork ? b->side : s;
+  for (int w = kLevels - 1; w >= 0; --w) {
     if (b->ge_count[w])
       HIPCHK(launch_lbm_edge3_batch(b->prec, b->variant, kEdge | b->gkind[w], desc, b->ge_case[w], b->ge_tile[w],
-                                    b->ge_count[w], route(A, B), b->mask, b->xcd_remap, s));
-    if (b->g_count[w])
+                                    b->ge_count[w], route(A, B), b->mask, b->xcd_remap, ss));
+    if (b->g_count[w] && w > 0)
       HIPCHK(launch_lbm3_batch(b->prec, b->variant, b->gkind[w], desc, b->g_case[w], b->g_tile[w], b->g_count[w],
-                               route(A, B), b->mask, b->xcd_remap, s));
+                               route(A, B), b->mask, b->xcd_remap, ss));
   }
+  if (fork) HIPCHK(hipEventRecord(b->join_ev, b->side));
+  if (b->g_count[0])
+    HIPCHK(launch_lbm3_batch(b->prec, b->variant, b->gkind[0], desc, b->g_case[0], b->g_tile[0], b->g_count[0],
+                             route(A, B), b->mask, b->xcd_remap, s));
+  if (fork) HIPCHK(hipStreamWaitEvent(s, b->join_ev, 0));
   HIPCHK(rec(3));
   HIPCHK(launch_ib_batch(b->prec, desc, b->map, route(2, 2), s));
   HIPCHK(rec(4));
@@ -437,6 +460,12 @@ int btdf_batch_destroy(btdf_batch_t *b) {
     if (b->ws && hipStreamSynchronize(b->stream) != hipSuccess) rc = fail(BTDF_EDEVICE, "stream sync failed");
     batch_drop_graph(b);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->side) {
+      (void)hipStreamSynchronize(b->side);
+      (void)hipStreamDestroy(b->side);
+    }
+    if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+    if (b->join_ev) (void)hipEventDestroy(b->join_ev);
     for (btdf_t *h : b->cases) {
       h->owner = nullptr;
       h->ws = nullptr;  // slices of the batch workspace are not the case's to free

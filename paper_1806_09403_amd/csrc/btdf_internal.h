@@ -139,6 +139,10 @@ struct btdf_sim {
   hipGraphExec_t graph = nullptr;
   int graph_depth = 0;  // steps per pass the graph was captured with (1: single steps)
   hipStream_t cap_stream = nullptr;
+  // passes of four or five steps: the small groups' launches run on a second
+  // stream beside the largest groups' (fork and join events)
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   btdf_event_pool tev;  // events of the timed stepping calls
 
   int nb() const { return (int)cx.size(); }
