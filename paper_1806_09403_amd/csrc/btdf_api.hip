@@ -1267,6 +1267,17 @@ static int enqueue_pair(btdf_t *h, const LbmParams &p, const IbParams &ib, hipSt
   return ok();
 }
 
+// Fork a second stream from s for the blocked pass's smaller launches (the
+// caller records join_ev on it after them and makes s wait for that).
+static int fork_side(btdf_t *h, hipStream_t s) {
+  if (!h->side) HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+  if (!h->fork_ev) HIPCHK(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
+  if (!h->join_ev) HIPCHK(hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(h->fork_ev, s));
+  HIPCHK(hipStreamWaitEvent(h->side, h->fork_ev, 0));
+  return ok();
+}
+
 // three steps from buffer cur into 1 - cur (three-step blocking): as a pair,
 // with the near tiles' states n+1 and n+2 in X1 and X2 and the marker kernel
 // before each of their steps. The three-step pass writes both rings, so it
@@ -1289,13 +1300,28 @@ static int enqueue_triple(btdf_t *h, const LbmParams &p, const IbParams &ib, hip
   HIPCHK(launch_lbm(h->prec, h->variant, A, X1, p, TileRange{fm, nb0, h->n_near, 1}, ib, s));
   if (p.outlet == 2) HIPCHK(launch_conv_outlet(h->prec, A, X1, p, s));
   if (ev && ev[2]) HIPCHK(hipEventRecord(ev[2], s));
-  // the pass: the smallest groups (which border near tiles) first, the largest last
+  // the pass: the smallest groups (which border near tiles) first, the
+  // largest last; every launch but the largest interior groups' on a second
+  // stream beside it (see enqueue_deep)
   if (ev && ev[5]) HIPCHK(hipEventRecord(ev[5], s));
+  bool small = h->n_edge[0] > 0;
+  for (int g = 1; g < kLevels; ++g) small = small || h->n_grp[g] > 0;
+  const int n0 = h->n_grp[0] - h->n_edge[0];
+  hipStream_t ss = s;
+  if (small && n0 > 0) {
+    const int rc = fork_side(h, s);
+    if (rc) return rc;
+    ss = h->side;
+  }
   for (int g = kLevels - 1; g >= 0; --g) {
     const int ne = h->n_edge[g], ni = h->n_grp[g] - ne, *lv = fm + h->grp_start(g);
-    if (ne) HIPCHK(launch_lbm_edge3(h->prec, h->variant, kEdge | h->gkind[g], A, B, p, lv, ne, X1, X2, near, s));
-    if (ni) HIPCHK(launch_lbm3(h->prec, h->variant, h->gkind[g], A, B, p, lv + ne, ni, X1, X2, near, s));
+    if (ne) HIPCHK(launch_lbm_edge3(h->prec, h->variant, kEdge | h->gkind[g], A, B, p, lv, ne, X1, X2, near, ss));
+    if (ni && g > 0) HIPCHK(launch_lbm3(h->prec, h->variant, h->gkind[g], A, B, p, lv + ne, ni, X1, X2, near, ss));
   }
+  if (ss != s) HIPCHK(hipEventRecord(h->join_ev, ss));
+  if (n0 > 0)
+    HIPCHK(launch_lbm3(h->prec, h->variant, h->gkind[0], A, B, p, fm + h->n_edge[0], n0, X1, X2, near, s));
+  if (ss != s) HIPCHK(hipStreamWaitEvent(s, h->join_ev, 0));
   if (ev && ev[6]) HIPCHK(hipEventRecord(ev[6], s));
   HIPCHK(launch_ib(h->prec, X1, p, ib, s));
   if (ev && ev[3]) HIPCHK(hipEventRecord(ev[3], s));
@@ -1339,11 +1365,8 @@ static int enqueue_deep(btdf_t *h, const LbmParams &p, const IbParams &ib, hipSt
   bool small = false;
   for (int g = 1; g < kLevels; ++g) small = small || h->n_grp[g] > 0;
   if (small && h->n_grp[0]) {
-    if (!h->side) HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
-    if (!h->fork_ev) HIPCHK(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
-    if (!h->join_ev) HIPCHK(hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming));
-    HIPCHK(hipEventRecord(h->fork_ev, s));
-    HIPCHK(hipStreamWaitEvent(h->side, h->fork_ev, 0));
+    int rc;
+    if ((rc = fork_side(h, s))) return rc;
     for (int g = kLevels - 1; g >= 1; --g)
       if (h->n_grp[g])
         HIPCHK(launch_lbm_deep(h->prec, h->variant, d, h->gkind[g], A, B, p, fm + h->grp_start(g), h->n_grp[g],
