@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <tuple>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -315,6 +316,16 @@ void fused_lists(btdf_t *h) {
       };
       const auto mid = std::stable_partition(h->fmap.begin() + start, h->fmap.end(), ring);
       h->n_ring[g] = (int)(mid - (h->fmap.begin() + start));
+      // Groups two tiles tall are launched down bands of kSquareBand tile
+      // columns, row by row within a band: the groups above and below one
+      // are then a band's width of launch slots away instead of a whole
+      // row's, and the halo rows they share are still in the XCD's L2.
+      if (gh == 2) {
+        auto key = [&](int t) { return std::make_tuple((t % ntx) / kSquareBand, t / ntx, t % ntx); };
+        auto cmp = [&](int a, int b) { return key(a) < key(b); };
+        std::stable_sort(h->fmap.begin() + start, mid, cmp);
+        std::stable_sort(mid, h->fmap.end(), cmp);
+      }
       // each ring group's window of near flags (bit 8 r + c, r from the row
       // below, c from the column left of the group)
       h->rwin.resize(h->fmap.size(), 0u);

@@ -208,6 +208,8 @@ constexpr int kMoveMargin = 2;  // nodes a moving marker may travel between tile
 constexpr long long kBlockMinNodes = 1ll << 20;
 // steps per pass by default on a single lattice, where the launch shape has them
 constexpr int kDefaultDepth = 5;
+// width in tile columns of the bands down which groups two tiles tall are launched
+constexpr int kSquareBand = 32;
 std::string forcing_setup(btdf_t *h);
 LbmParams make_params(const btdf_t *h);
 IbParams make_ib(const btdf_t *h);
