@@ -303,6 +303,14 @@ int btdf_get_macroscopic(btdf_t *h, double *rho, double *ux, double *uy);
  * clears the instability flag. Synchronising. */
 int btdf_get_populations(btdf_t *h, double *dst);
 int btdf_set_populations(btdf_t *h, const double *src);
+/* The same with the FP64 [9][ny][nx] array in host memory (on_device = 0)
+ * or in device memory of the handle's device (on_device = 1). A device array
+ * is written or read by kernels on the handle's stream, with no copy through
+ * the host; the caller owns it and keeps it allocated for the call.
+ * BTDF_EINVAL if it is not device memory on the handle's device (checked
+ * with hipPointerGetAttributes). Synchronising. */
+int btdf_get_populations_to(btdf_t *h, void *dst, int dst_on_device);
+int btdf_set_populations_from(btdf_t *h, const void *src, int src_on_device);
 
 /* Per-marker values of the last step (host arrays of length = total
  * markers, any may be NULL): interpolated rho_l and u*_l (eqs 12, 14) and

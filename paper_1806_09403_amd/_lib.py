@@ -89,6 +89,8 @@ SIGNATURES = {
     "btdf_get_macroscopic": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "btdf_get_populations": (ctypes.c_int, [_vp, _dp]),
     "btdf_set_populations": (ctypes.c_int, [_vp, _dp]),
+    "btdf_get_populations_to": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "btdf_set_populations_from": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
     "btdf_get_marker_data": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp, _dp]),
     "btdf_marker_velocity": (ctypes.c_int, [_vp, _dp, _dp]),
     "btdf_marker_velocity_noalloc": (ctypes.c_int, [_vp, _dp, _dp]),

@@ -115,6 +115,15 @@ def btdf_set_populations(h, f):
     return check(load().btdf_set_populations(h, dptr(f)))
 
 
+def btdf_get_populations_to(h, dst_ptr, dst_on_device):
+    """dst_ptr: address (int) of an FP64 [9][ny][nx] array, host or device."""
+    return check(load().btdf_get_populations_to(h, ctypes.c_void_p(dst_ptr), int(dst_on_device)))
+
+
+def btdf_set_populations_from(h, src_ptr, src_on_device):
+    return check(load().btdf_set_populations_from(h, ctypes.c_void_p(src_ptr), int(src_on_device)))
+
+
 def btdf_get_marker_data(h):
     nm = btdf_counts(h)[1]
     arrs = [np.empty(max(nm, 1)) for _ in range(5)]

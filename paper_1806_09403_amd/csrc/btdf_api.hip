@@ -1847,6 +1847,58 @@ int btdf_set_populations(btdf_t *h, const double *src) {
   });
 }
 
+// whether ptr is device memory on the handle's device, the memory a kernel
+// on the handle's stream may read or write
+static int check_device_ptr(const btdf_t *h, const void *ptr) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+    (void)hipGetLastError();  // (clear the sticky error of an unknown pointer)
+    return fail(BTDF_EINVAL, "the array is not memory HIP knows");
+  }
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (a.type != hipMemoryTypeDevice || a.device != dev)
+    return fail(BTDF_EINVAL, "the array is not device memory on the handle's device");
+  (void)h;
+  return ok();
+}
+
+int btdf_get_populations_to(btdf_t *h, void *dst, int dst_on_device) {
+  if (!dst_on_device) return btdf_get_populations(h, static_cast<double *>(dst));
+  return guard([&]() -> int {
+    if (!h || !dst) return fail(BTDF_EINVAL, "NULL argument");
+    int rc = ensure_device(h);
+    if (rc) return rc;
+    if ((rc = check_device_ptr(h, dst))) return rc;
+    const size_t n = (size_t)h->nx * h->ny;
+    LbmParams p = make_params(h);
+    double *out = static_cast<double *>(dst);
+    for (int q = 0; q < 9; ++q)
+      HIPCHK(launch_plane_to_f64(h->prec, h->ws + h->off_pop[h->cur], p, q, out + (size_t)q * n, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return ok();
+  });
+}
+
+int btdf_set_populations_from(btdf_t *h, const void *src, int src_on_device) {
+  if (!src_on_device) return btdf_set_populations(h, static_cast<const double *>(src));
+  return guard([&]() -> int {
+    if (!h || !src) return fail(BTDF_EINVAL, "NULL argument");
+    int rc = ensure_device(h);
+    if (rc) return rc;
+    if ((rc = check_device_ptr(h, src))) return rc;
+    const size_t n = (size_t)h->nx * h->ny;
+    LbmParams p = make_params(h);
+    const double *in = static_cast<const double *>(src);
+    for (int q = 0; q < 9; ++q)
+      HIPCHK(launch_f64_to_plane(h->prec, h->ws + h->off_pop[h->cur], p, q, in + (size_t)q * n, h->stream));
+    h->stepped = false;
+    if ((rc = clear_flag(h))) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return ok();
+  });
+}
+
 int btdf_get_marker_data(btdf_t *h, double *rho_l, double *ux_l, double *uy_l, double *Fx, double *Fy) {
   return guard([&]() -> int {
     if (!h) return fail(BTDF_EINVAL, "NULL handle");

@@ -95,6 +95,22 @@ class Sim:
     def set_populations(self, f):
         return api.btdf_set_populations(self._workspace(), f)
 
+    def populations_to(self, out):
+        """Fill a contiguous FP64 torch tensor of shape (9, ny, nx) on the
+        handle's device with the populations, with no copy through the host."""
+        import torch
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        assert tuple(out.shape) == (9, self.ny, self.nx)
+        return api.btdf_get_populations_to(self._workspace(), out.data_ptr(), 1)
+
+    def set_populations_from(self, src):
+        """Set the populations from a contiguous FP64 torch tensor (9, ny, nx)
+        on the handle's device."""
+        import torch
+        assert src.dtype == torch.float64 and src.is_cuda and src.is_contiguous()
+        assert tuple(src.shape) == (9, self.ny, self.nx)
+        return api.btdf_set_populations_from(self._workspace(), src.data_ptr(), 1)
+
     def marker_data(self):
         return api.btdf_get_marker_data(self._workspace())
 
