@@ -245,9 +245,13 @@ __device__ __forceinline__ void lbm3_edge_group(const T *__restrict__ A, T *__re
   if (s_any && keep && mine && (ii == 0 || ii == OX - 1 || jj == 0 || jj == OY - 1 || x == p.nx - 1 || y == p.ny - 1))
     rmask = edge_ring(p, near, __builtin_ctz((unsigned)tile_x), __builtin_ctz((unsigned)tile_y), x, y);
   if (rmask) {
+    const global_ptr<T> Xg = (global_ptr<T>)X1;
+    T v[9];
+#pragma unroll
+    for (int q = 1; q < 9; ++q) v[q] = s_f[q * RN + kown];
 #pragma unroll
     for (int q = 1; q < 9; ++q)
-      if (rmask & (1u << q)) X1[(long long)q * p.plane + node] = s_f[q * RN + kown];
+      if (rmask & (1u << q)) Xg[(long long)q * p.plane + node] = v[q];
   }
   // step n+2 over the group grown by one (at most two nodes per thread),
   // into registers
@@ -299,22 +303,29 @@ __device__ __forceinline__ void lbm3_edge_group(const T *__restrict__ A, T *__re
       edge_pull_lds<T, RN, RX>(p, n.y, s_f, kown, g);
       collide<T>(g, F, K, out, rho);
       bad |= !rho_ok(rho);
+      // (global stores: the buffers come from the case table as generic
+      // pointers, whose stores would otherwise be flat ones)
+      const global_ptr<T> Cg = (global_ptr<T>)C;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) C[(long long)q * p.plane + node] = out[q];
+      for (int q = 0; q < 9; ++q) Cg[(long long)q * p.plane + node] = out[q];
       if (p.inlet && x == 1) {
         const T dr = inlet_dr<T>(out);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) C[(long long)q * p.plane + node - 1] = inlet_ghost<T>(dr, p, q);
+        for (int q = 0; q < 9; ++q) Cg[(long long)q * p.plane + node - 1] = inlet_ghost<T>(dr, p, q);
       }
       if (p.outlet == 1 && x == p.nx - 2) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) C[(long long)q * p.plane + node + 1] = out[q];
+        for (int q = 0; q < 9; ++q) Cg[(long long)q * p.plane + node + 1] = out[q];
       }
     }
     if (rmask) {
+      const global_ptr<T> Xg = (global_ptr<T>)X2;
+      T v[9];
+#pragma unroll
+      for (int q = 1; q < 9; ++q) v[q] = s_f[q * RN + kown];
 #pragma unroll
       for (int q = 1; q < 9; ++q)
-        if (rmask & (1u << q)) X2[(long long)q * p.plane + node] = s_f[q * RN + kown];
+        if (rmask & (1u << q)) Xg[(long long)q * p.plane + node] = v[q];
     }
   }
   if (bad && keep) p.flag[0] = -1;
