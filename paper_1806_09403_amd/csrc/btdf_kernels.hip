@@ -44,12 +44,41 @@ __device__ __forceinline__ void ib_marker(const T *__restrict__ A, const LbmPara
   const int a = node & 3, c = node >> 2;
 
   double wr = 0.0, wu = 0.0, wv = 0.0, X = 0.0, Y = 0.0;
+  // the marker's velocity and spreading factor, loaded with its position:
+  // read after the stores below they would wait for them (the arrays may
+  // alias as far as the compiler knows) and add a round trip at the end
+  double Ub = 0.0, Vb = 0.0, sdl = 0.0;
   int bx = 0, by = 0;
   if (act) {
     X = ib.X[l];
     Y = ib.Y[l];
+    Ub = ib.U[l];
+    Vb = ib.V[l];
+    sdl = ib.sdrs[l];
     bx = stencil_base(p.kind, X);
     by = stencil_base(p.kind, Y);
+  }
+  // this lane's stencil node and its nine populations, loaded before the
+  // weights are evaluated, so that the loads are in flight meanwhile
+  const bool on = act && a < S && c < S;
+  int i = bx + a, j = by + c;
+  if (p.xper) i = wrap_index(i, p.nx);
+  if (p.yper) j = wrap_index(j, p.ny);
+  T gq[9];
+  if (on) {
+    if (i >= 1 && i <= p.nx - 2 && j >= 1 && j <= p.ny - 2) {
+      // no wrap, no wall: one 32-bit offset, the shifts fold into the plane base
+      const unsigned off = ((unsigned)j * (unsigned)p.pitch + (unsigned)i) * (unsigned)sizeof(T);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const char *base = reinterpret_cast<const char *>(A + (long long)q * p.plane -
+                                                          (long long)ey(q) * p.pitch - ex(q));
+        gq[q] = *reinterpret_cast<const T *>(base + off);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) gq[q] = pull(A, p, q, i, j);
+    }
   }
   // lanes 0-3 of the group evaluate the x weights, lanes 4-7 the y weights
   double ph = 0.0;
@@ -65,32 +94,15 @@ __device__ __forceinline__ void ib_marker(const T *__restrict__ A, const LbmPara
     T *mw = reinterpret_cast<T *>(ib.mk_w) + 10 * (long long)l;
     if (c == 0) mw[a] = (T)phx;
     if (a == 0) mw[4 + c] = (T)phy;
-    if (a < S && c < S) {
+    if (on) {
       const double W = phx * phy;
-      int i = bx + a, j = by + c;
-      if (p.xper) i = wrap_index(i, p.nx);
-      if (p.yper) j = wrap_index(j, p.ny);
       double drho = 0.0, mx = 0.0, my = 0.0;
-      if (i >= 1 && i <= p.nx - 2 && j >= 1 && j <= p.ny - 2) {
-        // no wrap, no wall: one 32-bit offset, the shifts fold into the plane base
-        const unsigned off = ((unsigned)j * (unsigned)p.pitch + (unsigned)i) * (unsigned)sizeof(T);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-          const char *base = reinterpret_cast<const char *>(A + (long long)q * p.plane -
-                                                            (long long)ey(q) * p.pitch - ex(q));
-          const double g = (double)*reinterpret_cast<const T *>(base + off);
-          drho += g;
-          mx += ex(q) * g;
-          my += ey(q) * g;
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-          const double g = (double)pull(A, p, q, i, j);
-          drho += g;
-          mx += ex(q) * g;
-          my += ey(q) * g;
-        }
+      for (int q = 0; q < 9; ++q) {
+        const double g = (double)gq[q];
+        drho += g;
+        mx += ex(q) * g;
+        my += ey(q) * g;
       }
       const double rho = 1.0 + drho;
       const double inv = 1.0 / rho;
@@ -114,14 +126,14 @@ __device__ __forceinline__ void ib_marker(const T *__restrict__ A, const LbmPara
     wv += __shfl_xor(wv, off, 16);
   }
   if (act && node == 0) {
-    const double Fx = 2.0 * wr * (ib.U[l] - wu);
-    const double Fy = 2.0 * wr * (ib.V[l] - wv);
+    const double Fx = 2.0 * wr * (Ub - wu);
+    const double Fy = 2.0 * wr * (Vb - wv);
     ib.Fx[l] = Fx;
     ib.Fy[l] = Fy;
     ib.rho_l[l] = wr;
     ib.ux_l[l] = wu;
     ib.uy_l[l] = wv;
-    const double sd = ib.sdrs[l];
+    const double sd = sdl;
     T *mw = reinterpret_cast<T *>(ib.mk_w) + 10 * (long long)l;
     mw[8] = (T)(Fx * sd);
     mw[9] = (T)(Fy * sd);
