@@ -119,16 +119,39 @@ __global__ __launch_bounds__(OX *OY) void lbmd_kernel(const T *__restrict__ A, T
     }
   }
   __syncthreads();
-  // the ring directions of this thread's node (edge nodes only): bit q when
-  // x + e_q lies in a near tile (the group's own tiles never are)
+  // The edge node whose ring stores this thread makes: the bottom row's by
+  // the first OX threads and the top row's by the last OX (their own nodes),
+  // the two columns' other nodes by 2 (OY - 2) threads of the first wave past
+  // the bottom row, so that only these waves run the ring code.
+  int ri = 0, rj = 0;
+  bool redge = false;
+  if (RING) {
+    constexpr int CB = (OX + 63) / 64 * 64, NC = OY - 2;
+    static_assert(CB + 2 * NC <= NTH - OX, "the column threads lie between the two rows' threads");
+    if (tid < OX) {
+      ri = tid;
+      redge = true;
+    } else if (tid >= NTH - OX) {
+      ri = tid - (NTH - OX);
+      rj = OY - 1;
+      redge = true;
+    } else if (tid >= CB && tid < CB + 2 * NC) {
+      const int c = tid - CB;
+      ri = c < NC ? 0 : OX - 1;
+      rj = 1 + (c < NC ? c : c - NC);
+      redge = true;
+    }
+  }
+  // its ring directions: bit q when x + e_q lies in a near tile (the group's
+  // own tiles never are)
   unsigned rmask = 0;
-  if (RING && (ii == 0 || ii == OX - 1 || jj == 0 || jj == OY - 1)) {
+  if (RING && redge) {
     constexpr int W = OX / TX, H = OY / TY;
     constexpr int shx = __builtin_ctz((unsigned)TX), shy = __builtin_ctz((unsigned)TY);
-    const int cl = ii == 0 ? 0 : 1 + ((ii - 1) >> shx), cm = 1 + (ii >> shx);
-    const int cr = ii == OX - 1 ? W + 1 : 1 + ((ii + 1) >> shx);
-    const int rd = jj == 0 ? 0 : 1 + ((jj - 1) >> shy), rm = 1 + (jj >> shy);
-    const int ru = jj == OY - 1 ? H + 1 : 1 + ((jj + 1) >> shy);
+    const int cl = ri == 0 ? 0 : 1 + ((ri - 1) >> shx), cm = 1 + (ri >> shx);
+    const int cr = ri == OX - 1 ? W + 1 : 1 + ((ri + 1) >> shx);
+    const int rd = rj == 0 ? 0 : 1 + ((rj - 1) >> shy), rm = 1 + (rj >> shy);
+    const int ru = rj == OY - 1 ? H + 1 : 1 + ((rj + 1) >> shy);
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
       const int r = ey(q) < 0 ? rd : (ey(q) > 0 ? ru : rm);
@@ -137,7 +160,7 @@ __global__ __launch_bounds__(OX *OY) void lbmd_kernel(const T *__restrict__ A, T
     }
   }
   const unsigned off = (unsigned)(jj * p.pitch + ii) * (unsigned)sizeof(T);
-  // the ring: state n+s of this thread's node, from LDS, in its ring directions
+  // the ring: state n+s of that node, from LDS, in its ring directions
   // (a per-lane zero the compiler cannot see through keeps these rare
   // stores' addresses in vector registers, so their bases are not held in
   // scalar registers across the pass)
@@ -147,11 +170,11 @@ __global__ __launch_bounds__(OX *OY) void lbmd_kernel(const T *__restrict__ A, T
     asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
     const long long plane = p.plane + vz;
     global_ptr<T> X = (global_ptr<T>)ring + (long long)(s - 1) * ring_stride<T>(p) + vz +
-                      (long long)(y0 + jj) * p.pitch + (x0 + ii);
+                      (long long)(y0 + rj) * p.pitch + (x0 + ri);
     // the eight LDS reads first, so they are in flight together, then the stores
     T v[9];
 #pragma unroll
-    for (int q = 1; q < 9; ++q) v[q] = s_f[q][jj + G][ii + G];
+    for (int q = 1; q < 9; ++q) v[q] = s_f[q][rj + G][ri + G];
 #pragma unroll
     for (int q = 1; q < 9; ++q)
       if (rmask & (1u << q)) X[q * plane] = v[q];
